@@ -1,0 +1,225 @@
+"""Benchmark: damped, smoothing-regularised LSQR on one MI355X.
+
+A step is one LSQR solve of the paper-shaped synthetic system (80x80x20 grid,
+229 stations, all pairs x 20 periods, paths >= 2 wavelengths, bent rays;
+~0.49M rows, ~0.59B stored entries) for a fixed 300 iterations with the
+system and right-hand side already resident in HBM.  value = LSQR
+iterations per second.  The two sparse kernels are timed with HIP events on
+the solve's stream inside the timed region; the dominant one is reported
+against the HBM roofline.  The FP64 CPU oracle is timed on a bounded sample
+of the same solve on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg1|cfg0]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LSQR iters/s + SpMV HBM GB/s; time-to-tol mixed/learned vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def host_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except Exception:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(s, iters_sample):
+    """The FP64 oracle on the same system: a bounded number of LSQR iterations
+    timed on the host cores (transpose set-up excluded)."""
+    import oracle
+    nt = host_threads()
+    op = oracle.Operator.from_system(s, nthreads=nt)
+    t0 = time.perf_counter()
+    r = op.lsqr(s.dt, iters_sample)
+    dt = time.perf_counter() - t0
+    return {"value": r["iters"] / dt, "unit": "iters/s", "cores": nt, "kind": "oracle",
+            "sample": f"{r['iters']} FP64 LSQR iterations (plus the start step) of the same "
+                      f"system, {dt:.1f} s"}
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_11920_amd", "csrc", "kernels_lsqr.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cfg1_fp64.txt")
+CALIB_BYTES = float(1 << 30)        # the calibration kernel reads 1 GiB and writes 1 GiB
+
+
+def source_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def pmc_summary(fetch_csv, write_csv):
+    """Per-launch HBM bytes of the solver kernels from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the same
+    counter reads for the 1 GiB elementwise calibration kernel."""
+    import csv
+    out = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        calib = [float(r["Counter_Value"]) for r in rows
+                 if "elementwise" in r["Kernel_Name"] and "Fill" not in r["Kernel_Name"]]
+        factor = CALIB_BYTES / 1024.0 / (sum(calib) / len(calib))
+        out[counter + "_factor"] = factor
+        for tag, key in (("fwd", "k_fwd"), ("adj", "k_adj")):
+            v = [float(r["Counter_Value"]) for r in rows if key in r["Kernel_Name"]]
+            out[f"{tag}_{counter}_bytes"] = sum(v) / len(v) * 1024.0 * factor
+    for tag in ("fwd", "adj"):
+        out[f"{tag}_traffic_bytes"] = out[f"{tag}_FETCH_SIZE_bytes"] + out[f"{tag}_WRITE_SIZE_bytes"]
+    out["source_sha256_16"] = source_hash()
+    return out
+
+
+def measured_traffic(tag):
+    """Traffic of kernel `tag` from the committed counter summary, or None when
+    the kernel source changed since the counters were taken."""
+    try:
+        kv = dict(line.split(None, 1) for line in open(TRAFFIC_FILE).read().splitlines()
+                  if line and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("source_sha256_16", "").strip() != source_hash():
+        return None
+    v = kv.get(f"{tag}_traffic_bytes")
+    return float(v) if v else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="cfg1", choices=["cfg1", "cfg0"])
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print per-launch HBM traffic from two rocprofv3 --pmc runs and exit")
+    args = ap.parse_args()
+    if args.pmc_summary:
+        for k, v in pmc_summary(*args.pmc_summary).items():
+            print(k, v)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the solver is single-GPU)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2604_11920_amd import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    if args.config == "cfg1":
+        cfg = synth.config1()
+        iters = args.iters or 300
+        workload = ("cfg1: 80x80x20 grid (128,000 unknowns), 229 stations, 26,106 pairs x 20 "
+                    "periods 1-40 s, paths >= 2 wavelengths, bent rays, 7-point smoothing x0.5, "
+                    f"damp 0.1, {iters} LSQR iterations per step")
+    else:
+        cfg = synth.config0()
+        iters = args.iters or 100
+        workload = ("cfg0: 16x16x9 grid (2,304 unknowns), 40 stations, 780 pairs x 10 periods, "
+                    f"straight rays, smoothing x0.5, damp 0.1, {iters} LSQR iterations per step")
+    s = synth.make_system(cfg)
+    log(f"[bench] generated {args.config}: m={s.m} n={s.n} nnz={s.nnz} "
+        f"in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    sol = Solver.from_system(s, timing=True)
+    torch.cuda.synchronize()
+    log(f"[bench] create (copy + device transpose) {time.perf_counter() - t0:.2f}s")
+    dt = torch.from_numpy(s.dt).cuda()
+    dm = torch.empty(s.n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calib:
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 2.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+
+    for _ in range(args.warmup):
+        sol.solve(dt, iters, dm=dm, history=False)
+    torch.cuda.synchronize()
+    fwd_ms = adj_ms = 0.0
+    fwd_n = adj_n = 0
+    per_step = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, _, info = sol.solve(dt, iters, dm=dm, history=False)
+        per_step.append(time.perf_counter() - ts)
+        ks = sol.kernel_stats()
+        fwd_ms += ks["fwd_ms"]; adj_ms += ks["adj_ms"]
+        fwd_n += ks["fwd_launches"]; adj_n += ks["adj_launches"]
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    gpu_ms = ev0.elapsed_time(ev1)
+    assert info["iters"] == iters, info
+    ms_per_step = wall * 1e3 / args.steps
+    value = iters * args.steps / wall
+    fwd_avg = fwd_ms / max(fwd_n, 1)
+    adj_avg = adj_ms / max(adj_n, 1)
+    fwd_gbs = ks["fwd_bytes"] / (fwd_avg * 1e-3) / 1e9
+    adj_gbs = ks["adj_bytes"] / (adj_avg * 1e-3) / 1e9
+    dom = "fwd" if fwd_ms >= adj_ms else "adj"
+    dom_gbs = fwd_gbs if dom == "fwd" else adj_gbs
+    # paper protocol: drop the slowest and fastest step, average the rest
+    ps = sorted(per_step)
+    trimmed = ps[1:-1] if len(ps) > 2 else ps
+    log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step (events {gpu_ms / args.steps:.2f}), "
+        f"{value:.1f} it/s; fwd {fwd_avg * 1e3:.1f} us {fwd_gbs:.0f} GB/s, adj {adj_avg * 1e3:.1f} us "
+        f"{adj_gbs:.0f} GB/s")
+    out = {
+        "metric": METRIC, "value": value, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": workload, "m": s.m, "n": s.n, "nnz": s.nnz,
+                   "iters_per_step": iters, "precision": "fp64", "precond": "none"},
+        "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "kernel": "k_fwd (forward CSR product)" if dom == "fwd"
+                     else "k_adj (transposed CSC product)"},
+        "kernels": {"fwd": {"avg_us": fwd_avg * 1e3, "alg_bytes": ks["fwd_bytes"], "gbs": fwd_gbs},
+                    "adj": {"avg_us": adj_avg * 1e3, "alg_bytes": ks["adj_bytes"], "gbs": adj_gbs}},
+        "paper_protocol_ms_per_step": 1e3 * sum(trimmed) / len(trimmed),
+    }
+    sol.close()
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle sample ...")
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_iters)
+        log(f"[bench] cpu oracle {out['cpu_baseline']['value']:.3f} it/s on "
+            f"{out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

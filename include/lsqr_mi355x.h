@@ -1,0 +1,195 @@
+/*
+ * lsqr_mi355x.h — C ABI of the MI355X (gfx950) damped, smoothing-regularised
+ * LSQR library.
+ *
+ * Problem.  The paper (pDSurfTomo, arXiv 2604.11920) reduces each inversion
+ * step to the sparse overdetermined system Delta d = G Delta m (its eq. (6)),
+ * solved in the least-squares sense by a Krylov solver (its section "Solver for
+ * the Large-scale Linear System", which names LSQR of Paige & Saunders 1982 and
+ * LSMR; the unknown ordering is its eq. (7), depth fastest).  This library
+ * solves the regularised form
+ *
+ *     dm = argmin |G dm - dt|^2 + w^2 |L dm|^2 + lambda^2 |dm|^2
+ *
+ * where w = smooth_weight, lambda = damp and L is the 3-D 7-point Laplacian on
+ * the (nx, ny, nz) model grid in index space (off-grid neighbours dropped,
+ * centre = -(number of in-grid neighbours), so L 1 = 0).  LSQR runs on the
+ * explicit block operator Abar = [G; w L; lambda I] times an optional column
+ * scaling D (x = D y), with right-hand side bbar = [dt; 0; 0].
+ *
+ * Conventions for every function:
+ *   - Returns an lsqr_status; never throws, aborts or exits.  After a failure a
+ *     message is available from lsqr_last_error().
+ *   - The caller owns every pointer it passes; pointers need to stay valid only
+ *     for the duration of the call.  Device pointers are HIP device addresses
+ *     on the device that was current when the context was created.
+ *   - Work is issued on opts.stream (a hipStream_t, NULL = default stream).
+ *     lsqr_solve and lsqr_solve_batched return after the stream has finished
+ *     the solve (they read back the stop state); the operator entry points
+ *     lsqr_apply / lsqr_apply_t only enqueue work.
+ *   - A context is not thread-safe; separate contexts may be used concurrently.
+ */
+#ifndef LSQR_MI355X_H
+#define LSQR_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LSQR_OK = 0,
+    LSQR_E_INVALID_ARG = -1,   /* null pointer, bad size, negative damp, ...       */
+    LSQR_E_BAD_CSR = -2,       /* row_ptr not monotone, column out of range,        */
+                               /* columns unsorted or duplicated within a row       */
+    LSQR_E_NONFINITE = -3,     /* NaN/Inf in G, dt or a scale; or a solver scalar    */
+    LSQR_E_DEVICE = -4,        /* a HIP call failed (message names it)              */
+    LSQR_E_OOM = -5,           /* allocation failed                                 */
+    LSQR_E_UNSUPPORTED = -6    /* valid request this build does not provide         */
+} lsqr_status;
+
+typedef enum { LSQR_MEM_HOST = 0, LSQR_MEM_DEVICE = 1 } lsqr_mem;
+
+/* Storage/arithmetic of the sparse products.  FP64: FP64 values, vectors and
+ * accumulation.  FP32: FP32 values, vectors and accumulation, FP64 scalars and
+ * norms.  BF16/FP16: quantised values with per-row scales inside FP64
+ * iterative refinement (see lsqr_create). */
+typedef enum { LSQR_FP64 = 0, LSQR_FP32 = 1, LSQR_BF16 = 2, LSQR_FP16 = 3 } lsqr_precision;
+
+/* Column scaling D.  NONE: D = I.  JACOBI: d_j = 1 / |column j of Abar|
+ * (data, smoothing and damping entries).  USER: d_j = col_scale[j]. */
+typedef enum { LSQR_PRECOND_NONE = 0, LSQR_PRECOND_JACOBI = 1, LSQR_PRECOND_USER = 2 } lsqr_precond;
+
+/* The data block G in CSR form (smoothing and damping rows are implicit). */
+typedef struct {
+    int64_t m, n, nnz;          /* rows, columns, stored entries; n == nx*ny*nz        */
+    int32_t nx, ny, nz;         /* grid; column l = (iy*nx + ix)*nz + iz               */
+    const int64_t *row_ptr;     /* [m+1]; row_ptr[0] = 0, non-decreasing, [m] = nnz    */
+    const int32_t *col_idx;     /* [nnz]; strictly increasing within a row, in [0, n)  */
+    const double *val;          /* [nnz]; finite                                       */
+    lsqr_mem mem;               /* where row_ptr/col_idx/val live                      */
+} lsqr_csr;
+
+/* Optional device allocator (e.g. PyTorch's caching allocator).  When alloc is
+ * NULL the library calls hipMalloc/hipFree itself. */
+typedef void *(*lsqr_alloc_fn)(size_t bytes, void *user);
+typedef void (*lsqr_free_fn)(void *ptr, size_t bytes, void *user);
+
+#define LSQR_FLAG_TIMING 1u     /* record HIP events around the sparse kernels  */
+#define LSQR_FLAG_NO_GRAPH 2u   /* launch iterations one by one, no hipGraph     */
+
+typedef struct {
+    lsqr_precision precision;
+    lsqr_precond precond;
+    const double *col_scale;    /* host [n], > 0 and finite, when precond == USER      */
+    int refine_sweeps;          /* mixed precision: maximum refinement sweeps (>= 1)   */
+    int check_every;            /* iterations per device-side convergence block (>= 1) */
+    void *stream;               /* hipStream_t                                         */
+    lsqr_alloc_fn alloc;
+    lsqr_free_fn dealloc;
+    void *alloc_user;
+    uint32_t flags;             /* LSQR_FLAG_*                                         */
+    int lanes_per_row;          /* 0 = auto; else 4, 8, 16, 32 or 64 lanes per row    */
+    int lanes_per_col;          /* 0 = auto; same choices for the transposed product   */
+} lsqr_opts;
+
+/* Stop reasons (info.istop):
+ *   0  bbar = 0 or Abar^T bbar = 0; dm = 0
+ *   1  eta_k <= tol, with eta_k = |Abar^T rbar_k| / |Abar^T bbar| estimated from
+ *      the bidiagonalisation (LSQR's |A^T r| estimate times |D^-1 v_{k+1}|)
+ *   2  iteration limit reached
+ *   3  exact breakdown (alpha or beta exactly 0): dm is the least-squares
+ *      solution over the Krylov space reached
+ *   4  mixed-precision refinement stalled (eta did not halve in a sweep)  */
+typedef struct {
+    int istop;
+    int iters;                  /* iterations done (total inner iterations if mixed)  */
+    int sweeps;                 /* refinement sweeps done (mixed forms), else 0        */
+    int fallback_used;          /* 1 if user scales were rejected for Jacobi           */
+    double eta;                 /* final eta estimate                                  */
+    double phibar;              /* final |bbar - Abar dm| estimate                     */
+} lsqr_info;
+
+typedef struct lsqr_ctx lsqr_ctx;
+
+/* Kernel timing (LSQR_FLAG_TIMING): totals over the last solve. */
+typedef struct {
+    double fwd_ms;              /* forward products Abar D v                          */
+    double adj_ms;              /* transposed products D Abar^T u                      */
+    int fwd_launches;
+    int adj_launches;
+    double fwd_bytes;           /* algorithmic bytes of one forward launch            */
+    double adj_bytes;           /* algorithmic bytes of one transposed launch         */
+} lsqr_kstats;
+
+/*
+ * lsqr_create — validate G, copy it to the device, build its transpose (CSC, a
+ * stable device sort by column so rows stay ascending within a column) and the
+ * column scaling.  damp >= 0 and smooth_weight >= 0 (damp > 0 is required by
+ * the mixed forms, whose refinement folds the FP64 correction into the damping
+ * block).  opts may be NULL (FP64, no scaling, default stream, hipMalloc).
+ * On success *out owns every derived buffer; free it with lsqr_destroy.
+ * Errors: INVALID_ARG, BAD_CSR, NONFINITE, DEVICE, OOM, UNSUPPORTED.
+ */
+lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
+                        const lsqr_opts *opts, lsqr_ctx **out);
+
+/*
+ * lsqr_solve — run LSQR (Paige & Saunders) on bbar = [dt; 0; 0] from x0 = 0.
+ *   dt        [m]   data right-hand side (vec_mem says host or device), finite
+ *   iters     >= 0  iteration limit K (forward products after the start)
+ *   tol       >= 0  stop when eta_k <= tol (0: run exactly K iterations)
+ *   dm        [n]   output solution (vec_mem)
+ *   res_hist  host [3*(K+1)] or NULL: row k = (phibar_{k+1} = |rbar_k| estimate,
+ *                   psi_k = |A_D^T rbar_k| estimate, eta_k); row 0 is the start
+ *                   (beta_1, alpha_1*beta_1, 1); rows past info.iters are NaN
+ *   info      output, may be NULL
+ * For the mixed forms (precision BF16/FP16) dm is refined in FP64 until
+ * eta <= tol (tol must be > 0) or opts.refine_sweeps sweeps; iters then caps
+ * each inner solve and res_hist receives the inner history of the last sweep.
+ * Errors: INVALID_ARG, NONFINITE (dt or a solver scalar), DEVICE, OOM.
+ */
+lsqr_status lsqr_solve(lsqr_ctx *ctx, const double *dt, lsqr_mem vec_mem, int iters, double tol,
+                       double *dm, double *res_hist, lsqr_info *info);
+
+/*
+ * lsqr_apply — y = Abar D x on the device: y[0:m] = G (D x),
+ * y[m:m+n] = w L (D x), y[m+n:m+2n] = lambda (D x).  x [n], y [m+2n], FP64,
+ * device pointers.  Uses the same kernel as the solver's forward product.
+ */
+lsqr_status lsqr_apply(lsqr_ctx *ctx, const double *x, double *y);
+
+/*
+ * lsqr_apply_t — x = D Abar^T y = D (G^T y[0:m] + w L y[m:m+n] + lambda y[m+n:]),
+ * device pointers, FP64.  Uses the stored transpose (no atomics).
+ */
+lsqr_status lsqr_apply_t(lsqr_ctx *ctx, const double *y, double *x);
+
+/*
+ * lsqr_get_scale — copy the column scaling d [n] (host buffer).
+ * lsqr_get_transpose — copy the device-built CSC of G to host buffers
+ * col_ptr [n+1], row_idx [nnz], val [nnz] (any may be NULL).
+ */
+lsqr_status lsqr_get_scale(const lsqr_ctx *ctx, double *d);
+lsqr_status lsqr_get_transpose(const lsqr_ctx *ctx, int64_t *col_ptr, int32_t *row_idx, double *val);
+
+/* lsqr_kernel_stats — kernel timing of the last solve (LSQR_FLAG_TIMING). */
+lsqr_status lsqr_kernel_stats(const lsqr_ctx *ctx, lsqr_kstats *out);
+
+/* lsqr_destroy — free every buffer of ctx (NULL is a no-op). */
+void lsqr_destroy(lsqr_ctx *ctx);
+
+/* lsqr_status_string — static text for a status code. */
+const char *lsqr_status_string(lsqr_status s);
+
+/* lsqr_last_error — message of the last failure on ctx; ctx == NULL gives the
+ * calling thread's message from a failed lsqr_create. */
+const char *lsqr_last_error(const lsqr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSQR_MI355X_H */

@@ -1,0 +1,262 @@
+"""Thin ctypes binding of the C ABI in include/lsqr_mi355x.h.
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+PyTorch supplies device memory (its caching allocator is handed to the
+library as the allocation callback) and the stream (torch's current stream).
+There is no CPU fallback: if the compiled library is missing this module
+raises on import of the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblsqr_mi355x.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "lsqr_mi355x.h")
+
+LSQR_OK, LSQR_E_INVALID_ARG, LSQR_E_BAD_CSR, LSQR_E_NONFINITE = 0, -1, -2, -3
+LSQR_E_DEVICE, LSQR_E_OOM, LSQR_E_UNSUPPORTED = -4, -5, -6
+MEM_HOST, MEM_DEVICE = 0, 1
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+PRECOND = {"none": 0, "jacobi": 1, "user": 2}
+FLAG_TIMING, FLAG_NO_GRAPH = 1, 2
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class LsqrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("mem", ctypes.c_int)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("precond", ctypes.c_int),
+                ("col_scale", ctypes.c_void_p), ("refine_sweeps", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("alloc", _ALLOC_FN), ("dealloc", _FREE_FN), ("alloc_user", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32), ("lanes_per_row", ctypes.c_int),
+                ("lanes_per_col", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("istop", ctypes.c_int), ("iters", ctypes.c_int), ("sweeps", ctypes.c_int),
+                ("fallback_used", ctypes.c_int), ("eta", ctypes.c_double),
+                ("phibar", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class KStats(ctypes.Structure):
+    _fields_ = [("fwd_ms", ctypes.c_double), ("adj_ms", ctypes.c_double),
+                ("fwd_launches", ctypes.c_int), ("adj_launches", ctypes.c_int),
+                ("fwd_bytes", ctypes.c_double), ("adj_bytes", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load the compiled library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2604_11920_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "lsqr_create": (I, [ctypes.POINTER(CSR), D, D, ctypes.POINTER(Opts), ctypes.POINTER(P)]),
+        "lsqr_solve": (I, [P, P, I, I, D, P, P, ctypes.POINTER(Info)]),
+        "lsqr_apply": (I, [P, P, P]),
+        "lsqr_apply_t": (I, [P, P, P]),
+        "lsqr_get_scale": (I, [P, P]),
+        "lsqr_get_transpose": (I, [P, P, P, P]),
+        "lsqr_kernel_stats": (I, [P, ctypes.POINTER(KStats)]),
+        "lsqr_destroy": (None, [P]),
+        "lsqr_status_string": (ctypes.c_char_p, [I]),
+        "lsqr_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_functions():
+    """Names of the functions declared in include/lsqr_mi355x.h."""
+    import re
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lsqr_[a-z_]+)\s*\(", txt)))
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data)
+    return ctypes.c_void_p(a.data_ptr())      # torch tensor
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+class Solver:
+    """One regularised LSQR system on the GPU (wraps an lsqr_ctx)."""
+
+    def __init__(self, row_ptr, col, val, nx, ny, nz, damp, smooth, precision="fp64",
+                 precond="none", col_scale=None, stream=None, timing=False, graph=True,
+                 lanes_per_row=0, lanes_per_col=0, check_every=0, refine_sweeps=5,
+                 torch_alloc=True):
+        import torch
+        lib = load()
+        self._torch = torch
+        self._keep = []
+        dev = all(_is_torch(a) for a in (row_ptr, col, val))
+        if not dev:
+            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            val = np.ascontiguousarray(val, dtype=np.float64)
+        self._keep += [row_ptr, col, val]
+        m = len(row_ptr) - 1
+        self.m, self.n = int(m), int(nx) * int(ny) * int(nz)
+        self.nnz = int(row_ptr[-1]) if not dev else int(row_ptr[-1].item())
+        csr = CSR(self.m, self.n, self.nnz, int(nx), int(ny), int(nz), _ptr(row_ptr), _ptr(col),
+                  _ptr(val), MEM_DEVICE if dev else MEM_HOST)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._device = torch.cuda.current_device()
+        opts = Opts()
+        opts.precision = PRECISION[precision]
+        opts.precond = PRECOND[precond]
+        if col_scale is not None:
+            cs = np.ascontiguousarray(col_scale, dtype=np.float64)
+            self._keep.append(cs)
+            opts.col_scale = cs.ctypes.data
+        opts.refine_sweeps = int(refine_sweeps)
+        opts.check_every = int(check_every)
+        opts.stream = stream.cuda_stream
+        opts.flags = (FLAG_TIMING if timing else 0) | (0 if graph else FLAG_NO_GRAPH)
+        opts.lanes_per_row = int(lanes_per_row)
+        opts.lanes_per_col = int(lanes_per_col)
+        if torch_alloc:
+            self._blocks = {}
+            sp = stream
+
+            def _alloc(nbytes, user):
+                try:
+                    p = torch.cuda.caching_allocator_alloc(int(nbytes), self._device, sp)
+                except Exception:
+                    return None
+                self._blocks[p] = nbytes
+                return p
+
+            def _free(p, nbytes, user):
+                if p in self._blocks:
+                    del self._blocks[p]
+                    torch.cuda.caching_allocator_delete(p)
+
+            self._alloc_cb, self._free_cb = _ALLOC_FN(_alloc), _FREE_FN(_free)
+            opts.alloc, opts.dealloc = self._alloc_cb, self._free_cb
+        ctx = ctypes.c_void_p()
+        rc = lib.lsqr_create(ctypes.byref(csr), float(damp), float(smooth), ctypes.byref(opts),
+                             ctypes.byref(ctx))
+        if rc != LSQR_OK:
+            raise LsqrError(rc, lib.lsqr_last_error(None).decode())
+        self._ctx = ctx
+        self._lib = lib
+
+    @classmethod
+    def from_system(cls, s, **kw):
+        kw.setdefault("damp", s.damp)
+        kw.setdefault("smooth", s.smooth)
+        return cls(s.row_ptr, s.col, s.val, s.nx, s.ny, s.nz, **kw)
+
+    def _check(self, rc):
+        if rc != LSQR_OK:
+            raise LsqrError(rc, self._lib.lsqr_last_error(self._ctx).decode())
+
+    def solve(self, dt, iters, tol=0.0, dm=None, history=True):
+        """Run LSQR.  dt: numpy (host) or torch CUDA float64 tensor (device).
+        Returns (dm, hist [iters+1, 3] or None, info dict)."""
+        torch = self._torch
+        if _is_torch(dt):
+            assert dt.is_cuda and dt.dtype == torch.float64 and dt.is_contiguous()
+            mem = MEM_DEVICE
+            if dm is None:
+                dm = torch.empty(self.n, dtype=torch.float64, device=dt.device)
+        else:
+            dt = np.ascontiguousarray(dt, dtype=np.float64)
+            mem = MEM_HOST
+            if dm is None:
+                dm = np.empty(self.n)
+        hist = np.empty((iters + 1, 3)) if history else None
+        info = Info()
+        self._check(self._lib.lsqr_solve(self._ctx, _ptr(dt), mem, int(iters), float(tol),
+                                         _ptr(dm), _ptr(hist), ctypes.byref(info)))
+        return dm, hist, info.as_dict()
+
+    def apply(self, x, y=None):
+        """y = Abar D x (device tensors, float64)."""
+        if y is None:
+            y = self._torch.empty(self.m + 2 * self.n, dtype=self._torch.float64, device=x.device)
+        self._check(self._lib.lsqr_apply(self._ctx, _ptr(x), _ptr(y)))
+        return y
+
+    def apply_t(self, y, x=None):
+        """x = D Abar^T y (device tensors, float64)."""
+        if x is None:
+            x = self._torch.empty(self.n, dtype=self._torch.float64, device=y.device)
+        self._check(self._lib.lsqr_apply_t(self._ctx, _ptr(y), _ptr(x)))
+        return x
+
+    def scale(self):
+        d = np.empty(self.n)
+        self._check(self._lib.lsqr_get_scale(self._ctx, _ptr(d)))
+        return d
+
+    def transpose(self):
+        cp = np.empty(self.n + 1, dtype=np.int64)
+        ri = np.empty(self.nnz, dtype=np.int32)
+        cv = np.empty(self.nnz, dtype=np.float64)
+        self._check(self._lib.lsqr_get_transpose(self._ctx, _ptr(cp), _ptr(ri), _ptr(cv)))
+        return cp, ri, cv
+
+    def kernel_stats(self):
+        ks = KStats()
+        self._check(self._lib.lsqr_kernel_stats(self._ctx, ctypes.byref(ks)))
+        return {f: getattr(ks, f) for f, _ in ks._fields_}
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.lsqr_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,72 @@
+"""Full-size parity on the paper-shaped system (~0.49M rows, ~0.59B entries,
+128,000 unknowns) in the launch configuration the benchmark times.
+
+The oracle computes every output of the seeded operator products and the
+first iterates; over the benchmark's 300 iterations the checks are
+properties that hold at any size (monotone residual norm, the residual
+estimate against the explicit residual of the returned solution)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+from _helpers import eta_explicit
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def big():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    s = synth.make_system(synth.config1())
+    print(f"[fullsize] m={s.m} n={s.n} nnz={s.nnz}", flush=True)
+    op = oracle.Operator.from_system(s, nthreads=16)
+    from paper_2604_11920_amd import Solver
+    sol = Solver.from_system(s)
+    yield s, op, sol
+    sol.close()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_fullsize_operator(big):
+    s, op, sol = big
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(s.n)
+    ybar = rng.standard_normal(op.mbar)
+    yg = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    xg = sol.apply_t(torch.from_numpy(ybar).cuda()).cpu().numpy()
+    eps = 2.0 ** -52
+    absG = sp.csr_matrix((np.abs(s.val), s.col, s.row_ptr), shape=(s.m, s.n))
+    bd = 2 * (np.diff(s.row_ptr) + 2) * eps * (absG @ np.abs(x))
+    assert np.all(np.abs(yg[:s.m] - op.apply(x)[:s.m]) <= bd)
+    lc = np.bincount(s.col, minlength=s.n)
+    bt = 2 * (lc + 4) * eps * (absG.T @ np.abs(ybar[:s.m]) + 6 * np.abs(ybar[s.m:]).max())
+    assert np.all(np.abs(xg - op.apply_t(ybar)) <= bt)
+
+
+def test_fullsize_first_iterates(big):
+    s, op, sol = big
+    for K in (1, 3):
+        ref = op.lsqr(s.dt, K)
+        dm, hist, info = sol.solve(s.dt, K)
+        assert rel(dm, ref["x"]) <= 1e-10, K
+        assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0)
+
+
+def test_fullsize_300_iterations(big):
+    s, op, sol = big
+    dm, hist, info = sol.solve(torch.from_numpy(s.dt).cuda(), 300)
+    dm = dm.cpu().numpy()
+    assert info["iters"] == 300 and info["istop"] == 2
+    assert np.all(np.diff(hist[:, 0]) <= 1e-13 * hist[0, 0])
+    # explicit residuals of the returned solution (SciPy operator, not the oracle)
+    eta, rn = eta_explicit(s, dm)
+    assert abs(rn - hist[-1, 0]) <= 1e-6 * hist[-1, 0]
+    assert 0.5 * hist[-1, 2] <= eta <= 2.0 * hist[-1, 2]

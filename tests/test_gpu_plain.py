@@ -1,0 +1,268 @@
+"""GPU parity of the plain FP64 path against the FP64 CPU oracle.
+
+Parity bars (the oracle's own summation-order sensitivity, measured in
+test_oracle_pins.py, decides what a fixed iteration count can promise):
+  * iterates x_k for k <= 8 and converged solutions (eta <= 1e-13): <= 1e-10
+    relative, the bound the plain form must meet;
+  * fixed counts past the loss of orthogonality (K = 100): the residual-norm
+    history within 1e-3 relative and the GPU/oracle gap a small fraction of
+    the distance to the solution, as for two valid orders of summation;
+  * integer-valued operators: bitwise.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+from _helpers import eta_explicit
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def Solver(*a, **k):
+    from paper_2604_11920_amd import Solver as S
+    return S(*a, **k)
+
+
+def from_sys(s, **k):
+    from paper_2604_11920_amd import Solver as S
+    return S.from_system(s, **k)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def ragged_system(seed=0, integer=False):
+    """Rows of 0..700 entries (empty rows, rows longer than the unrolled
+    lane span) and columns that no row touches; several workgroups' worth."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = 7, 5, 6
+    n = nx * ny * nz
+    m = 900
+    lens = rng.integers(0, 40, size=m)
+    lens[rng.choice(m, 30, replace=False)] = rng.integers(200, 700, size=30)
+    lens[:5] = 0
+    avail = np.arange(n - 17)          # the last 17 columns stay empty
+    row_ptr = np.zeros(m + 1, np.int64)
+    row_ptr[1:] = np.cumsum(np.minimum(lens, len(avail)))
+    col = np.concatenate([np.sort(rng.choice(avail, size=row_ptr[i + 1] - row_ptr[i],
+                                             replace=False)) for i in range(m)]).astype(np.int32)
+    if integer:
+        val = rng.integers(-8, 9, size=len(col)).astype(np.float64)
+        dt = rng.integers(-8, 9, size=m).astype(np.float64)
+    else:
+        val = rng.standard_normal(len(col))
+        dt = rng.standard_normal(m)
+    return synth.RandomSystem(m=m, n=n, nx=nx, ny=ny, nz=nz, row_ptr=row_ptr, col=col, val=val,
+                              dt=dt, damp=0.25 if integer else 0.1, smooth=0.5)
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    return synth.make_system(synth.config0())
+
+
+@pytest.fixture(scope="module")
+def cfg0_xstar(cfg0):
+    return oracle.lsqr(cfg0, 40000, tol=1e-13)["x"]
+
+
+# ------------------------------------------------------------ operator ------
+@pytest.mark.parametrize("which", ["ragged", "cfg0"])
+def test_transpose_matches_library_csc(which, cfg0):
+    s = ragged_system(1) if which == "ragged" else cfg0
+    with from_sys(s) as sol:
+        cp, ri, cv = sol.transpose()
+    ref = sp.csr_matrix((s.val, s.col, s.row_ptr), shape=(s.m, s.n)).tocsc()
+    ref.sort_indices()
+    assert np.array_equal(cp, ref.indptr) and np.array_equal(ri, ref.indices)
+    assert np.array_equal(cv, ref.data)
+
+
+@pytest.mark.parametrize("lanes", [0, 4, 16, 64])
+def test_operator_integer_bitwise(lanes):
+    s = ragged_system(2, integer=True)
+    op = oracle.Operator.from_system(s)
+    rng = np.random.default_rng(3)
+    x = rng.integers(-8, 9, size=s.n).astype(np.float64)
+    ybar = rng.integers(-8, 9, size=op.mbar).astype(np.float64)
+    with from_sys(s, lanes_per_row=lanes, lanes_per_col=lanes) as sol:
+        yg = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+        xg = sol.apply_t(torch.from_numpy(ybar).cuda()).cpu().numpy()
+    assert np.array_equal(yg, op.apply(x))
+    assert np.array_equal(xg, op.apply_t(ybar))
+
+
+def test_jacobi_scale_within_rounding(cfg0):
+    s = cfg0
+    d = oracle.Operator.from_system(s).jacobi()
+    with from_sys(s, precond="jacobi") as sol:
+        dg = sol.scale()
+    # sums of L_j positive squares in two orders: relative gap <= (L_j + 4) eps
+    lcol = np.bincount(s.col, minlength=s.n)
+    assert np.all(np.abs(dg - d) <= (lcol + 4) * 2.0 ** -52 * d)
+
+
+@pytest.mark.parametrize("precond", ["none", "user"])
+def test_operator_random_within_rounding(cfg0, precond):
+    s = cfg0
+    # a power-of-two column scale is applied exactly on both sides
+    d = 2.0 ** np.random.default_rng(8).integers(-3, 4, s.n) if precond == "user" else None
+    op = oracle.Operator.from_system(s, d=d)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(s.n)
+    ybar = rng.standard_normal(op.mbar)
+    with from_sys(s, precond=precond, col_scale=d) as sol:
+        if d is not None:
+            assert np.array_equal(sol.scale(), d)
+        yg = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+        xg = sol.apply_t(torch.from_numpy(ybar).cuda()).cpu().numpy()
+    # two valid summation orders of an L-term sum differ by at most
+    # 2 L eps sum|terms|; the 7-point rows have at most 7 terms of size <= 12 max|z|
+    eps = 2.0 ** -52
+    dd = np.ones(s.n) if d is None else d
+    z = dd * x
+    absG = sp.csr_matrix((np.abs(s.val), s.col, s.row_ptr), shape=(s.m, s.n))
+    lr = np.diff(s.row_ptr)
+    bd = np.r_[2 * (lr + 2) * eps * (absG @ np.abs(z)),
+               np.full(s.n, 2 * 9 * eps * s.smooth * 12 * np.abs(z).max()),
+               np.full(s.n, eps * s.damp * np.abs(z).max())]
+    assert np.all(np.abs(yg - op.apply(x)) <= bd)
+    yG, yL, yD = ybar[:s.m], ybar[s.m:s.m + s.n], ybar[s.m + s.n:]
+    lc = np.bincount(s.col, minlength=s.n)
+    bt = 2 * (lc + 4) * eps * dd * (absG.T @ np.abs(yG) + s.smooth * 12 * np.abs(yL).max()
+                                    + s.damp * np.abs(yD))
+    assert np.all(np.abs(xg - op.apply_t(ybar)) <= bt)
+
+
+# --------------------------------------------------------------- solves -----
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_early_iterates_strict(cfg0, precond):
+    s = cfg0
+    d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
+    op = oracle.Operator.from_system(s, d=d)
+    with from_sys(s, precond=precond) as sol:
+        for K in (1, 2, 3, 5, 8):
+            ref = op.lsqr(s.dt, K)
+            dm, hist, info = sol.solve(s.dt, K)
+            assert info["iters"] == K and info["istop"] == 2
+            assert rel(dm, ref["x"]) <= 1e-10, (K, rel(dm, ref["x"]))
+            assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0), K
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_converged_strict(cfg0, cfg0_xstar, precond):
+    s = cfg0
+    d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
+    ref = oracle.Operator.from_system(s, d=d).lsqr(s.dt, 40000, tol=1e-13)
+    with from_sys(s, precond=precond) as sol:
+        dm, hist, info = sol.solve(s.dt, 40000, tol=1e-13)
+    assert info["istop"] == 1 and ref["istop"] == 1
+    assert info["eta"] <= 1e-13
+    assert rel(dm, ref["x"]) <= 1e-10
+    assert rel(dm, cfg0_xstar) <= 1e-10
+    # the iteration counts of two valid summation orders differ only slightly
+    assert abs(info["iters"] - ref["iters"]) <= 0.1 * ref["iters"]
+
+
+def test_fixed_100_iterations(cfg0, cfg0_xstar):
+    s = cfg0
+    ref = oracle.lsqr(s, 100)
+    with from_sys(s) as sol:
+        dm, hist, info = sol.solve(s.dt, 100)
+    assert info["iters"] == 100 and info["istop"] == 2
+    # the oracle against itself (compensated vs plain sums) shows residual-norm
+    # gaps up to 1.1e-3 relative around k = 20 on this system; allow 5x that
+    assert np.all(np.abs(hist[:, 0] - ref["hist"][:, 0]) <= 5e-3 * ref["hist"][:, 0])
+    assert abs(hist[-1, 0] - ref["hist"][-1, 0]) <= 1e-4 * ref["hist"][-1, 0]
+    assert np.all(np.diff(hist[:, 0]) <= 1e-14 * hist[0, 0])       # monotone |r|
+    gap = np.linalg.norm(dm - ref["x"])
+    assert gap <= 0.1 * np.linalg.norm(ref["x"] - cfg0_xstar), gap
+
+
+def test_tolerance_stop(cfg0):
+    s = cfg0
+    tol = 1e-6
+    ref = oracle.lsqr(s, 20000, tol=tol)
+    with from_sys(s, check_every=16) as sol:
+        dm, hist, info = sol.solve(s.dt, 20000, tol=tol)
+    assert info["istop"] == 1 and info["eta"] <= tol
+    assert abs(info["iters"] - ref["iters"]) <= 0.1 * ref["iters"] + 2
+    assert np.isnan(hist[info["iters"] + 1:]).all()
+    # the estimate matches the explicit normal-equation residual of the returned dm
+    eta, _ = eta_explicit(s, dm)
+    assert eta <= 2 * tol
+
+
+def test_ragged_system_strict():
+    s = ragged_system(5)
+    for K in (1, 4, 8):
+        ref = oracle.lsqr(s, K)
+        with from_sys(s) as sol:
+            dm, hist, info = sol.solve(s.dt, K)
+        assert rel(dm, ref["x"]) <= 1e-10, K
+
+
+def test_small_shapes():
+    for grid in [(1, 1, 1), (1, 1, 3), (2, 1, 1), (3, 2, 1)]:
+        s = synth.random_system(25, *grid, row_len=(0, 4), seed=sum(grid))
+        ref = oracle.lsqr(s, 3)
+        with from_sys(s) as sol:
+            dm, hist, info = sol.solve(s.dt, 3)
+        assert rel(dm, ref["x"]) <= 1e-10 or info["istop"] in (1, 3), grid
+
+
+def test_degenerate_right_hand_sides(cfg0):
+    with from_sys(cfg0) as sol:
+        dm, hist, info = sol.solve(np.zeros(cfg0.m), 10)
+        assert info["istop"] == 0 and np.all(dm == 0) and np.all(hist[0] == 0)
+        dm, hist, info = sol.solve(cfg0.dt, 0)
+        assert info["istop"] == 2 and info["iters"] == 0 and np.all(dm == 0)
+        with pytest.raises(Exception):
+            bad = cfg0.dt.copy()
+            bad[17] = np.nan
+            sol.solve(bad, 5)
+    z = synth.RandomSystem(m=2, n=1, nx=1, ny=1, nz=1, row_ptr=np.array([0, 1, 2], np.int64),
+                           col=np.zeros(2, np.int32), val=np.array([1.0, 1.0]),
+                           dt=np.array([1.0, -1.0]), damp=0.1, smooth=0.5)
+    with from_sys(z) as sol:
+        dm, hist, info = sol.solve(z.dt, 10)
+    assert info["istop"] == 0 and np.all(dm == 0)
+
+
+def test_device_inputs_and_determinism(cfg0):
+    s = cfg0
+    with from_sys(s) as sol:
+        dm_h, _, _ = sol.solve(s.dt, 60)
+        dm_h2, _, _ = sol.solve(s.dt, 60)
+    assert np.array_equal(dm_h, dm_h2)                    # run to run, bitwise
+    with from_sys(s, graph=False) as sol:
+        dm_e, _, _ = sol.solve(s.dt, 60)
+    assert np.array_equal(dm_h, dm_e)                     # graph replay == eager
+    dev = [torch.from_numpy(a).cuda() for a in (s.row_ptr, s.col, s.val)]
+    with Solver(*dev, s.nx, s.ny, s.nz, s.damp, s.smooth) as sol:
+        dm_d, _, _ = sol.solve(torch.from_numpy(s.dt).cuda(), 60)
+    assert np.array_equal(dm_d.cpu().numpy(), dm_h)
+
+
+def test_timing_counters(cfg0):
+    with from_sys(cfg0, timing=True) as sol:
+        dm, _, info = sol.solve(cfg0.dt, 20)
+        ks = sol.kernel_stats()
+    assert ks["fwd_launches"] == 20 and ks["adj_launches"] == 20
+    assert ks["fwd_ms"] > 0 and ks["adj_ms"] > 0
+    assert ks["fwd_bytes"] > 12 * cfg0.nnz and ks["adj_bytes"] > 12 * cfg0.nnz
+    with from_sys(cfg0) as sol:
+        dm_g, _, _ = sol.solve(cfg0.dt, 20)
+    assert np.array_equal(dm, dm_g)          # event timing does not change the arithmetic
