@@ -99,6 +99,72 @@ def measured_traffic(tag):
     return float(v) if v else None
 
 
+
+def fp32_rate(s, dt, iters, steps=3):
+    """FP32 values, vectors and accumulation (FP64 scalars): iterations/s and
+    kernel rates on the same system, same iteration count."""
+    import torch
+    from paper_2604_11920_amd import Solver
+    with Solver.from_system(s, precision="fp32", timing=True) as sol:
+        dm = torch.empty(s.n, dtype=torch.float64, device="cuda")
+        sol.solve(dt, iters, dm=dm, history=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fwd = adj = 0.0
+        nf = na = 0
+        for _ in range(steps):
+            sol.solve(dt, iters, dm=dm, history=False)
+            ks = sol.kernel_stats()
+            fwd += ks["fwd_ms"]; adj += ks["adj_ms"]; nf += ks["fwd_launches"]; na += ks["adj_launches"]
+        wall = time.perf_counter() - t0
+    fa, aa = fwd / nf, adj / na
+    r = {"iters_per_s": iters * steps / wall, "ms_per_step": wall * 1e3 / steps,
+         "fwd": {"avg_us": fa * 1e3, "alg_bytes": ks["fwd_bytes"], "gbs": ks["fwd_bytes"] / fa / 1e6},
+         "adj": {"avg_us": aa * 1e3, "alg_bytes": ks["adj_bytes"], "gbs": ks["adj_bytes"] / aa / 1e6}}
+    log(f"[bench] fp32: {r['iters_per_s']:.1f} it/s; fwd {r['fwd']['gbs']:.0f} GB/s, "
+        f"adj {r['adj']['gbs']:.0f} GB/s")
+    return r
+
+
+def time_to_tol(s, dt, tol):
+    """Wall time to eta = |Abar^T r| / |Abar^T bbar| <= tol for each form, each
+    result's eta re-checked explicitly with the FP64 operator on the GPU."""
+    import torch
+    from paper_2604_11920_amd import Solver
+    forms = [("fp64", "none", 20000), ("fp64", "jacobi", 20000), ("bf16", "jacobi", 4000),
+             ("fp16", "jacobi", 4000)]
+    out = {}
+    ref = None
+    checker = Solver.from_system(s)
+    b = torch.zeros(s.m + 2 * s.n, dtype=torch.float64, device="cuda")
+    b[:s.m] = dt
+    atb = checker.apply_t(b).norm().item()
+    for prec, pc, cap in forms:
+        with Solver.from_system(s, precision=prec, precond=pc, refine_sweeps=8) as sol:
+            dm = torch.empty(s.n, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info = sol.solve(dt, cap, tol=tol, dm=dm, history=False)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        r = b - checker.apply(dm)
+        eta = checker.apply_t(r).norm().item() / atb
+        key = f"{prec}_{pc}"
+        out[key] = {"seconds": wall, "iters": info["iters"], "sweeps": info["sweeps"],
+                    "istop": info["istop"], "eta_fp64": eta}
+        if prec == "fp64" and pc == "jacobi":
+            ref = dm.clone()
+        if ref is not None and prec != "fp64":
+            out[key]["rel_diff_vs_fp64_jacobi"] = ((dm - ref).norm() / ref.norm()).item()
+        log(f"[bench] time-to-tol {key}: {wall:.2f}s, iters={info['iters']} "
+            f"sweeps={info['sweeps']} istop={info['istop']} eta_fp64={eta:.2e}")
+    checker.close()
+    base = out["fp64_none"]["seconds"]
+    for k in out:
+        out[k]["speedup_vs_fp64_none"] = base / out[k]["seconds"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +174,10 @@ def main():
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--row-format", default="auto", choices=["auto", "csr", "runs"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP32 rate and the time-to-tolerance comparisons")
+    ap.add_argument("--ttt-tol", type=float, default=1e-6)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -145,7 +215,7 @@ def main():
     log(f"[bench] generated {args.config}: m={s.m} n={s.n} nnz={s.nnz} "
         f"in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    sol = Solver.from_system(s, timing=True)
+    sol = Solver.from_system(s, timing=True, row_format=args.row_format)
     torch.cuda.synchronize()
     log(f"[bench] create (copy + device transpose) {time.perf_counter() - t0:.2f}s")
     dt = torch.from_numpy(s.dt).cuda()
@@ -203,7 +273,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": workload, "m": s.m, "n": s.n, "nnz": s.nnz,
-                   "iters_per_step": iters, "precision": "fp64", "precond": "none"},
+                   "iters_per_step": iters, "precision": "fp64", "precond": "none",
+                   "row_format": args.row_format},
         "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "kernel": "k_fwd (forward CSR product)" if dom == "fwd"
@@ -213,6 +284,10 @@ def main():
         "paper_protocol_ms_per_step": 1e3 * sum(trimmed) / len(trimmed),
     }
     sol.close()
+    del sol
+    if not args.no_extras:
+        out["fp32"] = fp32_rate(s, dt, iters)
+        out["time_to_tol"] = time_to_tol(s, dt, args.ttt_tol)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_iters)

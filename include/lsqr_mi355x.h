@@ -53,9 +53,13 @@ typedef enum {
 typedef enum { LSQR_MEM_HOST = 0, LSQR_MEM_DEVICE = 1 } lsqr_mem;
 
 /* Storage/arithmetic of the sparse products.  FP64: FP64 values, vectors and
- * accumulation.  FP32: FP32 values, vectors and accumulation, FP64 scalars and
- * norms.  BF16/FP16: quantised values with per-row scales inside FP64
- * iterative refinement (see lsqr_create). */
+ * accumulation.  FP32: FP32 values, vectors and accumulation; LSQR scalars,
+ * norms and x, w stay FP64.  BF16/FP16: each data row i is stored as a
+ * power-of-two FP32 scale sigma_i times 16-bit codes q_ij = RNE(g_ij/sigma_i)
+ * (rounded once, directly from FP64); the inner LSQR runs on these with FP32
+ * vectors and accumulation and FP64 scalars, inside an FP64 iterative
+ * refinement whose residuals use the FP64 operator (see lsqr_solve).  The
+ * smoothing and damping rows are never quantised. */
 typedef enum { LSQR_FP64 = 0, LSQR_FP32 = 1, LSQR_BF16 = 2, LSQR_FP16 = 3 } lsqr_precision;
 
 /* Column scaling D.  NONE: D = I.  JACOBI: d_j = 1 / |column j of Abar|
@@ -93,6 +97,10 @@ typedef struct {
     uint32_t flags;             /* LSQR_FLAG_*                                         */
     int lanes_per_row;          /* 0 = auto; else 4, 8, 16, 32 or 64 lanes per row    */
     int lanes_per_col;          /* 0 = auto; same choices for the transposed product   */
+    int row_format;             /* data rows of the forward product: 0 = auto (depth  */
+                                /* runs when runs average >= 2.5 columns), 1 = plain  */
+                                /* CSR, 2 = depth runs (runs of consecutive columns,  */
+                                /* i.e. of depth nodes under one lateral node, eq. 7) */
 } lsqr_opts;
 
 /* Stop reasons (info.istop):
@@ -138,6 +146,14 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
 
 /*
  * lsqr_solve — run LSQR (Paige & Saunders) on bbar = [dt; 0; 0] from x0 = 0.
+ * BF16/FP16 forms: each refinement sweep forms rbar = bbar - Abar dm, the
+ * exact eta = |Abar^T rbar| / |Abar^T bbar| and g - ghat = (G - Ghat)^T r_G in
+ * FP64, then runs the inner LSQR on [Ghat; w L; lambda I] D with right-hand
+ * side [r_G; r_L; r_D + (g - ghat)/lambda] (so that its normal-equation
+ * residual equals Abar^T rbar exactly) to a relative eta of 1e-3, and adds
+ * the correction; the solve stops when eta <= tol (istop 1), after
+ * opts.refine_sweeps sweeps (istop 2), or when a sweep fails to halve eta
+ * (istop 4).
  *   dt        [m]   data right-hand side (vec_mem says host or device), finite
  *   iters     >= 0  iteration limit K (forward products after the start)
  *   tol       >= 0  stop when eta_k <= tol (0: run exactly K iterations)
@@ -174,6 +190,16 @@ lsqr_status lsqr_apply_t(lsqr_ctx *ctx, const double *y, double *x);
  */
 lsqr_status lsqr_get_scale(const lsqr_ctx *ctx, double *d);
 lsqr_status lsqr_get_transpose(const lsqr_ctx *ctx, int64_t *col_ptr, int32_t *row_idx, double *val);
+
+/*
+ * lsqr_get_quantised — the BF16/FP16 forms' stored values, for inspection:
+ * row_scale [m] (FP32 powers of two), q_rows [nnz] (16-bit codes in CSR order)
+ * and q_cols [nnz] (the same codes in CSC order); host buffers, any may be
+ * NULL.  Entry (i, j) of the quantised G is row_scale[i] * q.  UNSUPPORTED for
+ * the FP64/FP32 forms.
+ */
+lsqr_status lsqr_get_quantised(const lsqr_ctx *ctx, float *row_scale, uint16_t *q_rows,
+                               uint16_t *q_cols);
 
 /* lsqr_kernel_stats — kernel timing of the last solve (LSQR_FLAG_TIMING). */
 lsqr_status lsqr_kernel_stats(const lsqr_ctx *ctx, lsqr_kstats *out);

@@ -1,8 +1,9 @@
 // Host runtime of the C ABI declared in lsqr_mi355x.h.
 //
 // Owns validation, device buffers (through the caller's allocator), the
-// transpose and scale set-up, the iteration schedule on the caller's stream,
-// optional hipGraph replay of blocks of iterations, and read-back of the stop
+// transpose, depth-run, scale and quantisation set-up, the iteration schedule
+// on the caller's stream (hipGraph replay of blocks of iterations), the FP64
+// iterative refinement of the quantised forms, and read-back of the stop
 // state and residual history.
 #include <math.h>
 #include <string.h>
@@ -16,9 +17,32 @@
 
 using namespace lsqr;
 
+namespace {
+
+// One LSQR kernel set: the stored formats it reads, its vector type and its
+// work buffers, loop state and captured graph.
+struct Engine {
+    int vec = VT_F64;
+    RowFmt R;
+    ColFmt C;
+    int g_fwd = 1, g_adj = 1, g_upd = 1;
+    void *T[2] = {nullptr, nullptr};
+    void *Ts = nullptr;            // sigma * t for the quantised forms
+    void *q = nullptr, *v = nullptr, *z = nullptr, *vzero = nullptr;
+    double *w = nullptr, *y = nullptr;
+    double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
+    double *S = nullptr;
+    int64_t s_rows = 0;
+    int *ctl = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_iters = 0;
+    double graph_tol = -1.0;
+};
+
+}  // namespace
+
 struct lsqr_ctx {
     Problem P;
-    Geometry g;
     Allocator al;
     hipStream_t st = nullptr;
     hipStream_t cap_st = nullptr;   // private stream used only for graph capture
@@ -27,27 +51,32 @@ struct lsqr_ctx {
     lsqr_precond precond = LSQR_PRECOND_NONE;
     uint32_t flags = 0;
     int check_every = 32;
+    int refine_sweeps = 5;
     int fallback_used = 0;
     std::vector<std::pair<void *, size_t>> owned;
-    // operator
+    // FP64 operator: CSR, depth runs, CSC, column scale
     int64_t *rp = nullptr; int32_t *ci = nullptr; double *va = nullptr;
+    int64_t *run_ptr = nullptr; uint32_t *runs = nullptr; uint16_t *roff = nullptr;
+    int64_t nruns = 0;
     int64_t *cp = nullptr; int32_t *ri = nullptr; double *cv = nullptr;
-    double *d = nullptr;
-    // work
-    double *T[2] = {nullptr, nullptr};
-    double *q = nullptr, *v = nullptr, *w = nullptr, *y = nullptr, *z = nullptr;
-    double *vzero = nullptr, *dtbuf = nullptr, *dmbuf = nullptr;
-    double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
-    double *S = nullptr;
-    int64_t s_rows = 0;
-    int *ctl = nullptr;
+    double *d = nullptr, *ones = nullptr;
+    RowFmt R64;
+    ColFmt C64;
+    // reduced-precision copies
+    float *va32 = nullptr, *cv32 = nullptr;
+    float *sigma = nullptr;
+    uint16_t *qrow = nullptr, *qcol = nullptr;
+    ColFmt CQ;                      // quantised transpose (FP64 refinement product)
+    Engine eng;                     // the solver's kernel set
+    // refinement and operator scratch (FP64)
+    double *xbuf = nullptr, *ybuf = nullptr, *rbar = nullptr, *rs = nullptr, *gbuf = nullptr;
+    double *ghat = nullptr, *fbuf = nullptr, *Pr = nullptr, *Pa = nullptr, *Pf = nullptr;
+    double *sums = nullptr;
+    int g_ref = 1;
+    double *dtbuf = nullptr, *dmbuf = nullptr;
     int *flag = nullptr;
-    int *hctl = nullptr;            // pinned host mirror of the control words
-    // graph of `graph_iters` iterations (even), rebuilt when S moves
-    hipGraphExec_t gexec = nullptr;
-    int graph_iters = 0;
-    double graph_tol = -1.0;
-    // timing
+    int *hctl = nullptr;            // pinned host mirror of control words
+    double *hsum = nullptr;         // pinned host mirror of reductions
     std::vector<hipEvent_t> ev;
     lsqr_kstats ks{};
     std::string err;
@@ -84,14 +113,18 @@ struct DeviceGuard {
     }
 };
 
+void *ctx_alloc_bytes(lsqr_ctx *c, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    void *p = c->al.get(bytes);
+    if (p) c->owned.push_back({p, bytes});
+    return p;
+}
+
 template <class T>
 T *ctx_alloc(lsqr_ctx *c, size_t count)
 {
-    size_t bytes = count * sizeof(T);
-    if (bytes == 0) bytes = sizeof(T);
-    void *p = c->al.get(bytes);
-    if (p) c->owned.push_back({p, bytes});
-    return (T *)p;
+    return (T *)ctx_alloc_bytes(c, count * sizeof(T));
 }
 
 void ctx_release(lsqr_ctx *c, void *p)
@@ -122,9 +155,9 @@ lsqr_status validate_host_csr(const lsqr_csr *G)
             int b = 0;
             for (int64_t i = m * t / nt; i < m * (t + 1) / nt; ++i)
                 for (int64_t p = G->row_ptr[i]; p < G->row_ptr[i + 1]; ++p) {
-                    const int32_t c = G->col_idx[p];
-                    if (c < 0 || c >= n) b |= 2;
-                    if (p > G->row_ptr[i] && c <= G->col_idx[p - 1]) b |= 4;
+                    const int32_t cc = G->col_idx[p];
+                    if (cc < 0 || cc >= n) b |= 2;
+                    if (p > G->row_ptr[i] && cc <= G->col_idx[p - 1]) b |= 4;
                     if (!isfinite(G->val[p])) b |= 8;
                 }
             bad[t] = b;
@@ -135,6 +168,63 @@ lsqr_status validate_host_csr(const lsqr_csr *G)
     if (all & 4) return fail(nullptr, LSQR_E_BAD_CSR, "columns not strictly increasing within a row");
     if (all & 8) return fail(nullptr, LSQR_E_NONFINITE, "non-finite value in G");
     return LSQR_OK;
+}
+
+// Depth runs of a CSR: maximal stretches of consecutive columns within a row
+// (eq. 7 orders unknowns depth fastest, so each lateral node of a ray gives a
+// run of depths), split at 255 entries.  run = (first column << 8) | length;
+// roff = offset of the run's first value within its row.  Returns false when
+// the format cannot hold the matrix (row longer than 65535 or n >= 2^24).
+bool build_runs_host(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
+                     std::vector<int64_t> &run_ptr, std::vector<uint32_t> &runs,
+                     std::vector<uint16_t> &roff)
+{
+    if (n >= (1 << 24)) return false;
+    for (int64_t i = 0; i < m; ++i)
+        if (rp[i + 1] - rp[i] > 65535) return false;
+    run_ptr.assign((size_t)m + 1, 0);
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (rp[m] < (1 << 20)) nt = 1;
+    auto is_start = [&](int64_t i, int64_t p, int64_t len) {
+        return p == rp[i] || ci[p] != ci[p - 1] + 1 || len == 255;
+    };
+    {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t]() {
+                for (int64_t i = m * t / nt; i < m * (t + 1) / nt; ++i) {
+                    int64_t cnt = 0, len = 0;
+                    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+                        if (is_start(i, p, len)) { ++cnt; len = 0; }
+                        ++len;
+                    }
+                    run_ptr[i + 1] = cnt;
+                }
+            });
+        for (auto &x : th) x.join();
+    }
+    for (int64_t i = 0; i < m; ++i) run_ptr[i + 1] += run_ptr[i];
+    runs.resize((size_t)run_ptr[m]);
+    roff.resize((size_t)run_ptr[m]);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int64_t i = m * t / nt; i < m * (t + 1) / nt; ++i) {
+                int64_t r = run_ptr[i] - 1, len = 0;
+                for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+                    if (is_start(i, p, len)) {
+                        if (r >= run_ptr[i]) runs[r] = ((uint32_t)ci[p - len] << 8) | (uint32_t)len;
+                        ++r;
+                        len = 0;
+                        roff[r] = (uint16_t)(p - rp[i]);
+                    }
+                    ++len;
+                }
+                if (r >= run_ptr[i]) runs[r] = ((uint32_t)ci[rp[i + 1] - len] << 8) | (uint32_t)len;
+            }
+        });
+    for (auto &x : th) x.join();
+    return true;
 }
 
 int pick_lanes(double avg)
@@ -148,52 +238,192 @@ int pick_lanes(double avg)
 
 bool valid_lanes(int l) { return l == 4 || l == 8 || l == 16 || l == 32 || l == 64; }
 
-lsqr_status ensure_state(lsqr_ctx *c, int iters)
+int cap_blocks(int64_t work, int per, int cap)
+{
+    int64_t b = (work + per - 1) / per;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+lsqr_status setup_engine(lsqr_ctx *c, Engine &E, int vec, const RowFmt &R, const ColFmt &C)
+{
+    const int64_t m = c->P.m, n = c->P.n, mb = m + 2 * n;
+    const size_t vs = vt_size(vec);
+    E.vec = vec;
+    E.R = R;
+    E.C = C;
+    if (R.run_ptr) E.g_fwd = cap_blocks(std::max<int64_t>(m * 64, 2 * n), kBlock, 2048);
+    else E.g_fwd = cap_blocks(std::max<int64_t>(m * R.lpr, 2 * n), kBlock, 2048);
+    E.g_adj = cap_blocks(n * C.lpc, kBlock, 2048);
+    E.g_upd = cap_blocks(n, kBlock, 1024);
+    E.T[0] = ctx_alloc_bytes(c, mb * vs);
+    E.T[1] = ctx_alloc_bytes(c, mb * vs);
+    if (R.sigma) E.Ts = ctx_alloc_bytes(c, std::max<int64_t>(m, 1) * vs);
+    E.q = ctx_alloc_bytes(c, n * vs);
+    E.v = ctx_alloc_bytes(c, n * vs);
+    E.z = ctx_alloc_bytes(c, n * vs);
+    E.vzero = ctx_alloc_bytes(c, n * vs);
+    E.w = ctx_alloc<double>(c, n);
+    E.y = ctx_alloc<double>(c, n);
+    E.P1 = ctx_alloc<double>(c, E.g_fwd);
+    E.P2 = ctx_alloc<double>(c, E.g_adj);
+    E.P3 = ctx_alloc<double>(c, E.g_upd);
+    E.ctl = ctx_alloc<int>(c, C_WORDS);
+    if (!E.T[0] || !E.T[1] || (R.sigma && !E.Ts) || !E.q || !E.v || !E.z || !E.vzero || !E.w ||
+        !E.y || !E.P1 || !E.P2 || !E.P3 || !E.ctl)
+        return fail(nullptr, LSQR_E_OOM, "device allocation failed");
+    return LSQR_OK;
+}
+
+lsqr_status ensure_state(lsqr_ctx *c, Engine &E, int iters)
 {
     const int64_t need = (int64_t)iters + 2;
-    if (c->s_rows >= need) return LSQR_OK;
-    if (c->S) ctx_release(c, c->S);
+    if (E.s_rows >= need) return LSQR_OK;
+    if (E.S) ctx_release(c, E.S);
     const int64_t rows = std::max<int64_t>(need, 512);
-    c->S = ctx_alloc<double>(c, (size_t)rows * kStateWords);
-    if (!c->S) return fail(c, LSQR_E_OOM, "state allocation failed");
-    c->s_rows = rows;
-    if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    E.S = ctx_alloc<double>(c, (size_t)rows * kStateWords);
+    if (!E.S) return fail(c, LSQR_E_OOM, "state allocation failed");
+    E.s_rows = rows;
+    if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
     return LSQR_OK;
 }
 
 // One LSQR iteration of parity p (0: odd k, 1: even k).
-void launch_iteration(lsqr_ctx *c, hipStream_t st, int p, double tol, bool timing, int slot)
+void launch_iteration(lsqr_ctx *c, Engine &E, hipStream_t st, int p, double tol, bool timing,
+                      int slot)
 {
-    const DevCSR A{c->rp, c->ci, c->va}, At{c->cp, c->ri, c->cv};
-    double *Tprev = c->T[p], *Tcur = c->T[1 - p];
+    const Problem &P = c->P;
+    void *Tprev = E.T[p], *Tcur = E.T[1 - p];
     if (timing) (void)hipEventRecord(c->ev[4 * slot + 0], st);
-    launch_fwd(st, c->P, c->g, A, c->z, Tprev, Tcur, c->P1, c->P3, c->S, c->ctl, p, tol, MODE_ITER);
+    launch_fwd(st, P, E.g_fwd, E.vec, E.R, E.z, Tprev, Tcur, E.Ts, E.P1, E.P3, E.g_upd, E.S,
+               E.ctl, p, tol, MODE_ITER);
     if (timing) (void)hipEventRecord(c->ev[4 * slot + 1], st);
     if (timing) (void)hipEventRecord(c->ev[4 * slot + 2], st);
-    launch_adj(st, c->P, c->g, At, c->d, Tcur, c->v, c->q, c->P2, c->P1, c->S, c->ctl, p, MODE_ITER);
+    launch_adj(st, P, E.g_adj, E.vec, E.C, c->d, Tcur, E.Ts ? E.Ts : Tcur, E.v, E.q, E.P2, E.P1,
+               E.g_fwd, E.S, E.ctl, p, MODE_ITER, 0);
     if (timing) (void)hipEventRecord(c->ev[4 * slot + 3], st);
-    launch_update(st, c->P, c->g, c->d, c->q, c->v, c->w, c->y, c->z, c->P3, c->P2, c->S, c->ctl,
-                  p, MODE_ITER);
+    launch_update(st, P, E.g_upd, E.vec, c->d, E.q, E.v, E.w, E.y, E.z, E.P3, E.P2, E.g_adj, E.S,
+                  E.ctl, p, MODE_ITER);
 }
 
-lsqr_status build_graph(lsqr_ctx *c, int iters, double tol)
+lsqr_status build_graph(lsqr_ctx *c, Engine &E, int iters, double tol)
 {
-    if (c->gexec && c->graph_iters == iters && c->graph_tol == tol) return LSQR_OK;
-    if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (E.gexec && E.graph_iters == iters && E.graph_tol == tol) return LSQR_OK;
+    if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
     if (!c->cap_st) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < iters; ++i) launch_iteration(c, c->cap_st, i & 1, tol, false, 0);
+    for (int i = 0; i < iters; ++i) launch_iteration(c, E, c->cap_st, i & 1, tol, false, 0);
     HIP_TRY(c, hipStreamEndCapture(c->cap_st, &graph));
-    hipError_t e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&E.gexec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-        c->gexec = nullptr;
+        E.gexec = nullptr;
         return fail(c, LSQR_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
-    c->graph_iters = iters;
-    c->graph_tol = tol;
+    E.graph_iters = iters;
+    E.graph_tol = tol;
     return LSQR_OK;
+}
+
+// Run LSQR on engine E from x0 = 0 with right-hand side rhs ([dt; 0; 0] when
+// full == 0, else a full FP64 [m+2n] vector); writes D y into out (or adds it
+// when accumulate != 0).  Leaves the stop state in E.ctl and E.S; returns after
+// enqueuing (polls the device only when tol > 0).
+lsqr_status engine_solve(lsqr_ctx *c, Engine &E, const double *rhs, int full, int iters,
+                         double tol, double *out, int accumulate, bool timing)
+{
+    hipStream_t st = c->st;
+    const Problem &P = c->P;
+    lsqr_status s = ensure_state(c, E, iters);
+    if (s != LSQR_OK) return s;
+    if (timing && (int)c->ev.size() < 4 * iters) {
+        while ((int)c->ev.size() < 4 * iters) {
+            hipEvent_t e;
+            HIP_TRY(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+    }
+    const bool use_graph = !timing && !(c->flags & LSQR_FLAG_NO_GRAPH);
+    // start: beta_1 u_1 = rhs, alpha_1 v_1 = A_D^T u_1
+    launch_init(st, P, E.g_fwd, E.vec, rhs, full, E.T[0], E.R.sigma, E.Ts, E.y, E.vzero, E.P1,
+                E.ctl, iters);
+    launch_adj(st, P, E.g_adj, E.vec, E.C, c->d, E.T[0], E.Ts ? E.Ts : E.T[0], E.vzero, E.q, E.P2,
+               E.P1, E.g_fwd, E.S, E.ctl, 0, MODE_INIT, 0);
+    launch_update(st, P, E.g_upd, E.vec, c->d, E.q, E.v, E.w, E.y, E.z, E.P3, E.P2, E.g_adj, E.S,
+                  E.ctl, 0, MODE_INIT);
+    HIP_TRY(c, hipGetLastError());
+    // iterations: blocks of an even number of iterations replayed as one graph
+    // (parity returns to 0 after each block); with tol > 0 the host reads the
+    // device stop flag after every block of check_every iterations
+    const int block = tol > 0.0 ? c->check_every : iters;
+    int done = 0;
+    bool stopped = false;
+    auto poll = [&]() -> lsqr_status {
+        HIP_TRY(c, hipMemcpyAsync(c->hctl, E.ctl, C_WORDS * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        stopped = c->hctl[C_STOP] != 0;
+        return LSQR_OK;
+    };
+    if (use_graph && block >= 2) {
+        const int gb = std::min(block, 64) & ~1;
+        s = build_graph(c, E, gb, tol);
+        if (s != LSQR_OK) return s;
+        while (!stopped && iters - done >= gb) {
+            HIP_TRY(c, hipGraphLaunch(E.gexec, st));
+            done += gb;
+            if (tol > 0.0 && done < iters && (s = poll()) != LSQR_OK) return s;
+        }
+    }
+    while (!stopped && done < iters) {
+        launch_iteration(c, E, st, done & 1, tol, timing, done);
+        ++done;
+        if (tol > 0.0 && done % c->check_every == 0 && done < iters && (s = poll()) != LSQR_OK)
+            return s;
+    }
+    launch_finalize(st, P, E.g_upd, c->d, E.y, out, E.P3, E.g_upd, E.S, E.ctl, tol, accumulate);
+    HIP_TRY(c, hipGetLastError());
+    if (timing) {
+        HIP_TRY(c, hipStreamSynchronize(st));
+        const int nt = std::min(done, iters);
+        for (int i = 0; i < nt; ++i) {
+            float a = 0.f, b = 0.f;
+            if (hipEventElapsedTime(&a, c->ev[4 * i + 0], c->ev[4 * i + 1]) == hipSuccess) {
+                c->ks.fwd_ms += a; c->ks.fwd_launches++;
+            }
+            if (hipEventElapsedTime(&b, c->ev[4 * i + 2], c->ev[4 * i + 3]) == hipSuccess) {
+                c->ks.adj_ms += b; c->ks.adj_launches++;
+            }
+        }
+    }
+    return LSQR_OK;
+}
+
+// Reads the engine's stop state and history after a solve.
+lsqr_status read_state(lsqr_ctx *c, Engine &E, int iters, std::vector<double> &hs)
+{
+    hipStream_t st = c->st;
+    HIP_TRY(c, hipMemcpyAsync(c->hctl, E.ctl, C_WORDS * sizeof(int), hipMemcpyDeviceToHost, st));
+    hs.resize((size_t)(iters + 1) * kStateWords);
+    HIP_TRY(c, hipMemcpyAsync(hs.data(), E.S, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (c->hctl[C_ERR]) return fail(c, LSQR_E_NONFINITE, "a solver scalar became non-finite");
+    return LSQR_OK;
+}
+
+void write_history(const std::vector<double> &hs, int iters, int kdone, int istop, double *res_hist)
+{
+    for (int k = 0; k <= iters; ++k) {
+        for (int f = 0; f < 3; ++f) res_hist[3 * k + f] = NAN;
+        if (k > kdone || (istop == 0 && k > 0)) continue;
+        const double *Sk = hs.data() + (size_t)k * kStateWords;
+        if (istop == 0) {  // bbar = 0 or Abar^T bbar = 0
+            res_hist[0] = Sk[S_BETA]; res_hist[1] = 0.0; res_hist[2] = 0.0;
+            continue;
+        }
+        res_hist[3 * k + 0] = Sk[S_PHIBAR];
+        res_hist[3 * k + 1] = Sk[S_PSI];
+        res_hist[3 * k + 2] = Sk[S_ETA];
+    }
 }
 
 }  // namespace
@@ -224,11 +454,12 @@ void lsqr_destroy(lsqr_ctx *c)
     if (!c) return;
     DeviceGuard dg(c->device);
     if (c->st) (void)hipStreamSynchronize(c->st);
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->eng.gexec) (void)hipGraphExecDestroy(c->eng.gexec);
     if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     for (auto &pr : c->owned) c->al.put(pr.first, pr.second);
     if (c->hctl) (void)hipHostFree(c->hctl);
+    if (c->hsum) (void)hipHostFree(c->hsum);
     delete c;
 }
 
@@ -250,8 +481,12 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         return fail(nullptr, LSQR_E_INVALID_ARG, "damp and smooth_weight must be finite and >= 0");
     lsqr_opts o{};
     if (opts) o = *opts;
-    if (o.precision != LSQR_FP64)
-        return fail(nullptr, LSQR_E_UNSUPPORTED, "only LSQR_FP64 is provided by this build");
+    if (o.precision < LSQR_FP64 || o.precision > LSQR_FP16)
+        return fail(nullptr, LSQR_E_INVALID_ARG, "unknown precision");
+    const bool mixed = o.precision == LSQR_BF16 || o.precision == LSQR_FP16;
+    if (mixed && !(damp > 0.0))
+        return fail(nullptr, LSQR_E_UNSUPPORTED,
+                    "the BF16/FP16 forms need damp > 0 (the refinement corrects through the damping block)");
     if (o.precond < LSQR_PRECOND_NONE || o.precond > LSQR_PRECOND_USER)
         return fail(nullptr, LSQR_E_INVALID_ARG, "unknown precond");
     if (o.precond == LSQR_PRECOND_USER && !o.col_scale)
@@ -259,7 +494,10 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if ((o.lanes_per_row && !valid_lanes(o.lanes_per_row)) ||
         (o.lanes_per_col && !valid_lanes(o.lanes_per_col)))
         return fail(nullptr, LSQR_E_INVALID_ARG, "lanes must be 0, 4, 8, 16, 32 or 64");
+    if (o.row_format < 0 || o.row_format > 2)
+        return fail(nullptr, LSQR_E_INVALID_ARG, "row_format must be 0, 1 or 2");
     if (o.check_every < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "check_every must be >= 0");
+    if (o.refine_sweeps < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "refine_sweeps must be >= 0");
     if (G->mem == LSQR_MEM_HOST) {
         lsqr_status s = validate_host_csr(G);
         if (s != LSQR_OK) return s;
@@ -276,6 +514,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     c->prec = o.precision; c->precond = o.precond; c->flags = o.flags;
     c->check_every = o.check_every > 0 ? o.check_every : 32;
     c->check_every += c->check_every & 1;
+    c->refine_sweeps = o.refine_sweeps > 0 ? o.refine_sweeps : 5;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, LSQR_E_DEVICE, "no HIP device available");
@@ -298,36 +537,21 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     c->ri = ctx_alloc<int32_t>(c, nnz);
     c->cv = ctx_alloc<double>(c, nnz);
     c->d = ctx_alloc<double>(c, n);
-    c->T[0] = ctx_alloc<double>(c, mb);
-    c->T[1] = ctx_alloc<double>(c, mb);
-    c->q = ctx_alloc<double>(c, n); c->v = ctx_alloc<double>(c, n); c->w = ctx_alloc<double>(c, n);
-    c->y = ctx_alloc<double>(c, n); c->z = ctx_alloc<double>(c, n);
-    c->vzero = ctx_alloc<double>(c, n); c->dtbuf = ctx_alloc<double>(c, std::max<int64_t>(m, 1));
+    c->ones = ctx_alloc<double>(c, n);
+    c->dtbuf = ctx_alloc<double>(c, std::max<int64_t>(m, 1));
     c->dmbuf = ctx_alloc<double>(c, n);
-    c->ctl = ctx_alloc<int>(c, C_WORDS);
     c->flag = ctx_alloc<int>(c, 4);
-    if (!c->rp || !c->ci || !c->va || !c->cp || !c->ri || !c->cv || !c->d || !c->T[0] || !c->T[1] ||
-        !c->q || !c->v || !c->w || !c->y || !c->z || !c->vzero || !c->dtbuf || !c->dmbuf ||
-        !c->ctl || !c->flag)
+    c->g_ref = cap_blocks(mb, kBlock, 1024);
+    c->ybuf = ctx_alloc<double>(c, mb);
+    c->Pr = ctx_alloc<double>(c, c->g_ref);
+    c->Pa = ctx_alloc<double>(c, 2048);   // partials of operator launches (<= 2048 workgroups)
+    c->Pf = ctx_alloc<double>(c, 2048);
+    c->sums = ctx_alloc<double>(c, 4);
+    if (!c->rp || !c->ci || !c->va || !c->cp || !c->ri || !c->cv || !c->d || !c->ones ||
+        !c->dtbuf || !c->dmbuf || !c->flag || !c->ybuf || !c->Pr || !c->Pa || !c->Pf || !c->sums)
         return bail(LSQR_E_OOM, "device allocation failed");
     CR_TRY(hipHostMalloc((void **)&c->hctl, C_WORDS * sizeof(int), hipHostMallocDefault));
-
-    // launch geometry: enough resident workgroups to fill 256 CUs
-    const double avg_row = m > 0 ? (double)nnz / (double)m : 0.0;
-    const double avg_col = (double)nnz / (double)n;
-    c->g.lpr = o.lanes_per_row ? o.lanes_per_row : pick_lanes(avg_row);
-    c->g.lpc = o.lanes_per_col ? o.lanes_per_col : pick_lanes(avg_col);
-    auto cap_blocks = [](int64_t work, int per, int cap) {
-        int64_t b = (work + per - 1) / per;
-        return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
-    };
-    c->g.g_fwd = cap_blocks(std::max<int64_t>(m * c->g.lpr, 2 * n), kBlock, 2048);
-    c->g.g_adj = cap_blocks(n * c->g.lpc, kBlock, 2048);
-    c->g.g_upd = cap_blocks(n, kBlock, 1024);
-    c->P1 = ctx_alloc<double>(c, c->g.g_fwd);
-    c->P2 = ctx_alloc<double>(c, c->g.g_adj);
-    c->P3 = ctx_alloc<double>(c, c->g.g_upd);
-    if (!c->P1 || !c->P2 || !c->P3) return bail(LSQR_E_OOM, "device allocation failed");
+    CR_TRY(hipHostMalloc((void **)&c->hsum, 4 * sizeof(double), hipHostMallocDefault));
 
     hipStream_t st = c->st;
     const hipMemcpyKind kind = G->mem == LSQR_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
@@ -336,6 +560,10 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         CR_TRY(hipMemcpyAsync(c->ci, G->col_idx, nnz * sizeof(int32_t), kind, st));
         CR_TRY(hipMemcpyAsync(c->va, G->val, nnz * sizeof(double), kind, st));
     }
+    std::vector<int64_t> hrp;
+    std::vector<int32_t> hci;
+    const int64_t *hrow = G->row_ptr;
+    const int32_t *hcol = G->col_idx;
     if (G->mem == LSQR_MEM_DEVICE) {
         int64_t ends[2] = {0, 0};
         CR_TRY(hipMemcpyAsync(&ends[0], c->rp, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -352,16 +580,54 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         if (f & 2) return bail(LSQR_E_BAD_CSR, "column index out of range");
         if (f & 4) return bail(LSQR_E_BAD_CSR, "columns not strictly increasing within a row");
         if (f & 8) return bail(LSQR_E_NONFINITE, "non-finite value in G");
+        hrp.resize((size_t)m + 1);
+        hci.resize((size_t)nnz);
+        CR_TRY(hipMemcpy(hrp.data(), c->rp, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+        if (nnz) CR_TRY(hipMemcpy(hci.data(), c->ci, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+        hrow = hrp.data();
+        hcol = hci.data();
     }
     {
         std::string terr;
-        hipError_t e = build_transpose(st, c->al, m, n, nnz, DevCSR{c->rp, c->ci, c->va}, c->cp,
-                                       c->ri, c->cv, terr);
+        hipError_t e = build_transpose(st, c->al, m, n, nnz, c->rp, c->ci, c->va, c->cp, c->ri,
+                                       c->cv, terr);
         if (e != hipSuccess)
             return bail(e == hipErrorOutOfMemory ? LSQR_E_OOM : LSQR_E_DEVICE,
                         terr + ": " + hipGetErrorString(e));
     }
+    // depth runs of the data rows
+    const double avg_row = m > 0 ? (double)nnz / (double)m : 0.0;
+    const double avg_col = (double)nnz / (double)n;
+    bool use_runs = false;
+    if (o.row_format != 1 && m > 0 && nnz > 0) {
+        std::vector<int64_t> run_ptr;
+        std::vector<uint32_t> runs;
+        std::vector<uint16_t> roff;
+        if (build_runs_host(m, n, hrow, hcol, run_ptr, runs, roff)) {
+            c->nruns = run_ptr[m];
+            const double avg_run = (double)nnz / (double)std::max<int64_t>(c->nruns, 1);
+            use_runs = o.row_format == 2 || avg_run >= 2.5;
+            if (use_runs) {
+                c->run_ptr = ctx_alloc<int64_t>(c, m + 1);
+                c->runs = ctx_alloc<uint32_t>(c, c->nruns);
+                c->roff = ctx_alloc<uint16_t>(c, c->nruns);
+                if (!c->run_ptr || !c->runs || !c->roff) return bail(LSQR_E_OOM, "device allocation failed");
+                CR_TRY(hipMemcpy(c->run_ptr, run_ptr.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+                CR_TRY(hipMemcpy(c->runs, runs.data(), c->nruns * sizeof(uint32_t), hipMemcpyHostToDevice));
+                CR_TRY(hipMemcpy(c->roff, roff.data(), c->nruns * sizeof(uint16_t), hipMemcpyHostToDevice));
+            }
+        } else if (o.row_format == 2) {
+            return bail(LSQR_E_UNSUPPORTED, "depth-run rows need rows of <= 65535 entries and n < 2^24");
+        }
+    }
+    // FP64 formats
+    c->R64.vt = VT_F64; c->R64.rp = c->rp; c->R64.ci = c->ci; c->R64.val = c->va;
+    c->R64.lpr = o.lanes_per_row ? o.lanes_per_row : pick_lanes(avg_row);
+    if (use_runs) { c->R64.run_ptr = c->run_ptr; c->R64.runs = c->runs; c->R64.roff = c->roff; }
+    c->C64.vt = VT_F64; c->C64.cp = c->cp; c->C64.ri = c->ri; c->C64.val = c->cv;
+    c->C64.lpc = o.lanes_per_col ? o.lanes_per_col : pick_lanes(avg_col);
     // column scaling
+    launch_fill(st, n, 1.0, c->ones);
     if (o.precond == LSQR_PRECOND_NONE) {
         launch_fill(st, n, 1.0, c->d);
     } else {
@@ -372,14 +638,54 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             if (ok) CR_TRY(hipMemcpyAsync(c->d, o.col_scale, n * sizeof(double), hipMemcpyHostToDevice, st));
             else { use_jacobi = true; c->fallback_used = 1; }
         }
-        if (use_jacobi) launch_jacobi(st, c->P, DevCSR{c->cp, c->ri, c->cv}, c->d);
+        if (use_jacobi) launch_jacobi(st, c->P, c->C64, c->d);
     }
+    // the solver's formats
+    RowFmt R = c->R64;
+    ColFmt C = c->C64;
+    int vec = VT_F64;
+    if (o.precision == LSQR_FP32) {
+        c->va32 = ctx_alloc<float>(c, nnz);
+        c->cv32 = ctx_alloc<float>(c, nnz);
+        if (!c->va32 || !c->cv32) return bail(LSQR_E_OOM, "device allocation failed");
+        launch_convert_f32(st, nnz, c->va, c->va32);
+        launch_convert_f32(st, nnz, c->cv, c->cv32);
+        R.vt = VT_F32; R.val = c->va32;
+        C.vt = VT_F32; C.val = c->cv32;
+        vec = VT_F32;
+    } else if (mixed) {
+        const int vt = o.precision == LSQR_BF16 ? VT_BF16 : VT_F16;
+        c->sigma = ctx_alloc<float>(c, std::max<int64_t>(m, 1));
+        c->qrow = ctx_alloc<uint16_t>(c, nnz);
+        c->qcol = ctx_alloc<uint16_t>(c, nnz);
+        c->xbuf = ctx_alloc<double>(c, n);
+        c->rbar = ctx_alloc<double>(c, mb);
+        c->rs = ctx_alloc<double>(c, std::max<int64_t>(m, 1));
+        c->gbuf = ctx_alloc<double>(c, n);
+        c->ghat = ctx_alloc<double>(c, n);
+        c->fbuf = ctx_alloc<double>(c, mb);
+        if (!c->sigma || !c->qrow || !c->qcol || !c->xbuf || !c->rbar || !c->rs || !c->gbuf ||
+            !c->ghat || !c->fbuf)
+            return bail(LSQR_E_OOM, "device allocation failed");
+        launch_row_scales(st, m, c->rp, c->va, vt, c->sigma);
+        launch_quantise_rows(st, m, c->rp, c->va, c->sigma, vt, c->qrow);
+        launch_quantise_cols(st, nnz, c->ri, c->cv, c->sigma, vt, c->qcol);
+        R.vt = vt; R.val = c->qrow; R.sigma = c->sigma;
+        C.vt = vt; C.val = c->qcol;
+        c->CQ = C;
+        vec = VT_F32;
+    }
+    lsqr_status s = setup_engine(c, c->eng, vec, R, C);
+    if (s != LSQR_OK) return bail(s, g_err);
     CR_TRY(hipGetLastError());
     CR_TRY(hipStreamSynchronize(st));
     *out = c;
     return LSQR_OK;
 #undef CR_TRY
 }
+
+static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, int iters, double tol, double *ddm,
+                               double *res_hist, lsqr_info *info);
 
 lsqr_status lsqr_solve(lsqr_ctx *c, const double *dt, lsqr_mem vec_mem, int iters, double tol,
                        double *dm, double *res_hist, lsqr_info *info)
@@ -390,12 +696,12 @@ lsqr_status lsqr_solve(lsqr_ctx *c, const double *dt, lsqr_mem vec_mem, int iter
     if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, LSQR_E_INVALID_ARG, "tol must be finite and >= 0");
     if (vec_mem != LSQR_MEM_HOST && vec_mem != LSQR_MEM_DEVICE)
         return fail(c, LSQR_E_INVALID_ARG, "unknown memory kind");
+    const bool mixed = c->prec == LSQR_BF16 || c->prec == LSQR_FP16;
+    if (mixed && !(tol > 0.0))
+        return fail(c, LSQR_E_INVALID_ARG, "the BF16/FP16 forms refine to a tolerance: tol must be > 0");
     DeviceGuard dg(c->device);
     hipStream_t st = c->st;
-    const Problem &P = c->P;
-    const int64_t m = P.m, n = P.n;
-    lsqr_status s = ensure_state(c, iters);
-    if (s != LSQR_OK) return s;
+    const int64_t m = c->P.m, n = c->P.n;
 
     // right-hand side in, checked for NaN/Inf
     const double *ddt = dt;
@@ -412,102 +718,118 @@ lsqr_status lsqr_solve(lsqr_ctx *c, const double *dt, lsqr_mem vec_mem, int iter
         if (c->hctl[0]) return fail(c, LSQR_E_NONFINITE, "non-finite value in dt");
     }
     double *ddm = vec_mem == LSQR_MEM_HOST ? c->dmbuf : dm;
-
-    const bool timing = (c->flags & LSQR_FLAG_TIMING) != 0;
-    const bool use_graph = !timing && !(c->flags & LSQR_FLAG_NO_GRAPH);
-    if (timing && (int)c->ev.size() < 4 * iters) {
-        while ((int)c->ev.size() < 4 * iters) {
-            hipEvent_t e;
-            HIP_TRY(c, hipEventCreate(&e));
-            c->ev.push_back(e);
+    lsqr_status s;
+    if (mixed) {
+        s = solve_mixed(c, ddt, iters, tol, ddm, res_hist, info);
+        if (s != LSQR_OK) return s;
+    } else {
+        const bool timing = (c->flags & LSQR_FLAG_TIMING) != 0;
+        if (timing) c->ks = lsqr_kstats{};
+        s = engine_solve(c, c->eng, ddt, 0, iters, tol, ddm, 0, timing);
+        if (s != LSQR_OK) return s;
+        std::vector<double> hs;
+        s = read_state(c, c->eng, iters, hs);
+        if (s != LSQR_OK) return s;
+        const int kdone = c->hctl[C_ITERS], istop = c->hctl[C_ISTOP];
+        if (res_hist) write_history(hs, iters, kdone, istop, res_hist);
+        if (info) {
+            info->istop = istop;
+            info->iters = kdone;
+            info->sweeps = 0;
+            info->fallback_used = c->fallback_used;
+            const double *Sk = hs.data() + (size_t)kdone * kStateWords;
+            info->eta = istop == 0 ? 0.0 : Sk[S_ETA];
+            info->phibar = istop == 0 ? hs[S_BETA] : Sk[S_PHIBAR];
         }
     }
-    const DevCSR At{c->cp, c->ri, c->cv};
-    // start: beta_1 u_1 = bbar, alpha_1 v_1 = A_D^T u_1
-    launch_init_rhs(st, P, c->g, ddt, c->T[0], c->y, c->vzero, c->P1, c->ctl, iters);
-    launch_adj(st, P, c->g, At, c->d, c->T[0], c->vzero, c->q, c->P2, c->P1, c->S, c->ctl, 0, MODE_INIT);
-    launch_update(st, P, c->g, c->d, c->q, c->v, c->w, c->y, c->z, c->P3, c->P2, c->S, c->ctl, 0,
-                  MODE_INIT);
-    HIP_TRY(c, hipGetLastError());
-
-    // iterations: blocks of an even number of iterations replayed as one graph
-    // (parity returns to 0 after each block); with tol > 0 the host reads the
-    // device stop flag after every block of check_every iterations
-    const int block = tol > 0.0 ? c->check_every : iters;
-    int done = 0;
-    bool stopped = false;
-    auto poll = [&]() -> lsqr_status {
-        HIP_TRY(c, hipMemcpyAsync(c->hctl, c->ctl, C_WORDS * sizeof(int), hipMemcpyDeviceToHost, st));
+    if (vec_mem == LSQR_MEM_HOST) {
+        HIP_TRY(c, hipMemcpyAsync(dm, c->dmbuf, n * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(c, hipStreamSynchronize(st));
-        stopped = c->hctl[C_STOP] != 0;
+    }
+    return LSQR_OK;
+}
+
+// Iterative refinement of the quantised forms.  Each sweep: rbar = bbar -
+// Abar x with the FP64 operator; g = G^T r_G (FP64 values) and ghat =
+// Ghat^T r_G (the quantised values, FP64 arithmetic); the exact eta =
+// |Abar^T rbar| / |Abar^T bbar|; then an inner LSQR on the quantised
+// operator with right-hand side f = [r_G; r_L; r_D + (g - ghat)/lambda], for
+// which Ahat^T f = Abar^T rbar, so the refinement's fixed point is the FP64
+// solution; x += D y_inner.
+static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, int iters, double tol, double *ddm,
+                               double *res_hist, lsqr_info *info)
+{
+    hipStream_t st = c->st;
+    const Problem &P = c->P;
+    const int64_t n = P.n;
+    Engine &E = c->eng;
+    const double inner_tol = 1e-3;
+    const int gadj = std::min(2048, E.g_adj);
+    auto fetch = [&]() -> lsqr_status {
+        HIP_TRY(c, hipMemcpyAsync(c->hsum, c->sums, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
         return LSQR_OK;
     };
-    if (use_graph && block >= 2) {
-        const int gb = std::min(block, 64) & ~1;
-        s = build_graph(c, gb, tol);
-        if (s != LSQR_OK) return s;
-        while (!stopped && iters - done >= gb) {
-            HIP_TRY(c, hipGraphLaunch(c->gexec, st));
-            done += gb;
-            if (tol > 0.0 && done < iters && (s = poll()) != LSQR_OK) return s;
-        }
-    }
-    while (!stopped && done < iters) {
-        launch_iteration(c, st, done & 1, tol, timing, done);
-        ++done;
-        if (tol > 0.0 && done % c->check_every == 0 && done < iters && (s = poll()) != LSQR_OK)
-            return s;
-    }
-    launch_finalize(st, P, c->g, c->d, c->y, ddm, c->P3, c->S, c->ctl, 0, tol);
-    HIP_TRY(c, hipGetLastError());
-    if (vec_mem == LSQR_MEM_HOST)
-        HIP_TRY(c, hipMemcpyAsync(dm, c->dmbuf, n * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(c, hipMemcpyAsync(c->hctl, c->ctl, C_WORDS * sizeof(int), hipMemcpyDeviceToHost, st));
+    launch_fill(st, n, 0.0, c->xbuf);
+    // |Abar^T bbar| = |G^T dt|
+    launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, nullptr, ddt, nullptr, c->gbuf, c->Pa,
+               nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
+    launch_sum_partials(st, c->Pa, gadj, c->sums + 0);
+    lsqr_status s = fetch();
+    if (s != LSQR_OK) return s;
+    const double arnorm = sqrt(c->hsum[0]);
+    int istop = 2, total = 0, sweeps = 0, last_iters = 0, last_istop = 2;
+    double eta = 0.0, rnorm = 0.0, eta_prev = INFINITY;
     std::vector<double> hs;
-    if (res_hist || info) {
-        hs.resize((size_t)(iters + 1) * kStateWords);
-        HIP_TRY(c, hipMemcpyAsync(hs.data(), c->S, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (!(arnorm > 0.0)) {
+        istop = 0;
+    } else {
+        for (int sw = 0;; ++sw) {
+            // FP64 residual and its normal-equation residual
+            if (sw > 0)
+                launch_fwd(st, P, E.g_fwd, VT_F64, c->R64, c->xbuf, nullptr, c->ybuf, nullptr,
+                           c->Pf, nullptr, 0, nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
+            launch_residual(st, P, c->g_ref, ddt, sw > 0 ? c->ybuf : nullptr, c->rbar, c->sigma,
+                            c->rs, c->Pr);
+            launch_sum_partials(st, c->Pr, c->g_ref, c->sums + 1);
+            launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, nullptr, c->rbar, nullptr, c->gbuf,
+                       c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
+            launch_adj(st, P, gadj, VT_F64, c->CQ, c->ones, nullptr, c->rs, nullptr, c->ghat,
+                       c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
+            launch_form_rhs(st, P, c->g_ref, c->rbar, c->gbuf, c->ghat, c->fbuf, c->Pr);
+            launch_sum_partials(st, c->Pr, c->g_ref, c->sums + 2);
+            HIP_TRY(c, hipGetLastError());
+            if ((s = fetch()) != LSQR_OK) return s;
+            rnorm = sqrt(c->hsum[1]);
+            eta = sqrt(c->hsum[2]) / arnorm;
+            if (!isfinite(eta)) return fail(c, LSQR_E_NONFINITE, "refinement residual became non-finite");
+            if (eta <= tol) { istop = 1; break; }
+            if (sw >= c->refine_sweeps) { istop = 2; break; }
+            if (sw > 0 && eta > 0.5 * eta_prev) { istop = 4; break; }
+            eta_prev = eta;
+            // inner solve on the quantised operator, x += D y
+            s = engine_solve(c, E, c->fbuf, 1, iters, inner_tol, c->xbuf, 1, false);
+            if (s != LSQR_OK) return s;
+            if ((s = read_state(c, E, iters, hs)) != LSQR_OK) return s;
+            last_iters = c->hctl[C_ITERS];
+            last_istop = c->hctl[C_ISTOP];
+            total += last_iters;
+            ++sweeps;
+        }
     }
+    HIP_TRY(c, hipMemcpyAsync(ddm, c->xbuf, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIP_TRY(c, hipStreamSynchronize(st));
-    if (timing) {
-        c->ks = lsqr_kstats{};
-        const int nt = std::min(done, iters);
-        for (int i = 0; i < nt; ++i) {
-            float a = 0.f, b = 0.f;
-            if (hipEventElapsedTime(&a, c->ev[4 * i + 0], c->ev[4 * i + 1]) == hipSuccess) {
-                c->ks.fwd_ms += a; c->ks.fwd_launches++;
-            }
-            if (hipEventElapsedTime(&b, c->ev[4 * i + 2], c->ev[4 * i + 3]) == hipSuccess) {
-                c->ks.adj_ms += b; c->ks.adj_launches++;
-            }
-        }
-    }
-    const int kdone = c->hctl[C_ITERS];
-    const int istop = c->hctl[C_ISTOP];
-    if (c->hctl[C_ERR]) return fail(c, LSQR_E_NONFINITE, "a solver scalar became non-finite");
     if (res_hist) {
-        for (int k = 0; k <= iters; ++k) {
-            const bool ok = k <= kdone && !(istop == 0 && k > 0);
-            for (int f = 0; f < 3; ++f) res_hist[3 * k + f] = NAN;
-            if (!ok) continue;
-            const double *Sk = hs.data() + (size_t)k * kStateWords;
-            if (istop == 0) {  // bbar = 0 or Abar^T bbar = 0
-                res_hist[0] = Sk[S_BETA]; res_hist[1] = 0.0; res_hist[2] = 0.0;
-                continue;
-            }
-            res_hist[3 * k + 0] = Sk[S_PHIBAR];
-            res_hist[3 * k + 1] = Sk[S_PSI];
-            res_hist[3 * k + 2] = Sk[S_ETA];
-        }
+        if (sweeps > 0) write_history(hs, iters, last_iters, last_istop, res_hist);
+        else for (int k = 0; k <= iters; ++k) for (int f = 0; f < 3; ++f) res_hist[3 * k + f] = NAN;
     }
     if (info) {
         info->istop = istop;
-        info->iters = kdone;
-        info->sweeps = 0;
+        info->iters = total;
+        info->sweeps = sweeps;
         info->fallback_used = c->fallback_used;
-        const double *Sk = hs.data() + (size_t)kdone * kStateWords;
-        info->eta = istop == 0 ? 0.0 : Sk[S_ETA];
-        info->phibar = istop == 0 ? hs[S_BETA] : Sk[S_PHIBAR];
+        info->eta = eta;
+        info->phibar = rnorm;
     }
     return LSQR_OK;
 }
@@ -517,9 +839,9 @@ lsqr_status lsqr_apply(lsqr_ctx *c, const double *x, double *y)
     if (!c) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx is NULL");
     if (!x || !y) return fail(c, LSQR_E_INVALID_ARG, "x and y must not be NULL");
     DeviceGuard dg(c->device);
-    launch_scale_vec(c->st, c->P.n, c->d, x, c->z);
-    launch_fwd(c->st, c->P, c->g, DevCSR{c->rp, c->ci, c->va}, c->z, nullptr, y, c->P1, c->P3,
-               c->S, c->ctl, 0, 0.0, MODE_OPERATOR);
+    launch_scale_vec(c->st, c->P.n, c->d, x, c->dmbuf);
+    launch_fwd(c->st, c->P, c->eng.g_fwd, VT_F64, c->R64, c->dmbuf, nullptr, y, nullptr,
+               c->Pf, nullptr, 0, nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
     HIP_TRY(c, hipGetLastError());
     return LSQR_OK;
 }
@@ -529,8 +851,8 @@ lsqr_status lsqr_apply_t(lsqr_ctx *c, const double *y, double *x)
     if (!c) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx is NULL");
     if (!x || !y) return fail(c, LSQR_E_INVALID_ARG, "x and y must not be NULL");
     DeviceGuard dg(c->device);
-    launch_adj(c->st, c->P, c->g, DevCSR{c->cp, c->ri, c->cv}, c->d, y, nullptr, x, c->P2, c->P1,
-               c->S, c->ctl, 0, MODE_OPERATOR);
+    launch_adj(c->st, c->P, std::min(2048, c->eng.g_adj), VT_F64, c->C64, c->d, y, y, nullptr, x,
+               c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 0);
     HIP_TRY(c, hipGetLastError());
     return LSQR_OK;
 }
@@ -559,15 +881,38 @@ lsqr_status lsqr_get_transpose(const lsqr_ctx *cc, int64_t *col_ptr, int32_t *ro
     return LSQR_OK;
 }
 
+lsqr_status lsqr_get_quantised(const lsqr_ctx *cc, float *row_scale, uint16_t *q_rows,
+                               uint16_t *q_cols)
+{
+    lsqr_ctx *c = const_cast<lsqr_ctx *>(cc);
+    if (!c) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx is NULL");
+    if (!c->qrow) return fail(c, LSQR_E_UNSUPPORTED, "the context holds no quantised values");
+    DeviceGuard dg(c->device);
+    const hipMemcpyKind k = hipMemcpyDeviceToHost;
+    if (row_scale && c->P.m) HIP_TRY(c, hipMemcpyAsync(row_scale, c->sigma, c->P.m * sizeof(float), k, c->st));
+    if (q_rows && c->P.nnz) HIP_TRY(c, hipMemcpyAsync(q_rows, c->qrow, c->P.nnz * 2, k, c->st));
+    if (q_cols && c->P.nnz) HIP_TRY(c, hipMemcpyAsync(q_cols, c->qcol, c->P.nnz * 2, k, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return LSQR_OK;
+}
+
 lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
 {
     if (!c || !out) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx and out must not be NULL");
     *out = c->ks;
+    // algorithmic bytes of one launch of the solver's kernels: every stored
+    // value and index once, the row/column pointers, one pass over each vector
+    const Engine &E = c->eng;
     const double nnz = (double)c->P.nnz, m = (double)c->P.m, n = (double)c->P.n;
-    // algorithmic bytes of one launch: matrix stream + pointers + one read of
-    // each gathered vector + vector writes
-    out->fwd_bytes = nnz * 12.0 + (m + 1) * 8.0 + n * 8.0 + (m + 2 * n) * 16.0;
-    out->adj_bytes = nnz * 12.0 + (n + 1) * 8.0 + (m + 2 * n) * 8.0 + n * 8.0 * 3.0;
+    const double mb = m + 2 * n;
+    const double sv = (double)vt_size(E.R.vt), sx = (double)vt_size(E.vec);
+    double fwd = nnz * sv + (m + 1) * 8.0 + n * sx + 2.0 * mb * sx;
+    if (E.R.run_ptr) fwd += (double)c->nruns * 6.0 + (m + 1) * 8.0;
+    else fwd += nnz * 4.0;
+    if (E.R.sigma) fwd += m * 4.0 + m * sx;
+    out->fwd_bytes = fwd;
+    out->adj_bytes = nnz * ((double)vt_size(E.C.vt) + 4.0) + (n + 1) * 8.0 + mb * sx +
+                     n * (8.0 + 2.0 * sx);
     return LSQR_OK;
 }
 

@@ -44,20 +44,11 @@ enum CtlField {
     C_WORDS = 8,
 };
 
-struct DevCSR {
-    const int64_t *ptr = nullptr;   // [rows+1]
-    const int32_t *idx = nullptr;   // [nnz]
-    const double *val = nullptr;    // [nnz]
-};
+enum { MODE_ITER = 0, MODE_INIT = 1, MODE_OPERATOR = 2 };
 
-// Launch geometry of the solver kernels.
-struct Geometry {
-    int lpr = 64;      // lanes per data row (forward)
-    int lpc = 64;      // lanes per column (transposed)
-    int g_fwd = 1;     // workgroups of the forward kernel
-    int g_adj = 1;     // workgroups of the transposed kernel
-    int g_upd = 1;     // workgroups of the update kernel
-};
+// Element types of stored matrix values and of vectors.
+enum ValType { VT_F64 = 0, VT_F32 = 1, VT_BF16 = 2, VT_F16 = 3 };
+size_t vt_size(int vt);
 
 struct Problem {
     int64_t m = 0, n = 0, nnz = 0;
@@ -65,34 +56,72 @@ struct Problem {
     double w = 0.0, damp = 0.0;
 };
 
-// Kernel launchers (kernels_lsqr.hip).
-void launch_init_rhs(hipStream_t st, const Problem &P, const Geometry &g, const double *dt,
-                     double *T0, double *y, double *vzero, double *part, int *ctl, int kmax);
-void launch_fwd(hipStream_t st, const Problem &P, const Geometry &g, DevCSR A, const double *z,
-                const double *Tprev, double *Tcur, double *part_out, const double *part_v,
-                double *S, int *ctl, int parity, double tol, int mode);
-void launch_adj(hipStream_t st, const Problem &P, const Geometry &g, DevCSR At, const double *d,
-                const double *T, const double *v, double *q, double *part_out,
-                const double *part_t, double *S, int *ctl, int parity, int mode);
-void launch_update(hipStream_t st, const Problem &P, const Geometry &g, const double *d,
-                   const double *q, double *v, double *w, double *y, double *z,
-                   double *part_out, const double *part_q, double *S, int *ctl, int parity,
-                   int mode);
-void launch_finalize(hipStream_t st, const Problem &P, const Geometry &g, const double *d,
-                     const double *y, double *dm, const double *part_v, double *S, int *ctl,
-                     int parity, double tol);
+// Data rows of the forward product.
+struct RowFmt {
+    int vt = VT_F64;
+    const int64_t *rp = nullptr;       // [m+1] value offsets
+    const int32_t *ci = nullptr;       // [nnz] columns (plain CSR)
+    const int64_t *run_ptr = nullptr;  // [m+1] run offsets (depth-run rows) or nullptr
+    const uint32_t *runs = nullptr;    // (first column << 8) | length
+    const uint16_t *roff = nullptr;    // value offset of each run in its row
+    const void *val = nullptr;
+    const float *sigma = nullptr;      // [m] row scales (quantised values) or nullptr
+    int lpr = 64;                      // lanes per row (plain CSR)
+};
+
+// Stored transpose (CSC) for the transposed product.
+struct ColFmt {
+    int vt = VT_F64;
+    const int64_t *cp = nullptr;       // [n+1]
+    const int32_t *ri = nullptr;       // [nnz] rows, ascending within a column
+    const void *val = nullptr;
+    int lpc = 64;
+};
+
+// Type-dispatched launchers (kernels_f64.hip, kernels_f32.hip).
+void launch_init(hipStream_t st, const Problem &P, int grid, int vec, const double *rhs, int full,
+                 void *T0, const float *sigma, void *Ts0, double *y, void *vzero, double *part,
+                 int *ctl, int kmax);
+void launch_fwd(hipStream_t st, const Problem &P, int grid, int vec, const RowFmt &R,
+                const void *z, const void *Tprev, void *Tcur, void *Ts, double *part_out,
+                const double *part_v, int np_v, double *S, int *ctl, int parity, double tol,
+                int mode);
+void launch_adj(hipStream_t st, const Problem &P, int grid, int vec, const ColFmt &C,
+                const double *d, const void *T, const void *Tg, const void *v, void *q,
+                double *part_out, const double *part_t, int np_t, double *S, int *ctl,
+                int parity, int mode, int data_only);
+void launch_update(hipStream_t st, const Problem &P, int grid, int vec, const double *d,
+                   const void *q, void *v, double *w, double *y, void *z, double *part_out,
+                   const double *part_q, int np_q, double *S, int *ctl, int parity, int mode);
+
+// Helpers (kernels_common.hip).
+void launch_finalize(hipStream_t st, const Problem &P, int grid, const double *d,
+                     const double *y, double *dm, const double *part_v, int np_v, double *S,
+                     int *ctl, double tol, int accumulate);
 void launch_scale_vec(hipStream_t st, int64_t n, const double *d, const double *x, double *z);
-void launch_jacobi(hipStream_t st, const Problem &P, DevCSR At, double *d);
 void launch_fill(hipStream_t st, int64_t n, double value, double *x);
+void launch_jacobi(hipStream_t st, const Problem &P, const ColFmt &C, double *d);
 void launch_check_csr(hipStream_t st, int64_t m, int64_t n, const int64_t *row_ptr,
                       const int32_t *col, const double *val, int *flag);
 void launch_check_vec(hipStream_t st, int64_t n, const double *x, int positive, int *flag);
+void launch_convert_f32(hipStream_t st, int64_t nnz, const double *src, float *dst);
+void launch_row_scales(hipStream_t st, int64_t m, const int64_t *rp, const double *val, int vt,
+                       float *sigma);
+void launch_quantise_rows(hipStream_t st, int64_t m, const int64_t *rp, const double *val,
+                          const float *sigma, int vt, uint16_t *q);
+void launch_quantise_cols(hipStream_t st, int64_t nnz, const int32_t *ri, const double *cv,
+                          const float *sigma, int vt, uint16_t *q);
+// refinement: rbar = bbar - y (FP64), rs = sigma * rbar_G; partials of |rbar|^2
+void launch_residual(hipStream_t st, const Problem &P, int grid, const double *dt,
+                     const double *y, double *rbar, const float *sigma, double *rs,
+                     double *part);
+// f = [r_G; r_L; r_D + (g - ghat)/lambda]; partials of |Abar^T rbar|^2 where
+// Abar^T rbar = g + w L r_L + lambda r_D
+void launch_form_rhs(hipStream_t st, const Problem &P, int grid, const double *rbar,
+                     const double *g, const double *ghat, double *f, double *part);
+void launch_sum_partials(hipStream_t st, const double *part, int np, double *out);
 
-// Modes of the generic kernels.
-enum { MODE_ITER = 0, MODE_INIT = 1, MODE_OPERATOR = 2 };
-
-// Transpose (transpose.hip): CSC of the m x n CSR, rows ascending within a
-// column.  Scratch is obtained from the allocator callbacks.
+// Transpose (transpose.hip).
 struct Allocator {
     lsqr_alloc_fn alloc = nullptr;
     lsqr_free_fn dealloc = nullptr;
@@ -101,7 +130,7 @@ struct Allocator {
     void put(void *p, size_t bytes);
 };
 hipError_t build_transpose(hipStream_t st, Allocator &al, int64_t m, int64_t n, int64_t nnz,
-                           DevCSR A, int64_t *col_ptr, int32_t *row_idx, double *cval,
-                           std::string &err);
+                           const int64_t *rp, const int32_t *ci, const double *val,
+                           int64_t *col_ptr, int32_t *row_idx, double *cval, std::string &err);
 
 }  // namespace lsqr

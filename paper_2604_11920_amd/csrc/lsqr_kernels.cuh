@@ -1,0 +1,662 @@
+// Templated LSQR kernels for gfx950 (wave64), shared by the per-precision
+// translation units.
+//
+// One LSQR iteration k is three launches on one stream:
+//   fwd    t = Abar D v_k - alpha_k u_k over the data rows (plain CSR or
+//          depth-run rows), the 7-point smoothing rows and the damping rows;
+//          per-workgroup partial sums of t^2 (FP64)
+//   adj    beta_{k+1} from those partials; q = D Abar^T t / beta - beta v_k
+//          over the stored transpose (CSC, no atomics); partial sums of q^2
+//   update alpha_{k+1}, the Givens step (Paige & Saunders) in FP64 and the
+//          x/w/v sweep (x, w in FP64)
+// Every workgroup of a consumer kernel reduces the producer's partials in the
+// same fixed order, so all workgroups hold bitwise-identical scalars without a
+// separate reduction launch or atomics.  The iteration index, stop flag and
+// per-iteration scalars live in device memory, so a block of iterations can be
+// captured once as a hipGraph and replayed.
+//
+// Type parameters: M = stored matrix value (double, float, bf16_t, fp16_t),
+// V = vector element (double, float).  Products accumulate in double when V
+// is double and in float otherwise; norms and LSQR scalars are always FP64.
+#pragma once
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace lsqr {
+
+struct bf16_t { uint16_t b; };
+struct fp16_t { uint16_t b; };
+
+template <class V> struct AccOf { using type = float; };
+template <> struct AccOf<double> { using type = double; };
+
+template <class A> __device__ __forceinline__ A ld(const double *p) { return (A)*p; }
+template <class A> __device__ __forceinline__ A ld(const float *p) { return (A)*p; }
+template <class A> __device__ __forceinline__ A ld(const bf16_t *p)
+{
+    return (A)__uint_as_float((uint32_t)p->b << 16);
+}
+template <class A> __device__ __forceinline__ A ld(const fp16_t *p)
+{
+    _Float16 h;
+    __builtin_memcpy(&h, &p->b, 2);
+    return (A)(float)h;
+}
+template <class A> __device__ __forceinline__ A ld_nt(const double *p)
+{
+    return (A)__builtin_nontemporal_load(p);
+}
+template <class A> __device__ __forceinline__ A ld_nt(const float *p)
+{
+    return (A)__builtin_nontemporal_load(p);
+}
+template <class A> __device__ __forceinline__ A ld_nt(const bf16_t *p)
+{
+    const uint16_t b = __builtin_nontemporal_load(&p->b);
+    return (A)__uint_as_float((uint32_t)b << 16);
+}
+template <class A> __device__ __forceinline__ A ld_nt(const fp16_t *p)
+{
+    const uint16_t b = __builtin_nontemporal_load(&p->b);
+    _Float16 h;
+    __builtin_memcpy(&h, &b, 2);
+    return (A)(float)h;
+}
+
+// ------------------------------------------------------------ reductions --
+template <int W, class T>
+__device__ __forceinline__ T group_sum(T v)
+{
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+    return v;
+}
+
+// Sum over the workgroup (kBlock threads) in a fixed order; every thread
+// receives the same value.
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    v = group_sum<64>(v);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[wid] = v;
+    __syncthreads();
+    double r = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+    __syncthreads();
+    return r;
+}
+
+// Total of a producer's per-workgroup partials, identical in every workgroup.
+__device__ __forceinline__ double reduce_partials(const double *p, int np, double *lds)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += kBlock) acc += p[i];
+    return block_sum(acc, lds);
+}
+
+// (L x)_p for the 7-point Laplacian, neighbours in the order -x +x -y +y -z +z,
+// centre -(number of in-grid neighbours).
+template <class V>
+__device__ __forceinline__ typename AccOf<V>::type stencil(const V *x, int p, int nx, int ny, int nz)
+{
+#pragma clang fp contract(off)
+    using A = typename AccOf<V>::type;
+    const int iz = p % nz, ixy = p / nz, ix = ixy % nx, iy = ixy / nx;
+    const int sxy = nx * nz;
+    A acc = 0;
+    int deg = 0;
+    if (ix > 0) { acc += (A)x[p - nz]; ++deg; }
+    if (ix < nx - 1) { acc += (A)x[p + nz]; ++deg; }
+    if (iy > 0) { acc += (A)x[p - sxy]; ++deg; }
+    if (iy < ny - 1) { acc += (A)x[p + sxy]; ++deg; }
+    if (iz > 0) { acc += (A)x[p - 1]; ++deg; }
+    if (iz < nz - 1) { acc += (A)x[p + 1]; ++deg; }
+    return acc - (A)deg * (A)x[p];
+}
+
+// ----------------------------------------------------------------- init --
+// T0 = rhs (bbar = [dt; 0; 0] when full == 0, else a full [m+2n] vector),
+// y = 0, vzero = 0, partial sums of rhs^2 (FP64), control words.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_init_rhs(int64_t m, int64_t n, const double *rhs,
+                                                     int full, V *T0, const float *sigma, V *Ts0,
+                                                     double *y, V *vzero, double *part, int *ctl,
+                                                     int kmax)
+{
+    __shared__ double lds[4];
+    const int64_t mb = m + 2 * n;
+    double sq = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < mb;
+         i += (int64_t)gridDim.x * kBlock) {
+        const double b = (full || i < m) ? rhs[i] : 0.0;
+        T0[i] = (V)b;
+        if (Ts0 && i < m) Ts0[i] = (V)((double)sigma[i] * b);
+        sq += b * b;
+        if (i < n) { y[i] = 0.0; vzero[i] = (V)0; }
+    }
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl[C_STOP] = 0; ctl[C_ISTOP] = 2; ctl[C_ITERS] = 0; ctl[C_ERR] = 0;
+        ctl[C_CNT0] = 1; ctl[C_CNT1] = 0; ctl[C_KMAX] = kmax;
+    }
+}
+
+// --------------------------------------------------------------- forward --
+struct FwdArgs {
+    // data rows
+    const int64_t *rp;        // [m+1] value offsets
+    const int32_t *ci;        // [nnz] columns (plain CSR) or nullptr
+    const int64_t *run_ptr;   // [m+1] run offsets (depth-run rows) or nullptr
+    const uint32_t *runs;     // (first column << 8) | length
+    const uint16_t *roff;     // value offset of each run within its row
+    const void *va;           // [nnz] values of type M
+    const float *sigma;       // [m] row scales or nullptr
+    int64_t m;
+    int n, nx, ny, nz;
+    double w, damp;
+    const void *z;            // D v   [n] (V)
+    const void *Tprev;        // previous t (u = Tprev / beta_k) [m+2n] (V)
+    void *Tcur;               // [m+2n] (V)
+    void *Ts;                 // [m] sigma * t (V) or nullptr
+    double *part_out;         // [gridDim.x]
+    const double *part_v;     // partials of |D^-1 v_k|^2
+    int np_v;
+    double *S;
+    int *ctl;
+    int parity;
+    int mode;
+    double tol;
+};
+
+// Prologue of an LSQR forward step: the scalars of the previous step, the
+// convergence check on eta_{k-1} and the stop flag.  Returns false when this
+// launch has nothing to do.
+__device__ __forceinline__ bool fwd_prologue(const FwdArgs &a, double &alpha, double &beta,
+                                             double *lds)
+{
+#pragma clang fp contract(off)
+    alpha = 0.0;
+    beta = 1.0;
+    if (a.mode != MODE_ITER) return true;
+    if (a.ctl[C_STOP]) return false;
+    const int k = a.ctl[C_CNT0 + a.parity];
+    if (k > a.ctl[C_KMAX]) return false;
+    double *Sp = a.S + (int64_t)(k - 1) * kStateWords;
+    alpha = Sp[S_ALPHA];
+    beta = Sp[S_BETA];
+    const double vn = sqrt(reduce_partials(a.part_v, a.np_v, lds));
+    double arnorm0, eta = 1.0;
+    bool stop = false;
+    int istop = 2;
+    if (k == 1) {
+        arnorm0 = (a.S[S_ALPHA] * a.S[S_BETA]) * vn;
+    } else {
+        arnorm0 = a.S[S_ARNORM0];
+        eta = Sp[S_PSI] * vn / arnorm0;
+        if (a.tol > 0.0 && eta <= a.tol) { stop = true; istop = 1; }
+        else if (alpha == 0.0 || beta == 0.0) { stop = true; istop = 3; }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (k == 1) { a.S[S_ARNORM0] = arnorm0; a.S[S_VNORM] = vn; }
+        else { Sp[S_ETA] = eta; Sp[S_VNORM] = vn; }
+        if (stop) { a.ctl[C_ISTOP] = istop; a.ctl[C_STOP] = 1; }
+    }
+    return !stop;
+}
+
+// Row epilogue: t_i = sigma_i acc - alpha u_i with u_i = Tprev_i / beta.
+template <class V>
+__device__ __forceinline__ double fwd_row_out(const FwdArgs &a, int64_t row, double acc,
+                                              double alpha, double beta)
+{
+#pragma clang fp contract(off)
+    const double sacc = a.sigma ? (double)a.sigma[row] * acc : acc;
+    const double u = a.mode == MODE_ITER ? (double)((const V *)a.Tprev)[row] / beta : 0.0;
+    const V t = (V)(sacc - alpha * u);
+    ((V *)a.Tcur)[row] = t;
+    if (a.Ts) ((V *)a.Ts)[row] = (V)((double)a.sigma[row] * (double)t);
+    return (double)t * (double)t;
+}
+
+// Smoothing rows (m .. m+n) and damping rows (m+n .. m+2n): one thread each.
+template <class V>
+__device__ __forceinline__ double fwd_reg_rows(const FwdArgs &a, double alpha, double beta)
+{
+#pragma clang fp contract(off)
+    using A = typename AccOf<V>::type;
+    const V *z = (const V *)a.z;
+    double sq = 0.0;
+    const int64_t nreg = 2 * (int64_t)a.n;
+    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < nreg;
+         r += (int64_t)gridDim.x * kBlock) {
+        A yv;
+        if (r < a.n) yv = stencil<V>(z, (int)r, a.nx, a.ny, a.nz) * (A)a.w;
+        else yv = (A)a.damp * (A)z[r - a.n];
+        const double u = a.mode == MODE_ITER ? (double)((const V *)a.Tprev)[a.m + r] / beta : 0.0;
+        const V t = (V)((double)yv - alpha * u);
+        ((V *)a.Tcur)[a.m + r] = t;
+        sq += (double)t * (double)t;
+    }
+    return sq;
+}
+
+// Plain CSR rows, LPR lanes per row.
+template <class M, class V, int LPR>
+__global__ __launch_bounds__(kBlock) void k_fwd_csr(FwdArgs a)
+{
+    using A = typename AccOf<V>::type;
+    __shared__ double lds[4];
+    double alpha, beta;
+    if (!fwd_prologue(a, alpha, beta, lds)) return;
+    const M *va = (const M *)a.va;
+    const V *z = (const V *)a.z;
+    double sq = 0.0;
+    constexpr int RPB = kBlock / LPR;
+    const int lane = threadIdx.x % LPR;
+    const int64_t gstride = (int64_t)gridDim.x * RPB;
+    for (int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR; row < a.m; row += gstride) {
+        const int64_t s = a.rp[row], e = a.rp[row + 1];
+        A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int64_t j = s + lane;
+        for (; j + 3 * LPR < e; j += 4 * LPR) {
+            const int c0 = __builtin_nontemporal_load(a.ci + j);
+            const int c1 = __builtin_nontemporal_load(a.ci + j + LPR);
+            const int c2 = __builtin_nontemporal_load(a.ci + j + 2 * LPR);
+            const int c3 = __builtin_nontemporal_load(a.ci + j + 3 * LPR);
+            const A v0 = ld_nt<A>(va + j), v1 = ld_nt<A>(va + j + LPR);
+            const A v2 = ld_nt<A>(va + j + 2 * LPR), v3 = ld_nt<A>(va + j + 3 * LPR);
+            a0 = fma(v0, (A)z[c0], a0);
+            a1 = fma(v1, (A)z[c1], a1);
+            a2 = fma(v2, (A)z[c2], a2);
+            a3 = fma(v3, (A)z[c3], a3);
+        }
+        for (; j < e; j += LPR) a0 = fma(ld_nt<A>(va + j), (A)z[__builtin_nontemporal_load(a.ci + j)], a0);
+        const A acc = group_sum<LPR>((a0 + a1) + (a2 + a3));
+        if (lane == 0) sq += fwd_row_out<V>(a, row, (double)acc, alpha, beta);
+    }
+    sq += fwd_reg_rows<V>(a, alpha, beta);
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+}
+
+// Depth-run rows: one wave per row.  The wave loads up to 64 run descriptors
+// with one coalesced load (one per lane), then four 16-lane groups each take
+// one run (a contiguous stretch of columns and values) per step, taking the
+// descriptor from a register with a cross-lane shuffle; four steps (16 runs)
+// are in flight at once, so value loads and v gathers never wait on a
+// descriptor load.
+template <class M, class V>
+__global__ __launch_bounds__(kBlock) void k_fwd_runs(FwdArgs a)
+{
+    using A = typename AccOf<V>::type;
+    __shared__ double lds[4];
+    double alpha, beta;
+    if (!fwd_prologue(a, alpha, beta, lds)) return;
+    const M *va = (const M *)a.va;
+    const V *z = (const V *)a.z;
+    double sq = 0.0;
+    const int lane = threadIdx.x & 63, g = lane >> 4, gl = lane & 15;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); row < a.m;
+         row += nwaves) {
+        const int64_t vs = a.rp[row];
+        const int64_t rs = a.run_ptr[row], re = a.run_ptr[row + 1];
+        A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        for (int64_t base = rs; base < re; base += 64) {
+            const int nr = (int)(re - base < 64 ? re - base : 64);
+            uint32_t md = 0u;
+            int mo = 0;
+            if (lane < nr) {
+                md = __builtin_nontemporal_load(a.runs + base + lane);
+                mo = (int)__builtin_nontemporal_load(a.roff + base + lane);
+            }
+            for (int s0 = 0; s0 < nr; s0 += 16) {
+                // lanes >= nr hold md = 0, i.e. an empty run
+                const uint32_t d0 = __shfl(md, s0 + g), d1 = __shfl(md, s0 + 4 + g);
+                const uint32_t d2 = __shfl(md, s0 + 8 + g), d3 = __shfl(md, s0 + 12 + g);
+                const int o0 = __shfl(mo, s0 + g), o1 = __shfl(mo, s0 + 4 + g);
+                const int o2 = __shfl(mo, s0 + 8 + g), o3 = __shfl(mo, s0 + 12 + g);
+                const int n0 = (int)(d0 & 255u), n1 = (int)(d1 & 255u);
+                const int n2 = (int)(d2 & 255u), n3 = (int)(d3 & 255u);
+                const int c0 = (int)(d0 >> 8), c1 = (int)(d1 >> 8);
+                const int c2 = (int)(d2 >> 8), c3 = (int)(d3 >> 8);
+                const int nmax = max(max(n0, n1), max(n2, n3));
+                for (int e = gl; e < nmax; e += 16) {
+                    if (e < n0) a0 = fma(ld_nt<A>(va + vs + o0 + e), (A)z[c0 + e], a0);
+                    if (e < n1) a1 = fma(ld_nt<A>(va + vs + o1 + e), (A)z[c1 + e], a1);
+                    if (e < n2) a2 = fma(ld_nt<A>(va + vs + o2 + e), (A)z[c2 + e], a2);
+                    if (e < n3) a3 = fma(ld_nt<A>(va + vs + o3 + e), (A)z[c3 + e], a3);
+                }
+            }
+        }
+        const A acc = group_sum<64>((a0 + a1) + (a2 + a3));
+        if (lane == 0) sq += fwd_row_out<V>(a, row, (double)acc, alpha, beta);
+    }
+    sq += fwd_reg_rows<V>(a, alpha, beta);
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+}
+
+// ------------------------------------------------------------- transposed --
+struct AdjArgs {
+    const int64_t *cp;
+    const int32_t *ri;
+    const void *cv;          // [nnz] values of type M
+    int64_t m;
+    int n, nx, ny, nz;
+    double w, damp;
+    const double *d;         // column scale [n]
+    const void *T;           // t [m+2n] (V): smoothing/damping blocks
+    const void *Tg;          // data block gathered by rows (sigma * t when scaled) (V)
+    const void *v;           // v_k [n] (V) or nullptr
+    void *q;                 // out [n] (V)
+    double *part_out;
+    const double *part_t;    // partials of |t|^2
+    int np_t;
+    double *S;
+    int *ctl;
+    int parity;
+    int mode;
+    int data_only;           // 1: G^T part only (no smoothing/damping, no scale)
+};
+
+template <class M, class V, int LPC>
+__global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
+{
+#pragma clang fp contract(off)
+    using A = typename AccOf<V>::type;
+    __shared__ double lds[4];
+    double beta = 1.0;
+    if (a.mode != MODE_OPERATOR) {
+        if (a.ctl[C_STOP]) return;
+        int k = 0;
+        if (a.mode == MODE_ITER) {
+            k = a.ctl[C_CNT0 + a.parity];
+            if (k > a.ctl[C_KMAX]) return;
+        }
+        beta = sqrt(reduce_partials(a.part_t, a.np_t, lds));
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.S[(int64_t)k * kStateWords + S_BETA] = beta;
+            if (a.mode == MODE_INIT && beta == 0.0) { a.ctl[C_ISTOP] = 0; a.ctl[C_STOP] = 1; }
+        }
+        if (beta == 0.0) return;   // breakdown: the update kernel sets alpha = 0
+    }
+    const M *cv = (const M *)a.cv;
+    const V *T = (const V *)a.T;
+    const V *Tg = (const V *)a.Tg;
+    const V *vv = (const V *)a.v;
+    V *q = (V *)a.q;
+    double sq = 0.0;
+    constexpr int CPB = kBlock / LPC;
+    const int lane = threadIdx.x % LPC;
+    const int64_t tL = a.m, tD = a.m + a.n;
+    for (int j = blockIdx.x * CPB + threadIdx.x / LPC; j < a.n; j += gridDim.x * CPB) {
+        const int64_t s = a.cp[j], e = a.cp[j + 1];
+        A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int64_t p = s + lane;
+        for (; p + 3 * LPC < e; p += 4 * LPC) {
+            const int r0 = __builtin_nontemporal_load(a.ri + p);
+            const int r1 = __builtin_nontemporal_load(a.ri + p + LPC);
+            const int r2 = __builtin_nontemporal_load(a.ri + p + 2 * LPC);
+            const int r3 = __builtin_nontemporal_load(a.ri + p + 3 * LPC);
+            const A v0 = ld_nt<A>(cv + p), v1 = ld_nt<A>(cv + p + LPC);
+            const A v2 = ld_nt<A>(cv + p + 2 * LPC), v3 = ld_nt<A>(cv + p + 3 * LPC);
+            a0 = fma(v0, (A)Tg[r0], a0);
+            a1 = fma(v1, (A)Tg[r1], a1);
+            a2 = fma(v2, (A)Tg[r2], a2);
+            a3 = fma(v3, (A)Tg[r3], a3);
+        }
+        for (; p < e; p += LPC)
+            a0 = fma(ld_nt<A>(cv + p), (A)Tg[__builtin_nontemporal_load(a.ri + p)], a0);
+        const A g = group_sum<LPC>((a0 + a1) + (a2 + a3));
+        if (lane == 0) {
+            double qj;
+            if (a.data_only) {
+                qj = (double)g;
+            } else {
+                const A lap = stencil<V>(T + tL, j, a.nx, a.ny, a.nz);
+                const A sj = g + (A)a.w * lap + (A)a.damp * (A)T[tD + j];
+                const double xj = a.d[j] * (double)sj;
+                qj = vv ? xj / beta - beta * (double)vv[j] : xj / beta;
+            }
+            const V qv = (V)qj;
+            q[j] = qv;
+            sq += (double)qv * (double)qv;
+        }
+    }
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+}
+
+// ----------------------------------------------------------------- update --
+struct UpdArgs {
+    int n;
+    const double *d;
+    const void *q;           // (V)
+    void *v;                 // (V)
+    double *w, *y;
+    void *z;                 // D v (V)
+    double *part_out;        // partials of |D^-1 v_{k+1}|^2
+    const double *part_q;    // partials of |q|^2
+    int np_q;
+    double *S;
+    int *ctl;
+    int parity;
+    int mode;
+};
+
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_update(UpdArgs a)
+{
+#pragma clang fp contract(off)
+    __shared__ double lds[4];
+    if (a.ctl[C_STOP]) return;
+    const V *q = (const V *)a.q;
+    V *v = (V *)a.v;
+    V *z = (V *)a.z;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (a.mode == MODE_INIT) {
+        const double beta = a.S[S_BETA];
+        const double alpha = sqrt(reduce_partials(a.part_q, a.np_q, lds));
+        if (!isfinite(alpha) || !isfinite(beta)) {
+            if (lead) { a.ctl[C_ERR] = 1; a.ctl[C_ISTOP] = -3; a.ctl[C_STOP] = 1; }
+            return;
+        }
+        if (alpha == 0.0) {
+            if (lead) { a.S[S_ALPHA] = 0.0; a.ctl[C_ISTOP] = 0; a.ctl[C_STOP] = 1; }
+            return;
+        }
+        double sq = 0.0;
+        for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
+            const double vj = (double)q[j] / alpha;
+            const V vv = (V)vj;
+            v[j] = vv;
+            a.w[j] = (double)vv;
+            z[j] = (V)(a.d[j] * (double)vv);
+            const double dv = (double)vv / a.d[j];
+            sq += dv * dv;
+        }
+        const double tot = block_sum(sq, lds);
+        if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+        if (lead) {
+            double *S0 = a.S;
+            S0[S_ALPHA] = alpha; S0[S_RHOBAR] = alpha; S0[S_PHIBAR] = beta;
+            S0[S_PSI] = alpha * beta; S0[S_ETA] = 1.0;
+        }
+        return;
+    }
+    const int k = a.ctl[C_CNT0 + a.parity];
+    if (k > a.ctl[C_KMAX]) return;
+    const double *Sp = a.S + (int64_t)(k - 1) * kStateWords;
+    double *Sk = a.S + (int64_t)k * kStateWords;
+    const double beta = Sk[S_BETA];
+    const double alpha = beta > 0.0 ? sqrt(reduce_partials(a.part_q, a.np_q, lds)) : 0.0;
+    const double rhobar = Sp[S_RHOBAR], phibar = Sp[S_PHIBAR];
+    const double rho = sqrt(rhobar * rhobar + beta * beta);
+    const double c = rhobar / rho;
+    const double s = beta / rho;
+    const double theta = s * alpha;
+    const double rhobar_n = -c * alpha;
+    const double phi = c * phibar;
+    const double phibar_n = s * phibar;
+    const double t1 = phi / rho;
+    const double t2 = theta / rho;
+    const double psi = phibar_n * alpha * fabs(c);
+    if (!isfinite(alpha) || !isfinite(beta) || !isfinite(rho) || !isfinite(phi)) {
+        if (lead) { a.ctl[C_ERR] = 1; a.ctl[C_ISTOP] = -3; a.ctl[C_STOP] = 1; }
+        return;
+    }
+    double sq = 0.0;
+    const bool newv = alpha > 0.0;
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
+        double vj;
+        if (newv) {
+            const V vv = (V)((double)q[j] / alpha);
+            v[j] = vv;
+            vj = (double)vv;
+        } else {
+            vj = (double)v[j];
+        }
+        const double wj = a.w[j];
+        a.y[j] = a.y[j] + t1 * wj;
+        a.w[j] = vj - t2 * wj;
+        z[j] = (V)(a.d[j] * vj);
+        const double dv = vj / a.d[j];
+        sq += dv * dv;
+    }
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+    if (lead) {
+        Sk[S_ALPHA] = alpha; Sk[S_RHOBAR] = rhobar_n; Sk[S_PHIBAR] = phibar_n; Sk[S_RHO] = rho;
+        Sk[S_C] = c; Sk[S_S] = s; Sk[S_THETA] = theta; Sk[S_PHI] = phi; Sk[S_PSI] = psi;
+        a.ctl[C_ITERS] = k;
+        a.ctl[C_CNT0 + (1 - a.parity)] = k + 1;
+    }
+}
+
+}  // namespace lsqr
+
+// ---------------------------------------------------------------- launchers --
+// Instantiated once per vector type V in kernels_f64.hip / kernels_f32.hip.
+namespace lsqr {
+
+template <class M, class V>
+static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArgs &a)
+{
+    if (R.run_ptr) {
+        hipLaunchKernelGGL((k_fwd_runs<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
+        return;
+    }
+    switch (R.lpr) {
+    case 4: hipLaunchKernelGGL((k_fwd_csr<M, V, 4>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_fwd_csr<M, V, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_fwd_csr<M, V, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_fwd_csr<M, V, 32>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_fwd_csr<M, V, 64>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    }
+}
+
+template <class M, class V>
+static void adj_launch_m(hipStream_t st, int grid, const ColFmt &C, const AdjArgs &a)
+{
+    switch (C.lpc) {
+    case 4: hipLaunchKernelGGL((k_adj<M, V, 4>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_adj<M, V, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_adj<M, V, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_adj<M, V, 32>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_adj<M, V, 64>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    }
+}
+
+// The stored value types a vector type supports: FP64 vectors take FP64
+// values (and quantised values in the FP64 refinement products); FP32
+// vectors take FP32 and quantised values.
+template <class V> struct Wide { static constexpr bool value = false; };
+template <> struct Wide<double> { static constexpr bool value = true; };
+
+template <class V>
+hipError_t fwd_launch(hipStream_t st, const Problem &P, int grid, const RowFmt &R,
+                      const void *z, const void *Tprev, void *Tcur, void *Ts, double *part_out,
+                      const double *part_v, int np_v, double *S, int *ctl, int parity,
+                      double tol, int mode)
+{
+    FwdArgs a{R.rp, R.ci, R.run_ptr, R.runs, R.roff, R.val, R.sigma, P.m, (int)P.n, P.nx, P.ny,
+              P.nz, P.w, P.damp, z, Tprev, Tcur, Ts, part_out, part_v, np_v, S, ctl, parity,
+              mode, tol};
+    if constexpr (Wide<V>::value) {
+        if (R.vt != VT_F64) return hipErrorInvalidValue;
+        fwd_launch_m<double, V>(st, grid, R, a);
+    } else {
+        switch (R.vt) {
+        case VT_F32: fwd_launch_m<float, V>(st, grid, R, a); break;
+        case VT_BF16: fwd_launch_m<bf16_t, V>(st, grid, R, a); break;
+        case VT_F16: fwd_launch_m<fp16_t, V>(st, grid, R, a); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+template <class V>
+hipError_t adj_launch(hipStream_t st, const Problem &P, int grid, const ColFmt &C,
+                      const double *d, const void *T, const void *Tg, const void *v, void *q,
+                      double *part_out, const double *part_t, int np_t, double *S, int *ctl,
+                      int parity, int mode, int data_only)
+{
+    AdjArgs a{C.cp, C.ri, C.val, P.m, (int)P.n, P.nx, P.ny, P.nz, P.w, P.damp, d, T, Tg, v, q,
+              part_out, part_t, np_t, S, ctl, parity, mode, data_only};
+    switch (C.vt) {
+    case VT_F64:
+        if constexpr (Wide<V>::value) adj_launch_m<double, V>(st, grid, C, a);
+        else return hipErrorInvalidValue;
+        break;
+    case VT_F32:
+        if constexpr (!Wide<V>::value) adj_launch_m<float, V>(st, grid, C, a);
+        else return hipErrorInvalidValue;
+        break;
+    case VT_BF16: adj_launch_m<bf16_t, V>(st, grid, C, a); break;
+    case VT_F16: adj_launch_m<fp16_t, V>(st, grid, C, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class V>
+hipError_t init_launch(hipStream_t st, const Problem &P, int grid, const double *rhs, int full,
+                       void *T0, const float *sigma, void *Ts0, double *y, void *vzero,
+                       double *part, int *ctl, int kmax)
+{
+    hipLaunchKernelGGL((k_init_rhs<V>), dim3(grid), dim3(kBlock), 0, st, P.m, P.n, rhs, full,
+                       (V *)T0, sigma, (V *)Ts0, y, (V *)vzero, part, ctl, kmax);
+    return hipGetLastError();
+}
+
+template <class V>
+hipError_t update_launch(hipStream_t st, const Problem &P, int grid, const double *d,
+                         const void *q, void *v, double *w, double *y, void *z, double *part_out,
+                         const double *part_q, int np_q, double *S, int *ctl, int parity, int mode)
+{
+    UpdArgs a{(int)P.n, d, q, v, w, y, z, part_out, part_q, np_q, S, ctl, parity, mode};
+    hipLaunchKernelGGL((k_update<V>), dim3(grid), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+#define LSQR_INSTANTIATE_LAUNCHERS(V)                                                            \
+    template hipError_t fwd_launch<V>(hipStream_t, const Problem &, int, const RowFmt &,         \
+                                      const void *, const void *, void *, void *, double *,      \
+                                      const double *, int, double *, int *, int, double, int);   \
+    template hipError_t adj_launch<V>(hipStream_t, const Problem &, int, const ColFmt &,         \
+                                      const double *, const void *, const void *, const void *,  \
+                                      void *, double *, const double *, int, double *, int *,    \
+                                      int, int, int);                                            \
+    template hipError_t init_launch<V>(hipStream_t, const Problem &, int, const double *, int,   \
+                                       void *, const float *, void *, double *, void *,          \
+                                       double *, int *, int);                                    \
+    template hipError_t update_launch<V>(hipStream_t, const Problem &, int, const double *,      \
+                                         const void *, void *, double *, double *, void *,       \
+                                         double *, const double *, int, double *, int *, int,    \
+                                         int);
+
+}  // namespace lsqr

@@ -85,8 +85,8 @@ static int grid_for(int64_t work)
 }
 
 hipError_t build_transpose(hipStream_t st, Allocator &al, int64_t m, int64_t n, int64_t nnz,
-                           DevCSR A, int64_t *col_ptr, int32_t *row_idx, double *cval,
-                           std::string &err)
+                           const int64_t *rp, const int32_t *ci, const double *val,
+                           int64_t *col_ptr, int32_t *row_idx, double *cval, std::string &err)
 {
     if (nnz >= ((int64_t)1 << 32)) {
         err = "transpose: nnz must be below 2^32";
@@ -111,8 +111,8 @@ hipError_t build_transpose(hipStream_t st, Allocator &al, int64_t m, int64_t n, 
         rc = hipErrorOutOfMemory;
         goto out;
     }
-    hipLaunchKernelGGL(k_copy_keys, dim3(grid_for(nnz)), dim3(256), 0, st, nnz, A.idx, k0, p0);
-    hipLaunchKernelGGL(k_row_ids, dim3(grid_for(m * 64)), dim3(256), 0, st, m, A.ptr, rowid);
+    hipLaunchKernelGGL(k_copy_keys, dim3(grid_for(nnz)), dim3(256), 0, st, nnz, ci, k0, p0);
+    hipLaunchKernelGGL(k_row_ids, dim3(grid_for(m * 64)), dim3(256), 0, st, m, rp, rowid);
     {
         rocprim::double_buffer<uint32_t> keys(k0, k1);
         rocprim::double_buffer<uint32_t> vals(p0, p1);
@@ -123,7 +123,7 @@ hipError_t build_transpose(hipStream_t st, Allocator &al, int64_t m, int64_t n, 
         rc = rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, vals, (size_t)nnz, 0, end_bit, st);
         if (rc != hipSuccess) { err = "transpose: radix sort failed"; goto out; }
         hipLaunchKernelGGL(k_gather_csc, dim3(grid_for(nnz)), dim3(256), 0, st, nnz,
-                           vals.current(), rowid, A.val, row_idx, cval);
+                           vals.current(), rowid, val, row_idx, cval);
         hipLaunchKernelGGL(k_col_ptr, dim3(grid_for(nnz)), dim3(256), 0, st, nnz, n,
                            keys.current(), col_ptr);
         hipLaunchKernelGGL(k_col_ptr_tail, dim3(grid_for(n + 1)), dim3(256), 0, st, nnz, n,

@@ -47,7 +47,7 @@ class Opts(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("alloc", _ALLOC_FN), ("dealloc", _FREE_FN), ("alloc_user", ctypes.c_void_p),
                 ("flags", ctypes.c_uint32), ("lanes_per_row", ctypes.c_int),
-                ("lanes_per_col", ctypes.c_int)]
+                ("lanes_per_col", ctypes.c_int), ("row_format", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -85,6 +85,7 @@ def load():
         "lsqr_get_scale": (I, [P, P]),
         "lsqr_get_transpose": (I, [P, P, P, P]),
         "lsqr_kernel_stats": (I, [P, ctypes.POINTER(KStats)]),
+        "lsqr_get_quantised": (I, [P, P, P, P]),
         "lsqr_destroy": (None, [P]),
         "lsqr_status_string": (ctypes.c_char_p, [I]),
         "lsqr_last_error": (ctypes.c_char_p, [P]),
@@ -123,7 +124,7 @@ class Solver:
     def __init__(self, row_ptr, col, val, nx, ny, nz, damp, smooth, precision="fp64",
                  precond="none", col_scale=None, stream=None, timing=False, graph=True,
                  lanes_per_row=0, lanes_per_col=0, check_every=0, refine_sweeps=5,
-                 torch_alloc=True):
+                 row_format="auto", torch_alloc=True):
         import torch
         lib = load()
         self._torch = torch
@@ -156,6 +157,8 @@ class Solver:
         opts.flags = (FLAG_TIMING if timing else 0) | (0 if graph else FLAG_NO_GRAPH)
         opts.lanes_per_row = int(lanes_per_row)
         opts.lanes_per_col = int(lanes_per_col)
+        opts.row_format = {"auto": 0, "csr": 1, "runs": 2}[row_format]
+        self.precision = precision
         if torch_alloc:
             self._blocks = {}
             sp = stream
@@ -238,6 +241,14 @@ class Solver:
         cv = np.empty(self.nnz, dtype=np.float64)
         self._check(self._lib.lsqr_get_transpose(self._ctx, _ptr(cp), _ptr(ri), _ptr(cv)))
         return cp, ri, cv
+
+    def quantised(self):
+        """(row scales [m] float32, codes in CSR order, codes in CSC order), uint16."""
+        sc = np.empty(self.m, dtype=np.float32)
+        qr = np.empty(self.nnz, dtype=np.uint16)
+        qc = np.empty(self.nnz, dtype=np.uint16)
+        self._check(self._lib.lsqr_get_quantised(self._ctx, _ptr(sc), _ptr(qr), _ptr(qc)))
+        return sc, qr, qc
 
     def kernel_stats(self):
         ks = KStats()

@@ -1,0 +1,136 @@
+"""GPU checks of the reduced-precision forms.
+
+* The BF16/FP16 codes and row scales equal the oracle quantiser's bitwise, in
+  both the row-major and the transposed copy.
+* BF16/FP16 with FP64 refinement reach the FP64 solution x* (the oracle run to
+  eta <= 1e-12) within 1e-5 relative.
+* FP32 LSQR: error against the oracle reported, with bounds from FP32 rounding.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+from oracle import quant
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def from_sys(s, **k):
+    from paper_2604_11920_amd import Solver
+    return Solver.from_system(s, **k)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    return synth.make_system(synth.config0())
+
+
+@pytest.fixture(scope="module")
+def xstar(cfg0):
+    op = oracle.Operator.from_system(cfg0)
+    r = oracle.Operator.from_system(cfg0, d=op.jacobi(), compensated=True).lsqr(cfg0.dt, 40000,
+                                                                                 tol=1e-12)
+    assert r["istop"] == 1
+    return r["x"]
+
+
+def ragged():
+    s = synth.random_system(700, 6, 5, 4, row_len=(0, 60), seed=21)
+    s.val = s.val * np.exp(np.random.default_rng(2).uniform(-20, 20, s.nnz))
+    return s
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("which", ["cfg0", "ragged"])
+def test_quantised_codes_bitwise(cfg0, fmt, which):
+    s = cfg0 if which == "cfg0" else ragged()
+    sig_ref, q_ref = quant.quantise_csr(s.row_ptr, s.val, fmt)
+    with from_sys(s, precision=fmt) as sol:
+        sig, qr, qc = sol.quantised()
+    assert np.array_equal(sig, sig_ref)
+    assert np.array_equal(qr, q_ref)
+    # the transposed copy holds the same codes in column order
+    order = sp.csr_matrix((np.arange(s.nnz, dtype=np.float64) + 1, s.col, s.row_ptr),
+                          shape=(s.m, s.n)).tocsc()
+    order.sort_indices()
+    assert np.array_equal(qc, q_ref[order.data.astype(np.int64) - 1])
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_refinement_reaches_fp64_solution(cfg0, xstar, fmt, precond):
+    with from_sys(cfg0, precision=fmt, precond=precond, refine_sweeps=10) as sol:
+        dm, hist, info = sol.solve(cfg0.dt, 3000, tol=1e-7)
+    err = rel(dm, xstar)
+    print(f"[{fmt}/{precond}] sweeps={info['sweeps']} inner iters={info['iters']} "
+          f"eta={info['eta']:.2e} err_vs_x*={err:.2e}")
+    assert info["istop"] == 1 and info["eta"] <= 1e-7 and info["sweeps"] <= 5
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_refinement_floor_is_flagged(cfg0, xstar, fmt):
+    # FP32 inner vectors carry f ~ r* (large for noisy data) while
+    # Ahat^T f -> 0, which sets an eta floor of a few 1e-9 on this system;
+    # a tolerance below it ends with the stall flag and the FP64 solution
+    with from_sys(cfg0, precision=fmt, precond="jacobi", refine_sweeps=10) as sol:
+        dm, hist, info = sol.solve(cfg0.dt, 3000, tol=1e-13)
+    err = rel(dm, xstar)
+    print(f"[{fmt}] floor: istop={info['istop']} sweeps={info['sweeps']} eta={info['eta']:.2e} "
+          f"err={err:.2e}")
+    assert info["istop"] in (1, 4) and err <= 1e-5
+
+
+def test_mixed_form_rejections(cfg0):
+    from paper_2604_11920_amd import LsqrError
+    with pytest.raises(LsqrError):
+        from_sys(cfg0, precision="bf16", damp=0.0)
+    with from_sys(cfg0, precision="bf16") as sol:
+        with pytest.raises(LsqrError):
+            sol.solve(cfg0.dt, 100, tol=0.0)
+
+
+@pytest.mark.parametrize("row_format", ["csr", "runs"])
+def test_fp32_iterates(cfg0, row_format):
+    ref = oracle.lsqr(cfg0, 5)
+    with from_sys(cfg0, precision="fp32", row_format=row_format) as sol:
+        dm, hist, info = sol.solve(cfg0.dt, 5)
+    err = rel(dm, ref["x"])
+    print(f"[fp32/{row_format}] K=5 rel err {err:.2e}")
+    assert info["iters"] == 5 and err <= 1e-4
+    assert np.allclose(hist[:, 0], ref["hist"][:, 0], rtol=1e-5)
+
+
+def test_fp32_converged(cfg0, xstar):
+    # at a given eta the distance to x* is set by the conditioning; compare FP32
+    # with FP64 stopped at the same tolerance
+    with from_sys(cfg0, precision="fp32", precond="jacobi") as sol:
+        dm, hist, info = sol.solve(cfg0.dt, 5000, tol=1e-5)
+    with from_sys(cfg0, precond="jacobi") as sol:
+        dm64, _, info64 = sol.solve(cfg0.dt, 5000, tol=1e-5)
+    err, err64 = rel(dm, xstar), rel(dm64, xstar)
+    print(f"[fp32] tol 1e-5: iters={info['iters']} err_vs_x*={err:.2e} (fp64: {info64['iters']} "
+          f"iters, {err64:.2e})")
+    assert info["istop"] == 1 and err <= 3 * err64 + 1e-4
+
+
+@pytest.mark.parametrize("row_format", ["csr", "runs"])
+def test_fp64_row_formats_agree(cfg0, row_format):
+    ref = oracle.lsqr(cfg0, 6)
+    with from_sys(cfg0, row_format=row_format) as sol:
+        dm, hist, info = sol.solve(cfg0.dt, 6)
+    assert rel(dm, ref["x"]) <= 1e-10
