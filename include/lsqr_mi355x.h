@@ -171,6 +171,56 @@ lsqr_status lsqr_solve(lsqr_ctx *ctx, const double *dt, lsqr_mem vec_mem, int it
                        double *dm, double *res_hist, lsqr_info *info);
 
 /*
+ * lsqr_solve_batched — LSQR for nrhs right-hand sides of each of nsys systems,
+ * advanced together: sparse products read each system's matrix once per
+ * right-hand-side tile (FP32 values and vectors, FP64 per-RHS scalars), and
+ * every system's iterations are captured in one hipGraph and replayed.
+ *   ctxs      [nsys] contexts (any precision; the batch reads FP32 copies of G)
+ *   nrhs      1..32 (padded internally to a power of two with zero columns)
+ *   dt        [nsys] pointers to [m_s][nrhs] row-major right-hand sides (vec_mem)
+ *   iters     iteration limit; tol >= 0 as in lsqr_solve, applied per RHS (a
+ *             converged right-hand side is frozen while the others continue)
+ *   dm        [nsys] pointers to [n_s][nrhs] row-major outputs (vec_mem)
+ *   res_hist  NULL, or [nsys] host pointers (each NULL or [iters+1][nrhs][3])
+ *   info      NULL or [nsys*nrhs] per right-hand side (system-major)
+ * Work runs on ctxs[0]'s stream (other contexts' streams are synchronised
+ * first).  The schedule (RHS tile, workgroups) is each context's configuration:
+ * the default, lsqr_set_batch_config or lsqr_autotune_batched.
+ * Errors: INVALID_ARG, NONFINITE, DEVICE, OOM.
+ */
+lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const double *const *dt,
+                               lsqr_mem vec_mem, int iters, double tol, double *const *dm,
+                               double *const *res_hist, lsqr_info *info);
+
+/*
+ * lsqr_apply_block / lsqr_apply_t_block — the batched kernels as plain
+ * products on nrhs (a power of two <= 32) row-major FP32 blocks of device
+ * vectors: Y [m+2n][nrhs] = Abar D X [n][nrhs]; X = D Abar^T Y.  Enqueued only.
+ */
+lsqr_status lsqr_apply_block(lsqr_ctx *ctx, int nrhs, const float *x, float *y);
+lsqr_status lsqr_apply_t_block(lsqr_ctx *ctx, int nrhs, const float *y, float *x);
+
+/* Schedule of the batched kernels: right-hand sides per kernel pass (8, 16 or
+ * 32; smaller tiles re-read the matrix, larger ones gather wider rows of the
+ * vector blocks) and the cap on workgroups per launch. */
+typedef struct {
+    int rhs_tile;
+    int grid;
+    double ms_per_iter;         /* measured by the autotuner (output only)           */
+} lsqr_batch_cfg;
+
+/* lsqr_set_batch_config — use this schedule for ctx's batched solves. */
+lsqr_status lsqr_set_batch_config(lsqr_ctx *ctx, const lsqr_batch_cfg *cfg);
+
+/*
+ * lsqr_autotune_batched — time every schedule (RHS tile in {8,16,32} not above
+ * the padded nrhs, grid in {256,512,1024,2048}) on ctx's system for
+ * probe_iters batched iterations (median of 5 repeats, HIP events on ctx's
+ * stream), keep the fastest for ctx and return it in *best.
+ */
+lsqr_status lsqr_autotune_batched(lsqr_ctx *ctx, int nrhs, int probe_iters, lsqr_batch_cfg *best);
+
+/*
  * lsqr_apply — y = Abar D x on the device: y[0:m] = G (D x),
  * y[m:m+n] = w L (D x), y[m+n:m+2n] = lambda (D x).  x [n], y [m+2n], FP64,
  * device pointers.  Uses the same kernel as the solver's forward product.
@@ -200,6 +250,64 @@ lsqr_status lsqr_get_transpose(const lsqr_ctx *ctx, int64_t *col_ptr, int32_t *r
  */
 lsqr_status lsqr_get_quantised(const lsqr_ctx *ctx, float *row_scale, uint16_t *q_rows,
                                uint16_t *q_cols);
+
+/* ---------------------------------------------------------------------------
+ * Learned column scaling.  A small MLP maps six per-column features to a
+ * multiplier of the Jacobi scale, d_j = d_j^Jacobi * softplus(z_j), to cut the
+ * iterations LSQR needs; any d > 0 leaves the solution unchanged, and Jacobi
+ * (opts.precond = JACOBI) stays the fallback (lsqr_create falls back to it for
+ * USER scales that are not finite and positive).
+ * Features of column j of Abar (FP32, [n][6] row-major):
+ *   f1 log10 |column j of Abar|   f2 log(1 + rows of G hitting j)
+ *   f3 iz / (nz - 1)              f4, f5 |g|-weighted mean and standard
+ *   deviation, over the rows hitting j, of each row's depth centroid
+ *   sum_j |g_ij| iz(j) / sum_j |g_ij| / (nz - 1)
+ *   f6 log(1 + mean of f2's counts over the in-grid 7-point neighbours)
+ * Parameters: one flat FP32 vector W1[64][6], b1[64], W2[64][64], b2[64],
+ * W3[64], b3 (LSQR_MLP_NPARAMS values); hidden layers use the exact (erf) GELU.
+ * ------------------------------------------------------------------------- */
+#define LSQR_MLP_NPARAMS 4673
+
+/* lsqr_column_features — feat (device [n][6]) for ctx's system. */
+lsqr_status lsqr_column_features(lsqr_ctx *ctx, float *feat);
+
+/*
+ * lsqr_mlp_scale — inference: d (device [n], FP64) = Jacobi scale times
+ * softplus(MLP((feat - mean) / std)), with weights and activations rounded to
+ * BF16 (nearest even) and FP32 sums.  params: device [LSQR_MLP_NPARAMS];
+ * mean, std: host [6] standardisation of the training features (std > 0).
+ */
+lsqr_status lsqr_mlp_scale(lsqr_ctx *ctx, const float *params, const float *mean, const float *std,
+                           const float *feat, double *d);
+
+/* Training state (FP32 parameters and Adam moments on the device). */
+typedef struct lsqr_trainer lsqr_trainer;
+
+/* lsqr_trainer_create — params: host [LSQR_MLP_NPARAMS] initial values;
+ * max_batch: largest minibatch; stream: hipStream_t for all its work. */
+lsqr_status lsqr_trainer_create(int max_batch, const float *params, void *stream, lsqr_trainer **out);
+
+/*
+ * lsqr_trainer_grad — loss = mean over the batch of (log softplus(z_b) -
+ * target_b)^2 and its gradient (FP32 forward/backward per sample, per-parameter
+ * sums over the batch in sample order).  x: device [batch][6] standardised
+ * features; target: device [batch] log multipliers; grad: device
+ * [LSQR_MLP_NPARAMS] or NULL; loss: host or NULL.
+ */
+lsqr_status lsqr_trainer_grad(lsqr_trainer *t, int batch, const float *x, const float *target,
+                              float *grad, double *loss);
+
+/* lsqr_trainer_step — the same gradient, then one Adam step (beta1 0.9,
+ * beta2 0.999, eps 1e-8, learning rate lr). */
+lsqr_status lsqr_trainer_step(lsqr_trainer *t, int batch, const float *x, const float *target,
+                              float lr, double *loss);
+
+/* lsqr_trainer_params — copy the current parameters to a host and/or a device
+ * buffer ([LSQR_MLP_NPARAMS]; either may be NULL, not both). */
+lsqr_status lsqr_trainer_params(const lsqr_trainer *t, float *params, float *params_device);
+
+/* lsqr_trainer_destroy — free t (NULL is a no-op). */
+void lsqr_trainer_destroy(lsqr_trainer *t);
 
 /* lsqr_kernel_stats — kernel timing of the last solve (LSQR_FLAG_TIMING). */
 lsqr_status lsqr_kernel_stats(const lsqr_ctx *ctx, lsqr_kstats *out);

@@ -4,6 +4,7 @@ The compute lives in liblsqr_mi355x.so (hand-written HIP for gfx950, C ABI
 in include/lsqr_mi355x.h); this package is the build script and a ctypes
 binding.
 """
-from .lsqr import (CSR, Info, LsqrError, Solver, header_functions, load)  # noqa: F401
+from .lsqr import (CSR, Info, LsqrError, Solver, Trainer, header_functions, load,  # noqa: F401
+                   solve_batched)
 
-__all__ = ["Solver", "LsqrError", "load", "header_functions"]
+__all__ = ["Solver", "Trainer", "LsqrError", "load", "header_functions", "solve_batched"]

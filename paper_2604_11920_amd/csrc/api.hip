@@ -13,129 +13,24 @@
 #include <thread>
 #include <vector>
 
-#include "internal.h"
+#include "ctx.h"
 
 using namespace lsqr;
 
-namespace {
-
-// One LSQR kernel set: the stored formats it reads, its vector type and its
-// work buffers, loop state and captured graph.
-struct Engine {
-    int vec = VT_F64;
-    RowFmt R;
-    ColFmt C;
-    int g_fwd = 1, g_adj = 1, g_upd = 1;
-    void *T[2] = {nullptr, nullptr};
-    void *Ts = nullptr;            // sigma * t for the quantised forms
-    void *q = nullptr, *v = nullptr, *z = nullptr, *vzero = nullptr;
-    double *w = nullptr, *y = nullptr;
-    double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
-    double *S = nullptr;
-    int64_t s_rows = 0;
-    int *ctl = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    int graph_iters = 0;
-    double graph_tol = -1.0;
-};
-
-}  // namespace
-
-struct lsqr_ctx {
-    Problem P;
-    Allocator al;
-    hipStream_t st = nullptr;
-    hipStream_t cap_st = nullptr;   // private stream used only for graph capture
-    int device = 0;
-    lsqr_precision prec = LSQR_FP64;
-    lsqr_precond precond = LSQR_PRECOND_NONE;
-    uint32_t flags = 0;
-    int check_every = 32;
-    int refine_sweeps = 5;
-    int fallback_used = 0;
-    std::vector<std::pair<void *, size_t>> owned;
-    // FP64 operator: CSR, depth runs, CSC, column scale
-    int64_t *rp = nullptr; int32_t *ci = nullptr; double *va = nullptr;
-    int64_t *run_ptr = nullptr; uint32_t *runs = nullptr; uint16_t *roff = nullptr;
-    int64_t nruns = 0;
-    int64_t *cp = nullptr; int32_t *ri = nullptr; double *cv = nullptr;
-    double *d = nullptr, *ones = nullptr;
-    RowFmt R64;
-    ColFmt C64;
-    // reduced-precision copies
-    float *va32 = nullptr, *cv32 = nullptr;
-    float *sigma = nullptr;
-    uint16_t *qrow = nullptr, *qcol = nullptr;
-    ColFmt CQ;                      // quantised transpose (FP64 refinement product)
-    Engine eng;                     // the solver's kernel set
-    // refinement and operator scratch (FP64)
-    double *xbuf = nullptr, *ybuf = nullptr, *rbar = nullptr, *rs = nullptr, *gbuf = nullptr;
-    double *ghat = nullptr, *fbuf = nullptr, *Pr = nullptr, *Pa = nullptr, *Pf = nullptr;
-    double *sums = nullptr;
-    int g_ref = 1;
-    double *dtbuf = nullptr, *dmbuf = nullptr;
-    int *flag = nullptr;
-    int *hctl = nullptr;            // pinned host mirror of control words
-    double *hsum = nullptr;         // pinned host mirror of reductions
-    std::vector<hipEvent_t> ev;
-    lsqr_kstats ks{};
-    std::string err;
-};
+namespace lsqr {
 
 static thread_local std::string g_err;
 
-static lsqr_status fail(lsqr_ctx *c, lsqr_status s, const std::string &msg)
+lsqr_status fail(lsqr_ctx *c, lsqr_status s, const std::string &msg)
 {
     if (c) c->err = msg;
     else g_err = msg;
     return s;
 }
 
-#define HIP_TRY(ctx, expr)                                                                  \
-    do {                                                                                    \
-        hipError_t _e = (expr);                                                             \
-        if (_e != hipSuccess)                                                               \
-            return fail(ctx, LSQR_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
-    } while (0)
+}  // namespace lsqr
 
 namespace {
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-        else prev = -1;
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-void *ctx_alloc_bytes(lsqr_ctx *c, size_t bytes)
-{
-    if (bytes == 0) bytes = 8;
-    void *p = c->al.get(bytes);
-    if (p) c->owned.push_back({p, bytes});
-    return p;
-}
-
-template <class T>
-T *ctx_alloc(lsqr_ctx *c, size_t count)
-{
-    return (T *)ctx_alloc_bytes(c, count * sizeof(T));
-}
-
-void ctx_release(lsqr_ctx *c, void *p)
-{
-    for (size_t i = 0; i < c->owned.size(); ++i)
-        if (c->owned[i].first == p) {
-            c->al.put(p, c->owned[i].second);
-            c->owned.erase(c->owned.begin() + (long)i);
-            return;
-        }
-}
 
 lsqr_status validate_host_csr(const lsqr_csr *G)
 {

@@ -1,0 +1,443 @@
+// Batched LSQR kernels: R right-hand sides of one system advance together.
+//
+// Vectors are row-major blocks [rows][R] (FP32), so the R values one stored
+// entry multiplies are one contiguous segment: a wave covers 64/RT entries x
+// RT right-hand sides per step (RT = RHS tile: 8, 16 or 32) and reads the
+// matrix once per tile instead of once per right-hand side.  Every right-hand
+// side keeps its own FP64 LSQR scalars in a state row S[k][r]; per-RHS partial
+// sums [workgroup][R] are reduced in a fixed order by every consumer
+// workgroup, as in the single-RHS kernels (no atomics).  A right-hand side
+// whose eta reaches the tolerance (or that breaks down) is frozen: its
+// products are still formed but its x, w, v no longer change.
+//
+// R is a power of two <= 32 (the host pads with zero right-hand sides), so R
+// divides the workgroup size and thread t always owns right-hand side t % R
+// in every grid-stride loop over (row, rhs) pairs.
+#pragma once
+
+#include "lsqr_kernels.cuh"
+
+namespace lsqr {
+
+constexpr int kMaxRhs = 32;
+
+struct BArgs {
+    // operator (FP32 values)
+    const int64_t *rp;
+    const int32_t *ci;
+    const float *va;
+    const int64_t *cp;
+    const int32_t *ri;
+    const float *cv;
+    const double *d;
+    int64_t m;
+    int n, nx, ny, nz;
+    double w, damp;
+    int R;                  // right-hand sides (power of two <= 32)
+    // vectors (row-major [rows][R])
+    const float *Z;         // D v   [n][R]
+    const float *Tprev;     // [m+2n][R]
+    float *Tcur;            // [m+2n][R]
+    float *V;               // [n][R]
+    float *Q;               // [n][R]
+    double *W, *Y;          // [n][R]
+    float *Zout;            // [n][R]
+    const double *rhs;      // [m][R] FP64 (init)
+    // partials [workgroup][R]
+    double *part_out;
+    const double *part_in;
+    int np_in;
+    double *S;              // [(K+2)][R][kStateWords]
+    int *act;               // [R] 1 active, 0 frozen
+    int *why;               // [R] stop reason
+    int *ctl;               // counters, kmax, error flag
+    int parity;
+    int mode;
+    double tol;
+    int r0;                 // first right-hand side of this launch's tile
+};
+
+__device__ __forceinline__ double *srow(const BArgs &a, int k, int r)
+{
+    return a.S + ((int64_t)k * a.R + r) * kStateWords;
+}
+
+// out[r] = sum over b < np of p[b][r], for every r < R, in a fixed order; all
+// threads take part.  accs has kBlock entries.
+__device__ __forceinline__ void sum_rhs_all(const double *p, int np, int R, double *accs,
+                                            double *out)
+{
+    const int r = threadIdx.x % R, slot = threadIdx.x / R, per = kBlock / R;
+    double acc = 0.0;
+    for (int b = slot; b < np; b += per) acc += p[(int64_t)b * R + r];
+    accs[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double s = 0.0;
+        for (int q = 0; q < per; ++q) s += accs[q * R + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Per-RHS sum of one value per thread (thread t holds right-hand side
+// t % RR, RR divides 64); result in out[0..RR), fixed order.
+template <int RR>
+__device__ __forceinline__ void block_sum_rhs(double v, double *accs, double *out)
+{
+#pragma unroll
+    for (int off = RR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < RR) accs[wid * RR + lane] = v;
+    __syncthreads();
+    if (threadIdx.x < RR) {
+        const int r = threadIdx.x;
+        out[r] = ((accs[r] + accs[RR + r]) + accs[2 * RR + r]) + accs[3 * RR + r];
+    }
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------- init --
+// T0 = [rhs; 0; 0] for the tile's right-hand sides, y = v = 0, partials of |b|^2.
+template <int RT>
+__global__ __launch_bounds__(kBlock) void k_binit(BArgs a)
+{
+    __shared__ double accs[kBlock];
+    __shared__ double res[kMaxRhs];
+    const int64_t mb = a.m + 2 * (int64_t)a.n;
+    const int rr = threadIdx.x % RT, c = a.r0 + rr;
+    double sq = 0.0;
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < mb * RT;
+         idx += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = idx / RT;
+        const double b = i < a.m ? a.rhs[i * a.R + c] : 0.0;
+        a.Tcur[i * a.R + c] = (float)b;
+        sq += b * b;
+        if (i < a.n) { a.Y[i * a.R + c] = 0.0; a.V[i * a.R + c] = 0.0f; }
+    }
+    block_sum_rhs<RT>(sq, accs, res);
+    if (threadIdx.x < RT) a.part_out[(int64_t)blockIdx.x * a.R + a.r0 + threadIdx.x] = res[threadIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x < RT) {
+        a.act[a.r0 + threadIdx.x] = 1;
+        a.why[a.r0 + threadIdx.x] = 2;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.r0 == 0) {
+        a.ctl[C_STOP] = 0; a.ctl[C_ISTOP] = 2; a.ctl[C_ITERS] = 0; a.ctl[C_ERR] = 0;
+        a.ctl[C_CNT0] = 1; a.ctl[C_CNT1] = 0;
+    }
+}
+
+// --------------------------------------------------------------- forward --
+// T = A_D V - U diag(alpha) with U = Tprev diag(1/beta), for the tile.
+template <int RT>
+__global__ __launch_bounds__(kBlock) void k_bfwd(BArgs a)
+{
+#pragma clang fp contract(off)
+    __shared__ double accs[kBlock];
+    __shared__ double res[kMaxRhs];
+    __shared__ double vns[kMaxRhs];
+    __shared__ double sal[kMaxRhs], sbe[kMaxRhs];
+    const bool op = a.mode == MODE_OPERATOR;       // plain product: alpha = 0, no state
+    const int k = op ? 0 : a.ctl[C_CNT0 + a.parity];
+    if (!op && k > a.ctl[C_KMAX]) return;
+    if (op) {
+        if (threadIdx.x < RT) { sal[threadIdx.x] = 0.0; sbe[threadIdx.x] = 1.0; }
+    } else {
+        sum_rhs_all(a.part_in, a.np_in, a.R, accs, vns);
+    }
+    if (!op && threadIdx.x < RT) {
+        const int r = a.r0 + threadIdx.x;
+        const double *Sp = srow(a, k - 1, r);
+        sal[threadIdx.x] = Sp[S_ALPHA];
+        sbe[threadIdx.x] = Sp[S_BETA];
+        if (blockIdx.x == 0) {
+            // eta of the previous step and the per-RHS stop rules
+            const double vn = sqrt(vns[r]);
+            double *S0 = srow(a, 0, r);
+            if (k == 1) {
+                S0[S_ARNORM0] = (S0[S_ALPHA] * S0[S_BETA]) * vn;
+                S0[S_VNORM] = vn;
+            } else {
+                double *Sw = srow(a, k - 1, r);
+                const double eta = Sp[S_PSI] * vn / S0[S_ARNORM0];
+                Sw[S_ETA] = eta;
+                Sw[S_VNORM] = vn;
+                if (a.act[r]) {
+                    if (a.tol > 0.0 && eta <= a.tol) { a.act[r] = 0; a.why[r] = 1; }
+                    else if (Sp[S_ALPHA] == 0.0 || Sp[S_BETA] == 0.0) { a.act[r] = 0; a.why[r] = 3; }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    constexpr int EPW = 64 / RT;
+    const int lane = threadIdx.x & 63, er = lane / RT, rr = lane % RT;
+    const double alpha = sal[rr], beta = sbe[rr] > 0.0 ? sbe[rr] : 1.0;
+    const int R = a.R, cofs = a.r0 + rr;
+    double sq = 0.0;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); row < a.m;
+         row += nwaves) {
+        const int64_t s = a.rp[row], e = a.rp[row + 1];
+        float a0 = 0.f, a1 = 0.f;
+        int64_t p = s + er;
+        for (; p + EPW < e; p += 2 * EPW) {
+            const float g0 = __builtin_nontemporal_load(a.va + p);
+            const float g1 = __builtin_nontemporal_load(a.va + p + EPW);
+            const int c0 = __builtin_nontemporal_load(a.ci + p);
+            const int c1 = __builtin_nontemporal_load(a.ci + p + EPW);
+            a0 = fmaf(g0, a.Z[(int64_t)c0 * R + cofs], a0);
+            a1 = fmaf(g1, a.Z[(int64_t)c1 * R + cofs], a1);
+        }
+        if (p < e)
+            a0 = fmaf(__builtin_nontemporal_load(a.va + p),
+                      a.Z[(int64_t)__builtin_nontemporal_load(a.ci + p) * R + cofs], a0);
+        float acc = a0 + a1;
+#pragma unroll
+        for (int off = RT; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+        if (er == 0) {
+            const double u = op ? 0.0 : (double)a.Tprev[row * R + cofs] / beta;
+            const float t = (float)((double)acc - alpha * u);
+            a.Tcur[row * R + cofs] = t;
+            sq += (double)t * (double)t;
+        }
+    }
+    // smoothing and damping rows: one thread per (row, rhs)
+    const int64_t nreg = 2 * (int64_t)a.n;
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < nreg * RT;
+         idx += (int64_t)gridDim.x * kBlock) {
+        const int64_t r = idx / RT;
+        float yv;
+        if (r < a.n) {
+            const int pp = (int)r;
+            const int iz = pp % a.nz, ixy = pp / a.nz, ix = ixy % a.nx, iy = ixy / a.nx;
+            const int sxy = a.nx * a.nz;
+            float acc = 0.f;
+            int deg = 0;
+            if (ix > 0) { acc += a.Z[(int64_t)(pp - a.nz) * R + cofs]; ++deg; }
+            if (ix < a.nx - 1) { acc += a.Z[(int64_t)(pp + a.nz) * R + cofs]; ++deg; }
+            if (iy > 0) { acc += a.Z[(int64_t)(pp - sxy) * R + cofs]; ++deg; }
+            if (iy < a.ny - 1) { acc += a.Z[(int64_t)(pp + sxy) * R + cofs]; ++deg; }
+            if (iz > 0) { acc += a.Z[(int64_t)(pp - 1) * R + cofs]; ++deg; }
+            if (iz < a.nz - 1) { acc += a.Z[(int64_t)(pp + 1) * R + cofs]; ++deg; }
+            yv = (acc - (float)deg * a.Z[(int64_t)pp * R + cofs]) * (float)a.w;
+        } else {
+            yv = (float)a.damp * a.Z[(r - a.n) * R + cofs];
+        }
+        const int64_t row = a.m + r;
+        const double u = op ? 0.0 : (double)a.Tprev[row * R + cofs] / beta;
+        const float t = (float)((double)yv - alpha * u);
+        a.Tcur[row * R + cofs] = t;
+        sq += (double)t * (double)t;
+    }
+    block_sum_rhs<RT>(sq, accs, res);
+    if (threadIdx.x < RT) a.part_out[(int64_t)blockIdx.x * a.R + a.r0 + threadIdx.x] = res[threadIdx.x];
+}
+
+// ------------------------------------------------------------- transposed --
+// Q = D A^T T diag(1/beta) - V diag(beta) for the tile (INIT: no V term).
+template <int RT>
+__global__ __launch_bounds__(kBlock) void k_badj(BArgs a)
+{
+#pragma clang fp contract(off)
+    __shared__ double accs[kBlock];
+    __shared__ double res[kMaxRhs];
+    __shared__ double b2[kMaxRhs];
+    const bool op = a.mode == MODE_OPERATOR;       // plain product: beta = 1, no v
+    int k = 0;
+    if (a.mode == MODE_ITER) {
+        k = a.ctl[C_CNT0 + a.parity];
+        if (k > a.ctl[C_KMAX]) return;
+    }
+    if (op) {
+        if (threadIdx.x < a.R) b2[threadIdx.x] = 1.0;
+        __syncthreads();
+    } else {
+        sum_rhs_all(a.part_in, a.np_in, a.R, accs, b2);
+    }
+    if (!op && blockIdx.x == 0 && threadIdx.x < RT) {
+        const int r = a.r0 + threadIdx.x;
+        srow(a, k, r)[S_BETA] = sqrt(b2[r]);
+    }
+    constexpr int EPW = 64 / RT;
+    const int lane = threadIdx.x & 63, er = lane / RT, rr = lane % RT;
+    const int R = a.R, cofs = a.r0 + rr;
+    const double beta = sqrt(b2[cofs]);
+    const double ib = beta > 0.0 ? beta : 1.0;
+    const int64_t tL = a.m, tD = a.m + a.n;
+    double sq = 0.0;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); j < a.n; j += nwaves) {
+        const int64_t s = a.cp[j], e = a.cp[j + 1];
+        float a0 = 0.f, a1 = 0.f;
+        int64_t p = s + er;
+        for (; p + EPW < e; p += 2 * EPW) {
+            const float g0 = __builtin_nontemporal_load(a.cv + p);
+            const float g1 = __builtin_nontemporal_load(a.cv + p + EPW);
+            const int i0 = __builtin_nontemporal_load(a.ri + p);
+            const int i1 = __builtin_nontemporal_load(a.ri + p + EPW);
+            a0 = fmaf(g0, a.Tcur[(int64_t)i0 * R + cofs], a0);
+            a1 = fmaf(g1, a.Tcur[(int64_t)i1 * R + cofs], a1);
+        }
+        if (p < e)
+            a0 = fmaf(__builtin_nontemporal_load(a.cv + p),
+                      a.Tcur[(int64_t)__builtin_nontemporal_load(a.ri + p) * R + cofs], a0);
+        float g = a0 + a1;
+#pragma unroll
+        for (int off = RT; off < 64; off <<= 1) g += __shfl_xor(g, off, 64);
+        if (er == 0) {
+            const int pp = (int)j;
+            const int iz = pp % a.nz, ixy = pp / a.nz, ix = ixy % a.nx, iy = ixy / a.nx;
+            const int sxy = a.nx * a.nz;
+            const float *TL = a.Tcur + tL * R;
+            float acc = 0.f;
+            int deg = 0;
+            if (ix > 0) { acc += TL[(int64_t)(pp - a.nz) * R + cofs]; ++deg; }
+            if (ix < a.nx - 1) { acc += TL[(int64_t)(pp + a.nz) * R + cofs]; ++deg; }
+            if (iy > 0) { acc += TL[(int64_t)(pp - sxy) * R + cofs]; ++deg; }
+            if (iy < a.ny - 1) { acc += TL[(int64_t)(pp + sxy) * R + cofs]; ++deg; }
+            if (iz > 0) { acc += TL[(int64_t)(pp - 1) * R + cofs]; ++deg; }
+            if (iz < a.nz - 1) { acc += TL[(int64_t)(pp + 1) * R + cofs]; ++deg; }
+            const float lap = acc - (float)deg * TL[(int64_t)pp * R + cofs];
+            const float sj = g + (float)a.w * lap + (float)a.damp * a.Tcur[(tD + j) * R + cofs];
+            const double xj = a.d[j] * (double)sj;
+            const double vj = a.mode == MODE_ITER ? (double)a.V[j * R + cofs] : 0.0;
+            const float qv = (float)(xj / ib - beta * vj);
+            a.Q[j * R + cofs] = qv;
+            sq += (double)qv * (double)qv;
+        }
+    }
+    block_sum_rhs<RT>(sq, accs, res);
+    if (threadIdx.x < RT) a.part_out[(int64_t)blockIdx.x * a.R + a.r0 + threadIdx.x] = res[threadIdx.x];
+}
+
+// ----------------------------------------------------------------- update --
+// All R right-hand sides: alpha_r, the Givens step per r (FP64) and the
+// x/w/v sweep over [n][R]; frozen right-hand sides keep x, w, v.  Writes the
+// per-RHS partials of |D^-1 v|^2.
+__global__ __launch_bounds__(kBlock) void k_bupdate(BArgs a)
+{
+#pragma clang fp contract(off)
+    __shared__ double accs[kBlock];
+    __shared__ double a2[kMaxRhs], res[kMaxRhs];
+    __shared__ double t1s[kMaxRhs], t2s[kMaxRhs], als[kMaxRhs];
+    __shared__ int live[kMaxRhs];
+    const int R = a.R;
+    int k = 0;
+    if (a.mode == MODE_ITER) {
+        k = a.ctl[C_CNT0 + a.parity];
+        if (k > a.ctl[C_KMAX]) return;
+    }
+    sum_rhs_all(a.part_in, a.np_in, R, accs, a2);
+    if (threadIdx.x < R) {
+        const int r = threadIdx.x;
+        double *Sk = srow(a, k, r);
+        const double beta = Sk[S_BETA];
+        const double alpha = beta > 0.0 ? sqrt(a2[r]) : 0.0;
+        int on = a.act[r];
+        if (a.mode == MODE_INIT) {
+            on = alpha > 0.0 && beta > 0.0;
+            if (blockIdx.x == 0) {
+                Sk[S_ALPHA] = alpha; Sk[S_RHOBAR] = alpha; Sk[S_PHIBAR] = beta;
+                Sk[S_PSI] = alpha * beta; Sk[S_ETA] = on ? 1.0 : 0.0;
+                if (!on) { a.act[r] = 0; a.why[r] = 0; }
+                if (!isfinite(alpha) || !isfinite(beta)) { a.act[r] = 0; a.why[r] = -3; a.ctl[C_ERR] = 1; }
+            }
+            als[r] = alpha; t1s[r] = 0.0; t2s[r] = 0.0;
+        } else {
+            const double *Sp = srow(a, k - 1, r);
+            const double rhobar = Sp[S_RHOBAR], phibar = Sp[S_PHIBAR];
+            const double rho = sqrt(rhobar * rhobar + beta * beta);
+            const double c = rhobar / rho, s = beta / rho;
+            const double theta = s * alpha, rhobar_n = -c * alpha;
+            const double phi = c * phibar, phibar_n = s * phibar;
+            const double psi = phibar_n * alpha * fabs(c);
+            if (blockIdx.x == 0) {
+                if (on) {
+                    Sk[S_ALPHA] = alpha; Sk[S_RHOBAR] = rhobar_n; Sk[S_PHIBAR] = phibar_n;
+                    Sk[S_RHO] = rho; Sk[S_C] = c; Sk[S_S] = s; Sk[S_THETA] = theta;
+                    Sk[S_PHI] = phi; Sk[S_PSI] = psi;
+                    if (!isfinite(alpha) || !isfinite(rho) || !isfinite(phi)) {
+                        a.act[r] = 0; a.why[r] = -3; a.ctl[C_ERR] = 1;
+                    }
+                } else {
+                    // frozen: carry the last state forward
+                    for (int f = 0; f < kStateWords; ++f) Sk[f] = Sp[f];
+                }
+            }
+            als[r] = alpha;
+            t1s[r] = on ? phi / rho : 0.0;
+            t2s[r] = on ? theta / rho : 0.0;
+        }
+        live[r] = on;
+    }
+    __syncthreads();
+    double sq = 0.0;
+    const int64_t tot = (int64_t)a.n * R;
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < tot;
+         idx += (int64_t)gridDim.x * kBlock) {
+        const int r = (int)(idx % R);           // == threadIdx.x % R
+        const int64_t j = idx / R;
+        double vj;
+        if (live[r] && als[r] > 0.0) {
+            const float vv = (float)((double)a.Q[idx] / als[r]);
+            a.V[idx] = vv;
+            vj = (double)vv;
+        } else {
+            vj = (double)a.V[idx];
+        }
+        if (a.mode == MODE_INIT) {
+            a.W[idx] = vj;
+        } else if (live[r]) {
+            const double wj = a.W[idx];
+            a.Y[idx] = a.Y[idx] + t1s[r] * wj;
+            a.W[idx] = vj - t2s[r] * wj;
+        }
+        a.Zout[idx] = (float)(a.d[j] * vj);
+        const double dv = vj / a.d[j];
+        sq += dv * dv;
+    }
+    // per-RHS sum over the workgroup in a fixed order
+    accs[threadIdx.x] = sq;
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double s2 = 0.0;
+        for (int q = 0; q < kBlock / R; ++q) s2 += accs[q * R + threadIdx.x];
+        a.part_out[(int64_t)blockIdx.x * R + threadIdx.x] = s2;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.mode == MODE_ITER) {
+        a.ctl[C_ITERS] = k;
+        a.ctl[C_CNT0 + (1 - a.parity)] = k + 1;
+    }
+}
+
+// dm[j][r] = d_j y[j][r]; eta of the last step for right-hand sides still active.
+__global__ __launch_bounds__(kBlock) void k_bfinal(BArgs a, double *dm)
+{
+#pragma clang fp contract(off)
+    __shared__ double accs[kBlock];
+    __shared__ double v2[kMaxRhs];
+    const int R = a.R;
+    const int kk = a.ctl[C_ITERS];
+    if (blockIdx.x == 0 && kk >= 1) {
+        sum_rhs_all(a.part_in, a.np_in, R, accs, v2);
+        if (threadIdx.x < R) {
+            const int r = threadIdx.x;
+            double *Sk = srow(a, kk, r);
+            if (a.act[r]) {
+                const double vn = sqrt(v2[r]);
+                const double eta = Sk[S_PSI] * vn / srow(a, 0, r)[S_ARNORM0];
+                Sk[S_ETA] = eta;
+                Sk[S_VNORM] = vn;
+                if (a.tol > 0.0 && eta <= a.tol) a.why[r] = 1;
+                else if (Sk[S_ALPHA] == 0.0 || Sk[S_BETA] == 0.0) a.why[r] = 3;
+            }
+        }
+    }
+    const int64_t tot = (int64_t)a.n * R;
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < tot;
+         idx += (int64_t)gridDim.x * kBlock)
+        dm[idx] = a.d[idx / R] * a.Y[idx];
+}
+
+}  // namespace lsqr

@@ -1,0 +1,161 @@
+"""Learned column-scaling preconditioner: model container, target search,
+GPU training driver and the solve with the Jacobi fallback.
+
+A small MLP (6 -> 64 -> 64 -> 1, GELU, softplus output) maps per-column
+features to a multiplier of the Jacobi scale, d_j = d_j^Jacobi softplus(z_j).
+Any d > 0 leaves the least-squares solution unchanged; only the iteration
+count moves.  Features, inference (BF16) and training (FP32 forward/backward
+and Adam) run in the library's kernels; this module orchestrates them.
+
+Training targets come from a search per system over a low-dimensional family
+of log multipliers
+
+    l_j(theta) = a0 + a1 f3_j + b (f2_j - mean f2) + c (f6_j - mean f6)
+
+(depth index, ray coverage, neighbour coverage): coordinate descent over
+theta on a grid, minimising LSQR iterations to the tolerance, capped at twice
+Jacobi's count.  The target of column j is l_j at the best theta.
+
+Fallback and judge: a learned scale that is not finite and positive is
+replaced by Jacobi inside lsqr_create; a learned solve that has not reached
+the tolerance within twice the Jacobi iteration count is redone with Jacobi.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import math
+import time
+
+import numpy as np
+
+from .lsqr import Solver, Trainer
+
+NPARAMS = 4673
+H = 64
+
+
+@dataclasses.dataclass
+class ColumnScaleModel:
+    params: np.ndarray          # float32 [NPARAMS]
+    mean: np.ndarray            # float32 [6] feature standardisation
+    std: np.ndarray             # float32 [6]
+    meta: dict
+
+    def save(self, path):
+        np.savez(path, params=self.params.astype(np.float32), mean=self.mean.astype(np.float32),
+                 std=self.std.astype(np.float32), meta=np.array(json.dumps(self.meta)))
+
+    @classmethod
+    def load(cls, path):
+        z = np.load(path, allow_pickle=False)
+        return cls(params=z["params"], mean=z["mean"], std=z["std"], meta=json.loads(str(z["meta"])))
+
+
+def initial_params(seed=0):
+    """He-normal hidden weights, zero hidden biases, small output weights and
+    the output bias at softplus^-1(1) = log(e - 1): the untrained net is Jacobi."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.standard_normal(H * 6) * math.sqrt(2.0 / 6), np.zeros(H),
+             rng.standard_normal(H * H) * math.sqrt(2.0 / H), np.zeros(H),
+             rng.standard_normal(H) * math.sqrt(2.0 / H) * 0.1, [math.log(math.e - 1.0)]]
+    return np.concatenate([np.asarray(p, dtype=np.float64) for p in parts]).astype(np.float32)
+
+
+def family_log_multiplier(feat, theta):
+    """l_j(theta) for host features [n, 6] (see the module docstring)."""
+    a0, a1, b, c = theta
+    f = np.asarray(feat, dtype=np.float64)
+    return a0 + a1 * f[:, 2] + b * (f[:, 1] - f[:, 1].mean()) + c * (f[:, 5] - f[:, 5].mean())
+
+
+def iterations_to_tol(system, col_scale, tol, cap):
+    """LSQR iterations to eta <= tol with the given scale (None: Jacobi)."""
+    kw = dict(precond="jacobi") if col_scale is None else dict(precond="user", col_scale=col_scale)
+    with Solver.from_system(system, check_every=8, **kw) as sol:
+        dm, _, info = sol.solve(system.dt, int(cap), tol=tol, history=False)
+    return info["iters"] if info["istop"] == 1 else int(cap) + 1, info
+
+
+def search_targets(system, tol=1e-6, grid=(-1.0, -0.5, 0.5, 1.0), scales=(1.0, 1.0, 0.5, 0.5),
+                   rounds=1, log=None):
+    """Coordinate descent over theta; returns (features [n,6], targets [n],
+    theta, Jacobi iterations, best iterations)."""
+    with Solver.from_system(system, precond="jacobi") as sol:
+        feat = sol.column_features().cpu().numpy().astype(np.float64)
+        djac = sol.scale()
+    kj, _ = iterations_to_tol(system, None, tol, 20000)
+    theta = np.zeros(4)
+    best = kj
+    for _ in range(rounds):
+        for p in range(4):
+            for v in grid:
+                th = theta.copy()
+                th[p] = v * scales[p]
+                d = djac * np.exp(family_log_multiplier(feat, th))
+                k, _ = iterations_to_tol(system, d, tol, 2 * kj)
+                if k < best:
+                    best, theta = k, th
+    if log:
+        log(f"  search: jacobi {kj} -> best {best} at theta {np.round(theta, 3).tolist()}")
+    return feat, family_log_multiplier(feat, theta), theta, kj, best
+
+
+def train(feats, targets, epochs=60, batch=4096, lr=1e-3, seed=0, log=None):
+    """Fit the MLP on the GPU (the library's FP32 forward/backward and Adam)."""
+    import torch
+    X = np.concatenate(feats).astype(np.float64)
+    T = np.concatenate(targets).astype(np.float64)
+    mean = X.mean(axis=0)
+    std = X.std(axis=0)
+    std[std == 0] = 1.0
+    Xs = torch.from_numpy(((X - mean) / std).astype(np.float32)).cuda()
+    Tt = torch.from_numpy(T.astype(np.float32)).cuda()
+    N = len(T)
+    batch = min(batch, N)
+    tr = Trainer(initial_params(seed), batch)
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(N)).cuda()
+        for s0 in range(0, N - batch + 1, batch):
+            idx = perm[s0:s0 + batch]
+            tr.step(Xs[idx].contiguous(), Tt[idx].contiguous(), lr)
+        if ep % 10 == 9 or ep == epochs - 1:
+            losses = [tr.grad(Xs[i:i + batch].contiguous(), Tt[i:i + batch].contiguous())[1]
+                      for i in range(0, N - batch + 1, batch)]
+            hist.append((ep + 1, float(np.mean(losses))))
+            if log:
+                log(f"  epoch {ep + 1}: loss {hist[-1][1]:.4e}")
+    params = tr.params()
+    tr.close()
+    base = float(np.mean(T ** 2))       # loss of the untrained (Jacobi) multiplier
+    return ColumnScaleModel(params=params, mean=mean.astype(np.float32), std=std.astype(np.float32),
+                            meta={"samples": int(N), "epochs": epochs, "batch": batch, "lr": lr,
+                                  "loss_history": hist, "loss_at_jacobi": base})
+
+
+def learned_scale(system, model):
+    """Host float64 [n] learned column scale for a system."""
+    import torch
+    with Solver.from_system(system) as sol:
+        p = torch.from_numpy(np.ascontiguousarray(model.params, dtype=np.float32)).cuda()
+        d = sol.mlp_scale(p, model.mean, model.std)
+        return d.cpu().numpy()
+
+
+def solve_learned(system, model, tol, k_jacobi=None, cap=20000, precision="fp64"):
+    """Solve with the learned scale; fall back to Jacobi when the learned solve
+    has not converged within twice the Jacobi count (or within cap)."""
+    t0 = time.perf_counter()
+    d = learned_scale(system, model)
+    limit = 2 * k_jacobi if k_jacobi else cap
+    with Solver.from_system(system, precond="user", col_scale=d, precision=precision,
+                            check_every=16) as sol:
+        dm, _, info = sol.solve(system.dt, int(limit), tol=tol, history=False)
+    if info["istop"] != 1 and k_jacobi is not None:
+        with Solver.from_system(system, precond="jacobi", precision=precision) as sol:
+            dm, _, info = sol.solve(system.dt, cap, tol=tol, history=False)
+        info["fallback_used"] = 1
+    info["seconds"] = time.perf_counter() - t0
+    return dm, info

@@ -59,6 +59,10 @@ class Info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class BatchCfg(ctypes.Structure):
+    _fields_ = [("rhs_tile", ctypes.c_int), ("grid", ctypes.c_int), ("ms_per_iter", ctypes.c_double)]
+
+
 class KStats(ctypes.Structure):
     _fields_ = [("fwd_ms", ctypes.c_double), ("adj_ms", ctypes.c_double),
                 ("fwd_launches", ctypes.c_int), ("adj_launches", ctypes.c_int),
@@ -86,6 +90,19 @@ def load():
         "lsqr_get_transpose": (I, [P, P, P, P]),
         "lsqr_kernel_stats": (I, [P, ctypes.POINTER(KStats)]),
         "lsqr_get_quantised": (I, [P, P, P, P]),
+        "lsqr_solve_batched": (I, [ctypes.POINTER(P), I, I, ctypes.POINTER(P), I, I, D,
+                                   ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(Info)]),
+        "lsqr_apply_block": (I, [P, I, P, P]),
+        "lsqr_apply_t_block": (I, [P, I, P, P]),
+        "lsqr_set_batch_config": (I, [P, ctypes.POINTER(BatchCfg)]),
+        "lsqr_autotune_batched": (I, [P, I, I, ctypes.POINTER(BatchCfg)]),
+        "lsqr_column_features": (I, [P, P]),
+        "lsqr_mlp_scale": (I, [P, P, P, P, P, P]),
+        "lsqr_trainer_create": (I, [I, P, P, ctypes.POINTER(P)]),
+        "lsqr_trainer_grad": (I, [P, I, P, P, P, ctypes.POINTER(D)]),
+        "lsqr_trainer_step": (I, [P, I, P, P, ctypes.c_float, ctypes.POINTER(D)]),
+        "lsqr_trainer_params": (I, [P, P, P]),
+        "lsqr_trainer_destroy": (None, [P]),
         "lsqr_destroy": (None, [P]),
         "lsqr_status_string": (ctypes.c_char_p, [I]),
         "lsqr_last_error": (ctypes.c_char_p, [P]),
@@ -250,6 +267,79 @@ class Solver:
         self._check(self._lib.lsqr_get_quantised(self._ctx, _ptr(sc), _ptr(qr), _ptr(qc)))
         return sc, qr, qc
 
+    def apply_block(self, x, y=None):
+        """Y = Abar D X for a row-major [n][R] float32 device block (R a power of 2 <= 32)."""
+        R = x.shape[1]
+        if y is None:
+            y = self._torch.empty((self.m + 2 * self.n, R), dtype=self._torch.float32,
+                                  device=x.device)
+        self._check(self._lib.lsqr_apply_block(self._ctx, R, _ptr(x), _ptr(y)))
+        return y
+
+    def apply_t_block(self, y, x=None):
+        """X = D Abar^T Y for a row-major [m+2n][R] float32 device block."""
+        R = y.shape[1]
+        if x is None:
+            x = self._torch.empty((self.n, R), dtype=self._torch.float32, device=y.device)
+        self._check(self._lib.lsqr_apply_t_block(self._ctx, R, _ptr(y), _ptr(x)))
+        return x
+
+    def set_batch_config(self, rhs_tile, grid):
+        cfg = BatchCfg(int(rhs_tile), int(grid), 0.0)
+        self._check(self._lib.lsqr_set_batch_config(self._ctx, ctypes.byref(cfg)))
+
+    def autotune_batched(self, nrhs, probe_iters=4, cache=None):
+        """Choose the batched schedule for nrhs right-hand sides: from the JSON
+        cache file `cache` when it holds this shape, else by timing every
+        schedule on the device (median of 5) and storing the winner."""
+        import json
+        key = self.shape_key(nrhs)
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            t = table[key]
+            self.set_batch_config(t["rhs_tile"], t["grid"])
+            return dict(t, cached=True)
+        cfg = BatchCfg()
+        self._check(self._lib.lsqr_autotune_batched(self._ctx, int(nrhs), int(probe_iters),
+                                                    ctypes.byref(cfg)))
+        t = {"rhs_tile": cfg.rhs_tile, "grid": cfg.grid, "ms_per_iter": cfg.ms_per_iter}
+        if cache:
+            table[key] = t
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(t, cached=False)
+
+    def shape_key(self, nrhs):
+        """Shape signature of a batched schedule: system size, padded RHS count, device."""
+        R = 1
+        while R < nrhs:
+            R *= 2
+        name = self._torch.cuda.get_device_name(self._device).replace(" ", "_")
+        return f"m{self.m}_n{self.n}_nnz{self.nnz}_R{R}_{name}"
+
+    def column_features(self):
+        """[n, 6] float32 device tensor of the learned scale's column features."""
+        f = self._torch.empty((self.n, 6), dtype=self._torch.float32, device="cuda")
+        self._check(self._lib.lsqr_column_features(self._ctx, _ptr(f)))
+        return f
+
+    def mlp_scale(self, params, mean, std, feat=None):
+        """Learned column scale (device float64 [n]): Jacobi times softplus of the
+        BF16 MLP on standardised features.  params: float32 device tensor."""
+        if feat is None:
+            feat = self.column_features()
+        mean = np.ascontiguousarray(mean, dtype=np.float32)
+        std = np.ascontiguousarray(std, dtype=np.float32)
+        d = self._torch.empty(self.n, dtype=self._torch.float64, device="cuda")
+        self._check(self._lib.lsqr_mlp_scale(self._ctx, _ptr(params), _ptr(mean), _ptr(std),
+                                             _ptr(feat), _ptr(d)))
+        return d
+
     def kernel_stats(self):
         ks = KStats()
         self._check(self._lib.lsqr_kernel_stats(self._ctx, ctypes.byref(ks)))
@@ -271,3 +361,91 @@ class Solver:
 
     def __exit__(self, *a):
         self.close()
+
+
+def solve_batched(solvers, dts, iters, tol=0.0, history=True):
+    """LSQR for several systems with nrhs right-hand sides each, in one batched
+    call.  dts: list of [m_s, nrhs] arrays (numpy: host, torch CUDA float64:
+    device), all on the same side.  Returns (dms, hists, infos): dms [n_s, nrhs],
+    hists [iters+1, nrhs, 3] per system (or None), infos[s][r] dicts."""
+    lib = load()
+    nsys = len(solvers)
+    nrhs = int(dts[0].shape[1])
+    dev = _is_torch(dts[0])
+    if dev:
+        import torch
+        dts = [d.contiguous() for d in dts]
+        dms = [torch.empty((s.n, nrhs), dtype=torch.float64, device=dts[0].device) for s in solvers]
+    else:
+        dts = [np.ascontiguousarray(d, dtype=np.float64) for d in dts]
+        dms = [np.empty((s.n, nrhs)) for s in solvers]
+    for s, d in zip(solvers, dts):
+        assert tuple(d.shape) == (s.m, nrhs)
+    hists = [np.empty((iters + 1, nrhs, 3)) for _ in solvers] if history else None
+    P = ctypes.c_void_p
+    ctxs = (P * nsys)(*[s._ctx.value for s in solvers])
+    dtp = (P * nsys)(*[_ptr(d).value for d in dts])
+    dmp = (P * nsys)(*[_ptr(d).value for d in dms])
+    hp = (P * nsys)(*[h.ctypes.data for h in hists]) if history else None
+    infos = (Info * (nsys * nrhs))()
+    rc = lib.lsqr_solve_batched(ctxs, nsys, nrhs, dtp, MEM_DEVICE if dev else MEM_HOST, int(iters),
+                                float(tol), dmp, hp, infos)
+    if rc != LSQR_OK:
+        raise LsqrError(rc, lib.lsqr_last_error(solvers[0]._ctx).decode())
+    out = [[infos[s * nrhs + r].as_dict() for r in range(nrhs)] for s in range(nsys)]
+    return dms, hists, out
+
+
+class Trainer:
+    """FP32 training state of the column-scale MLP on the GPU."""
+
+    NPARAMS = 4673
+
+    def __init__(self, params, max_batch, stream=None):
+        import torch
+        self._lib = load()
+        self._torch = torch
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.NPARAMS
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        h = ctypes.c_void_p()
+        rc = self._lib.lsqr_trainer_create(int(max_batch), _ptr(p), st, ctypes.byref(h))
+        if rc != LSQR_OK:
+            raise LsqrError(rc, "trainer creation failed")
+        self._h = h
+        self.max_batch = int(max_batch)
+
+    def grad(self, x, target):
+        g = self._torch.empty(self.NPARAMS, dtype=self._torch.float32, device="cuda")
+        loss = ctypes.c_double()
+        rc = self._lib.lsqr_trainer_grad(self._h, int(x.shape[0]), _ptr(x), _ptr(target), _ptr(g),
+                                         ctypes.byref(loss))
+        if rc != LSQR_OK:
+            raise LsqrError(rc, "trainer gradient failed")
+        return g, loss.value
+
+    def step(self, x, target, lr=1e-3, want_loss=False):
+        loss = ctypes.c_double()
+        rc = self._lib.lsqr_trainer_step(self._h, int(x.shape[0]), _ptr(x), _ptr(target),
+                                         float(lr), ctypes.byref(loss) if want_loss else None)
+        if rc != LSQR_OK:
+            raise LsqrError(rc, "trainer step failed")
+        return loss.value if want_loss else None
+
+    def params(self):
+        p = np.empty(self.NPARAMS, dtype=np.float32)
+        rc = self._lib.lsqr_trainer_params(self._h, _ptr(p), None)
+        if rc != LSQR_OK:
+            raise LsqrError(rc, "trainer read-back failed")
+        return p
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lsqr_trainer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -134,6 +134,29 @@ def config3_systems() -> list[Config]:
     return out
 
 
+def config0_variant(seed: int, n_stations: int, damp: float) -> Config:
+    """Config-0 geometry (16x16x9 grid, 1.5 degree region, 10 periods 2-20 s,
+    straight rays) with another station draw, station count and damping: the
+    family the learned column scale is trained and evaluated on."""
+    c = config0(seed)
+    c.n_stations = int(n_stations)
+    c.damp = float(damp)
+    c.name = f"cfg0_s{n_stations}_d{damp:.3f}_seed{seed}"
+    return c
+
+
+def learned_family(first_seed: int, count: int, stations=(20, 60), damp=(0.05, 0.5)):
+    """`count` config-0-variant systems with station counts uniform in
+    `stations` and damping log-uniform in `damp`, seeds first_seed, ..."""
+    rng = np.random.default_rng(first_seed * 7919 + count)
+    out = []
+    for i in range(count):
+        ns = int(rng.integers(stations[0], stations[1] + 1))
+        dp = float(np.exp(rng.uniform(np.log(damp[0]), np.log(damp[1]))))
+        out.append(config0_variant(first_seed + i, ns, dp))
+    return out
+
+
 def small_config(nx=8, ny=8, nz=6, n_stations=12, n_periods=5, region=0.7, bent=True,
                  seed=0, damp=0.1, smooth=0.5, min_wavelengths=None) -> Config:
     """A reduced geometry with the same structure, for fast tests."""
