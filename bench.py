@@ -54,14 +54,18 @@ def cpu_baseline(s, iters_sample):
                       f"system, {dt:.1f} s"}
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_2604_11920_amd", "csrc", "kernels_lsqr.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_11920_amd", "csrc", f)
+               for f in ("lsqr_kernels.cuh", "internal.h", "kernels_f64.hip", "kernels_common.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cfg1_fp64.txt")
 CALIB_BYTES = float(1 << 30)        # the calibration kernel reads 1 GiB and writes 1 GiB
 
 
 def source_hash():
     import hashlib
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def pmc_summary(fetch_csv, write_csv):
@@ -175,6 +179,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--row-format", default="auto", choices=["auto", "csr", "runs"])
+    ap.add_argument("--xcd-bands", action="store_true",
+                    help="transposed product: one contiguous column band per XCD")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32 rate and the time-to-tolerance comparisons")
     ap.add_argument("--ttt-tol", type=float, default=1e-6)
@@ -215,7 +221,7 @@ def main():
     log(f"[bench] generated {args.config}: m={s.m} n={s.n} nnz={s.nnz} "
         f"in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    sol = Solver.from_system(s, timing=True, row_format=args.row_format)
+    sol = Solver.from_system(s, timing=True, row_format=args.row_format, xcd_bands=args.xcd_bands)
     torch.cuda.synchronize()
     log(f"[bench] create (copy + device transpose) {time.perf_counter() - t0:.2f}s")
     dt = torch.from_numpy(s.dt).cuda()
@@ -274,7 +280,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": workload, "m": s.m, "n": s.n, "nnz": s.nnz,
                    "iters_per_step": iters, "precision": "fp64", "precond": "none",
-                   "row_format": args.row_format},
+                   "row_format": args.row_format, "xcd_bands": args.xcd_bands},
         "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "kernel": "k_fwd (forward CSR product)" if dom == "fwd"

@@ -83,6 +83,9 @@ typedef void (*lsqr_free_fn)(void *ptr, size_t bytes, void *user);
 
 #define LSQR_FLAG_TIMING 1u     /* record HIP events around the sparse kernels  */
 #define LSQR_FLAG_NO_GRAPH 2u   /* launch iterations one by one, no hipGraph     */
+#define LSQR_FLAG_XCD_BANDS 4u  /* transposed product: each of the 8 XCDs walks a
+                                   contiguous eighth of the columns (L2 locality);
+                                   results are bitwise identical either way      */
 
 typedef struct {
     lsqr_precision precision;

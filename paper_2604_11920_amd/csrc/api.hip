@@ -521,6 +521,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if (use_runs) { c->R64.run_ptr = c->run_ptr; c->R64.runs = c->runs; c->R64.roff = c->roff; }
     c->C64.vt = VT_F64; c->C64.cp = c->cp; c->C64.ri = c->ri; c->C64.val = c->cv;
     c->C64.lpc = o.lanes_per_col ? o.lanes_per_col : pick_lanes(avg_col);
+    c->C64.xcd_bands = (o.flags & LSQR_FLAG_XCD_BANDS) ? 1 : 0;
     // column scaling
     launch_fill(st, n, 1.0, c->ones);
     if (o.precond == LSQR_PRECOND_NONE) {

@@ -76,6 +76,7 @@ struct ColFmt {
     const int32_t *ri = nullptr;       // [nnz] rows, ascending within a column
     const void *val = nullptr;
     int lpc = 64;
+    int xcd_bands = 0;                 // 1: contiguous column band per XCD (k_adj)
 };
 
 // Type-dispatched launchers (kernels_f64.hip, kernels_f32.hip).

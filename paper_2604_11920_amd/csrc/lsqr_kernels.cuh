@@ -360,6 +360,7 @@ struct AdjArgs {
     int parity;
     int mode;
     int data_only;           // 1: G^T part only (no smoothing/damping, no scale)
+    int xcd_bands;           // 1: each XCD's workgroups take a contiguous band of columns
 };
 
 template <class M, class V, int LPC>
@@ -392,7 +393,18 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
     constexpr int CPB = kBlock / LPC;
     const int lane = threadIdx.x % LPC;
     const int64_t tL = a.m, tD = a.m + a.n;
-    for (int j = blockIdx.x * CPB + threadIdx.x / LPC; j < a.n; j += gridDim.x * CPB) {
+    // Columns visited by this workgroup.  With XCD bands, workgroup b (which the
+    // dispatcher places on XCD b % 8) walks a contiguous eighth of the columns,
+    // so each XCD's L2 serves the gathers of one lateral band of the model.
+    int jlo = 0, jhi = a.n, jstart = blockIdx.x * CPB, jstep = gridDim.x * CPB;
+    if (a.xcd_bands && gridDim.x % 8 == 0) {
+        const int band = blockIdx.x & 7, slot = blockIdx.x >> 3;
+        jlo = (int)((int64_t)a.n * band / 8);
+        jhi = (int)((int64_t)a.n * (band + 1) / 8);
+        jstart = jlo + slot * CPB;
+        jstep = (gridDim.x >> 3) * CPB;
+    }
+    for (int j = jstart + threadIdx.x / LPC; j < jhi; j += jstep) {
         const int64_t s = a.cp[j], e = a.cp[j + 1];
         A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
         int64_t p = s + lane;
@@ -606,7 +618,7 @@ hipError_t adj_launch(hipStream_t st, const Problem &P, int grid, const ColFmt &
                       int parity, int mode, int data_only)
 {
     AdjArgs a{C.cp, C.ri, C.val, P.m, (int)P.n, P.nx, P.ny, P.nz, P.w, P.damp, d, T, Tg, v, q,
-              part_out, part_t, np_t, S, ctl, parity, mode, data_only};
+              part_out, part_t, np_t, S, ctl, parity, mode, data_only, C.xcd_bands};
     switch (C.vt) {
     case VT_F64:
         if constexpr (Wide<V>::value) adj_launch_m<double, V>(st, grid, C, a);

@@ -22,7 +22,7 @@ LSQR_E_DEVICE, LSQR_E_OOM, LSQR_E_UNSUPPORTED = -4, -5, -6
 MEM_HOST, MEM_DEVICE = 0, 1
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 PRECOND = {"none": 0, "jacobi": 1, "user": 2}
-FLAG_TIMING, FLAG_NO_GRAPH = 1, 2
+FLAG_TIMING, FLAG_NO_GRAPH, FLAG_XCD_BANDS = 1, 2, 4
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -141,7 +141,7 @@ class Solver:
     def __init__(self, row_ptr, col, val, nx, ny, nz, damp, smooth, precision="fp64",
                  precond="none", col_scale=None, stream=None, timing=False, graph=True,
                  lanes_per_row=0, lanes_per_col=0, check_every=0, refine_sweeps=5,
-                 row_format="auto", torch_alloc=True):
+                 row_format="auto", xcd_bands=False, torch_alloc=True):
         import torch
         lib = load()
         self._torch = torch
@@ -171,7 +171,8 @@ class Solver:
         opts.refine_sweeps = int(refine_sweeps)
         opts.check_every = int(check_every)
         opts.stream = stream.cuda_stream
-        opts.flags = (FLAG_TIMING if timing else 0) | (0 if graph else FLAG_NO_GRAPH)
+        opts.flags = ((FLAG_TIMING if timing else 0) | (0 if graph else FLAG_NO_GRAPH)
+                      | (FLAG_XCD_BANDS if xcd_bands else 0))
         opts.lanes_per_row = int(lanes_per_row)
         opts.lanes_per_col = int(lanes_per_col)
         opts.row_format = {"auto": 0, "csr": 1, "runs": 2}[row_format]
