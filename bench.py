@@ -179,6 +179,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--row-format", default="auto", choices=["auto", "csr", "runs"])
+    ap.add_argument("--col-format", default="auto", choices=["auto", "csc", "runs"])
     ap.add_argument("--xcd-bands", action="store_true",
                     help="transposed product: one contiguous column band per XCD")
     ap.add_argument("--no-extras", action="store_true",
@@ -221,7 +222,8 @@ def main():
     log(f"[bench] generated {args.config}: m={s.m} n={s.n} nnz={s.nnz} "
         f"in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    sol = Solver.from_system(s, timing=True, row_format=args.row_format, xcd_bands=args.xcd_bands)
+    sol = Solver.from_system(s, timing=True, row_format=args.row_format,
+                             col_format=args.col_format, xcd_bands=args.xcd_bands)
     torch.cuda.synchronize()
     log(f"[bench] create (copy + device transpose) {time.perf_counter() - t0:.2f}s")
     dt = torch.from_numpy(s.dt).cuda()
@@ -280,7 +282,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": workload, "m": s.m, "n": s.n, "nnz": s.nnz,
                    "iters_per_step": iters, "precision": "fp64", "precond": "none",
-                   "row_format": args.row_format, "xcd_bands": args.xcd_bands},
+                   "row_format": args.row_format, "col_format": args.col_format,
+                   "xcd_bands": args.xcd_bands},
         "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "kernel": "k_fwd (forward CSR product)" if dom == "fwd"

@@ -85,7 +85,8 @@ typedef void (*lsqr_free_fn)(void *ptr, size_t bytes, void *user);
 #define LSQR_FLAG_NO_GRAPH 2u   /* launch iterations one by one, no hipGraph     */
 #define LSQR_FLAG_XCD_BANDS 4u  /* transposed product: each of the 8 XCDs walks a
                                    contiguous eighth of the columns (L2 locality);
-                                   results are bitwise identical either way      */
+                                   the product is unchanged, the partial sums of
+                                   its norm are grouped differently (last bits)  */
 
 typedef struct {
     lsqr_precision precision;
@@ -104,6 +105,10 @@ typedef struct {
                                 /* runs when runs average >= 2.5 columns), 1 = plain  */
                                 /* CSR, 2 = depth runs (runs of consecutive columns,  */
                                 /* i.e. of depth nodes under one lateral node, eq. 7) */
+    int col_format;             /* data block of the transposed product: 0 = auto,    */
+                                /* 1 = CSC, 2 = node runs (per lateral node, the rows */
+                                /* reaching it with their stretch of consecutive      */
+                                /* depths; needs nz <= 64, nnz < 2^32)                */
 } lsqr_opts;
 
 /* Stop reasons (info.istop):
@@ -232,7 +237,8 @@ lsqr_status lsqr_apply(lsqr_ctx *ctx, const double *x, double *y);
 
 /*
  * lsqr_apply_t — x = D Abar^T y = D (G^T y[0:m] + w L y[m:m+n] + lambda y[m+n:]),
- * device pointers, FP64.  Uses the stored transpose (no atomics).
+ * device pointers, FP64.  Uses the FP64 transposed format of the solver (the
+ * CSC, or the node runs when opts.col_format selected them; no atomics).
  */
 lsqr_status lsqr_apply_t(lsqr_ctx *ctx, const double *y, double *x);
 

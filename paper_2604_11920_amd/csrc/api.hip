@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "runs_host.h"
 
 using namespace lsqr;
 
@@ -65,63 +66,6 @@ lsqr_status validate_host_csr(const lsqr_csr *G)
     return LSQR_OK;
 }
 
-// Depth runs of a CSR: maximal stretches of consecutive columns within a row
-// (eq. 7 orders unknowns depth fastest, so each lateral node of a ray gives a
-// run of depths), split at 255 entries.  run = (first column << 8) | length;
-// roff = offset of the run's first value within its row.  Returns false when
-// the format cannot hold the matrix (row longer than 65535 or n >= 2^24).
-bool build_runs_host(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
-                     std::vector<int64_t> &run_ptr, std::vector<uint32_t> &runs,
-                     std::vector<uint16_t> &roff)
-{
-    if (n >= (1 << 24)) return false;
-    for (int64_t i = 0; i < m; ++i)
-        if (rp[i + 1] - rp[i] > 65535) return false;
-    run_ptr.assign((size_t)m + 1, 0);
-    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (rp[m] < (1 << 20)) nt = 1;
-    auto is_start = [&](int64_t i, int64_t p, int64_t len) {
-        return p == rp[i] || ci[p] != ci[p - 1] + 1 || len == 255;
-    };
-    {
-        std::vector<std::thread> th;
-        for (unsigned t = 0; t < nt; ++t)
-            th.emplace_back([&, t]() {
-                for (int64_t i = m * t / nt; i < m * (t + 1) / nt; ++i) {
-                    int64_t cnt = 0, len = 0;
-                    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
-                        if (is_start(i, p, len)) { ++cnt; len = 0; }
-                        ++len;
-                    }
-                    run_ptr[i + 1] = cnt;
-                }
-            });
-        for (auto &x : th) x.join();
-    }
-    for (int64_t i = 0; i < m; ++i) run_ptr[i + 1] += run_ptr[i];
-    runs.resize((size_t)run_ptr[m]);
-    roff.resize((size_t)run_ptr[m]);
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < nt; ++t)
-        th.emplace_back([&, t]() {
-            for (int64_t i = m * t / nt; i < m * (t + 1) / nt; ++i) {
-                int64_t r = run_ptr[i] - 1, len = 0;
-                for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
-                    if (is_start(i, p, len)) {
-                        if (r >= run_ptr[i]) runs[r] = ((uint32_t)ci[p - len] << 8) | (uint32_t)len;
-                        ++r;
-                        len = 0;
-                        roff[r] = (uint16_t)(p - rp[i]);
-                    }
-                    ++len;
-                }
-                if (r >= run_ptr[i]) runs[r] = ((uint32_t)ci[rp[i + 1] - len] << 8) | (uint32_t)len;
-            }
-        });
-    for (auto &x : th) x.join();
-    return true;
-}
-
 int pick_lanes(double avg)
 {
     if (avg >= 384) return 64;
@@ -148,7 +92,8 @@ lsqr_status setup_engine(lsqr_ctx *c, Engine &E, int vec, const RowFmt &R, const
     E.C = C;
     if (R.run_ptr) E.g_fwd = cap_blocks(std::max<int64_t>(m * 64, 2 * n), kBlock, 2048);
     else E.g_fwd = cap_blocks(std::max<int64_t>(m * R.lpr, 2 * n), kBlock, 2048);
-    E.g_adj = cap_blocks(n * C.lpc, kBlock, 2048);
+    if (C.nrp) E.g_adj = (int)std::max<int64_t>(1, std::min<int64_t>(n / c->P.nz, 2048));
+    else E.g_adj = cap_blocks(n * C.lpc, kBlock, 2048);
     E.g_upd = cap_blocks(n, kBlock, 1024);
     E.T[0] = ctx_alloc_bytes(c, mb * vs);
     E.T[1] = ctx_alloc_bytes(c, mb * vs);
@@ -391,6 +336,8 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         return fail(nullptr, LSQR_E_INVALID_ARG, "lanes must be 0, 4, 8, 16, 32 or 64");
     if (o.row_format < 0 || o.row_format > 2)
         return fail(nullptr, LSQR_E_INVALID_ARG, "row_format must be 0, 1 or 2");
+    if (o.col_format < 0 || o.col_format > 2)
+        return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1 or 2");
     if (o.check_every < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "check_every must be >= 0");
     if (o.refine_sweeps < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "refine_sweeps must be >= 0");
     if (G->mem == LSQR_MEM_HOST) {
@@ -515,6 +462,34 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             return bail(LSQR_E_UNSUPPORTED, "depth-run rows need rows of <= 65535 entries and n < 2^24");
         }
     }
+    // node runs of the data block for the transposed product
+    bool use_nruns = false;
+    if (o.col_format == 2 && nnz > 0) {
+        NodeRuns NR;
+        if (!build_node_runs_host(m, n, G->nz, hrow, hcol, NR))
+            return bail(LSQR_E_UNSUPPORTED, "node runs need nz <= 64, m < 2^32 and nnz < 2^32");
+        const int64_t nr = NR.nrp.back(), nn = n / G->nz;
+        c->nnruns = nr;
+        c->nrp = ctx_alloc<int64_t>(c, nn + 1);
+        c->nvq = ctx_alloc<int64_t>(c, 4 * nn + 1);
+        c->nrow = ctx_alloc<uint32_t>(c, nr);
+        c->ndesc = ctx_alloc<uint16_t>(c, nr);
+        c->norder = ctx_alloc<int32_t>(c, nn);
+        c->nsrc = ctx_alloc<uint32_t>(c, nr);
+        c->ndst = ctx_alloc<uint32_t>(c, nr);
+        c->nval = ctx_alloc<double>(c, nnz);
+        if (!c->nrp || !c->nvq || !c->nrow || !c->ndesc || !c->norder || !c->nsrc || !c->ndst || !c->nval)
+            return bail(LSQR_E_OOM, "device allocation failed");
+        CR_TRY(hipMemcpy(c->nrp, NR.nrp.data(), (nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->nvq, NR.nvq.data(), (4 * nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->nrow, NR.row.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->ndesc, NR.desc.data(), nr * sizeof(uint16_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->norder, NR.order.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->nsrc, NR.src.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->ndst, NR.dst.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
+        launch_gather_runs(st, nr, c->nsrc, c->ndst, c->ndesc, c->va, c->nval, 8);
+        use_nruns = true;
+    }
     // FP64 formats
     c->R64.vt = VT_F64; c->R64.rp = c->rp; c->R64.ci = c->ci; c->R64.val = c->va;
     c->R64.lpr = o.lanes_per_row ? o.lanes_per_row : pick_lanes(avg_row);
@@ -539,6 +514,10 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     // the solver's formats
     RowFmt R = c->R64;
     ColFmt C = c->C64;
+    if (use_nruns) {
+        C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
+        C.norder = c->norder; C.val = c->nval;
+    }
     int vec = VT_F64;
     if (o.precision == LSQR_FP32) {
         c->va32 = ctx_alloc<float>(c, nnz);
@@ -548,6 +527,12 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         launch_convert_f32(st, nnz, c->cv, c->cv32);
         R.vt = VT_F32; R.val = c->va32;
         C.vt = VT_F32; C.val = c->cv32;
+        if (use_nruns) {
+            c->nval32 = ctx_alloc<float>(c, nnz);
+            if (!c->nval32) return bail(LSQR_E_OOM, "device allocation failed");
+            launch_convert_f32(st, nnz, c->nval, c->nval32);
+            C.val = c->nval32;
+        }
         vec = VT_F32;
     } else if (mixed) {
         const int vt = o.precision == LSQR_BF16 ? VT_BF16 : VT_F16;
@@ -568,6 +553,12 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         launch_quantise_cols(st, nnz, c->ri, c->cv, c->sigma, vt, c->qcol);
         R.vt = vt; R.val = c->qrow; R.sigma = c->sigma;
         C.vt = vt; C.val = c->qcol;
+        if (use_nruns) {      // the same codes, node-major
+            c->nvalq = ctx_alloc<uint16_t>(c, nnz);
+            if (!c->nvalq) return bail(LSQR_E_OOM, "device allocation failed");
+            launch_gather_runs(st, c->nnruns, c->nsrc, c->ndst, c->ndesc, c->qrow, c->nvalq, 2);
+            C.val = c->nvalq;
+        }
         c->CQ = C;
         vec = VT_F32;
     }
@@ -575,6 +566,11 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if (s != LSQR_OK) return bail(s, g_err);
     CR_TRY(hipGetLastError());
     CR_TRY(hipStreamSynchronize(st));
+    if (use_nruns) {          // the run map is only needed for the value gathers
+        ctx_release(c, c->nsrc);
+        ctx_release(c, c->ndst);
+        c->nsrc = c->ndst = nullptr;
+    }
     *out = c;
     return LSQR_OK;
 #undef CR_TRY
@@ -747,7 +743,13 @@ lsqr_status lsqr_apply_t(lsqr_ctx *c, const double *y, double *x)
     if (!c) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx is NULL");
     if (!x || !y) return fail(c, LSQR_E_INVALID_ARG, "x and y must not be NULL");
     DeviceGuard dg(c->device);
-    launch_adj(c->st, c->P, std::min(2048, c->eng.g_adj), VT_F64, c->C64, c->d, y, y, nullptr, x,
+    // the FP64 transposed format the solver reads (node runs when built)
+    ColFmt C = c->C64;
+    if (c->nrp) {
+        C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
+        C.norder = c->norder; C.val = c->nval;
+    }
+    launch_adj(c->st, c->P, std::min(2048, c->eng.g_adj), VT_F64, C, c->d, y, y, nullptr, x,
                c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 0);
     HIP_TRY(c, hipGetLastError());
     return LSQR_OK;
@@ -807,8 +809,15 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
     else fwd += nnz * 4.0;
     if (E.R.sigma) fwd += m * 4.0 + m * sx;
     out->fwd_bytes = fwd;
-    out->adj_bytes = nnz * ((double)vt_size(E.C.vt) + 4.0) + (n + 1) * 8.0 + mb * sx +
-                     n * (8.0 + 2.0 * sx);
+    if (E.C.nrp) {
+        const double nn = n / (double)c->P.nz;
+        out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->nnruns * 6.0 +
+                         (nn + 1) * 8.0 + (4 * nn + 1) * 8.0 + nn * 4.0 + mb * sx +
+                         n * (8.0 + 2.0 * sx);
+    } else {
+        out->adj_bytes = nnz * ((double)vt_size(E.C.vt) + 4.0) + (n + 1) * 8.0 + mb * sx +
+                         n * (8.0 + 2.0 * sx);
+    }
     return LSQR_OK;
 }
 

@@ -66,6 +66,11 @@ struct lsqr_ctx {
     int64_t *run_ptr = nullptr; uint32_t *runs = nullptr; uint16_t *roff = nullptr;
     int64_t nruns = 0;
     int64_t *cp = nullptr; int32_t *ri = nullptr; double *cv = nullptr;
+    // node runs of the data block (transposed product), values in node-major order
+    int64_t *nrp = nullptr, *nvq = nullptr; uint32_t *nrow = nullptr; uint16_t *ndesc = nullptr;
+    int32_t *norder = nullptr; double *nval = nullptr; float *nval32 = nullptr;
+    uint16_t *nvalq = nullptr; uint32_t *nsrc = nullptr, *ndst = nullptr;
+    int64_t nnruns = 0;
     double *d = nullptr, *ones = nullptr;
     lsqr::RowFmt R64;
     lsqr::ColFmt C64;

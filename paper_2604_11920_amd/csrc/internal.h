@@ -77,6 +77,13 @@ struct ColFmt {
     const void *val = nullptr;
     int lpc = 64;
     int xcd_bands = 0;                 // 1: contiguous column band per XCD (k_adj)
+    // Node runs (used instead of the CSC when nrp is set; val then holds the
+    // values in node-major run order).  Node k = columns [k nz, (k+1) nz).
+    const int64_t *nrp = nullptr;      // [nnodes+1] runs of node k: [nrp[k], nrp[k+1])
+    const int64_t *nvq = nullptr;      // [4 nnodes+1] value offset of each quarter of a node's runs
+    const uint32_t *nrow = nullptr;    // [nruns] data row of the run
+    const uint16_t *ndesc = nullptr;   // [nruns] (iz0 << 8) | len
+    const int32_t *norder = nullptr;   // [nnodes] nodes by decreasing run count
 };
 
 // Type-dispatched launchers (kernels_f64.hip, kernels_f32.hip).
@@ -105,6 +112,9 @@ void launch_jacobi(hipStream_t st, const Problem &P, const ColFmt &C, double *d)
 void launch_check_csr(hipStream_t st, int64_t m, int64_t n, const int64_t *row_ptr,
                       const int32_t *col, const double *val, int *flag);
 void launch_check_vec(hipStream_t st, int64_t n, const double *x, int positive, int *flag);
+// out[dst[r] + e] = in[src[r] + e] for e < len(desc[r]) (elements of elem_bytes = 2, 4 or 8)
+void launch_gather_runs(hipStream_t st, int64_t nr, const uint32_t *src, const uint32_t *dst,
+                        const uint16_t *desc, const void *in, void *out, int elem_bytes);
 void launch_convert_f32(hipStream_t st, int64_t nnz, const double *src, float *dst);
 void launch_row_scales(hipStream_t st, int64_t m, const int64_t *rp, const double *val, int vt,
                        float *sigma);

@@ -3,6 +3,8 @@
 // iterative refinement.  Also the vector-type dispatch of the LSQR launchers.
 #include <math.h>
 
+#include <algorithm>
+
 #include "lsqr_kernels.cuh"
 
 namespace lsqr {
@@ -411,6 +413,43 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double *part, int
 void launch_sum_partials(hipStream_t st, const double *part, int np, double *out)
 {
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, st, part, np, out);
+}
+
+}  // namespace lsqr
+
+namespace lsqr {
+
+template <class T>
+__global__ void k_gather_runs(int64_t nr, const uint32_t *src, const uint32_t *dst,
+                              const uint16_t *desc, const T *in, T *out)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nr;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int len = desc[r] & 255;
+        const int64_t s = src[r], d = dst[r];
+        for (int e = 0; e < len; ++e) out[d + e] = in[s + e];
+    }
+}
+
+void launch_gather_runs(hipStream_t st, int64_t nr, const uint32_t *src, const uint32_t *dst,
+                        const uint16_t *desc, const void *in, void *out, int elem_bytes)
+{
+    if (nr <= 0) return;
+    const int grid = (int)std::min<int64_t>((nr + 255) / 256, 65536);
+    switch (elem_bytes) {
+    case 8:
+        hipLaunchKernelGGL(k_gather_runs<uint64_t>, dim3(grid), dim3(256), 0, st, nr, src, dst,
+                           desc, (const uint64_t *)in, (uint64_t *)out);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_gather_runs<uint32_t>, dim3(grid), dim3(256), 0, st, nr, src, dst,
+                           desc, (const uint32_t *)in, (uint32_t *)out);
+        break;
+    default:
+        hipLaunchKernelGGL(k_gather_runs<uint16_t>, dim3(grid), dim3(256), 0, st, nr, src, dst,
+                           desc, (const uint16_t *)in, (uint16_t *)out);
+        break;
+    }
 }
 
 }  // namespace lsqr

@@ -361,7 +361,57 @@ struct AdjArgs {
     int mode;
     int data_only;           // 1: G^T part only (no smoothing/damping, no scale)
     int xcd_bands;           // 1: each XCD's workgroups take a contiguous band of columns
+    // node runs (k_adj_nruns): see ColFmt
+    const int64_t *nrp;
+    const int64_t *nvq;
+    const uint32_t *nrow;
+    const uint16_t *ndesc;
+    const int32_t *norder;
 };
+
+// beta_{k+1} from the forward partials (FP64, fixed order); false when the
+// workgroup has nothing to do (stopped, past the last iteration, breakdown).
+__device__ __forceinline__ bool adj_prologue(const AdjArgs &a, double &beta, double *lds)
+{
+    beta = 1.0;
+    if (a.mode == MODE_OPERATOR) return true;
+    if (a.ctl[C_STOP]) return false;
+    int k = 0;
+    if (a.mode == MODE_ITER) {
+        k = a.ctl[C_CNT0 + a.parity];
+        if (k > a.ctl[C_KMAX]) return false;
+    }
+    beta = sqrt(reduce_partials(a.part_t, a.np_t, lds));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.S[(int64_t)k * kStateWords + S_BETA] = beta;
+        if (a.mode == MODE_INIT && beta == 0.0) { a.ctl[C_ISTOP] = 0; a.ctl[C_STOP] = 1; }
+    }
+    return beta != 0.0;      // breakdown: the update kernel sets alpha = 0
+}
+
+// Column j of q from g = (G^T t)_j: adds the smoothing and damping blocks,
+// applies the scale and the -beta v term, stores q_j and returns q_j^2.
+template <class V>
+__device__ __forceinline__ double adj_col_out(const AdjArgs &a, int j,
+                                              typename AccOf<V>::type g, double beta)
+{
+#pragma clang fp contract(off)
+    using A = typename AccOf<V>::type;
+    const V *T = (const V *)a.T;
+    const V *vv = (const V *)a.v;
+    double qj;
+    if (a.data_only) {
+        qj = (double)g;
+    } else {
+        const A lap = stencil<V>(T + a.m, j, a.nx, a.ny, a.nz);
+        const A sj = g + (A)a.w * lap + (A)a.damp * (A)T[a.m + a.n + j];
+        const double xj = a.d[j] * (double)sj;
+        qj = vv ? xj / beta - beta * (double)vv[j] : xj / beta;
+    }
+    const V qv = (V)qj;
+    ((V *)a.q)[j] = qv;
+    return (double)qv * (double)qv;
+}
 
 template <class M, class V, int LPC>
 __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
@@ -369,30 +419,13 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
 #pragma clang fp contract(off)
     using A = typename AccOf<V>::type;
     __shared__ double lds[4];
-    double beta = 1.0;
-    if (a.mode != MODE_OPERATOR) {
-        if (a.ctl[C_STOP]) return;
-        int k = 0;
-        if (a.mode == MODE_ITER) {
-            k = a.ctl[C_CNT0 + a.parity];
-            if (k > a.ctl[C_KMAX]) return;
-        }
-        beta = sqrt(reduce_partials(a.part_t, a.np_t, lds));
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.S[(int64_t)k * kStateWords + S_BETA] = beta;
-            if (a.mode == MODE_INIT && beta == 0.0) { a.ctl[C_ISTOP] = 0; a.ctl[C_STOP] = 1; }
-        }
-        if (beta == 0.0) return;   // breakdown: the update kernel sets alpha = 0
-    }
+    double beta;
+    if (!adj_prologue(a, beta, lds)) return;
     const M *cv = (const M *)a.cv;
-    const V *T = (const V *)a.T;
     const V *Tg = (const V *)a.Tg;
-    const V *vv = (const V *)a.v;
-    V *q = (V *)a.q;
     double sq = 0.0;
     constexpr int CPB = kBlock / LPC;
     const int lane = threadIdx.x % LPC;
-    const int64_t tL = a.m, tD = a.m + a.n;
     // Columns visited by this workgroup.  With XCD bands, workgroup b (which the
     // dispatcher places on XCD b % 8) walks a contiguous eighth of the columns,
     // so each XCD's L2 serves the gathers of one lateral band of the model.
@@ -423,20 +456,99 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
         for (; p < e; p += LPC)
             a0 = fma(ld_nt<A>(cv + p), (A)Tg[__builtin_nontemporal_load(a.ri + p)], a0);
         const A g = group_sum<LPC>((a0 + a1) + (a2 + a3));
-        if (lane == 0) {
-            double qj;
-            if (a.data_only) {
-                qj = (double)g;
-            } else {
-                const A lap = stencil<V>(T + tL, j, a.nx, a.ny, a.nz);
-                const A sj = g + (A)a.w * lap + (A)a.damp * (A)T[tD + j];
-                const double xj = a.d[j] * (double)sj;
-                qj = vv ? xj / beta - beta * (double)vv[j] : xj / beta;
+        if (lane == 0) sq += adj_col_out<V>(a, j, g, beta);
+    }
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+}
+
+// Transposed product over node runs.  The data block is stored per lateral
+// node (the nz consecutive columns of one (ix, iy), eq. 7) as runs: for each
+// data row reaching the node, in ascending row order, its stretch of
+// consecutive depths [iz0, iz0 + len) and their values.  Row indices and the
+// gathers of t are paid once per run instead of once per entry.
+//
+// One workgroup per node; nodes are visited in decreasing order of run count,
+// dealt to workgroups boustrophedon-wise so every workgroup gets a similar
+// load.  The 4 waves of a workgroup take fixed contiguous quarters of the
+// node's runs (value offsets of the quarters are stored).  Inside a wave the
+// lanes form 64/nz groups of nz lanes, lane iz of a group owning depth iz;
+// group g takes runs g, g + 64/nz, ... of each 64-run chunk, so the values of
+// a run are read by consecutive lanes.  Per column, the sum runs over the
+// groups in order, then over the waves in order: fixed, no atomics.
+template <class M, class V>
+__global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
+{
+#pragma clang fp contract(off)
+    using A = typename AccOf<V>::type;
+    __shared__ double lds[4];
+    __shared__ A wsum[kBlock / 64][64];
+    double beta;
+    if (!adj_prologue(a, beta, lds)) return;
+    const M *nv = (const M *)a.cv;
+    const V *Tg = (const V *)a.Tg;
+    const int nz = a.nz, ngr = 64 / nz;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int grp = lane / nz, iz = lane - grp * nz;
+    const bool live = grp < ngr;
+    const int nnodes = a.n / nz;
+    const int G = gridDim.x;
+    double sq = 0.0;
+    for (int s = 0; s * G < nnodes; ++s) {
+        const int idx = s * G + ((s & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        if (idx >= nnodes) continue;         // uniform over the workgroup
+        const int node = a.norder[idx];
+        const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
+        const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
+        int64_t vb = a.nvq[4 * (int64_t)node + wid];
+        A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        for (int64_t base = rs; base < re; base += 64) {
+            const int nr = (int)(re - base < 64 ? re - base : 64);
+            uint32_t dsc = 0u;
+            A tr = 0;
+            if (lane < nr) {
+                dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
+                tr = (A)Tg[__builtin_nontemporal_load(a.nrow + base + lane)];
             }
-            const V qv = (V)qj;
-            q[j] = qv;
-            sq += (double)qv * (double)qv;
+            const int len = (int)(dsc & 255u);
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            // (value offset in the chunk << 16) | (iz0 << 8) | len; offsets < 64 * 64
+            const uint32_t pk = ((uint32_t)(incl - len) << 16) | dsc;
+            const int tot = __shfl(incl, 63);
+            for (int s0 = 0; s0 < nr; s0 += 4 * ngr) {
+                const int r0 = s0 + grp, r1 = r0 + ngr, r2 = r1 + ngr, r3 = r2 + ngr;
+                const uint32_t p0 = __shfl(pk, r0 & 63), p1 = __shfl(pk, r1 & 63);
+                const uint32_t p2 = __shfl(pk, r2 & 63), p3 = __shfl(pk, r3 & 63);
+                const A t0 = __shfl(tr, r0 & 63), t1 = __shfl(tr, r1 & 63);
+                const A t2 = __shfl(tr, r2 & 63), t3 = __shfl(tr, r3 & 63);
+                const int e0 = iz - (int)((p0 >> 8) & 255u), e1 = iz - (int)((p1 >> 8) & 255u);
+                const int e2 = iz - (int)((p2 >> 8) & 255u), e3 = iz - (int)((p3 >> 8) & 255u);
+                if (live && r0 < nr && (unsigned)e0 < (p0 & 255u))
+                    a0 = fma(ld_nt<A>(nv + vb + (p0 >> 16) + e0), t0, a0);
+                if (live && r1 < nr && (unsigned)e1 < (p1 & 255u))
+                    a1 = fma(ld_nt<A>(nv + vb + (p1 >> 16) + e1), t1, a1);
+                if (live && r2 < nr && (unsigned)e2 < (p2 & 255u))
+                    a2 = fma(ld_nt<A>(nv + vb + (p2 >> 16) + e2), t2, a2);
+                if (live && r3 < nr && (unsigned)e3 < (p3 & 255u))
+                    a3 = fma(ld_nt<A>(nv + vb + (p3 >> 16) + e3), t3, a3);
+            }
+            vb += tot;
         }
+        const A acc = (a0 + a1) + (a2 + a3);
+        A col = 0;
+        for (int g = 0; g < ngr; ++g) col += __shfl(acc, (g * nz + iz) & 63);
+        if (lane < nz) wsum[wid][lane] = col;
+        __syncthreads();
+        if (wid == 0 && lane < nz) {
+            const A g = ((wsum[0][lane] + wsum[1][lane]) + wsum[2][lane]) + wsum[3][lane];
+            sq += adj_col_out<V>(a, node * nz + lane, g, beta);
+        }
+        __syncthreads();
     }
     const double tot = block_sum(sq, lds);
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
@@ -573,6 +685,10 @@ static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArg
 template <class M, class V>
 static void adj_launch_m(hipStream_t st, int grid, const ColFmt &C, const AdjArgs &a)
 {
+    if (C.nrp) {
+        hipLaunchKernelGGL((k_adj_nruns<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
+        return;
+    }
     switch (C.lpc) {
     case 4: hipLaunchKernelGGL((k_adj<M, V, 4>), dim3(grid), dim3(kBlock), 0, st, a); break;
     case 8: hipLaunchKernelGGL((k_adj<M, V, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
@@ -618,7 +734,8 @@ hipError_t adj_launch(hipStream_t st, const Problem &P, int grid, const ColFmt &
                       int parity, int mode, int data_only)
 {
     AdjArgs a{C.cp, C.ri, C.val, P.m, (int)P.n, P.nx, P.ny, P.nz, P.w, P.damp, d, T, Tg, v, q,
-              part_out, part_t, np_t, S, ctl, parity, mode, data_only, C.xcd_bands};
+              part_out, part_t, np_t, S, ctl, parity, mode, data_only, C.xcd_bands,
+              C.nrp, C.nvq, C.nrow, C.ndesc, C.norder};
     switch (C.vt) {
     case VT_F64:
         if constexpr (Wide<V>::value) adj_launch_m<double, V>(st, grid, C, a);

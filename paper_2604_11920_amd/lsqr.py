@@ -47,7 +47,8 @@ class Opts(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("alloc", _ALLOC_FN), ("dealloc", _FREE_FN), ("alloc_user", ctypes.c_void_p),
                 ("flags", ctypes.c_uint32), ("lanes_per_row", ctypes.c_int),
-                ("lanes_per_col", ctypes.c_int), ("row_format", ctypes.c_int)]
+                ("lanes_per_col", ctypes.c_int), ("row_format", ctypes.c_int),
+                ("col_format", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -141,7 +142,7 @@ class Solver:
     def __init__(self, row_ptr, col, val, nx, ny, nz, damp, smooth, precision="fp64",
                  precond="none", col_scale=None, stream=None, timing=False, graph=True,
                  lanes_per_row=0, lanes_per_col=0, check_every=0, refine_sweeps=5,
-                 row_format="auto", xcd_bands=False, torch_alloc=True):
+                 row_format="auto", col_format="auto", xcd_bands=False, torch_alloc=True):
         import torch
         lib = load()
         self._torch = torch
@@ -176,6 +177,7 @@ class Solver:
         opts.lanes_per_row = int(lanes_per_row)
         opts.lanes_per_col = int(lanes_per_col)
         opts.row_format = {"auto": 0, "csr": 1, "runs": 2}[row_format]
+        opts.col_format = {"auto": 0, "csc": 1, "runs": 2}[col_format]
         self.precision = precision
         if torch_alloc:
             self._blocks = {}

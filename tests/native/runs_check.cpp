@@ -1,0 +1,52 @@
+// CPU driver for the host run builders: reads a CSR structure from a binary
+// file, runs both builders and writes their arrays back for checking.
+//   in : int64 m, n, nz, nnz; int64 row_ptr[m+1]; int32 col[nnz]
+//   out: int64 ok_rows, nruns; int64 run_ptr[m+1]; uint32 runs[]; uint16 roff[];
+//        int64 ok_nodes, nnruns, nnodes; int64 nrp[nnodes+1]; int64 nvq[4 nnodes+1];
+//        uint32 row[]; uint32 src[]; uint32 dst[]; uint16 desc[]; int32 order[nnodes]
+#include <stdio.h>
+#include <stdlib.h>
+
+#include "runs_host.h"
+
+template <class T>
+static void put(FILE *f, const T *p, size_t n) { if (n) fwrite(p, sizeof(T), n, f); }
+
+int main(int argc, char **argv)
+{
+    if (argc != 3) { fprintf(stderr, "usage: runs_check IN OUT\n"); return 2; }
+    FILE *fi = fopen(argv[1], "rb");
+    if (!fi) return 2;
+    int64_t hdr[4];
+    if (fread(hdr, 8, 4, fi) != 4) return 2;
+    const int64_t m = hdr[0], n = hdr[1], nz = hdr[2], nnz = hdr[3];
+    std::vector<int64_t> rp((size_t)m + 1);
+    std::vector<int32_t> ci((size_t)nnz);
+    if (fread(rp.data(), 8, (size_t)m + 1, fi) != (size_t)m + 1) return 2;
+    if (nnz && fread(ci.data(), 4, (size_t)nnz, fi) != (size_t)nnz) return 2;
+    fclose(fi);
+    FILE *fo = fopen(argv[2], "wb");
+    if (!fo) return 2;
+    std::vector<int64_t> run_ptr;
+    std::vector<uint32_t> runs;
+    std::vector<uint16_t> roff;
+    const int64_t ok1 = lsqr::build_runs_host(m, n, rp.data(), ci.data(), run_ptr, runs, roff);
+    const int64_t nr1 = ok1 ? (int64_t)runs.size() : 0;
+    put(fo, &ok1, 1);
+    put(fo, &nr1, 1);
+    if (ok1) { put(fo, run_ptr.data(), run_ptr.size()); put(fo, runs.data(), runs.size()); put(fo, roff.data(), roff.size()); }
+    lsqr::NodeRuns R;
+    const int64_t ok2 = lsqr::build_node_runs_host(m, n, (int)nz, rp.data(), ci.data(), R);
+    const int64_t nr2 = ok2 ? (int64_t)R.row.size() : 0, nn = ok2 ? n / nz : 0;
+    put(fo, &ok2, 1);
+    put(fo, &nr2, 1);
+    put(fo, &nn, 1);
+    if (ok2) {
+        put(fo, R.nrp.data(), R.nrp.size()); put(fo, R.nvq.data(), R.nvq.size());
+        put(fo, R.row.data(), R.row.size()); put(fo, R.src.data(), R.src.size());
+        put(fo, R.dst.data(), R.dst.size()); put(fo, R.desc.data(), R.desc.size());
+        put(fo, R.order.data(), R.order.size());
+    }
+    fclose(fo);
+    return 0;
+}

@@ -90,23 +90,26 @@ def test_transpose_matches_library_csc(which, cfg0):
     assert np.array_equal(cv, ref.data)
 
 
-@pytest.mark.parametrize("lanes,row_format", [(0, "auto"), (4, "csr"), (16, "csr"), (64, "csr"),
-                                               (0, "runs")])
-def test_operator_integer_bitwise(lanes, row_format):
+@pytest.mark.parametrize("lanes,row_format,col_format",
+                         [(0, "auto", "auto"), (4, "csr", "csc"), (16, "csr", "csc"),
+                          (64, "csr", "csc"), (0, "runs", "runs")])
+def test_operator_integer_bitwise(lanes, row_format, col_format):
     s = ragged_system(2, integer=True)
     op = oracle.Operator.from_system(s)
     rng = np.random.default_rng(3)
     x = rng.integers(-8, 9, size=s.n).astype(np.float64)
     ybar = rng.integers(-8, 9, size=op.mbar).astype(np.float64)
-    with from_sys(s, lanes_per_row=lanes, lanes_per_col=lanes, row_format=row_format) as sol:
+    with from_sys(s, lanes_per_row=lanes, lanes_per_col=lanes, row_format=row_format,
+                  col_format=col_format) as sol:
         yg = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
         xg = sol.apply_t(torch.from_numpy(ybar).cuda()).cpu().numpy()
     assert np.array_equal(yg, op.apply(x))
     assert np.array_equal(xg, op.apply_t(ybar))
 
 
-@pytest.mark.parametrize("row_format", ["csr", "runs"])
-def test_operator_integer_bitwise_tomography_pattern(cfg0, row_format):
+@pytest.mark.parametrize("row_format,col_format", [("csr", "csc"), ("runs", "csc"),
+                                                    ("runs", "runs")])
+def test_operator_integer_bitwise_tomography_pattern(cfg0, row_format, col_format):
     # the tomography sparsity (runs of depth columns, merged across nodes) with
     # integer values: every sum is exact, so both row formats match bitwise
     s = synth.RandomSystem(m=cfg0.m, n=cfg0.n, nx=cfg0.nx, ny=cfg0.ny, nz=cfg0.nz,
@@ -116,7 +119,7 @@ def test_operator_integer_bitwise_tomography_pattern(cfg0, row_format):
     rng = np.random.default_rng(5)
     x = rng.integers(-8, 9, size=s.n).astype(np.float64)
     ybar = rng.integers(-8, 9, size=op.mbar).astype(np.float64)
-    with from_sys(s, row_format=row_format) as sol:
+    with from_sys(s, row_format=row_format, col_format=col_format) as sol:
         yg = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
         xg = sol.apply_t(torch.from_numpy(ybar).cuda()).cpu().numpy()
     assert np.array_equal(yg, op.apply(x))
@@ -166,12 +169,13 @@ def test_operator_random_within_rounding(cfg0, precond):
 
 
 # --------------------------------------------------------------- solves -----
-@pytest.mark.parametrize("precond", ["none", "jacobi"])
-def test_early_iterates_strict(cfg0, precond):
+@pytest.mark.parametrize("precond,col_format", [("none", "auto"), ("jacobi", "auto"),
+                                                ("jacobi", "runs")])
+def test_early_iterates_strict(cfg0, precond, col_format):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
     op = oracle.Operator.from_system(s, d=d)
-    with from_sys(s, precond=precond) as sol:
+    with from_sys(s, precond=precond, col_format=col_format) as sol:
         for K in (1, 2, 3, 5, 8):
             ref = op.lsqr(s.dt, K)
             dm, hist, info = sol.solve(s.dt, K)
@@ -180,12 +184,13 @@ def test_early_iterates_strict(cfg0, precond):
             assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0), K
 
 
-@pytest.mark.parametrize("precond", ["none", "jacobi"])
-def test_converged_strict(cfg0, cfg0_xstar, precond):
+@pytest.mark.parametrize("precond,col_format", [("none", "auto"), ("jacobi", "auto"),
+                                                ("none", "runs")])
+def test_converged_strict(cfg0, cfg0_xstar, precond, col_format):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
     ref = oracle.Operator.from_system(s, d=d).lsqr(s.dt, 40000, tol=1e-13)
-    with from_sys(s, precond=precond) as sol:
+    with from_sys(s, precond=precond, col_format=col_format) as sol:
         dm, hist, info = sol.solve(s.dt, 40000, tol=1e-13)
     assert info["istop"] == 1 and ref["istop"] == 1
     assert info["eta"] <= 1e-13
@@ -224,20 +229,22 @@ def test_tolerance_stop(cfg0):
     assert eta <= 2 * tol
 
 
-def test_ragged_system_strict():
+@pytest.mark.parametrize("col_format", ["auto", "runs"])
+def test_ragged_system_strict(col_format):
     s = ragged_system(5)
     for K in (1, 4, 8):
         ref = oracle.lsqr(s, K)
-        with from_sys(s) as sol:
+        with from_sys(s, col_format=col_format) as sol:
             dm, hist, info = sol.solve(s.dt, K)
         assert rel(dm, ref["x"]) <= 1e-10, K
 
 
-def test_small_shapes():
+@pytest.mark.parametrize("col_format", ["auto", "runs"])
+def test_small_shapes(col_format):
     for grid in [(1, 1, 1), (1, 1, 3), (2, 1, 1), (3, 2, 1)]:
         s = synth.random_system(25, *grid, row_len=(0, 4), seed=sum(grid))
         ref = oracle.lsqr(s, 3)
-        with from_sys(s) as sol:
+        with from_sys(s, col_format=col_format) as sol:
             dm, hist, info = sol.solve(s.dt, 3)
         assert rel(dm, ref["x"]) <= 1e-10 or info["istop"] in (1, 3), grid
 

@@ -70,13 +70,15 @@ def test_quantised_codes_bitwise(cfg0, fmt, which):
     assert np.array_equal(qc, q_ref[order.data.astype(np.int64) - 1])
 
 
-@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("precond", ["none", "jacobi"])
-def test_refinement_reaches_fp64_solution(cfg0, xstar, fmt, precond):
-    with from_sys(cfg0, precision=fmt, precond=precond, refine_sweeps=10) as sol:
+@pytest.mark.parametrize("fmt,precond,col_format", [
+    ("bf16", "none", "auto"), ("bf16", "jacobi", "auto"), ("fp16", "none", "auto"),
+    ("fp16", "jacobi", "auto"), ("bf16", "jacobi", "runs"), ("fp16", "jacobi", "runs")])
+def test_refinement_reaches_fp64_solution(cfg0, xstar, fmt, precond, col_format):
+    with from_sys(cfg0, precision=fmt, precond=precond, refine_sweeps=10,
+                  col_format=col_format) as sol:
         dm, hist, info = sol.solve(cfg0.dt, 3000, tol=1e-7)
     err = rel(dm, xstar)
-    print(f"[{fmt}/{precond}] sweeps={info['sweeps']} inner iters={info['iters']} "
+    print(f"[{fmt}/{precond}/{col_format}] sweeps={info['sweeps']} inner iters={info['iters']} "
           f"eta={info['eta']:.2e} err_vs_x*={err:.2e}")
     assert info["istop"] == 1 and info["eta"] <= 1e-7 and info["sweeps"] <= 5
     assert err <= 1e-5
@@ -104,13 +106,14 @@ def test_mixed_form_rejections(cfg0):
             sol.solve(cfg0.dt, 100, tol=0.0)
 
 
-@pytest.mark.parametrize("row_format", ["csr", "runs"])
-def test_fp32_iterates(cfg0, row_format):
+@pytest.mark.parametrize("row_format,col_format", [("csr", "csc"), ("runs", "csc"),
+                                                    ("runs", "runs")])
+def test_fp32_iterates(cfg0, row_format, col_format):
     ref = oracle.lsqr(cfg0, 5)
-    with from_sys(cfg0, precision="fp32", row_format=row_format) as sol:
+    with from_sys(cfg0, precision="fp32", row_format=row_format, col_format=col_format) as sol:
         dm, hist, info = sol.solve(cfg0.dt, 5)
     err = rel(dm, ref["x"])
-    print(f"[fp32/{row_format}] K=5 rel err {err:.2e}")
+    print(f"[fp32/{row_format}/{col_format}] K=5 rel err {err:.2e}")
     assert info["iters"] == 5 and err <= 1e-4
     assert np.allclose(hist[:, 0], ref["hist"][:, 0], rtol=1e-5)
 

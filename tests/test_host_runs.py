@@ -1,0 +1,216 @@
+"""CPU checks of the host builders of the run formats (no GPU).
+
+The forward product's depth runs and the transposed product's node runs are
+built on the host from the CSR structure (csrc/runs_host.h); the kernels index
+memory with them, so they are checked here exhaustively against the CSR they
+describe: every stored entry covered exactly once, runs maximal, node runs in
+ascending row order, value offsets and quarter offsets consistent, the node
+order a stable sort by decreasing run count.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "tests", "native", "runs_check.cpp")
+INC = os.path.join(ROOT, "paper_2604_11920_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no g++")
+    exe = str(tmp_path_factory.mktemp("runs") / "runs_check")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-pthread", "-I", INC, SRC, "-o", exe], check=True)
+    return exe
+
+
+def run_builders(exe, tmp, row_ptr, col, n, nz):
+    row_ptr = np.asarray(row_ptr, np.int64)
+    col = np.asarray(col, np.int32)
+    m, nnz = len(row_ptr) - 1, len(col)
+    fin, fout = str(tmp / "in.bin"), str(tmp / "out.bin")
+    with open(fin, "wb") as f:
+        np.array([m, n, nz, nnz], np.int64).tofile(f)
+        row_ptr.tofile(f)
+        col.tofile(f)
+    subprocess.run([exe, fin, fout], check=True)
+    buf = open(fout, "rb").read()
+    pos = 0
+
+    def take(dt, k):
+        nonlocal pos
+        a = np.frombuffer(buf, dtype=dt, count=k, offset=pos)
+        pos += a.nbytes
+        return a
+
+    out = {}
+    ok1, nr1 = take(np.int64, 2)
+    out["rows_ok"] = bool(ok1)
+    if ok1:
+        out["run_ptr"] = take(np.int64, m + 1)
+        out["runs"] = take(np.uint32, nr1)
+        out["roff"] = take(np.uint16, nr1)
+    ok2, nr2, nn = take(np.int64, 3)
+    out["nodes_ok"] = bool(ok2)
+    if ok2:
+        out["nrp"] = take(np.int64, nn + 1)
+        out["nvq"] = take(np.int64, 4 * nn + 1)
+        out["row"] = take(np.uint32, nr2)
+        out["src"] = take(np.uint32, nr2)
+        out["dst"] = take(np.uint32, nr2)
+        out["desc"] = take(np.uint16, nr2)
+        out["order"] = take(np.int32, nn)
+    assert pos == len(buf)
+    return out
+
+
+def check_row_runs(o, row_ptr, col):
+    rp, runs, roff, run_ptr = row_ptr, o["runs"], o["roff"], o["run_ptr"]
+    m = len(rp) - 1
+    assert run_ptr[0] == 0 and np.all(np.diff(run_ptr) >= 0) and run_ptr[-1] == len(runs)
+    for i in range(m):
+        cols = col[rp[i]:rp[i + 1]]
+        pos = 0
+        prev_end, prev_len = None, None
+        for r in range(run_ptr[i], run_ptr[i + 1]):
+            c0, ln = int(runs[r] >> 8), int(runs[r] & 255)
+            assert ln >= 1 and roff[r] == pos
+            assert np.array_equal(cols[pos:pos + ln], np.arange(c0, c0 + ln))
+            if prev_end is not None:      # maximal unless split at 255 entries
+                assert c0 != prev_end or prev_len == 255
+            prev_end, prev_len = c0 + ln, ln
+            pos += ln
+        assert pos == len(cols)
+
+
+def check_node_runs(o, row_ptr, col, n, nz):
+    nrp, nvq, row, src, dst, desc, order = (o[k] for k in
+                                            ("nrp", "nvq", "row", "src", "dst", "desc", "order"))
+    nn = n // nz
+    nnz = len(col)
+    assert nrp[0] == 0 and np.all(np.diff(nrp) >= 0) and nrp[-1] == len(row)
+    iz0 = (desc >> 8).astype(np.int64)
+    ln = (desc & 255).astype(np.int64)
+    assert np.all(ln >= 1) and np.all(iz0 + ln <= nz)
+    # values: node-major, consecutive
+    assert np.array_equal(dst.astype(np.int64), np.concatenate([[0], np.cumsum(ln)[:-1]]))
+    covered = np.zeros(nnz, np.int64)
+    for k in range(nn):
+        r0, r1 = nrp[k], nrp[k + 1]
+        key_prev = None
+        for r in range(r0, r1):
+            i, s, a, L = int(row[r]), int(src[r]), int(iz0[r]), int(ln[r])
+            assert row_ptr[i] <= s and s + L <= row_ptr[i + 1]
+            assert np.array_equal(col[s:s + L], k * nz + a + np.arange(L))
+            # maximal within the node: the entries before/after are not adjacent
+            if s > row_ptr[i] and a > 0:
+                assert col[s - 1] != k * nz + a - 1
+            if s + L < row_ptr[i + 1] and a + L < nz:
+                assert col[s + L] != k * nz + a + L
+            covered[s:s + L] += 1
+            key = (i, a)
+            if key_prev is not None:
+                assert key > key_prev
+            key_prev = key
+        c = r1 - r0
+        end = dst[r1 - 1] + ln[r1 - 1] if c else (nvq[4 * k] if k else 0)
+        for w in range(4):
+            q = r0 + c * w // 4
+            assert nvq[4 * k + w] == (dst[q] if q < r1 else end)
+    assert nvq[4 * nn] == nnz
+    assert np.all(covered == 1)
+    counts = np.diff(nrp)
+    assert np.array_equal(order, np.argsort(-counts, kind="stable"))
+
+
+def test_small_config(driver, tmp_path):
+    s = synth.make_system(synth.small_config(nx=8, ny=8, nz=6, n_stations=14, seed=2))
+    o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
+    assert o["rows_ok"] and o["nodes_ok"]
+    check_row_runs(o, s.row_ptr, s.col)
+    check_node_runs(o, s.row_ptr, s.col, s.n, s.nz)
+
+
+def test_full_depth_rows_cross_node_boundaries(driver, tmp_path):
+    # every row covers all depths of consecutive lateral nodes: one forward
+    # run spans several nodes, node runs split it at every node boundary
+    nx, ny, nz = 6, 5, 4
+    n = nx * ny * nz
+    rng = np.random.default_rng(3)
+    rows = []
+    for _ in range(40):
+        k0 = int(rng.integers(0, nx * ny - 3))
+        k1 = k0 + int(rng.integers(1, 4))
+        rows.append(np.arange(k0 * nz, k1 * nz))
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])])
+    col = np.concatenate(rows)
+    o = run_builders(driver, tmp_path, rp, col, n, nz)
+    check_row_runs(o, rp, col)
+    check_node_runs(o, rp, col, n, nz)
+    assert len(o["runs"]) == len(rows)            # one forward run per row
+    assert len(o["row"]) == sum(len(r) // nz for r in rows)
+
+
+def test_random_structure_with_gaps_and_empty_rows(driver, tmp_path):
+    nx, ny, nz = 7, 3, 9
+    n = nx * ny * nz
+    rng = np.random.default_rng(5)
+    rows = []
+    for i in range(300):
+        if i % 17 == 0:
+            rows.append(np.zeros(0, np.int64))
+            continue
+        keep = rng.random(n) < rng.uniform(0.02, 0.6)
+        rows.append(np.nonzero(keep)[0])
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])])
+    col = np.concatenate(rows)
+    o = run_builders(driver, tmp_path, rp, col, n, nz)
+    check_row_runs(o, rp, col)
+    check_node_runs(o, rp, col, n, nz)
+
+
+def test_long_rows_split_at_255(driver, tmp_path):
+    n, nz = 1000, 1
+    rp = np.array([0, 700, 700, 1000])
+    col = np.concatenate([np.arange(0, 700), np.arange(100, 400)])
+    o = run_builders(driver, tmp_path, rp, col, n, nz)
+    check_row_runs(o, rp, col)
+    assert [int(x & 255) for x in o["runs"]] == [255, 255, 190, 255, 45]
+    check_node_runs(o, rp, col, n, nz)
+
+
+def test_node_runs_refused_for_deep_grids(driver, tmp_path):
+    n, nz = 130, 65
+    rp = np.array([0, 3])
+    col = np.array([0, 1, 70])
+    o = run_builders(driver, tmp_path, rp, col, n, nz)
+    assert o["rows_ok"] and not o["nodes_ok"]
+
+
+def test_config0(driver, tmp_path):
+    s = synth.make_system(synth.config0())
+    o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
+    check_row_runs(o, s.row_ptr, s.col)
+    # node runs: vectorised subset of the checks (the system is ~1M entries)
+    nrp, row, src, desc, dst = o["nrp"], o["row"], o["src"], o["desc"], o["dst"]
+    ln = (desc & 255).astype(np.int64)
+    iz0 = (desc >> 8).astype(np.int64)
+    node = np.repeat(np.arange(len(nrp) - 1), np.diff(nrp))
+    assert ln.sum() == s.nnz
+    starts = src.astype(np.int64)
+    assert np.array_equal(s.col[starts], node * s.nz + iz0)
+    last = starts + ln - 1
+    assert np.array_equal(s.col[last], node * s.nz + iz0 + ln - 1)
+    assert np.all(s.row_ptr[row] <= starts) and np.all(last < s.row_ptr[row.astype(np.int64) + 1])
+    cov = np.zeros(s.nnz + 1, np.int64)
+    np.add.at(cov, starts, 1)
+    np.add.at(cov, last + 1, -1)
+    assert np.all(np.cumsum(cov)[:-1] == 1)
+    assert np.array_equal(dst.astype(np.int64), np.concatenate([[0], np.cumsum(ln)[:-1]]))
