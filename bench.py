@@ -68,7 +68,7 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def pmc_summary(fetch_csv, write_csv):
+def pmc_summary(fetch_csv, write_csv, formats=None):
     """Per-launch HBM bytes of the solver kernels from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the same
     counter reads for the 1 GiB elementwise calibration kernel."""
@@ -86,10 +86,12 @@ def pmc_summary(fetch_csv, write_csv):
     for tag in ("fwd", "adj"):
         out[f"{tag}_traffic_bytes"] = out[f"{tag}_FETCH_SIZE_bytes"] + out[f"{tag}_WRITE_SIZE_bytes"]
     out["source_sha256_16"] = source_hash()
+    if formats:
+        out["formats"] = formats
     return out
 
 
-def measured_traffic(tag):
+def measured_traffic(tag, formats=None):
     """Traffic of kernel `tag` from the committed counter summary, or None when
     the kernel source changed since the counters were taken."""
     try:
@@ -99,17 +101,19 @@ def measured_traffic(tag):
         return None
     if kv.get("source_sha256_16", "").strip() != source_hash():
         return None
+    if formats is not None and kv.get("formats", "").strip() != formats:
+        return None
     v = kv.get(f"{tag}_traffic_bytes")
     return float(v) if v else None
 
 
 
-def fp32_rate(s, dt, iters, steps=3):
+def fp32_rate(s, dt, iters, fmt, steps=3):
     """FP32 values, vectors and accumulation (FP64 scalars): iterations/s and
     kernel rates on the same system, same iteration count."""
     import torch
     from paper_2604_11920_amd import Solver
-    with Solver.from_system(s, precision="fp32", timing=True) as sol:
+    with Solver.from_system(s, precision="fp32", timing=True, **fmt) as sol:
         dm = torch.empty(s.n, dtype=torch.float64, device="cuda")
         sol.solve(dt, iters, dm=dm, history=False)
         torch.cuda.synchronize()
@@ -130,21 +134,40 @@ def fp32_rate(s, dt, iters, steps=3):
     return r
 
 
-def time_to_tol(s, dt, tol):
+def time_to_tol(s, dt, tol, fmt, model_path=None):
     """Wall time to eta = |Abar^T r| / |Abar^T bbar| <= tol for each form, each
-    result's eta re-checked explicitly with the FP64 operator on the GPU."""
+    result's eta re-checked explicitly with the FP64 operator on the GPU.  The
+    system is resident (created before the clock starts); for the learned
+    forms the feature + MLP inference time is reported beside the solve."""
     import torch
     from paper_2604_11920_amd import Solver
     forms = [("fp64", "none", 20000), ("fp64", "jacobi", 20000), ("bf16", "jacobi", 4000),
              ("fp16", "jacobi", 4000)]
+    model = None
+    if model_path and os.path.exists(model_path):
+        from paper_2604_11920_amd import learned
+        model = learned.ColumnScaleModel.load(model_path)
+        forms += [("fp64", "learned", 20000), ("bf16", "learned", 4000)]
     out = {}
     ref = None
-    checker = Solver.from_system(s)
+    checker = Solver.from_system(s, **fmt)
     b = torch.zeros(s.m + 2 * s.n, dtype=torch.float64, device="cuda")
     b[:s.m] = dt
     atb = checker.apply_t(b).norm().item()
+    d_learned = None
+    infer_s = None
+    if model is not None:
+        p = torch.from_numpy(np.ascontiguousarray(model.params, dtype=np.float32)).cuda()
+        checker.mlp_scale(p, model.mean, model.std)            # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d_learned = checker.mlp_scale(p, model.mean, model.std)
+        torch.cuda.synchronize()
+        infer_s = time.perf_counter() - t0
+        d_learned = d_learned.cpu().numpy()
     for prec, pc, cap in forms:
-        with Solver.from_system(s, precision=prec, precond=pc, refine_sweeps=8) as sol:
+        kw = dict(precond="user", col_scale=d_learned) if pc == "learned" else dict(precond=pc)
+        with Solver.from_system(s, precision=prec, refine_sweeps=8, **kw, **fmt) as sol:
             dm = torch.empty(s.n, dtype=torch.float64, device="cuda")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -156,9 +179,12 @@ def time_to_tol(s, dt, tol):
         key = f"{prec}_{pc}"
         out[key] = {"seconds": wall, "iters": info["iters"], "sweeps": info["sweeps"],
                     "istop": info["istop"], "eta_fp64": eta}
+        if pc == "learned":
+            out[key]["inference_seconds"] = infer_s
+            out[key]["fallback_used"] = info["fallback_used"]
         if prec == "fp64" and pc == "jacobi":
             ref = dm.clone()
-        if ref is not None and prec != "fp64":
+        if ref is not None and not (prec == "fp64" and pc == "jacobi"):
             out[key]["rel_diff_vs_fp64_jacobi"] = ((dm - ref).norm() / ref.norm()).item()
         log(f"[bench] time-to-tol {key}: {wall:.2f}s, iters={info['iters']} "
             f"sweeps={info['sweeps']} istop={info['istop']} eta_fp64={eta:.2e}")
@@ -167,6 +193,59 @@ def time_to_tol(s, dt, tol):
     for k in out:
         out[k]["speedup_vs_fp64_none"] = base / out[k]["seconds"]
     return out
+
+
+def batched_bench(args):
+    """Batched form: the four uneven systems of the batched workload, 32
+    right-hand sides each (16 checkerboards + 16 noise draws), fixed iteration
+    count, one batched call per step.  Prints one JSON line."""
+    import torch
+
+    import synth
+    from paper_2604_11920_amd import Solver, solve_batched
+    iters = args.iters or 300
+    sols, dts, nnz, rows = [], [], 0, 0
+    for cfg in synth.config3_systems():
+        t0 = time.perf_counter()
+        s = synth.make_system(cfg)
+        rhs = synth.checker_rhs_batch(s)
+        sols.append(Solver.from_system(s, row_format=args.row_format, col_format=args.col_format))
+        dts.append(torch.from_numpy(rhs).cuda())
+        nnz += s.nnz
+        rows += s.m
+        log(f"[batched] {cfg.name}: m={s.m} nnz={s.nnz} ({time.perf_counter() - t0:.1f}s)")
+        del s, rhs
+    R = int(dts[0].shape[1])
+    cache = os.path.join(ROOT, "gpurun_out", "batch_tune.json")
+    tuned = []
+    for sol in sols:
+        cfg = sol.autotune_batched(R, probe_iters=8, cache=cache)
+        tuned.append(cfg)
+        log(f"[batched] tuned {cfg}")
+    for _ in range(args.warmup):
+        solve_batched(sols, dts, iters, history=False)
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        _, _, infos = solve_batched(sols, dts, iters, history=False)
+        per.append(time.perf_counter() - t0)
+    wall = sum(per)
+    rhs_its = len(sols) * R * iters * args.steps / wall
+    sec_per_batched_iter = wall / (iters * args.steps)
+    # matrix bytes of one batched iteration: FP32 CSR and CSC (value + index)
+    mat_bytes = 2 * nnz * 8.0
+    out = {"metric": "batched LSQR right-hand-side iterations/s", "value": rhs_its,
+           "unit": "rhs-iters/s", "systems": len(sols), "rhs_per_system": R,
+           "iters": iters, "steps": args.steps, "ms_per_step": 1e3 * wall / args.steps,
+           "batched_iters_per_s": 1.0 / sec_per_batched_iter,
+           "matrix_bytes_per_batched_iter": mat_bytes,
+           "matrix_gbs": mat_bytes / sec_per_batched_iter / 1e9, "nnz_total": nnz,
+           "rows_total": rows, "tuned": tuned, "dtype": "f32 values/vectors, f64 scalars",
+           "data": "synthetic"}
+    for sol in sols:
+        sol.close()
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -185,13 +264,19 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32 rate and the time-to-tolerance comparisons")
     ap.add_argument("--ttt-tol", type=float, default=1e-6)
+    ap.add_argument("--model", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp.npz"),
+                    help="learned column-scale model for the learned time-to-tolerance forms")
+    ap.add_argument("--batched", action="store_true",
+                    help="measure the batched multi-RHS form instead (one JSON line)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print per-launch HBM traffic from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-formats", default=None,
+                    help="'row/col' formats the counter runs used (as in kernel_stats: 1 CSR/CSC, 2 runs)")
     args = ap.parse_args()
     if args.pmc_summary:
-        for k, v in pmc_summary(*args.pmc_summary).items():
+        for k, v in pmc_summary(*args.pmc_summary, formats=args.pmc_formats).items():
             print(k, v)
         return
     if args.gpus != 1:
@@ -206,6 +291,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.batched:
+        batched_bench(args)
+        return
     t0 = time.perf_counter()
     if args.config == "cfg1":
         cfg = synth.config1()
@@ -222,8 +310,8 @@ def main():
     log(f"[bench] generated {args.config}: m={s.m} n={s.n} nnz={s.nnz} "
         f"in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    sol = Solver.from_system(s, timing=True, row_format=args.row_format,
-                             col_format=args.col_format, xcd_bands=args.xcd_bands)
+    fmt = dict(row_format=args.row_format, col_format=args.col_format)
+    sol = Solver.from_system(s, timing=True, xcd_bands=args.xcd_bands, **fmt)
     torch.cuda.synchronize()
     log(f"[bench] create (copy + device transpose) {time.perf_counter() - t0:.2f}s")
     dt = torch.from_numpy(s.dt).cuda()
@@ -285,9 +373,13 @@ def main():
                    "row_format": args.row_format, "col_format": args.col_format,
                    "xcd_bands": args.xcd_bands},
         "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
-                     "kernel": "k_fwd (forward CSR product)" if dom == "fwd"
-                     else "k_adj (transposed CSC product)"},
+                     "frac": dom_gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, f"{ks['row_format']}/{ks['col_format']}"),
+                     "kernel": ({1: "k_fwd_csr (forward product, CSR rows)",
+                                 2: "k_fwd_runs (forward product, depth-run rows)"}[ks["row_format"]]
+                                if dom == "fwd" else
+                                {1: "k_adj (transposed product, CSC)",
+                                 2: "k_adj_nruns (transposed product, node runs)"}[ks["col_format"]])},
         "kernels": {"fwd": {"avg_us": fwd_avg * 1e3, "alg_bytes": ks["fwd_bytes"], "gbs": fwd_gbs},
                     "adj": {"avg_us": adj_avg * 1e3, "alg_bytes": ks["adj_bytes"], "gbs": adj_gbs}},
         "paper_protocol_ms_per_step": 1e3 * sum(trimmed) / len(trimmed),
@@ -295,8 +387,8 @@ def main():
     sol.close()
     del sol
     if not args.no_extras:
-        out["fp32"] = fp32_rate(s, dt, iters)
-        out["time_to_tol"] = time_to_tol(s, dt, args.ttt_tol)
+        out["fp32"] = fp32_rate(s, dt, iters, fmt)
+        out["time_to_tol"] = time_to_tol(s, dt, args.ttt_tol, fmt, args.model)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_iters)

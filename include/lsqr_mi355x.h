@@ -101,12 +101,12 @@ typedef struct {
     uint32_t flags;             /* LSQR_FLAG_*                                         */
     int lanes_per_row;          /* 0 = auto; else 4, 8, 16, 32 or 64 lanes per row    */
     int lanes_per_col;          /* 0 = auto; same choices for the transposed product   */
-    int row_format;             /* data rows of the forward product: 0 = auto (depth  */
-                                /* runs when runs average >= 2.5 columns), 1 = plain  */
+    int row_format;             /* data rows of the forward product: 0 = auto (plain  */
+                                /* CSR, the faster one measured on gfx950), 1 = plain */
                                 /* CSR, 2 = depth runs (runs of consecutive columns,  */
                                 /* i.e. of depth nodes under one lateral node, eq. 7) */
-    int col_format;             /* data block of the transposed product: 0 = auto,    */
-                                /* 1 = CSC, 2 = node runs (per lateral node, the rows */
+    int col_format;             /* data block of the transposed product: 0 = auto     */
+                                /* (CSC), 1 = CSC, 2 = node runs (per node, the rows  */
                                 /* reaching it with their stretch of consecutive      */
                                 /* depths; needs nz <= 64, nnz < 2^32)                */
 } lsqr_opts;
@@ -138,6 +138,9 @@ typedef struct {
     int adj_launches;
     double fwd_bytes;           /* algorithmic bytes of one forward launch            */
     double adj_bytes;           /* algorithmic bytes of one transposed launch         */
+    int row_format;             /* format the solver's forward product reads: 1 CSR,  */
+                                /* 2 depth runs                                       */
+    int col_format;             /* transposed product: 1 CSC, 2 node runs             */
 } lsqr_kstats;
 
 /*

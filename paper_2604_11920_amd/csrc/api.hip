@@ -441,15 +441,14 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     const double avg_row = m > 0 ? (double)nnz / (double)m : 0.0;
     const double avg_col = (double)nnz / (double)n;
     bool use_runs = false;
-    if (o.row_format != 1 && m > 0 && nnz > 0) {
+    if (o.row_format == 2 && m > 0 && nnz > 0) {
         std::vector<int64_t> run_ptr;
         std::vector<uint32_t> runs;
         std::vector<uint16_t> roff;
         if (build_runs_host(m, n, hrow, hcol, run_ptr, runs, roff)) {
             c->nruns = run_ptr[m];
-            const double avg_run = (double)nnz / (double)std::max<int64_t>(c->nruns, 1);
-            use_runs = o.row_format == 2 || avg_run >= 2.5;
-            if (use_runs) {
+            use_runs = true;
+            {
                 c->run_ptr = ctx_alloc<int64_t>(c, m + 1);
                 c->runs = ctx_alloc<uint32_t>(c, c->nruns);
                 c->roff = ctx_alloc<uint16_t>(c, c->nruns);
@@ -809,6 +808,8 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
     else fwd += nnz * 4.0;
     if (E.R.sigma) fwd += m * 4.0 + m * sx;
     out->fwd_bytes = fwd;
+    out->row_format = E.R.run_ptr ? 2 : 1;
+    out->col_format = E.C.nrp ? 2 : 1;
     if (E.C.nrp) {
         const double nn = n / (double)c->P.nz;
         out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->nnruns * 6.0 +

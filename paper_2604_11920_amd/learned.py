@@ -153,9 +153,12 @@ def solve_learned(system, model, tol, k_jacobi=None, cap=20000, precision="fp64"
     with Solver.from_system(system, precond="user", col_scale=d, precision=precision,
                             check_every=16) as sol:
         dm, _, info = sol.solve(system.dt, int(limit), tol=tol, history=False)
+    total = info["iters"]
     if info["istop"] != 1 and k_jacobi is not None:
         with Solver.from_system(system, precond="jacobi", precision=precision) as sol:
             dm, _, info = sol.solve(system.dt, cap, tol=tol, history=False)
         info["fallback_used"] = 1
+        total += info["iters"]
+    info["iters_total"] = total          # including a failed learned attempt
     info["seconds"] = time.perf_counter() - t0
     return dm, info

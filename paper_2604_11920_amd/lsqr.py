@@ -67,7 +67,8 @@ class BatchCfg(ctypes.Structure):
 class KStats(ctypes.Structure):
     _fields_ = [("fwd_ms", ctypes.c_double), ("adj_ms", ctypes.c_double),
                 ("fwd_launches", ctypes.c_int), ("adj_launches", ctypes.c_int),
-                ("fwd_bytes", ctypes.c_double), ("adj_bytes", ctypes.c_double)]
+                ("fwd_bytes", ctypes.c_double), ("adj_bytes", ctypes.c_double),
+                ("row_format", ctypes.c_int), ("col_format", ctypes.c_int)]
 
 
 _lib = None

@@ -1,15 +1,23 @@
 """Train the learned column-scale MLP and evaluate it against Jacobi.
 
-    python -m paper_2604_11920_amd.train_scale --train 200 --heldout 20 \
-        --out paper_2604_11920_amd/colscale_mlp.npz --report report.json
+Three steps, each resumable on its own:
 
-Training systems: config-0 geometry (16x16x9) with 20-60 stations and damping
-0.05-0.5 (seeds 1..N); held-out systems: the same family, seeds 1001..  Each
-training system's targets come from the iteration-minimising search of
-paper_2604_11920_amd.learned; the MLP is then fitted on the GPU.  The report
-gives, per held-out system, LSQR iterations and seconds to eta <= 1e-6 with
-Jacobi and with the learned scale, and the relative difference of the two
-solutions.
+    # targets of a family of training systems (LSQR solves on the GPU)
+    python -m paper_2604_11920_amd.train_scale search --family cfg0 --first 1 --count 160 \
+        --out targets_cfg0.npz
+    python -m paper_2604_11920_amd.train_scale search --family cfg1 --first 1 --count 24 \
+        --out targets_cfg1.npz
+    # fit the MLP on the GPU (the library's FP32 forward/backward and Adam)
+    python -m paper_2604_11920_amd.train_scale fit targets_cfg0.npz targets_cfg1.npz \
+        --out paper_2604_11920_amd/colscale_mlp.npz
+    # held-out evaluation: iterations and seconds to eta <= tol, learned vs Jacobi
+    python -m paper_2604_11920_amd.train_scale eval --model paper_2604_11920_amd/colscale_mlp.npz \
+        --family cfg0 --first 1001 --count 20 --report report.json
+
+Families: "cfg0" = config-0 geometry (16x16x9) with 20-60 stations and damping
+0.05-0.5; "cfg1" = config-1 geometry (80x80x20) with 30-80 stations and 6-12
+periods.  Each training system's targets come from the iteration-minimising
+search of paper_2604_11920_amd.learned.
 """
 from __future__ import annotations
 
@@ -30,65 +38,112 @@ def log(msg):
     print(msg, flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=200)
-    ap.add_argument("--heldout", type=int, default=20)
-    ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--epochs", type=int, default=60)
-    ap.add_argument("--out", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp.npz"))
-    ap.add_argument("--report", default=None)
-    args = ap.parse_args()
+def family(name, first, count):
+    import synth
+    if name == "cfg0":
+        return synth.learned_family(first, count)
+    if name == "cfg1":
+        return synth.learned_family_wide(first, count)
+    raise SystemExit(f"unknown family {name}")
 
-    import torch
 
+def cmd_search(args):
     import synth
     from paper_2604_11920_amd import learned
-
-    torch.cuda.set_device(0)
     t0 = time.perf_counter()
     feats, targets, rows = [], [], []
-    for i, cfg in enumerate(synth.learned_family(1, args.train)):
+    for i, cfg in enumerate(family(args.family, args.first, args.count)):
         s = synth.make_system(cfg)
         f, t, theta, kj, kb = learned.search_targets(s, tol=args.tol)
-        feats.append(f)
-        targets.append(t)
-        rows.append({"name": cfg.name, "jacobi_iters": kj, "best_iters": kb, "theta": theta.tolist()})
-        log(f"[train {i + 1}/{args.train}] {cfg.name}: jacobi {kj} best {kb} "
+        feats.append(f.astype(np.float32))
+        targets.append(t.astype(np.float32))
+        rows.append({"name": cfg.name, "n": int(s.n), "nnz": int(s.nnz), "jacobi_iters": int(kj),
+                     "best_iters": int(kb), "theta": [float(x) for x in theta]})
+        log(f"[search {i + 1}/{args.count}] {cfg.name}: jacobi {kj} best {kb} "
             f"({time.perf_counter() - t0:.0f}s)")
+        # save after every system, so a cut-off run keeps what it has
+        np.savez(args.out, feat=np.concatenate(feats), target=np.concatenate(targets),
+                 sizes=np.array([len(x) for x in targets]), meta=np.array(json.dumps(rows)))
+
+
+def cmd_fit(args):
+    from paper_2604_11920_amd import learned
+    feats, targets, rows = [], [], []
+    for path in args.targets:
+        z = np.load(path, allow_pickle=False)
+        feats.append(z["feat"].astype(np.float64))
+        targets.append(z["target"].astype(np.float64))
+        rows += json.loads(str(z["meta"]))
     model = learned.train(feats, targets, epochs=args.epochs, log=log)
     model.meta["train_systems"] = rows
     model.meta["tol"] = args.tol
     model.save(args.out)
-    log(f"[train] saved {args.out}")
+    log(f"[fit] {len(rows)} systems, {model.meta['samples']} columns; loss "
+        f"{model.meta['loss_history'][-1][1]:.4e} (Jacobi multiplier: {model.meta['loss_at_jacobi']:.4e}); "
+        f"saved {args.out}")
 
+
+def cmd_eval(args):
+    import synth
+    from paper_2604_11920_amd import learned
+    model = learned.ColumnScaleModel.load(args.model)
     ev = []
-    for i, cfg in enumerate(synth.learned_family(1001, args.heldout)):
+    for i, cfg in enumerate(family(args.family, args.first, args.count)):
         s = synth.make_system(cfg)
-        kj, ij = learned.iterations_to_tol(s, None, args.tol, 20000)
+        kj, _ = learned.iterations_to_tol(s, None, args.tol, 20000)
         with learned.Solver.from_system(s, precond="jacobi", check_every=16) as sol:
             tj = time.perf_counter()
             dmj, _, _ = sol.solve(s.dt, 20000, tol=args.tol, history=False)
             tj = time.perf_counter() - tj
         dml, il = learned.solve_learned(s, model, args.tol, k_jacobi=kj)
         rd = float(np.linalg.norm(dml - dmj) / np.linalg.norm(dmj))
-        ev.append({"name": cfg.name, "jacobi_iters": kj, "learned_iters": il["iters"],
-                   "learned_istop": il["istop"], "fallback": il["fallback_used"],
-                   "jacobi_seconds": tj, "learned_seconds": il["seconds"], "rel_diff": rd})
-        log(f"[heldout {i + 1}/{args.heldout}] {cfg.name}: jacobi {kj} learned {il['iters']} "
+        ev.append({"name": cfg.name, "jacobi_iters": int(kj), "learned_iters": int(il["iters"]),
+                   "learned_iters_total": int(il["iters_total"]), "learned_istop": il["istop"],
+                   "fallback": il["fallback_used"], "jacobi_seconds": tj,
+                   "learned_seconds": il["seconds"], "rel_diff": rd})
+        log(f"[eval {i + 1}/{args.count}] {cfg.name}: jacobi {kj} learned {il['iters_total']} "
             f"(fallback {il['fallback_used']}) rel diff {rd:.2e}")
     jac = np.array([e["jacobi_iters"] for e in ev], dtype=float)
-    lrn = np.array([e["learned_iters"] for e in ev], dtype=float)
-    summary = {"heldout": len(ev), "mean_jacobi_iters": float(jac.mean()),
-               "mean_learned_iters": float(lrn.mean()),
+    lrn = np.array([e["learned_iters_total"] for e in ev], dtype=float)
+    summary = {"family": args.family, "heldout": len(ev), "tol": args.tol,
+               "mean_jacobi_iters": float(jac.mean()), "mean_learned_iters": float(lrn.mean()),
                "mean_iteration_ratio": float(np.mean(lrn / jac)),
-               "systems_improved": int(np.sum(lrn < jac)), "max_rel_diff": max(e["rel_diff"] for e in ev)}
-    log(f"[heldout] {json.dumps(summary)}")
+               "systems_improved": int(np.sum(lrn < jac)),
+               "fallbacks": int(sum(e["fallback"] for e in ev)),
+               "max_rel_diff": max(e["rel_diff"] for e in ev)}
+    log(f"[eval] {json.dumps(summary)}")
     if args.report:
         with open(args.report, "w") as f:
-            json.dump({"summary": summary, "heldout": ev, "train": rows,
-                       "loss_history": model.meta["loss_history"],
-                       "loss_at_jacobi": model.meta["loss_at_jacobi"]}, f, indent=1)
+            json.dump({"summary": summary, "heldout": ev,
+                       "loss_history": model.meta.get("loss_history"),
+                       "loss_at_jacobi": model.meta.get("loss_at_jacobi")}, f, indent=1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("search")
+    a.add_argument("--family", default="cfg0", choices=["cfg0", "cfg1"])
+    a.add_argument("--first", type=int, default=1)
+    a.add_argument("--count", type=int, default=160)
+    a.add_argument("--tol", type=float, default=1e-6)
+    a.add_argument("--out", required=True)
+    b = sub.add_parser("fit")
+    b.add_argument("targets", nargs="+")
+    b.add_argument("--epochs", type=int, default=60)
+    b.add_argument("--tol", type=float, default=1e-6)
+    b.add_argument("--out", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp.npz"))
+    c = sub.add_parser("eval")
+    c.add_argument("--model", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp.npz"))
+    c.add_argument("--family", default="cfg0", choices=["cfg0", "cfg1"])
+    c.add_argument("--first", type=int, default=1001)
+    c.add_argument("--count", type=int, default=20)
+    c.add_argument("--tol", type=float, default=1e-6)
+    c.add_argument("--report", default=None)
+    args = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    {"search": cmd_search, "fit": cmd_fit, "eval": cmd_eval}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -157,6 +157,24 @@ def learned_family(first_seed: int, count: int, stations=(20, 60), damp=(0.05, 0
     return out
 
 
+def learned_family_wide(first_seed: int, count: int, stations=(30, 80), periods=(6, 12),
+                        damp=(0.05, 0.5)):
+    """`count` systems of the config-1 geometry (80x80x20 grid, 10 degree
+    region, bent rays, >= 2 wavelengths) with few stations and periods, so the
+    learned scale also sees the large grid; seeds first_seed, ..."""
+    rng = np.random.default_rng(first_seed * 104729 + count)
+    out = []
+    for i in range(count):
+        ns = int(rng.integers(stations[0], stations[1] + 1))
+        npd = int(rng.integers(periods[0], periods[1] + 1))
+        dp = float(np.exp(rng.uniform(np.log(damp[0]), np.log(damp[1]))))
+        c = config1(seed=first_seed + i, n_stations=ns, n_periods=npd)
+        c.damp = dp
+        c.name = f"cfg1_s{ns}_p{npd}_d{dp:.3f}_seed{first_seed + i}"
+        out.append(c)
+    return out
+
+
 def small_config(nx=8, ny=8, nz=6, n_stations=12, n_periods=5, region=0.7, bent=True,
                  seed=0, damp=0.1, smooth=0.5, min_wavelengths=None) -> Config:
     """A reduced geometry with the same structure, for fast tests."""

@@ -141,9 +141,11 @@ def test_autotune_and_cache(small_systems, tmp_path):
         assert not t["cached"] and t["ms_per_iter"] > 0
         t2 = sol.autotune_batched(nrhs, cache=cache)
         assert t2["cached"] and t2["rhs_tile"] == t["rhs_tile"]
-        dm, _, inf = solve_batched([sol], [dt], 10)
+        dm, _, inf = solve_batched([sol], [dt], 5)
     table = json.load(open(cache))
     assert len(table) == 1
+    # the tuned schedule keeps the FP32 bar of the early-iterate test; past ~8
+    # iterations FP32 iterates drift from the FP64 ones by loss of orthogonality
     ref = oracle.Operator.from_system(s)
     for r in (0, 17, 31):
-        assert rel(dm[0][:, r], ref.lsqr(dt[:, r], 10)["x"]) <= 1e-3
+        assert rel(dm[0][:, r], ref.lsqr(dt[:, r], 5)["x"]) <= 1e-4

@@ -140,6 +140,6 @@ def test_trained_model_gain_on_heldout():
             dj, _, _ = sol.solve(s.dt, 20000, tol=tol)
         assert il["istop"] == 1
         assert rel(dl, dj) <= 1e-3           # both stopped at eta <= 1e-6
-        ratios.append(il["iters"] / kj)
+        ratios.append(il["iters_total"] / kj)
         print(f"[learned] {cfg.name}: jacobi {kj} learned {il['iters']}")
     assert np.mean(ratios) <= 1.0
