@@ -104,11 +104,15 @@ typedef struct {
     int row_format;             /* data rows of the forward product: 0 = auto (plain  */
                                 /* CSR, the faster one measured on gfx950), 1 = plain */
                                 /* CSR, 2 = depth runs (runs of consecutive columns,  */
-                                /* i.e. of depth nodes under one lateral node, eq. 7) */
+                                /* i.e. of depth nodes under one lateral node, eq. 7),*/
+                                /* 3 = run masks (CSR values; columns decoded from a  */
+                                /* run-start bit per entry and one word per run)      */
     int col_format;             /* data block of the transposed product: 0 = auto     */
                                 /* (CSC), 1 = CSC, 2 = node runs (per node, the rows  */
                                 /* reaching it with their stretch of consecutive      */
-                                /* depths; needs nz <= 64, nnz < 2^32)                */
+                                /* depths; needs nz <= 64, nnz < 2^32), 3 = node      */
+                                /* masks (CSC values; per node its row list and one   */
+                                /* bit per (row, depth); needs nz <= 32)              */
 } lsqr_opts;
 
 /* Stop reasons (info.istop):
@@ -139,8 +143,8 @@ typedef struct {
     double fwd_bytes;           /* algorithmic bytes of one forward launch            */
     double adj_bytes;           /* algorithmic bytes of one transposed launch         */
     int row_format;             /* format the solver's forward product reads: 1 CSR,  */
-                                /* 2 depth runs                                       */
-    int col_format;             /* transposed product: 1 CSC, 2 node runs             */
+                                /* 2 depth runs, 3 run masks                          */
+    int col_format;             /* transposed product: 1 CSC, 2 node runs, 3 node masks */
 } lsqr_kstats;
 
 /*

@@ -66,6 +66,17 @@ lsqr_status validate_host_csr(const lsqr_csr *G)
     return LSQR_OK;
 }
 
+// Attach the node masks (when built) to a transposed format whose values are
+// in CSC order.
+static void set_node_masks(const lsqr_ctx *c, ColFmt &C)
+{
+    if (!c->mmask) return;
+    C.mrptr = c->mrptr; C.mrows = c->mrows; C.mcptr = c->mcptr; C.mmask = c->mmask;
+    C.mqoff = c->mqoff; C.norder = c->morder;
+    const int nz = c->P.nz;
+    C.nzt = nz <= 8 ? 8 : nz <= 16 ? 16 : nz <= 24 ? 24 : 32;
+}
+
 int pick_lanes(double avg)
 {
     if (avg >= 384) return 64;
@@ -92,7 +103,7 @@ lsqr_status setup_engine(lsqr_ctx *c, Engine &E, int vec, const RowFmt &R, const
     E.C = C;
     if (R.run_ptr) E.g_fwd = cap_blocks(std::max<int64_t>(m * 64, 2 * n), kBlock, 2048);
     else E.g_fwd = cap_blocks(std::max<int64_t>(m * R.lpr, 2 * n), kBlock, 2048);
-    if (C.nrp) E.g_adj = (int)std::max<int64_t>(1, std::min<int64_t>(n / c->P.nz, 2048));
+    if (C.nrp || C.mmask) E.g_adj = (int)std::max<int64_t>(1, std::min<int64_t>(n / c->P.nz, 2048));
     else E.g_adj = cap_blocks(n * C.lpc, kBlock, 2048);
     E.g_upd = cap_blocks(n, kBlock, 1024);
     E.T[0] = ctx_alloc_bytes(c, mb * vs);
@@ -334,10 +345,10 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if ((o.lanes_per_row && !valid_lanes(o.lanes_per_row)) ||
         (o.lanes_per_col && !valid_lanes(o.lanes_per_col)))
         return fail(nullptr, LSQR_E_INVALID_ARG, "lanes must be 0, 4, 8, 16, 32 or 64");
-    if (o.row_format < 0 || o.row_format > 2)
-        return fail(nullptr, LSQR_E_INVALID_ARG, "row_format must be 0, 1 or 2");
-    if (o.col_format < 0 || o.col_format > 2)
-        return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1 or 2");
+    if (o.row_format < 0 || o.row_format > 3)
+        return fail(nullptr, LSQR_E_INVALID_ARG, "row_format must be 0, 1, 2 or 3");
+    if (o.col_format < 0 || o.col_format > 3)
+        return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1, 2 or 3");
     if (o.check_every < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "check_every must be >= 0");
     if (o.refine_sweeps < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "refine_sweeps must be >= 0");
     if (G->mem == LSQR_MEM_HOST) {
@@ -489,8 +500,47 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         launch_gather_runs(st, nr, c->nsrc, c->ndst, c->ndesc, c->va, c->nval, 8);
         use_nruns = true;
     }
+    // run masks of the data rows (index the CSR values directly)
+    if (o.row_format == 3 && nnz > 0) {
+        RowMasks RM;
+        if (!build_row_masks_host(m, hrow, hcol, RM))
+            return bail(LSQR_E_UNSUPPORTED, "run masks need nnz < 2^32");
+        c->rmask_words = (int64_t)RM.mask.size();
+        c->rmask_runs = (int64_t)RM.rcol.size();
+        c->rmask = ctx_alloc<uint64_t>(c, c->rmask_words);
+        c->rbase = ctx_alloc<uint32_t>(c, c->rmask_words);
+        c->rcol = ctx_alloc<int32_t>(c, c->rmask_runs);
+        if (!c->rmask || !c->rbase || !c->rcol) return bail(LSQR_E_OOM, "device allocation failed");
+        CR_TRY(hipMemcpy(c->rmask, RM.mask.data(), c->rmask_words * sizeof(uint64_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->rbase, RM.base.data(), c->rmask_words * sizeof(uint32_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->rcol, RM.rcol.data(), c->rmask_runs * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    // node masks of the data block (index the CSC values directly)
+    if (o.col_format == 3 && nnz > 0) {
+        NodeMasks NM;
+        if (!build_node_masks_host(m, n, G->nz, hrow, hcol, NM))
+            return bail(LSQR_E_UNSUPPORTED, "node masks need nz <= 32 and m < 2^32");
+        const int64_t nn = n / G->nz;
+        c->mrows_n = (int64_t)NM.rows.size();
+        c->mchunks = NM.cptr.back();
+        c->mrptr = ctx_alloc<int64_t>(c, nn + 1);
+        c->mcptr = ctx_alloc<int64_t>(c, nn + 1);
+        c->mrows = ctx_alloc<uint32_t>(c, c->mrows_n);
+        c->mmask = ctx_alloc<uint64_t>(c, c->mchunks * G->nz);
+        c->mqoff = ctx_alloc<int64_t>(c, nn * 4 * G->nz);
+        c->morder = ctx_alloc<int32_t>(c, nn);
+        if (!c->mrptr || !c->mcptr || !c->mrows || !c->mmask || !c->mqoff || !c->morder)
+            return bail(LSQR_E_OOM, "device allocation failed");
+        CR_TRY(hipMemcpy(c->mrptr, NM.rptr.data(), (nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->mcptr, NM.cptr.data(), (nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->mrows, NM.rows.data(), c->mrows_n * sizeof(uint32_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->mmask, NM.mask.data(), c->mchunks * G->nz * sizeof(uint64_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->mqoff, NM.qoff.data(), nn * 4 * G->nz * sizeof(int64_t), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(c->morder, NM.order.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     // FP64 formats
     c->R64.vt = VT_F64; c->R64.rp = c->rp; c->R64.ci = c->ci; c->R64.val = c->va;
+    if (c->rmask) { c->R64.rmask = c->rmask; c->R64.rbase = c->rbase; c->R64.rcol = c->rcol; }
     c->R64.lpr = o.lanes_per_row ? o.lanes_per_row : pick_lanes(avg_row);
     if (use_runs) { c->R64.run_ptr = c->run_ptr; c->R64.runs = c->runs; c->R64.roff = c->roff; }
     c->C64.vt = VT_F64; c->C64.cp = c->cp; c->C64.ri = c->ri; c->C64.val = c->cv;
@@ -517,6 +567,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
         C.norder = c->norder; C.val = c->nval;
     }
+    set_node_masks(c, C);
     int vec = VT_F64;
     if (o.precision == LSQR_FP32) {
         c->va32 = ctx_alloc<float>(c, nnz);
@@ -742,12 +793,13 @@ lsqr_status lsqr_apply_t(lsqr_ctx *c, const double *y, double *x)
     if (!c) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx is NULL");
     if (!x || !y) return fail(c, LSQR_E_INVALID_ARG, "x and y must not be NULL");
     DeviceGuard dg(c->device);
-    // the FP64 transposed format the solver reads (node runs when built)
+    // the FP64 transposed format the solver reads (node runs / masks when built)
     ColFmt C = c->C64;
     if (c->nrp) {
         C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
         C.norder = c->norder; C.val = c->nval;
     }
+    set_node_masks(c, C);
     launch_adj(c->st, c->P, std::min(2048, c->eng.g_adj), VT_F64, C, c->d, y, y, nullptr, x,
                c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 0);
     HIP_TRY(c, hipGetLastError());
@@ -804,13 +856,19 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
     const double mb = m + 2 * n;
     const double sv = (double)vt_size(E.R.vt), sx = (double)vt_size(E.vec);
     double fwd = nnz * sv + (m + 1) * 8.0 + n * sx + 2.0 * mb * sx;
-    if (E.R.run_ptr) fwd += (double)c->nruns * 6.0 + (m + 1) * 8.0;
+    if (E.R.rmask) fwd += (double)c->rmask_words * 12.0 + (double)c->rmask_runs * 4.0;
+    else if (E.R.run_ptr) fwd += (double)c->nruns * 6.0 + (m + 1) * 8.0;
     else fwd += nnz * 4.0;
     if (E.R.sigma) fwd += m * 4.0 + m * sx;
     out->fwd_bytes = fwd;
-    out->row_format = E.R.run_ptr ? 2 : 1;
-    out->col_format = E.C.nrp ? 2 : 1;
-    if (E.C.nrp) {
+    out->row_format = E.R.rmask ? 3 : E.R.run_ptr ? 2 : 1;
+    out->col_format = E.C.mmask ? 3 : E.C.nrp ? 2 : 1;
+    if (E.C.mmask) {
+        const double nn = n / (double)c->P.nz, nzd = (double)c->P.nz;
+        out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->mrows_n * 4.0 +
+                         (double)c->mchunks * nzd * 8.0 + nn * 4.0 * nzd * 8.0 +
+                         2.0 * (nn + 1) * 8.0 + nn * 4.0 + mb * sx + n * (8.0 + 2.0 * sx);
+    } else if (E.C.nrp) {
         const double nn = n / (double)c->P.nz;
         out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->nnruns * 6.0 +
                          (nn + 1) * 8.0 + (4 * nn + 1) * 8.0 + nn * 4.0 + mb * sx +

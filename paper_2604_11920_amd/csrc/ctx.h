@@ -71,6 +71,13 @@ struct lsqr_ctx {
     int32_t *norder = nullptr; double *nval = nullptr; float *nval32 = nullptr;
     uint16_t *nvalq = nullptr; uint32_t *nsrc = nullptr, *ndst = nullptr;
     int64_t nnruns = 0;
+    // run masks of the data rows (forward product over va)
+    uint64_t *rmask = nullptr; uint32_t *rbase = nullptr; int32_t *rcol = nullptr;
+    int64_t rmask_words = 0, rmask_runs = 0;
+    // node masks of the data block (transposed product over cv)
+    int64_t *mrptr = nullptr, *mcptr = nullptr, *mqoff = nullptr; uint32_t *mrows = nullptr;
+    uint64_t *mmask = nullptr; int32_t *morder = nullptr;
+    int64_t mrows_n = 0, mchunks = 0;
     double *d = nullptr, *ones = nullptr;
     lsqr::RowFmt R64;
     lsqr::ColFmt C64;

@@ -67,6 +67,13 @@ struct RowFmt {
     const void *val = nullptr;
     const float *sigma = nullptr;      // [m] row scales (quantised values) or nullptr
     int lpr = 64;                      // lanes per row (plain CSR)
+    // run masks (used instead of ci when rmask is set): bit p of rmask marks
+    // entry p as the start of a run of consecutive columns; rbase[w] = runs
+    // starting before word w; column of entry p of row i in run r =
+    // rcol[r] + (p - rp[i])
+    const uint64_t *rmask = nullptr;   // [ceil(nnz / 64)]
+    const uint32_t *rbase = nullptr;   // [ceil(nnz / 64)]
+    const int32_t *rcol = nullptr;     // [runs]
 };
 
 // Stored transpose (CSC) for the transposed product.
@@ -83,7 +90,18 @@ struct ColFmt {
     const int64_t *nvq = nullptr;      // [4 nnodes+1] value offset of each quarter of a node's runs
     const uint32_t *nrow = nullptr;    // [nruns] data row of the run
     const uint16_t *ndesc = nullptr;   // [nruns] (iz0 << 8) | len
-    const int32_t *norder = nullptr;   // [nnodes] nodes by decreasing run count
+    const int32_t *norder = nullptr;   // [nnodes] nodes by decreasing work
+    // Node masks (used instead of the CSC rows when mmask is set; val is the
+    // CSC value array): rows mrows[mrptr[k] ..] of node k in chunks of 64;
+    // word mmask[c nz + iz] of global chunk c flags the chunk's rows with an
+    // entry in depth iz; mqoff[(k 4 + w) nz + iz] = CSC position of the first
+    // value of column k nz + iz in quarter w of the node's chunks.
+    const int64_t *mrptr = nullptr;    // [nnodes+1]
+    const uint32_t *mrows = nullptr;   // [node rows]
+    const int64_t *mcptr = nullptr;    // [nnodes+1] first global chunk of node k
+    const uint64_t *mmask = nullptr;   // [chunks nz]
+    const int64_t *mqoff = nullptr;    // [nnodes 4 nz]
+    int nzt = 32;                      // compile-time depth bound of the kernel (>= nz)
 };
 
 // Type-dispatched launchers (kernels_f64.hip, kernels_f32.hip).

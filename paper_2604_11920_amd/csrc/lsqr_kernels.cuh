@@ -153,6 +153,9 @@ struct FwdArgs {
     const uint16_t *roff;     // value offset of each run within its row
     const void *va;           // [nnz] values of type M
     const float *sigma;       // [m] row scales or nullptr
+    const uint64_t *rmask;    // run masks (see RowFmt) or nullptr
+    const uint32_t *rbase;
+    const int32_t *rcol;
     int64_t m;
     int n, nx, ny, nz;
     double w, damp;
@@ -339,6 +342,65 @@ __global__ __launch_bounds__(kBlock) void k_fwd_runs(FwdArgs a)
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
 }
 
+// Run-mask rows: the CSR values, with the column indices replaced by run
+// masks.  One wave per row walks 64-aligned windows of the value array (lane l
+// of a window takes entry 64 w + l), four windows in flight.  A window's mask
+// word and run base are uniform: the run of entry p is rbase[w] plus the set
+// bits of the mask up to and including bit p (mbcnt), and its column is
+// rcol[run] + (p - row start).  Loads per window: the values, the run
+// descriptors (a few distinct words, one or two cache lines) and the v
+// gathers, as in plain CSR; index bytes fall from 4 per entry to ~0.2 plus
+// 4 per run.
+template <class M, class V>
+__global__ __launch_bounds__(kBlock) void k_fwd_rmask(FwdArgs a)
+{
+    using A = typename AccOf<V>::type;
+    __shared__ double lds[4];
+    double alpha, beta;
+    if (!fwd_prologue(a, alpha, beta, lds)) return;
+    const M *va = (const M *)a.va;
+    const V *z = (const V *)a.z;
+    double sq = 0.0;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lanebit = 1ull << lane;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); row < a.m;
+         row += nwaves) {
+        const int64_t s = a.rp[row], e = a.rp[row + 1];
+        A acc[4] = {0, 0, 0, 0};
+        for (int64_t w = s >> 6; w * 64 < e; w += 4) {
+            int col[4];
+            A val[4];
+            bool act[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t ww = w + u, p = ww * 64 + lane;
+                act[u] = p >= s && p < e;            // false for every lane past the row
+                col[u] = 0;
+                val[u] = 0;
+                if (ww * 64 < e) {                   // uniform
+                    const uint64_t mk = a.rmask[ww];
+                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                    const int64_t r = (int64_t)a.rbase[ww] + below + ((mk & lanebit) ? 1 : 0) - 1;
+                    if (act[u]) {
+                        col[u] = a.rcol[r] + (int)(p - s);
+                        val[u] = ld_nt<A>(va + p);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (act[u]) acc[u] = fma(val[u], (A)z[col[u]], acc[u]);
+        }
+        const A tot = group_sum<64>((acc[0] + acc[1]) + (acc[2] + acc[3]));
+        if (lane == 0) sq += fwd_row_out<V>(a, row, (double)tot, alpha, beta);
+    }
+    sq += fwd_reg_rows<V>(a, alpha, beta);
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+}
+
 // ------------------------------------------------------------- transposed --
 struct AdjArgs {
     const int64_t *cp;
@@ -367,6 +429,12 @@ struct AdjArgs {
     const uint32_t *nrow;
     const uint16_t *ndesc;
     const int32_t *norder;
+    // node masks (k_adj_nmask): see ColFmt
+    const int64_t *mrptr;
+    const uint32_t *mrows;
+    const int64_t *mcptr;
+    const uint64_t *mmask;
+    const int64_t *mqoff;
 };
 
 // beta_{k+1} from the forward partials (FP64, fixed order); false when the
@@ -554,6 +622,81 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
 }
 
+// Transposed product over node masks: the CSC values, with the row indices
+// replaced by per-node row lists and bit masks.  Node k's rows (the data rows
+// reaching any of its nz columns, ascending) are cut into chunks of 64; lane l
+// of a chunk owns row 64 c + l, gathers t for it once and, for every depth iz,
+// adds its entry when bit l of the chunk's mask word for iz is set.  The set
+// bits enumerate column k nz + iz in CSC order, so the entry sits at the
+// column's running position plus mbcnt of the mask; the running positions are
+// uniform (scalar registers).  A workgroup takes a node (decreasing work,
+// boustrophedon over workgroups); its 4 waves take fixed quarters of the
+// node's chunks, the column sums combine lanes, then waves, in fixed order.
+// NZ >= nz is a compile-time bound (per-depth accumulators in registers).
+template <class M, class V, int NZ>
+__global__ __launch_bounds__(kBlock) void k_adj_nmask(AdjArgs a)
+{
+#pragma clang fp contract(off)
+    using A = typename AccOf<V>::type;
+    __shared__ double lds[4];
+    __shared__ A wsum[kBlock / 64][NZ];
+    double beta;
+    if (!adj_prologue(a, beta, lds)) return;
+    const M *cv = (const M *)a.cv;
+    const V *Tg = (const V *)a.Tg;
+    const int nz = a.nz;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint64_t lanebit = 1ull << lane;
+    const int nnodes = a.n / nz;
+    const int G = gridDim.x;
+    double sq = 0.0;
+    for (int s = 0; s * G < nnodes; ++s) {
+        const int idx = s * G + ((s & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        if (idx >= nnodes) continue;         // uniform over the workgroup
+        const int node = a.norder[idx];
+        const int64_t c0 = a.mcptr[node], nc = a.mcptr[node + 1] - c0;
+        const int64_t r0 = a.mrptr[node], nrows = a.mrptr[node + 1] - r0;
+        const int64_t cw0 = nc * wid / 4, cw1 = nc * (wid + 1) / 4;
+        int64_t vb[NZ];
+        A acc[NZ];
+#pragma unroll
+        for (int iz = 0; iz < NZ; ++iz) {
+            vb[iz] = iz < nz ? a.mqoff[((int64_t)node * 4 + wid) * nz + iz] : 0;
+            acc[iz] = 0;
+        }
+        for (int64_t c = cw0; c < cw1; ++c) {
+            const int64_t q = c * 64 + lane;
+            const A t = q < nrows ? (A)Tg[__builtin_nontemporal_load(a.mrows + r0 + q)] : (A)0;
+            const uint64_t *mk = a.mmask + (c0 + c) * nz;
+#pragma unroll
+            for (int iz = 0; iz < NZ; ++iz) {
+                if (iz < nz) {                   // uniform
+                    const uint64_t wbits = mk[iz];
+                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(wbits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)wbits, 0u));
+                    if (wbits & lanebit) acc[iz] = fma(ld_nt<A>(cv + vb[iz] + below), t, acc[iz]);
+                    vb[iz] += __builtin_popcountll(wbits);
+                }
+            }
+        }
+#pragma unroll
+        for (int iz = 0; iz < NZ; ++iz) {
+            if (iz < nz) {
+                const A v = group_sum<64>(acc[iz]);
+                if (lane == 0) wsum[wid][iz] = v;
+            }
+        }
+        __syncthreads();
+        if (wid == 0 && lane < nz) {
+            const A g = ((wsum[0][lane] + wsum[1][lane]) + wsum[2][lane]) + wsum[3][lane];
+            sq += adj_col_out<V>(a, node * nz + lane, g, beta);
+        }
+        __syncthreads();
+    }
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+}
+
 // ----------------------------------------------------------------- update --
 struct UpdArgs {
     int n;
@@ -669,6 +812,10 @@ namespace lsqr {
 template <class M, class V>
 static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArgs &a)
 {
+    if (R.rmask) {
+        hipLaunchKernelGGL((k_fwd_rmask<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
+        return;
+    }
     if (R.run_ptr) {
         hipLaunchKernelGGL((k_fwd_runs<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
         return;
@@ -685,6 +832,15 @@ static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArg
 template <class M, class V>
 static void adj_launch_m(hipStream_t st, int grid, const ColFmt &C, const AdjArgs &a)
 {
+    if (C.mmask) {
+        switch (C.nzt) {
+        case 8: hipLaunchKernelGGL((k_adj_nmask<M, V, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 16: hipLaunchKernelGGL((k_adj_nmask<M, V, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 24: hipLaunchKernelGGL((k_adj_nmask<M, V, 24>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_adj_nmask<M, V, 32>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        }
+        return;
+    }
     if (C.nrp) {
         hipLaunchKernelGGL((k_adj_nruns<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
         return;
@@ -710,7 +866,8 @@ hipError_t fwd_launch(hipStream_t st, const Problem &P, int grid, const RowFmt &
                       const double *part_v, int np_v, double *S, int *ctl, int parity,
                       double tol, int mode)
 {
-    FwdArgs a{R.rp, R.ci, R.run_ptr, R.runs, R.roff, R.val, R.sigma, P.m, (int)P.n, P.nx, P.ny,
+    FwdArgs a{R.rp, R.ci, R.run_ptr, R.runs, R.roff, R.val, R.sigma, R.rmask, R.rbase, R.rcol,
+              P.m, (int)P.n, P.nx, P.ny,
               P.nz, P.w, P.damp, z, Tprev, Tcur, Ts, part_out, part_v, np_v, S, ctl, parity,
               mode, tol};
     if constexpr (Wide<V>::value) {
@@ -735,7 +892,8 @@ hipError_t adj_launch(hipStream_t st, const Problem &P, int grid, const ColFmt &
 {
     AdjArgs a{C.cp, C.ri, C.val, P.m, (int)P.n, P.nx, P.ny, P.nz, P.w, P.damp, d, T, Tg, v, q,
               part_out, part_t, np_t, S, ctl, parity, mode, data_only, C.xcd_bands,
-              C.nrp, C.nvq, C.nrow, C.ndesc, C.norder};
+              C.nrp, C.nvq, C.nrow, C.ndesc, C.norder, C.mrptr, C.mrows, C.mcptr, C.mmask,
+              C.mqoff};
     switch (C.vt) {
     case VT_F64:
         if constexpr (Wide<V>::value) adj_launch_m<double, V>(st, grid, C, a);

@@ -1,6 +1,7 @@
-// Host-side builders of the run formats (plain C++, no HIP): depth runs of
-// the data rows (forward product) and node runs of the data block
-// (transposed product).  Both read only the CSR structure.
+// Host-side builders of the compressed index formats (plain C++, no HIP):
+// depth runs of the data rows and run masks (forward product), node runs and
+// node masks of the data block (transposed product).  All read only the CSR
+// structure; the masked formats index the existing CSR / CSC value arrays.
 #pragma once
 
 #include <stdint.h>
@@ -164,6 +165,181 @@ inline bool build_node_runs_host(int64_t m, int64_t n, int nz, const int64_t *rp
         return R.nrp[(size_t)x + 1] - R.nrp[(size_t)x] > R.nrp[(size_t)y + 1] - R.nrp[(size_t)y];
     });
     return off == nnz;
+}
+
+// Run masks of the data rows (forward product over the CSR values).  A run is
+// a maximal stretch of consecutive columns inside a row.  Bit p of the global
+// mask (word p / 64, bit p % 64) is set when stored entry p starts a run;
+// base[w] = number of runs starting before word w; rcol[r] = first column of
+// run r minus the offset of its first entry inside its row, so the column of
+// entry p in row i, run r, is rcol[r] + (p - row_ptr[i]).  Needs nnz < 2^32.
+struct RowMasks {
+    std::vector<uint64_t> mask;     // [ceil(nnz / 64)]
+    std::vector<uint32_t> base;     // [ceil(nnz / 64)]
+    std::vector<int32_t> rcol;      // [runs]
+};
+
+inline bool build_row_masks_host(int64_t m, const int64_t *rp, const int32_t *ci, RowMasks &R)
+{
+    const int64_t nnz = rp[m];
+    if (nnz >= ((int64_t)1 << 32)) return false;
+    const int64_t nw = (nnz + 63) / 64;
+    R.mask.assign((size_t)nw, 0ull);
+    R.base.assign((size_t)nw, 0u);
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (nnz < (1 << 20)) nt = 1;
+    auto start = [&](int64_t i, int64_t p) { return p == rp[i] || ci[p] != ci[p - 1] + 1; };
+    // bits: threads own whole mask words (entry ranges split at multiples of 64)
+    {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t]() {
+                const int64_t w0 = nw * t / nt, w1 = nw * (t + 1) / nt;
+                if (w0 >= w1) return;
+                // first row holding entry 64 w0
+                int64_t i = std::upper_bound(rp, rp + m + 1, 64 * w0) - rp - 1;
+                for (int64_t p = 64 * w0; p < std::min(64 * w1, nnz); ++p) {
+                    while (rp[i + 1] <= p) ++i;
+                    if (start(i, p)) R.mask[(size_t)(p >> 6)] |= 1ull << (p & 63);
+                }
+            });
+        for (auto &x : th) x.join();
+    }
+    uint64_t runs = 0;
+    for (int64_t w = 0; w < nw; ++w) {
+        R.base[(size_t)w] = (uint32_t)runs;
+        runs += (uint64_t)__builtin_popcountll(R.mask[(size_t)w]);
+    }
+    if (runs >= ((uint64_t)1 << 32)) return false;
+    R.rcol.resize((size_t)runs);
+    {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t]() {
+                for (int64_t i = m * t / nt; i < m * (t + 1) / nt; ++i)
+                    for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+                        if (start(i, p)) {
+                            const int64_t w = p >> 6;
+                            const uint64_t below = R.mask[(size_t)w] & ((1ull << (p & 63)) - 1);
+                            const int64_t r = (int64_t)R.base[(size_t)w] + __builtin_popcountll(below);
+                            R.rcol[(size_t)r] = (int32_t)(ci[p] - (p - rp[i]));
+                        }
+            });
+        for (auto &x : th) x.join();
+    }
+    return true;
+}
+
+// Node masks of the data block (transposed product over the CSC values).  For
+// lateral node k (columns [k nz, (k+1) nz), eq. 7): rows[rp_k .. rp_{k+1}) =
+// the data rows reaching the node, ascending, cut into chunks of 64; chunk c
+// of all nodes (global chunk index) has nz mask words, bit l of word
+// mask[c nz + iz] set when row 64 (c - chunk0_k) + l of node k has an entry in
+// column k nz + iz.  The entries of a column sit in the CSC in ascending row
+// order, so the set bits, in order, enumerate the column's values.  qoff
+// [(k 4 + w) nz + iz] = CSC position of the first value of column k nz + iz
+// in quarter w of the node's chunks (wave w of the workgroup takes chunks
+// [chunk0 + c w / 4, chunk0 + c (w+1) / 4)).  order = nodes by decreasing
+// chunk count (stable).
+struct NodeMasks {
+    std::vector<int64_t> rptr;      // [nnodes+1] into rows
+    std::vector<uint32_t> rows;     // [node rows]
+    std::vector<int64_t> cptr;      // [nnodes+1] first global chunk of a node
+    std::vector<uint64_t> mask;     // [chunks * nz]
+    std::vector<int64_t> qoff;      // [nnodes * 4 * nz]
+    std::vector<int32_t> order;     // [nnodes]
+};
+
+inline bool build_node_masks_host(int64_t m, int64_t n, int nz, const int64_t *rp,
+                                  const int32_t *ci, NodeMasks &R)
+{
+    const int64_t nnz = rp[m];
+    if (nz < 1 || nz > 32 || n % nz != 0 || m >= ((int64_t)1 << 32)) return false;
+    const int64_t nn = n / nz;
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (nnz < (1 << 20)) nt = 1;
+    // (row, node) pairs: entries of one node are contiguous inside a row
+    std::vector<std::vector<int64_t>> cnt(nt, std::vector<int64_t>((size_t)nn, 0));
+    {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t]() {
+                auto &c = cnt[t];
+                for (int64_t i = m * t / nt; i < m * (t + 1) / nt; ++i)
+                    for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+                        if (p == rp[i] || ci[p] / nz != ci[p - 1] / nz) ++c[(size_t)(ci[p] / nz)];
+            });
+        for (auto &x : th) x.join();
+    }
+    R.rptr.assign((size_t)nn + 1, 0);
+    for (int64_t k = 0; k < nn; ++k) {
+        int64_t tot = 0;
+        for (unsigned t = 0; t < nt; ++t) {
+            const int64_t c = cnt[t][(size_t)k];
+            cnt[t][(size_t)k] = R.rptr[(size_t)k] + tot;      // becomes the cursor
+            tot += c;
+        }
+        R.rptr[(size_t)k + 1] = R.rptr[(size_t)k] + tot;
+    }
+    R.cptr.assign((size_t)nn + 1, 0);
+    for (int64_t k = 0; k < nn; ++k)
+        R.cptr[(size_t)k + 1] = R.cptr[(size_t)k] + (R.rptr[(size_t)k + 1] - R.rptr[(size_t)k] + 63) / 64;
+    R.rows.resize((size_t)R.rptr[(size_t)nn]);
+    R.mask.assign((size_t)(R.cptr[(size_t)nn] * nz), 0ull);
+    {
+        // a thread's rows land in disjoint slots; the mask bits are set in a
+        // second pass split by node, so every mask word has one writer
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t]() {
+                auto &cur = cnt[t];
+                for (int64_t i = m * t / nt; i < m * (t + 1) / nt; ++i)
+                    for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+                        if (p == rp[i] || ci[p] / nz != ci[p - 1] / nz)
+                            R.rows[(size_t)cur[(size_t)(ci[p] / nz)]++] = (uint32_t)i;
+            });
+        for (auto &x : th) x.join();
+    }
+    {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t]() {
+                for (int64_t k = nn * t / nt; k < nn * (t + 1) / nt; ++k)
+                    for (int64_t q = R.rptr[(size_t)k]; q < R.rptr[(size_t)k + 1]; ++q) {
+                        const int64_t i = R.rows[(size_t)q], idx = q - R.rptr[(size_t)k];
+                        const int64_t chunk = R.cptr[(size_t)k] + idx / 64;
+                        // the row's entries in node k: binary search the row's columns
+                        const int32_t *b = ci + rp[i], *e = ci + rp[i + 1];
+                        for (const int32_t *c = std::lower_bound(b, e, (int32_t)(k * nz));
+                             c < e && *c < (k + 1) * nz; ++c)
+                            R.mask[(size_t)(chunk * nz + (*c - k * nz))] |= 1ull << (idx & 63);
+                    }
+            });
+        for (auto &x : th) x.join();
+    }
+    // quarter offsets: column start (CSC) plus the set bits of earlier chunks
+    std::vector<int64_t> colcnt((size_t)n + 1, 0);
+    for (int64_t p = 0; p < nnz; ++p) ++colcnt[(size_t)ci[p] + 1];
+    for (int64_t j = 0; j < n; ++j) colcnt[(size_t)j + 1] += colcnt[(size_t)j];
+    R.qoff.assign((size_t)(nn * 4 * nz), 0);
+    for (int64_t k = 0; k < nn; ++k) {
+        const int64_t c0 = R.cptr[(size_t)k], nc = R.cptr[(size_t)k + 1] - c0;
+        for (int iz = 0; iz < nz; ++iz) {
+            int64_t pos = colcnt[(size_t)(k * nz + iz)];
+            int64_t c = 0;
+            for (int w = 0; w < 4; ++w) {
+                const int64_t cw = nc * w / 4;
+                for (; c < cw; ++c) pos += __builtin_popcountll(R.mask[(size_t)((c0 + c) * nz + iz)]);
+                R.qoff[(size_t)((k * 4 + w) * nz + iz)] = pos;
+            }
+        }
+    }
+    R.order.resize((size_t)nn);
+    for (int64_t k = 0; k < nn; ++k) R.order[(size_t)k] = (int32_t)k;
+    std::stable_sort(R.order.begin(), R.order.end(), [&](int32_t x, int32_t y) {
+        return R.cptr[(size_t)x + 1] - R.cptr[(size_t)x] > R.cptr[(size_t)y + 1] - R.cptr[(size_t)y];
+    });
+    return true;
 }
 
 }  // namespace lsqr

@@ -3,7 +3,10 @@
 //   in : int64 m, n, nz, nnz; int64 row_ptr[m+1]; int32 col[nnz]
 //   out: int64 ok_rows, nruns; int64 run_ptr[m+1]; uint32 runs[]; uint16 roff[];
 //        int64 ok_nodes, nnruns, nnodes; int64 nrp[nnodes+1]; int64 nvq[4 nnodes+1];
-//        uint32 row[]; uint32 src[]; uint32 dst[]; uint16 desc[]; int32 order[nnodes]
+//        uint32 row[]; uint32 src[]; uint32 dst[]; uint16 desc[]; int32 order[nnodes];
+//        int64 ok_rmask, nwords, nruns; uint64 mask[]; uint32 base[]; int32 rcol[];
+//        int64 ok_nmask, nnodes, nrows, nchunks; int64 rptr[]; uint32 rows[]; int64 cptr[];
+//        uint64 mask[nchunks nz]; int64 qoff[nnodes 4 nz]; int32 order[]
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -46,6 +49,26 @@ int main(int argc, char **argv)
         put(fo, R.row.data(), R.row.size()); put(fo, R.src.data(), R.src.size());
         put(fo, R.dst.data(), R.dst.size()); put(fo, R.desc.data(), R.desc.size());
         put(fo, R.order.data(), R.order.size());
+    }
+    lsqr::RowMasks M;
+    const int64_t ok3 = lsqr::build_row_masks_host(m, rp.data(), ci.data(), M);
+    const int64_t nw = ok3 ? (int64_t)M.mask.size() : 0, nr3 = ok3 ? (int64_t)M.rcol.size() : 0;
+    put(fo, &ok3, 1);
+    put(fo, &nw, 1);
+    put(fo, &nr3, 1);
+    if (ok3) { put(fo, M.mask.data(), M.mask.size()); put(fo, M.base.data(), M.base.size()); put(fo, M.rcol.data(), M.rcol.size()); }
+    lsqr::NodeMasks K;
+    const int64_t ok4 = lsqr::build_node_masks_host(m, n, (int)nz, rp.data(), ci.data(), K);
+    const int64_t nn4 = ok4 ? n / nz : 0, nrow4 = ok4 ? (int64_t)K.rows.size() : 0;
+    const int64_t nch4 = ok4 ? K.cptr.back() : 0;
+    put(fo, &ok4, 1);
+    put(fo, &nn4, 1);
+    put(fo, &nrow4, 1);
+    put(fo, &nch4, 1);
+    if (ok4) {
+        put(fo, K.rptr.data(), K.rptr.size()); put(fo, K.rows.data(), K.rows.size());
+        put(fo, K.cptr.data(), K.cptr.size()); put(fo, K.mask.data(), K.mask.size());
+        put(fo, K.qoff.data(), K.qoff.size()); put(fo, K.order.data(), K.order.size());
     }
     fclose(fo);
     return 0;

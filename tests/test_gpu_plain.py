@@ -92,7 +92,7 @@ def test_transpose_matches_library_csc(which, cfg0):
 
 @pytest.mark.parametrize("lanes,row_format,col_format",
                          [(0, "auto", "auto"), (4, "csr", "csc"), (16, "csr", "csc"),
-                          (64, "csr", "csc"), (0, "runs", "runs")])
+                          (64, "csr", "csc"), (0, "runs", "runs"), (0, "masks", "masks")])
 def test_operator_integer_bitwise(lanes, row_format, col_format):
     s = ragged_system(2, integer=True)
     op = oracle.Operator.from_system(s)
@@ -108,7 +108,7 @@ def test_operator_integer_bitwise(lanes, row_format, col_format):
 
 
 @pytest.mark.parametrize("row_format,col_format", [("csr", "csc"), ("runs", "csc"),
-                                                    ("runs", "runs")])
+                                                    ("runs", "runs"), ("masks", "masks")])
 def test_operator_integer_bitwise_tomography_pattern(cfg0, row_format, col_format):
     # the tomography sparsity (runs of depth columns, merged across nodes) with
     # integer values: every sum is exact, so both row formats match bitwise
@@ -169,13 +169,14 @@ def test_operator_random_within_rounding(cfg0, precond):
 
 
 # --------------------------------------------------------------- solves -----
-@pytest.mark.parametrize("precond,col_format", [("none", "auto"), ("jacobi", "auto"),
-                                                ("jacobi", "runs")])
-def test_early_iterates_strict(cfg0, precond, col_format):
+@pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"),
+                                         ("jacobi", "runs"), ("jacobi", "masks")])
+def test_early_iterates_strict(cfg0, precond, fmt):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
     op = oracle.Operator.from_system(s, d=d)
-    with from_sys(s, precond=precond, col_format=col_format) as sol:
+    rf = "csr" if fmt == "runs" else fmt
+    with from_sys(s, precond=precond, row_format=rf, col_format=fmt) as sol:
         for K in (1, 2, 3, 5, 8):
             ref = op.lsqr(s.dt, K)
             dm, hist, info = sol.solve(s.dt, K)
@@ -184,13 +185,14 @@ def test_early_iterates_strict(cfg0, precond, col_format):
             assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0), K
 
 
-@pytest.mark.parametrize("precond,col_format", [("none", "auto"), ("jacobi", "auto"),
-                                                ("none", "runs")])
-def test_converged_strict(cfg0, cfg0_xstar, precond, col_format):
+@pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"),
+                                         ("none", "runs"), ("none", "masks")])
+def test_converged_strict(cfg0, cfg0_xstar, precond, fmt):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
     ref = oracle.Operator.from_system(s, d=d).lsqr(s.dt, 40000, tol=1e-13)
-    with from_sys(s, precond=precond, col_format=col_format) as sol:
+    rf = "csr" if fmt == "runs" else fmt
+    with from_sys(s, precond=precond, row_format=rf, col_format=fmt) as sol:
         dm, hist, info = sol.solve(s.dt, 40000, tol=1e-13)
     assert info["istop"] == 1 and ref["istop"] == 1
     assert info["eta"] <= 1e-13
@@ -229,22 +231,22 @@ def test_tolerance_stop(cfg0):
     assert eta <= 2 * tol
 
 
-@pytest.mark.parametrize("col_format", ["auto", "runs"])
-def test_ragged_system_strict(col_format):
+@pytest.mark.parametrize("fmt", ["auto", "runs", "masks"])
+def test_ragged_system_strict(fmt):
     s = ragged_system(5)
     for K in (1, 4, 8):
         ref = oracle.lsqr(s, K)
-        with from_sys(s, col_format=col_format) as sol:
+        with from_sys(s, row_format=fmt, col_format=fmt) as sol:
             dm, hist, info = sol.solve(s.dt, K)
         assert rel(dm, ref["x"]) <= 1e-10, K
 
 
-@pytest.mark.parametrize("col_format", ["auto", "runs"])
-def test_small_shapes(col_format):
+@pytest.mark.parametrize("fmt", ["auto", "runs", "masks"])
+def test_small_shapes(fmt):
     for grid in [(1, 1, 1), (1, 1, 3), (2, 1, 1), (3, 2, 1)]:
         s = synth.random_system(25, *grid, row_len=(0, 4), seed=sum(grid))
         ref = oracle.lsqr(s, 3)
-        with from_sys(s, col_format=col_format) as sol:
+        with from_sys(s, row_format=fmt, col_format=fmt) as sol:
             dm, hist, info = sol.solve(s.dt, 3)
         assert rel(dm, ref["x"]) <= 1e-10 or info["istop"] in (1, 3), grid
 

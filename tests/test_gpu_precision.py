@@ -72,9 +72,11 @@ def test_quantised_codes_bitwise(cfg0, fmt, which):
 
 @pytest.mark.parametrize("fmt,precond,col_format", [
     ("bf16", "none", "auto"), ("bf16", "jacobi", "auto"), ("fp16", "none", "auto"),
-    ("fp16", "jacobi", "auto"), ("bf16", "jacobi", "runs"), ("fp16", "jacobi", "runs")])
+    ("fp16", "jacobi", "auto"), ("bf16", "jacobi", "runs"), ("fp16", "jacobi", "runs"),
+    ("bf16", "jacobi", "masks"), ("fp16", "none", "masks")])
 def test_refinement_reaches_fp64_solution(cfg0, xstar, fmt, precond, col_format):
     with from_sys(cfg0, precision=fmt, precond=precond, refine_sweeps=10,
+                  row_format="masks" if col_format == "masks" else "auto",
                   col_format=col_format) as sol:
         dm, hist, info = sol.solve(cfg0.dt, 3000, tol=1e-7)
     err = rel(dm, xstar)
@@ -107,7 +109,7 @@ def test_mixed_form_rejections(cfg0):
 
 
 @pytest.mark.parametrize("row_format,col_format", [("csr", "csc"), ("runs", "csc"),
-                                                    ("runs", "runs")])
+                                                    ("runs", "runs"), ("masks", "masks")])
 def test_fp32_iterates(cfg0, row_format, col_format):
     ref = oracle.lsqr(cfg0, 5)
     with from_sys(cfg0, precision="fp32", row_format=row_format, col_format=col_format) as sol:
@@ -131,7 +133,7 @@ def test_fp32_converged(cfg0, xstar):
     assert info["istop"] == 1 and err <= 3 * err64 + 1e-4
 
 
-@pytest.mark.parametrize("row_format", ["csr", "runs"])
+@pytest.mark.parametrize("row_format", ["csr", "runs", "masks"])
 def test_fp64_row_formats_agree(cfg0, row_format):
     ref = oracle.lsqr(cfg0, 6)
     with from_sys(cfg0, row_format=row_format) as sol:

@@ -67,8 +67,80 @@ def run_builders(exe, tmp, row_ptr, col, n, nz):
         out["dst"] = take(np.uint32, nr2)
         out["desc"] = take(np.uint16, nr2)
         out["order"] = take(np.int32, nn)
+    ok3, nw, nr3 = take(np.int64, 3)
+    out["rmask_ok"] = bool(ok3)
+    if ok3:
+        out["rmask"] = take(np.uint64, nw)
+        out["rbase"] = take(np.uint32, nw)
+        out["rcol"] = take(np.int32, nr3)
+    ok4, nn4, nrow4, nch4 = take(np.int64, 4)
+    out["nmask_ok"] = bool(ok4)
+    if ok4:
+        out["m_rptr"] = take(np.int64, nn4 + 1)
+        out["m_rows"] = take(np.uint32, nrow4)
+        out["m_cptr"] = take(np.int64, nn4 + 1)
+        out["m_mask"] = take(np.uint64, nch4 * nz)
+        out["m_qoff"] = take(np.int64, nn4 * 4 * nz)
+        out["m_order"] = take(np.int32, nn4)
     assert pos == len(buf)
     return out
+
+
+def bits_of(words, count):
+    """Bit p of a little-endian array of u64 words, for p < count."""
+    b = np.unpackbits(np.asarray(words, dtype='<u8').view(np.uint8), bitorder="little")
+    return b[:count].astype(bool)
+
+
+def check_row_masks(o, row_ptr, col):
+    nnz = len(col)
+    mask, base, rcol = o["rmask"], o["rbase"], o["rcol"]
+    bits = bits_of(mask, nnz)
+    row = np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
+    starts = np.ones(nnz, bool)
+    starts[1:] = (col[1:] != col[:-1] + 1) | (row[1:] != row[:-1])
+    assert np.array_equal(bits, starts)
+    pc = np.array([bin(int(w)).count("1") for w in mask], np.int64)
+    assert np.array_equal(base.astype(np.int64), np.concatenate([[0], np.cumsum(pc)[:-1]]))
+    assert len(rcol) == starts.sum()
+    ridx = np.cumsum(starts) - 1              # run of every entry
+    # what the kernel computes: base of the word + set bits up to and including p
+    p = np.arange(nnz)
+    incl = np.array([bin(int(mask[q >> 6]) & ((2 << (q & 63)) - 1)).count("1")
+                     for q in map(int, p)]) if nnz < 200000 else None
+    if incl is not None:
+        assert np.array_equal(base[p >> 6].astype(np.int64) + incl - 1, ridx)
+    assert np.array_equal(rcol[ridx].astype(np.int64) + (p - row_ptr[row]), col)
+
+
+def check_node_masks(o, row_ptr, col, n, nz):
+    rptr, rows, cptr, mask, qoff, order = (o[k] for k in
+                                           ("m_rptr", "m_rows", "m_cptr", "m_mask", "m_qoff", "m_order"))
+    nn = n // nz
+    row = np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
+    node = col // nz
+    # rows of each node: the ascending unique rows with an entry in the node
+    for k in range(nn):
+        ref = np.unique(row[node == k])
+        assert np.array_equal(rows[rptr[k]:rptr[k + 1]], ref)
+        assert cptr[k + 1] - cptr[k] == (len(ref) + 63) // 64
+    colptr = np.concatenate([[0], np.cumsum(np.bincount(col, minlength=n))])
+    for k in range(nn):
+        rk = rows[rptr[k]:rptr[k + 1]].astype(np.int64)
+        c0, nc = cptr[k], cptr[k + 1] - cptr[k]
+        for iz in range(nz):
+            j = k * nz + iz
+            words = mask[(c0 + np.arange(nc)) * nz + iz]
+            b = bits_of(words, len(rk))
+            assert not bits_of(words, 64 * nc)[len(rk):].any()
+            # the set bits, in order, are the column's rows in CSC order
+            assert np.array_equal(rk[b], np.sort(row[col == j]))
+            pos = colptr[j]
+            for w in range(4):
+                cw = nc * w // 4
+                assert qoff[(k * 4 + w) * nz + iz] == colptr[j] + b[:64 * cw].sum()
+    counts = np.diff(cptr)
+    assert np.array_equal(order, np.argsort(-counts, kind="stable"))
 
 
 def check_row_runs(o, row_ptr, col):
@@ -136,6 +208,8 @@ def test_small_config(driver, tmp_path):
     assert o["rows_ok"] and o["nodes_ok"]
     check_row_runs(o, s.row_ptr, s.col)
     check_node_runs(o, s.row_ptr, s.col, s.n, s.nz)
+    check_row_masks(o, s.row_ptr, s.col)
+    check_node_masks(o, s.row_ptr, s.col, s.n, s.nz)
 
 
 def test_full_depth_rows_cross_node_boundaries(driver, tmp_path):
@@ -154,6 +228,8 @@ def test_full_depth_rows_cross_node_boundaries(driver, tmp_path):
     o = run_builders(driver, tmp_path, rp, col, n, nz)
     check_row_runs(o, rp, col)
     check_node_runs(o, rp, col, n, nz)
+    check_row_masks(o, rp, col)
+    check_node_masks(o, rp, col, n, nz)
     assert len(o["runs"]) == len(rows)            # one forward run per row
     assert len(o["row"]) == sum(len(r) // nz for r in rows)
 
@@ -174,6 +250,8 @@ def test_random_structure_with_gaps_and_empty_rows(driver, tmp_path):
     o = run_builders(driver, tmp_path, rp, col, n, nz)
     check_row_runs(o, rp, col)
     check_node_runs(o, rp, col, n, nz)
+    check_row_masks(o, rp, col)
+    check_node_masks(o, rp, col, n, nz)
 
 
 def test_long_rows_split_at_255(driver, tmp_path):
@@ -191,7 +269,7 @@ def test_node_runs_refused_for_deep_grids(driver, tmp_path):
     rp = np.array([0, 3])
     col = np.array([0, 1, 70])
     o = run_builders(driver, tmp_path, rp, col, n, nz)
-    assert o["rows_ok"] and not o["nodes_ok"]
+    assert o["rows_ok"] and not o["nodes_ok"] and o["rmask_ok"] and not o["nmask_ok"]
 
 
 def test_config0(driver, tmp_path):
