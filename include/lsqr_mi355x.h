@@ -325,7 +325,11 @@ lsqr_status lsqr_trainer_params(const lsqr_trainer *t, float *params, float *par
 /* lsqr_trainer_destroy — free t (NULL is a no-op). */
 void lsqr_trainer_destroy(lsqr_trainer *t);
 
-/* lsqr_kernel_stats — kernel timing of the last solve (LSQR_FLAG_TIMING). */
+/* lsqr_kernel_stats — kernel timing of the last solve (LSQR_FLAG_TIMING; for
+ * the BF16/FP16 forms, the inner products of all refinement sweeps), the
+ * algorithmic bytes of one launch of each sparse kernel and the formats they
+ * read.  Timing records events around every launch, so timed solves run
+ * without hipGraph replay. */
 lsqr_status lsqr_kernel_stats(const lsqr_ctx *ctx, lsqr_kstats *out);
 
 /* lsqr_destroy — free every buffer of ctx (NULL is a no-op). */

@@ -707,6 +707,8 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, int iters, double
     Engine &E = c->eng;
     const double inner_tol = 1e-3;
     const int gadj = std::min(2048, E.g_adj);
+    const bool timing = (c->flags & LSQR_FLAG_TIMING) != 0;   // inner products, all sweeps
+    if (timing) c->ks = lsqr_kstats{};
     auto fetch = [&]() -> lsqr_status {
         HIP_TRY(c, hipMemcpyAsync(c->hsum, c->sums, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(c, hipStreamSynchronize(st));
@@ -750,7 +752,7 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, int iters, double
             if (sw > 0 && eta > 0.5 * eta_prev) { istop = 4; break; }
             eta_prev = eta;
             // inner solve on the quantised operator, x += D y
-            s = engine_solve(c, E, c->fbuf, 1, iters, inner_tol, c->xbuf, 1, false);
+            s = engine_solve(c, E, c->fbuf, 1, iters, inner_tol, c->xbuf, 1, timing);
             if (s != LSQR_OK) return s;
             if ((s = read_state(c, E, iters, hs)) != LSQR_OK) return s;
             last_iters = c->hctl[C_ITERS];

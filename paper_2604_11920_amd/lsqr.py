@@ -79,9 +79,10 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2604_11920_amd.build.build()")
-    lib = ctypes.CDLL(LIB_PATH)
+    path = os.environ.get("LSQR_MI355X_LIB", LIB_PATH)      # an alternative build
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2604_11920_amd.build.build()")
+    lib = ctypes.CDLL(path)
     P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     sig = {
         "lsqr_create": (I, [ctypes.POINTER(CSR), D, D, ctypes.POINTER(Opts), ctypes.POINTER(P)]),
