@@ -65,24 +65,7 @@ template <class A> __device__ __forceinline__ A ld_nt(const fp16_t *p)
     return (A)(float)h;
 }
 
-// Entries per lane in flight in the CSR / CSC products.
-#ifndef LSQR_UNROLL
-#define LSQR_UNROLL 4
-#endif
-constexpr int kUnroll = LSQR_UNROLL;
-
 // ------------------------------------------------------------ reductions --
-// Pairwise sum of U accumulators in a fixed tree order.
-template <int U, class T>
-__device__ __forceinline__ T tree_sum(const T *v)
-{
-    if constexpr (U == 1) {
-        return v[0];
-    } else {
-        return tree_sum<U / 2>(v) + tree_sum<U - U / 2>(v + U / 2);
-    }
-}
-
 template <int W, class T>
 __device__ __forceinline__ T group_sum(T v)
 {
@@ -278,25 +261,22 @@ __global__ __launch_bounds__(kBlock) void k_fwd_csr(FwdArgs a)
     const int64_t gstride = (int64_t)gridDim.x * RPB;
     for (int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR; row < a.m; row += gstride) {
         const int64_t s = a.rp[row], e = a.rp[row + 1];
-        // kUnroll entries per lane in flight; the row's tail runs through the
-        // same predicated body (one pass, not a serial remainder loop)
-        A ac[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) ac[u] = 0;
-        for (int64_t j = s + lane; j < e; j += kUnroll * LPR) {
-            int c[kUnroll];
-            A v[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const bool in = j + u * LPR < e;
-                c[u] = in ? __builtin_nontemporal_load(a.ci + j + u * LPR) : 0;
-                v[u] = in ? ld_nt<A>(va + j + u * LPR) : (A)0;
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                if (j + u * LPR < e) ac[u] = fma(v[u], (A)z[c[u]], ac[u]);
+        A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int64_t j = s + lane;
+        for (; j + 3 * LPR < e; j += 4 * LPR) {
+            const int c0 = __builtin_nontemporal_load(a.ci + j);
+            const int c1 = __builtin_nontemporal_load(a.ci + j + LPR);
+            const int c2 = __builtin_nontemporal_load(a.ci + j + 2 * LPR);
+            const int c3 = __builtin_nontemporal_load(a.ci + j + 3 * LPR);
+            const A v0 = ld_nt<A>(va + j), v1 = ld_nt<A>(va + j + LPR);
+            const A v2 = ld_nt<A>(va + j + 2 * LPR), v3 = ld_nt<A>(va + j + 3 * LPR);
+            a0 = fma(v0, (A)z[c0], a0);
+            a1 = fma(v1, (A)z[c1], a1);
+            a2 = fma(v2, (A)z[c2], a2);
+            a3 = fma(v3, (A)z[c3], a3);
         }
-        const A acc = group_sum<LPR>(tree_sum<kUnroll>(ac));
+        for (; j < e; j += LPR) a0 = fma(ld_nt<A>(va + j), (A)z[__builtin_nontemporal_load(a.ci + j)], a0);
+        const A acc = group_sum<LPR>((a0 + a1) + (a2 + a3));
         if (lane == 0) sq += fwd_row_out<V>(a, row, (double)acc, alpha, beta);
     }
     sq += fwd_reg_rows<V>(a, alpha, beta);
@@ -527,23 +507,23 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
     }
     for (int j = jstart + threadIdx.x / LPC; j < jhi; j += jstep) {
         const int64_t s = a.cp[j], e = a.cp[j + 1];
-        A ac[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) ac[u] = 0;
-        for (int64_t p = s + lane; p < e; p += kUnroll * LPC) {
-            int r[kUnroll];
-            A v[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const bool in = p + u * LPC < e;
-                r[u] = in ? __builtin_nontemporal_load(a.ri + p + u * LPC) : 0;
-                v[u] = in ? ld_nt<A>(cv + p + u * LPC) : (A)0;
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                if (p + u * LPC < e) ac[u] = fma(v[u], (A)Tg[r[u]], ac[u]);
+        A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int64_t p = s + lane;
+        for (; p + 3 * LPC < e; p += 4 * LPC) {
+            const int r0 = __builtin_nontemporal_load(a.ri + p);
+            const int r1 = __builtin_nontemporal_load(a.ri + p + LPC);
+            const int r2 = __builtin_nontemporal_load(a.ri + p + 2 * LPC);
+            const int r3 = __builtin_nontemporal_load(a.ri + p + 3 * LPC);
+            const A v0 = ld_nt<A>(cv + p), v1 = ld_nt<A>(cv + p + LPC);
+            const A v2 = ld_nt<A>(cv + p + 2 * LPC), v3 = ld_nt<A>(cv + p + 3 * LPC);
+            a0 = fma(v0, (A)Tg[r0], a0);
+            a1 = fma(v1, (A)Tg[r1], a1);
+            a2 = fma(v2, (A)Tg[r2], a2);
+            a3 = fma(v3, (A)Tg[r3], a3);
         }
-        const A g = group_sum<LPC>(tree_sum<kUnroll>(ac));
+        for (; p < e; p += LPC)
+            a0 = fma(ld_nt<A>(cv + p), (A)Tg[__builtin_nontemporal_load(a.ri + p)], a0);
+        const A g = group_sum<LPC>((a0 + a1) + (a2 + a3));
         if (lane == 0) sq += adj_col_out<V>(a, j, g, beta);
     }
     const double tot = block_sum(sq, lds);

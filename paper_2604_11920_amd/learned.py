@@ -8,13 +8,15 @@ count moves.  Features, inference (BF16) and training (FP32 forward/backward
 and Adam) run in the library's kernels; this module orchestrates them.
 
 Training targets come from a search per system over a low-dimensional family
-of log multipliers
+of log multipliers, either per depth layer
 
-    l_j(theta) = a0 + a1 f3_j + b (f2_j - mean f2) + c (f6_j - mean f6)
+    l_j(theta) = a_{iz(j)} + b (f2_j - mean f2) + c (f6_j - mean f6)
 
-(depth index, ray coverage, neighbour coverage): coordinate descent over
-theta on a grid, minimising LSQR iterations to the tolerance, capped at twice
-Jacobi's count.  The target of column j is l_j at the best theta.
+(nz + 2 parameters: one per depth layer, ray coverage, neighbour coverage) or
+the linear-in-depth family a0 + a1 f3_j + b (...) + c (...): coordinate
+descent over theta on a grid {-1, -1/2, 1/2, 1} x step, the step halved each
+round, minimising LSQR iterations to the tolerance, capped at twice Jacobi's
+count.  The target of column j is l_j at the best theta.
 
 Fallback and judge: a learned scale that is not finite and positive is
 replaced by Jacobi inside lsqr_create; a learned solve that has not reached
@@ -62,11 +64,18 @@ def initial_params(seed=0):
     return np.concatenate([np.asarray(p, dtype=np.float64) for p in parts]).astype(np.float32)
 
 
-def family_log_multiplier(feat, theta):
-    """l_j(theta) for host features [n, 6] (see the module docstring)."""
-    a0, a1, b, c = theta
+def family_log_multiplier(feat, theta, nz=None):
+    """l_j(theta) for host features [n, 6]: per-depth family when theta has
+    nz + 2 entries, else the linear-in-depth family (see the module docstring)."""
     f = np.asarray(feat, dtype=np.float64)
-    return a0 + a1 * f[:, 2] + b * (f[:, 1] - f[:, 1].mean()) + c * (f[:, 5] - f[:, 5].mean())
+    cov = f[:, 1] - f[:, 1].mean()
+    nbr = f[:, 5] - f[:, 5].mean()
+    theta = np.asarray(theta, dtype=np.float64)
+    if nz is not None and len(theta) == nz + 2:
+        iz = np.arange(len(f)) % nz
+        return theta[iz] + theta[nz] * cov + theta[nz + 1] * nbr
+    a0, a1, b, c = theta
+    return a0 + a1 * f[:, 2] + b * cov + c * nbr
 
 
 def iterations_to_tol(system, col_scale, tol, cap):
@@ -77,28 +86,31 @@ def iterations_to_tol(system, col_scale, tol, cap):
     return info["iters"] if info["istop"] == 1 else int(cap) + 1, info
 
 
-def search_targets(system, tol=1e-6, grid=(-1.0, -0.5, 0.5, 1.0), scales=(1.0, 1.0, 0.5, 0.5),
-                   rounds=1, log=None):
+def search_targets(system, tol=1e-6, family="depth", grid=(-1.0, -0.5, 0.5, 1.0), step=0.5,
+                   rounds=2, log=None):
     """Coordinate descent over theta; returns (features [n,6], targets [n],
     theta, Jacobi iterations, best iterations)."""
     with Solver.from_system(system, precond="jacobi") as sol:
         feat = sol.column_features().cpu().numpy().astype(np.float64)
         djac = sol.scale()
     kj, _ = iterations_to_tol(system, None, tol, 20000)
-    theta = np.zeros(4)
+    nz = int(system.nz)
+    theta = np.zeros(nz + 2 if family == "depth" else 4)
     best = kj
-    for _ in range(rounds):
-        for p in range(4):
+    for rnd in range(rounds):
+        h = step * 0.5 ** rnd
+        for p in range(len(theta)):
+            base = theta[p]
             for v in grid:
                 th = theta.copy()
-                th[p] = v * scales[p]
-                d = djac * np.exp(family_log_multiplier(feat, th))
-                k, _ = iterations_to_tol(system, d, tol, 2 * kj)
+                th[p] = base + v * h
+                d = djac * np.exp(family_log_multiplier(feat, th, nz))
+                k, _ = iterations_to_tol(system, d, tol, min(2 * kj, best + 1))
                 if k < best:
                     best, theta = k, th
     if log:
         log(f"  search: jacobi {kj} -> best {best} at theta {np.round(theta, 3).tolist()}")
-    return feat, family_log_multiplier(feat, theta), theta, kj, best
+    return feat, family_log_multiplier(feat, theta, nz), theta, kj, best
 
 
 def train(feats, targets, epochs=60, batch=4096, lr=1e-3, seed=0, log=None):

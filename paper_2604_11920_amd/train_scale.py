@@ -54,7 +54,8 @@ def cmd_search(args):
     feats, targets, rows = [], [], []
     for i, cfg in enumerate(family(args.family, args.first, args.count)):
         s = synth.make_system(cfg)
-        f, t, theta, kj, kb = learned.search_targets(s, tol=args.tol)
+        f, t, theta, kj, kb = learned.search_targets(s, tol=args.tol, family=args.param,
+                                                     rounds=args.rounds)
         feats.append(f.astype(np.float32))
         targets.append(t.astype(np.float32))
         rows.append({"name": cfg.name, "n": int(s.n), "nnz": int(s.nnz), "jacobi_iters": int(kj),
@@ -127,6 +128,9 @@ def main():
     a.add_argument("--first", type=int, default=1)
     a.add_argument("--count", type=int, default=160)
     a.add_argument("--tol", type=float, default=1e-6)
+    a.add_argument("--param", default="depth", choices=["depth", "linear"],
+                   help="target family: one log multiplier per depth layer, or linear in depth")
+    a.add_argument("--rounds", type=int, default=2, help="coordinate-descent rounds (step halved)")
     a.add_argument("--out", required=True)
     b = sub.add_parser("fit")
     b.add_argument("targets", nargs="+")
