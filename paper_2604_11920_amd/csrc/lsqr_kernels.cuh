@@ -65,6 +65,12 @@ template <class A> __device__ __forceinline__ A ld_nt(const fp16_t *p)
     return (A)(float)h;
 }
 
+// 1: the CSR / CSC products finish a row / column with one clamped pass
+// instead of a serial remainder loop.
+#ifndef LSQR_CLAMPED_TAIL
+#define LSQR_CLAMPED_TAIL 0
+#endif
+
 // ------------------------------------------------------------ reductions --
 template <int W, class T>
 __device__ __forceinline__ T group_sum(T v)
@@ -275,7 +281,25 @@ __global__ __launch_bounds__(kBlock) void k_fwd_csr(FwdArgs a)
             a2 = fma(v2, (A)z[c2], a2);
             a3 = fma(v3, (A)z[c3], a3);
         }
+#if LSQR_CLAMPED_TAIL
+        if (j < e) {          // one pass over the last < 4 LPR entries, loads clamped
+            int c[4];
+            A v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t jj = j + u * LPR < e ? j + u * LPR : e - 1;
+                c[u] = __builtin_nontemporal_load(a.ci + jj);
+                v[u] = ld_nt<A>(va + jj);
+                if (j + u * LPR >= e) v[u] = 0;
+            }
+            a0 = fma(v[0], (A)z[c[0]], a0);
+            a1 = fma(v[1], (A)z[c[1]], a1);
+            a2 = fma(v[2], (A)z[c[2]], a2);
+            a3 = fma(v[3], (A)z[c[3]], a3);
+        }
+#else
         for (; j < e; j += LPR) a0 = fma(ld_nt<A>(va + j), (A)z[__builtin_nontemporal_load(a.ci + j)], a0);
+#endif
         const A acc = group_sum<LPR>((a0 + a1) + (a2 + a3));
         if (lane == 0) sq += fwd_row_out<V>(a, row, (double)acc, alpha, beta);
     }
@@ -285,57 +309,89 @@ __global__ __launch_bounds__(kBlock) void k_fwd_csr(FwdArgs a)
 }
 
 // Depth-run rows: one wave per row.  The wave loads up to 64 run descriptors
-// with one coalesced load (one per lane), then four 16-lane groups each take
-// one run (a contiguous stretch of columns and values) per step, taking the
-// descriptor from a register with a cross-lane shuffle; four steps (16 runs)
-// are in flight at once, so value loads and v gathers never wait on a
-// descriptor load.
+// (one per lane, coalesced), expands them into the columns of the next
+// entries of the row in a wave-private LDS window (each run-lane writes its
+// stretch of consecutive columns), then walks the window like a CSR row: lane
+// l takes entries l, l + 64, ... with four entries in flight (value loads and
+// v gathers coalesced and fully active; out-of-range slots load a clamped
+// address and are multiplied by zero, so no branch splits the loads).  The
+// next window's descriptors are loaded while the current one is walked.
+// Index bytes: 6 per run instead of 4 per entry.
+constexpr int kFwdWin = 1024;        // columns per wave window (LDS)
+
 template <class M, class V>
 __global__ __launch_bounds__(kBlock) void k_fwd_runs(FwdArgs a)
 {
     using A = typename AccOf<V>::type;
     __shared__ double lds[4];
+    __shared__ int colw[kBlock / 64][kFwdWin];
     double alpha, beta;
     if (!fwd_prologue(a, alpha, beta, lds)) return;
     const M *va = (const M *)a.va;
     const V *z = (const V *)a.z;
     double sq = 0.0;
-    const int lane = threadIdx.x & 63, g = lane >> 4, gl = lane & 15;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int *cw = colw[wid];
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); row < a.m;
-         row += nwaves) {
+    for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + wid; row < a.m; row += nwaves) {
         const int64_t vs = a.rp[row];
         const int64_t rs = a.run_ptr[row], re = a.run_ptr[row + 1];
-        A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        for (int64_t base = rs; base < re; base += 64) {
-            const int nr = (int)(re - base < 64 ? re - base : 64);
-            uint32_t md = 0u;
-            int mo = 0;
-            if (lane < nr) {
-                md = __builtin_nontemporal_load(a.runs + base + lane);
-                mo = (int)__builtin_nontemporal_load(a.roff + base + lane);
+        A acc[4] = {0, 0, 0, 0};
+        int64_t vpos = vs;               // first entry of the current window
+        int64_t base = rs;
+        uint32_t md = 0u;
+        if (base + lane < re) md = __builtin_nontemporal_load(a.runs + base + lane);
+        while (base < re) {
+            // runs of this window: the longest prefix of the (up to 64) loaded
+            // runs whose lengths sum to <= kFwdWin (at least 4: len <= 255)
+            const int len = (int)(md & 255u);
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
             }
-            for (int s0 = 0; s0 < nr; s0 += 16) {
-                // lanes >= nr hold md = 0, i.e. an empty run
-                const uint32_t d0 = __shfl(md, s0 + g), d1 = __shfl(md, s0 + 4 + g);
-                const uint32_t d2 = __shfl(md, s0 + 8 + g), d3 = __shfl(md, s0 + 12 + g);
-                const int o0 = __shfl(mo, s0 + g), o1 = __shfl(mo, s0 + 4 + g);
-                const int o2 = __shfl(mo, s0 + 8 + g), o3 = __shfl(mo, s0 + 12 + g);
-                const int n0 = (int)(d0 & 255u), n1 = (int)(d1 & 255u);
-                const int n2 = (int)(d2 & 255u), n3 = (int)(d3 & 255u);
-                const int c0 = (int)(d0 >> 8), c1 = (int)(d1 >> 8);
-                const int c2 = (int)(d2 >> 8), c3 = (int)(d3 >> 8);
-                const int nmax = max(max(n0, n1), max(n2, n3));
-                for (int e = gl; e < nmax; e += 16) {
-                    if (e < n0) a0 = fma(ld_nt<A>(va + vs + o0 + e), (A)z[c0 + e], a0);
-                    if (e < n1) a1 = fma(ld_nt<A>(va + vs + o1 + e), (A)z[c1 + e], a1);
-                    if (e < n2) a2 = fma(ld_nt<A>(va + vs + o2 + e), (A)z[c2 + e], a2);
-                    if (e < n3) a3 = fma(ld_nt<A>(va + vs + o3 + e), (A)z[c3 + e], a3);
+            const bool in_win = base + lane < re && incl <= kFwdWin;
+            const uint64_t fit = __ballot(in_win);
+            const int nr = __popcll(fit);                  // the fitting runs are a prefix
+            const int tot = nr > 0 ? __shfl(incl, nr - 1) : 0;
+            // expand the window's columns into LDS
+            const int c0 = (int)(md >> 8), off = incl - len;
+            int maxlen = in_win ? len : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o));
+            for (int e = 0; e < maxlen; ++e)
+                if (in_win && e < len) cw[off + e] = c0 + e;
+            // next window's descriptors
+            const int64_t nb = base + nr;
+            uint32_t md_n = 0u;
+            if (nb + lane < re) md_n = __builtin_nontemporal_load(a.runs + nb + lane);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // walk the window's entries [vpos, vpos + tot)
+            for (int q = lane; q < tot; q += 4 * 64) {
+                int c[4];
+                A v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int qq = q + u * 64 < tot ? q + u * 64 : tot - 1;   // clamped
+                    c[u] = cw[qq];
+                    v[u] = ld_nt<A>(va + vpos + qq);
+                    if (q + u * 64 >= tot) v[u] = 0;
                 }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] = fma(v[u], (A)z[c[u]], acc[u]);
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            vpos += tot;
+            base = nb;             // md_n holds the runs from nb on
+            md = md_n;
         }
-        const A acc = group_sum<64>((a0 + a1) + (a2 + a3));
-        if (lane == 0) sq += fwd_row_out<V>(a, row, (double)acc, alpha, beta);
+        const A tot = group_sum<64>((acc[0] + acc[1]) + (acc[2] + acc[3]));
+        if (lane == 0) sq += fwd_row_out<V>(a, row, (double)tot, alpha, beta);
     }
     sq += fwd_reg_rows<V>(a, alpha, beta);
     const double tot = block_sum(sq, lds);
@@ -521,8 +577,26 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
             a2 = fma(v2, (A)Tg[r2], a2);
             a3 = fma(v3, (A)Tg[r3], a3);
         }
+#if LSQR_CLAMPED_TAIL
+        if (p < e) {          // one pass over the last < 4 LPC entries, loads clamped
+            int r[4];
+            A v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t pp = p + u * LPC < e ? p + u * LPC : e - 1;
+                r[u] = __builtin_nontemporal_load(a.ri + pp);
+                v[u] = ld_nt<A>(cv + pp);
+                if (p + u * LPC >= e) v[u] = 0;
+            }
+            a0 = fma(v[0], (A)Tg[r[0]], a0);
+            a1 = fma(v[1], (A)Tg[r[1]], a1);
+            a2 = fma(v[2], (A)Tg[r[2]], a2);
+            a3 = fma(v[3], (A)Tg[r[3]], a3);
+        }
+#else
         for (; p < e; p += LPC)
             a0 = fma(ld_nt<A>(cv + p), (A)Tg[__builtin_nontemporal_load(a.ri + p)], a0);
+#endif
         const A g = group_sum<LPC>((a0 + a1) + (a2 + a3));
         if (lane == 0) sq += adj_col_out<V>(a, j, g, beta);
     }
@@ -540,10 +614,16 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
 // dealt to workgroups boustrophedon-wise so every workgroup gets a similar
 // load.  The 4 waves of a workgroup take fixed contiguous quarters of the
 // node's runs (value offsets of the quarters are stored).  Inside a wave the
-// lanes form 64/nz groups of nz lanes, lane iz of a group owning depth iz;
-// group g takes runs g, g + 64/nz, ... of each 64-run chunk, so the values of
-// a run are read by consecutive lanes.  Per column, the sum runs over the
-// groups in order, then over the waves in order: fixed, no atomics.
+// lanes form 64/nz groups of nz lanes, lane iz of a group owning depth iz.
+// The wave walks its runs in chunks of kRunsPerGroup runs per group: the
+// chunk's descriptors and t values sit one per lane, a wave prefix sum gives
+// each run's value offset, and every lane issues all of its chunk's value
+// loads before the first multiply-add, while the next chunk's descriptors and
+// t gathers are already in flight.  Per column, the sum runs over the chunks
+// in order, then over the groups in order, then over the waves in order:
+// fixed, no atomics.
+constexpr int kRunsPerGroup = 8;
+
 template <class M, class V>
 __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
 {
@@ -556,6 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
     const M *nv = (const M *)a.cv;
     const V *Tg = (const V *)a.Tg;
     const int nz = a.nz, ngr = 64 / nz;
+    const int ch = ngr * kRunsPerGroup < 64 ? ngr * kRunsPerGroup : 64;   // runs per chunk
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int grp = lane / nz, iz = lane - grp * nz;
     const bool live = grp < ngr;
@@ -569,15 +650,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
         const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
         const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
         int64_t vb = a.nvq[4 * (int64_t)node + wid];
-        A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        for (int64_t base = rs; base < re; base += 64) {
-            const int nr = (int)(re - base < 64 ? re - base : 64);
-            uint32_t dsc = 0u;
-            A tr = 0;
-            if (lane < nr) {
-                dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
-                tr = (A)Tg[__builtin_nontemporal_load(a.nrow + base + lane)];
-            }
+        A acc = 0;
+        // first chunk's descriptors and t
+        int64_t base = rs;
+        int nr = (int)(re - base < ch ? re - base : ch);
+        uint32_t dsc = 0u;
+        A tr = 0;
+        if (lane < nr) {
+            dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
+            tr = (A)Tg[__builtin_nontemporal_load(a.nrow + base + lane)];
+        }
+        while (base < re) {
             const int len = (int)(dsc & 255u);
             int incl = len;
 #pragma unroll
@@ -588,26 +671,36 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
             // (value offset in the chunk << 16) | (iz0 << 8) | len; offsets < 64 * 64
             const uint32_t pk = ((uint32_t)(incl - len) << 16) | dsc;
             const int tot = __shfl(incl, 63);
-            for (int s0 = 0; s0 < nr; s0 += 4 * ngr) {
-                const int r0 = s0 + grp, r1 = r0 + ngr, r2 = r1 + ngr, r3 = r2 + ngr;
-                const uint32_t p0 = __shfl(pk, r0 & 63), p1 = __shfl(pk, r1 & 63);
-                const uint32_t p2 = __shfl(pk, r2 & 63), p3 = __shfl(pk, r3 & 63);
-                const A t0 = __shfl(tr, r0 & 63), t1 = __shfl(tr, r1 & 63);
-                const A t2 = __shfl(tr, r2 & 63), t3 = __shfl(tr, r3 & 63);
-                const int e0 = iz - (int)((p0 >> 8) & 255u), e1 = iz - (int)((p1 >> 8) & 255u);
-                const int e2 = iz - (int)((p2 >> 8) & 255u), e3 = iz - (int)((p3 >> 8) & 255u);
-                if (live && r0 < nr && (unsigned)e0 < (p0 & 255u))
-                    a0 = fma(ld_nt<A>(nv + vb + (p0 >> 16) + e0), t0, a0);
-                if (live && r1 < nr && (unsigned)e1 < (p1 & 255u))
-                    a1 = fma(ld_nt<A>(nv + vb + (p1 >> 16) + e1), t1, a1);
-                if (live && r2 < nr && (unsigned)e2 < (p2 & 255u))
-                    a2 = fma(ld_nt<A>(nv + vb + (p2 >> 16) + e2), t2, a2);
-                if (live && r3 < nr && (unsigned)e3 < (p3 & 255u))
-                    a3 = fma(ld_nt<A>(nv + vb + (p3 >> 16) + e3), t3, a3);
+            // next chunk's descriptors (issued before this chunk's values)
+            const int64_t nb = base + nr;
+            const int nn = nb < re ? (int)(re - nb < ch ? re - nb : ch) : 0;
+            uint32_t dsc_n = 0u, row_n = 0u;
+            if (lane < nn) {
+                dsc_n = __builtin_nontemporal_load(a.ndesc + nb + lane);
+                row_n = __builtin_nontemporal_load(a.nrow + nb + lane);
             }
+            // this chunk's values: run grp + u ngr of the chunk for lane (grp, iz)
+            A v[kRunsPerGroup];
+#pragma unroll
+            for (int u = 0; u < kRunsPerGroup; ++u) {
+                const int r = grp + u * ngr;
+                const uint32_t p = __shfl(pk, r & 63);
+                const int e = iz - (int)((p >> 8) & 255u);
+                v[u] = 0;
+                if (live && r < nr && (unsigned)e < (p & 255u))
+                    v[u] = ld_nt<A>(nv + vb + (p >> 16) + e);
+            }
+            A tr_n = 0;
+            if (lane < nn) tr_n = (A)Tg[row_n];
+#pragma unroll
+            for (int u = 0; u < kRunsPerGroup; ++u)
+                acc = fma(v[u], __shfl(tr, (grp + u * ngr) & 63), acc);
             vb += tot;
+            base = nb;
+            nr = nn;
+            dsc = dsc_n;
+            tr = tr_n;
         }
-        const A acc = (a0 + a1) + (a2 + a3);
         A col = 0;
         for (int g = 0; g < ngr; ++g) col += __shfl(acc, (g * nz + iz) & 63);
         if (lane < nz) wsum[wid][lane] = col;
