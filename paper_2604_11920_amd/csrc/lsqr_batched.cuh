@@ -21,6 +21,23 @@ namespace lsqr {
 
 constexpr int kMaxRhs = 32;
 
+// Stored entries per lane in flight in the batched products.
+#ifndef LSQR_BATCH_UNROLL
+#define LSQR_BATCH_UNROLL 8
+#endif
+constexpr int kBatchUnroll = LSQR_BATCH_UNROLL;
+
+// Pairwise sum of U accumulators in a fixed tree order.
+template <int U, class T>
+__device__ __forceinline__ T tree_sum(const T *v)
+{
+    if constexpr (U == 1) {
+        return v[0];
+    } else {
+        return tree_sum<U / 2>(v) + tree_sum<U - U / 2>(v + U / 2);
+    }
+}
+
 struct BArgs {
     // operator (FP32 values)
     const int64_t *rp;
@@ -179,20 +196,26 @@ __global__ __launch_bounds__(kBlock) void k_bfwd(BArgs a)
     for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); row < a.m;
          row += nwaves) {
         const int64_t s = a.rp[row], e = a.rp[row + 1];
-        float a0 = 0.f, a1 = 0.f;
+        float ac[kBatchUnroll];
+#pragma unroll
+        for (int u = 0; u < kBatchUnroll; ++u) ac[u] = 0.f;
         int64_t p = s + er;
-        for (; p + EPW < e; p += 2 * EPW) {
-            const float g0 = __builtin_nontemporal_load(a.va + p);
-            const float g1 = __builtin_nontemporal_load(a.va + p + EPW);
-            const int c0 = __builtin_nontemporal_load(a.ci + p);
-            const int c1 = __builtin_nontemporal_load(a.ci + p + EPW);
-            a0 = fmaf(g0, a.Z[(int64_t)c0 * R + cofs], a0);
-            a1 = fmaf(g1, a.Z[(int64_t)c1 * R + cofs], a1);
+        for (; p + (kBatchUnroll - 1) * EPW < e; p += kBatchUnroll * EPW) {
+            float g[kBatchUnroll];
+            int c[kBatchUnroll];
+#pragma unroll
+            for (int u = 0; u < kBatchUnroll; ++u) {
+                g[u] = __builtin_nontemporal_load(a.va + p + u * EPW);
+                c[u] = __builtin_nontemporal_load(a.ci + p + u * EPW);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatchUnroll; ++u)
+                ac[u] = fmaf(g[u], a.Z[(int64_t)c[u] * R + cofs], ac[u]);
         }
-        if (p < e)
-            a0 = fmaf(__builtin_nontemporal_load(a.va + p),
-                      a.Z[(int64_t)__builtin_nontemporal_load(a.ci + p) * R + cofs], a0);
-        float acc = a0 + a1;
+        for (; p < e; p += EPW)
+            ac[0] = fmaf(__builtin_nontemporal_load(a.va + p),
+                         a.Z[(int64_t)__builtin_nontemporal_load(a.ci + p) * R + cofs], ac[0]);
+        float acc = tree_sum<kBatchUnroll>(ac);
 #pragma unroll
         for (int off = RT; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
         if (er == 0) {
@@ -269,20 +292,27 @@ __global__ __launch_bounds__(kBlock) void k_badj(BArgs a)
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
     for (int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); j < a.n; j += nwaves) {
         const int64_t s = a.cp[j], e = a.cp[j + 1];
-        float a0 = 0.f, a1 = 0.f;
+        // kBatchUnroll entries (each a row segment of RT right-hand sides) in flight
+        float ac[kBatchUnroll];
+#pragma unroll
+        for (int u = 0; u < kBatchUnroll; ++u) ac[u] = 0.f;
         int64_t p = s + er;
-        for (; p + EPW < e; p += 2 * EPW) {
-            const float g0 = __builtin_nontemporal_load(a.cv + p);
-            const float g1 = __builtin_nontemporal_load(a.cv + p + EPW);
-            const int i0 = __builtin_nontemporal_load(a.ri + p);
-            const int i1 = __builtin_nontemporal_load(a.ri + p + EPW);
-            a0 = fmaf(g0, a.Tcur[(int64_t)i0 * R + cofs], a0);
-            a1 = fmaf(g1, a.Tcur[(int64_t)i1 * R + cofs], a1);
+        for (; p + (kBatchUnroll - 1) * EPW < e; p += kBatchUnroll * EPW) {
+            float g[kBatchUnroll];
+            int i[kBatchUnroll];
+#pragma unroll
+            for (int u = 0; u < kBatchUnroll; ++u) {
+                g[u] = __builtin_nontemporal_load(a.cv + p + u * EPW);
+                i[u] = __builtin_nontemporal_load(a.ri + p + u * EPW);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatchUnroll; ++u)
+                ac[u] = fmaf(g[u], a.Tcur[(int64_t)i[u] * R + cofs], ac[u]);
         }
-        if (p < e)
-            a0 = fmaf(__builtin_nontemporal_load(a.cv + p),
-                      a.Tcur[(int64_t)__builtin_nontemporal_load(a.ri + p) * R + cofs], a0);
-        float g = a0 + a1;
+        for (; p < e; p += EPW)
+            ac[0] = fmaf(__builtin_nontemporal_load(a.cv + p),
+                         a.Tcur[(int64_t)__builtin_nontemporal_load(a.ri + p) * R + cofs], ac[0]);
+        float g = tree_sum<kBatchUnroll>(ac);
 #pragma unroll
         for (int off = RT; off < 64; off <<= 1) g += __shfl_xor(g, off, 64);
         if (er == 0) {
