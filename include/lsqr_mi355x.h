@@ -108,7 +108,8 @@ typedef struct {
                                 /* 3 = run masks (CSR values; columns decoded from a  */
                                 /* run-start bit per entry and one word per run)      */
     int col_format;             /* data block of the transposed product: 0 = auto     */
-                                /* (CSC), 1 = CSC, 2 = node runs (per node, the rows  */
+                                /* (node runs when the matrix fits the format, else   */
+                                /* CSC), 1 = CSC, 2 = node runs (per node, the rows   */
                                 /* reaching it with their stretch of consecutive      */
                                 /* depths; needs nz <= 64, nnz < 2^32), 3 = node      */
                                 /* masks (CSC values; per node its row list and one   */

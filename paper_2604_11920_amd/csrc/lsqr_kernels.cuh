@@ -65,10 +65,10 @@ template <class A> __device__ __forceinline__ A ld_nt(const fp16_t *p)
     return (A)(float)h;
 }
 
-// 1: the CSR / CSC products finish a row / column with one clamped pass
-// instead of a serial remainder loop.
-#ifndef LSQR_CLAMPED_TAIL
-#define LSQR_CLAMPED_TAIL 0
+// 1: the CSR / CSC products load the next row's (column's) bounds and the
+// current row's u term before the current row's entries.
+#ifndef LSQR_ROW_PREFETCH
+#define LSQR_ROW_PREFETCH 0
 #endif
 
 // ------------------------------------------------------------ reductions --
@@ -229,6 +229,20 @@ __device__ __forceinline__ double fwd_row_out(const FwdArgs &a, int64_t row, dou
     return (double)t * (double)t;
 }
 
+// As fwd_row_out, with t_prev[row] already loaded.
+template <class V>
+__device__ __forceinline__ double fwd_row_out_u(const FwdArgs &a, int64_t row, double acc,
+                                                double alpha, double beta, double tprev)
+{
+#pragma clang fp contract(off)
+    const double sacc = a.sigma ? (double)a.sigma[row] * acc : acc;
+    const double u = a.mode == MODE_ITER ? tprev / beta : 0.0;
+    const V t = (V)(sacc - alpha * u);
+    ((V *)a.Tcur)[row] = t;
+    if (a.Ts) ((V *)a.Ts)[row] = (V)((double)a.sigma[row] * (double)t);
+    return (double)t * (double)t;
+}
+
 // Smoothing rows (m .. m+n) and damping rows (m+n .. m+2n): one thread each.
 template <class V>
 __device__ __forceinline__ double fwd_reg_rows(const FwdArgs &a, double alpha, double beta)
@@ -265,8 +279,20 @@ __global__ __launch_bounds__(kBlock) void k_fwd_csr(FwdArgs a)
     constexpr int RPB = kBlock / LPR;
     const int lane = threadIdx.x % LPR;
     const int64_t gstride = (int64_t)gridDim.x * RPB;
+#if LSQR_ROW_PREFETCH
+    int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
+    int64_t s = 0, e = 0;
+    if (row < a.m) { s = a.rp[row]; e = a.rp[row + 1]; }
+    for (; row < a.m; row += gstride) {
+        const int64_t nrow = row + gstride;
+        int64_t ns = 0, ne = 0;
+        if (nrow < a.m) { ns = a.rp[nrow]; ne = a.rp[nrow + 1]; }
+        double up = 0.0;
+        if (lane == 0 && a.mode == MODE_ITER) up = (double)((const V *)a.Tprev)[row];
+#else
     for (int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR; row < a.m; row += gstride) {
         const int64_t s = a.rp[row], e = a.rp[row + 1];
+#endif
         A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
         int64_t j = s + lane;
         for (; j + 3 * LPR < e; j += 4 * LPR) {
@@ -281,27 +307,15 @@ __global__ __launch_bounds__(kBlock) void k_fwd_csr(FwdArgs a)
             a2 = fma(v2, (A)z[c2], a2);
             a3 = fma(v3, (A)z[c3], a3);
         }
-#if LSQR_CLAMPED_TAIL
-        if (j < e) {          // one pass over the last < 4 LPR entries, loads clamped
-            int c[4];
-            A v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t jj = j + u * LPR < e ? j + u * LPR : e - 1;
-                c[u] = __builtin_nontemporal_load(a.ci + jj);
-                v[u] = ld_nt<A>(va + jj);
-                if (j + u * LPR >= e) v[u] = 0;
-            }
-            a0 = fma(v[0], (A)z[c[0]], a0);
-            a1 = fma(v[1], (A)z[c[1]], a1);
-            a2 = fma(v[2], (A)z[c[2]], a2);
-            a3 = fma(v[3], (A)z[c[3]], a3);
-        }
-#else
         for (; j < e; j += LPR) a0 = fma(ld_nt<A>(va + j), (A)z[__builtin_nontemporal_load(a.ci + j)], a0);
-#endif
         const A acc = group_sum<LPR>((a0 + a1) + (a2 + a3));
+#if LSQR_ROW_PREFETCH
+        if (lane == 0) sq += fwd_row_out_u<V>(a, row, (double)acc, alpha, beta, up);
+        s = ns;
+        e = ne;
+#else
         if (lane == 0) sq += fwd_row_out<V>(a, row, (double)acc, alpha, beta);
+#endif
     }
     sq += fwd_reg_rows<V>(a, alpha, beta);
     const double tot = block_sum(sq, lds);
@@ -561,8 +575,18 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
         jstart = jlo + slot * CPB;
         jstep = (gridDim.x >> 3) * CPB;
     }
+#if LSQR_ROW_PREFETCH
+    int j = jstart + threadIdx.x / LPC;
+    int64_t s = 0, e = 0;
+    if (j < jhi) { s = a.cp[j]; e = a.cp[j + 1]; }
+    for (; j < jhi; j += jstep) {
+        const int jn = j + jstep;
+        int64_t ns = 0, ne = 0;
+        if (jn < jhi) { ns = a.cp[jn]; ne = a.cp[jn + 1]; }
+#else
     for (int j = jstart + threadIdx.x / LPC; j < jhi; j += jstep) {
         const int64_t s = a.cp[j], e = a.cp[j + 1];
+#endif
         A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
         int64_t p = s + lane;
         for (; p + 3 * LPC < e; p += 4 * LPC) {
@@ -577,28 +601,14 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
             a2 = fma(v2, (A)Tg[r2], a2);
             a3 = fma(v3, (A)Tg[r3], a3);
         }
-#if LSQR_CLAMPED_TAIL
-        if (p < e) {          // one pass over the last < 4 LPC entries, loads clamped
-            int r[4];
-            A v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t pp = p + u * LPC < e ? p + u * LPC : e - 1;
-                r[u] = __builtin_nontemporal_load(a.ri + pp);
-                v[u] = ld_nt<A>(cv + pp);
-                if (p + u * LPC >= e) v[u] = 0;
-            }
-            a0 = fma(v[0], (A)Tg[r[0]], a0);
-            a1 = fma(v[1], (A)Tg[r[1]], a1);
-            a2 = fma(v[2], (A)Tg[r[2]], a2);
-            a3 = fma(v[3], (A)Tg[r[3]], a3);
-        }
-#else
         for (; p < e; p += LPC)
             a0 = fma(ld_nt<A>(cv + p), (A)Tg[__builtin_nontemporal_load(a.ri + p)], a0);
-#endif
         const A g = group_sum<LPC>((a0 + a1) + (a2 + a3));
         if (lane == 0) sq += adj_col_out<V>(a, j, g, beta);
+#if LSQR_ROW_PREFETCH
+        s = ns;
+        e = ne;
+#endif
     }
     const double tot = block_sum(sq, lds);
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;

@@ -68,6 +68,11 @@ def ragged_system(seed=0, integer=False):
                               dt=dt, damp=0.25 if integer else 0.1, smooth=0.5)
 
 
+# stored formats (forward rows, transposed columns) exercised by the solves
+FORMATS = {"auto": ("auto", "auto"), "csc": ("csr", "csc"), "runs": ("runs", "runs"),
+           "masks": ("masks", "masks")}
+
+
 @pytest.fixture(scope="module")
 def cfg0():
     return synth.make_system(synth.config0())
@@ -169,14 +174,14 @@ def test_operator_random_within_rounding(cfg0, precond):
 
 
 # --------------------------------------------------------------- solves -----
-@pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"),
+@pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"), ("none", "csc"),
                                          ("jacobi", "runs"), ("jacobi", "masks")])
 def test_early_iterates_strict(cfg0, precond, fmt):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
     op = oracle.Operator.from_system(s, d=d)
-    rf = "csr" if fmt == "runs" else fmt
-    with from_sys(s, precond=precond, row_format=rf, col_format=fmt) as sol:
+    rf, cf = FORMATS[fmt]
+    with from_sys(s, precond=precond, row_format=rf, col_format=cf) as sol:
         for K in (1, 2, 3, 5, 8):
             ref = op.lsqr(s.dt, K)
             dm, hist, info = sol.solve(s.dt, K)
@@ -185,14 +190,14 @@ def test_early_iterates_strict(cfg0, precond, fmt):
             assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0), K
 
 
-@pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"),
+@pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"), ("none", "csc"),
                                          ("none", "runs"), ("none", "masks")])
 def test_converged_strict(cfg0, cfg0_xstar, precond, fmt):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
     ref = oracle.Operator.from_system(s, d=d).lsqr(s.dt, 40000, tol=1e-13)
-    rf = "csr" if fmt == "runs" else fmt
-    with from_sys(s, precond=precond, row_format=rf, col_format=fmt) as sol:
+    rf, cf = FORMATS[fmt]
+    with from_sys(s, precond=precond, row_format=rf, col_format=cf) as sol:
         dm, hist, info = sol.solve(s.dt, 40000, tol=1e-13)
     assert info["istop"] == 1 and ref["istop"] == 1
     assert info["eta"] <= 1e-13
@@ -231,22 +236,24 @@ def test_tolerance_stop(cfg0):
     assert eta <= 2 * tol
 
 
-@pytest.mark.parametrize("fmt", ["auto", "runs", "masks"])
+@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks"])
 def test_ragged_system_strict(fmt):
     s = ragged_system(5)
+    rf, cf = FORMATS[fmt]
     for K in (1, 4, 8):
         ref = oracle.lsqr(s, K)
-        with from_sys(s, row_format=fmt, col_format=fmt) as sol:
+        with from_sys(s, row_format=rf, col_format=cf) as sol:
             dm, hist, info = sol.solve(s.dt, K)
         assert rel(dm, ref["x"]) <= 1e-10, K
 
 
-@pytest.mark.parametrize("fmt", ["auto", "runs", "masks"])
+@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks"])
 def test_small_shapes(fmt):
+    rf, cf = FORMATS[fmt]
     for grid in [(1, 1, 1), (1, 1, 3), (2, 1, 1), (3, 2, 1)]:
         s = synth.random_system(25, *grid, row_len=(0, 4), seed=sum(grid))
         ref = oracle.lsqr(s, 3)
-        with from_sys(s, row_format=fmt, col_format=fmt) as sol:
+        with from_sys(s, row_format=rf, col_format=cf) as sol:
             dm, hist, info = sol.solve(s.dt, 3)
         assert rel(dm, ref["x"]) <= 1e-10 or info["istop"] in (1, 3), grid
 

@@ -71,7 +71,7 @@ def test_quantised_codes_bitwise(cfg0, fmt, which):
 
 
 @pytest.mark.parametrize("fmt,precond,col_format", [
-    ("bf16", "none", "auto"), ("bf16", "jacobi", "auto"), ("fp16", "none", "auto"),
+    ("bf16", "none", "auto"), ("bf16", "jacobi", "auto"), ("fp16", "none", "csc"),
     ("fp16", "jacobi", "auto"), ("bf16", "jacobi", "runs"), ("fp16", "jacobi", "runs"),
     ("bf16", "jacobi", "masks"), ("fp16", "none", "masks")])
 def test_refinement_reaches_fp64_solution(cfg0, xstar, fmt, precond, col_format):
