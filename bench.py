@@ -141,13 +141,15 @@ def time_to_tol(s, dt, tol, fmt, model_path=None):
     forms the feature + MLP inference time is reported beside the solve."""
     import torch
     from paper_2604_11920_amd import Solver
-    forms = [("fp64", "none", 20000), ("fp64", "jacobi", 20000), ("bf16", "jacobi", 4000),
-             ("fp16", "jacobi", 4000)]
+    # (precision, scaling, iteration cap, inner tolerance of the refinement)
+    forms = [("fp64", "none", 20000, 0.0), ("fp64", "jacobi", 20000, 0.0),
+             ("bf16", "jacobi", 4000, 0.0), ("bf16", "jacobi", 4000, 1e-2),
+             ("fp16", "jacobi", 4000, 0.0)]
     model = None
     if model_path and os.path.exists(model_path):
         from paper_2604_11920_amd import learned
         model = learned.ColumnScaleModel.load(model_path)
-        forms += [("fp64", "learned", 20000), ("bf16", "learned", 4000)]
+        forms += [("fp64", "learned", 20000, 0.0), ("bf16", "learned", 4000, 1e-2)]
     out = {}
     ref = None
     checker = Solver.from_system(s, **fmt)
@@ -165,9 +167,10 @@ def time_to_tol(s, dt, tol, fmt, model_path=None):
         torch.cuda.synchronize()
         infer_s = time.perf_counter() - t0
         d_learned = d_learned.cpu().numpy()
-    for prec, pc, cap in forms:
+    for prec, pc, cap, itol in forms:
         kw = dict(precond="user", col_scale=d_learned) if pc == "learned" else dict(precond=pc)
-        with Solver.from_system(s, precision=prec, refine_sweeps=8, **kw, **fmt) as sol:
+        with Solver.from_system(s, precision=prec, refine_sweeps=8, refine_inner_tol=itol,
+                                **kw, **fmt) as sol:
             dm = torch.empty(s.n, dtype=torch.float64, device="cuda")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -176,7 +179,7 @@ def time_to_tol(s, dt, tol, fmt, model_path=None):
             wall = time.perf_counter() - t0
         r = b - checker.apply(dm)
         eta = checker.apply_t(r).norm().item() / atb
-        key = f"{prec}_{pc}"
+        key = f"{prec}_{pc}" + (f"_inner{itol:g}" if itol else "")
         out[key] = {"seconds": wall, "iters": info["iters"], "sweeps": info["sweeps"],
                     "istop": info["istop"], "eta_fp64": eta}
         if pc == "learned":

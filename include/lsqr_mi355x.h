@@ -114,6 +114,11 @@ typedef struct {
                                 /* depths; needs nz <= 64, nnz < 2^32), 3 = node      */
                                 /* masks (CSC values; per node its row list and one   */
                                 /* bit per (row, depth); needs nz <= 32)              */
+    double refine_inner_tol;    /* mixed precision: relative eta each inner solve     */
+                                /* reaches before the FP64 correction (0 = 1e-3); a   */
+                                /* sweep cannot gain more than the quantisation error */
+                                /* allows (about 1e-2 for BF16), so looser inner      */
+                                /* solves can save restarts' work                     */
 } lsqr_opts;
 
 /* Stop reasons (info.istop):
@@ -149,9 +154,12 @@ typedef struct {
 } lsqr_kstats;
 
 /*
- * lsqr_create — validate G, copy it to the device, build its transpose (CSC, a
- * stable device sort by column so rows stay ascending within a column) and the
- * column scaling.  damp >= 0 and smooth_weight >= 0 (damp > 0 is required by
+ * lsqr_create — validate G (the data block of eq. (6), columns ordered as in
+ * eq. (7)), copy it to the device, build its transpose (CSC, a stable device
+ * sort by column so rows stay ascending within a column), the stored formats
+ * opts.row_format / opts.col_format select (by default the node runs of the
+ * data block for the transposed product, built from the CSR structure on the
+ * host) and the column scaling.  damp >= 0 and smooth_weight >= 0 (damp > 0 is required by
  * the mixed forms, whose refinement folds the FP64 correction into the damping
  * block).  opts may be NULL (FP64, no scaling, default stream, hipMalloc).
  * On success *out owns every derived buffer; free it with lsqr_destroy.
@@ -166,7 +174,8 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
  * exact eta = |Abar^T rbar| / |Abar^T bbar| and g - ghat = (G - Ghat)^T r_G in
  * FP64, then runs the inner LSQR on [Ghat; w L; lambda I] D with right-hand
  * side [r_G; r_L; r_D + (g - ghat)/lambda] (so that its normal-equation
- * residual equals Abar^T rbar exactly) to a relative eta of 1e-3, and adds
+ * residual equals Abar^T rbar exactly) to the relative eta opts.refine_inner_tol
+ * (default 1e-3), and adds
  * the correction; the solve stops when eta <= tol (istop 1), after
  * opts.refine_sweeps sweeps (istop 2), or when a sweep fails to halve eta
  * (istop 4).

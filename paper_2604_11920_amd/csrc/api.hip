@@ -351,6 +351,8 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1, 2 or 3");
     if (o.check_every < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "check_every must be >= 0");
     if (o.refine_sweeps < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "refine_sweeps must be >= 0");
+    if (!(o.refine_inner_tol >= 0.0 && o.refine_inner_tol < 1.0))
+        return fail(nullptr, LSQR_E_INVALID_ARG, "refine_inner_tol must be in [0, 1)");
     if (G->mem == LSQR_MEM_HOST) {
         lsqr_status s = validate_host_csr(G);
         if (s != LSQR_OK) return s;
@@ -368,6 +370,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     c->check_every = o.check_every > 0 ? o.check_every : 32;
     c->check_every += c->check_every & 1;
     c->refine_sweeps = o.refine_sweeps > 0 ? o.refine_sweeps : 5;
+    c->refine_inner_tol = o.refine_inner_tol > 0.0 ? o.refine_inner_tol : 1e-3;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, LSQR_E_DEVICE, "no HIP device available");
@@ -709,7 +712,7 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, int iters, double
     const Problem &P = c->P;
     const int64_t n = P.n;
     Engine &E = c->eng;
-    const double inner_tol = 1e-3;
+    const double inner_tol = c->refine_inner_tol;
     const int gadj = std::min(2048, E.g_adj);
     const bool timing = (c->flags & LSQR_FLAG_TIMING) != 0;   // inner products, all sweeps
     if (timing) c->ks = lsqr_kstats{};

@@ -59,6 +59,7 @@ struct lsqr_ctx {
     uint32_t flags = 0;
     int check_every = 32;
     int refine_sweeps = 5;
+    double refine_inner_tol = 1e-3;
     int fallback_used = 0;
     std::vector<std::pair<void *, size_t>> owned;
     // FP64 operator: CSR, depth runs, CSC, column scale

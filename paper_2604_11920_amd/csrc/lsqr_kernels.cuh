@@ -347,9 +347,21 @@ __global__ __launch_bounds__(kBlock) void k_fwd_runs(FwdArgs a)
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int *cw = colw[wid];
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+#if LSQR_ROW_PREFETCH
+    int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + wid;
+    int64_t vs = 0, rs = 0, re = 0;
+    if (row < a.m) { vs = a.rp[row]; rs = a.run_ptr[row]; re = a.run_ptr[row + 1]; }
+    for (; row < a.m; row += nwaves) {
+        const int64_t nrow = row + nwaves;
+        int64_t nvs = 0, nrs = 0, nre = 0;
+        if (nrow < a.m) { nvs = a.rp[nrow]; nrs = a.run_ptr[nrow]; nre = a.run_ptr[nrow + 1]; }
+        double up = 0.0;
+        if (lane == 0 && a.mode == MODE_ITER) up = (double)((const V *)a.Tprev)[row];
+#else
     for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + wid; row < a.m; row += nwaves) {
         const int64_t vs = a.rp[row];
         const int64_t rs = a.run_ptr[row], re = a.run_ptr[row + 1];
+#endif
         A acc[4] = {0, 0, 0, 0};
         int64_t vpos = vs;               // first entry of the current window
         int64_t base = rs;
@@ -405,7 +417,14 @@ __global__ __launch_bounds__(kBlock) void k_fwd_runs(FwdArgs a)
             md = md_n;
         }
         const A tot = group_sum<64>((acc[0] + acc[1]) + (acc[2] + acc[3]));
+#if LSQR_ROW_PREFETCH
+        if (lane == 0) sq += fwd_row_out_u<V>(a, row, (double)tot, alpha, beta, up);
+        vs = nvs;
+        rs = nrs;
+        re = nre;
+#else
         if (lane == 0) sq += fwd_row_out<V>(a, row, (double)tot, alpha, beta);
+#endif
     }
     sq += fwd_reg_rows<V>(a, alpha, beta);
     const double tot = block_sum(sq, lds);
@@ -632,7 +651,10 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
 // t gathers are already in flight.  Per column, the sum runs over the chunks
 // in order, then over the groups in order, then over the waves in order:
 // fixed, no atomics.
-constexpr int kRunsPerGroup = 8;
+#ifndef LSQR_RUNS_PER_GROUP
+#define LSQR_RUNS_PER_GROUP 8
+#endif
+constexpr int kRunsPerGroup = LSQR_RUNS_PER_GROUP;
 
 template <class M, class V>
 __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)

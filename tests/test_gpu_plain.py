@@ -297,7 +297,9 @@ def test_timing_counters(cfg0):
         ks = sol.kernel_stats()
     assert ks["fwd_launches"] == 20 and ks["adj_launches"] == 20
     assert ks["fwd_ms"] > 0 and ks["adj_ms"] > 0
-    assert ks["fwd_bytes"] > 8 * cfg0.nnz and ks["adj_bytes"] > 12 * cfg0.nnz
+    # at least the stored values and some index bytes; the CSC adds 4 per entry
+    assert ks["fwd_bytes"] > 8 * cfg0.nnz and ks["adj_bytes"] > 8 * cfg0.nnz
+    assert ks["col_format"] != 1 or ks["adj_bytes"] > 12 * cfg0.nnz
     with from_sys(cfg0) as sol:
         dm_g, _, _ = sol.solve(cfg0.dt, 20)
     assert np.array_equal(dm, dm_g)          # event timing does not change the arithmetic
