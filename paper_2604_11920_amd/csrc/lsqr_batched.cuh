@@ -27,16 +27,7 @@ constexpr int kMaxRhs = 32;
 #endif
 constexpr int kBatchUnroll = LSQR_BATCH_UNROLL;
 
-// Pairwise sum of U accumulators in a fixed tree order.
-template <int U, class T>
-__device__ __forceinline__ T tree_sum(const T *v)
-{
-    if constexpr (U == 1) {
-        return v[0];
-    } else {
-        return tree_sum<U / 2>(v) + tree_sum<U - U / 2>(v + U / 2);
-    }
-}
+
 
 struct BArgs {
     // operator (FP32 values)
