@@ -160,10 +160,10 @@ def time_to_tol(s, dt, tol, fmt, model_path=None):
     infer_s = None
     if model is not None:
         p = torch.from_numpy(np.ascontiguousarray(model.params, dtype=np.float32)).cuda()
-        checker.mlp_scale(p, model.mean, model.std)            # warm-up
+        checker.mlp_scale(p, model.mean, model.std, centre=model.centre)   # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        d_learned = checker.mlp_scale(p, model.mean, model.std)
+        d_learned = checker.mlp_scale(p, model.mean, model.std, centre=model.centre)
         torch.cuda.synchronize()
         infer_s = time.perf_counter() - t0
         d_learned = d_learned.cpu().numpy()

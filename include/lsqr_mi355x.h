@@ -301,10 +301,13 @@ lsqr_status lsqr_column_features(lsqr_ctx *ctx, float *feat);
  * lsqr_mlp_scale — inference: d (device [n], FP64) = Jacobi scale times
  * softplus(MLP((feat - mean) / std)), with weights and activations rounded to
  * BF16 (nearest even) and FP32 sums.  params: device [LSQR_MLP_NPARAMS];
- * mean, std: host [6] standardisation of the training features (std > 0).
+ * mean, std: host [6] standardisation of the training features (std > 0);
+ * centre: bit f set = feature f is centred on this system's own mean over its
+ * columns (computed here, FP64, fixed order) instead of mean[f], for
+ * features whose level shifts with the survey size (coverage, norms).
  */
 lsqr_status lsqr_mlp_scale(lsqr_ctx *ctx, const float *params, const float *mean, const float *std,
-                           const float *feat, double *d);
+                           unsigned centre, const float *feat, double *d);
 
 /* Training state (FP32 parameters and Adam moments on the device). */
 typedef struct lsqr_trainer lsqr_trainer;

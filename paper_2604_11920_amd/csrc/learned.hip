@@ -120,18 +120,45 @@ struct Norm {
     float mean[NF], inv_std[NF];
 };
 
-// d_j = djac_j * softplus(z_j), BF16 weights and activations, FP32 sums
+// Means over the system's columns of the features flagged in `mask` (FP64,
+// one workgroup, fixed order: strided per-thread sums, then a fixed tree).
+__global__ __launch_bounds__(256) void k_feature_means(int n, const float *feat, unsigned mask,
+                                                       double *out)
+{
+    __shared__ double acc[NF][256];
+    for (int f = 0; f < NF; ++f) {
+        double sum = 0.0;
+        if ((mask >> f) & 1u)
+            for (int j = threadIdx.x; j < n; j += 256) sum += (double)feat[(int64_t)j * NF + f];
+        acc[f][threadIdx.x] = sum;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int f = 0; f < NF; ++f) acc[f][threadIdx.x] += acc[f][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < NF) out[threadIdx.x] = n > 0 ? acc[threadIdx.x][0] / (double)n : 0.0;
+}
+
+// d_j = djac_j * softplus(z_j), BF16 weights and activations, FP32 sums.
+// Features flagged in `mask` are centred on the system's own means (sysmean).
 __global__ __launch_bounds__(256) void k_mlp_infer(int n, const float *params, Norm nrm,
+                                                   unsigned mask, const double *sysmean,
                                                    const float *feat, const double *djac,
                                                    double *d)
 {
     __shared__ float W[NP];
+    __shared__ float mu[NF];
     for (int i = threadIdx.x; i < NP; i += blockDim.x) W[i] = bf16r(params[i]);
+    if (threadIdx.x < NF)
+        mu[threadIdx.x] = ((mask >> threadIdx.x) & 1u) ? (float)sysmean[threadIdx.x]
+                                                         : nrm.mean[threadIdx.x];
     __syncthreads();
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
         float x[NF];
         for (int f = 0; f < NF; ++f)
-            x[f] = bf16r((feat[(int64_t)j * NF + f] - nrm.mean[f]) * nrm.inv_std[f]);
+            x[f] = bf16r((feat[(int64_t)j * NF + f] - mu[f]) * nrm.inv_std[f]);
         float h1[H];
         for (int k = 0; k < H; ++k) {
             float a = W[OB1 + k];
@@ -290,10 +317,11 @@ lsqr_status lsqr_column_features(lsqr_ctx *c, float *feat)
 }
 
 lsqr_status lsqr_mlp_scale(lsqr_ctx *c, const float *params, const float *mean, const float *std,
-                           const float *feat, double *d)
+                           unsigned centre, const float *feat, double *d)
 {
     if (!c || !params || !mean || !std || !feat || !d)
         return fail(c, LSQR_E_INVALID_ARG, "arguments must not be NULL");
+    if (centre >> NF) return fail(c, LSQR_E_INVALID_ARG, "centre flags only features 0..5");
     Norm nrm;
     for (int f = 0; f < NF; ++f) {
         if (!(std[f] > 0.0f) || !isfinite(std[f]) || !isfinite(mean[f]))
@@ -303,12 +331,15 @@ lsqr_status lsqr_mlp_scale(lsqr_ctx *c, const float *params, const float *mean, 
     }
     DeviceGuard dg(c->device);
     const Problem &P = c->P;
-    double *djac = ctx_alloc<double>(c, P.n);
+    double *djac = ctx_alloc<double>(c, P.n + NF);
     if (!djac) return fail(c, LSQR_E_OOM, "device allocation failed");
+    double *sysmean = djac + P.n;
     launch_jacobi(c->st, P, c->C64, djac);
+    hipLaunchKernelGGL(k_feature_means, dim3(1), dim3(256), 0, c->st, (int)P.n, feat, centre,
+                       sysmean);
     const int g = (int)std::min<int64_t>((P.n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_mlp_infer, dim3(std::max(g, 1)), dim3(256), 0, c->st, (int)P.n, params,
-                       nrm, feat, djac, d);
+                       nrm, centre, (const double *)sysmean, feat, (const double *)djac, d);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->st));
     ctx_release(c, djac);

@@ -35,6 +35,9 @@ from .lsqr import Solver, Trainer
 
 NPARAMS = 4673
 H = 64
+# features centred on each system's own mean (their level shifts with the size
+# of the survey): log column norm, log ray coverage, log neighbour coverage
+CENTRE = (1 << 0) | (1 << 1) | (1 << 5)
 
 
 @dataclasses.dataclass
@@ -43,6 +46,10 @@ class ColumnScaleModel:
     mean: np.ndarray            # float32 [6] feature standardisation
     std: np.ndarray             # float32 [6]
     meta: dict
+
+    @property
+    def centre(self):
+        return int(self.meta.get("centre", 0))
 
     def save(self, path):
         np.savez(path, params=self.params.astype(np.float32), mean=self.mean.astype(np.float32),
@@ -113,10 +120,21 @@ def search_targets(system, tol=1e-6, family="depth", grid=(-1.0, -0.5, 0.5, 1.0)
     return feat, family_log_multiplier(feat, theta, nz), theta, kj, best
 
 
-def train(feats, targets, epochs=60, batch=4096, lr=1e-3, seed=0, log=None):
-    """Fit the MLP on the GPU (the library's FP32 forward/backward and Adam)."""
+def centred(feat, centre=CENTRE):
+    """Features of one system with the flagged columns minus their mean."""
+    f = np.array(feat, dtype=np.float64)
+    for k in range(f.shape[1]):
+        if (centre >> k) & 1:
+            f[:, k] -= f[:, k].mean()
+    return f
+
+
+def train(feats, targets, epochs=60, batch=4096, lr=1e-3, seed=0, centre=CENTRE, log=None):
+    """Fit the MLP on the GPU (the library's FP32 forward/backward and Adam).
+    feats: per-system [n_s, 6] feature blocks (flagged columns are centred per
+    system, as inference does)."""
     import torch
-    X = np.concatenate(feats).astype(np.float64)
+    X = np.concatenate([centred(f, centre) for f in feats]).astype(np.float64)
     T = np.concatenate(targets).astype(np.float64)
     mean = X.mean(axis=0)
     std = X.std(axis=0)
@@ -144,7 +162,8 @@ def train(feats, targets, epochs=60, batch=4096, lr=1e-3, seed=0, log=None):
     base = float(np.mean(T ** 2))       # loss of the untrained (Jacobi) multiplier
     return ColumnScaleModel(params=params, mean=mean.astype(np.float32), std=std.astype(np.float32),
                             meta={"samples": int(N), "epochs": epochs, "batch": batch, "lr": lr,
-                                  "loss_history": hist, "loss_at_jacobi": base})
+                                  "loss_history": hist, "loss_at_jacobi": base,
+                                  "centre": int(centre)})
 
 
 def learned_scale(system, model):
@@ -152,7 +171,7 @@ def learned_scale(system, model):
     import torch
     with Solver.from_system(system) as sol:
         p = torch.from_numpy(np.ascontiguousarray(model.params, dtype=np.float32)).cuda()
-        d = sol.mlp_scale(p, model.mean, model.std)
+        d = sol.mlp_scale(p, model.mean, model.std, centre=model.centre)
         return d.cpu().numpy()
 
 

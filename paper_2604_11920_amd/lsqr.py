@@ -100,7 +100,7 @@ def load():
         "lsqr_set_batch_config": (I, [P, ctypes.POINTER(BatchCfg)]),
         "lsqr_autotune_batched": (I, [P, I, I, ctypes.POINTER(BatchCfg)]),
         "lsqr_column_features": (I, [P, P]),
-        "lsqr_mlp_scale": (I, [P, P, P, P, P, P]),
+        "lsqr_mlp_scale": (I, [P, P, P, P, ctypes.c_uint, P, P]),
         "lsqr_trainer_create": (I, [I, P, P, ctypes.POINTER(P)]),
         "lsqr_trainer_grad": (I, [P, I, P, P, P, ctypes.POINTER(D)]),
         "lsqr_trainer_step": (I, [P, I, P, P, ctypes.c_float, ctypes.POINTER(D)]),
@@ -335,16 +335,17 @@ class Solver:
         self._check(self._lib.lsqr_column_features(self._ctx, _ptr(f)))
         return f
 
-    def mlp_scale(self, params, mean, std, feat=None):
+    def mlp_scale(self, params, mean, std, feat=None, centre=0):
         """Learned column scale (device float64 [n]): Jacobi times softplus of the
-        BF16 MLP on standardised features.  params: float32 device tensor."""
+        BF16 MLP on standardised features.  params: float32 device tensor;
+        centre: bit mask of features centred on this system's own means."""
         if feat is None:
             feat = self.column_features()
         mean = np.ascontiguousarray(mean, dtype=np.float32)
         std = np.ascontiguousarray(std, dtype=np.float32)
         d = self._torch.empty(self.n, dtype=self._torch.float64, device="cuda")
         self._check(self._lib.lsqr_mlp_scale(self._ctx, _ptr(params), _ptr(mean), _ptr(std),
-                                             _ptr(feat), _ptr(d)))
+                                             int(centre), _ptr(feat), _ptr(d)))
         return d
 
     def kernel_stats(self):

@@ -72,8 +72,10 @@ def cmd_fit(args):
     feats, targets, rows = [], [], []
     for path in args.targets:
         z = np.load(path, allow_pickle=False)
-        feats.append(z["feat"].astype(np.float64))
-        targets.append(z["target"].astype(np.float64))
+        # per-system blocks (features are centred per system)
+        cut = np.cumsum(z["sizes"])[:-1]
+        feats += np.split(z["feat"].astype(np.float64), cut)
+        targets += np.split(z["target"].astype(np.float64), cut)
         rows += json.loads(str(z["meta"]))
     model = learned.train(feats, targets, epochs=args.epochs, log=log)
     model.meta["train_systems"] = rows

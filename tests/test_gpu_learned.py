@@ -107,6 +107,29 @@ def test_bf16_inference_matches_reference(cfg0):
     assert np.median(r) < 1e-2 and r.max() < 6e-2
 
 
+def test_bf16_inference_centred_features(cfg0):
+    # flagged features are centred on the system's own means (computed by the
+    # library); the reference centres the oracle's FP64 features the same way
+    s = cfg0
+    theta = mlp.init_params(6) + 0.2 * np.random.default_rng(9).standard_normal(mlp.NPARAMS)
+    feat = mlp.column_features(s.row_ptr, s.col, s.val, s.nx, s.ny, s.nz, s.damp, s.smooth)
+    centre = (1 << 0) | (1 << 1) | (1 << 5)
+    mean, std = feat.mean(0) * 0.5, feat.std(0)
+    std[std == 0] = 1.0
+    mu = mean.copy()
+    for f in range(6):
+        if (centre >> f) & 1:
+            mu[f] = feat[:, f].mean()
+    djac = oracle.Operator.from_system(s).jacobi()
+    ref = djac * mlp.multiplier(theta, (feat - mu) / std)
+    with from_sys(s) as sol:
+        p = torch.from_numpy(theta.astype(np.float32)).cuda()
+        d = sol.mlp_scale(p, mean.astype(np.float32), std.astype(np.float32),
+                          centre=centre).cpu().numpy()
+    r = np.abs(d / ref - 1)
+    assert np.median(r) < 1e-2 and r.max() < 6e-2
+
+
 def test_any_positive_scale_keeps_the_solution_and_bad_scales_fall_back(cfg0):
     s = cfg0
     theta = mlp.init_params(3) + 0.2 * np.random.default_rng(4).standard_normal(mlp.NPARAMS)
