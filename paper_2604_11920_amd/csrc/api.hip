@@ -387,8 +387,8 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     } while (0)
 
     c->rp = ctx_alloc<int64_t>(c, m + 1);
-    c->ci = ctx_alloc<int32_t>(c, nnz + kPadEntries);
-    c->va = ctx_alloc<double>(c, nnz + kPadEntries);
+    c->ci = ctx_alloc<int32_t>(c, nnz);
+    c->va = ctx_alloc<double>(c, nnz);
     c->cp = ctx_alloc<int64_t>(c, n + 1);
     c->ri = ctx_alloc<int32_t>(c, nnz);
     c->cv = ctx_alloc<double>(c, nnz);
@@ -403,10 +403,6 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     c->Pa = ctx_alloc<double>(c, 2048);   // partials of operator launches (<= 2048 workgroups)
     c->Pf = ctx_alloc<double>(c, 2048);
     c->sums = ctx_alloc<double>(c, 4);
-    if (c->ci && c->va) {   // zero padding past nnz (vector loads of the last chunk)
-        (void)hipMemsetAsync(c->ci + nnz, 0, kPadEntries * sizeof(int32_t), c->st);
-        (void)hipMemsetAsync(c->va + nnz, 0, kPadEntries * sizeof(double), c->st);
-    }
     if (!c->rp || !c->ci || !c->va || !c->cp || !c->ri || !c->cv || !c->d || !c->ones ||
         !c->dtbuf || !c->dmbuf || !c->flag || !c->ybuf || !c->Pr || !c->Pa || !c->Pf || !c->sums)
         return bail(LSQR_E_OOM, "device allocation failed");
@@ -553,7 +549,6 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     c->R64.vt = VT_F64; c->R64.rp = c->rp; c->R64.ci = c->ci; c->R64.val = c->va;
     if (c->rmask) { c->R64.rmask = c->rmask; c->R64.rbase = c->rbase; c->R64.rcol = c->rcol; }
     c->R64.lpr = o.lanes_per_row ? o.lanes_per_row : pick_lanes(avg_row);
-    c->R64.vec = LSQR_CSR_VEC;      // vector loads (values and columns are padded)
     if (use_runs) { c->R64.run_ptr = c->run_ptr; c->R64.runs = c->runs; c->R64.roff = c->roff; }
     c->C64.vt = VT_F64; c->C64.cp = c->cp; c->C64.ri = c->ri; c->C64.val = c->cv;
     c->C64.lpc = o.lanes_per_col ? o.lanes_per_col : pick_lanes(avg_col);
@@ -582,10 +577,9 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     set_node_masks(c, C);
     int vec = VT_F64;
     if (o.precision == LSQR_FP32) {
-        c->va32 = ctx_alloc<float>(c, nnz + kPadEntries);
+        c->va32 = ctx_alloc<float>(c, nnz);
         c->cv32 = ctx_alloc<float>(c, nnz);
         if (!c->va32 || !c->cv32) return bail(LSQR_E_OOM, "device allocation failed");
-        CR_TRY(hipMemsetAsync(c->va32 + nnz, 0, kPadEntries * sizeof(float), st));
         launch_convert_f32(st, nnz, c->va, c->va32);
         launch_convert_f32(st, nnz, c->cv, c->cv32);
         R.vt = VT_F32; R.val = c->va32;
@@ -600,7 +594,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     } else if (mixed) {
         const int vt = o.precision == LSQR_BF16 ? VT_BF16 : VT_F16;
         c->sigma = ctx_alloc<float>(c, std::max<int64_t>(m, 1));
-        c->qrow = ctx_alloc<uint16_t>(c, nnz + kPadEntries);
+        c->qrow = ctx_alloc<uint16_t>(c, nnz);
         c->qcol = ctx_alloc<uint16_t>(c, nnz);
         c->xbuf = ctx_alloc<double>(c, n);
         c->rbar = ctx_alloc<double>(c, mb);
@@ -611,7 +605,6 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         if (!c->sigma || !c->qrow || !c->qcol || !c->xbuf || !c->rbar || !c->rs || !c->gbuf ||
             !c->ghat || !c->fbuf)
             return bail(LSQR_E_OOM, "device allocation failed");
-        CR_TRY(hipMemsetAsync(c->qrow + nnz, 0, kPadEntries * sizeof(uint16_t), st));
         launch_row_scales(st, m, c->rp, c->va, vt, c->sigma);
         launch_quantise_rows(st, m, c->rp, c->va, c->sigma, vt, c->qrow);
         launch_quantise_cols(st, nnz, c->ri, c->cv, c->sigma, vt, c->qcol);

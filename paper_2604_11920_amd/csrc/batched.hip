@@ -66,10 +66,9 @@ lsqr_status ensure_fp32(lsqr_ctx *c, hipStream_t st)
 {
     if (c->va32 && c->cv32) return LSQR_OK;
     const int64_t nnz = c->P.nnz;
-    c->va32 = ctx_alloc<float>(c, nnz + kPadEntries);
+    c->va32 = ctx_alloc<float>(c, nnz);
     c->cv32 = ctx_alloc<float>(c, nnz);
     if (!c->va32 || !c->cv32) return fail(c, LSQR_E_OOM, "device allocation failed");
-    HIP_TRY(c, hipMemsetAsync(c->va32 + nnz, 0, kPadEntries * sizeof(float), st));
     launch_convert_f32(st, nnz, c->va, c->va32);
     launch_convert_f32(st, nnz, c->cv, c->cv32);
     HIP_TRY(c, hipGetLastError());

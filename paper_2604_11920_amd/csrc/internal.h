@@ -57,15 +57,6 @@ struct Problem {
 };
 
 // Data rows of the forward product.
-// Zeroed entries allocated past nnz in the CSR value and column arrays, so a
-// vector load of the chunk holding the last entry stays in bounds.
-constexpr int64_t kPadEntries = 8;
-
-// 1: long CSR rows use the vector-load forward kernel.
-#ifndef LSQR_CSR_VEC
-#define LSQR_CSR_VEC 0
-#endif
-
 struct RowFmt {
     int vt = VT_F64;
     const int64_t *rp = nullptr;       // [m+1] value offsets
@@ -76,8 +67,6 @@ struct RowFmt {
     const void *val = nullptr;
     const float *sigma = nullptr;      // [m] row scales (quantised values) or nullptr
     int lpr = 64;                      // lanes per row (plain CSR)
-    int vec = 0;                       // 1: vector loads of 16 value bytes per lane
-                                       // (values and columns padded, see kPadEntries)
     // run masks (used instead of ci when rmask is set): bit p of rmask marks
     // entry p as the start of a run of consecutive columns; rbase[w] = runs
     // starting before word w; column of entry p of row i in run r =

@@ -68,7 +68,7 @@ template <class A> __device__ __forceinline__ A ld_nt(const fp16_t *p)
 // 1: the CSR / CSC products load the next row's (column's) bounds and the
 // current row's u term before the current row's entries.
 #ifndef LSQR_ROW_PREFETCH
-#define LSQR_ROW_PREFETCH 0
+#define LSQR_ROW_PREFETCH 1
 #endif
 
 // ------------------------------------------------------------ reductions --
@@ -327,108 +327,6 @@ __global__ __launch_bounds__(kBlock) void k_fwd_csr(FwdArgs a)
 #else
         if (lane == 0) sq += fwd_row_out<V>(a, row, (double)acc, alpha, beta);
 #endif
-    }
-    sq += fwd_reg_rows<V>(a, alpha, beta);
-    const double tot = block_sum(sq, lds);
-    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
-}
-
-// Vector loads of VEC consecutive stored entries (aligned: the value and
-// column arrays carry kPadEntries zeroed entries past nnz, and start on a
-// 256-byte boundary).
-template <int N> using vint_t = int __attribute__((ext_vector_type(N)));
-template <int N> using vdbl_t = double __attribute__((ext_vector_type(N)));
-template <int N> using vflt_t = float __attribute__((ext_vector_type(N)));
-template <int N> using vu16_t = unsigned short __attribute__((ext_vector_type(N)));
-
-template <class A, int VEC>
-__device__ __forceinline__ void ld_vals(const double *p, A *out)
-{
-    const vdbl_t<VEC> v = __builtin_nontemporal_load((const vdbl_t<VEC> *)p);
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) out[i] = (A)v[i];
-}
-template <class A, int VEC>
-__device__ __forceinline__ void ld_vals(const float *p, A *out)
-{
-    const vflt_t<VEC> v = __builtin_nontemporal_load((const vflt_t<VEC> *)p);
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) out[i] = (A)v[i];
-}
-template <class A, int VEC>
-__device__ __forceinline__ void ld_vals(const bf16_t *p, A *out)
-{
-    const vu16_t<VEC> v = __builtin_nontemporal_load((const vu16_t<VEC> *)p);
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) out[i] = (A)__uint_as_float((uint32_t)v[i] << 16);
-}
-template <class A, int VEC>
-__device__ __forceinline__ void ld_vals(const fp16_t *p, A *out)
-{
-    const vu16_t<VEC> v = __builtin_nontemporal_load((const vu16_t<VEC> *)p);
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-        const uint16_t b = v[i];
-        _Float16 h;
-        __builtin_memcpy(&h, &b, 2);
-        out[i] = (A)(float)h;
-    }
-}
-
-// Entries per vector load for a stored value type: 16 bytes of values.
-template <class M> struct VecOf { static constexpr int value = 16 / (int)sizeof(M); };
-
-// Plain CSR rows, one wave per row, VEC consecutive entries per lane per load
-// (16-byte value loads, 4 VEC-byte column loads).  The row is walked in
-// VEC-aligned chunks; entries of a chunk outside the row (the neighbouring
-// rows' ends, or the zero padding past nnz) are multiplied by zero, so the
-// loads need no branches.  U chunks per lane are in flight.
-template <class M, class V, int U>
-__global__ __launch_bounds__(kBlock) void k_fwd_csrv(FwdArgs a)
-{
-    using A = typename AccOf<V>::type;
-    constexpr int VEC = VecOf<M>::value;
-    __shared__ double lds[4];
-    double alpha, beta;
-    if (!fwd_prologue(a, alpha, beta, lds)) return;
-    const M *va = (const M *)a.va;
-    const V *z = (const V *)a.z;
-    double sq = 0.0;
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); row < a.m;
-         row += nwaves) {
-        const int64_t s = a.rp[row], e = a.rp[row + 1];
-        const int64_t c0 = s / VEC, c1 = (e + VEC - 1) / VEC;
-        A acc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] = 0;
-        for (int64_t c = c0 + lane; c < c1; c += 64 * U) {
-            A v[U][VEC];
-            vint_t<VEC> col[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t cu = c + u * 64;
-                if (cu < c1) {
-                    ld_vals<A, VEC>(va + cu * VEC, v[u]);
-                    col[u] = __builtin_nontemporal_load((const vint_t<VEC> *)(a.ci + cu * VEC));
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) {
-                        const int64_t p = cu * VEC + i;
-                        if (p < s || p >= e) v[u][i] = 0;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) { v[u][i] = 0; col[u][i] = 0; }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) acc[u] = fma(v[u][i], (A)z[col[u][i]], acc[u]);
-        }
-        const A tot = group_sum<64>(tree_sum<U>(acc));
-        if (lane == 0) sq += fwd_row_out<V>(a, row, (double)tot, alpha, beta);
     }
     sq += fwd_reg_rows<V>(a, alpha, beta);
     const double tot = block_sum(sq, lds);
@@ -765,7 +663,7 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
 // in order, then over the groups in order, then over the waves in order:
 // fixed, no atomics.
 #ifndef LSQR_RUNS_PER_GROUP
-#define LSQR_RUNS_PER_GROUP 8
+#define LSQR_RUNS_PER_GROUP 12
 #endif
 constexpr int kRunsPerGroup = LSQR_RUNS_PER_GROUP;
 
@@ -825,15 +723,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
                 row_n = __builtin_nontemporal_load(a.nrow + nb + lane);
             }
             // this chunk's values: run grp + u ngr of the chunk for lane (grp, iz)
+            // loads are unconditional (an idle slot reads the chunk's first
+            // value, always in bounds) and masked afterwards, so no branch
+            // separates them and all are in flight before the first use
             A v[kRunsPerGroup];
 #pragma unroll
             for (int u = 0; u < kRunsPerGroup; ++u) {
                 const int r = grp + u * ngr;
                 const uint32_t p = __shfl(pk, r & 63);
                 const int e = iz - (int)((p >> 8) & 255u);
-                v[u] = 0;
-                if (live && r < nr && (unsigned)e < (p & 255u))
-                    v[u] = ld_nt<A>(nv + vb + (p >> 16) + e);
+                const bool in = live && r < nr && (unsigned)e < (p & 255u);
+                const A x = ld_nt<A>(nv + (in ? vb + (int64_t)(p >> 16) + e : vb));
+                v[u] = in ? x : (A)0;
             }
             A tr_n = 0;
             if (lane < nn) tr_n = (A)Tg[row_n];
@@ -1056,11 +957,6 @@ static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArg
     }
     if (R.run_ptr) {
         hipLaunchKernelGGL((k_fwd_runs<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
-        return;
-    }
-    if (R.vec && R.lpr == 64) {
-        hipLaunchKernelGGL((k_fwd_csrv<M, V, (VecOf<M>::value >= 8 ? 1 : 2)>), dim3(grid),
-                           dim3(kBlock), 0, st, a);
         return;
     }
     switch (R.lpr) {
