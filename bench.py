@@ -143,13 +143,13 @@ def time_to_tol(s, dt, tol, fmt, model_path=None):
     from paper_2604_11920_amd import Solver
     # (precision, scaling, iteration cap, inner tolerance of the refinement)
     forms = [("fp64", "none", 20000, 0.0), ("fp64", "jacobi", 20000, 0.0),
-             ("bf16", "jacobi", 4000, 0.0), ("bf16", "jacobi", 4000, 1e-2),
+             ("bf16", "jacobi", 4000, 0.0), ("bf16", "jacobi", 4000, 1e-3),
              ("fp16", "jacobi", 4000, 0.0)]
     model = None
     if model_path and os.path.exists(model_path):
         from paper_2604_11920_amd import learned
         model = learned.ColumnScaleModel.load(model_path)
-        forms += [("fp64", "learned", 20000, 0.0), ("bf16", "learned", 4000, 1e-2)]
+        forms += [("fp64", "learned", 20000, 0.0), ("bf16", "learned", 4000, 0.0)]
     out = {}
     ref = None
     checker = Solver.from_system(s, **fmt)

@@ -115,10 +115,10 @@ typedef struct {
                                 /* masks (CSC values; per node its row list and one   */
                                 /* bit per (row, depth); needs nz <= 32)              */
     double refine_inner_tol;    /* mixed precision: relative eta each inner solve     */
-                                /* reaches before the FP64 correction (0 = 1e-3); a   */
+                                /* reaches before the FP64 correction (0 = 1e-2); a   */
                                 /* sweep cannot gain more than the quantisation error */
-                                /* allows (about 1e-2 for BF16), so looser inner      */
-                                /* solves can save restarts' work                     */
+                                /* allows (about 1e-2 for BF16), so tighter inner     */
+                                /* solves mostly add restarted work                   */
 } lsqr_opts;
 
 /* Stop reasons (info.istop):
@@ -175,7 +175,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
  * FP64, then runs the inner LSQR on [Ghat; w L; lambda I] D with right-hand
  * side [r_G; r_L; r_D + (g - ghat)/lambda] (so that its normal-equation
  * residual equals Abar^T rbar exactly) to the relative eta opts.refine_inner_tol
- * (default 1e-3), and adds
+ * (default 1e-2), and adds
  * the correction; the solve stops when eta <= tol (istop 1), after
  * opts.refine_sweeps sweeps (istop 2), or when a sweep fails to halve eta
  * (istop 4).

@@ -370,7 +370,9 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     c->check_every = o.check_every > 0 ? o.check_every : 32;
     c->check_every += c->check_every & 1;
     c->refine_sweeps = o.refine_sweeps > 0 ? o.refine_sweeps : 5;
-    c->refine_inner_tol = o.refine_inner_tol > 0.0 ? o.refine_inner_tol : 1e-3;
+    // an inner solve need not go far below the per-sweep gain the quantisation
+    // allows (~1e-2 for BF16, ~1e-3 for FP16 on the tomography systems)
+    c->refine_inner_tol = o.refine_inner_tol > 0.0 ? o.refine_inner_tol : 1e-2;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, LSQR_E_DEVICE, "no HIP device available");
