@@ -168,6 +168,13 @@ def laplacian_apply(nx, ny, nz, x, nthreads=1):
     return y
 
 
+def lsmr(sys, iters, tol=0.0, d=None, nthreads=1, dt=None):
+    """Convenience: explicit-block LSMR (oracle/lsmr.py) on a generated system."""
+    from .lsmr import lsmr as _lsmr
+    op = Operator.from_system(sys, d=d, nthreads=nthreads)
+    return _lsmr(op, sys.dt if dt is None else dt, iters, tol)
+
+
 def lsqr(sys, iters, tol=0.0, d=None, compensated=False, nthreads=1, ncap=0, dt=None):
     """Convenience: explicit-block LSQR on a generated system."""
     op = Operator.from_system(sys, d=d, compensated=compensated, nthreads=nthreads)
