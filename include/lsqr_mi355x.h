@@ -119,6 +119,15 @@ typedef struct {
                                 /* sweep cannot gain more than the quantisation error */
                                 /* allows (about 1e-2 for BF16), so tighter inner     */
                                 /* solves mostly add restarted work                   */
+    int method;                 /* 0 = LSQR (Paige & Saunders 1982); 1 = LSMR (Fong &  */
+                                /* Saunders 2011, the solver the paper's "Solver for  */
+                                /* the Large-scale Linear System" section says        */
+                                /* DSurfTomo adopts): same products, MINRES on the    */
+                                /* normal equations, |r| and |A^T r| both monotone.   */
+                                /* LSMR's eta is the scaled-variable normal residual  */
+                                /* |A_D^T r| / |A_D^T bbar| (equal to the original    */
+                                /* variables' for D = I); the batched entry point     */
+                                /* runs LSQR                                          */
 } lsqr_opts;
 
 /* Stop reasons (info.istop):

@@ -115,6 +115,10 @@ lsqr_status setup_engine(lsqr_ctx *c, Engine &E, int vec, const RowFmt &R, const
     E.vzero = ctx_alloc_bytes(c, n * vs);
     E.w = ctx_alloc<double>(c, n);
     E.y = ctx_alloc<double>(c, n);
+    if (c->method == 1) {
+        E.hbar = ctx_alloc<double>(c, n);
+        if (!E.hbar) return fail(c, LSQR_E_OOM, "device allocation failed");
+    }
     E.P1 = ctx_alloc<double>(c, E.g_fwd);
     E.P2 = ctx_alloc<double>(c, E.g_adj);
     E.P3 = ctx_alloc<double>(c, E.g_upd);
@@ -153,7 +157,7 @@ void launch_iteration(lsqr_ctx *c, Engine &E, hipStream_t st, int p, double tol,
                E.g_fwd, E.S, E.ctl, p, MODE_ITER, 0);
     if (timing) (void)hipEventRecord(c->ev[4 * slot + 3], st);
     launch_update(st, P, E.g_upd, E.vec, c->d, E.q, E.v, E.w, E.y, E.z, E.P3, E.P2, E.g_adj, E.S,
-                  E.ctl, p, MODE_ITER);
+                  E.ctl, p, MODE_ITER, E.hbar);
 }
 
 lsqr_status build_graph(lsqr_ctx *c, Engine &E, int iters, double tol)
@@ -201,7 +205,7 @@ lsqr_status engine_solve(lsqr_ctx *c, Engine &E, const double *rhs, int full, in
     launch_adj(st, P, E.g_adj, E.vec, E.C, c->d, E.T[0], E.Ts ? E.Ts : E.T[0], E.vzero, E.q, E.P2,
                E.P1, E.g_fwd, E.S, E.ctl, 0, MODE_INIT, 0);
     launch_update(st, P, E.g_upd, E.vec, c->d, E.q, E.v, E.w, E.y, E.z, E.P3, E.P2, E.g_adj, E.S,
-                  E.ctl, 0, MODE_INIT);
+                  E.ctl, 0, MODE_INIT, E.hbar);
     HIP_TRY(c, hipGetLastError());
     // iterations: blocks of an even number of iterations replayed as one graph
     // (parity returns to 0 after each block); with tol > 0 the host reads the
@@ -349,6 +353,8 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         return fail(nullptr, LSQR_E_INVALID_ARG, "row_format must be 0, 1, 2 or 3");
     if (o.col_format < 0 || o.col_format > 3)
         return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1, 2 or 3");
+    if (o.method < 0 || o.method > 1)
+        return fail(nullptr, LSQR_E_INVALID_ARG, "method must be 0 (LSQR) or 1 (LSMR)");
     if (o.check_every < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "check_every must be >= 0");
     if (o.refine_sweeps < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "refine_sweeps must be >= 0");
     if (!(o.refine_inner_tol >= 0.0 && o.refine_inner_tol < 1.0))
@@ -367,6 +373,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     c->al.alloc = o.alloc; c->al.dealloc = o.dealloc; c->al.user = o.alloc_user;
     c->st = (hipStream_t)o.stream;
     c->prec = o.precision; c->precond = o.precond; c->flags = o.flags;
+    c->method = o.method;
     c->check_every = o.check_every > 0 ? o.check_every : 32;
     c->check_every += c->check_every & 1;
     c->refine_sweeps = o.refine_sweeps > 0 ? o.refine_sweeps : 5;

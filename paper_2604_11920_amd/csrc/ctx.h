@@ -21,6 +21,7 @@ struct Engine {
     void *Ts = nullptr;            // sigma * t for the quantised forms
     void *q = nullptr, *v = nullptr, *z = nullptr, *vzero = nullptr;
     double *w = nullptr, *y = nullptr;
+    double *hbar = nullptr;        // LSMR only (w then holds h)
     double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
     double *S = nullptr;
     int64_t s_rows = 0;
@@ -58,6 +59,7 @@ struct lsqr_ctx {
     lsqr_precond precond = LSQR_PRECOND_NONE;
     uint32_t flags = 0;
     int check_every = 32;
+    int method = 0;                 // 0 LSQR, 1 LSMR
     int refine_sweeps = 5;
     double refine_inner_tol = 1e-3;
     int fallback_used = 0;

@@ -12,7 +12,7 @@
 namespace lsqr {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
-constexpr int kStateWords = 16;      // doubles per per-iteration state row
+constexpr int kStateWords = 32;      // doubles per per-iteration state row
 
 // Per-iteration state row S[k] (doubles), written by the update kernel of
 // iteration k (k = 0 is the start) and read by the next iteration.
@@ -29,7 +29,20 @@ enum StateField {
     S_PSI = 9,      // |A_D^T rbar_k| estimate
     S_ETA = 10,     // psi_k |D^-1 v_{k+1}| / |Abar^T bbar|
     S_VNORM = 11,   // |D^-1 v_{k+1}|
-    S_ARNORM0 = 12, // |Abar^T bbar| (row 0 only)
+    S_ARNORM0 = 12, // |Abar^T bbar| (row 0 only; LSMR: alpha_1 beta_1)
+    // LSMR (Fong & Saunders): the second rotation chain and the |r| chain;
+    // S_PHIBAR holds |r_k|, S_PSI |A_D^T r_k| = |zetabar_{k+1}|
+    S_ALPHABAR = 13,
+    S_ZETABAR = 14,
+    S_CBAR = 15,
+    S_SBAR = 16,
+    S_ZETA = 17,
+    S_BETADD = 18,
+    S_BETAD = 19,
+    S_RHODOLD = 20,
+    S_TAUTILDE = 21,
+    S_THETATILDE = 22,
+    S_METHOD = 23,  // row 0: 0 LSQR, 1 LSMR (written by the start step)
 };
 
 // Control words (int32) on the device.
@@ -116,9 +129,11 @@ void launch_adj(hipStream_t st, const Problem &P, int grid, int vec, const ColFm
                 const double *d, const void *T, const void *Tg, const void *v, void *q,
                 double *part_out, const double *part_t, int np_t, double *S, int *ctl,
                 int parity, int mode, int data_only);
+// hbar != nullptr selects the LSMR step (w then holds LSMR's h).
 void launch_update(hipStream_t st, const Problem &P, int grid, int vec, const double *d,
                    const void *q, void *v, double *w, double *y, void *z, double *part_out,
-                   const double *part_q, int np_q, double *S, int *ctl, int parity, int mode);
+                   const double *part_q, int np_q, double *S, int *ctl, int parity, int mode,
+                   double *hbar);
 
 // Helpers (kernels_common.hip).
 void launch_finalize(hipStream_t st, const Problem &P, int grid, const double *d,

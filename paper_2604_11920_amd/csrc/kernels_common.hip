@@ -23,7 +23,7 @@ hipError_t init_launch(hipStream_t, const Problem &, int, const double *, int, v
 template <class V>
 hipError_t update_launch(hipStream_t, const Problem &, int, const double *, const void *, void *,
                          double *, double *, void *, double *, const double *, int, double *,
-                         int *, int, int);
+                         int *, int, int, double *);
 
 size_t vt_size(int vt)
 {
@@ -66,12 +66,15 @@ void launch_adj(hipStream_t st, const Problem &P, int grid, int vec, const ColFm
 
 void launch_update(hipStream_t st, const Problem &P, int grid, int vec, const double *d,
                    const void *q, void *v, double *w, double *y, void *z, double *part_out,
-                   const double *part_q, int np_q, double *S, int *ctl, int parity, int mode)
+                   const double *part_q, int np_q, double *S, int *ctl, int parity, int mode,
+                   double *hbar)
 {
     if (vec == VT_F64)
-        update_launch<double>(st, P, grid, d, q, v, w, y, z, part_out, part_q, np_q, S, ctl, parity, mode);
+        update_launch<double>(st, P, grid, d, q, v, w, y, z, part_out, part_q, np_q, S, ctl, parity,
+                              mode, hbar);
     else
-        update_launch<float>(st, P, grid, d, q, v, w, y, z, part_out, part_q, np_q, S, ctl, parity, mode);
+        update_launch<float>(st, P, grid, d, q, v, w, y, z, part_out, part_q, np_q, S, ctl, parity,
+                             mode, hbar);
 }
 
 // --------------------------------------------------------------- finalize --
@@ -88,9 +91,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int n, const double *d, con
     if (!stopped && kk >= 1) {
         const double vn = sqrt(reduce_partials(part_v, np_v, lds));
         double *Sk = S + (int64_t)kk * kStateWords;
-        // |Abar^T bbar| was stored by the forward kernel of iteration 1 (from |D^-1 v_1|)
+        // |Abar^T bbar| was stored by the forward kernel of iteration 1 (from
+        // |D^-1 v_1|); LSMR: the scaled normal residual |zetabar| / (alpha_1 beta_1)
         const double arnorm0 = S[S_ARNORM0];
-        const double eta = Sk[S_PSI] * vn / arnorm0;
+        const double eta = S[S_METHOD] != 0.0 ? Sk[S_PSI] / arnorm0 : Sk[S_PSI] * vn / arnorm0;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             Sk[S_ETA] = eta;
             Sk[S_VNORM] = vn;

@@ -210,11 +210,14 @@ __device__ __forceinline__ bool fwd_prologue(const FwdArgs &a, double &alpha, do
     double arnorm0, eta = 1.0;
     bool stop = false;
     int istop = 2;
+    // LSMR keeps |A_D^T r_k| = |zetabar_{k+1}| itself: eta in the scaled
+    // variables, against alpha_1 beta_1 (set by its start step)
+    const bool lsmr = a.S[S_METHOD] != 0.0;
     if (k == 1) {
-        arnorm0 = (a.S[S_ALPHA] * a.S[S_BETA]) * vn;
+        arnorm0 = lsmr ? a.S[S_ARNORM0] : (a.S[S_ALPHA] * a.S[S_BETA]) * vn;
     } else {
         arnorm0 = a.S[S_ARNORM0];
-        eta = Sp[S_PSI] * vn / arnorm0;
+        eta = lsmr ? Sp[S_PSI] / arnorm0 : Sp[S_PSI] * vn / arnorm0;
         if (a.tol > 0.0 && eta <= a.tol) { stop = true; istop = 1; }
         else if (alpha == 0.0 || beta == 0.0) { stop = true; istop = 3; }
     }
@@ -851,6 +854,7 @@ struct UpdArgs {
     int *ctl;
     int parity;
     int mode;
+    double *hbar;            // LSMR only: hbar [n] (w holds h)
 };
 
 template <class V>
@@ -889,7 +893,7 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdArgs a)
         if (lead) {
             double *S0 = a.S;
             S0[S_ALPHA] = alpha; S0[S_RHOBAR] = alpha; S0[S_PHIBAR] = beta;
-            S0[S_PSI] = alpha * beta; S0[S_ETA] = 1.0;
+            S0[S_PSI] = alpha * beta; S0[S_ETA] = 1.0; S0[S_METHOD] = 0.0;
         }
         return;
     }
@@ -937,6 +941,126 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdArgs a)
     if (lead) {
         Sk[S_ALPHA] = alpha; Sk[S_RHOBAR] = rhobar_n; Sk[S_PHIBAR] = phibar_n; Sk[S_RHO] = rho;
         Sk[S_C] = c; Sk[S_S] = s; Sk[S_THETA] = theta; Sk[S_PHI] = phi; Sk[S_PSI] = psi;
+        a.ctl[C_ITERS] = k;
+        a.ctl[C_CNT0 + (1 - a.parity)] = k + 1;
+    }
+}
+
+// LSMR step (Fong & Saunders 2011): after the bidiagonalisation shared with
+// LSQR (forward and transposed kernels), the rotation P_k on
+// [alphabar_k; beta_{k+1}], the rotation Pbar_k on [cbar_{k-1} rho_k;
+// theta_{k+1}], the h / hbar / y sweep, and the third rotation chain that
+// carries |r_k|.  Every workgroup computes the scalars identically (FP64, no
+// contraction) from the previous state row; w holds h.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_update_lsmr(UpdArgs a)
+{
+#pragma clang fp contract(off)
+    __shared__ double lds[4];
+    if (a.ctl[C_STOP]) return;
+    const V *q = (const V *)a.q;
+    V *v = (V *)a.v;
+    V *z = (V *)a.z;
+    double *h = a.w, *hbar = a.hbar;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (a.mode == MODE_INIT) {
+        const double beta = a.S[S_BETA];
+        const double alpha = sqrt(reduce_partials(a.part_q, a.np_q, lds));
+        if (!isfinite(alpha) || !isfinite(beta)) {
+            if (lead) { a.ctl[C_ERR] = 1; a.ctl[C_ISTOP] = -3; a.ctl[C_STOP] = 1; }
+            return;
+        }
+        if (alpha == 0.0) {
+            if (lead) { a.S[S_ALPHA] = 0.0; a.ctl[C_ISTOP] = 0; a.ctl[C_STOP] = 1; }
+            return;
+        }
+        double sq = 0.0;
+        for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
+            const V vv = (V)((double)q[j] / alpha);
+            v[j] = vv;
+            h[j] = (double)vv;
+            hbar[j] = 0.0;
+            z[j] = (V)(a.d[j] * (double)vv);
+            const double dv = (double)vv / a.d[j];
+            sq += dv * dv;
+        }
+        const double tot = block_sum(sq, lds);
+        if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+        if (lead) {
+            double *S0 = a.S;
+            S0[S_ALPHA] = alpha; S0[S_ALPHABAR] = alpha; S0[S_ZETABAR] = alpha * beta;
+            S0[S_RHO] = 1.0; S0[S_RHOBAR] = 1.0; S0[S_CBAR] = 1.0; S0[S_SBAR] = 0.0;
+            S0[S_ZETA] = 0.0; S0[S_BETADD] = beta; S0[S_BETAD] = 0.0; S0[S_RHODOLD] = 1.0;
+            S0[S_TAUTILDE] = 0.0; S0[S_THETATILDE] = 0.0;
+            S0[S_PHIBAR] = beta; S0[S_PSI] = alpha * beta; S0[S_ETA] = 1.0;
+            S0[S_ARNORM0] = alpha * beta; S0[S_METHOD] = 1.0;
+        }
+        return;
+    }
+    const int k = a.ctl[C_CNT0 + a.parity];
+    if (k > a.ctl[C_KMAX]) return;
+    const double *Sp = a.S + (int64_t)(k - 1) * kStateWords;
+    double *Sk = a.S + (int64_t)k * kStateWords;
+    const double beta = Sk[S_BETA];
+    const double alpha = beta > 0.0 ? sqrt(reduce_partials(a.part_q, a.np_q, lds)) : 0.0;
+    // rotation P_k
+    const double rhoold = Sp[S_RHO], alphabar = Sp[S_ALPHABAR];
+    const double rho = sqrt(alphabar * alphabar + beta * beta);
+    const double c = alphabar / rho, s = beta / rho;
+    const double thetanew = s * alpha, alphabar_n = c * alpha;
+    // rotation Pbar_k
+    const double rhobarold = Sp[S_RHOBAR], zetaold = Sp[S_ZETA], zetabar = Sp[S_ZETABAR];
+    const double thetabar = Sp[S_SBAR] * rho, rhotemp = Sp[S_CBAR] * rho;
+    const double rhobar = sqrt(rhotemp * rhotemp + thetanew * thetanew);
+    const double cbar = rhotemp / rhobar, sbar = thetanew / rhobar;
+    const double zeta = cbar * zetabar, zetabar_n = -sbar * zetabar;
+    const double c1 = thetabar * rho / (rhoold * rhobarold);
+    const double c2 = zeta / (rho * rhobar);
+    const double c3 = thetanew / rho;
+    // |r_k| chain
+    const double betahat = c * Sp[S_BETADD], betadd = -s * Sp[S_BETADD];
+    const double thetatildeold = Sp[S_THETATILDE], rhodoldp = Sp[S_RHODOLD];
+    const double rhotildeold = sqrt(rhodoldp * rhodoldp + thetabar * thetabar);
+    const double ctildeold = rhodoldp / rhotildeold, stildeold = thetabar / rhotildeold;
+    const double thetatilde = stildeold * rhobar, rhodold = ctildeold * rhobar;
+    const double betad = -stildeold * Sp[S_BETAD] + ctildeold * betahat;
+    const double tautilde = (zetaold - thetatildeold * Sp[S_TAUTILDE]) / rhotildeold;
+    const double taud = (zeta - thetatilde * tautilde) / rhodold;
+    const double normr = sqrt((betad - taud) * (betad - taud) + betadd * betadd);
+    const double normar = fabs(zetabar_n);
+    if (!isfinite(alpha) || !isfinite(rho) || !isfinite(rhobar) || !isfinite(zeta) ||
+        !isfinite(normr)) {
+        if (lead) { a.ctl[C_ERR] = 1; a.ctl[C_ISTOP] = -3; a.ctl[C_STOP] = 1; }
+        return;
+    }
+    double sq = 0.0;
+    const bool newv = alpha > 0.0;
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
+        double vj;
+        if (newv) {
+            const V vv = (V)((double)q[j] / alpha);
+            v[j] = vv;
+            vj = (double)vv;
+        } else {
+            vj = (double)v[j];
+        }
+        const double hb = h[j] - c1 * hbar[j];
+        hbar[j] = hb;
+        a.y[j] = a.y[j] + c2 * hb;
+        h[j] = vj - c3 * h[j];
+        z[j] = (V)(a.d[j] * vj);
+        const double dv = vj / a.d[j];
+        sq += dv * dv;
+    }
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+    if (lead) {
+        Sk[S_ALPHA] = alpha; Sk[S_ALPHABAR] = alphabar_n; Sk[S_RHO] = rho; Sk[S_RHOBAR] = rhobar;
+        Sk[S_CBAR] = cbar; Sk[S_SBAR] = sbar; Sk[S_ZETA] = zeta; Sk[S_ZETABAR] = zetabar_n;
+        Sk[S_BETADD] = betadd; Sk[S_BETAD] = betad; Sk[S_RHODOLD] = rhodold;
+        Sk[S_TAUTILDE] = tautilde; Sk[S_THETATILDE] = thetatilde;
+        Sk[S_C] = c; Sk[S_S] = s; Sk[S_THETA] = thetanew;
+        Sk[S_PHIBAR] = normr; Sk[S_PSI] = normar;
         a.ctl[C_ITERS] = k;
         a.ctl[C_CNT0 + (1 - a.parity)] = k + 1;
     }
@@ -1062,10 +1186,12 @@ hipError_t init_launch(hipStream_t st, const Problem &P, int grid, const double 
 template <class V>
 hipError_t update_launch(hipStream_t st, const Problem &P, int grid, const double *d,
                          const void *q, void *v, double *w, double *y, void *z, double *part_out,
-                         const double *part_q, int np_q, double *S, int *ctl, int parity, int mode)
+                         const double *part_q, int np_q, double *S, int *ctl, int parity, int mode,
+                         double *hbar)
 {
-    UpdArgs a{(int)P.n, d, q, v, w, y, z, part_out, part_q, np_q, S, ctl, parity, mode};
-    hipLaunchKernelGGL((k_update<V>), dim3(grid), dim3(kBlock), 0, st, a);
+    UpdArgs a{(int)P.n, d, q, v, w, y, z, part_out, part_q, np_q, S, ctl, parity, mode, hbar};
+    if (hbar) hipLaunchKernelGGL((k_update_lsmr<V>), dim3(grid), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_update<V>), dim3(grid), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
@@ -1083,6 +1209,6 @@ hipError_t update_launch(hipStream_t st, const Problem &P, int grid, const doubl
     template hipError_t update_launch<V>(hipStream_t, const Problem &, int, const double *,      \
                                          const void *, void *, double *, double *, void *,       \
                                          double *, const double *, int, double *, int *, int,    \
-                                         int);
+                                         int, double *);
 
 }  // namespace lsqr

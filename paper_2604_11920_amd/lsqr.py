@@ -48,7 +48,8 @@ class Opts(ctypes.Structure):
                 ("alloc", _ALLOC_FN), ("dealloc", _FREE_FN), ("alloc_user", ctypes.c_void_p),
                 ("flags", ctypes.c_uint32), ("lanes_per_row", ctypes.c_int),
                 ("lanes_per_col", ctypes.c_int), ("row_format", ctypes.c_int),
-                ("col_format", ctypes.c_int), ("refine_inner_tol", ctypes.c_double)]
+                ("col_format", ctypes.c_int), ("refine_inner_tol", ctypes.c_double),
+                ("method", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -145,7 +146,7 @@ class Solver:
                  precond="none", col_scale=None, stream=None, timing=False, graph=True,
                  lanes_per_row=0, lanes_per_col=0, check_every=0, refine_sweeps=5,
                  row_format="auto", col_format="auto", xcd_bands=False, refine_inner_tol=0.0,
-                 torch_alloc=True):
+                 method="lsqr", torch_alloc=True):
         import torch
         lib = load()
         self._torch = torch
@@ -174,6 +175,7 @@ class Solver:
             opts.col_scale = cs.ctypes.data
         opts.refine_sweeps = int(refine_sweeps)
         opts.refine_inner_tol = float(refine_inner_tol)
+        opts.method = {"lsqr": 0, "lsmr": 1}[method]
         opts.check_every = int(check_every)
         opts.stream = stream.cuda_stream
         opts.flags = ((FLAG_TIMING if timing else 0) | (0 if graph else FLAG_NO_GRAPH)

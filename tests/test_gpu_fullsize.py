@@ -60,6 +60,18 @@ def test_fullsize_first_iterates(big):
         assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0)
 
 
+def test_fullsize_lsmr_first_iterates(big):
+    from oracle.lsmr import lsmr
+    from paper_2604_11920_amd import Solver
+    s, op, _ = big
+    with Solver.from_system(s, method="lsmr") as sol:
+        for K in (1, 3):
+            ref = lsmr(op, s.dt, K)
+            dm, hist, info = sol.solve(s.dt, K)
+            assert rel(dm, ref["x"]) <= 1e-10, K
+            assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0)
+
+
 def test_fullsize_300_iterations(big):
     s, op, sol = big
     dm, hist, info = sol.solve(torch.from_numpy(s.dt).cuda(), 300)

@@ -78,13 +78,17 @@ def test_refinement_reaches_fp64_solution(cfg0, xstar, fmt, precond, col_format)
     with from_sys(cfg0, precision=fmt, precond=precond, refine_sweeps=10,
                   row_format="masks" if col_format == "masks" else "auto",
                   col_format=col_format) as sol:
-        dm, hist, info = sol.solve(cfg0.dt, 3000, tol=1e-7)
+        # |x - x*| / |x*| is bounded by about cond(Abar^T Abar) eta: without
+        # column scaling that condition number is ~3e5 on this system, so the
+        # unscaled forms stop at a tighter eta than the Jacobi-scaled ones
+        tol = 1e-7 if precond == "jacobi" else 2e-8
+        dm, hist, info = sol.solve(cfg0.dt, 3000, tol=tol)
     err = rel(dm, xstar)
     print(f"[{fmt}/{precond}/{col_format}] sweeps={info['sweeps']} inner iters={info['iters']} "
           f"eta={info['eta']:.2e} err_vs_x*={err:.2e}")
     # each sweep gains at least ~30x (the quantisation error and the inner
-    # tolerance bound it), so 1e-7 takes a handful of sweeps
-    assert info["istop"] == 1 and info["eta"] <= 1e-7 and info["sweeps"] <= 8
+    # tolerance bound it), so the tolerance takes a handful of sweeps
+    assert info["istop"] == 1 and info["eta"] <= tol and info["sweeps"] <= 8
     assert err <= 1e-5
 
 
