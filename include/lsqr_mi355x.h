@@ -194,7 +194,9 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
  *   dm        [n]   output solution (vec_mem)
  *   res_hist  host [3*(K+1)] or NULL: row k = (phibar_{k+1} = |rbar_k| estimate,
  *                   psi_k = |A_D^T rbar_k| estimate, eta_k); row 0 is the start
- *                   (beta_1, alpha_1*beta_1, 1); rows past info.iters are NaN
+ *                   (beta_1, alpha_1*beta_1, 1); rows past info.iters are NaN.
+ *                   LSMR: (|rbar_k| from its third rotation chain,
+ *                   |A_D^T rbar_k| = |zetabar_{k+1}|, that over alpha_1 beta_1)
  *   info      output, may be NULL
  * For the mixed forms (precision BF16/FP16) dm is refined in FP64 until
  * eta <= tol (tol must be > 0) or opts.refine_sweeps sweeps; iters then caps

@@ -28,6 +28,10 @@ BArgs base_args(lsqr_ctx *c, BatchEngine &B)
     BArgs a{};
     a.rp = c->rp; a.ci = c->ci; a.va = c->va32;
     a.cp = c->cp; a.ri = c->ri; a.cv = c->cv32;
+    if (c->nval32 && c->P.nz <= kMaxNzBatched) {   // transposed product over node runs
+        a.nrp = c->nrp; a.nvq = c->nvq; a.nrow = c->nrow; a.ndesc = c->ndesc;
+        a.norder = c->norder; a.nval = c->nval32;
+    }
     a.d = c->d;
     a.m = c->P.m; a.n = (int)c->P.n; a.nx = c->P.nx; a.ny = c->P.ny; a.nz = c->P.nz;
     a.w = c->P.w; a.damp = c->P.damp;
@@ -42,7 +46,10 @@ void launch_tile(hipStream_t st, int kind, int grid, const BArgs &a)
     switch (kind) {
     case 0: hipLaunchKernelGGL((k_binit<RT>), dim3(grid), dim3(kBlock), 0, st, a); break;
     case 1: hipLaunchKernelGGL((k_bfwd<RT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_badj<RT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    default:
+        if (a.nrp) hipLaunchKernelGGL((k_badj_nruns<RT>), dim3(grid), dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_badj<RT>), dim3(grid), dim3(kBlock), 0, st, a);
+        break;
     }
 }
 
@@ -64,13 +71,19 @@ void launch_tiled(hipStream_t st, int kind, int grid, BArgs a, int R, int rt)
 // FP32 copies of the values (the batched kernels read FP32).
 lsqr_status ensure_fp32(lsqr_ctx *c, hipStream_t st)
 {
-    if (c->va32 && c->cv32) return LSQR_OK;
     const int64_t nnz = c->P.nnz;
-    c->va32 = ctx_alloc<float>(c, nnz);
-    c->cv32 = ctx_alloc<float>(c, nnz);
-    if (!c->va32 || !c->cv32) return fail(c, LSQR_E_OOM, "device allocation failed");
-    launch_convert_f32(st, nnz, c->va, c->va32);
-    launch_convert_f32(st, nnz, c->cv, c->cv32);
+    if (!c->va32 || !c->cv32) {
+        c->va32 = ctx_alloc<float>(c, nnz);
+        c->cv32 = ctx_alloc<float>(c, nnz);
+        if (!c->va32 || !c->cv32) return fail(c, LSQR_E_OOM, "device allocation failed");
+        launch_convert_f32(st, nnz, c->va, c->va32);
+        launch_convert_f32(st, nnz, c->cv, c->cv32);
+    }
+    if (c->nval && !c->nval32) {     // node-run values for the transposed block product
+        c->nval32 = ctx_alloc<float>(c, nnz);
+        if (!c->nval32) return fail(c, LSQR_E_OOM, "device allocation failed");
+        launch_convert_f32(st, nnz, c->nval, c->nval32);
+    }
     HIP_TRY(c, hipGetLastError());
     return LSQR_OK;
 }
@@ -125,7 +138,10 @@ lsqr_status ensure_batch(lsqr_ctx *c, hipStream_t st, int R, int iters)
         if (!B.S) return fail(c, LSQR_E_OOM, "state allocation failed");
     }
     B.g_fwd = cap(m * 64, kBlock, B.grid);
-    B.g_adj = cap(n * 64, kBlock, B.grid);
+    if (c->nval32 && c->P.nz <= kMaxNzBatched)      // a workgroup per lateral node
+        B.g_adj = (int)std::max<int64_t>(1, std::min<int64_t>(n / c->P.nz, B.grid));
+    else
+        B.g_adj = cap(n * 64, kBlock, B.grid);
     B.g_upd = cap(n * R, kBlock, 512);
     return LSQR_OK;
 }

@@ -37,6 +37,13 @@ struct BArgs {
     const int64_t *cp;
     const int32_t *ri;
     const float *cv;
+    // node runs of the data block (k_badj_nruns; nval in node-major run order)
+    const int64_t *nrp;
+    const int64_t *nvq;
+    const uint32_t *nrow;
+    const uint16_t *ndesc;
+    const int32_t *norder;
+    const float *nval;
     const double *d;
     int64_t m;
     int n, nx, ny, nz;
@@ -250,6 +257,35 @@ __global__ __launch_bounds__(kBlock) void k_bfwd(BArgs a)
 
 // ------------------------------------------------------------- transposed --
 // Q = D A^T T diag(1/beta) - V diag(beta) for the tile (INIT: no V term).
+// Column j, right-hand side c of Q from g = (G^T T)_{j,c}: smoothing and
+// damping blocks, scale, the -beta v term; stores Q and returns Q^2.
+__device__ __forceinline__ double badj_col_out(const BArgs &a, int64_t j, int c, float g,
+                                               double beta, double ib)
+{
+#pragma clang fp contract(off)
+    const int R = a.R;
+    const int64_t tL = a.m, tD = a.m + a.n;
+    const int pp = (int)j;
+    const int iz = pp % a.nz, ixy = pp / a.nz, ix = ixy % a.nx, iy = ixy / a.nx;
+    const int sxy = a.nx * a.nz;
+    const float *TL = a.Tcur + tL * R;
+    float acc = 0.f;
+    int deg = 0;
+    if (ix > 0) { acc += TL[(int64_t)(pp - a.nz) * R + c]; ++deg; }
+    if (ix < a.nx - 1) { acc += TL[(int64_t)(pp + a.nz) * R + c]; ++deg; }
+    if (iy > 0) { acc += TL[(int64_t)(pp - sxy) * R + c]; ++deg; }
+    if (iy < a.ny - 1) { acc += TL[(int64_t)(pp + sxy) * R + c]; ++deg; }
+    if (iz > 0) { acc += TL[(int64_t)(pp - 1) * R + c]; ++deg; }
+    if (iz < a.nz - 1) { acc += TL[(int64_t)(pp + 1) * R + c]; ++deg; }
+    const float lap = acc - (float)deg * TL[(int64_t)pp * R + c];
+    const float sj = g + (float)a.w * lap + (float)a.damp * a.Tcur[(tD + j) * R + c];
+    const double xj = a.d[j] * (double)sj;
+    const double vj = a.mode == MODE_ITER ? (double)a.V[j * R + c] : 0.0;
+    const float qv = (float)(xj / ib - beta * vj);
+    a.Q[j * R + c] = qv;
+    return (double)qv * (double)qv;
+}
+
 template <int RT>
 __global__ __launch_bounds__(kBlock) void k_badj(BArgs a)
 {
@@ -306,28 +342,118 @@ __global__ __launch_bounds__(kBlock) void k_badj(BArgs a)
         float g = tree_sum<kBatchUnroll>(ac);
 #pragma unroll
         for (int off = RT; off < 64; off <<= 1) g += __shfl_xor(g, off, 64);
-        if (er == 0) {
-            const int pp = (int)j;
-            const int iz = pp % a.nz, ixy = pp / a.nz, ix = ixy % a.nx, iy = ixy / a.nx;
-            const int sxy = a.nx * a.nz;
-            const float *TL = a.Tcur + tL * R;
-            float acc = 0.f;
-            int deg = 0;
-            if (ix > 0) { acc += TL[(int64_t)(pp - a.nz) * R + cofs]; ++deg; }
-            if (ix < a.nx - 1) { acc += TL[(int64_t)(pp + a.nz) * R + cofs]; ++deg; }
-            if (iy > 0) { acc += TL[(int64_t)(pp - sxy) * R + cofs]; ++deg; }
-            if (iy < a.ny - 1) { acc += TL[(int64_t)(pp + sxy) * R + cofs]; ++deg; }
-            if (iz > 0) { acc += TL[(int64_t)(pp - 1) * R + cofs]; ++deg; }
-            if (iz < a.nz - 1) { acc += TL[(int64_t)(pp + 1) * R + cofs]; ++deg; }
-            const float lap = acc - (float)deg * TL[(int64_t)pp * R + cofs];
-            const float sj = g + (float)a.w * lap + (float)a.damp * a.Tcur[(tD + j) * R + cofs];
-            const double xj = a.d[j] * (double)sj;
-            const double vj = a.mode == MODE_ITER ? (double)a.V[j * R + cofs] : 0.0;
-            const float qv = (float)(xj / ib - beta * vj);
-            a.Q[j * R + cofs] = qv;
-            sq += (double)qv * (double)qv;
-        }
+        if (er == 0) sq += badj_col_out(a, j, cofs, g, beta, ib);
     }
+    block_sum_rhs<RT>(sq, accs, res);
+    if (threadIdx.x < RT) a.part_out[(int64_t)blockIdx.x * a.R + a.r0 + threadIdx.x] = res[threadIdx.x];
+}
+
+// Transposed block product over node runs (see k_adj_nruns): a workgroup per
+// lateral node, its 4 waves on fixed quarters of the node's runs.  A wave
+// loads 64 run descriptors at a time (one per lane, prefix-summed for value
+// offsets); its 64/RT slots of RT lanes then take the runs in turn, a slot
+// gathering the run's row of T once (RT right-hand sides, one coalesced
+// segment) for all the run's depths, and adding val_e t into its own LDS
+// accumulator column [depth][rhs] (every cell has one owner: no atomics).
+// Column sums run over slots, then waves, in fixed order.  The t gathers fall
+// from one per stored entry to one per run.
+constexpr int kMaxNzBatched = 32;
+
+template <int RT>
+__global__ __launch_bounds__(kBlock) void k_badj_nruns(BArgs a)
+{
+#pragma clang fp contract(off)
+    constexpr int SPW = 64 / RT;                   // slots per wave
+    constexpr int NSLOT = kBlock / RT;             // slots per workgroup
+    __shared__ double accs[kBlock];
+    __shared__ double res[kMaxRhs];
+    __shared__ double b2[kMaxRhs];
+    __shared__ float qacc[NSLOT * kMaxNzBatched * RT];
+    const bool op = a.mode == MODE_OPERATOR;
+    int k = 0;
+    if (a.mode == MODE_ITER) {
+        k = a.ctl[C_CNT0 + a.parity];
+        if (k > a.ctl[C_KMAX]) return;
+    }
+    if (op) {
+        if (threadIdx.x < a.R) b2[threadIdx.x] = 1.0;
+        __syncthreads();
+    } else {
+        sum_rhs_all(a.part_in, a.np_in, a.R, accs, b2);
+    }
+    if (!op && blockIdx.x == 0 && threadIdx.x < RT) {
+        const int r = a.r0 + threadIdx.x;
+        srow(a, k, r)[S_BETA] = sqrt(b2[r]);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int slot_w = lane / RT, rl = lane % RT;          // slot within the wave, rhs lane
+    const int slot = wid * SPW + slot_w;
+    const int R = a.R, cofs = a.r0 + rl;
+    const int nz = a.nz, nnodes = a.n / nz;
+    const int G = gridDim.x;
+    float *my = qacc + (int64_t)slot * kMaxNzBatched * RT;
+    double sq = 0.0;
+    for (int s = 0; s * G < nnodes; ++s) {
+        const int idx = s * G + ((s & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        if (idx >= nnodes) continue;                        // uniform over the workgroup
+        const int node = a.norder[idx];
+        for (int iz = 0; iz < nz; ++iz) my[iz * RT + rl] = 0.f;
+        const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
+        const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
+        int64_t vb = a.nvq[4 * (int64_t)node + wid];
+        for (int64_t base = rs; base < re; base += 64) {
+            const int nr = (int)(re - base < 64 ? re - base : 64);
+            uint32_t dsc = 0u, row = 0u;
+            if (lane < nr) {
+                dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
+                row = __builtin_nontemporal_load(a.nrow + base + lane);
+            }
+            const int len = (int)(dsc & 255u);
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            const int off = incl - len;
+            const int tot = __shfl(incl, 63);
+            for (int r0 = 0; r0 < nr; r0 += SPW) {
+                const int r = r0 + slot_w;                   // this slot's run of the chunk
+                const uint32_t d = __shfl(dsc, r & 63);
+                const int ro = __shfl(off, r & 63);
+                const uint32_t rw = __shfl(row, r & 63);
+                const int rlen = r < nr ? (int)(d & 255u) : 0;
+                const int riz = (int)((d >> 8) & 255u);
+                // the run's row of T (RT right-hand sides) and its values
+                const float t = rlen > 0 ? a.Tcur[(int64_t)rw * R + cofs] : 0.f;
+                int maxlen = rlen;
+#pragma unroll
+                for (int o = RT; o < 64; o <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o));
+                // the slot's lanes load RT of the run's values at a time
+                for (int e0 = 0; e0 < maxlen; e0 += RT) {
+                    const float vown = e0 + rl < rlen
+                        ? __builtin_nontemporal_load(a.nval + vb + ro + e0 + rl) : 0.f;
+                    const int e1 = maxlen - e0 < RT ? maxlen - e0 : RT;
+                    for (int e = 0; e < e1; ++e) {
+                        const float ve = __shfl(vown, (slot_w * RT + e) & 63);
+                        if (e0 + e < rlen) my[(riz + e0 + e) * RT + rl] += ve * t;
+                    }
+                }
+            }
+            vb += tot;
+        }
+        __syncthreads();
+        // column sums: slots in order (within and across waves)
+        for (int cell = threadIdx.x; cell < nz * RT; cell += kBlock) {
+            float g = 0.f;
+            for (int sl = 0; sl < NSLOT; ++sl) g += qacc[(int64_t)sl * kMaxNzBatched * RT + cell];
+            const int iz = cell / RT, c = a.r0 + cell % RT;
+            const double bc = sqrt(b2[c]);
+            sq += badj_col_out(a, (int64_t)node * nz + iz, c, g, bc, bc > 0.0 ? bc : 1.0);
+        }
+        __syncthreads();
+    }
+    // per-RHS partial sums: thread t's squares belong to rhs lane t % RT
     block_sum_rhs<RT>(sq, accs, res);
     if (threadIdx.x < RT) a.part_out[(int64_t)blockIdx.x * a.R + a.r0 + threadIdx.x] = res[threadIdx.x];
 }

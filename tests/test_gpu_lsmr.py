@@ -97,10 +97,16 @@ def test_bf16_refinement_with_lsmr_inner_solves(cfg0):
     op = oracle.Operator.from_system(cfg0)
     xs = oracle.Operator.from_system(cfg0, d=op.jacobi(), compensated=True).lsqr(
         cfg0.dt, 40000, tol=1e-12)["x"]
-    with from_sys(cfg0, precision="bf16", precond="jacobi", refine_sweeps=10) as sol:
-        dm, hist, info = sol.solve(cfg0.dt, 3000, tol=1e-7)
-    print(f"[bf16/lsmr] sweeps={info['sweeps']} iters={info['iters']} err={rel(dm, xs):.2e}")
-    assert info["istop"] == 1 and rel(dm, xs) <= 1e-5
+    # LSMR drives |A^T r| down faster than the error in the small singular
+    # directions (LSQR's error, not LSMR's, decreases monotonically), so the
+    # same error needs a tighter eta than with LSQR inner solves (still above
+    # the refinement's FP32 floor of a few 1e-9)
+    with from_sys(cfg0, precision="bf16", precond="jacobi", refine_sweeps=10,
+                  refine_inner_tol=1e-3) as sol:
+        dm, hist, info = sol.solve(cfg0.dt, 3000, tol=1e-8)
+    print(f"[bf16/lsmr] sweeps={info['sweeps']} iters={info['iters']} eta={info['eta']:.2e} "
+          f"err={rel(dm, xs):.2e}")
+    assert info["istop"] in (1, 4) and rel(dm, xs) <= 1e-5
 
 
 def test_degenerate_right_hand_side(cfg0):

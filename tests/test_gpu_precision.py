@@ -75,13 +75,16 @@ def test_quantised_codes_bitwise(cfg0, fmt, which):
     ("fp16", "jacobi", "auto"), ("bf16", "jacobi", "runs"), ("fp16", "jacobi", "runs"),
     ("bf16", "jacobi", "masks"), ("fp16", "none", "masks")])
 def test_refinement_reaches_fp64_solution(cfg0, xstar, fmt, precond, col_format):
-    with from_sys(cfg0, precision=fmt, precond=precond, refine_sweeps=10,
+    # Without column scaling the error at a given eta is ~100x larger on this
+    # system (|x - x*| is bounded by cond(Abar^T Abar) eta, ~3e5 unscaled), and
+    # the refinement's FP32 floor (a few 1e-9) leaves little room to tighten
+    # eta; the unscaled forms instead take tighter inner solves, whose sweeps
+    # overshoot the tolerance.  The Jacobi-scaled forms use the default.
+    tol = 1e-7
+    inner = 0.0 if precond == "jacobi" else 1e-3
+    with from_sys(cfg0, precision=fmt, precond=precond, refine_sweeps=10, refine_inner_tol=inner,
                   row_format="masks" if col_format == "masks" else "auto",
                   col_format=col_format) as sol:
-        # |x - x*| / |x*| is bounded by about cond(Abar^T Abar) eta: without
-        # column scaling that condition number is ~3e5 on this system, so the
-        # unscaled forms stop at a tighter eta than the Jacobi-scaled ones
-        tol = 1e-7 if precond == "jacobi" else 2e-8
         dm, hist, info = sol.solve(cfg0.dt, 3000, tol=tol)
     err = rel(dm, xstar)
     print(f"[{fmt}/{precond}/{col_format}] sweeps={info['sweeps']} inner iters={info['iters']} "
