@@ -271,6 +271,15 @@ lsqr_status lsqr_apply(lsqr_ctx *ctx, const double *x, double *y);
 lsqr_status lsqr_apply_t(lsqr_ctx *ctx, const double *y, double *x);
 
 /*
+ * lsqr_set_scale — replace the column scaling D (x = D y) by host d [n],
+ * finite and > 0 (else INVALID_ARG and D unchanged).  Any d leaves the
+ * regularised least-squares solution unchanged (only the iteration count
+ * moves), so a learned scale can be tried on a context without rebuilding it.
+ * The captured iteration graphs read D from the same buffer and stay valid.
+ */
+lsqr_status lsqr_set_scale(lsqr_ctx *ctx, const double *d);
+
+/*
  * lsqr_get_scale — copy the column scaling d [n] (host buffer).
  * lsqr_get_transpose — copy the device-built CSC of G to host buffers
  * col_ptr [n+1], row_idx [nnz], val [nnz] (any may be NULL).

@@ -824,6 +824,20 @@ lsqr_status lsqr_apply_t(lsqr_ctx *c, const double *y, double *x)
     return LSQR_OK;
 }
 
+lsqr_status lsqr_set_scale(lsqr_ctx *c, const double *d)
+{
+    if (!c) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx is NULL");
+    if (!d) return fail(c, LSQR_E_INVALID_ARG, "d is NULL");
+    for (int64_t j = 0; j < c->P.n; ++j)
+        if (!(isfinite(d[j]) && d[j] > 0.0))
+            return fail(c, LSQR_E_INVALID_ARG, "column scale must be finite and > 0");
+    DeviceGuard dg(c->device);
+    HIP_TRY(c, hipMemcpyAsync(c->d, d, c->P.n * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    c->fallback_used = 0;
+    return LSQR_OK;
+}
+
 lsqr_status lsqr_get_scale(const lsqr_ctx *cc, double *d)
 {
     lsqr_ctx *c = const_cast<lsqr_ctx *>(cc);

@@ -31,7 +31,7 @@ import time
 
 import numpy as np
 
-from .lsqr import Solver, Trainer
+from .lsqr import LsqrError, Solver, Trainer
 
 NPARAMS = 4673
 H = 64
@@ -85,48 +85,47 @@ def family_log_multiplier(feat, theta, nz=None):
     return a0 + a1 * f[:, 2] + b * cov + c * nbr
 
 
-def iterations_to_tol(system, col_scale, tol, cap):
-    """LSQR iterations to eta <= tol with the given scale (None: Jacobi)."""
-    kw = dict(precond="jacobi") if col_scale is None else dict(precond="user", col_scale=col_scale)
-    with Solver.from_system(system, check_every=8, **kw) as sol:
-        dm, _, info = sol.solve(system.dt, int(cap), tol=tol, history=False)
+def iterations_to_tol(system, col_scale, tol, cap, solver=None):
+    """LSQR iterations to eta <= tol with the given scale (None: Jacobi);
+    cap + 1 when the tolerance is not reached.  `solver` (created with Jacobi
+    scaling) is reused when given: the scale is swapped in place."""
+    if solver is None:
+        kw = dict(precond="jacobi") if col_scale is None else dict(precond="user", col_scale=col_scale)
+        with Solver.from_system(system, check_every=8, **kw) as sol:
+            dm, _, info = sol.solve(system.dt, int(cap), tol=tol, history=False)
+    else:
+        solver.set_scale(solver.jacobi_scale if col_scale is None else col_scale)
+        dm, _, info = solver.solve(system.dt, int(cap), tol=tol, history=False)
     return info["iters"] if info["istop"] == 1 else int(cap) + 1, info
 
 
 def search_targets(system, tol=1e-6, family="depth", grid=(-1.0, -0.5, 0.5, 1.0), step=0.5,
                    rounds=2, log=None):
     """Coordinate descent over theta; returns (features [n,6], targets [n],
-    theta, Jacobi iterations, best iterations)."""
-    with Solver.from_system(system, precond="jacobi") as sol:
+    theta, Jacobi iterations, best iterations).  One solver context serves
+    every candidate (the scale is swapped in place)."""
+    with Solver.from_system(system, precond="jacobi", check_every=8) as sol:
         feat = sol.column_features().cpu().numpy().astype(np.float64)
         djac = sol.scale()
-    kj, _ = iterations_to_tol(system, None, tol, 20000)
-    nz = int(system.nz)
-    theta = np.zeros(nz + 2 if family == "depth" else 4)
-    best = kj
-    for rnd in range(rounds):
-        h = step * 0.5 ** rnd
-        for p in range(len(theta)):
-            base = theta[p]
-            for v in grid:
-                th = theta.copy()
-                th[p] = base + v * h
-                d = djac * np.exp(family_log_multiplier(feat, th, nz))
-                k, _ = iterations_to_tol(system, d, tol, min(2 * kj, best + 1))
-                if k < best:
-                    best, theta = k, th
+        sol.jacobi_scale = djac
+        kj, _ = iterations_to_tol(system, None, tol, 20000, solver=sol)
+        nz = int(system.nz)
+        theta = np.zeros(nz + 2 if family == "depth" else 4)
+        best = kj
+        for rnd in range(rounds):
+            h = step * 0.5 ** rnd
+            for p in range(len(theta)):
+                base = theta[p]
+                for v in grid:
+                    th = theta.copy()
+                    th[p] = base + v * h
+                    d = djac * np.exp(family_log_multiplier(feat, th, nz))
+                    k, _ = iterations_to_tol(system, d, tol, min(2 * kj, best + 1), solver=sol)
+                    if k < best:
+                        best, theta = k, th
     if log:
         log(f"  search: jacobi {kj} -> best {best} at theta {np.round(theta, 3).tolist()}")
     return feat, family_log_multiplier(feat, theta, nz), theta, kj, best
-
-
-def centred(feat, centre=CENTRE):
-    """Features of one system with the flagged columns minus their mean."""
-    f = np.array(feat, dtype=np.float64)
-    for k in range(f.shape[1]):
-        if (centre >> k) & 1:
-            f[:, k] -= f[:, k].mean()
-    return f
 
 
 def train(feats, targets, epochs=60, batch=4096, lr=1e-3, seed=0, centre=CENTRE, log=None):
@@ -166,30 +165,39 @@ def train(feats, targets, epochs=60, batch=4096, lr=1e-3, seed=0, centre=CENTRE,
                                   "centre": int(centre)})
 
 
-def learned_scale(system, model):
+def learned_scale(system, model, solver=None):
     """Host float64 [n] learned column scale for a system."""
     import torch
+    p = torch.from_numpy(np.ascontiguousarray(model.params, dtype=np.float32)).cuda()
+    if solver is not None:
+        return solver.mlp_scale(p, model.mean, model.std, centre=model.centre).cpu().numpy()
     with Solver.from_system(system) as sol:
-        p = torch.from_numpy(np.ascontiguousarray(model.params, dtype=np.float32)).cuda()
-        d = sol.mlp_scale(p, model.mean, model.std, centre=model.centre)
-        return d.cpu().numpy()
+        return sol.mlp_scale(p, model.mean, model.std, centre=model.centre).cpu().numpy()
 
 
 def solve_learned(system, model, tol, k_jacobi=None, cap=20000, precision="fp64"):
     """Solve with the learned scale; fall back to Jacobi when the learned solve
-    has not converged within twice the Jacobi count (or within cap)."""
+    has not converged within twice the Jacobi count (or within cap).  One
+    context: features and inference on it, then the scale is swapped in."""
     t0 = time.perf_counter()
-    d = learned_scale(system, model)
-    limit = 2 * k_jacobi if k_jacobi else cap
-    with Solver.from_system(system, precond="user", col_scale=d, precision=precision,
-                            check_every=16) as sol:
-        dm, _, info = sol.solve(system.dt, int(limit), tol=tol, history=False)
-    total = info["iters"]
-    if info["istop"] != 1 and k_jacobi is not None:
-        with Solver.from_system(system, precond="jacobi", precision=precision) as sol:
+    with Solver.from_system(system, precond="jacobi", precision=precision, check_every=16) as sol:
+        djac = sol.scale()
+        d = learned_scale(system, model, solver=sol)
+        try:
+            sol.set_scale(d)             # rejected unless finite and > 0
+            rejected = False
+        except LsqrError:
+            rejected = True
+        limit = 2 * k_jacobi if k_jacobi else cap
+        dm, _, info = sol.solve(system.dt, int(limit if not rejected else cap), tol=tol,
+                                history=False)
+        info["fallback_used"] = int(rejected)
+        total = info["iters"]
+        if not rejected and info["istop"] != 1 and k_jacobi is not None:
+            sol.set_scale(djac)
             dm, _, info = sol.solve(system.dt, cap, tol=tol, history=False)
-        info["fallback_used"] = 1
-        total += info["iters"]
+            info["fallback_used"] = 1
+            total += info["iters"]
     info["iters_total"] = total          # including a failed learned attempt
     info["seconds"] = time.perf_counter() - t0
     return dm, info

@@ -91,6 +91,7 @@ def load():
         "lsqr_apply": (I, [P, P, P]),
         "lsqr_apply_t": (I, [P, P, P]),
         "lsqr_get_scale": (I, [P, P]),
+        "lsqr_set_scale": (I, [P, P]),
         "lsqr_get_transpose": (I, [P, P, P, P]),
         "lsqr_kernel_stats": (I, [P, ctypes.POINTER(KStats)]),
         "lsqr_get_quantised": (I, [P, P, P, P]),
@@ -255,6 +256,12 @@ class Solver:
             x = self._torch.empty(self.n, dtype=self._torch.float64, device=y.device)
         self._check(self._lib.lsqr_apply_t(self._ctx, _ptr(y), _ptr(x)))
         return x
+
+    def set_scale(self, d):
+        """Replace the column scaling D (host array [n], finite, > 0)."""
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        assert d.shape == (self.n,)
+        self._check(self._lib.lsqr_set_scale(self._ctx, d.ctypes.data))
 
     def scale(self):
         d = np.empty(self.n)

@@ -16,7 +16,8 @@ Three steps, each resumable on its own:
 
 Families: "cfg0" = config-0 geometry (16x16x9) with 20-60 stations and damping
 0.05-0.5; "cfg1" = config-1 geometry (80x80x20) with 30-80 stations and 6-12
-periods.  Each training system's targets come from the iteration-minimising
+periods; "cfg1large" = config-1 geometry with 100-200 stations and 14-20
+periods (near the benchmark system).  Each training system's targets come from the iteration-minimising
 search of paper_2604_11920_amd.learned.
 """
 from __future__ import annotations
@@ -44,6 +45,8 @@ def family(name, first, count):
         return synth.learned_family(first, count)
     if name == "cfg1":
         return synth.learned_family_wide(first, count)
+    if name == "cfg1large":
+        return synth.learned_family_large(first, count)
     raise SystemExit(f"unknown family {name}")
 
 
@@ -126,7 +129,7 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("search")
-    a.add_argument("--family", default="cfg0", choices=["cfg0", "cfg1"])
+    a.add_argument("--family", default="cfg0", choices=["cfg0", "cfg1", "cfg1large"])
     a.add_argument("--first", type=int, default=1)
     a.add_argument("--count", type=int, default=160)
     a.add_argument("--tol", type=float, default=1e-6)
@@ -141,7 +144,7 @@ def main():
     b.add_argument("--out", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp.npz"))
     c = sub.add_parser("eval")
     c.add_argument("--model", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp.npz"))
-    c.add_argument("--family", default="cfg0", choices=["cfg0", "cfg1"])
+    c.add_argument("--family", default="cfg0", choices=["cfg0", "cfg1", "cfg1large"])
     c.add_argument("--first", type=int, default=1001)
     c.add_argument("--count", type=int, default=20)
     c.add_argument("--tol", type=float, default=1e-6)

@@ -175,6 +175,13 @@ def learned_family_wide(first_seed: int, count: int, stations=(30, 80), periods=
     return out
 
 
+def learned_family_large(first_seed: int, count: int, stations=(100, 200), periods=(14, 20),
+                         damp=(0.05, 0.2)):
+    """`count` config-1-geometry systems near the benchmark's size (100-200
+    stations, 14-20 periods), for the learned scale's targets."""
+    return learned_family_wide(first_seed, count, stations=stations, periods=periods, damp=damp)
+
+
 def small_config(nx=8, ny=8, nz=6, n_stations=12, n_periods=5, region=0.7, bent=True,
                  seed=0, damp=0.1, smooth=0.5, min_wavelengths=None) -> Config:
     """A reduced geometry with the same structure, for fast tests."""

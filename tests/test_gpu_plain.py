@@ -131,6 +131,26 @@ def test_operator_integer_bitwise_tomography_pattern(cfg0, row_format, col_forma
     assert np.array_equal(xg, op.apply_t(ybar))
 
 
+def test_set_scale_in_place(cfg0):
+    from paper_2604_11920_amd import LsqrError
+    s = cfg0
+    d = 2.0 ** np.random.default_rng(12).integers(-3, 4, s.n)
+    op = oracle.Operator.from_system(s, d=d)
+    x = np.random.default_rng(13).integers(-8, 9, size=s.n).astype(np.float64)
+    with from_sys(s, precond="jacobi") as sol:
+        sol.solve(s.dt, 4)                  # graphs captured with the Jacobi scale
+        sol.set_scale(d)
+        assert np.array_equal(sol.scale(), d)
+        dm, _, _ = sol.solve(s.dt, 5)
+        bad = d.copy()
+        bad[3] = 0.0
+        with pytest.raises(LsqrError):
+            sol.set_scale(bad)
+        assert np.array_equal(sol.scale(), d)
+    ref = op.lsqr(s.dt, 5)
+    assert rel(dm, ref["x"]) <= 1e-10
+
+
 def test_jacobi_scale_within_rounding(cfg0):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi()
