@@ -100,7 +100,7 @@ def iterations_to_tol(system, col_scale, tol, cap, solver=None):
 
 
 def search_targets(system, tol=1e-6, family="depth", grid=(-1.0, -0.5, 0.5, 1.0), step=0.5,
-                   rounds=2, log=None):
+                   rounds=2, log=None, progress=None):
     """Coordinate descent over theta; returns (features [n,6], targets [n],
     theta, Jacobi iterations, best iterations).  One solver context serves
     every candidate (the scale is swapped in place)."""
@@ -123,6 +123,8 @@ def search_targets(system, tol=1e-6, family="depth", grid=(-1.0, -0.5, 0.5, 1.0)
                     k, _ = iterations_to_tol(system, d, tol, min(2 * kj, best + 1), solver=sol)
                     if k < best:
                         best, theta = k, th
+                if progress:
+                    progress(f"    round {rnd + 1} parameter {p + 1}/{len(theta)}: best {best}")
     if log:
         log(f"  search: jacobi {kj} -> best {best} at theta {np.round(theta, 3).tolist()}")
     return feat, family_log_multiplier(feat, theta, nz), theta, kj, best

@@ -57,8 +57,9 @@ def cmd_search(args):
     feats, targets, rows = [], [], []
     for i, cfg in enumerate(family(args.family, args.first, args.count)):
         s = synth.make_system(cfg)
-        f, t, theta, kj, kb = learned.search_targets(s, tol=args.tol, family=args.param,
-                                                     rounds=args.rounds)
+        f, t, theta, kj, kb = learned.search_targets(
+            s, tol=args.tol, family=args.param, rounds=args.rounds,
+            progress=log if s.nnz > 50_000_000 else None)
         feats.append(f.astype(np.float32))
         targets.append(t.astype(np.float32))
         rows.append({"name": cfg.name, "n": int(s.n), "nnz": int(s.nnz), "jacobi_iters": int(kj),
