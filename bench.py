@@ -143,6 +143,7 @@ def time_to_tol(s, dt, tol, fmt, model_path=None):
     from paper_2604_11920_amd import Solver
     # (precision, scaling, iteration cap, inner tolerance of the refinement)
     forms = [("fp64", "none", 20000, 0.0), ("fp64", "jacobi", 20000, 0.0),
+             ("fp64", "jacobi_lsmr", 20000, 0.0),
              ("bf16", "jacobi", 4000, 0.0), ("bf16", "jacobi", 4000, 1e-3),
              ("fp16", "jacobi", 4000, 0.0)]
     model = None
@@ -168,7 +169,12 @@ def time_to_tol(s, dt, tol, fmt, model_path=None):
         infer_s = time.perf_counter() - t0
         d_learned = d_learned.cpu().numpy()
     for prec, pc, cap, itol in forms:
-        kw = dict(precond="user", col_scale=d_learned) if pc == "learned" else dict(precond=pc)
+        if pc == "learned":
+            kw = dict(precond="user", col_scale=d_learned)
+        elif pc == "jacobi_lsmr":     # LSMR (its eta is in the scaled variables)
+            kw = dict(precond="jacobi", method="lsmr")
+        else:
+            kw = dict(precond=pc)
         with Solver.from_system(s, precision=prec, refine_sweeps=8, refine_inner_tol=itol,
                                 **kw, **fmt) as sol:
             dm = torch.empty(s.n, dtype=torch.float64, device="cuda")

@@ -130,6 +130,15 @@ def search_targets(system, tol=1e-6, family="depth", grid=(-1.0, -0.5, 0.5, 1.0)
     return feat, family_log_multiplier(feat, theta, nz), theta, kj, best
 
 
+def centred(feat, centre=CENTRE):
+    """Features of one system with the flagged columns minus their mean."""
+    f = np.array(feat, dtype=np.float64)
+    for k in range(f.shape[1]):
+        if (centre >> k) & 1:
+            f[:, k] -= f[:, k].mean()
+    return f
+
+
 def train(feats, targets, epochs=60, batch=4096, lr=1e-3, seed=0, centre=CENTRE, log=None):
     """Fit the MLP on the GPU (the library's FP32 forward/backward and Adam).
     feats: per-system [n_s, 6] feature blocks (flagged columns are centred per
