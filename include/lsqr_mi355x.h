@@ -232,6 +232,8 @@ lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const 
  * lsqr_apply_block / lsqr_apply_t_block — the batched kernels as plain
  * products on nrhs (a power of two <= 32) row-major FP32 blocks of device
  * vectors: Y [m+2n][nrhs] = Abar D X [n][nrhs]; X = D Abar^T Y.  Enqueued only.
+ * For nrhs >= 4 the transposed product reads rows of Y as 16-byte vectors:
+ * y must then be 16-byte aligned (LSQR_E_INVALID_ARG otherwise).
  */
 lsqr_status lsqr_apply_block(lsqr_ctx *ctx, int nrhs, const float *x, float *y);
 lsqr_status lsqr_apply_t_block(lsqr_ctx *ctx, int nrhs, const float *y, float *x);

@@ -356,6 +356,8 @@ lsqr_status lsqr_apply_t_block(lsqr_ctx *c, int nrhs, const float *y, float *x)
     if (!x || !y) return fail(c, LSQR_E_INVALID_ARG, "x and y must not be NULL");
     if (nrhs < 1 || nrhs > kMaxRhs || (nrhs & (nrhs - 1)))
         return fail(c, LSQR_E_INVALID_ARG, "nrhs must be a power of two <= 32");
+    if (nrhs >= 4 && ((uintptr_t)y & 15u))                // rows of y are read as 16-byte vectors
+        return fail(c, LSQR_E_INVALID_ARG, "y must be 16-byte aligned when nrhs >= 4");
     DeviceGuard dg(c->device);
     lsqr_status e = ensure_batch(c, c->st, nrhs, 1);
     if (e != LSQR_OK) return e;

@@ -349,26 +349,40 @@ __global__ __launch_bounds__(kBlock) void k_badj(BArgs a)
 }
 
 // Transposed block product over node runs (see k_adj_nruns): a workgroup per
-// lateral node, its 4 waves on fixed quarters of the node's runs.  A wave
-// loads 64 run descriptors at a time (one per lane, prefix-summed for value
-// offsets); its 64/RT slots of RT lanes then take the runs in turn, a slot
-// gathering the run's row of T once (RT right-hand sides, one coalesced
-// segment) for all the run's depths, and adding val_e t into its own LDS
-// accumulator column [depth][rhs] (every cell has one owner: no atomics).
-// Column sums run over slots, then waves, in fixed order.  The t gathers fall
-// from one per stored entry to one per run.
+// lateral node, its 4 waves on fixed quarters of the node's runs, lanes in
+// 64/nz groups of nz lanes, lane iz of a group owning depth iz and keeping the
+// RT right-hand sides of its column in registers.  Per run, a group reads the
+// run's values (consecutive lanes, one value each) and the run's row of T
+// once (RT floats, the same address for the whole group), and every lane adds
+// val * T[row, :] to its RT accumulators.  The t gathers fall from one per
+// stored entry to one per run and no LDS is touched in the run loop.  Column
+// sums: groups in order (shuffles), then waves in order (LDS).
 constexpr int kMaxNzBatched = 32;
+
+template <int RT>
+__device__ __forceinline__ void ld_trow(const float *p, float *t)
+{
+    if constexpr (RT >= 4) {
+#pragma unroll
+        for (int q = 0; q < RT / 4; ++q) {
+            const float4 x = *(const float4 *)(p + 4 * q);
+            t[4 * q] = x.x; t[4 * q + 1] = x.y; t[4 * q + 2] = x.z; t[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < RT; ++q) t[q] = p[q];
+    }
+}
 
 template <int RT>
 __global__ __launch_bounds__(kBlock) void k_badj_nruns(BArgs a)
 {
 #pragma clang fp contract(off)
-    constexpr int SPW = 64 / RT;                   // slots per wave
-    constexpr int NSLOT = kBlock / RT;             // slots per workgroup
+    constexpr int K = RT >= 32 ? 2 : 4;            // runs per group in flight
     __shared__ double accs[kBlock];
     __shared__ double res[kMaxRhs];
     __shared__ double b2[kMaxRhs];
-    __shared__ float qacc[NSLOT * kMaxNzBatched * RT];
+    __shared__ float wsum[kBlock / 64][kMaxNzBatched][RT];
     const bool op = a.mode == MODE_OPERATOR;
     int k = 0;
     if (a.mode == MODE_ITER) {
@@ -386,21 +400,21 @@ __global__ __launch_bounds__(kBlock) void k_badj_nruns(BArgs a)
         srow(a, k, r)[S_BETA] = sqrt(b2[r]);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int slot_w = lane / RT, rl = lane % RT;          // slot within the wave, rhs lane
-    const int slot = wid * SPW + slot_w;
-    const int R = a.R, cofs = a.r0 + rl;
-    const int nz = a.nz, nnodes = a.n / nz;
+    const int R = a.R, nz = a.nz, ngr = 64 / nz, nnodes = a.n / nz;
+    const int grp = lane / nz, iz = lane - grp * nz;
+    const bool live = grp < ngr;
     const int G = gridDim.x;
-    float *my = qacc + (int64_t)slot * kMaxNzBatched * RT;
     double sq = 0.0;
     for (int s = 0; s * G < nnodes; ++s) {
         const int idx = s * G + ((s & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
         if (idx >= nnodes) continue;                        // uniform over the workgroup
         const int node = a.norder[idx];
-        for (int iz = 0; iz < nz; ++iz) my[iz * RT + rl] = 0.f;
         const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
         const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
         int64_t vb = a.nvq[4 * (int64_t)node + wid];
+        float acc[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] = 0.f;
         for (int64_t base = rs; base < re; base += 64) {
             const int nr = (int)(re - base < 64 ? re - base : 64);
             uint32_t dsc = 0u, row = 0u;
@@ -415,41 +429,46 @@ __global__ __launch_bounds__(kBlock) void k_badj_nruns(BArgs a)
                 const int y = __shfl_up(incl, o);
                 if (lane >= o) incl += y;
             }
-            const int off = incl - len;
+            const uint32_t pk = ((uint32_t)(incl - len) << 16) | dsc;
             const int tot = __shfl(incl, 63);
-            for (int r0 = 0; r0 < nr; r0 += SPW) {
-                const int r = r0 + slot_w;                   // this slot's run of the chunk
-                const uint32_t d = __shfl(dsc, r & 63);
-                const int ro = __shfl(off, r & 63);
-                const uint32_t rw = __shfl(row, r & 63);
-                const int rlen = r < nr ? (int)(d & 255u) : 0;
-                const int riz = (int)((d >> 8) & 255u);
-                // the run's row of T (RT right-hand sides) and its values
-                const float t = rlen > 0 ? a.Tcur[(int64_t)rw * R + cofs] : 0.f;
-                int maxlen = rlen;
+            for (int s0 = 0; s0 < nr; s0 += K * ngr) {
+                float v[K];
+                uint32_t rw[K];
 #pragma unroll
-                for (int o = RT; o < 64; o <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o));
-                // the slot's lanes load RT of the run's values at a time
-                for (int e0 = 0; e0 < maxlen; e0 += RT) {
-                    const float vown = e0 + rl < rlen
-                        ? __builtin_nontemporal_load(a.nval + vb + ro + e0 + rl) : 0.f;
-                    const int e1 = maxlen - e0 < RT ? maxlen - e0 : RT;
-                    for (int e = 0; e < e1; ++e) {
-                        const float ve = __shfl(vown, (slot_w * RT + e) & 63);
-                        if (e0 + e < rlen) my[(riz + e0 + e) * RT + rl] += ve * t;
-                    }
+                for (int u = 0; u < K; ++u) {
+                    const int r = s0 + grp + u * ngr;
+                    const uint32_t p = __shfl(pk, r & 63);
+                    rw[u] = __shfl(row, r & 63);               // rows past nr read row 0
+                    const int e = iz - (int)((p >> 8) & 255u);
+                    const bool in = live && r < nr && (unsigned)e < (p & 255u);
+                    const float x = __builtin_nontemporal_load(
+                        a.nval + (in ? vb + (int64_t)(p >> 16) + e : vb));
+                    v[u] = in ? x : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < K; ++u) {
+                    float t[RT];
+                    ld_trow<RT>(a.Tcur + (int64_t)rw[u] * R + a.r0, t);
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) acc[r] = fmaf(v[u], t[r], acc[r]);
                 }
             }
             vb += tot;
         }
+        // groups in order (shuffles), then waves in order (LDS)
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            float col = 0.f;
+            for (int g = 0; g < ngr; ++g) col += __shfl(acc[r], (g * nz + iz) & 63);
+            if (lane < nz) wsum[wid][lane][r] = col;
+        }
         __syncthreads();
-        // column sums: slots in order (within and across waves)
         for (int cell = threadIdx.x; cell < nz * RT; cell += kBlock) {
-            float g = 0.f;
-            for (int sl = 0; sl < NSLOT; ++sl) g += qacc[(int64_t)sl * kMaxNzBatched * RT + cell];
-            const int iz = cell / RT, c = a.r0 + cell % RT;
+            const int cz = cell / RT, cr = cell % RT;
+            const float g = ((wsum[0][cz][cr] + wsum[1][cz][cr]) + wsum[2][cz][cr]) + wsum[3][cz][cr];
+            const int c = a.r0 + cr;
             const double bc = sqrt(b2[c]);
-            sq += badj_col_out(a, (int64_t)node * nz + iz, c, g, bc, bc > 0.0 ? bc : 1.0);
+            sq += badj_col_out(a, (int64_t)node * nz + cz, c, g, bc, bc > 0.0 ? bc : 1.0);
         }
         __syncthreads();
     }

@@ -665,10 +665,13 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
 // t gathers are already in flight.  Per column, the sum runs over the chunks
 // in order, then over the groups in order, then over the waves in order:
 // fixed, no atomics.
-#ifndef LSQR_RUNS_PER_GROUP
-#define LSQR_RUNS_PER_GROUP 12
+// Runs per group per chunk (value loads in flight per lane): 12 for 8-byte
+// values, 16 for 4- and 2-byte values (measured on config 1).
+#ifdef LSQR_RUNS_PER_GROUP
+template <class M> struct RunsPerGroup { static constexpr int value = LSQR_RUNS_PER_GROUP; };
+#else
+template <class M> struct RunsPerGroup { static constexpr int value = sizeof(M) >= 8 ? 12 : 16; };
 #endif
-constexpr int kRunsPerGroup = LSQR_RUNS_PER_GROUP;
 
 template <class M, class V>
 __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
@@ -681,6 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
     if (!adj_prologue(a, beta, lds)) return;
     const M *nv = (const M *)a.cv;
     const V *Tg = (const V *)a.Tg;
+    constexpr int kRunsPerGroup = RunsPerGroup<M>::value;
     const int nz = a.nz, ngr = 64 / nz;
     const int ch = ngr * kRunsPerGroup < 64 ? ngr * kRunsPerGroup : 64;   // runs per chunk
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
