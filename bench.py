@@ -384,7 +384,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom_gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, f"{ks['row_format']}/{ks['col_format']}"),
-                     "kernel": ({1: "k_fwd_csr (forward product, CSR rows)",
+                     "kernel": ({1: "k_fwd_pipe (forward product, CSR rows, 64 lanes per row)",
                                  2: "k_fwd_runs (forward product, depth-run rows)",
                                  3: "k_fwd_rmask (forward product, run-mask rows)"}[ks["row_format"]]
                                 if dom == "fwd" else

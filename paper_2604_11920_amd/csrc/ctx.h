@@ -22,6 +22,7 @@ struct Engine {
     void *q = nullptr, *v = nullptr, *z = nullptr, *vzero = nullptr;
     double *w = nullptr, *y = nullptr;
     double *hbar = nullptr;        // LSMR only (w then holds h)
+    int32_t *wrow = nullptr;       // balanced wave partition of the CSR rows (or nullptr)
     double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
     double *S = nullptr;
     int64_t s_rows = 0;

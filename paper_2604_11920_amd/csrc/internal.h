@@ -87,6 +87,11 @@ struct RowFmt {
     const uint64_t *rmask = nullptr;   // [ceil(nnz / 64)]
     const uint32_t *rbase = nullptr;   // [ceil(nnz / 64)]
     const int32_t *rcol = nullptr;     // [runs]
+    // plain CSR with 64 lanes per row: wave w of a launch of wgrid workgroups
+    // takes rows wrow[w] .. wrow[w+1]-1 (contiguous, balanced in entries);
+    // other launch sizes take rows w, w + waves, ...
+    const int32_t *wrow = nullptr;     // [4 wgrid + 1]
+    int wgrid = 0;
 };
 
 // Stored transpose (CSC) for the transposed product.
@@ -121,6 +126,10 @@ struct ColFmt {
 void launch_init(hipStream_t st, const Problem &P, int grid, int vec, const double *rhs, int full,
                  void *T0, const float *sigma, void *Ts0, double *y, void *vzero, double *part,
                  int *ctl, int kmax);
+// Workgroups of the pipelined CSR forward product that the device holds at
+// once (0 when R does not use it), and its balanced wave partition.
+int fwd_pipe_grid(int vec, const RowFmt &R);
+void launch_wave_rows(hipStream_t st, const int64_t *rp, int64_t m, int waves, int32_t *wrow);
 void launch_fwd(hipStream_t st, const Problem &P, int grid, int vec, const RowFmt &R,
                 const void *z, const void *Tprev, void *Tcur, void *Ts, double *part_out,
                 const double *part_v, int np_v, double *S, int *ctl, int parity, double tol,

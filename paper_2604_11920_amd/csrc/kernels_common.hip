@@ -25,6 +25,47 @@ hipError_t update_launch(hipStream_t, const Problem &, int, const double *, cons
                          double *, double *, void *, double *, const double *, int, double *,
                          int *, int, int, double *);
 
+template <class V>
+int fwd_pipe_blocks_per_cu(const RowFmt &);
+
+// Balanced wave partition of the CSR rows: boundary w is the first row r with
+// rp[r] + kRowCost r >= w (nnz + kRowCost m) / waves (each row also costs a
+// reduction and a store, counted as kRowCost entries).  One thread per boundary,
+// binary search; boundaries are non-decreasing, wrow[0] = 0, wrow[waves] = m.
+constexpr int64_t kRowCost = 64;
+
+__global__ void k_wave_rows(const int64_t *rp, int64_t m, int waves, int32_t *wrow)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w > waves) return;
+    const int64_t total = rp[m] + kRowCost * m;
+    const int64_t target = (int64_t)(((__int128)total * w) / waves);
+    int64_t lo = 0, hi = m;                          // first r in [0, m] with cost(r) >= target
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (rp[mid] + kRowCost * mid >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    wrow[w] = (int32_t)(w == waves ? m : lo);
+}
+
+void launch_wave_rows(hipStream_t st, const int64_t *rp, int64_t m, int waves, int32_t *wrow)
+{
+    hipLaunchKernelGGL(k_wave_rows, dim3((waves + 1 + 255) / 256), dim3(256), 0, st, rp, m, waves,
+                       wrow);
+}
+
+int fwd_pipe_grid(int vec, const RowFmt &R)
+{
+    if (!LSQR_FWD_PIPE || R.run_ptr || R.rmask || R.lpr != 64) return 0;
+    const int per_cu = vec == VT_F64 ? fwd_pipe_blocks_per_cu<double>(R) : fwd_pipe_blocks_per_cu<float>(R);
+    int dev = 0, cus = 0;
+    if (per_cu < 1 || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return 0;
+    return std::min(per_cu * cus, 2048);
+}
+
 size_t vt_size(int vt)
 {
     switch (vt) {

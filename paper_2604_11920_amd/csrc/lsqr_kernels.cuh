@@ -65,6 +65,29 @@ template <class A> __device__ __forceinline__ A ld_nt(const fp16_t *p)
     return (A)(float)h;
 }
 
+// Raw stored bits of a value (loaded under a lane mask, converted after it, so
+// that no conversion waits on a load inside the masked region); raw 0 is +0
+// in every format.
+template <class M> struct RawOf { using type = M; };
+template <> struct RawOf<bf16_t> { using type = uint16_t; };
+template <> struct RawOf<fp16_t> { using type = uint16_t; };
+__device__ __forceinline__ double raw_nt(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float raw_nt(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ uint16_t raw_nt(const bf16_t *p) { return __builtin_nontemporal_load(&p->b); }
+__device__ __forceinline__ uint16_t raw_nt(const fp16_t *p) { return __builtin_nontemporal_load(&p->b); }
+template <class A, class M> __device__ __forceinline__ A from_raw(typename RawOf<M>::type r)
+{
+    if constexpr (sizeof(M) >= 4) {
+        return (A)r;
+    } else if constexpr (sizeof(M) == 2 && __is_same(M, bf16_t)) {
+        return (A)__uint_as_float((uint32_t)r << 16);
+    } else {
+        _Float16 h;
+        __builtin_memcpy(&h, &r, 2);
+        return (A)(float)h;
+    }
+}
+
 // 1: the CSR / CSC products load the next row's (column's) bounds and the
 // current row's u term before the current row's entries.
 #ifndef LSQR_ROW_PREFETCH
@@ -188,6 +211,8 @@ struct FwdArgs {
     int parity;
     int mode;
     double tol;
+    const int32_t *wrow;      // balanced wave partition (see RowFmt) or nullptr
+    int wgrid;
 };
 
 // Prologue of an LSQR forward step: the scalars of the previous step, the
@@ -330,6 +355,149 @@ __global__ __launch_bounds__(kBlock) void k_fwd_csr(FwdArgs a)
 #else
         if (lane == 0) sq += fwd_row_out<V>(a, row, (double)acc, alpha, beta);
 #endif
+    }
+    sq += fwd_reg_rows<V>(a, alpha, beta);
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+}
+
+// Plain CSR rows, one wave per row, software-pipelined.  A wave walks its
+// rows as one stream of batches of U entries per lane (64 U per batch): the
+// columns and values of the next batch (the rest of this row, else the start
+// of the wave's next row) are loaded before the current batch's v gathers and
+// products, so HBM loads stay in flight while the gathers wait on L2 and
+// while a finished row is reduced.  Lanes past a row's end load nothing and
+// add zero.
+#ifndef LSQR_FWD_PIPE
+#define LSQR_FWD_PIPE 1
+#endif
+#ifndef LSQR_FWD_PIPE_U
+#define LSQR_FWD_PIPE_U 8
+#endif
+
+// A load through the constant address space: with a wave-uniform index it
+// becomes a scalar load, whose wait does not hold up the vector loads in
+// flight.  Only for memory that no kernel of the launch writes.
+template <class T>
+__device__ __forceinline__ T ld_uniform(const T *p, int64_t i)
+{
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
+// One batch of a CSR row walk: U entries per lane (entry jb + lane + 64 u).
+// Entries past eb load a clamped in-range address (the row's last entry, else
+// entry 0) and are left out of the products (u >= the lane's valid count):
+// every batch issues the same loads with no branch, and the raw values are
+// converted only where they are used, so no wait is placed before the use.
+template <class M, int U>
+struct CsrBatch {
+    int c[U];
+    typename RawOf<M>::type r[U];
+    int nv;                              // entries u < nv of this lane are in the row
+};
+
+template <class M, int U>
+__device__ __forceinline__ void csr_batch(const FwdArgs &a, const M *va, int64_t jb, int64_t eb,
+                                          int lane, CsrBatch<M, U> &b)
+{
+    const int64_t safe = jb < eb ? eb - 1 : 0;
+    const int64_t left = eb - jb - lane;                 // entries from this lane's first on
+    b.nv = left <= 0 ? 0 : (left >= 64 * (int64_t)U ? U : (int)((left + 63) >> 6));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t j = jb + lane + 64 * u;
+        const int64_t jj = j < eb ? j : safe;
+        b.c[u] = __builtin_nontemporal_load(a.ci + jj);
+        b.r[u] = raw_nt(va + jj);
+    }
+}
+
+template <class M, class V>
+__global__ __launch_bounds__(kBlock) void k_fwd_pipe(FwdArgs a)
+{
+    using A = typename AccOf<V>::type;
+    constexpr int U = LSQR_FWD_PIPE_U;
+    constexpr int64_t B = 64 * U;
+    __shared__ double lds[4];
+    double alpha, beta;
+    if (!fwd_prologue(a, alpha, beta, lds)) return;
+    const M *va = (const M *)a.va;
+    const V *z = (const V *)a.z;
+    const V *tp = (const V *)a.Tprev;
+    const bool iter = a.mode == MODE_ITER;
+    double sq = 0.0;
+    const int lane = threadIdx.x & 63;
+    // the wave's rows: a contiguous balanced range, else every wstride-th row.
+    // Row indexes are uniform over the wave: row bounds and the u term come
+    // through scalar loads.
+    const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
+    int row = wave, rend = (int)a.m, wstride = gridDim.x * (kBlock / 64);
+    if (a.wrow && a.wgrid == (int)gridDim.x) {
+        row = ld_uniform(a.wrow, wave);
+        rend = ld_uniform(a.wrow, wave + 1);
+        wstride = 1;
+    }
+    if (a.m > 0 && a.rp[a.m] == 0) {                      // no stored entries: rows of zeros
+        for (; row < rend; row += wstride)
+            if (lane == 0) sq += fwd_row_out<V>(a, row, 0.0, alpha, beta);
+    }
+    if (row < rend) {
+        int64_t j = ld_uniform(a.rp, row), e = ld_uniform(a.rp, row + 1);
+        int nrow = row + wstride;
+        int64_t ns = 0, ne = 0;
+        if (nrow < rend) { ns = ld_uniform(a.rp, nrow); ne = ld_uniform(a.rp, nrow + 1); }
+        double up = iter ? (double)ld_uniform(tp, row) : 0.0;
+        double sg = a.sigma ? (double)ld_uniform(a.sigma, row) : 1.0;
+        CsrBatch<M, U> b0, b1;
+        A acc[U];
+        csr_batch<M, U>(a, va, j, e, lane, b0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = 0;
+        // one batch: gathers of the current batch, loads of the next one (the
+        // current batch's gathers go first: loads complete in issue order, so
+        // the products wait for the gathers only), products, and the row's end
+        auto step = [&](const CsrBatch<M, U> &cur, CsrBatch<M, U> &nxt) -> bool {
+            const bool last = j + B >= e;
+            const int64_t jn = last ? ns : j + B, en = last ? ne : e;
+            A zg[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) zg[u] = (A)z[cur.c[u]];
+            csr_batch<M, U>(a, va, jn, en, lane, nxt);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const A p = fma(from_raw<A, M>(cur.r[u]), zg[u], acc[u]);
+                acc[u] = u < cur.nv ? p : acc[u];
+            }
+            j = jn;
+            if (last) {
+                const A t = group_sum<64>(tree_sum<U>(acc));
+                if (lane == 0) {                          // as fwd_row_out, sigma preloaded
+#pragma clang fp contract(off)
+                    const double sacc = a.sigma ? sg * (double)t : (double)t;
+                    const double u = iter ? up / beta : 0.0;
+                    const V tv = (V)(sacc - alpha * u);
+                    ((V *)a.Tcur)[row] = tv;
+                    if (a.Ts) ((V *)a.Ts)[row] = (V)(sg * (double)tv);
+                    sq += (double)tv * (double)tv;
+                }
+                if (nrow >= rend) return true;
+                row = nrow;
+                e = ne;
+                nrow = row + wstride;
+                ns = ne = 0;
+                if (nrow < rend) { ns = ld_uniform(a.rp, nrow); ne = ld_uniform(a.rp, nrow + 1); }
+                up = iter ? (double)ld_uniform(tp, row) : 0.0;
+                if (a.sigma) sg = (double)ld_uniform(a.sigma, row);
+#pragma unroll
+                for (int u = 0; u < U; ++u) acc[u] = 0;
+            }
+            return false;
+        };
+        // two register sets in turn, so no batch is copied
+        for (;;) {
+            if (step(b0, b1)) break;
+            if (step(b1, b0)) break;
+        }
     }
     sq += fwd_reg_rows<V>(a, alpha, beta);
     const double tot = block_sum(sq, lds);
@@ -1092,7 +1260,10 @@ static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArg
     case 8: hipLaunchKernelGGL((k_fwd_csr<M, V, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
     case 16: hipLaunchKernelGGL((k_fwd_csr<M, V, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;
     case 32: hipLaunchKernelGGL((k_fwd_csr<M, V, 32>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_fwd_csr<M, V, 64>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    default:
+        if (LSQR_FWD_PIPE) hipLaunchKernelGGL((k_fwd_pipe<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_fwd_csr<M, V, 64>), dim3(grid), dim3(kBlock), 0, st, a);
+        break;
     }
 }
 
@@ -1136,7 +1307,7 @@ hipError_t fwd_launch(hipStream_t st, const Problem &P, int grid, const RowFmt &
     FwdArgs a{R.rp, R.ci, R.run_ptr, R.runs, R.roff, R.val, R.sigma, R.rmask, R.rbase, R.rcol,
               P.m, (int)P.n, P.nx, P.ny,
               P.nz, P.w, P.damp, z, Tprev, Tcur, Ts, part_out, part_v, np_v, S, ctl, parity,
-              mode, tol};
+              mode, tol, R.wrow, R.wgrid};
     if constexpr (Wide<V>::value) {
         if (R.vt != VT_F64) return hipErrorInvalidValue;
         fwd_launch_m<double, V>(st, grid, R, a);
@@ -1149,6 +1320,26 @@ hipError_t fwd_launch(hipStream_t st, const Problem &P, int grid, const RowFmt &
         }
     }
     return hipGetLastError();
+}
+
+// Workgroups of k_fwd_pipe per compute unit for R's value type.
+template <class V>
+int fwd_pipe_blocks_per_cu(const RowFmt &R)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if constexpr (Wide<V>::value) {
+        if (R.vt == VT_F64)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_pipe<double, V>, kBlock, 0);
+    } else {
+        switch (R.vt) {
+        case VT_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_pipe<float, V>, kBlock, 0); break;
+        case VT_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_pipe<bf16_t, V>, kBlock, 0); break;
+        case VT_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_pipe<fp16_t, V>, kBlock, 0); break;
+        default: break;
+        }
+    }
+    return e == hipSuccess ? nb : 0;
 }
 
 template <class V>
@@ -1200,6 +1391,7 @@ hipError_t update_launch(hipStream_t st, const Problem &P, int grid, const doubl
 }
 
 #define LSQR_INSTANTIATE_LAUNCHERS(V)                                                            \
+    template int fwd_pipe_blocks_per_cu<V>(const RowFmt &);                                      \
     template hipError_t fwd_launch<V>(hipStream_t, const Problem &, int, const RowFmt &,         \
                                       const void *, const void *, void *, void *, double *,      \
                                       const double *, int, double *, int *, int, double, int);   \
