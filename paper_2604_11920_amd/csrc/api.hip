@@ -521,6 +521,11 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         CR_TRY(hipMemcpy(c->nvq, NR.nvq.data(), (4 * nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->nrow, NR.row.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->ndesc, NR.desc.data(), nr * sizeof(uint16_t), hipMemcpyHostToDevice));
+        if (o.flags & LSQR_FLAG_XCD_BANDS) {   // nodes in 8 bands, one per XCD
+            std::vector<int32_t> seg;
+            xcd_band_order(NR, nn, 8, NR.order, seg);
+            for (int x = 0; x < 9; ++x) c->nseg[x] = seg[(size_t)x];
+        }
         CR_TRY(hipMemcpy(c->norder, NR.order.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->nsrc, NR.src.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->ndst, NR.dst.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -593,6 +598,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if (use_nruns) {
         C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
         C.norder = c->norder; C.val = c->nval;
+        for (int x = 0; x < 9; ++x) C.nseg[x] = c->nseg[x];
     }
     set_node_masks(c, C);
     int vec = VT_F64;
@@ -827,6 +833,7 @@ lsqr_status lsqr_apply_t(lsqr_ctx *c, const double *y, double *x)
     if (c->nrp) {
         C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
         C.norder = c->norder; C.val = c->nval;
+        for (int x = 0; x < 9; ++x) C.nseg[x] = c->nseg[x];
     }
     set_node_masks(c, C);
     launch_adj(c->st, c->P, std::min(2048, c->eng.g_adj), VT_F64, C, c->d, y, y, nullptr, x,

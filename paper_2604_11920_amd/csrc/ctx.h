@@ -73,6 +73,7 @@ struct lsqr_ctx {
     // node runs of the data block (transposed product), values in node-major order
     int64_t *nrp = nullptr, *nvq = nullptr; uint32_t *nrow = nullptr; uint16_t *ndesc = nullptr;
     int32_t *norder = nullptr; double *nval = nullptr; float *nval32 = nullptr;
+    int nseg[9] = {0};             // XCD bands of norder (when requested)
     uint16_t *nvalq = nullptr; uint32_t *nsrc = nullptr, *ndst = nullptr;
     int64_t nnruns = 0;
     // run masks of the data rows (forward product over va)

@@ -700,6 +700,7 @@ struct AdjArgs {
     const uint32_t *nrow;
     const uint16_t *ndesc;
     const int32_t *norder;
+    int nseg[9];
     // node masks (k_adj_nmask): see ColFmt
     const int64_t *mrptr;
     const uint32_t *mrows;
@@ -858,13 +859,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int grp = lane / nz, iz = lane - grp * nz;
     const bool live = grp < ngr;
-    const int nnodes = a.n / nz;
-    const int G = gridDim.x;
+    // nodes: serpentine over norder, or, with XCD bands, over band
+    // (blockIdx mod 8) by the workgroups of that XCD
+    int G = gridDim.x, slot = blockIdx.x, nb0 = 0, nnodes = a.n / nz;
+    if (a.xcd_bands && G % 8 == 0) {
+        const int x = blockIdx.x & 7;
+        G >>= 3;
+        slot = blockIdx.x >> 3;
+        nb0 = a.nseg[x];
+        nnodes = a.nseg[x + 1] - nb0;
+    }
     double sq = 0.0;
     for (int s = 0; s * G < nnodes; ++s) {
-        const int idx = s * G + ((s & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        const int idx = s * G + ((s & 1) ? G - 1 - slot : slot);
         if (idx >= nnodes) continue;         // uniform over the workgroup
-        const int node = a.norder[idx];
+        const int node = a.norder[nb0 + idx];
         const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
         const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
         int64_t vb = a.nvq[4 * (int64_t)node + wid];
@@ -1350,8 +1359,9 @@ hipError_t adj_launch(hipStream_t st, const Problem &P, int grid, const ColFmt &
 {
     AdjArgs a{C.cp, C.ri, C.val, P.m, (int)P.n, P.nx, P.ny, P.nz, P.w, P.damp, d, T, Tg, v, q,
               part_out, part_t, np_t, S, ctl, parity, mode, data_only, C.xcd_bands,
-              C.nrp, C.nvq, C.nrow, C.ndesc, C.norder, C.mrptr, C.mrows, C.mcptr, C.mmask,
+              C.nrp, C.nvq, C.nrow, C.ndesc, C.norder, {}, C.mrptr, C.mrows, C.mcptr, C.mmask,
               C.mqoff};
+    for (int x = 0; x < 9; ++x) a.nseg[x] = C.nseg[x];
     switch (C.vt) {
     case VT_F64:
         if constexpr (Wide<V>::value) adj_launch_m<double, V>(st, grid, C, a);

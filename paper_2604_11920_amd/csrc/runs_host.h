@@ -167,6 +167,36 @@ inline bool build_node_runs_host(int64_t m, int64_t n, int nz, const int64_t *rp
     return off == nnz;
 }
 
+// XCD bands of the lateral nodes for the transposed product: the node range
+// [0, nn) is cut into nb contiguous bands of about equal cost (stored values
+// plus 8 per run), each band's nodes sorted by decreasing run count (stable).
+// Band x occupies order[seg[x] .. seg[x+1]).  The kernel gives band x to the
+// workgroups that the dispatcher places on XCD x, so the t entries of the rays
+// that cross a band are reused from that XCD's L2.
+inline void xcd_band_order(const NodeRuns &R, int64_t nn, int nb, std::vector<int32_t> &order,
+                           std::vector<int32_t> &seg)
+{
+    std::vector<int64_t> pre((size_t)nn + 1, 0);
+    for (int64_t k = 0; k < nn; ++k)
+        pre[(size_t)k + 1] = pre[(size_t)k] + (R.nvq[(size_t)(4 * k + 4)] - R.nvq[(size_t)(4 * k)]) +
+                             8 * (R.nrp[(size_t)k + 1] - R.nrp[(size_t)k]);
+    seg.assign((size_t)nb + 1, 0);
+    for (int x = 1; x < nb; ++x) {
+        const int64_t target = (int64_t)(((__int128)pre[(size_t)nn] * x) / nb);
+        seg[(size_t)x] = (int32_t)(std::lower_bound(pre.begin(), pre.end(), target) - pre.begin());
+        if (seg[(size_t)x] < seg[(size_t)x - 1]) seg[(size_t)x] = seg[(size_t)x - 1];
+    }
+    seg[(size_t)nb] = (int32_t)nn;
+    order.resize((size_t)nn);
+    for (int64_t k = 0; k < nn; ++k) order[(size_t)k] = (int32_t)k;
+    for (int x = 0; x < nb; ++x)
+        std::stable_sort(order.begin() + seg[(size_t)x], order.begin() + seg[(size_t)x + 1],
+                         [&](int32_t a, int32_t b) {
+                             return R.nrp[(size_t)a + 1] - R.nrp[(size_t)a] >
+                                    R.nrp[(size_t)b + 1] - R.nrp[(size_t)b];
+                         });
+}
+
 // Run masks of the data rows (forward product over the CSR values).  A run is
 // a maximal stretch of consecutive columns inside a row.  Bit p of the global
 // mask (word p / 64, bit p % 64) is set when stored entry p starts a run;

@@ -210,6 +210,21 @@ def test_early_iterates_strict(cfg0, precond, fmt):
             assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0), K
 
 
+@pytest.mark.parametrize("col_format", ["runs", "csc"])
+def test_xcd_bands_iterates(cfg0, col_format):
+    # each XCD's workgroups take a band of nodes (node runs) or columns (CSC):
+    # same iterates as the oracle, only the partial sums are grouped otherwise
+    for s in (cfg0, synth.random_system(500, 8, 6, 5, row_len=(0, 50), seed=31)):
+        op = oracle.Operator.from_system(s)
+        with from_sys(s, col_format=col_format, xcd_bands=True) as sol:
+            for K in (1, 3, 8):
+                ref = op.lsqr(s.dt, K)
+                dm, hist, info = sol.solve(s.dt, K)
+                assert info["iters"] == K
+                assert rel(dm, ref["x"]) <= 1e-10, (K, rel(dm, ref["x"]))
+                assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0), K
+
+
 @pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"), ("none", "csc"),
                                          ("none", "runs"), ("none", "masks")])
 def test_converged_strict(cfg0, cfg0_xstar, precond, fmt):
