@@ -273,8 +273,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32 rate and the time-to-tolerance comparisons")
     ap.add_argument("--ttt-tol", type=float, default=1e-6)
-    ap.add_argument("--model", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp.npz"),
-                    help="learned column-scale model for the learned time-to-tolerance forms")
+    ap.add_argument("--model", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp_cfg1.npz"),
+                    help="learned column-scale model for the learned time-to-tolerance forms "
+                         "(default: the model fitted on config-1-geometry training systems)")
     ap.add_argument("--batched", action="store_true",
                     help="measure the batched multi-RHS form instead (one JSON line)")
     ap.add_argument("--copy-calib", action="store_true",

@@ -14,6 +14,21 @@ Three steps, each resumable on its own:
     python -m paper_2604_11920_amd.train_scale eval --model paper_2604_11920_amd/colscale_mlp.npz \
         --family cfg0 --first 1001 --count 20 --report report.json
 
+Shipped models: colscale_mlp.npz (fitted on cfg0 and cfg1 targets) and
+colscale_mlp_cfg1.npz (fitted on config-1-geometry targets only: cfg1 seeds
+1-6, and cfg1large seeds 1-5, depth family, one search round; the benchmark
+system itself, seed 0 with 229 stations, is not among them):
+
+    python -m paper_2604_11920_amd.train_scale search --family cfg1 --first 1 --count 6 \
+        --param depth --rounds 1 --out targets_cfg1_depth.npz
+    python -m paper_2604_11920_amd.train_scale search --family cfg1large --first 1 --count 2 \
+        --param depth --rounds 1 --out targets_cfg1large_a.npz
+    python -m paper_2604_11920_amd.train_scale search --family cfg1large --first 3 --count 3 \
+        --param depth --rounds 1 --out targets_cfg1large_b.npz
+    python -m paper_2604_11920_amd.train_scale fit targets_cfg1_depth.npz \
+        targets_cfg1large_a.npz targets_cfg1large_b.npz --epochs 40 \
+        --out paper_2604_11920_amd/colscale_mlp_cfg1.npz
+
 Families: "cfg0" = config-0 geometry (16x16x9) with 20-60 stations and damping
 0.05-0.5; "cfg1" = config-1 geometry (80x80x20) with 30-80 stations and 6-12
 periods; "cfg1large" = config-1 geometry with 100-200 stations and 14-20
