@@ -103,14 +103,15 @@ lsqr_status setup_engine(lsqr_ctx *c, Engine &E, int vec, const RowFmt &R, const
     E.C = C;
     if (R.run_ptr) E.g_fwd = cap_blocks(std::max<int64_t>(m * 64, 2 * n), kBlock, 2048);
     else E.g_fwd = cap_blocks(std::max<int64_t>(m * R.lpr, 2 * n), kBlock, 2048);
-    // pipelined CSR rows: as many workgroups as the device holds at once, each
-    // wave on a contiguous row range balanced in entries
+    // pipelined CSR rows: as many workgroups as the device holds at once, on
+    // contiguous row ranges balanced in entries
     const int gp = m > 0 ? fwd_pipe_grid(vec, R) : 0;
     if (gp > 0) {
         E.g_fwd = gp;
-        E.wrow = ctx_alloc<int32_t>(c, 4 * (int64_t)gp + 1);
+        const int parts = fwd_pipe_parts(gp);
+        E.wrow = ctx_alloc<int32_t>(c, (int64_t)parts + 1);
         if (!E.wrow) return fail(c, LSQR_E_OOM, "device allocation failed");
-        launch_wave_rows(c->st, R.rp, m, 4 * gp, E.wrow);
+        launch_wave_rows(c->st, R.rp, m, parts, E.wrow);
         E.R.wrow = E.wrow;
         E.R.wgrid = gp;
     }

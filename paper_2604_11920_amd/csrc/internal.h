@@ -87,10 +87,11 @@ struct RowFmt {
     const uint64_t *rmask = nullptr;   // [ceil(nnz / 64)]
     const uint32_t *rbase = nullptr;   // [ceil(nnz / 64)]
     const int32_t *rcol = nullptr;     // [runs]
-    // plain CSR with 64 lanes per row: wave w of a launch of wgrid workgroups
-    // takes rows wrow[w] .. wrow[w+1]-1 (contiguous, balanced in entries);
+    // plain CSR with 64 lanes per row: a launch of wgrid workgroups takes
+    // contiguous row ranges balanced in entries, wrow[p] .. wrow[p+1]-1, one
+    // per workgroup (its waves interleaved) or per wave (fwd_pipe_parts);
     // other launch sizes take rows w, w + waves, ...
-    const int32_t *wrow = nullptr;     // [4 wgrid + 1]
+    const int32_t *wrow = nullptr;     // [fwd_pipe_parts(wgrid) + 1]
     int wgrid = 0;
 };
 
@@ -130,6 +131,7 @@ void launch_init(hipStream_t st, const Problem &P, int grid, int vec, const doub
 // Workgroups of the pipelined CSR forward product that the device holds at
 // once (0 when R does not use it), and its balanced wave partition.
 int fwd_pipe_grid(int vec, const RowFmt &R);
+int fwd_pipe_parts(int grid);          // row ranges of the balanced partition for a grid
 void launch_wave_rows(hipStream_t st, const int64_t *rp, int64_t m, int waves, int32_t *wrow);
 void launch_fwd(hipStream_t st, const Problem &P, int grid, int vec, const RowFmt &R,
                 const void *z, const void *Tprev, void *Tcur, void *Ts, double *part_out,

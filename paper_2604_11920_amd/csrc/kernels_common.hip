@@ -28,10 +28,11 @@ hipError_t update_launch(hipStream_t, const Problem &, int, const double *, cons
 template <class V>
 int fwd_pipe_blocks_per_cu(const RowFmt &);
 
-// Balanced wave partition of the CSR rows: boundary w is the first row r with
-// rp[r] + kRowCost r >= w (nnz + kRowCost m) / waves (each row also costs a
-// reduction and a store, counted as kRowCost entries).  One thread per boundary,
-// binary search; boundaries are non-decreasing, wrow[0] = 0, wrow[waves] = m.
+// Balanced partition of the CSR rows into `waves` contiguous ranges: boundary
+// w is the first row r with rp[r] + kRowCost r >= w (nnz + kRowCost m) / waves
+// (each row also costs a reduction and a store, counted as kRowCost entries).
+// One thread per boundary, binary search; boundaries are non-decreasing,
+// wrow[0] = 0, wrow[waves] = m.
 constexpr int64_t kRowCost = 64;
 
 __global__ void k_wave_rows(const int64_t *rp, int64_t m, int waves, int32_t *wrow)
@@ -54,6 +55,8 @@ void launch_wave_rows(hipStream_t st, const int64_t *rp, int64_t m, int waves, i
     hipLaunchKernelGGL(k_wave_rows, dim3((waves + 1 + 255) / 256), dim3(256), 0, st, rp, m, waves,
                        wrow);
 }
+
+int fwd_pipe_parts(int grid) { return LSQR_FWD_WG_ROWS ? grid : grid * (kBlock / 64); }
 
 int fwd_pipe_grid(int vec, const RowFmt &R)
 {

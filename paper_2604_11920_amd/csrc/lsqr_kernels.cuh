@@ -374,6 +374,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd_csr(FwdArgs a)
 #ifndef LSQR_FWD_PIPE_U
 #define LSQR_FWD_PIPE_U 8
 #endif
+// 1: the balanced row ranges belong to workgroups and the workgroup's 4 waves
+// take its rows in turn (neighbouring rows share columns, so their v gathers
+// meet in L1); 0: each wave has its own range.
+#ifndef LSQR_FWD_WG_ROWS
+#define LSQR_FWD_WG_ROWS 1
+#endif
 
 // A load through the constant address space: with a wave-uniform index it
 // becomes a scalar load, whose wait does not hold up the vector loads in
@@ -433,9 +439,15 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pipe(FwdArgs a)
     const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
     int row = wave, rend = (int)a.m, wstride = gridDim.x * (kBlock / 64);
     if (a.wrow && a.wgrid == (int)gridDim.x) {
-        row = ld_uniform(a.wrow, wave);
-        rend = ld_uniform(a.wrow, wave + 1);
-        wstride = 1;
+        if (LSQR_FWD_WG_ROWS) {
+            row = ld_uniform(a.wrow, (int)blockIdx.x) + (wave & 3);
+            rend = ld_uniform(a.wrow, (int)blockIdx.x + 1);
+            wstride = kBlock / 64;
+        } else {
+            row = ld_uniform(a.wrow, wave);
+            rend = ld_uniform(a.wrow, wave + 1);
+            wstride = 1;
+        }
     }
     if (a.m > 0 && a.rp[a.m] == 0) {                      // no stored entries: rows of zeros
         for (; row < rend; row += wstride)
