@@ -145,6 +145,7 @@ def time_to_tol(s, dt, tol, fmt, model_path=None):
     forms = [("fp64", "none", 20000, 0.0), ("fp64", "jacobi", 20000, 0.0),
              ("fp64", "jacobi_lsmr", 20000, 0.0),
              ("bf16", "jacobi", 4000, 0.0), ("bf16", "jacobi", 4000, 1e-3),
+             ("bf16", "jacobi_lsmr", 4000, 0.0),
              ("fp16", "jacobi", 4000, 0.0)]
     model = None
     if model_path and os.path.exists(model_path):

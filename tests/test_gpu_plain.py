@@ -282,6 +282,34 @@ def test_ragged_system_strict(fmt):
         assert rel(dm, ref["x"]) <= 1e-10, K
 
 
+@pytest.mark.parametrize("which", ["ragged", "cfg0", "no_entries"])
+def test_pipelined_forward_rows(cfg0, which):
+    # 64 lanes per row selects the pipelined forward product: solves use its
+    # balanced row ranges, the plain products its strided rows; empty rows,
+    # rows shorter than a batch and longer than several, and a system with no
+    # stored entry at all
+    if which == "ragged":
+        s = ragged_system(7)
+    elif which == "cfg0":
+        s = cfg0
+    else:
+        s = synth.RandomSystem(m=300, n=60, nx=4, ny=3, nz=5, row_ptr=np.zeros(301, np.int64),
+                               col=np.zeros(0, np.int32), val=np.zeros(0),
+                               dt=np.random.default_rng(1).standard_normal(300), damp=0.1,
+                               smooth=0.5)
+    op = oracle.Operator.from_system(s)
+    x = np.random.default_rng(5).standard_normal(s.n)
+    with from_sys(s, lanes_per_row=64) as sol:
+        for K in (1, 3, 8):
+            ref = op.lsqr(s.dt, K)
+            dm, hist, info = sol.solve(s.dt, K)
+            assert info["istop"] == ref["istop"] and info["iters"] == ref["iters"]
+            assert rel(dm, ref["x"]) <= 1e-10, (K, rel(dm, ref["x"]))
+        y = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    yr = op.apply(x)
+    assert np.abs(y - yr).max() <= 1e-12 * max(np.abs(yr).max(), 1.0)
+
+
 @pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks"])
 def test_small_shapes(fmt):
     rf, cf = FORMATS[fmt]
