@@ -240,7 +240,10 @@ lsqr_status lsqr_apply_t_block(lsqr_ctx *ctx, int nrhs, const float *y, float *x
 
 /* Schedule of the batched kernels: right-hand sides per kernel pass (8, 16 or
  * 32; smaller tiles re-read the matrix, larger ones gather wider rows of the
- * vector blocks) and the cap on workgroups per launch. */
+ * vector blocks; with node runs, 32-wide tiles run both products on the
+ * matrix cores, per lateral node: the forward product as per-run partial rows
+ * then per-row sums, the transposed product reduced over the node's runs) and
+ * the cap on workgroups per launch. */
 typedef struct {
     int rhs_tile;
     int grid;

@@ -531,6 +531,16 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         CR_TRY(hipMemcpy(c->nsrc, NR.src.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->ndst, NR.dst.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         launch_gather_runs(st, nr, c->nsrc, c->ndst, c->ndesc, c->va, c->nval, 8);
+        if (G->nz <= 32) {        // row order of the runs, for the batched forward product
+            std::vector<int64_t> rrp;
+            std::vector<uint32_t> rrid;
+            row_order_of_runs(NR, m, rrp, rrid);
+            c->rrp = ctx_alloc<int64_t>(c, m + 1);
+            c->rrid = ctx_alloc<uint32_t>(c, nr);
+            if (!c->rrp || !c->rrid) return bail(LSQR_E_OOM, "device allocation failed");
+            CR_TRY(hipMemcpy(c->rrp, rrp.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+            CR_TRY(hipMemcpy(c->rrid, rrid.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
+        }
         use_nruns = true;
     }
     // run masks of the data rows (index the CSR values directly)

@@ -31,6 +31,7 @@ BArgs base_args(lsqr_ctx *c, BatchEngine &B)
     if (c->nval32 && c->P.nz <= kMaxNzBatched) {   // transposed product over node runs
         a.nrp = c->nrp; a.nvq = c->nvq; a.nrow = c->nrow; a.ndesc = c->ndesc;
         a.norder = c->norder; a.nval = c->nval32;
+        if (B.Pr) { a.rrp = c->rrp; a.rrid = c->rrid; a.Pr = B.Pr; a.g_pr = B.g_adj; }
     }
     a.d = c->d;
     a.m = c->P.m; a.n = (int)c->P.n; a.nx = c->P.nx; a.ny = c->P.ny; a.nz = c->P.nz;
@@ -45,9 +46,19 @@ void launch_tile(hipStream_t st, int kind, int grid, const BArgs &a)
 {
     switch (kind) {
     case 0: hipLaunchKernelGGL((k_binit<RT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_bfwd<RT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 1:
+        if (a.Pr && RT == 32) {       // two-phase product over the node runs
+            hipLaunchKernelGGL(k_bfwd_pr32, dim3(a.g_pr), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_bfwd<RT>), dim3(grid), dim3(kBlock), 0, st, a);
+        } else {                      // entry-wise over the CSR rows
+            BArgs b = a;
+            b.Pr = nullptr;
+            hipLaunchKernelGGL((k_bfwd<RT>), dim3(grid), dim3(kBlock), 0, st, b);
+        }
+        break;
     default:
-        if (a.nrp) hipLaunchKernelGGL((k_badj_nruns<RT>), dim3(grid), dim3(kBlock), 0, st, a);
+        if (a.nrp && RT == 32) hipLaunchKernelGGL(k_badj_mfma32, dim3(grid), dim3(kBlock), 0, st, a);
+        else if (a.nrp) hipLaunchKernelGGL((k_badj_nruns<RT>), dim3(grid), dim3(kBlock), 0, st, a);
         else hipLaunchKernelGGL((k_badj<RT>), dim3(grid), dim3(kBlock), 0, st, a);
         break;
     }
@@ -104,7 +115,8 @@ lsqr_status ensure_batch(lsqr_ctx *c, hipStream_t st, int R, int iters)
     if (B.R != R) {
         for (void *p : {(void *)B.T[0], (void *)B.T[1], (void *)B.V, (void *)B.Q, (void *)B.Z,
                         (void *)B.W, (void *)B.Y, (void *)B.rhs, (void *)B.dm, (void *)B.P1,
-                        (void *)B.P2, (void *)B.P3, (void *)B.act, (void *)B.why, (void *)B.ctl})
+                        (void *)B.P2, (void *)B.P3, (void *)B.act, (void *)B.why, (void *)B.ctl,
+                        (void *)B.Pr})
             if (p) ctx_release(c, p);
         const int keep_rt = B.tuned ? B.rt : 0, keep_grid = B.tuned ? B.grid : 0;
         B = BatchEngine{};
@@ -129,6 +141,11 @@ lsqr_status ensure_batch(lsqr_ctx *c, hipStream_t st, int R, int iters)
         if (!B.T[0] || !B.T[1] || !B.V || !B.Q || !B.Z || !B.W || !B.Y || !B.rhs || !B.dm ||
             !B.P1 || !B.P2 || !B.P3 || !B.act || !B.why || !B.ctl)
             return fail(c, LSQR_E_OOM, "device allocation failed");
+        // per-run partial rows of the two-phase forward product (node runs)
+        if (c->rrid && c->nval32 && c->P.nz <= kMaxNzBatched) {
+            B.Pr = ctx_alloc<float>(c, std::max<int64_t>(c->nnruns, 1) * R);
+            if (!B.Pr) return fail(c, LSQR_E_OOM, "device allocation failed");
+        }
     }
     const int64_t need = (int64_t)iters + 2;
     if (B.s_rows < need) {

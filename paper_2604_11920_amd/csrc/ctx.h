@@ -42,6 +42,7 @@ struct BatchEngine {
     float *V = nullptr, *Q = nullptr, *Z = nullptr;
     double *W = nullptr, *Y = nullptr, *rhs = nullptr, *dm = nullptr;
     double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
+    float *Pr = nullptr;           // [node runs][R] per-run partial sums of the forward product
     double *S = nullptr;
     int64_t s_rows = 0;
     int *act = nullptr, *why = nullptr, *ctl = nullptr;
@@ -74,6 +75,7 @@ struct lsqr_ctx {
     int64_t *nrp = nullptr, *nvq = nullptr; uint32_t *nrow = nullptr; uint16_t *ndesc = nullptr;
     int32_t *norder = nullptr; double *nval = nullptr; float *nval32 = nullptr;
     int nseg[9] = {0};             // XCD bands of norder (when requested)
+    int64_t *rrp = nullptr; uint32_t *rrid = nullptr;   // row order of the node runs (batched forward)
     uint16_t *nvalq = nullptr; uint32_t *nsrc = nullptr, *ndst = nullptr;
     int64_t nnruns = 0;
     // run masks of the data rows (forward product over va)

@@ -20,6 +20,7 @@
 namespace lsqr {
 
 constexpr int kMaxRhs = 32;
+constexpr int kMaxNzBatched = 32;      // node-run block products: depths per node
 
 // Stored entries per lane in flight in the batched products.
 #ifndef LSQR_BATCH_UNROLL
@@ -44,6 +45,13 @@ struct BArgs {
     const uint16_t *ndesc;
     const int32_t *norder;
     const float *nval;
+    // two-phase forward product over the node runs: per-run partial rows Pr
+    // (k_bfwd_pr, a workgroup per node), then per-row sums over the row's runs
+    // rrid[rrp[i] .. rrp[i+1]) (k_bfwd); Pr == nullptr: entry-wise CSR
+    const int64_t *rrp;
+    const uint32_t *rrid;
+    float *Pr;              // [node runs][R]
+    int g_pr;               // workgroups of k_bfwd_pr
     const double *d;
     int64_t m;
     int n, nx, ny, nz;
@@ -193,26 +201,43 @@ __global__ __launch_bounds__(kBlock) void k_bfwd(BArgs a)
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
     for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); row < a.m;
          row += nwaves) {
-        const int64_t s = a.rp[row], e = a.rp[row + 1];
         float ac[kBatchUnroll];
 #pragma unroll
         for (int u = 0; u < kBatchUnroll; ++u) ac[u] = 0.f;
-        int64_t p = s + er;
-        for (; p + (kBatchUnroll - 1) * EPW < e; p += kBatchUnroll * EPW) {
-            float g[kBatchUnroll];
-            int c[kBatchUnroll];
+        if (a.Pr) {
+            // sums of the row's per-run partials, in the order of its entries
+            const int64_t s = a.rrp[row], e = a.rrp[row + 1];
+            int64_t p = s + er;
+            for (; p + (kBatchUnroll - 1) * EPW < e; p += kBatchUnroll * EPW) {
+                uint32_t q[kBatchUnroll];
 #pragma unroll
-            for (int u = 0; u < kBatchUnroll; ++u) {
-                g[u] = __builtin_nontemporal_load(a.va + p + u * EPW);
-                c[u] = __builtin_nontemporal_load(a.ci + p + u * EPW);
+                for (int u = 0; u < kBatchUnroll; ++u) q[u] = __builtin_nontemporal_load(a.rrid + p + u * EPW);
+#pragma unroll
+                for (int u = 0; u < kBatchUnroll; ++u)
+                    ac[u] += __builtin_nontemporal_load(a.Pr + (int64_t)q[u] * R + cofs);
             }
+            for (; p < e; p += EPW)
+                ac[0] += __builtin_nontemporal_load(
+                    a.Pr + (int64_t)__builtin_nontemporal_load(a.rrid + p) * R + cofs);
+        } else {
+            const int64_t s = a.rp[row], e = a.rp[row + 1];
+            int64_t p = s + er;
+            for (; p + (kBatchUnroll - 1) * EPW < e; p += kBatchUnroll * EPW) {
+                float g[kBatchUnroll];
+                int c[kBatchUnroll];
 #pragma unroll
-            for (int u = 0; u < kBatchUnroll; ++u)
-                ac[u] = fmaf(g[u], a.Z[(int64_t)c[u] * R + cofs], ac[u]);
+                for (int u = 0; u < kBatchUnroll; ++u) {
+                    g[u] = __builtin_nontemporal_load(a.va + p + u * EPW);
+                    c[u] = __builtin_nontemporal_load(a.ci + p + u * EPW);
+                }
+#pragma unroll
+                for (int u = 0; u < kBatchUnroll; ++u)
+                    ac[u] = fmaf(g[u], a.Z[(int64_t)c[u] * R + cofs], ac[u]);
+            }
+            for (; p < e; p += EPW)
+                ac[0] = fmaf(__builtin_nontemporal_load(a.va + p),
+                             a.Z[(int64_t)__builtin_nontemporal_load(a.ci + p) * R + cofs], ac[0]);
         }
-        for (; p < e; p += EPW)
-            ac[0] = fmaf(__builtin_nontemporal_load(a.va + p),
-                         a.Z[(int64_t)__builtin_nontemporal_load(a.ci + p) * R + cofs], ac[0]);
         float acc = tree_sum<kBatchUnroll>(ac);
 #pragma unroll
         for (int off = RT; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
@@ -253,6 +278,110 @@ __global__ __launch_bounds__(kBlock) void k_bfwd(BArgs a)
     }
     block_sum_rhs<RT>(sq, accs, res);
     if (threadIdx.x < RT) a.part_out[(int64_t)blockIdx.x * a.R + a.r0 + threadIdx.x] = res[threadIdx.x];
+}
+
+// First phase of the two-phase forward block product (32-wide tiles): for
+// every node run (row i, depths iz0 .. iz0+len-1 of lateral node k) the
+// partial row Pr[run, c] = sum_e val_e Z[k nz + iz0 + e, c] over the tile's
+// 32 right-hand sides.  Per node this is a dense product: the node's runs as
+// rows of a [runs x 32] matrix (run r holds its values at depths iz0 ..
+// iz0+len-1, zeros elsewhere; nz <= 32) times the node's [32 x 32] block of
+// Z, done on the matrix cores with v_mfma_f32_32x32x2f32, 32 runs by 32
+// right-hand sides per product, 16 products over the depth pairs.  A
+// workgroup per node (decreasing work, boustrophedon, as the transposed
+// product); its 4 waves take fixed quarters of the node's runs, stage the
+// values of 64 runs at a time in their own LDS area (all loads in flight
+// together) and keep the node's Z block as the B operand in registers.  The
+// Z gathers fall from one per stored entry to one per (node, depth).
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(kBlock) void k_bfwd_pr32(BArgs a)
+{
+    if (a.mode == MODE_ITER) {
+        const int k = a.ctl[C_CNT0 + a.parity];
+        if (k > a.ctl[C_KMAX]) return;
+    }
+    constexpr int kStage = 16;                     // value loads per lane in flight
+    __shared__ float vs[kBlock / 64][64 * kMaxNzBatched];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int hi = lane >> 5, j = lane & 31;       // MFMA operand row/column roles
+    const int R = a.R, nz = a.nz, nnodes = a.n / nz, G = gridDim.x;
+    float *my = vs[wid];
+    for (int s = 0; s * G < nnodes; ++s) {
+        const int idx = s * G + ((s & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        if (idx >= nnodes) continue;                        // uniform over the workgroup
+        const int node = a.norder[idx];
+        // B operand of product t: Z[node nz + 2t + hi][r0 + j] (zero past nz)
+        float zb[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int k = 2 * t + hi;
+            zb[t] = k < nz ? a.Z[((int64_t)node * nz + k) * R + a.r0 + j] : 0.f;
+        }
+        const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
+        const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
+        int64_t vb = a.nvq[4 * (int64_t)node + wid];
+        for (int64_t base = rs; base < re; base += 64) {
+            const int nr = (int)(re - base < 64 ? re - base : 64);
+            uint32_t dsc = 0u;
+            if (lane < nr) dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
+            const int len = (int)(dsc & 255u);
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            // (value offset in the chunk << 16) | (iz0 << 8) | len; offsets < 64 * 64
+            const uint32_t pk = ((uint32_t)(incl - len) << 16) | dsc;
+            const int tot = __shfl(incl, 63);               // >= 1: runs are not empty
+            // the chunk's values into the wave's LDS area, kStage loads per
+            // lane in flight (slots past the end read the last value, in
+            // bounds, and are not stored); the previous chunk's reads first
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i0 = 0; i0 < tot; i0 += 64 * kStage) {
+                float t[kStage];
+#pragma unroll
+                for (int k = 0; k < kStage; ++k) {
+                    const int i = i0 + 64 * k + lane;
+                    t[k] = __builtin_nontemporal_load(a.nval + vb + (i < tot ? i : tot - 1));
+                }
+#pragma unroll
+                for (int k = 0; k < kStage; ++k) {
+                    const int i = i0 + 64 * k + lane;
+                    if (i < tot) my[i] = t[k];
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int blk = 0; blk < nr; blk += 32) {
+                // A operand of product t: row j = run blk + j, column 2t + hi
+                const int r = blk + j;
+                const uint32_t p = __shfl(pk, r & 63);
+                const int rlen = r < nr ? (int)(p & 255u) : 0;
+                const int iz0 = (int)((p >> 8) & 255u);
+                const int voff = (int)(p >> 16);
+                floatx16 acc = {};
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const int e = 2 * t + hi - iz0;
+                    const bool in = (unsigned)e < (unsigned)rlen;
+                    const float v = my[in ? voff + e : 0];
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(in ? v : 0.f, zb[t], acc, 0, 0, 0);
+                }
+                // D[row][col]: col = lane mod 32, row = 8 (q / 4) + 4 hi + q mod 4
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int row = 8 * (q >> 2) + 4 * hi + (q & 3);
+                    if (blk + row < nr) a.Pr[(base + blk + row) * R + a.r0 + j] = acc[q];
+                }
+            }
+            vb += tot;
+        }
+    }
 }
 
 // ------------------------------------------------------------- transposed --
@@ -348,6 +477,130 @@ __global__ __launch_bounds__(kBlock) void k_badj(BArgs a)
     if (threadIdx.x < RT) a.part_out[(int64_t)blockIdx.x * a.R + a.r0 + threadIdx.x] = res[threadIdx.x];
 }
 
+// Transposed block product over node runs on the matrix cores (32-wide
+// tiles): per lateral node, Q_node[depth, c] = sum over the node's runs r of
+// V[r, depth] T[row_r, c], a product [32 depths x runs] x [runs x 32
+// right-hand sides] reduced over the runs by v_mfma_f32_32x32x2f32, two runs
+// per product (A: the runs' values at the 32 depths, zero outside their depth
+// windows, from the chunk staged in the wave's LDS area; B: the runs' rows of
+// T).  A workgroup per node (decreasing work, boustrophedon); its 4 waves
+// take fixed quarters of the node's runs, each accumulating in its own
+// matrix-core registers; the column sums add the waves in order.
+__global__ __launch_bounds__(kBlock) void k_badj_mfma32(BArgs a)
+{
+#pragma clang fp contract(off)
+    constexpr int RT = 32;
+    constexpr int kStage = 16;                     // value loads per lane in flight
+    constexpr int kPairs = 8;                      // products (run pairs) per batch
+    __shared__ double accs[kBlock];
+    __shared__ double res[kMaxRhs];
+    __shared__ double b2[kMaxRhs];
+    __shared__ float vs[kBlock / 64][64 * kMaxNzBatched];
+    __shared__ float wsum[kBlock / 64][kMaxNzBatched][RT];
+    const bool op = a.mode == MODE_OPERATOR;
+    int k = 0;
+    if (a.mode == MODE_ITER) {
+        k = a.ctl[C_CNT0 + a.parity];
+        if (k > a.ctl[C_KMAX]) return;
+    }
+    if (op) {
+        if (threadIdx.x < a.R) b2[threadIdx.x] = 1.0;
+        __syncthreads();
+    } else {
+        sum_rhs_all(a.part_in, a.np_in, a.R, accs, b2);
+    }
+    if (!op && blockIdx.x == 0 && threadIdx.x < RT) {
+        const int r = a.r0 + threadIdx.x;
+        srow(a, k, r)[S_BETA] = sqrt(b2[r]);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int hi = lane >> 5, j = lane & 31;       // MFMA operand roles
+    const int R = a.R, nz = a.nz, nnodes = a.n / nz, G = gridDim.x;
+    float *my = vs[wid];
+    double sq = 0.0;
+    for (int s = 0; s * G < nnodes; ++s) {
+        const int idx = s * G + ((s & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        if (idx >= nnodes) continue;                        // uniform over the workgroup
+        const int node = a.norder[idx];
+        const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
+        const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
+        int64_t vb = a.nvq[4 * (int64_t)node + wid];
+        floatx16 acc = {};
+        for (int64_t base = rs; base < re; base += 64) {
+            const int nr = (int)(re - base < 64 ? re - base : 64);
+            uint32_t dsc = 0u, row = 0u;
+            if (lane < nr) {
+                dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
+                row = __builtin_nontemporal_load(a.nrow + base + lane);
+            }
+            const int len = (int)(dsc & 255u);
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            // (value offset in the chunk << 16) | (iz0 << 8) | len; offsets < 64 * 64
+            const uint32_t pk = ((uint32_t)(incl - len) << 16) | dsc;
+            const int tot = __shfl(incl, 63);               // >= 1: runs are not empty
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i0 = 0; i0 < tot; i0 += 64 * kStage) {
+                float t[kStage];
+#pragma unroll
+                for (int q = 0; q < kStage; ++q) {
+                    const int i = i0 + 64 * q + lane;
+                    t[q] = __builtin_nontemporal_load(a.nval + vb + (i < tot ? i : tot - 1));
+                }
+#pragma unroll
+                for (int q = 0; q < kStage; ++q) {
+                    const int i = i0 + 64 * q + lane;
+                    if (i < tot) my[i] = t[q];
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // products over run pairs: A[depth j][run hi], B[run hi][rhs j]
+            for (int p0 = 0; p0 < nr; p0 += 2 * kPairs) {
+                float av[kPairs], bv[kPairs];
+#pragma unroll
+                for (int u = 0; u < kPairs; ++u) {
+                    const int r = p0 + 2 * u + hi;          // past nr: row 0, zero values
+                    const uint32_t pp = __shfl(pk, r & 63);
+                    const uint32_t rw = __shfl(row, r & 63);
+                    const int rlen = r < nr ? (int)(pp & 255u) : 0;
+                    const int e = j - (int)((pp >> 8) & 255u);
+                    const bool in = (unsigned)e < (unsigned)rlen;
+                    const float v = my[in ? (int)(pp >> 16) + e : 0];
+                    av[u] = in ? v : 0.f;
+                    bv[u] = a.Tcur[(int64_t)(r < nr ? rw : 0u) * R + a.r0 + j];
+                }
+#pragma unroll
+                for (int u = 0; u < kPairs; ++u)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], acc, 0, 0, 0);
+            }
+            vb += tot;
+        }
+        // D[depth][rhs]: rhs = lane mod 32, depth = 8 (q / 4) + 4 hi + q mod 4
+#pragma unroll
+        for (int q = 0; q < 16; ++q) wsum[wid][8 * (q >> 2) + 4 * hi + (q & 3)][j] = acc[q];
+        __syncthreads();
+        for (int cell = threadIdx.x; cell < nz * RT; cell += kBlock) {
+            const int cz = cell / RT, cr = cell % RT;
+            const float g = ((wsum[0][cz][cr] + wsum[1][cz][cr]) + wsum[2][cz][cr]) + wsum[3][cz][cr];
+            const int c = a.r0 + cr;
+            const double bc = sqrt(b2[c]);
+            sq += badj_col_out(a, (int64_t)node * nz + cz, c, g, bc, bc > 0.0 ? bc : 1.0);
+        }
+        __syncthreads();
+    }
+    // per-RHS partial sums: thread t's squares belong to rhs lane t % RT
+    block_sum_rhs<RT>(sq, accs, res);
+    if (threadIdx.x < RT) a.part_out[(int64_t)blockIdx.x * a.R + a.r0 + threadIdx.x] = res[threadIdx.x];
+}
+
 // Transposed block product over node runs (see k_adj_nruns): a workgroup per
 // lateral node, its 4 waves on fixed quarters of the node's runs, lanes in
 // 64/nz groups of nz lanes, lane iz of a group owning depth iz and keeping the
@@ -357,7 +610,6 @@ __global__ __launch_bounds__(kBlock) void k_badj(BArgs a)
 // val * T[row, :] to its RT accumulators.  The t gathers fall from one per
 // stored entry to one per run and no LDS is touched in the run loop.  Column
 // sums: groups in order (shuffles), then waves in order (LDS).
-constexpr int kMaxNzBatched = 32;
 
 template <int RT>
 __device__ __forceinline__ void ld_trow(const float *p, float *t)

@@ -197,6 +197,22 @@ inline void xcd_band_order(const NodeRuns &R, int64_t nn, int nb, std::vector<in
                          });
 }
 
+// Row order of the node runs: the runs of row i are rrid[rrp[i] .. rrp[i+1]),
+// node-major run indices in ascending node (= column) order, so a row's
+// per-run partial sums are added in the order of its stored entries.  A
+// stable counting sort of the node-major runs by row.
+inline void row_order_of_runs(const NodeRuns &R, int64_t m, std::vector<int64_t> &rrp,
+                              std::vector<uint32_t> &rrid)
+{
+    const int64_t nr = (int64_t)R.row.size();
+    rrp.assign((size_t)m + 1, 0);
+    for (int64_t r = 0; r < nr; ++r) ++rrp[(size_t)R.row[(size_t)r] + 1];
+    for (int64_t i = 0; i < m; ++i) rrp[(size_t)i + 1] += rrp[(size_t)i];
+    std::vector<int64_t> fill(rrp.begin(), rrp.end() - 1);
+    rrid.resize((size_t)nr);
+    for (int64_t r = 0; r < nr; ++r) rrid[(size_t)fill[(size_t)R.row[(size_t)r]]++] = (uint32_t)r;
+}
+
 // Run masks of the data rows (forward product over the CSR values).  A run is
 // a maximal stretch of consecutive columns inside a row.  Bit p of the global
 // mask (word p / 64, bit p % 64) is set when stored entry p starts a run;

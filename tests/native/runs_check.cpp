@@ -6,7 +6,8 @@
 //        uint32 row[]; uint32 src[]; uint32 dst[]; uint16 desc[]; int32 order[nnodes];
 //        int64 ok_rmask, nwords, nruns; uint64 mask[]; uint32 base[]; int32 rcol[];
 //        int64 ok_nmask, nnodes, nrows, nchunks; int64 rptr[]; uint32 rows[]; int64 cptr[];
-//        uint64 mask[nchunks nz]; int64 qoff[nnodes 4 nz]; int32 order[]
+//        uint64 mask[nchunks nz]; int64 qoff[nnodes 4 nz]; int32 order[];
+//        (node runs built) int64 rrp[m+1]; uint32 rrid[nnruns]  (row order of the runs)
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -69,6 +70,13 @@ int main(int argc, char **argv)
         put(fo, K.rptr.data(), K.rptr.size()); put(fo, K.rows.data(), K.rows.size());
         put(fo, K.cptr.data(), K.cptr.size()); put(fo, K.mask.data(), K.mask.size());
         put(fo, K.qoff.data(), K.qoff.size()); put(fo, K.order.data(), K.order.size());
+    }
+    // row order of the node runs
+    if (ok2) {
+        std::vector<int64_t> rrp;
+        std::vector<uint32_t> rrid;
+        lsqr::row_order_of_runs(R, m, rrp, rrid);
+        put(fo, rrp.data(), rrp.size()); put(fo, rrid.data(), rrid.size());
     }
     fclose(fo);
     return 0;

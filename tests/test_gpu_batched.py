@@ -129,6 +129,30 @@ def test_batched_deterministic_and_graph_equal(small_systems):
         sol.close()
 
 
+@pytest.mark.parametrize("grid", [256, 1024])
+def test_batched_32_wide_tiles_follow_oracle(small_systems, grid):
+    # 32-wide tiles take the matrix-core forms: the two-phase forward product
+    # (per-run partial rows, then per-row sums) and the transposed product
+    # reduced over runs on the matrix cores
+    from paper_2604_11920_amd import solve_batched
+    nrhs = 32
+    dts = [rhs_block(s, nrhs, i) for i, s in enumerate(small_systems)]
+    sols = [from_sys(s) for s in small_systems]
+    try:
+        for sol in sols:
+            sol.set_batch_config(32, grid)
+        dm, _, infos = solve_batched(sols, dts, 5)
+        dm2, _, _ = solve_batched(sols, dts, 5)
+    finally:
+        for sol in sols:
+            sol.close()
+    for i, s in enumerate(small_systems):
+        ref = oracle.Operator.from_system(s)
+        assert np.array_equal(dm[i], dm2[i])              # fixed summation orders
+        for r in (0, 9, 31):
+            assert rel(dm[i][:, r], ref.lsqr(dts[i][:, r], 5)["x"]) <= 1e-4, (i, r)
+
+
 def test_autotune_and_cache(small_systems, tmp_path):
     from paper_2604_11920_amd import solve_batched
     s = small_systems[2]

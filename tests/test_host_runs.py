@@ -5,7 +5,9 @@ built on the host from the CSR structure (csrc/runs_host.h); the kernels index
 memory with them, so they are checked here exhaustively against the CSR they
 describe: every stored entry covered exactly once, runs maximal, node runs in
 ascending row order, value offsets and quarter offsets consistent, the node
-order a stable sort by decreasing run count.
+order a stable sort by decreasing run count, and the row order of the node
+runs (the batched forward product's per-row sums) a permutation listing each
+row's runs in the order of its stored entries.
 """
 import os
 import shutil
@@ -82,6 +84,9 @@ def run_builders(exe, tmp, row_ptr, col, n, nz):
         out["m_mask"] = take(np.uint64, nch4 * nz)
         out["m_qoff"] = take(np.int64, nn4 * 4 * nz)
         out["m_order"] = take(np.int32, nn4)
+    if ok2:
+        out["rrp"] = take(np.int64, m + 1)
+        out["rrid"] = take(np.uint32, nr2)
     assert pos == len(buf)
     return out
 
@@ -292,3 +297,27 @@ def test_config0(driver, tmp_path):
     np.add.at(cov, last + 1, -1)
     assert np.all(np.cumsum(cov)[:-1] == 1)
     assert np.array_equal(dst.astype(np.int64), np.concatenate([[0], np.cumsum(ln)[:-1]]))
+
+
+def check_row_order(o, row_ptr, col, nz):
+    """rrid lists every node run once; row i's runs are those with row i, and
+    their stored entries, taken in the listed order, are row i's entries in
+    CSR order (so per-run partial sums are added in entry order)."""
+    rrp, rrid, row, src, desc = o["rrp"], o["rrid"], o["row"], o["src"], o["desc"]
+    m = len(row_ptr) - 1
+    assert rrp[0] == 0 and rrp[-1] == len(row) and np.all(np.diff(rrp) >= 0)
+    assert np.array_equal(np.sort(rrid), np.arange(len(row)))
+    for i in range(m):
+        ids = rrid[rrp[i]:rrp[i + 1]].astype(np.int64)
+        assert np.all(row[ids] == i)
+        ent = np.concatenate([src[r] + np.arange(desc[r] & 255) for r in ids]) if len(ids) else \
+            np.zeros(0, np.int64)
+        assert np.array_equal(ent, np.arange(row_ptr[i], row_ptr[i + 1]))
+
+
+def test_row_order_of_runs(driver, tmp_path):
+    for s in (synth.make_system(synth.small_config(nx=6, ny=5, nz=4, n_stations=10, seed=2)),
+              synth.random_system(300, 5, 4, 6, row_len=(0, 40), seed=9)):
+        o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
+        assert o["nodes_ok"]
+        check_row_order(o, s.row_ptr, s.col, s.nz)
