@@ -243,6 +243,28 @@ def batched_bench(args):
     wall = sum(per)
     rhs_its = len(sols) * R * iters * args.steps / wall
     sec_per_batched_iter = wall / (iters * args.steps)
+    # the block products of each system under its tuned schedule, timed apart
+    # (HIP events on the solver's stream, mean of 10 calls)
+    products = []
+    for sol in sols:
+        x = torch.randn(sol.n, R, device="cuda", dtype=torch.float32)
+        yb = torch.randn(sol.m + 2 * sol.n, R, device="cuda", dtype=torch.float32)
+        y = sol.apply_block(x)
+        xt = sol.apply_t_block(yb)
+        row = {}
+        for name, f in (("fwd_ms", lambda: sol.apply_block(x, y)),
+                        ("adj_ms", lambda: sol.apply_t_block(yb, xt))):
+            f()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                f()
+            e1.record()
+            torch.cuda.synchronize()
+            row[name] = e0.elapsed_time(e1) / 10
+        products.append(row)
+        log(f"[batched] block products: forward {row['fwd_ms']:.3f} ms, "
+            f"transposed {row['adj_ms']:.3f} ms")
     # matrix bytes of one batched iteration: FP32 CSR and CSC (value + index)
     mat_bytes = 2 * nnz * 8.0
     out = {"metric": "batched LSQR right-hand-side iterations/s", "value": rhs_its,
@@ -251,7 +273,8 @@ def batched_bench(args):
            "batched_iters_per_s": 1.0 / sec_per_batched_iter,
            "matrix_bytes_per_batched_iter": mat_bytes,
            "matrix_gbs": mat_bytes / sec_per_batched_iter / 1e9, "nnz_total": nnz,
-           "rows_total": rows, "tuned": tuned, "dtype": "f32 values/vectors, f64 scalars",
+           "rows_total": rows, "tuned": tuned, "block_products": products,
+           "dtype": "f32 values/vectors, f64 scalars",
            "data": "synthetic"}
     for sol in sols:
         sol.close()
