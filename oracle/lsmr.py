@@ -31,12 +31,16 @@ def _norm(x):
     return math.sqrt(float(np.dot(x, x)))
 
 
-def lsmr(op, dt, iters, tol=0.0):
-    """LSMR on the oracle operator `op` (oracle.Operator).  Returns
+def lsmr(op, dt, iters, tol=0.0, b=None):
+    """LSMR on the oracle operator `op` (oracle.Operator).  b: optional full
+    right-hand side [m + 2n] used instead of [dt; 0; 0].  Returns
     dict(x, hist [K+1, 3], istop, iters)."""
     m, n = op.m, op.n
-    b = np.zeros(op.mbar)
-    b[:m] = np.asarray(dt, dtype=np.float64)
+    if b is None:
+        b = np.zeros(op.mbar)
+        b[:m] = np.asarray(dt, dtype=np.float64)
+    else:
+        b = np.asarray(b, dtype=np.float64)
     hist = np.full((iters + 1, 3), np.nan)
     beta = _norm(b)
     if beta == 0.0:
