@@ -207,6 +207,25 @@ lsqr_status lsqr_solve(lsqr_ctx *ctx, const double *dt, lsqr_mem vec_mem, int it
                        double *dm, double *res_hist, lsqr_info *info);
 
 /*
+ * lsqr_solve_x0 — lsqr_solve started from an initial solution x0 (warm start),
+ * for the outer iterations of the inversion (the theoretical-framework section:
+ * the system of eq. (6) is solved again after each model update and
+ * re-linearisation) and for restarts and regularisation sweeps.  Plain forms:
+ * the solver runs on the correction problem A_D y ~ r0 = bbar - Abar x0 and
+ * returns dm = x0 + D y; its stopping ratio is rescaled so that eta keeps its
+ * meaning, |Abar^T (bbar - Abar dm)| / |Abar^T bbar| (LSMR: the D-scaled
+ * norms), in the history's eta column and info.eta as well (when
+ * Abar^T bbar = 0, eta is relative to |Abar^T r0|).  When x0 already satisfies
+ * the normal equations (Abar^T r0 = 0) nothing runs: dm = x0, istop 1, iters 0.
+ * BF16/FP16 forms: the FP64 refinement starts from x0 instead of 0.
+ *   x0   [n] initial solution (vec_mem), finite; may be the same device buffer
+ *        as dm.  Other arguments, outputs and errors as for lsqr_solve
+ *        (NONFINITE also for x0).
+ */
+lsqr_status lsqr_solve_x0(lsqr_ctx *ctx, const double *dt, const double *x0, lsqr_mem vec_mem,
+                          int iters, double tol, double *dm, double *res_hist, lsqr_info *info);
+
+/*
  * lsqr_solve_batched — LSQR for nrhs right-hand sides of each of nsys systems,
  * advanced together: sparse products read each system's matrix once per
  * right-hand-side tile (FP32 values and vectors, FP64 per-RHS scalars), and

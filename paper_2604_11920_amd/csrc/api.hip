@@ -670,11 +670,14 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
 #undef CR_TRY
 }
 
-static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, int iters, double tol, double *ddm,
-                               double *res_hist, lsqr_info *info);
+static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0, int iters,
+                               double tol, double *ddm, double *res_hist, lsqr_info *info);
+static lsqr_status solve_warm(lsqr_ctx *c, const double *ddt, int iters, double tol, double *ddm,
+                              double *res_hist, lsqr_info *info);
 
-lsqr_status lsqr_solve(lsqr_ctx *c, const double *dt, lsqr_mem vec_mem, int iters, double tol,
-                       double *dm, double *res_hist, lsqr_info *info)
+static lsqr_status solve_common(lsqr_ctx *c, const double *dt, const double *x0, lsqr_mem vec_mem,
+                                int iters, double tol, double *dm, double *res_hist,
+                                lsqr_info *info)
 {
     if (!c) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx is NULL");
     if (!dt || !dm) return fail(c, LSQR_E_INVALID_ARG, "dt and dm must not be NULL");
@@ -704,9 +707,28 @@ lsqr_status lsqr_solve(lsqr_ctx *c, const double *dt, lsqr_mem vec_mem, int iter
         if (c->hctl[0]) return fail(c, LSQR_E_NONFINITE, "non-finite value in dt");
     }
     double *ddm = vec_mem == LSQR_MEM_HOST ? c->dmbuf : dm;
+    // initial solution in: checked, then held in ddm (the mixed forms copy it)
+    if (x0) {
+        if (vec_mem == LSQR_MEM_HOST) {
+            for (int64_t j = 0; j < n; ++j)
+                if (!isfinite(x0[j])) return fail(c, LSQR_E_NONFINITE, "non-finite value in x0");
+            HIP_TRY(c, hipMemcpyAsync(ddm, x0, n * sizeof(double), hipMemcpyHostToDevice, st));
+        } else {
+            HIP_TRY(c, hipMemsetAsync(c->flag, 0, sizeof(int), st));
+            launch_check_vec(st, n, x0, 0, c->flag);
+            HIP_TRY(c, hipMemcpyAsync(c->hctl, c->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(c, hipStreamSynchronize(st));
+            if (c->hctl[0]) return fail(c, LSQR_E_NONFINITE, "non-finite value in x0");
+            if (x0 != ddm)
+                HIP_TRY(c, hipMemcpyAsync(ddm, x0, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        }
+    }
     lsqr_status s;
     if (mixed) {
-        s = solve_mixed(c, ddt, iters, tol, ddm, res_hist, info);
+        s = solve_mixed(c, ddt, x0 ? ddm : nullptr, iters, tol, ddm, res_hist, info);
+        if (s != LSQR_OK) return s;
+    } else if (x0) {
+        s = solve_warm(c, ddt, iters, tol, ddm, res_hist, info);
         if (s != LSQR_OK) return s;
     } else {
         const bool timing = (c->flags & LSQR_FLAG_TIMING) != 0;
@@ -735,6 +757,19 @@ lsqr_status lsqr_solve(lsqr_ctx *c, const double *dt, lsqr_mem vec_mem, int iter
     return LSQR_OK;
 }
 
+lsqr_status lsqr_solve(lsqr_ctx *c, const double *dt, lsqr_mem vec_mem, int iters, double tol,
+                       double *dm, double *res_hist, lsqr_info *info)
+{
+    return solve_common(c, dt, nullptr, vec_mem, iters, tol, dm, res_hist, info);
+}
+
+lsqr_status lsqr_solve_x0(lsqr_ctx *c, const double *dt, const double *x0, lsqr_mem vec_mem,
+                          int iters, double tol, double *dm, double *res_hist, lsqr_info *info)
+{
+    if (c && !x0) return fail(c, LSQR_E_INVALID_ARG, "x0 must not be NULL");
+    return solve_common(c, dt, x0, vec_mem, iters, tol, dm, res_hist, info);
+}
+
 // Iterative refinement of the quantised forms.  Each sweep: rbar = bbar -
 // Abar x with the FP64 operator; g = G^T r_G (FP64 values) and ghat =
 // Ghat^T r_G (the quantised values, FP64 arithmetic); the exact eta =
@@ -742,8 +777,8 @@ lsqr_status lsqr_solve(lsqr_ctx *c, const double *dt, lsqr_mem vec_mem, int iter
 // operator with right-hand side f = [r_G; r_L; r_D + (g - ghat)/lambda], for
 // which Ahat^T f = Abar^T rbar, so the refinement's fixed point is the FP64
 // solution; x += D y_inner.
-static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, int iters, double tol, double *ddm,
-                               double *res_hist, lsqr_info *info)
+static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0, int iters,
+                               double tol, double *ddm, double *res_hist, lsqr_info *info)
 {
     hipStream_t st = c->st;
     const Problem &P = c->P;
@@ -758,7 +793,8 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, int iters, double
         HIP_TRY(c, hipStreamSynchronize(st));
         return LSQR_OK;
     };
-    launch_fill(st, n, 0.0, c->xbuf);
+    if (dx0) HIP_TRY(c, hipMemcpyAsync(c->xbuf, dx0, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else launch_fill(st, n, 0.0, c->xbuf);
     // |Abar^T bbar| = |G^T dt|
     launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, nullptr, ddt, nullptr, c->gbuf, c->Pa,
                nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
@@ -774,10 +810,11 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, int iters, double
     } else {
         for (int sw = 0;; ++sw) {
             // FP64 residual and its normal-equation residual
-            if (sw > 0)
+            const bool from_x = sw > 0 || dx0;              // x != 0
+            if (from_x)
                 launch_fwd(st, P, E.g_fwd, VT_F64, c->R64, c->xbuf, nullptr, c->ybuf, nullptr,
                            c->Pf, nullptr, 0, nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
-            launch_residual(st, P, c->g_ref, ddt, sw > 0 ? c->ybuf : nullptr, c->rbar, c->sigma,
+            launch_residual(st, P, c->g_ref, ddt, from_x ? c->ybuf : nullptr, c->rbar, c->sigma,
                             c->rs, c->Pr);
             launch_sum_partials(st, c->Pr, c->g_ref, c->sums + 1);
             launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, nullptr, c->rbar, nullptr, c->gbuf,
@@ -818,6 +855,80 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, int iters, double
         info->fallback_used = c->fallback_used;
         info->eta = eta;
         info->phibar = rnorm;
+    }
+    return LSQR_OK;
+}
+
+// Warm start of the plain (FP64 / FP32) forms: x = x0 + D y with y the
+// solver's iterate on the correction problem A_D y ~ r0 = bbar - Abar x0 (a
+// full right-hand side).  The correction solve measures its stopping ratio
+// against |Abar^T r0| (LSQR; LSMR: |D Abar^T r0|), so its tolerance is the
+// caller's times |Abar^T bbar| / |Abar^T r0|, and its history's eta column is
+// rescaled by the inverse: eta keeps its meaning for the original problem.
+// x0 is in ddm already; the correction is added to it.
+static lsqr_status solve_warm(lsqr_ctx *c, const double *ddt, int iters, double tol, double *ddm,
+                              double *res_hist, lsqr_info *info)
+{
+    hipStream_t st = c->st;
+    const Problem &P = c->P;
+    const int64_t n = P.n, mb = P.m + 2 * n;
+    Engine &E = c->eng;
+    const int gadj = std::min(2048, E.g_adj);
+    if (!c->wr) c->wr = ctx_alloc<double>(c, mb);
+    if (!c->wg) c->wg = ctx_alloc<double>(c, n);
+    if (!c->wr || !c->wg) return fail(c, LSQR_E_OOM, "device allocation failed");
+    const double *dv = c->method == 1 ? c->d : c->ones;
+    // r0 = bbar - Abar x0 and |Abar^T r0|; then bbar and |Abar^T bbar|
+    launch_fwd(st, P, E.g_fwd, VT_F64, c->R64, ddm, nullptr, c->ybuf, nullptr, c->Pf, nullptr, 0,
+               nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
+    launch_residual(st, P, c->g_ref, ddt, c->ybuf, c->wr, nullptr, nullptr, c->Pr);
+    launch_adj(st, P, gadj, VT_F64, c->C64, dv, c->wr, c->wr, nullptr, c->wg, c->Pa, nullptr, 0,
+               nullptr, nullptr, 0, MODE_OPERATOR, 0);
+    launch_sum_partials(st, c->Pa, gadj, c->sums + 0);
+    launch_residual(st, P, c->g_ref, ddt, nullptr, c->ybuf, nullptr, nullptr, c->Pr);
+    launch_adj(st, P, gadj, VT_F64, c->C64, dv, c->ybuf, c->ybuf, nullptr, c->wg, c->Pa, nullptr, 0,
+               nullptr, nullptr, 0, MODE_OPERATOR, 0);
+    launch_sum_partials(st, c->Pa, gadj, c->sums + 1);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipMemcpyAsync(c->hsum, c->sums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    const double nr = sqrt(c->hsum[0]), nb = sqrt(c->hsum[1]);
+    if (!isfinite(nr)) return fail(c, LSQR_E_NONFINITE, "non-finite residual at x0");
+    // with Abar^T bbar = 0, eta is measured against |Abar^T r0| instead
+    const double ratio = nb > 0.0 ? nr / nb : 1.0;
+    if (!(nr > 0.0)) {                     // x0 satisfies the normal equations
+        if (res_hist)
+            for (int k = 0; k <= iters; ++k)
+                for (int f = 0; f < 3; ++f) res_hist[3 * k + f] = k == 0 ? 0.0 : NAN;
+        if (info) {
+            info->istop = 1;
+            info->iters = 0;
+            info->sweeps = 0;
+            info->fallback_used = c->fallback_used;
+            info->eta = 0.0;
+            info->phibar = 0.0;
+        }
+        return LSQR_OK;
+    }
+    const bool timing = (c->flags & LSQR_FLAG_TIMING) != 0;
+    if (timing) c->ks = lsqr_kstats{};
+    lsqr_status s = engine_solve(c, E, c->wr, 1, iters, tol > 0.0 ? tol / ratio : 0.0, ddm, 1, timing);
+    if (s != LSQR_OK) return s;
+    std::vector<double> hs;
+    if ((s = read_state(c, E, iters, hs)) != LSQR_OK) return s;
+    const int kdone = c->hctl[C_ITERS], istop = c->hctl[C_ISTOP];
+    if (res_hist) {
+        write_history(hs, iters, kdone, istop, res_hist);
+        for (int k = 0; k <= iters; ++k) res_hist[3 * k + 2] *= ratio;
+    }
+    if (info) {
+        info->istop = istop;
+        info->iters = kdone;
+        info->sweeps = 0;
+        info->fallback_used = c->fallback_used;
+        const double *Sk = hs.data() + (size_t)kdone * kStateWords;
+        info->eta = istop == 0 ? 0.0 : Sk[S_ETA] * ratio;
+        info->phibar = istop == 0 ? hs[S_BETA] : Sk[S_PHIBAR];
     }
     return LSQR_OK;
 }

@@ -101,6 +101,7 @@ struct lsqr_ctx {
     double *sums = nullptr;
     int g_ref = 1;
     double *dtbuf = nullptr, *dmbuf = nullptr;
+    double *wr = nullptr, *wg = nullptr;   // warm start: residual at x0 [m+2n], transposed product [n]
     int *flag = nullptr;
     int *hctl = nullptr;            // pinned host mirror of control words
     double *hsum = nullptr;         // pinned host mirror of reductions

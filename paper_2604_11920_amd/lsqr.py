@@ -88,6 +88,7 @@ def load():
     sig = {
         "lsqr_create": (I, [ctypes.POINTER(CSR), D, D, ctypes.POINTER(Opts), ctypes.POINTER(P)]),
         "lsqr_solve": (I, [P, P, I, I, D, P, P, ctypes.POINTER(Info)]),
+        "lsqr_solve_x0": (I, [P, P, P, I, I, D, P, P, ctypes.POINTER(Info)]),
         "lsqr_apply": (I, [P, P, P]),
         "lsqr_apply_t": (I, [P, P, P]),
         "lsqr_get_scale": (I, [P, P]),
@@ -223,24 +224,36 @@ class Solver:
         if rc != LSQR_OK:
             raise LsqrError(rc, self._lib.lsqr_last_error(self._ctx).decode())
 
-    def solve(self, dt, iters, tol=0.0, dm=None, history=True):
-        """Run LSQR.  dt: numpy (host) or torch CUDA float64 tensor (device).
-        Returns (dm, hist [iters+1, 3] or None, info dict)."""
+    def solve(self, dt, iters, tol=0.0, dm=None, history=True, x0=None):
+        """Run the solver.  dt: numpy (host) or torch CUDA float64 tensor
+        (device); x0: optional initial solution of the same kind (warm start,
+        lsqr_solve_x0).  Returns (dm, hist [iters+1, 3] or None, info dict)."""
         torch = self._torch
         if _is_torch(dt):
             assert dt.is_cuda and dt.dtype == torch.float64 and dt.is_contiguous()
             mem = MEM_DEVICE
             if dm is None:
                 dm = torch.empty(self.n, dtype=torch.float64, device=dt.device)
+            if x0 is not None:
+                assert _is_torch(x0) and x0.is_cuda and x0.dtype == torch.float64
+                x0 = x0.contiguous()
         else:
             dt = np.ascontiguousarray(dt, dtype=np.float64)
             mem = MEM_HOST
             if dm is None:
                 dm = np.empty(self.n)
+            if x0 is not None:
+                x0 = np.ascontiguousarray(x0, dtype=np.float64)
         hist = np.empty((iters + 1, 3)) if history else None
         info = Info()
-        self._check(self._lib.lsqr_solve(self._ctx, _ptr(dt), mem, int(iters), float(tol),
-                                         _ptr(dm), _ptr(hist), ctypes.byref(info)))
+        if x0 is None:
+            self._check(self._lib.lsqr_solve(self._ctx, _ptr(dt), mem, int(iters), float(tol),
+                                             _ptr(dm), _ptr(hist), ctypes.byref(info)))
+        else:
+            assert x0.shape == (self.n,)
+            self._check(self._lib.lsqr_solve_x0(self._ctx, _ptr(dt), _ptr(x0), mem, int(iters),
+                                                float(tol), _ptr(dm), _ptr(hist),
+                                                ctypes.byref(info)))
         return dm, hist, info.as_dict()
 
     def apply(self, x, y=None):
