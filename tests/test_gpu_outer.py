@@ -1,0 +1,114 @@
+"""GPU checks of the outer iterations with synthetic re-linearisation
+(paper_2604_11920_amd/outer.py) against a dense reference written here
+(numpy least squares on the same re-linearised systems): the model after
+two outer steps in both forms, the warm start reaching the cold start's
+solution at every step, the linear case (beta = 0) settling after one
+total-form step, and the RMS decrease of the update form.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from test_oracle_pins import kron_laplacian
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def geo():
+    return synth.make_system(synth.small_config(nx=6, ny=5, nz=4, n_stations=10, n_periods=4,
+                                                region=0.6, seed=3))
+
+
+def dense_outer(s, beta, d_obs, m0, steps, form):
+    """The outer iterations with dense least squares (no column scale)."""
+    G0 = sp.csr_matrix((s.val, s.col, s.row_ptr), shape=(s.m, s.n)).toarray()
+    reg = np.vstack([s.smooth * kron_laplacian(s.nx, s.ny, s.nz), s.damp * np.eye(s.n)])
+    T = lambda m: G0 @ m + 0.5 * beta * (G0 @ m) ** 2
+    m = m0.copy()
+    for _ in range(steps):
+        J = (1.0 + beta * (G0 @ m))[:, None] * G0
+        A = np.vstack([J, reg])
+        dd = d_obs - T(m)
+        if form == "update":
+            m = m + np.linalg.lstsq(A, np.r_[dd, np.zeros(2 * s.n)], rcond=None)[0]
+        else:
+            m = np.linalg.lstsq(A, np.r_[dd + J @ m, np.zeros(2 * s.n)], rcond=None)[0]
+    return m
+
+
+def problem(s, scale=0.3):
+    from paper_2604_11920_amd.outer import SyntheticForward
+    g0 = sp.csr_matrix((s.val, s.col, s.row_ptr), shape=(s.m, s.n)) @ s.m_true
+    beta = scale / np.abs(g0).max()
+    fwd = SyntheticForward(s, beta)
+    return fwd, beta, fwd.travel(s.m_true)
+
+
+@pytest.mark.parametrize("form", ["update", "total"])
+def test_two_outer_steps_match_dense_reference(geo, form):
+    from paper_2604_11920_amd.outer import gauss_newton
+    fwd, beta, d_obs = problem(geo)
+    try:
+        out = gauss_newton(fwd, d_obs, np.zeros(geo.n), outer=2, tol=1e-12, iters=40000,
+                           form=form)
+    finally:
+        fwd.close()
+    ref = dense_outer(geo, beta, d_obs, np.zeros(geo.n), 2, form)
+    assert rel(out["m"], ref) <= 1e-7, rel(out["m"], ref)
+
+
+def test_warm_start_reaches_the_cold_solution(geo):
+    from paper_2604_11920_amd.outer import gauss_newton
+    fwd, beta, d_obs = problem(geo)
+    try:
+        w = gauss_newton(fwd, d_obs, np.zeros(geo.n), outer=3, tol=1e-11, iters=40000,
+                         form="total", warm=True)
+        c = gauss_newton(fwd, d_obs, np.zeros(geo.n), outer=3, tol=1e-11, iters=40000,
+                         form="total", warm=False)
+    finally:
+        fwd.close()
+    assert rel(w["m"], c["m"]) <= 1e-6
+    # past the first step the warm start saves iterations
+    assert sum(w["iters"][1:]) < sum(c["iters"][1:])
+    print(f"[outer] warm {w['iters']} vs cold {c['iters']} iterations; rms {w['rms']}")
+
+
+def test_linear_case_settles_after_one_total_step(geo):
+    from paper_2604_11920_amd.outer import SyntheticForward, gauss_newton
+    fwd = SyntheticForward(geo, 0.0)
+    try:
+        d_obs = fwd.travel(geo.m_true)
+        out = gauss_newton(fwd, d_obs, np.zeros(geo.n), outer=2, tol=1e-12, iters=40000,
+                           form="total")
+        one = gauss_newton(fwd, d_obs, np.zeros(geo.n), outer=1, tol=1e-12, iters=40000,
+                           form="total")
+    finally:
+        fwd.close()
+    assert rel(out["m"], one["m"]) <= 1e-9
+    assert out["iters"][1] <= 1
+
+
+def test_update_form_decreases_rms(geo):
+    from paper_2604_11920_amd.outer import gauss_newton
+    fwd, beta, d_obs = problem(geo)
+    try:
+        out = gauss_newton(fwd, d_obs, np.zeros(geo.n), outer=4, tol=1e-10, iters=40000,
+                           form="update")
+    finally:
+        fwd.close()
+    assert np.all(np.diff(out["rms"]) <= 1e-12 * out["rms"][0]), out["rms"]
+    assert out["rms"][-1] < 0.5 * out["rms"][0]
