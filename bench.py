@@ -281,6 +281,34 @@ def batched_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def outer_bench(args):
+    """Outer iterations with synthetic re-linearisation on config 1 (3 steps,
+    total form, FP64 + Jacobi, eta <= 1e-6 per step): warm start from the
+    current model against a cold start, and the update form of eq. (6).
+    Prints one JSON line."""
+    import synth
+    from paper_2604_11920_amd.outer import SyntheticForward, gauss_newton
+    s = synth.make_system(synth.config1())
+    fwd = SyntheticForward(s, 0.0, precond="jacobi")
+    g0 = fwd.g0m(s.m_true)
+    fwd.beta = 0.3 / float(np.abs(g0).max())
+    d_obs = fwd.travel(s.m_true)
+    runs = {}
+    try:
+        for name, kw in (("total_warm", dict(form="total", warm=True)),
+                         ("total_cold", dict(form="total", warm=False)),
+                         ("update", dict(form="update"))):
+            out = gauss_newton(fwd, d_obs, np.zeros(s.n), outer=3, tol=1e-6, log=log, **kw)
+            runs[name] = {"iters": out["iters"], "seconds": out["seconds"],
+                          "rms": out["rms"].tolist(), "eta": out["eta"]}
+    finally:
+        fwd.close()
+    res = {"metric": "outer iterations: LSQR iterations and seconds per outer step",
+           "workload": "cfg1 re-linearised: T(m) = G0 m + beta/2 (G0 m)^2, beta = 0.3 / max|G0 m_true|",
+           "tol": 1e-6, "precond": "jacobi", "runs": runs, "data": "synthetic"}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +328,8 @@ def main():
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp_cfg1.npz"),
                     help="learned column-scale model for the learned time-to-tolerance forms "
                          "(default: the model fitted on config-1-geometry training systems)")
+    ap.add_argument("--outer", action="store_true",
+                    help="measure the outer iterations with re-linearisation instead (one JSON line)")
     ap.add_argument("--batched", action="store_true",
                     help="measure the batched multi-RHS form instead (one JSON line)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -325,6 +355,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.outer:
+        outer_bench(args)
+        return
     if args.batched:
         batched_bench(args)
         return
