@@ -108,6 +108,32 @@ def measured_traffic(tag, formats=None):
 
 
 
+def assembly_check(s, host_s):
+    """Device-side assembly of G from the same rays: seconds (host row
+    structure + device fill, median of 3) against the host generator, and a
+    bitwise comparison with the generator's arrays."""
+    import torch
+    from paper_2604_11920_amd import assemble_rays
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rp, col, val = assemble_rays(s.rays)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        if _ < 2:
+            del rp, col, val
+    same = (torch.equal(rp.cpu(), torch.from_numpy(s.row_ptr))
+            and torch.equal(col, torch.from_numpy(s.col).cuda())
+            and torch.equal(val.view(torch.int64), torch.from_numpy(s.val).cuda().view(torch.int64)))
+    del rp, col, val
+    torch.cuda.empty_cache()
+    r = {"device_s": sorted(times)[1], "host_generator_s": host_s, "bitwise_equal": bool(same)}
+    log(f"[bench] assembly on the device {r['device_s']:.3f} s (host generator {host_s:.2f} s), "
+        f"bitwise equal: {same}")
+    return r
+
+
 def fp32_rate(s, dt, iters, fmt, steps=3):
     """FP32 values, vectors and accumulation (FP64 scalars): iterations/s and
     kernel rates on the same system, same iteration count."""
@@ -374,8 +400,8 @@ def main():
         workload = ("cfg0: 16x16x9 grid (2,304 unknowns), 40 stations, 780 pairs x 10 periods, "
                     f"straight rays, smoothing x0.5, damp 0.1, {iters} LSQR iterations per step")
     s = synth.make_system(cfg)
-    log(f"[bench] generated {args.config}: m={s.m} n={s.n} nnz={s.nnz} "
-        f"in {time.perf_counter() - t0:.1f}s")
+    gen_s = time.perf_counter() - t0
+    log(f"[bench] generated {args.config}: m={s.m} n={s.n} nnz={s.nnz} in {gen_s:.1f}s")
     t0 = time.perf_counter()
     fmt = dict(row_format=args.row_format, col_format=args.col_format)
     sol = Solver.from_system(s, timing=True, xcd_bands=args.xcd_bands, **fmt)
@@ -456,6 +482,7 @@ def main():
     sol.close()
     del sol
     if not args.no_extras:
+        out["assembly"] = assembly_check(s, gen_s)
         out["fp32"] = fp32_rate(s, dt, iters, fmt)
         out["time_to_tol"] = time_to_tol(s, dt, args.ttt_tol, fmt, args.model)
     if not args.no_cpu:

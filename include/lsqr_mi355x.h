@@ -178,6 +178,48 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
                         const lsqr_opts *opts, lsqr_ctx **out);
 
 /*
+ * Device-side assembly of G from the rays (the data block of eq. (6); rows
+ * per (path, period) as in eq. (1), columns ordered as in eq. (7)).  Input:
+ * per path, the lateral nodes it crosses with the length of its path
+ * integral against each node's bilinear hat function; per period, the phase
+ * velocity and a depth kernel (weights on a contiguous range of depth nodes).
+ * Row (p, t) exists when keep[p nper + t] != 0; rows are ordered path-major
+ * (path p, then period t ascending), a row's entries node by node (in the
+ * path's node order) and depth by depth.  Entry (node a of path p, depth
+ * j0[t] + b) of row (p, t): column node_k[a] nz + j0[t] + b, value
+ * (-node_len[a] / cvel[t]) w[w_ptr[t] + b] (the traveltime sensitivity of
+ * the synthetic generator, evaluated in this order in FP64).  All inputs are
+ * host arrays (they are small next to G); outputs are device arrays.
+ */
+typedef struct {
+    int64_t npairs;             /* paths                                                 */
+    int32_t nper;               /* periods (>= 1)                                         */
+    int32_t nz;                 /* depth nodes per lateral node                           */
+    const int64_t *node_ptr;    /* [npairs+1] path p's nodes: node_ptr[p] .. node_ptr[p+1]-1 */
+    const int32_t *node_k;      /* [node_ptr[npairs]] lateral node index (>= 0)           */
+    const double *node_len;     /* [node_ptr[npairs]] path length against the node (finite) */
+    const double *cvel;         /* [nper] phase velocity (finite, != 0)                   */
+    const int32_t *j0;          /* [nper] first depth of the period's kernel              */
+    const int32_t *nj;          /* [nper] depths of the kernel; 0 <= j0, j0 + nj <= nz    */
+    const int64_t *w_ptr;       /* [nper+1] w_ptr[t+1] - w_ptr[t] == nj[t]                */
+    const double *w;            /* [w_ptr[nper]] depth weights (finite)                   */
+    const uint8_t *keep;        /* [npairs*nper] row (p, t) exists when nonzero           */
+} lsqr_rays;
+
+/* lsqr_rays_size — rows m and stored entries nnz of the assembled G (host
+ * work only; validates the rays).  Errors: INVALID_ARG, NONFINITE (node_len
+ * or w), UNSUPPORTED (m or a column >= 2^31). */
+lsqr_status lsqr_rays_size(const lsqr_rays *rays, int64_t *m, int64_t *nnz);
+
+/* lsqr_assemble_rays — write G as CSR into caller-owned device arrays
+ * row_ptr [m+1], col_idx [nnz], val [nnz] (sizes from lsqr_rays_size), on
+ * `stream` (a hipStream_t, NULL = default); returns after the arrays are
+ * complete.  The result can be passed to lsqr_create with mem = DEVICE.
+ * Errors: INVALID_ARG, UNSUPPORTED, DEVICE, OOM. */
+lsqr_status lsqr_assemble_rays(const lsqr_rays *rays, void *stream, int64_t *row_ptr,
+                               int32_t *col_idx, double *val);
+
+/*
  * lsqr_solve — run LSQR (Paige & Saunders) on bbar = [dt; 0; 0] from x0 = 0.
  * BF16/FP16 forms: each refinement sweep forms rbar = bbar - Abar dm, the
  * exact eta = |Abar^T rbar| / |Abar^T bbar| and g - ghat = (G - Ghat)^T r_G in

@@ -4,7 +4,8 @@ The compute lives in liblsqr_mi355x.so (hand-written HIP for gfx950, C ABI
 in include/lsqr_mi355x.h); this package is the build script and a ctypes
 binding.
 """
-from .lsqr import (CSR, Info, LsqrError, Solver, Trainer, header_functions, load,  # noqa: F401
-                   solve_batched)
+from .lsqr import (CSR, Info, LsqrError, Solver, Trainer, assemble_rays,  # noqa: F401
+                   header_functions, load, rays_size, solve_batched)
 
-__all__ = ["Solver", "Trainer", "LsqrError", "load", "header_functions", "solve_batched"]
+__all__ = ["Solver", "Trainer", "LsqrError", "load", "header_functions", "solve_batched",
+           "assemble_rays", "rays_size"]

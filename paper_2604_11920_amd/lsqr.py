@@ -72,6 +72,14 @@ class KStats(ctypes.Structure):
                 ("row_format", ctypes.c_int), ("col_format", ctypes.c_int)]
 
 
+class Rays(ctypes.Structure):
+    _fields_ = [("npairs", ctypes.c_int64), ("nper", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("node_ptr", ctypes.c_void_p), ("node_k", ctypes.c_void_p),
+                ("node_len", ctypes.c_void_p), ("cvel", ctypes.c_void_p),
+                ("j0", ctypes.c_void_p), ("nj", ctypes.c_void_p), ("w_ptr", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("keep", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -109,6 +117,9 @@ def load():
         "lsqr_trainer_step": (I, [P, I, P, P, ctypes.c_float, ctypes.POINTER(D)]),
         "lsqr_trainer_params": (I, [P, P, P]),
         "lsqr_trainer_destroy": (None, [P]),
+        "lsqr_rays_size": (I, [ctypes.POINTER(Rays), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(ctypes.c_int64)]),
+        "lsqr_assemble_rays": (I, [ctypes.POINTER(Rays), P, P, P, P]),
         "lsqr_destroy": (None, [P]),
         "lsqr_status_string": (ctypes.c_char_p, [I]),
         "lsqr_last_error": (ctypes.c_char_p, [P]),
@@ -479,3 +490,48 @@ class Trainer:
             self.close()
         except Exception:
             pass
+
+
+def _rays_struct(rays):
+    """ctypes view of a ray description (dict of numpy arrays, see synth's
+    System.rays); returns (struct, arrays kept alive)."""
+    keep = [np.ascontiguousarray(rays["node_ptr"], dtype=np.int64),
+            np.ascontiguousarray(rays["node_k"], dtype=np.int32),
+            np.ascontiguousarray(rays["node_len"], dtype=np.float64),
+            np.ascontiguousarray(rays["cvel"], dtype=np.float64),
+            np.ascontiguousarray(rays["j0"], dtype=np.int32),
+            np.ascontiguousarray(rays["nj"], dtype=np.int32),
+            np.ascontiguousarray(rays["w_ptr"], dtype=np.int64),
+            np.ascontiguousarray(rays["w"], dtype=np.float64),
+            np.ascontiguousarray(rays["keep"], dtype=np.uint8).reshape(-1)]
+    st = Rays(len(keep[0]) - 1, len(keep[3]), int(rays["nz"]), *[a.ctypes.data for a in keep])
+    return st, keep
+
+
+def rays_size(rays):
+    """(m, nnz) of the G assembled from `rays` (host work only)."""
+    lib = load()
+    st, _keep = _rays_struct(rays)
+    m, nnz = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib.lsqr_rays_size(ctypes.byref(st), ctypes.byref(m), ctypes.byref(nnz))
+    if rc != LSQR_OK:
+        raise LsqrError(rc, lib.lsqr_last_error(None).decode())
+    return int(m.value), int(nnz.value)
+
+
+def assemble_rays(rays, stream=None):
+    """G assembled on the device from `rays`: (row_ptr, col, val) as torch
+    CUDA tensors (int64, int32, float64), ready for Solver(..., device G)."""
+    import torch
+    lib = load()
+    m, nnz = rays_size(rays)
+    st, _keep = _rays_struct(rays)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rp = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]
+    val = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)[:nnz]
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    rc = lib.lsqr_assemble_rays(ctypes.byref(st), s, _ptr(rp), _ptr(col), _ptr(val))
+    if rc != LSQR_OK:
+        raise LsqrError(rc, lib.lsqr_last_error(None).decode())
+    return rp, col, val

@@ -347,6 +347,9 @@ class System:
     path_len: np.ndarray     # float64 [npairs] km
     damp: float
     smooth: float
+    # the rays G was built from (node_ptr, node_k, node_len, cvel, j0, nj,
+    # w_ptr, w, keep [npairs * nper], nz): input of the device-side assembly
+    rays: dict = dataclasses.field(default=None, repr=False)
 
     @property
     def nnz(self) -> int:
@@ -428,7 +431,10 @@ def make_system(cfg: Config, threads: int | None = None) -> System:
     return System(cfg=cfg, m=int(m), n=cfg.n, nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, row_ptr=row_ptr,
                   col=col, val=val, dt=dt, m_true=m_true, t_ref=t_ref, gm_true=gm,
                   row_pair=row_pair, row_period=row_period, periods=periods, path_len=path_len,
-                  damp=cfg.damp, smooth=cfg.smooth)
+                  damp=cfg.damp, smooth=cfg.smooth,
+                  rays=dict(node_ptr=node_ptr, node_k=node_k, node_len=node_len, cvel=cvel,
+                            j0=j0, nj=nj, w_ptr=w_ptr, w=wflat, keep=keep_u8.reshape(-1),
+                            nz=cfg.nz))
 
 
 # ----------------------------------------------------------------------------
