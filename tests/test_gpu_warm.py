@@ -132,3 +132,17 @@ def test_bf16_refinement_from_fp64_start(cfg0):
     assert info["iters"] <= ic["iters"]
     print(f"[bf16] cold {ic['iters']} inner iterations ({ic['sweeps']} sweeps); from the "
           f"1e-4 FP64 solution {info['iters']} ({info['sweeps']} sweeps)")
+
+
+def test_fp32_warm_iterates(cfg0):
+    # FP32 vectors and values, FP64 scalars: the early-iterate bar of the FP32
+    # form (1e-4), from the FP64 oracle's 4-step iterate
+    s = cfg0
+    op = oracle.Operator.from_system(s)
+    x0 = op.lsqr(s.dt, 4)["x"]
+    with from_sys(s, precision="fp32") as sol:
+        for K in (1, 3, 5):
+            ref = W.warm(op, s.dt, x0, K)
+            dm, hist, info = sol.solve(s.dt, K, x0=x0)
+            assert info["iters"] == K
+            assert rel(dm, ref["x"]) <= 1e-4, (K, rel(dm, ref["x"]))
