@@ -371,8 +371,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd_csr(FwdArgs a)
 #ifndef LSQR_FWD_PIPE
 #define LSQR_FWD_PIPE 1
 #endif
-#ifndef LSQR_FWD_PIPE_U
-#define LSQR_FWD_PIPE_U 8
+// Entries per lane and batch: 6 for 8-byte values, 8 for 4- and 2-byte
+// values (measured on config 1).
+#ifdef LSQR_FWD_PIPE_U
+template <class M> struct PipeU { static constexpr int value = LSQR_FWD_PIPE_U; };
+#else
+template <class M> struct PipeU { static constexpr int value = sizeof(M) >= 8 ? 6 : 8; };
 #endif
 // 1: the balanced row ranges belong to workgroups and the workgroup's 4 waves
 // take its rows in turn (neighbouring rows share columns, so their v gathers
@@ -422,7 +426,7 @@ template <class M, class V>
 __global__ __launch_bounds__(kBlock) void k_fwd_pipe(FwdArgs a)
 {
     using A = typename AccOf<V>::type;
-    constexpr int U = LSQR_FWD_PIPE_U;
+    constexpr int U = PipeU<M>::value;
     constexpr int64_t B = 64 * U;
     __shared__ double lds[4];
     double alpha, beta;
