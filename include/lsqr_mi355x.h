@@ -215,7 +215,9 @@ lsqr_status lsqr_rays_size(const lsqr_rays *rays, int64_t *m, int64_t *nnz);
  * row_ptr [m+1], col_idx [nnz], val [nnz] (sizes from lsqr_rays_size), on
  * `stream` (a hipStream_t, NULL = default); returns after the arrays are
  * complete.  The result can be passed to lsqr_create with mem = DEVICE.
- * Errors: INVALID_ARG, UNSUPPORTED, DEVICE, OOM. */
+ * The ray arrays are staged in temporary device buffers that the call
+ * allocates (hipMalloc) and frees before it returns.
+ * Errors: INVALID_ARG, NONFINITE, UNSUPPORTED, DEVICE, OOM. */
 lsqr_status lsqr_assemble_rays(const lsqr_rays *rays, void *stream, int64_t *row_ptr,
                                int32_t *col_idx, double *val);
 
