@@ -115,8 +115,15 @@ lsqr_status setup_engine(lsqr_ctx *c, Engine &E, int vec, const RowFmt &R, const
         E.R.wrow = E.wrow;
         E.R.wgrid = gp;
     }
-    if (C.nrp || C.mmask) E.g_adj = (int)std::max<int64_t>(1, std::min<int64_t>(n / c->P.nz, 2048));
-    else E.g_adj = cap_blocks(n * C.lpc, kBlock, 2048);
+    if (C.nrp || C.mmask) {
+        // node formats: a workgroup per node; for node runs no more workgroups
+        // than the device holds at once (one round, measured 3 % faster)
+        const int ga = adj_nruns_grid(vec, C);
+        const int64_t cap = ga > 0 ? std::min(ga, 2048) : 2048;
+        E.g_adj = (int)std::max<int64_t>(1, std::min<int64_t>(n / c->P.nz, cap));
+    } else {
+        E.g_adj = cap_blocks(n * C.lpc, kBlock, 2048);
+    }
     E.g_upd = cap_blocks(n, kBlock, 1024);
     E.T[0] = ctx_alloc_bytes(c, mb * vs);
     E.T[1] = ctx_alloc_bytes(c, mb * vs);

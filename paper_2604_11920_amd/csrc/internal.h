@@ -132,6 +132,9 @@ void launch_init(hipStream_t st, const Problem &P, int grid, int vec, const doub
 // once (0 when R does not use it), and its balanced wave partition.
 int fwd_pipe_grid(int vec, const RowFmt &R);
 int fwd_pipe_parts(int grid);          // row ranges of the balanced partition for a grid
+// Workgroups of the node-run transposed product the device holds at once (0
+// when C does not use it).
+int adj_nruns_grid(int vec, const ColFmt &C);
 void launch_wave_rows(hipStream_t st, const int64_t *rp, int64_t m, int waves, int32_t *wrow);
 void launch_fwd(hipStream_t st, const Problem &P, int grid, int vec, const RowFmt &R,
                 const void *z, const void *Tprev, void *Tcur, void *Ts, double *part_out,

@@ -56,6 +56,23 @@ void launch_wave_rows(hipStream_t st, const int64_t *rp, int64_t m, int waves, i
                        wrow);
 }
 
+template <class V>
+int adj_nruns_blocks_per_cu(const ColFmt &);
+
+static int resident(int per_cu)
+{
+    int dev = 0, cus = 0;
+    if (per_cu < 1 || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return 0;
+    return per_cu * cus;
+}
+
+int adj_nruns_grid(int vec, const ColFmt &C)
+{
+    return resident(vec == VT_F64 ? adj_nruns_blocks_per_cu<double>(C) : adj_nruns_blocks_per_cu<float>(C));
+}
+
 int fwd_pipe_parts(int grid) { return LSQR_FWD_WG_ROWS ? grid : grid * (kBlock / 64); }
 
 int fwd_pipe_grid(int vec, const RowFmt &R)

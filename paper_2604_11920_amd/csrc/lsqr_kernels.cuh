@@ -1367,6 +1367,30 @@ int fwd_pipe_blocks_per_cu(const RowFmt &R)
     return e == hipSuccess ? nb : 0;
 }
 
+// Workgroups of the node-run transposed product per compute unit for C's
+// value type (0 when C does not use it).
+template <class V>
+int adj_nruns_blocks_per_cu(const ColFmt &C)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (!C.nrp || C.mmask) return 0;
+    switch (C.vt) {
+    case VT_F64:
+        if constexpr (Wide<V>::value)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<double, V>, kBlock, 0);
+        break;
+    case VT_F32:
+        if constexpr (!Wide<V>::value)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<float, V>, kBlock, 0);
+        break;
+    case VT_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<bf16_t, V>, kBlock, 0); break;
+    case VT_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<fp16_t, V>, kBlock, 0); break;
+    default: break;
+    }
+    return e == hipSuccess ? nb : 0;
+}
+
 template <class V>
 hipError_t adj_launch(hipStream_t st, const Problem &P, int grid, const ColFmt &C,
                       const double *d, const void *T, const void *Tg, const void *v, void *q,
@@ -1418,6 +1442,7 @@ hipError_t update_launch(hipStream_t st, const Problem &P, int grid, const doubl
 
 #define LSQR_INSTANTIATE_LAUNCHERS(V)                                                            \
     template int fwd_pipe_blocks_per_cu<V>(const RowFmt &);                                      \
+    template int adj_nruns_blocks_per_cu<V>(const ColFmt &);                                     \
     template hipError_t fwd_launch<V>(hipStream_t, const Problem &, int, const RowFmt &,         \
                                       const void *, const void *, void *, void *, double *,      \
                                       const double *, int, double *, int *, int, double, int);   \
