@@ -344,7 +344,7 @@ def main():
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
-    ap.add_argument("--row-format", default="auto", choices=["auto", "csr", "runs", "masks"])
+    ap.add_argument("--row-format", default="auto", choices=["auto", "csr", "runs", "masks", "groups"])
     ap.add_argument("--col-format", default="auto", choices=["auto", "csc", "runs", "masks"])
     ap.add_argument("--xcd-bands", action="store_true",
                     help="transposed product: one contiguous column band per XCD")
@@ -470,7 +470,9 @@ def main():
                      "traffic": measured_traffic(dom, f"{ks['row_format']}/{ks['col_format']}"),
                      "kernel": ({1: "k_fwd_pipe (forward product, CSR rows, 64 lanes per row)",
                                  2: "k_fwd_runs (forward product, depth-run rows)",
-                                 3: "k_fwd_rmask (forward product, run-mask rows)"}[ks["row_format"]]
+                                 3: "k_fwd_rmask (forward product, run-mask rows)",
+                                 4: "k_fwd_lcol (forward product, row groups, columns staged in LDS)"}
+                                [ks["row_format"]]
                                 if dom == "fwd" else
                                 {1: "k_adj (transposed product, CSC)",
                                  2: "k_adj_nruns (transposed product, node runs)",

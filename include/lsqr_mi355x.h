@@ -101,12 +101,20 @@ typedef struct {
     uint32_t flags;             /* LSQR_FLAG_*                                         */
     int lanes_per_row;          /* 0 = auto; else 4, 8, 16, 32 or 64 lanes per row    */
     int lanes_per_col;          /* 0 = auto; same choices for the transposed product   */
-    int row_format;             /* data rows of the forward product: 0 = auto (plain  */
-                                /* CSR, the faster one measured on gfx950), 1 = plain */
-                                /* CSR, 2 = depth runs (runs of consecutive columns,  */
-                                /* i.e. of depth nodes under one lateral node, eq. 7),*/
-                                /* 3 = run masks (CSR values; columns decoded from a  */
-                                /* run-start bit per entry and one word per run)      */
+    int row_format;             /* data rows of the forward product: 0 = auto (row    */
+                                /* groups for rows of >= 384 entries on average when  */
+                                /* the groups' column lists hold at most nnz / 2      */
+                                /* columns, else plain CSR), 1 = plain CSR, 2 = depth */
+                                /* runs (runs of consecutive columns, i.e. of depth   */
+                                /* nodes under one lateral node, eq. 7), 3 = run      */
+                                /* masks (CSR values; columns decoded from a          */
+                                /* run-start bit per entry and one word per run),     */
+                                /* 4 = row groups (CSR values; consecutive rows       */
+                                /* grouped while their columns number at most the    */
+                                /* longest row rounded up to 1024; per group its      */
+                                /* sorted column list, per entry a 16-bit position in */
+                                /* it; the group's part of D v is staged in LDS; rows */
+                                /* of more than 7168 entries: UNSUPPORTED)            */
     int col_format;             /* data block of the transposed product: 0 = auto     */
                                 /* (node runs when the matrix fits the format, else   */
                                 /* CSC), 1 = CSC, 2 = node runs (per node, the rows   */
@@ -158,7 +166,7 @@ typedef struct {
     double fwd_bytes;           /* algorithmic bytes of one forward launch            */
     double adj_bytes;           /* algorithmic bytes of one transposed launch         */
     int row_format;             /* format the solver's forward product reads: 1 CSR,  */
-                                /* 2 depth runs, 3 run masks                          */
+                                /* 2 depth runs, 3 run masks, 4 row groups            */
     int col_format;             /* transposed product: 1 CSC, 2 node runs, 3 node masks */
 } lsqr_kstats;
 

@@ -78,6 +78,10 @@ struct lsqr_ctx {
     int64_t *rrp = nullptr; uint32_t *rrid = nullptr;   // row order of the node runs (batched forward)
     uint16_t *nvalq = nullptr; uint32_t *nsrc = nullptr, *ndst = nullptr;
     int64_t nnruns = 0;
+    // row groups with local columns (forward product over va)
+    int32_t *gp = nullptr, *gcol = nullptr; int64_t *gcp = nullptr; uint16_t *slot = nullptr;
+    int ngroups = 0, gcap = 0;
+    int64_t ngcols = 0;
     // run masks of the data rows (forward product over va)
     uint64_t *rmask = nullptr; uint32_t *rbase = nullptr; int32_t *rcol = nullptr;
     int64_t rmask_words = 0, rmask_runs = 0;

@@ -70,6 +70,10 @@ struct Problem {
 };
 
 // Data rows of the forward product.
+// Most columns a row group may hold (its part of D v is staged in LDS: 56 KB
+// at FP64, within the 64 KB a workgroup may take on any CDNA part).
+constexpr int kLcolMaxCap = 7168;
+
 struct RowFmt {
     int vt = VT_F64;
     const int64_t *rp = nullptr;       // [m+1] value offsets
@@ -93,6 +97,17 @@ struct RowFmt {
     // other launch sizes take rows w, w + waves, ...
     const int32_t *wrow = nullptr;     // [fwd_pipe_parts(wgrid) + 1]
     int wgrid = 0;
+    // row groups with local columns (used instead of ci when slot is set):
+    // group g = rows gp[g] .. gp[g+1]-1, its sorted columns gcol[gcp[g] ..
+    // gcp[g+1]-1] (at most gcap), slot[p] = position of entry p's column
+    // in its group's list.  With slot set, wrow holds the launch's group
+    // ranges (wrow[b] .. wrow[b+1]-1 for workgroup b of wgrid).
+    const int32_t *gp = nullptr;       // [ngroups + 1]
+    const int64_t *gcp = nullptr;      // [ngroups + 1]
+    const int32_t *gcol = nullptr;
+    const uint16_t *slot = nullptr;    // [nnz]
+    int ngroups = 0;
+    int gcap = 0;                      // columns per group at most (<= kLcolMaxCap)
 };
 
 // Stored transpose (CSC) for the transposed product.
@@ -136,6 +151,11 @@ int fwd_pipe_parts(int grid);          // row ranges of the balanced partition f
 // when C does not use it).
 int adj_nruns_grid(int vec, const ColFmt &C);
 void launch_wave_rows(hipStream_t st, const int64_t *rp, int64_t m, int waves, int32_t *wrow);
+// Row groups (RowFmt::slot): workgroups of k_fwd_lcol the device holds at once
+// (0 without groups) and the balanced group ranges of a launch of `parts`.
+int fwd_lcol_grid(int vec, const RowFmt &R);
+void launch_group_parts(hipStream_t st, const int64_t *rp, const int32_t *gp, int ng, int parts,
+                        int32_t *wgrp);
 void launch_fwd(hipStream_t st, const Problem &P, int grid, int vec, const RowFmt &R,
                 const void *z, const void *Tprev, void *Tcur, void *Ts, double *part_out,
                 const double *part_v, int np_v, double *S, int *ctl, int parity, double tol,

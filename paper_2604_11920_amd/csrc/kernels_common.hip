@@ -27,6 +27,18 @@ hipError_t update_launch(hipStream_t, const Problem &, int, const double *, cons
 
 template <class V>
 int fwd_pipe_blocks_per_cu(const RowFmt &);
+template <class V>
+int fwd_lcol_blocks_per_cu(const RowFmt &);
+
+// Workgroups the device holds at once at per_cu per compute unit (0 when unknown).
+static int resident(int per_cu)
+{
+    int dev = 0, cus = 0;
+    if (per_cu < 1 || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return 0;
+    return per_cu * cus;
+}
 
 // Balanced partition of the CSR rows into `waves` contiguous ranges: boundary
 // w is the first row r with rp[r] + kRowCost r >= w (nnz + kRowCost m) / waves
@@ -56,17 +68,43 @@ void launch_wave_rows(hipStream_t st, const int64_t *rp, int64_t m, int waves, i
                        wrow);
 }
 
+// Balanced partition of row groups into `parts` contiguous ranges: boundary w
+// is the first group g with cost(g) >= w cost(ng) / parts, cost(g) = rp[gp[g]]
+// + kRowCost gp[g] (entries and rows before group g).  cost is strictly
+// increasing (every group has a row), so boundaries are non-decreasing,
+// wgrp[0] = 0 and wgrp[parts] = ng.
+__global__ void k_group_parts(const int64_t *rp, const int32_t *gp, int ng, int parts, int32_t *wgrp)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w > parts) return;
+    const int64_t total = rp[gp[ng]] + kRowCost * (int64_t)gp[ng];
+    const int64_t target = (int64_t)(((__int128)total * w) / parts);
+    int lo = 0, hi = ng;
+    while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (rp[gp[mid]] + kRowCost * (int64_t)gp[mid] >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    wgrp[w] = w == parts ? ng : lo;
+}
+
+void launch_group_parts(hipStream_t st, const int64_t *rp, const int32_t *gp, int ng, int parts,
+                        int32_t *wgrp)
+{
+    hipLaunchKernelGGL(k_group_parts, dim3((parts + 1 + 255) / 256), dim3(256), 0, st, rp, gp, ng,
+                       parts, wgrp);
+}
+
+int fwd_lcol_grid(int vec, const RowFmt &R)
+{
+    if (!R.slot) return 0;
+    const int g = resident(vec == VT_F64 ? fwd_lcol_blocks_per_cu<double>(R) : fwd_lcol_blocks_per_cu<float>(R));
+    return std::min(g, 2048);
+}
+
 template <class V>
 int adj_nruns_blocks_per_cu(const ColFmt &);
 
-static int resident(int per_cu)
-{
-    int dev = 0, cus = 0;
-    if (per_cu < 1 || hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-        return 0;
-    return per_cu * cus;
-}
 
 int adj_nruns_grid(int vec, const ColFmt &C)
 {
@@ -77,7 +115,7 @@ int fwd_pipe_parts(int grid) { return LSQR_FWD_WG_ROWS ? grid : grid * (kBlock /
 
 int fwd_pipe_grid(int vec, const RowFmt &R)
 {
-    if (!LSQR_FWD_PIPE || R.run_ptr || R.rmask || R.lpr != 64) return 0;
+    if (!LSQR_FWD_PIPE || R.run_ptr || R.rmask || R.slot || R.lpr != 64) return 0;
     const int per_cu = vec == VT_F64 ? fwd_pipe_blocks_per_cu<double>(R) : fwd_pipe_blocks_per_cu<float>(R);
     int dev = 0, cus = 0;
     if (per_cu < 1 || hipGetDevice(&dev) != hipSuccess ||

@@ -213,6 +213,13 @@ struct FwdArgs {
     double tol;
     const int32_t *wrow;      // balanced wave partition (see RowFmt) or nullptr
     int wgrid;
+    // row groups with local columns (see RowFmt) or nullptr
+    const int32_t *gp;
+    const int64_t *gcp;
+    const int32_t *gcol;
+    const uint16_t *slot;
+    int ngroups;
+    int gcap;
 };
 
 // Prologue of an LSQR forward step: the scalars of the previous step, the
@@ -422,6 +429,23 @@ __device__ __forceinline__ void csr_batch(const FwdArgs &a, const M *va, int64_t
     }
 }
 
+// As csr_batch, reading the entries' local column slots (row groups).
+template <class M, int U>
+__device__ __forceinline__ void slot_batch(const FwdArgs &a, const M *va, int64_t jb, int64_t eb,
+                                           int lane, CsrBatch<M, U> &b)
+{
+    const int64_t safe = jb < eb ? eb - 1 : 0;
+    const int64_t left = eb - jb - lane;
+    b.nv = left <= 0 ? 0 : (left >= 64 * (int64_t)U ? U : (int)((left + 63) >> 6));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t j = jb + lane + 64 * u;
+        const int64_t jj = j < eb ? j : safe;
+        b.c[u] = (int)__builtin_nontemporal_load(a.slot + jj);
+        b.r[u] = raw_nt(va + jj);
+    }
+}
+
 template <class M, class V>
 __global__ __launch_bounds__(kBlock) void k_fwd_pipe(FwdArgs a)
 {
@@ -510,6 +534,124 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pipe(FwdArgs a)
             return false;
         };
         // two register sets in turn, so no batch is copied
+        for (;;) {
+            if (step(b0, b1)) break;
+            if (step(b1, b0)) break;
+        }
+    }
+    sq += fwd_reg_rows<V>(a, alpha, beta);
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+}
+
+// Row groups with local columns: a workgroup takes its groups in turn (a
+// contiguous range balanced in entries, wrow[b] .. wrow[b+1]-1, when the
+// launch has wgrid workgroups; else groups b, b + grid, ...).  Per group the
+// 256 threads gather D v at the group's columns into LDS (one coalesced pass
+// over the column list, whose stretches of consecutive depths share cache
+// lines), then the four waves take the group's rows in turn and walk them as
+// k_fwd_pipe does (U entries per lane per batch, the next batch's slots and
+// values loaded while the current batch is multiplied), reading D v from LDS
+// through the entries' 16-bit slots.  Per row the sum order is that of
+// k_fwd_pipe, so t is the same to the bit.  The launch gives gcap entries of
+// A of dynamic LDS; slots of entries outside the current group (the clamped
+// loads of an empty row) are below gcap too, so every LDS read stays inside
+// the array; such entries are not summed.
+
+template <class M, class V>
+__global__ __launch_bounds__(kBlock) void k_fwd_lcol(FwdArgs a)
+{
+    using A = typename AccOf<V>::type;
+    constexpr int U = PipeU<M>::value;
+    constexpr int64_t B = 64 * U;
+    constexpr int SU = 8;                                 // staging loads in flight per thread
+    __shared__ double lds[4];
+    extern __shared__ double zdyn[];
+    A *zl = (A *)zdyn;                                    // [gcap]
+    double alpha, beta;
+    if (!fwd_prologue(a, alpha, beta, lds)) return;
+    const M *va = (const M *)a.va;
+    const V *z = (const V *)a.z;
+    const V *tp = (const V *)a.Tprev;
+    const bool iter = a.mode == MODE_ITER;
+    double sq = 0.0;
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    int g = blockIdx.x, gend = a.ngroups, gstep = gridDim.x;
+    if (a.wrow && a.wgrid == (int)gridDim.x) {
+        g = ld_uniform(a.wrow, (int)blockIdx.x);
+        gend = ld_uniform(a.wrow, (int)blockIdx.x + 1);
+        gstep = 1;
+    }
+    for (; g < gend; g += gstep) {
+        const int r0 = ld_uniform(a.gp, g), r1 = ld_uniform(a.gp, g + 1);
+        const int64_t c0 = ld_uniform(a.gcp, g);
+        const int nc = (int)(ld_uniform(a.gcp, g + 1) - c0);
+        __syncthreads();                                  // the previous group's reads are done
+        for (int j0 = 0; j0 < nc; j0 += kBlock * SU) {
+            A zs[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int j = j0 + (int)threadIdx.x + kBlock * u;
+                zs[u] = (A)z[a.gcol[c0 + (j < nc ? j : nc - 1)]];
+            }
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int j = j0 + (int)threadIdx.x + kBlock * u;
+                if (j < nc) zl[j] = zs[u];
+            }
+        }
+        __syncthreads();
+        int row = r0 + wid;
+        if (row >= r1) continue;
+        int64_t j = ld_uniform(a.rp, row), e = ld_uniform(a.rp, row + 1);
+        int nrow = row + 4;
+        int64_t ns = 0, ne = 0;
+        if (nrow < r1) { ns = ld_uniform(a.rp, nrow); ne = ld_uniform(a.rp, nrow + 1); }
+        double up = iter ? (double)ld_uniform(tp, row) : 0.0;
+        double sg = a.sigma ? (double)ld_uniform(a.sigma, row) : 1.0;
+        CsrBatch<M, U> b0, b1;
+        A acc[U];
+        slot_batch<M, U>(a, va, j, e, lane, b0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = 0;
+        auto step = [&](const CsrBatch<M, U> &cur, CsrBatch<M, U> &nxt) -> bool {
+            const bool last = j + B >= e;
+            const int64_t jn = last ? ns : j + B, en = last ? ne : e;
+            A zg[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) zg[u] = zl[cur.c[u]];
+            slot_batch<M, U>(a, va, jn, en, lane, nxt);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const A p = fma(from_raw<A, M>(cur.r[u]), zg[u], acc[u]);
+                acc[u] = u < cur.nv ? p : acc[u];
+            }
+            j = jn;
+            if (last) {
+                const A t = group_sum<64>(tree_sum<U>(acc));
+                if (lane == 0) {
+#pragma clang fp contract(off)
+                    const double sacc = a.sigma ? sg * (double)t : (double)t;
+                    const double u = iter ? up / beta : 0.0;
+                    const V tv = (V)(sacc - alpha * u);
+                    ((V *)a.Tcur)[row] = tv;
+                    if (a.Ts) ((V *)a.Ts)[row] = (V)(sg * (double)tv);
+                    sq += (double)tv * (double)tv;
+                }
+                if (nrow >= r1) return true;
+                row = nrow;
+                e = ne;
+                nrow = row + 4;
+                ns = ne = 0;
+                if (nrow < r1) { ns = ld_uniform(a.rp, nrow); ne = ld_uniform(a.rp, nrow + 1); }
+                up = iter ? (double)ld_uniform(tp, row) : 0.0;
+                if (a.sigma) sg = (double)ld_uniform(a.sigma, row);
+#pragma unroll
+                for (int u = 0; u < U; ++u) acc[u] = 0;
+            }
+            return false;
+        };
         for (;;) {
             if (step(b0, b1)) break;
             if (step(b1, b0)) break;
@@ -1280,6 +1422,11 @@ static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArg
         hipLaunchKernelGGL((k_fwd_runs<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
         return;
     }
+    if (R.slot) {
+        hipLaunchKernelGGL((k_fwd_lcol<M, V>), dim3(grid), dim3(kBlock),
+                           (size_t)R.gcap * sizeof(typename AccOf<V>::type), st, a);
+        return;
+    }
     switch (R.lpr) {
     case 4: hipLaunchKernelGGL((k_fwd_csr<M, V, 4>), dim3(grid), dim3(kBlock), 0, st, a); break;
     case 8: hipLaunchKernelGGL((k_fwd_csr<M, V, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
@@ -1332,7 +1479,7 @@ hipError_t fwd_launch(hipStream_t st, const Problem &P, int grid, const RowFmt &
     FwdArgs a{R.rp, R.ci, R.run_ptr, R.runs, R.roff, R.val, R.sigma, R.rmask, R.rbase, R.rcol,
               P.m, (int)P.n, P.nx, P.ny,
               P.nz, P.w, P.damp, z, Tprev, Tcur, Ts, part_out, part_v, np_v, S, ctl, parity,
-              mode, tol, R.wrow, R.wgrid};
+              mode, tol, R.wrow, R.wgrid, R.gp, R.gcp, R.gcol, R.slot, R.ngroups, R.gcap};
     if constexpr (Wide<V>::value) {
         if (R.vt != VT_F64) return hipErrorInvalidValue;
         fwd_launch_m<double, V>(st, grid, R, a);
@@ -1361,6 +1508,27 @@ int fwd_pipe_blocks_per_cu(const RowFmt &R)
         case VT_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_pipe<float, V>, kBlock, 0); break;
         case VT_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_pipe<bf16_t, V>, kBlock, 0); break;
         case VT_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_pipe<fp16_t, V>, kBlock, 0); break;
+        default: break;
+        }
+    }
+    return e == hipSuccess ? nb : 0;
+}
+
+// Workgroups of k_fwd_lcol per compute unit for R's value type and group size.
+template <class V>
+int fwd_lcol_blocks_per_cu(const RowFmt &R)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    const size_t sh = (size_t)R.gcap * sizeof(typename AccOf<V>::type);
+    if constexpr (Wide<V>::value) {
+        if (R.vt == VT_F64)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<double, V>, kBlock, sh);
+    } else {
+        switch (R.vt) {
+        case VT_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<float, V>, kBlock, sh); break;
+        case VT_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<bf16_t, V>, kBlock, sh); break;
+        case VT_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<fp16_t, V>, kBlock, sh); break;
         default: break;
         }
     }
@@ -1442,6 +1610,7 @@ hipError_t update_launch(hipStream_t st, const Problem &P, int grid, const doubl
 
 #define LSQR_INSTANTIATE_LAUNCHERS(V)                                                            \
     template int fwd_pipe_blocks_per_cu<V>(const RowFmt &);                                      \
+    template int fwd_lcol_blocks_per_cu<V>(const RowFmt &);                                      \
     template int adj_nruns_blocks_per_cu<V>(const ColFmt &);                                     \
     template hipError_t fwd_launch<V>(hipStream_t, const Problem &, int, const RowFmt &,         \
                                       const void *, const void *, void *, void *, double *,      \

@@ -388,4 +388,73 @@ inline bool build_node_masks_host(int64_t m, int64_t n, int nz, const int64_t *r
     return true;
 }
 
+// Row groups with local columns (forward product): the data rows are cut, in
+// order, into groups of consecutive rows whose columns together number at
+// most cap (the rays of one path at all its periods cross the same lateral
+// nodes, so their columns largely coincide).  Per group its sorted column
+// list; per stored entry the position of its column in that list (u16), so a
+// workgroup stages the group's part of D v in LDS once and its rows read it
+// there.  gp[g] = first row of group g (gp[ng] = m); gcp[g] = offset of its
+// list in gcol.  Every slot is below the size of its group's list, hence below
+// cap.  Returns false when some row alone has more than cap distinct columns,
+// cap is not in [1, 65536], or m >= 2^31.
+struct RowGroups {
+    std::vector<int32_t> gp;
+    std::vector<int64_t> gcp;
+    std::vector<int32_t> gcol;
+    std::vector<uint16_t> slot;
+};
+
+inline bool build_row_groups_host(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
+                                  int cap, RowGroups &R)
+{
+    if (cap < 1 || cap > 65536 || m >= ((int64_t)1 << 31) || m < 0) return false;
+    R.gp.clear(); R.gcp.clear(); R.gcol.clear();
+    R.gp.push_back(0);
+    // group boundaries: a row joins the open group while the union fits
+    std::vector<int32_t> stamp((size_t)n, -1);
+    int32_t g = 0;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t fresh = 0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) fresh += stamp[(size_t)ci[p]] != g;
+        if (cnt + fresh > cap && i > R.gp.back()) {    // close the group before row i
+            R.gp.push_back((int32_t)i);
+            ++g;
+            cnt = 0;
+            fresh = rp[i + 1] - rp[i];                  // columns of a row are distinct
+        }
+        if (fresh > cap) return false;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) stamp[(size_t)ci[p]] = g;
+        cnt += fresh;
+    }
+    if (m > 0) R.gp.push_back((int32_t)m);
+    const int64_t ng = (int64_t)R.gp.size() - 1;
+    // column lists and slots, groups split over threads
+    std::vector<std::vector<int32_t>> lists((size_t)ng);
+    R.slot.assign((size_t)(m > 0 ? rp[m] : 0), 0);
+    const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            std::vector<int32_t> seen((size_t)n, -1), at((size_t)n, 0);
+            for (int64_t k = t; k < ng; k += nt) {
+                std::vector<int32_t> &L = lists[(size_t)k];
+                const int64_t p0 = rp[R.gp[(size_t)k]], p1 = rp[R.gp[(size_t)k + 1]];
+                for (int64_t p = p0; p < p1; ++p)
+                    if (seen[(size_t)ci[p]] != (int32_t)k) { seen[(size_t)ci[p]] = (int32_t)k; L.push_back(ci[p]); }
+                std::sort(L.begin(), L.end());
+                for (size_t q = 0; q < L.size(); ++q) at[(size_t)L[q]] = (int32_t)q;
+                for (int64_t p = p0; p < p1; ++p) R.slot[(size_t)p] = (uint16_t)at[(size_t)ci[p]];
+            }
+        });
+    for (auto &x : th) x.join();
+    R.gcp.assign((size_t)ng + 1, 0);
+    for (int64_t k = 0; k < ng; ++k) R.gcp[(size_t)k + 1] = R.gcp[(size_t)k] + (int64_t)lists[(size_t)k].size();
+    R.gcol.resize((size_t)R.gcp.back());
+    for (int64_t k = 0; k < ng; ++k)
+        std::copy(lists[(size_t)k].begin(), lists[(size_t)k].end(), R.gcol.begin() + R.gcp[(size_t)k]);
+    return true;
+}
+
 }  // namespace lsqr

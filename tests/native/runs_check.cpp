@@ -8,6 +8,9 @@
 //        int64 ok_nmask, nnodes, nrows, nchunks; int64 rptr[]; uint32 rows[]; int64 cptr[];
 //        uint64 mask[nchunks nz]; int64 qoff[nnodes 4 nz]; int32 order[];
 //        (node runs built) int64 rrp[m+1]; uint32 rrid[nnruns]  (row order of the runs)
+//        int64 ok_groups, ngroups, ngcols; int32 gp[ngroups+1]; int64 gcp[ngroups+1];
+//        int32 gcol[ngcols]; uint16 slot[nnz]   (row groups of at most CAP columns)
+// usage: runs_check IN OUT [CAP]   (CAP defaults to 4096)
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -18,7 +21,8 @@ static void put(FILE *f, const T *p, size_t n) { if (n) fwrite(p, sizeof(T), n, 
 
 int main(int argc, char **argv)
 {
-    if (argc != 3) { fprintf(stderr, "usage: runs_check IN OUT\n"); return 2; }
+    if (argc != 3 && argc != 4) { fprintf(stderr, "usage: runs_check IN OUT [CAP]\n"); return 2; }
+    const int cap = argc == 4 ? atoi(argv[3]) : 4096;
     FILE *fi = fopen(argv[1], "rb");
     if (!fi) return 2;
     int64_t hdr[4];
@@ -77,6 +81,16 @@ int main(int argc, char **argv)
         std::vector<uint32_t> rrid;
         lsqr::row_order_of_runs(R, m, rrp, rrid);
         put(fo, rrp.data(), rrp.size()); put(fo, rrid.data(), rrid.size());
+    }
+    lsqr::RowGroups G;
+    const int64_t ok5 = lsqr::build_row_groups_host(m, n, rp.data(), ci.data(), cap, G);
+    const int64_t ng5 = ok5 ? (int64_t)G.gp.size() - 1 : 0, nc5 = ok5 ? (int64_t)G.gcol.size() : 0;
+    put(fo, &ok5, 1);
+    put(fo, &ng5, 1);
+    put(fo, &nc5, 1);
+    if (ok5) {
+        put(fo, G.gp.data(), G.gp.size()); put(fo, G.gcp.data(), G.gcp.size());
+        put(fo, G.gcol.data(), G.gcol.size()); put(fo, G.slot.data(), G.slot.size());
     }
     fclose(fo);
     return 0;

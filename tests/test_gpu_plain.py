@@ -70,7 +70,7 @@ def ragged_system(seed=0, integer=False):
 
 # stored formats (forward rows, transposed columns) exercised by the solves
 FORMATS = {"auto": ("auto", "auto"), "csc": ("csr", "csc"), "runs": ("runs", "runs"),
-           "masks": ("masks", "masks")}
+           "masks": ("masks", "masks"), "groups": ("groups", "auto")}
 
 
 @pytest.fixture(scope="module")
@@ -97,7 +97,8 @@ def test_transpose_matches_library_csc(which, cfg0):
 
 @pytest.mark.parametrize("lanes,row_format,col_format",
                          [(0, "auto", "auto"), (4, "csr", "csc"), (16, "csr", "csc"),
-                          (64, "csr", "csc"), (0, "runs", "runs"), (0, "masks", "masks")])
+                          (64, "csr", "csc"), (0, "runs", "runs"), (0, "masks", "masks"),
+                          (0, "groups", "auto")])
 def test_operator_integer_bitwise(lanes, row_format, col_format):
     s = ragged_system(2, integer=True)
     op = oracle.Operator.from_system(s)
@@ -113,7 +114,8 @@ def test_operator_integer_bitwise(lanes, row_format, col_format):
 
 
 @pytest.mark.parametrize("row_format,col_format", [("csr", "csc"), ("runs", "csc"),
-                                                    ("runs", "runs"), ("masks", "masks")])
+                                                    ("runs", "runs"), ("masks", "masks"),
+                                                    ("groups", "runs")])
 def test_operator_integer_bitwise_tomography_pattern(cfg0, row_format, col_format):
     # the tomography sparsity (runs of depth columns, merged across nodes) with
     # integer values: every sum is exact, so both row formats match bitwise
@@ -195,7 +197,8 @@ def test_operator_random_within_rounding(cfg0, precond):
 
 # --------------------------------------------------------------- solves -----
 @pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"), ("none", "csc"),
-                                         ("jacobi", "runs"), ("jacobi", "masks")])
+                                         ("jacobi", "runs"), ("jacobi", "masks"),
+                                         ("jacobi", "groups")])
 def test_early_iterates_strict(cfg0, precond, fmt):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
@@ -226,7 +229,7 @@ def test_xcd_bands_iterates(cfg0, col_format):
 
 
 @pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"), ("none", "csc"),
-                                         ("none", "runs"), ("none", "masks")])
+                                         ("none", "runs"), ("none", "masks"), ("none", "groups")])
 def test_converged_strict(cfg0, cfg0_xstar, precond, fmt):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
@@ -271,7 +274,7 @@ def test_tolerance_stop(cfg0):
     assert eta <= 2 * tol
 
 
-@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks"])
+@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks", "groups"])
 def test_ragged_system_strict(fmt):
     s = ragged_system(5)
     rf, cf = FORMATS[fmt]
@@ -310,7 +313,73 @@ def test_pipelined_forward_rows(cfg0, which):
     assert np.abs(y - yr).max() <= 1e-12 * max(np.abs(yr).max(), 1.0)
 
 
-@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks"])
+def group_test_system(which, cfg0):
+    if which == "ragged":
+        return ragged_system(7)
+    if which == "cfg0":
+        return cfg0
+    if which == "wide":       # 12,000 columns, rows of up to 1500: ~500 groups of a few rows
+        return synth.random_system(3000, 40, 30, 10, row_len=(0, 1500), seed=11)
+    # rays over a 30x30x8 grid: rows of one path at several periods share a group
+    return synth.make_system(synth.small_config(nx=30, ny=30, nz=8, n_stations=24, n_periods=6,
+                                                region=3.0))
+
+
+@pytest.mark.parametrize("which", ["ragged", "cfg0", "wide", "paths"])
+def test_row_groups_forward(cfg0, which):
+    # row groups (each group's columns of D v staged in LDS, 16-bit slots per
+    # entry): solves against the oracle; the forward product equal to the bit
+    # to the pipelined CSR rows, which sum every row in the same order
+    s = group_test_system(which, cfg0)
+    op = oracle.Operator.from_system(s)
+    x = np.random.default_rng(5).standard_normal(s.n)
+    with from_sys(s, row_format="groups") as sol:
+        assert sol.kernel_stats()["row_format"] == 4
+        for K in (1, 3, 8):
+            ref = op.lsqr(s.dt, K)
+            dm, hist, info = sol.solve(s.dt, K)
+            assert info["istop"] == ref["istop"] and info["iters"] == ref["iters"]
+            assert rel(dm, ref["x"]) <= 1e-10, (K, rel(dm, ref["x"]))
+        yg = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    with from_sys(s, row_format="csr", lanes_per_row=64) as sol:
+        yp = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.array_equal(yg, yp)
+    yr = op.apply(x)
+    assert np.abs(yg - yr).max() <= 1e-12 * max(np.abs(yr).max(), 1.0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_row_groups_reduced_precision(cfg0, precision):
+    # the FP32 and quantised value types through the row groups: the same
+    # iterates as the CSR rows up to the order of the partial sums of |t|^2
+    # (the BF16 form refines to a tolerance: both solved to eta <= 1e-7)
+    s = group_test_system("paths", cfg0)
+    kw = dict(precision=precision, precond="jacobi")
+    iters, tol = (6, 0.0) if precision == "fp32" else (5000, 1e-7)
+    if precision == "bf16":
+        kw.update(refine_sweeps=10)
+    with from_sys(s, row_format="groups", **kw) as sol:
+        assert sol.kernel_stats()["row_format"] == 4
+        dg, _, _ = sol.solve(s.dt, iters, tol=tol)
+    with from_sys(s, row_format="csr", **kw) as sol:
+        dc, _, _ = sol.solve(s.dt, iters, tol=tol)
+    assert rel(dg, dc) <= 1e-4, rel(dg, dc)
+
+
+def test_row_groups_refuse_rows_above_the_cap():
+    from paper_2604_11920_amd import LsqrError
+    n = 8000
+    row_ptr = np.array([0, 3, 3 + 7169], np.int64)
+    col = np.concatenate([[0, 5, 9], np.arange(7169)]).astype(np.int32)
+    s = synth.RandomSystem(m=2, n=n, nx=40, ny=20, nz=10, row_ptr=row_ptr, col=col,
+                           val=np.ones(len(col)), dt=np.ones(2), damp=0.1, smooth=0.5)
+    with pytest.raises(LsqrError):
+        from_sys(s, row_format="groups")
+    with from_sys(s, row_format="csr") as sol:
+        assert sol.kernel_stats()["row_format"] == 1
+
+
+@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks", "groups"])
 def test_small_shapes(fmt):
     rf, cf = FORMATS[fmt]
     for grid in [(1, 1, 1), (1, 1, 3), (2, 1, 1), (3, 2, 1)]:

@@ -33,7 +33,7 @@ def driver(tmp_path_factory):
     return exe
 
 
-def run_builders(exe, tmp, row_ptr, col, n, nz):
+def run_builders(exe, tmp, row_ptr, col, n, nz, cap=4096):
     row_ptr = np.asarray(row_ptr, np.int64)
     col = np.asarray(col, np.int32)
     m, nnz = len(row_ptr) - 1, len(col)
@@ -42,7 +42,7 @@ def run_builders(exe, tmp, row_ptr, col, n, nz):
         np.array([m, n, nz, nnz], np.int64).tofile(f)
         row_ptr.tofile(f)
         col.tofile(f)
-    subprocess.run([exe, fin, fout], check=True)
+    subprocess.run([exe, fin, fout, str(cap)], check=True)
     buf = open(fout, "rb").read()
     pos = 0
 
@@ -87,6 +87,13 @@ def run_builders(exe, tmp, row_ptr, col, n, nz):
     if ok2:
         out["rrp"] = take(np.int64, m + 1)
         out["rrid"] = take(np.uint32, nr2)
+    ok5, ng5, nc5 = take(np.int64, 3)
+    out["groups_ok"] = bool(ok5)
+    if ok5:
+        out["gp"] = take(np.int32, ng5 + 1)
+        out["gcp"] = take(np.int64, ng5 + 1)
+        out["gcol"] = take(np.int32, nc5)
+        out["slot"] = take(np.uint16, len(col))
     assert pos == len(buf)
     return out
 
@@ -146,6 +153,27 @@ def check_node_masks(o, row_ptr, col, n, nz):
                 assert qoff[(k * 4 + w) * nz + iz] == colptr[j] + b[:64 * cw].sum()
     counts = np.diff(cptr)
     assert np.array_equal(order, np.argsort(-counts, kind="stable"))
+
+
+def check_row_groups(o, row_ptr, col, cap):
+    """Groups tile the rows in order; each group's list is the sorted set of
+    its rows' columns (at most cap); every entry's slot points at its column;
+    a group is closed only when the next row would not fit."""
+    gp, gcp, gcol, slot = (o[k] for k in ("gp", "gcp", "gcol", "slot"))
+    m = len(row_ptr) - 1
+    assert gp[0] == 0 and gp[-1] == m and np.all(np.diff(gp) >= 1)
+    assert gcp[0] == 0 and gcp[-1] == len(gcol) and np.all(np.diff(gcp) >= 0)
+    for g in range(len(gp) - 1):
+        p0, p1 = row_ptr[gp[g]], row_ptr[gp[g + 1]]
+        lst = gcol[gcp[g]:gcp[g + 1]]
+        assert np.array_equal(lst, np.unique(col[p0:p1]))
+        assert len(lst) <= cap
+        sl = slot[p0:p1].astype(np.int64)
+        assert np.all(sl < len(lst))
+        assert np.array_equal(lst[sl], col[p0:p1])
+        if g + 2 < len(gp):                        # greedy: the next row did not fit
+            nxt = col[row_ptr[gp[g + 1]]:row_ptr[gp[g + 1] + 1]]
+            assert len(np.union1d(lst, nxt)) > cap
 
 
 def check_row_runs(o, row_ptr, col):
@@ -321,3 +349,34 @@ def test_row_order_of_runs(driver, tmp_path):
         o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
         assert o["nodes_ok"]
         check_row_order(o, s.row_ptr, s.col, s.nz)
+
+
+def test_row_groups(driver, tmp_path):
+    s = synth.make_system(synth.small_config(nx=8, ny=8, nz=6, n_stations=14, seed=2))
+    longest = int(np.diff(s.row_ptr).max())
+    for cap in (4096, 3 * longest, longest):
+        o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz, cap=cap)
+        assert o["groups_ok"]
+        check_row_groups(o, s.row_ptr, s.col, cap)
+    assert len(o["gp"]) > 10
+    assert not run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz, cap=longest - 1)["groups_ok"]
+    # random structure with gaps and empty rows (an empty row joins any group)
+    nx, ny, nz = 7, 3, 9
+    n = nx * ny * nz
+    rng = np.random.default_rng(5)
+    rows = [np.zeros(0, np.int64) if i % 17 == 0 else np.nonzero(rng.random(n) < rng.uniform(0.02, 0.6))[0]
+            for i in range(300)]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])])
+    col = np.concatenate(rows)
+    for cap in (n, 150):
+        o = run_builders(driver, tmp_path, rp, col, n, nz, cap=cap)
+        assert o["groups_ok"]
+        check_row_groups(o, rp, col, cap)
+
+
+def test_row_groups_refused_for_a_row_above_the_cap(driver, tmp_path):
+    rp = np.array([0, 3, 8])
+    col = np.array([0, 1, 2, 0, 1, 2, 3, 4])
+    assert run_builders(driver, tmp_path, rp, col, 10, 1, cap=5)["groups_ok"]
+    o = run_builders(driver, tmp_path, rp, col, 10, 1, cap=4)
+    assert not o["groups_ok"]
