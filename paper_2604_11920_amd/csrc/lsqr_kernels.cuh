@@ -558,17 +558,11 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pipe(FwdArgs a)
 // loads of an empty row) are below gcap too, so every LDS read stays inside
 // the array; such entries are not summed.
 
-#ifdef LSQR_LCOL_U
-template <class M> struct LcolU { static constexpr int value = LSQR_LCOL_U; };
-#else
-template <class M> struct LcolU { static constexpr int value = PipeU<M>::value; };
-#endif
-
 template <class M, class V>
 __global__ __launch_bounds__(kBlock) void k_fwd_lcol(FwdArgs a)
 {
     using A = typename AccOf<V>::type;
-    constexpr int U = LcolU<M>::value;
+    constexpr int U = PipeU<M>::value;
     constexpr int64_t B = 64 * U;
     constexpr int SU = 8;                                 // staging loads in flight per thread
     __shared__ double lds[4];
