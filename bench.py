@@ -345,7 +345,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--row-format", default="auto", choices=["auto", "csr", "runs", "masks", "groups"])
-    ap.add_argument("--col-format", default="auto", choices=["auto", "csc", "runs", "masks"])
+    ap.add_argument("--col-format", default="auto", choices=["auto", "csc", "runs", "masks", "pairs"])
     ap.add_argument("--xcd-bands", action="store_true",
                     help="transposed product: one contiguous column band per XCD")
     ap.add_argument("--no-extras", action="store_true",
@@ -476,7 +476,9 @@ def main():
                                 if dom == "fwd" else
                                 {1: "k_adj (transposed product, CSC)",
                                  2: "k_adj_nruns (transposed product, node runs)",
-                                 3: "k_adj_nmask (transposed product, node masks)"}[ks["col_format"]])},
+                                 3: "k_adj_nmask (transposed product, node masks)",
+                                 4: "k_adj_npair (transposed product, node runs, depth pairs)"}
+                                [ks["col_format"]])},
         "kernels": {"fwd": {"avg_us": fwd_avg * 1e3, "alg_bytes": ks["fwd_bytes"], "gbs": fwd_gbs},
                     "adj": {"avg_us": adj_avg * 1e3, "alg_bytes": ks["adj_bytes"], "gbs": adj_gbs}},
         "paper_protocol_ms_per_step": 1e3 * sum(trimmed) / len(trimmed),

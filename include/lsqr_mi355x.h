@@ -116,12 +116,17 @@ typedef struct {
                                 /* it; the group's part of D v is staged in LDS; rows */
                                 /* of more than 7168 entries: UNSUPPORTED)            */
     int col_format;             /* data block of the transposed product: 0 = auto     */
-                                /* (node runs when the matrix fits the format, else   */
-                                /* CSC), 1 = CSC, 2 = node runs (per node, the rows   */
-                                /* reaching it with their stretch of consecutive      */
-                                /* depths; needs nz <= 64, nnz < 2^32), 3 = node      */
-                                /* masks (CSC values; per node its row list and one   */
-                                /* bit per (row, depth); needs nz <= 32)              */
+                                /* (node runs in the depth-pair layout when the       */
+                                /* matrix fits the format, else CSC), 1 = CSC, 2 =    */
+                                /* node runs (per node, the rows reaching it with     */
+                                /* their stretch of consecutive depths; needs nz <=   */
+                                /* 64, nnz < 2^32), 3 = node masks (CSC values; per   */
+                                /* node its row list and one bit per (row, depth);    */
+                                /* needs nz <= 32), 4 = node runs in the depth-pair   */
+                                /* layout (each run stored from an even position with */
+                                /* a zero before an odd first depth and after an odd  */
+                                /* end, so two depths load as one aligned word; a     */
+                                /* second, padded copy of the node-run values)        */
     double refine_inner_tol;    /* mixed precision: relative eta each inner solve     */
                                 /* reaches before the FP64 correction (0 = 1e-2); a   */
                                 /* sweep cannot gain more than the quantisation error */
@@ -167,7 +172,8 @@ typedef struct {
     double adj_bytes;           /* algorithmic bytes of one transposed launch         */
     int row_format;             /* format the solver's forward product reads: 1 CSR,  */
                                 /* 2 depth runs, 3 run masks, 4 row groups            */
-    int col_format;             /* transposed product: 1 CSC, 2 node runs, 3 node masks */
+    int col_format;             /* transposed product: 1 CSC, 2 node runs, 3 node     */
+                                /* masks, 4 node runs in the depth-pair layout        */
 } lsqr_kstats;
 
 /*

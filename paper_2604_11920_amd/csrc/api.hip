@@ -380,8 +380,8 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         return fail(nullptr, LSQR_E_INVALID_ARG, "lanes must be 0, 4, 8, 16, 32 or 64");
     if (o.row_format < 0 || o.row_format > 4)
         return fail(nullptr, LSQR_E_INVALID_ARG, "row_format must be 0, 1, 2, 3 or 4");
-    if (o.col_format < 0 || o.col_format > 3)
-        return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1, 2 or 3");
+    if (o.col_format < 0 || o.col_format > 4)
+        return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1, 2, 3 or 4");
     if (o.method < 0 || o.method > 1)
         return fail(nullptr, LSQR_E_INVALID_ARG, "method must be 0 (LSQR) or 1 (LSMR)");
     if (o.check_every < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "check_every must be >= 0");
@@ -518,9 +518,9 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     // transposed product measured on gfx950)
     bool use_nruns = false;
     NodeRuns NR;
-    const bool nruns_ok = (o.col_format == 2 || o.col_format == 0) && nnz > 0 &&
+    const bool nruns_ok = (o.col_format == 2 || o.col_format == 0 || o.col_format == 4) && nnz > 0 &&
                           build_node_runs_host(m, n, G->nz, hrow, hcol, NR);
-    if (o.col_format == 2 && nnz > 0 && !nruns_ok)
+    if ((o.col_format == 2 || o.col_format == 4) && nnz > 0 && !nruns_ok)
         return bail(LSQR_E_UNSUPPORTED, "node runs need nz <= 64, m < 2^32 and nnz < 2^32");
     if (nruns_ok) {
         const int64_t nr = NR.nrp.back(), nn = n / G->nz;
@@ -548,6 +548,24 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         CR_TRY(hipMemcpy(c->nsrc, NR.src.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->ndst, NR.dst.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         launch_gather_runs(st, nr, c->nsrc, c->ndst, c->ndesc, c->va, c->nval, 8);
+        // depth-pair layout (auto and col_format 4): runs padded to aligned
+        // pairs of depths, the faster transposed product measured on gfx950
+        std::vector<uint32_t> dstp;
+        std::vector<int64_t> nvqp;
+        const bool pairs_ok = (o.col_format == 4 || o.col_format == 0) &&
+                              pair_layout_host(NR, nn, dstp, nvqp, c->npad);
+        if (o.col_format == 4 && !pairs_ok)
+            return bail(LSQR_E_UNSUPPORTED, "the depth-pair layout needs fewer than 2^32 padded values");
+        if (pairs_ok) {
+            c->nvqp = ctx_alloc<int64_t>(c, 4 * nn + 1);
+            c->ndstp = ctx_alloc<uint32_t>(c, nr);
+            c->nvalp = ctx_alloc<double>(c, c->npad + 2);
+            if (!c->nvqp || !c->ndstp || !c->nvalp) return bail(LSQR_E_OOM, "device allocation failed");
+            CR_TRY(hipMemcpy(c->nvqp, nvqp.data(), (4 * nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+            CR_TRY(hipMemcpy(c->ndstp, dstp.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
+            CR_TRY(hipMemsetAsync(c->nvalp, 0, (c->npad + 2) * sizeof(double), st));
+            launch_gather_runs(st, nr, c->nsrc, c->ndstp, c->ndesc, c->va, c->nvalp, 8);
+        }
         if (G->nz <= 32) {        // row order of the runs, for the batched forward product
             std::vector<int64_t> rrp;
             std::vector<uint32_t> rrid;
@@ -662,6 +680,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
         C.norder = c->norder; C.val = c->nval;
         for (int x = 0; x < 9; ++x) C.nseg[x] = c->nseg[x];
+        if (c->nvalp) { C.nvq = c->nvqp; C.val = c->nvalp; C.pairs = 1; }
     }
     set_node_masks(c, C);
     int vec = VT_F64;
@@ -678,6 +697,12 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             if (!c->nval32) return bail(LSQR_E_OOM, "device allocation failed");
             launch_convert_f32(st, nnz, c->nval, c->nval32);
             C.val = c->nval32;
+            if (c->nvalp) {
+                c->nvalp32 = ctx_alloc<float>(c, c->npad + 2);
+                if (!c->nvalp32) return bail(LSQR_E_OOM, "device allocation failed");
+                launch_convert_f32(st, c->npad + 2, c->nvalp, c->nvalp32);
+                C.val = c->nvalp32;
+            }
         }
         vec = VT_F32;
     } else if (mixed) {
@@ -704,6 +729,13 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             if (!c->nvalq) return bail(LSQR_E_OOM, "device allocation failed");
             launch_gather_runs(st, c->nnruns, c->nsrc, c->ndst, c->ndesc, c->qrow, c->nvalq, 2);
             C.val = c->nvalq;
+            if (c->nvalp) {
+                c->nvalpq = ctx_alloc<uint16_t>(c, c->npad + 2);
+                if (!c->nvalpq) return bail(LSQR_E_OOM, "device allocation failed");
+                CR_TRY(hipMemsetAsync(c->nvalpq, 0, (c->npad + 2) * sizeof(uint16_t), st));
+                launch_gather_runs(st, c->nnruns, c->nsrc, c->ndstp, c->ndesc, c->qrow, c->nvalpq, 2);
+                C.val = c->nvalpq;
+            }
         }
         c->CQ = C;
         vec = VT_F32;
@@ -1008,6 +1040,7 @@ lsqr_status lsqr_apply_t(lsqr_ctx *c, const double *y, double *x)
         C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
         C.norder = c->norder; C.val = c->nval;
         for (int x = 0; x < 9; ++x) C.nseg[x] = c->nseg[x];
+        if (c->nvalp) { C.nvq = c->nvqp; C.val = c->nvalp; C.pairs = 1; }
     }
     set_node_masks(c, C);
     launch_adj(c->st, c->P, std::min(2048, c->eng.g_adj), VT_F64, C, c->d, y, y, nullptr, x,
@@ -1087,7 +1120,7 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
     if (E.R.sigma) fwd += m * 4.0 + m * sx;
     out->fwd_bytes = fwd;
     out->row_format = E.R.slot ? 4 : E.R.rmask ? 3 : E.R.run_ptr ? 2 : 1;
-    out->col_format = E.C.mmask ? 3 : E.C.nrp ? 2 : 1;
+    out->col_format = E.C.mmask ? 3 : E.C.nrp ? (E.C.pairs ? 4 : 2) : 1;
     if (E.C.mmask) {
         const double nn = n / (double)c->P.nz, nzd = (double)c->P.nz;
         out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->mrows_n * 4.0 +
@@ -1095,7 +1128,7 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
                          2.0 * (nn + 1) * 8.0 + nn * 4.0 + mb * sx + n * (8.0 + 2.0 * sx);
     } else if (E.C.nrp) {
         const double nn = n / (double)c->P.nz;
-        out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->nnruns * 6.0 +
+        out->adj_bytes = (E.C.pairs ? (double)c->npad : nnz) * (double)vt_size(E.C.vt) + (double)c->nnruns * 6.0 +
                          (nn + 1) * 8.0 + (4 * nn + 1) * 8.0 + nn * 4.0 + mb * sx +
                          n * (8.0 + 2.0 * sx);
     } else {

@@ -78,6 +78,9 @@ struct lsqr_ctx {
     int64_t *rrp = nullptr; uint32_t *rrid = nullptr;   // row order of the node runs (batched forward)
     uint16_t *nvalq = nullptr; uint32_t *nsrc = nullptr, *ndst = nullptr;
     int64_t nnruns = 0;
+    // depth-pair layout of the node-run values (k_adj_npair)
+    int64_t *nvqp = nullptr; uint32_t *ndstp = nullptr; int64_t npad = 0;
+    double *nvalp = nullptr; float *nvalp32 = nullptr; uint16_t *nvalpq = nullptr;
     // row groups with local columns (forward product over va)
     int32_t *gp = nullptr, *gcol = nullptr; int64_t *gcp = nullptr; uint16_t *slot = nullptr;
     int ngroups = 0, gcap = 0;

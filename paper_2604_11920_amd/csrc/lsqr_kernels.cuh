@@ -1103,6 +1103,145 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
 }
 
+// Two consecutive stored values from a position aligned to two elements.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <class A, class M>
+__device__ __forceinline__ void ld_pair(const M *p, A &x0, A &x1)
+{
+    if constexpr (sizeof(M) == 8) {
+        const f64x2 v = __builtin_nontemporal_load((const f64x2 *)p);
+        x0 = (A)v.x; x1 = (A)v.y;
+    } else if constexpr (sizeof(M) == 4) {
+        const f32x2 v = __builtin_nontemporal_load((const f32x2 *)p);
+        x0 = (A)v.x; x1 = (A)v.y;
+    } else {
+        const uint32_t w = __builtin_nontemporal_load((const uint32_t *)p);
+        x0 = from_raw<A, M>((uint16_t)(w & 0xffffu));
+        x1 = from_raw<A, M>((uint16_t)(w >> 16));
+    }
+}
+
+// Transposed product over node runs in the depth-pair layout (see
+// pair_layout_host): as k_adj_nruns, but a lane owns two depths, 2k and
+// 2k+1, so a group of ceil(nz/2) lanes covers a node's depths and a wave
+// holds twice as many groups.  Runs start at even positions with zeros
+// before an odd first depth and after an odd end, so a lane reads both of
+// its depths of a run with one aligned two-element load and no per-element
+// mask: a pair outside the run's window is skipped (its load reads the
+// quarter's first word, always in bounds, and is multiplied as zero).  Half
+// the load, shuffle and multiply-add instructions per value of k_adj_nruns,
+// for about one padding element per run.  Per column the sum order is fixed
+// (chunks, runs of a group, groups, waves): no atomics.
+constexpr int kPairRunsPerGroup = 10;
+
+template <class M, class V>
+__global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
+{
+#pragma clang fp contract(off)
+    using A = typename AccOf<V>::type;
+    constexpr int RPG = kPairRunsPerGroup;
+    __shared__ double lds[4];
+    __shared__ A wsum[kBlock / 64][64];
+    double beta;
+    if (!adj_prologue(a, beta, lds)) return;
+    const M *nv = (const M *)a.cv;
+    const V *Tg = (const V *)a.Tg;
+    const int nz = a.nz, hz = (nz + 1) >> 1, ngr = 64 / hz;
+    const int ch = ngr * RPG < 64 ? ngr * RPG : 64;       // runs per chunk
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int grp = lane / hz, k2 = 2 * (lane - grp * hz);  // the lane's depths k2, k2 + 1
+    const bool live = grp < ngr;
+    int G = gridDim.x, slot = blockIdx.x, nb0 = 0, nnodes = a.n / nz;
+    if (a.xcd_bands && G % 8 == 0) {
+        const int x = blockIdx.x & 7;
+        G >>= 3;
+        slot = blockIdx.x >> 3;
+        nb0 = a.nseg[x];
+        nnodes = a.nseg[x + 1] - nb0;
+    }
+    double sq = 0.0;
+    for (int s = 0; s * G < nnodes; ++s) {
+        const int idx = s * G + ((s & 1) ? G - 1 - slot : slot);
+        if (idx >= nnodes) continue;         // uniform over the workgroup
+        const int node = a.norder[nb0 + idx];
+        const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
+        const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
+        int64_t vb = a.nvq[4 * (int64_t)node + wid];        // even
+        A acc0 = 0, acc1 = 0;
+        int64_t base = rs;
+        int nr = (int)(re - base < ch ? re - base : ch);
+        uint32_t dsc = 0u;
+        A tr = 0;
+        if (lane < nr) {
+            dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
+            tr = (A)Tg[__builtin_nontemporal_load(a.nrow + base + lane)];
+        }
+        while (base < re) {
+            // padded length: one zero before an odd first depth, and to even
+            const int iz0l = (int)((dsc >> 8) & 255u);
+            const int plen = ((int)(dsc & 255u) + (iz0l & 1) + 1) & ~1;
+            int incl = plen;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            // (padded offset in the chunk << 16) | (iz0 << 8) | len; offsets < 64 * 66
+            const uint32_t pk = ((uint32_t)(incl - plen) << 16) | dsc;
+            const int tot = __shfl(incl, 63);
+            const int64_t nb = base + nr;
+            const int nn = nb < re ? (int)(re - nb < ch ? re - nb : ch) : 0;
+            uint32_t dsc_n = 0u, row_n = 0u;
+            if (lane < nn) {
+                dsc_n = __builtin_nontemporal_load(a.ndesc + nb + lane);
+                row_n = __builtin_nontemporal_load(a.nrow + nb + lane);
+            }
+            A v0[RPG], v1[RPG];
+#pragma unroll
+            for (int u = 0; u < RPG; ++u) {
+                const int r = grp + u * ngr;
+                const uint32_t p = __shfl(pk, r & 63);
+                const int iz0 = (int)((p >> 8) & 255u), lo = iz0 & ~1;
+                const bool in = live && r < nr && k2 >= lo && k2 < iz0 + (int)(p & 255u);
+                A x0, x1;
+                ld_pair<A, M>(nv + (in ? vb + (int64_t)(p >> 16) + (k2 - lo) : vb), x0, x1);
+                v0[u] = in ? x0 : (A)0;
+                v1[u] = in ? x1 : (A)0;
+            }
+            A tr_n = 0;
+            if (lane < nn) tr_n = (A)Tg[row_n];
+#pragma unroll
+            for (int u = 0; u < RPG; ++u) {
+                const A t = __shfl(tr, (grp + u * ngr) & 63);
+                acc0 = fma(v0[u], t, acc0);
+                acc1 = fma(v1[u], t, acc1);
+            }
+            vb += tot;
+            base = nb;
+            nr = nn;
+            dsc = dsc_n;
+            tr = tr_n;
+        }
+        // lane l < nz: depth l = pair l / 2, element l & 1, summed over groups
+        const int kk = lane >> 1;
+        A col = 0;
+        for (int g = 0; g < ngr; ++g) {
+            const A c0 = __shfl(acc0, (g * hz + kk) & 63), c1 = __shfl(acc1, (g * hz + kk) & 63);
+            col += (lane & 1) ? c1 : c0;
+        }
+        if (lane < nz) wsum[wid][lane] = col;
+        __syncthreads();
+        if (wid == 0 && lane < nz) {
+            const A g = ((wsum[0][lane] + wsum[1][lane]) + wsum[2][lane]) + wsum[3][lane];
+            sq += adj_col_out<V>(a, node * nz + lane, g, beta);
+        }
+        __syncthreads();
+    }
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+}
+
 // Transposed product over node masks: the CSC values, with the row indices
 // replaced by per-node row lists and bit masks.  Node k's rows (the data rows
 // reaching any of its nz columns, ascending) are cut into chunks of 64; lane l
@@ -1452,7 +1591,8 @@ static void adj_launch_m(hipStream_t st, int grid, const ColFmt &C, const AdjArg
         return;
     }
     if (C.nrp) {
-        hipLaunchKernelGGL((k_adj_nruns<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
+        if (C.pairs) hipLaunchKernelGGL((k_adj_npair<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_adj_nruns<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
         return;
     }
     switch (C.lpc) {
@@ -1543,19 +1683,20 @@ int adj_nruns_blocks_per_cu(const ColFmt &C)
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     if (!C.nrp || C.mmask) return 0;
+#define LSQR_ADJ_OCC(M_) (C.pairs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_npair<M_, V>, kBlock, 0) \
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<M_, V>, kBlock, 0))
     switch (C.vt) {
     case VT_F64:
-        if constexpr (Wide<V>::value)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<double, V>, kBlock, 0);
+        if constexpr (Wide<V>::value) e = LSQR_ADJ_OCC(double);
         break;
     case VT_F32:
-        if constexpr (!Wide<V>::value)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<float, V>, kBlock, 0);
+        if constexpr (!Wide<V>::value) e = LSQR_ADJ_OCC(float);
         break;
-    case VT_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<bf16_t, V>, kBlock, 0); break;
-    case VT_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<fp16_t, V>, kBlock, 0); break;
+    case VT_BF16: e = LSQR_ADJ_OCC(bf16_t); break;
+    case VT_F16: e = LSQR_ADJ_OCC(fp16_t); break;
     default: break;
     }
+#undef LSQR_ADJ_OCC
     return e == hipSuccess ? nb : 0;
 }
 

@@ -457,4 +457,35 @@ inline bool build_row_groups_host(int64_t m, int64_t n, const int64_t *rp, const
     return true;
 }
 
+// Depth-pair layout of the node-run values: each run is stored from an even
+// position, preceded by one zero when its first depth iz0 is odd and followed
+// by one zero when it would otherwise end at an odd length, so that depths
+// 2k and 2k+1 of a run share one aligned two-element word at run start +
+// 2k - (iz0 & ~1).  dst[r] = position of run r's first value; nvq as in
+// NodeRuns (the padded start of each quarter of a node's runs); total = the
+// padded length (even).  Returns false when it does not fit 32-bit positions.
+inline bool pair_layout_host(const NodeRuns &R, int64_t nn, std::vector<uint32_t> &dst,
+                             std::vector<int64_t> &nvq, int64_t &total)
+{
+    const int64_t nr = R.nrp[(size_t)nn];
+    dst.resize((size_t)nr);
+    nvq.assign((size_t)(4 * nn + 1), 0);
+    int64_t off = 0;
+    for (int64_t k = 0; k < nn; ++k) {
+        const int64_t r0 = R.nrp[(size_t)k], r1 = R.nrp[(size_t)k + 1], c = r1 - r0;
+        int w = 0;
+        for (int64_t r = r0; r <= r1; ++r) {
+            for (; w < 4 && r0 + c * w / 4 == r; ++w) nvq[(size_t)(4 * k + w)] = off;
+            if (r == r1) break;
+            const int iz0 = R.desc[(size_t)r] >> 8, len = R.desc[(size_t)r] & 255;
+            const int pre = iz0 & 1;
+            dst[(size_t)r] = (uint32_t)(off + pre);
+            off += (len + pre + 1) & ~1;
+        }
+    }
+    nvq[(size_t)(4 * nn)] = off;
+    total = off;
+    return off + 2 < ((int64_t)1 << 32);
+}
+
 }  // namespace lsqr

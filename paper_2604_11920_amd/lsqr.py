@@ -196,7 +196,7 @@ class Solver:
         opts.lanes_per_row = int(lanes_per_row)
         opts.lanes_per_col = int(lanes_per_col)
         opts.row_format = {"auto": 0, "csr": 1, "runs": 2, "masks": 3, "groups": 4}[row_format]
-        opts.col_format = {"auto": 0, "csc": 1, "runs": 2, "masks": 3}[col_format]
+        opts.col_format = {"auto": 0, "csc": 1, "runs": 2, "masks": 3, "pairs": 4}[col_format]
         self.precision = precision
         if torch_alloc:
             self._blocks = {}

@@ -10,6 +10,7 @@
 //        (node runs built) int64 rrp[m+1]; uint32 rrid[nnruns]  (row order of the runs)
 //        int64 ok_groups, ngroups, ngcols; int32 gp[ngroups+1]; int64 gcp[ngroups+1];
 //        int32 gcol[ngcols]; uint16 slot[nnz]   (row groups of at most CAP columns)
+//        (node runs built) int64 ok_pairs, total; uint32 dstp[nnruns]; int64 nvqp[4 nnodes+1]
 // usage: runs_check IN OUT [CAP]   (CAP defaults to 4096)
 #include <stdio.h>
 #include <stdlib.h>
@@ -91,6 +92,15 @@ int main(int argc, char **argv)
     if (ok5) {
         put(fo, G.gp.data(), G.gp.size()); put(fo, G.gcp.data(), G.gcp.size());
         put(fo, G.gcol.data(), G.gcol.size()); put(fo, G.slot.data(), G.slot.size());
+    }
+    if (ok2) {
+        std::vector<uint32_t> dstp;
+        std::vector<int64_t> nvqp;
+        int64_t total = 0;
+        const int64_t ok6 = lsqr::pair_layout_host(R, nn, dstp, nvqp, total);
+        put(fo, &ok6, 1);
+        put(fo, &total, 1);
+        put(fo, dstp.data(), dstp.size()); put(fo, nvqp.data(), nvqp.size());
     }
     fclose(fo);
     return 0;

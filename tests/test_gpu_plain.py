@@ -70,7 +70,7 @@ def ragged_system(seed=0, integer=False):
 
 # stored formats (forward rows, transposed columns) exercised by the solves
 FORMATS = {"auto": ("auto", "auto"), "csc": ("csr", "csc"), "runs": ("runs", "runs"),
-           "masks": ("masks", "masks"), "groups": ("groups", "auto")}
+           "masks": ("masks", "masks"), "groups": ("groups", "auto"), "pairs": ("csr", "pairs")}
 
 
 @pytest.fixture(scope="module")
@@ -98,7 +98,7 @@ def test_transpose_matches_library_csc(which, cfg0):
 @pytest.mark.parametrize("lanes,row_format,col_format",
                          [(0, "auto", "auto"), (4, "csr", "csc"), (16, "csr", "csc"),
                           (64, "csr", "csc"), (0, "runs", "runs"), (0, "masks", "masks"),
-                          (0, "groups", "auto")])
+                          (0, "groups", "auto"), (0, "groups", "pairs"), (8, "csr", "pairs")])
 def test_operator_integer_bitwise(lanes, row_format, col_format):
     s = ragged_system(2, integer=True)
     op = oracle.Operator.from_system(s)
@@ -115,7 +115,7 @@ def test_operator_integer_bitwise(lanes, row_format, col_format):
 
 @pytest.mark.parametrize("row_format,col_format", [("csr", "csc"), ("runs", "csc"),
                                                     ("runs", "runs"), ("masks", "masks"),
-                                                    ("groups", "runs")])
+                                                    ("groups", "runs"), ("csr", "pairs")])
 def test_operator_integer_bitwise_tomography_pattern(cfg0, row_format, col_format):
     # the tomography sparsity (runs of depth columns, merged across nodes) with
     # integer values: every sum is exact, so both row formats match bitwise
@@ -198,7 +198,7 @@ def test_operator_random_within_rounding(cfg0, precond):
 # --------------------------------------------------------------- solves -----
 @pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"), ("none", "csc"),
                                          ("jacobi", "runs"), ("jacobi", "masks"),
-                                         ("jacobi", "groups")])
+                                         ("jacobi", "groups"), ("jacobi", "pairs")])
 def test_early_iterates_strict(cfg0, precond, fmt):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
@@ -229,7 +229,8 @@ def test_xcd_bands_iterates(cfg0, col_format):
 
 
 @pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"), ("none", "csc"),
-                                         ("none", "runs"), ("none", "masks"), ("none", "groups")])
+                                         ("none", "runs"), ("none", "masks"), ("none", "groups"),
+                                         ("none", "pairs")])
 def test_converged_strict(cfg0, cfg0_xstar, precond, fmt):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
@@ -274,7 +275,7 @@ def test_tolerance_stop(cfg0):
     assert eta <= 2 * tol
 
 
-@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks", "groups"])
+@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks", "groups", "pairs"])
 def test_ragged_system_strict(fmt):
     s = ragged_system(5)
     rf, cf = FORMATS[fmt]
@@ -379,7 +380,7 @@ def test_row_groups_refuse_rows_above_the_cap():
         assert sol.kernel_stats()["row_format"] == 1
 
 
-@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks", "groups"])
+@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks", "groups", "pairs"])
 def test_small_shapes(fmt):
     rf, cf = FORMATS[fmt]
     for grid in [(1, 1, 1), (1, 1, 3), (2, 1, 1), (3, 2, 1)]:
@@ -435,3 +436,30 @@ def test_timing_counters(cfg0):
     with from_sys(cfg0) as sol:
         dm_g, _, _ = sol.solve(cfg0.dt, 20)
     assert np.array_equal(dm, dm_g)          # event timing does not change the arithmetic
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_depth_pairs_transposed(cfg0, precision):
+    # the depth-pair layout of the node runs (k_adj_npair): the transposed
+    # product against the oracle and the plain node runs, for every value
+    # type, on systems with odd and even depth counts
+    for s in (cfg0, synth.random_system(400, 5, 4, 9, row_len=(0, 60), seed=3),
+              synth.random_system(300, 4, 3, 1, row_len=(0, 8), seed=5)):
+        kw = dict(precision=precision, precond="jacobi")
+        iters, tol = (6, 0.0) if precision != "bf16" else (5000, 1e-7)
+        if precision == "bf16":
+            kw.update(refine_sweeps=10)
+        with from_sys(s, col_format="pairs", **kw) as sol:
+            assert sol.kernel_stats()["col_format"] == 4
+            dp, _, _ = sol.solve(s.dt, iters, tol=tol)
+        with from_sys(s, col_format="runs", **kw) as sol:
+            dr, _, _ = sol.solve(s.dt, iters, tol=tol)
+        bar = 1e-10 if precision == "fp64" else 1e-4
+        assert rel(dp, dr) <= bar, (s.nz, rel(dp, dr))
+        if precision == "fp64":
+            op = oracle.Operator.from_system(s)
+            y = np.random.default_rng(2).standard_normal(op.mbar)
+            with from_sys(s, col_format="pairs") as sol:
+                xg = sol.apply_t(torch.from_numpy(y).cuda()).cpu().numpy()
+            xr = op.apply_t(y)
+            assert np.abs(xg - xr).max() <= 1e-12 * max(np.abs(xr).max(), 1.0)

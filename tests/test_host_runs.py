@@ -94,6 +94,12 @@ def run_builders(exe, tmp, row_ptr, col, n, nz, cap=4096):
         out["gcp"] = take(np.int64, ng5 + 1)
         out["gcol"] = take(np.int32, nc5)
         out["slot"] = take(np.uint16, len(col))
+    if ok2:
+        ok6, tot6 = take(np.int64, 2)
+        out["pairs_ok"] = bool(ok6)
+        out["pad_total"] = int(tot6)
+        out["dstp"] = take(np.uint32, nr2)
+        out["nvqp"] = take(np.int64, 4 * nn + 1)
     assert pos == len(buf)
     return out
 
@@ -380,3 +386,39 @@ def test_row_groups_refused_for_a_row_above_the_cap(driver, tmp_path):
     assert run_builders(driver, tmp_path, rp, col, 10, 1, cap=5)["groups_ok"]
     o = run_builders(driver, tmp_path, rp, col, 10, 1, cap=4)
     assert not o["groups_ok"]
+
+
+def check_pair_layout(o, nz):
+    """Depth-pair layout: every run's depth iz sits at an index of the parity
+    of iz (its pair 2k, 2k+1 shares an aligned word), runs do not overlap,
+    the padding is at most one value on each side, and the quarter offsets
+    are the padded starts of the quarters' first runs."""
+    nrp, desc, dstp, nvqp = o["nrp"], o["desc"], o["dstp"].astype(np.int64), o["nvqp"]
+    iz0 = (desc >> 8).astype(np.int64)
+    ln = (desc & 255).astype(np.int64)
+    start = dstp - (iz0 & 1)                    # padded start of each run
+    plen = (ln + (iz0 & 1) + 1) & ~1
+    assert np.all(start % 2 == 0) and np.all((dstp - iz0) % 2 == 0)
+    assert np.array_equal(start[1:], start[:-1] + plen[:-1]) and start[0] == 0
+    assert o["pad_total"] == start[-1] + plen[-1]
+    assert o["pad_total"] - ln.sum() <= 2 * len(ln)
+    nn = len(nrp) - 1
+    for k in range(nn):
+        r0, r1 = nrp[k], nrp[k + 1]
+        c = r1 - r0
+        end = start[r1 - 1] + plen[r1 - 1] if c else None
+        for w in range(4):
+            q = r0 + c * w // 4
+            exp = start[q] if q < r1 else (end if c else None)
+            if exp is not None:
+                assert nvqp[4 * k + w] == exp
+    assert nvqp[4 * nn] == o["pad_total"]
+
+
+def test_pair_layout(driver, tmp_path):
+    for s in (synth.make_system(synth.small_config(nx=8, ny=8, nz=6, n_stations=14, seed=2)),
+              synth.random_system(300, 5, 4, 9, row_len=(0, 40), seed=9),
+              synth.random_system(200, 3, 3, 1, row_len=(0, 6), seed=4)):
+        o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
+        assert o["nodes_ok"] and o["pairs_ok"]
+        check_pair_layout(o, s.nz)
