@@ -53,6 +53,7 @@ def test_fullsize_operator(big):
     # row in the order of the pipelined CSR kernel, so the two agree to the bit
     from paper_2604_11920_amd import Solver
     assert sol.kernel_stats()["row_format"] == 4
+    assert sol.kernel_stats()["col_format"] == 4      # node runs, depth pairs (checked above)
     with Solver.from_system(s, row_format="csr") as sc:
         assert sc.kernel_stats()["row_format"] == 1
         yc = sc.apply(torch.from_numpy(x).cuda()).cpu().numpy()
