@@ -463,3 +463,48 @@ def test_depth_pairs_transposed(cfg0, precision):
                 xg = sol.apply_t(torch.from_numpy(y).cuda()).cpu().numpy()
             xr = op.apply_t(y)
             assert np.abs(xg - xr).max() <= 1e-12 * max(np.abs(xr).max(), 1.0)
+
+
+@pytest.mark.parametrize("nz", [64, 63, 2])
+def test_depth_pairs_deep_and_shallow_grids(nz):
+    # the widest pair groups (32 lanes, two groups per wave), an odd depth
+    # count whose last pair has one real depth, and a single pair
+    s = synth.random_system(240, 2, 2, nz, row_len=(0, 3 * nz), seed=nz)
+    op = oracle.Operator.from_system(s)
+    y = np.random.default_rng(nz).standard_normal(op.mbar)
+    with from_sys(s, col_format="pairs") as sol:
+        assert sol.kernel_stats()["col_format"] == 4
+        xg = sol.apply_t(torch.from_numpy(y).cuda()).cpu().numpy()
+        for K in (1, 4):
+            ref = op.lsqr(s.dt, K)
+            dm, hist, info = sol.solve(s.dt, K)
+            assert rel(dm, ref["x"]) <= 1e-10, (nz, K, rel(dm, ref["x"]))
+    xr = op.apply_t(y)
+    assert np.abs(xg - xr).max() <= 1e-12 * max(np.abs(xr).max(), 1.0)
+
+
+@pytest.mark.parametrize("longest", [1024, 1025, 7168])
+def test_row_groups_at_the_group_size_bounds(longest):
+    # the group size is the longest row rounded up to 1024 columns: a row of
+    # exactly 1024, one just above (group size 2048), and the largest allowed
+    rng = np.random.default_rng(longest)
+    n = 8000
+    lens = rng.integers(0, 300, size=120)
+    lens[17] = longest
+    rows = [np.sort(rng.choice(n, size=L, replace=False)) for L in lens]
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate(rows).astype(np.int32)
+    s = synth.RandomSystem(m=len(lens), n=n, nx=40, ny=20, nz=10, row_ptr=row_ptr, col=col,
+                           val=rng.standard_normal(len(col)), dt=rng.standard_normal(len(lens)),
+                           damp=0.1, smooth=0.5)
+    op = oracle.Operator.from_system(s)
+    x = rng.standard_normal(n)
+    with from_sys(s, row_format="groups") as sol:
+        assert sol.kernel_stats()["row_format"] == 4
+        yg = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+        ref = op.lsqr(s.dt, 3)
+        dm, _, _ = sol.solve(s.dt, 3)
+    with from_sys(s, row_format="csr", lanes_per_row=64) as sol:
+        yp = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.array_equal(yg, yp)
+    assert rel(dm, ref["x"]) <= 1e-10
