@@ -680,7 +680,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
         C.norder = c->norder; C.val = c->nval;
         for (int x = 0; x < 9; ++x) C.nseg[x] = c->nseg[x];
-        if (c->nvalp) { C.nvq = c->nvqp; C.val = c->nvalp; C.pairs = 1; }
+        if (c->nvalp) { C.nvq = c->nvqp; C.val = c->nvalp; C.pairs = 2; }
     }
     set_node_masks(c, C);
     int vec = VT_F64;
@@ -729,12 +729,23 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             if (!c->nvalq) return bail(LSQR_E_OOM, "device allocation failed");
             launch_gather_runs(st, c->nnruns, c->nsrc, c->ndst, c->ndesc, c->qrow, c->nvalq, 2);
             C.val = c->nvalq;
-            if (c->nvalp) {
-                c->nvalpq = ctx_alloc<uint16_t>(c, c->npad + 2);
-                if (!c->nvalpq) return bail(LSQR_E_OOM, "device allocation failed");
-                CR_TRY(hipMemsetAsync(c->nvalpq, 0, (c->npad + 2) * sizeof(uint16_t), st));
-                launch_gather_runs(st, c->nnruns, c->nsrc, c->ndstp, c->ndesc, c->qrow, c->nvalpq, 2);
+            if (c->nvalp) {   // the codes four depths to a word (one 8-byte load)
+                const int64_t nn = n / G->nz;
+                std::vector<uint32_t> dst4;
+                std::vector<int64_t> nvq4;
+                if (!pair_layout_host(NR, nn, dst4, nvq4, c->npad4, 4))
+                    return bail(LSQR_E_UNSUPPORTED, "the four-depth layout needs fewer than 2^32 padded values");
+                c->nvqp4 = ctx_alloc<int64_t>(c, 4 * nn + 1);
+                c->ndstp4 = ctx_alloc<uint32_t>(c, c->nnruns);
+                c->nvalpq = ctx_alloc<uint16_t>(c, c->npad4 + 4);
+                if (!c->nvqp4 || !c->ndstp4 || !c->nvalpq) return bail(LSQR_E_OOM, "device allocation failed");
+                CR_TRY(hipMemcpy(c->nvqp4, nvq4.data(), (4 * nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+                CR_TRY(hipMemcpy(c->ndstp4, dst4.data(), c->nnruns * sizeof(uint32_t), hipMemcpyHostToDevice));
+                CR_TRY(hipMemsetAsync(c->nvalpq, 0, (c->npad4 + 4) * sizeof(uint16_t), st));
+                launch_gather_runs(st, c->nnruns, c->nsrc, c->ndstp4, c->ndesc, c->qrow, c->nvalpq, 2);
                 C.val = c->nvalpq;
+                C.nvq = c->nvqp4;
+                C.pairs = 4;
             }
         }
         c->CQ = C;
@@ -1040,7 +1051,7 @@ lsqr_status lsqr_apply_t(lsqr_ctx *c, const double *y, double *x)
         C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
         C.norder = c->norder; C.val = c->nval;
         for (int x = 0; x < 9; ++x) C.nseg[x] = c->nseg[x];
-        if (c->nvalp) { C.nvq = c->nvqp; C.val = c->nvalp; C.pairs = 1; }
+        if (c->nvalp) { C.nvq = c->nvqp; C.val = c->nvalp; C.pairs = 2; }
     }
     set_node_masks(c, C);
     launch_adj(c->st, c->P, std::min(2048, c->eng.g_adj), VT_F64, C, c->d, y, y, nullptr, x,
@@ -1128,7 +1139,8 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
                          2.0 * (nn + 1) * 8.0 + nn * 4.0 + mb * sx + n * (8.0 + 2.0 * sx);
     } else if (E.C.nrp) {
         const double nn = n / (double)c->P.nz;
-        out->adj_bytes = (E.C.pairs ? (double)c->npad : nnz) * (double)vt_size(E.C.vt) + (double)c->nnruns * 6.0 +
+        const double stored = E.C.pairs == 4 ? (double)c->npad4 : E.C.pairs ? (double)c->npad : nnz;
+        out->adj_bytes = stored * (double)vt_size(E.C.vt) + (double)c->nnruns * 6.0 +
                          (nn + 1) * 8.0 + (4 * nn + 1) * 8.0 + nn * 4.0 + mb * sx +
                          n * (8.0 + 2.0 * sx);
     } else {

@@ -81,6 +81,8 @@ struct lsqr_ctx {
     // depth-pair layout of the node-run values (k_adj_npair)
     int64_t *nvqp = nullptr; uint32_t *ndstp = nullptr; int64_t npad = 0;
     double *nvalp = nullptr; float *nvalp32 = nullptr; uint16_t *nvalpq = nullptr;
+    // the 16-bit codes in the four-depth layout (mixed forms)
+    int64_t *nvqp4 = nullptr; uint32_t *ndstp4 = nullptr; int64_t npad4 = 0;
     // row groups with local columns (forward product over va)
     int32_t *gp = nullptr, *gcol = nullptr; int64_t *gcp = nullptr; uint16_t *slot = nullptr;
     int ngroups = 0, gcap = 0;

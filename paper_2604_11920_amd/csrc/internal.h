@@ -125,7 +125,8 @@ struct ColFmt {
     const uint32_t *nrow = nullptr;    // [nruns] data row of the run
     const uint16_t *ndesc = nullptr;   // [nruns] (iz0 << 8) | len
     const int32_t *norder = nullptr;   // [nnodes] nodes by decreasing work
-    int pairs = 0;                     // 1: val / nvq in the depth-pair layout (k_adj_npair)
+    int pairs = 0;                     // W = 2 (4: 16-bit codes only): val / nvq in the
+                                       // depth-pair (four-depth) layout (k_adj_npair<W>)
     int nseg[9] = {0};                 // with xcd_bands: band x = norder[nseg[x] .. nseg[x+1])
     // Node masks (used instead of the CSC rows when mmask is set; val is the
     // CSC value array): rows mrows[mrptr[k] ..] of node k in chunks of 64;

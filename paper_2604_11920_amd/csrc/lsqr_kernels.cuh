@@ -1103,22 +1103,30 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
 }
 
-// Two consecutive stored values from a position aligned to two elements.
+// W consecutive stored values from a position aligned to W elements (W = 2;
+// W = 4 for 16-bit codes).
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-template <class A, class M>
-__device__ __forceinline__ void ld_pair(const M *p, A &x0, A &x1)
+template <class A, class M, int W>
+__device__ __forceinline__ void ld_word(const M *p, A (&x)[W])
 {
     if constexpr (sizeof(M) == 8) {
+        static_assert(W == 2, "FP64 values: pairs");
         const f64x2 v = __builtin_nontemporal_load((const f64x2 *)p);
-        x0 = (A)v.x; x1 = (A)v.y;
+        x[0] = (A)v.x; x[1] = (A)v.y;
     } else if constexpr (sizeof(M) == 4) {
+        static_assert(W == 2, "FP32 values: pairs");
         const f32x2 v = __builtin_nontemporal_load((const f32x2 *)p);
-        x0 = (A)v.x; x1 = (A)v.y;
-    } else {
+        x[0] = (A)v.x; x[1] = (A)v.y;
+    } else if constexpr (W == 2) {
         const uint32_t w = __builtin_nontemporal_load((const uint32_t *)p);
-        x0 = from_raw<A, M>((uint16_t)(w & 0xffffu));
-        x1 = from_raw<A, M>((uint16_t)(w >> 16));
+        x[0] = from_raw<A, M>((uint16_t)(w & 0xffffu));
+        x[1] = from_raw<A, M>((uint16_t)(w >> 16));
+    } else {
+        static_assert(W == 4, "16-bit codes: pairs or quads");
+        const uint64_t w = __builtin_nontemporal_load((const uint64_t *)p);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) x[h] = from_raw<A, M>((uint16_t)(w >> (16 * h)));
     }
 }
 
@@ -1135,7 +1143,7 @@ __device__ __forceinline__ void ld_pair(const M *p, A &x0, A &x1)
 // (chunks, runs of a group, groups, waves): no atomics.
 constexpr int kPairRunsPerGroup = 10;
 
-template <class M, class V>
+template <class M, class V, int W>
 __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
 {
 #pragma clang fp contract(off)
@@ -1147,10 +1155,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
     if (!adj_prologue(a, beta, lds)) return;
     const M *nv = (const M *)a.cv;
     const V *Tg = (const V *)a.Tg;
-    const int nz = a.nz, hz = (nz + 1) >> 1, ngr = 64 / hz;
+    const int nz = a.nz, hz = (nz + W - 1) / W, ngr = 64 / hz;
     const int ch = ngr * RPG < 64 ? ngr * RPG : 64;       // runs per chunk
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int grp = lane / hz, k2 = 2 * (lane - grp * hz);  // the lane's depths k2, k2 + 1
+    const int grp = lane / hz, k2 = W * (lane - grp * hz);  // the lane's depths k2 .. k2 + W - 1
     const bool live = grp < ngr;
     int G = gridDim.x, slot = blockIdx.x, nb0 = 0, nnodes = a.n / nz;
     if (a.xcd_bands && G % 8 == 0) {
@@ -1167,8 +1175,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
         const int node = a.norder[nb0 + idx];
         const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
         const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
-        int64_t vb = a.nvq[4 * (int64_t)node + wid];        // even
-        A acc0 = 0, acc1 = 0;
+        int64_t vb = a.nvq[4 * (int64_t)node + wid];        // a multiple of W
+        A acc[W];
+#pragma unroll
+        for (int h = 0; h < W; ++h) acc[h] = 0;
         int64_t base = rs;
         int nr = (int)(re - base < ch ? re - base : ch);
         uint32_t dsc = 0u;
@@ -1178,16 +1188,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
             tr = (A)Tg[__builtin_nontemporal_load(a.nrow + base + lane)];
         }
         while (base < re) {
-            // padded length: one zero before an odd first depth, and to even
+            // padded length: iz0 mod W zeros before, and up to a multiple of W
             const int iz0l = (int)((dsc >> 8) & 255u);
-            const int plen = ((int)(dsc & 255u) + (iz0l & 1) + 1) & ~1;
+            const int plen = ((int)(dsc & 255u) + (iz0l & (W - 1)) + W - 1) & ~(W - 1);
             int incl = plen;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 const int y = __shfl_up(incl, o);
                 if (lane >= o) incl += y;
             }
-            // (padded offset in the chunk << 16) | (iz0 << 8) | len; offsets < 64 * 66
+            // (padded offset in the chunk << 16) | (iz0 << 8) | len; offsets < 64 * 68
             const uint32_t pk = ((uint32_t)(incl - plen) << 16) | dsc;
             const int tot = __shfl(incl, 63);
             const int64_t nb = base + nr;
@@ -1197,25 +1207,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
                 dsc_n = __builtin_nontemporal_load(a.ndesc + nb + lane);
                 row_n = __builtin_nontemporal_load(a.nrow + nb + lane);
             }
-            A v0[RPG], v1[RPG];
+            A v[RPG][W];
 #pragma unroll
             for (int u = 0; u < RPG; ++u) {
                 const int r = grp + u * ngr;
                 const uint32_t p = __shfl(pk, r & 63);
-                const int iz0 = (int)((p >> 8) & 255u), lo = iz0 & ~1;
+                const int iz0 = (int)((p >> 8) & 255u), lo = iz0 & ~(W - 1);
                 const bool in = live && r < nr && k2 >= lo && k2 < iz0 + (int)(p & 255u);
-                A x0, x1;
-                ld_pair<A, M>(nv + (in ? vb + (int64_t)(p >> 16) + (k2 - lo) : vb), x0, x1);
-                v0[u] = in ? x0 : (A)0;
-                v1[u] = in ? x1 : (A)0;
+                ld_word<A, M, W>(nv + (in ? vb + (int64_t)(p >> 16) + (k2 - lo) : vb), v[u]);
+#pragma unroll
+                for (int h = 0; h < W; ++h) v[u][h] = in ? v[u][h] : (A)0;
             }
             A tr_n = 0;
             if (lane < nn) tr_n = (A)Tg[row_n];
 #pragma unroll
             for (int u = 0; u < RPG; ++u) {
                 const A t = __shfl(tr, (grp + u * ngr) & 63);
-                acc0 = fma(v0[u], t, acc0);
-                acc1 = fma(v1[u], t, acc1);
+#pragma unroll
+                for (int h = 0; h < W; ++h) acc[h] = fma(v[u][h], t, acc[h]);
             }
             vb += tot;
             base = nb;
@@ -1223,12 +1232,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
             dsc = dsc_n;
             tr = tr_n;
         }
-        // lane l < nz: depth l = pair l / 2, element l & 1, summed over groups
-        const int kk = lane >> 1;
+        // lane l < nz: depth l = word l / W, element l mod W, summed over groups
+        const int kk = lane / W, hh = lane % W;
         A col = 0;
         for (int g = 0; g < ngr; ++g) {
-            const A c0 = __shfl(acc0, (g * hz + kk) & 63), c1 = __shfl(acc1, (g * hz + kk) & 63);
-            col += (lane & 1) ? c1 : c0;
+            A c = 0;
+#pragma unroll
+            for (int h = 0; h < W; ++h) {
+                const A ch_ = __shfl(acc[h], (g * hz + kk) & 63);
+                c = h == hh ? ch_ : c;
+            }
+            col += c;
         }
         if (lane < nz) wsum[wid][lane] = col;
         __syncthreads();
@@ -1591,7 +1605,14 @@ static void adj_launch_m(hipStream_t st, int grid, const ColFmt &C, const AdjArg
         return;
     }
     if (C.nrp) {
-        if (C.pairs) hipLaunchKernelGGL((k_adj_npair<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
+        if (C.pairs) {
+            if constexpr (sizeof(M) == 2) {
+                if (C.pairs == 4) hipLaunchKernelGGL((k_adj_npair<M, V, 4>), dim3(grid), dim3(kBlock), 0, st, a);
+                else hipLaunchKernelGGL((k_adj_npair<M, V, 2>), dim3(grid), dim3(kBlock), 0, st, a);
+            } else {
+                hipLaunchKernelGGL((k_adj_npair<M, V, 2>), dim3(grid), dim3(kBlock), 0, st, a);
+            }
+        }
         else hipLaunchKernelGGL((k_adj_nruns<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
         return;
     }
@@ -1683,7 +1704,9 @@ int adj_nruns_blocks_per_cu(const ColFmt &C)
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     if (!C.nrp || C.mmask) return 0;
-#define LSQR_ADJ_OCC(M_) (C.pairs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_npair<M_, V>, kBlock, 0) \
+#define LSQR_ADJ_OCC(M_) (C.pairs == 4 && sizeof(M_) == 2                                                              \
+                              ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_npair<M_, V, (sizeof(M_) == 2 ? 4 : 2)>, kBlock, 0) \
+                          : C.pairs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_npair<M_, V, 2>, kBlock, 0) \
                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<M_, V>, kBlock, 0))
     switch (C.vt) {
     case VT_F64:

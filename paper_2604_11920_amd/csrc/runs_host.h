@@ -457,16 +457,18 @@ inline bool build_row_groups_host(int64_t m, int64_t n, const int64_t *rp, const
     return true;
 }
 
-// Depth-pair layout of the node-run values: each run is stored from an even
-// position, preceded by one zero when its first depth iz0 is odd and followed
-// by one zero when it would otherwise end at an odd length, so that depths
-// 2k and 2k+1 of a run share one aligned two-element word at run start +
-// 2k - (iz0 & ~1).  dst[r] = position of run r's first value; nvq as in
-// NodeRuns (the padded start of each quarter of a node's runs); total = the
-// padded length (even).  Returns false when it does not fit 32-bit positions.
+// Depth-pair layout of the node-run values (W = 2; W = 4 groups four depths
+// the same way): each run is stored from a position that is a multiple of W,
+// preceded by iz0 mod W zeros and followed by zeros up to a multiple of W, so
+// that depths Wk .. Wk+W-1 of a run share one aligned W-element word at run
+// start + Wk - (iz0 - iz0 mod W).  dst[r] = position of run r's first value;
+// nvq as in NodeRuns (the padded start of each quarter of a node's runs);
+// total = the padded length (a multiple of W).  Returns false when it does
+// not fit 32-bit positions or W is not 2 or 4.
 inline bool pair_layout_host(const NodeRuns &R, int64_t nn, std::vector<uint32_t> &dst,
-                             std::vector<int64_t> &nvq, int64_t &total)
+                             std::vector<int64_t> &nvq, int64_t &total, int W = 2)
 {
+    if (W != 2 && W != 4) return false;
     const int64_t nr = R.nrp[(size_t)nn];
     dst.resize((size_t)nr);
     nvq.assign((size_t)(4 * nn + 1), 0);
@@ -478,9 +480,9 @@ inline bool pair_layout_host(const NodeRuns &R, int64_t nn, std::vector<uint32_t
             for (; w < 4 && r0 + c * w / 4 == r; ++w) nvq[(size_t)(4 * k + w)] = off;
             if (r == r1) break;
             const int iz0 = R.desc[(size_t)r] >> 8, len = R.desc[(size_t)r] & 255;
-            const int pre = iz0 & 1;
+            const int pre = iz0 & (W - 1);
             dst[(size_t)r] = (uint32_t)(off + pre);
-            off += (len + pre + 1) & ~1;
+            off += (len + pre + W - 1) & ~(W - 1);
         }
     }
     nvq[(size_t)(4 * nn)] = off;

@@ -10,7 +10,8 @@
 //        (node runs built) int64 rrp[m+1]; uint32 rrid[nnruns]  (row order of the runs)
 //        int64 ok_groups, ngroups, ngcols; int32 gp[ngroups+1]; int64 gcp[ngroups+1];
 //        int32 gcol[ngcols]; uint16 slot[nnz]   (row groups of at most CAP columns)
-//        (node runs built) int64 ok_pairs, total; uint32 dstp[nnruns]; int64 nvqp[4 nnodes+1]
+//        (node runs built, for W = 2 then W = 4) int64 ok_pairs, total; uint32 dstp[nnruns];
+//        int64 nvqp[4 nnodes+1]
 // usage: runs_check IN OUT [CAP]   (CAP defaults to 4096)
 #include <stdio.h>
 #include <stdlib.h>
@@ -93,11 +94,12 @@ int main(int argc, char **argv)
         put(fo, G.gp.data(), G.gp.size()); put(fo, G.gcp.data(), G.gcp.size());
         put(fo, G.gcol.data(), G.gcol.size()); put(fo, G.slot.data(), G.slot.size());
     }
-    if (ok2) {
+    for (int W : {2, 4}) {
+        if (!ok2) break;
         std::vector<uint32_t> dstp;
         std::vector<int64_t> nvqp;
         int64_t total = 0;
-        const int64_t ok6 = lsqr::pair_layout_host(R, nn, dstp, nvqp, total);
+        const int64_t ok6 = lsqr::pair_layout_host(R, nn, dstp, nvqp, total, W);
         put(fo, &ok6, 1);
         put(fo, &total, 1);
         put(fo, dstp.data(), dstp.size()); put(fo, nvqp.data(), nvqp.size());

@@ -94,12 +94,12 @@ def run_builders(exe, tmp, row_ptr, col, n, nz, cap=4096):
         out["gcp"] = take(np.int64, ng5 + 1)
         out["gcol"] = take(np.int32, nc5)
         out["slot"] = take(np.uint16, len(col))
-    if ok2:
+    for W in ((2, 4) if ok2 else ()):
         ok6, tot6 = take(np.int64, 2)
-        out["pairs_ok"] = bool(ok6)
-        out["pad_total"] = int(tot6)
-        out["dstp"] = take(np.uint32, nr2)
-        out["nvqp"] = take(np.int64, 4 * nn + 1)
+        out[f"pairs_ok{W}"] = bool(ok6)
+        out[f"pad_total{W}"] = int(tot6)
+        out[f"dstp{W}"] = take(np.uint32, nr2)
+        out[f"nvqp{W}"] = take(np.int64, 4 * nn + 1)
     assert pos == len(buf)
     return out
 
@@ -388,20 +388,22 @@ def test_row_groups_refused_for_a_row_above_the_cap(driver, tmp_path):
     assert not o["groups_ok"]
 
 
-def check_pair_layout(o, nz):
-    """Depth-pair layout: every run's depth iz sits at an index of the parity
-    of iz (its pair 2k, 2k+1 shares an aligned word), runs do not overlap,
-    the padding is at most one value on each side, and the quarter offsets
-    are the padded starts of the quarters' first runs."""
-    nrp, desc, dstp, nvqp = o["nrp"], o["desc"], o["dstp"].astype(np.int64), o["nvqp"]
+def check_pair_layout(o, nz, W=2):
+    """Depth-pair (W = 2) and four-depth (W = 4) layouts: every run's depth
+    iz sits at an index congruent to iz mod W (depths Wk .. Wk+W-1 share an
+    aligned word), runs do not overlap, the padding is below W values on each
+    side, and the quarter offsets are the padded starts of the quarters'
+    first runs."""
+    nrp, desc = o["nrp"], o["desc"]
+    dstp, nvqp, total = o[f"dstp{W}"].astype(np.int64), o[f"nvqp{W}"], o[f"pad_total{W}"]
     iz0 = (desc >> 8).astype(np.int64)
     ln = (desc & 255).astype(np.int64)
-    start = dstp - (iz0 & 1)                    # padded start of each run
-    plen = (ln + (iz0 & 1) + 1) & ~1
-    assert np.all(start % 2 == 0) and np.all((dstp - iz0) % 2 == 0)
+    start = dstp - (iz0 % W)                    # padded start of each run
+    plen = -(-(ln + iz0 % W) // W) * W
+    assert np.all(start % W == 0) and np.all((dstp - iz0) % W == 0)
     assert np.array_equal(start[1:], start[:-1] + plen[:-1]) and start[0] == 0
-    assert o["pad_total"] == start[-1] + plen[-1]
-    assert o["pad_total"] - ln.sum() <= 2 * len(ln)
+    assert total == start[-1] + plen[-1]
+    assert total - ln.sum() <= 2 * (W - 1) * len(ln)
     nn = len(nrp) - 1
     for k in range(nn):
         r0, r1 = nrp[k], nrp[k + 1]
@@ -412,7 +414,7 @@ def check_pair_layout(o, nz):
             exp = start[q] if q < r1 else (end if c else None)
             if exp is not None:
                 assert nvqp[4 * k + w] == exp
-    assert nvqp[4 * nn] == o["pad_total"]
+    assert nvqp[4 * nn] == total
 
 
 def test_pair_layout(driver, tmp_path):
@@ -420,5 +422,6 @@ def test_pair_layout(driver, tmp_path):
               synth.random_system(300, 5, 4, 9, row_len=(0, 40), seed=9),
               synth.random_system(200, 3, 3, 1, row_len=(0, 6), seed=4)):
         o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
-        assert o["nodes_ok"] and o["pairs_ok"]
-        check_pair_layout(o, s.nz)
+        assert o["nodes_ok"] and o["pairs_ok2"] and o["pairs_ok4"]
+        check_pair_layout(o, s.nz, 2)
+        check_pair_layout(o, s.nz, 4)
