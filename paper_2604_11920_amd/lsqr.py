@@ -153,7 +153,13 @@ def _is_torch(a):
 
 
 class Solver:
-    """One regularised LSQR system on the GPU (wraps an lsqr_ctx)."""
+    """One regularised LSQR system on the GPU (wraps an lsqr_ctx).
+
+    row_format: "auto" | "csr" | "runs" | "masks" | "groups" (forward product);
+    col_format: "auto" | "csc" | "runs" | "masks" | "pairs" (transposed
+    product).  The formats are those of opts.row_format / opts.col_format in
+    include/lsqr_mi355x.h; "auto" picks row groups and depth pairs where the
+    matrix fits them."""
 
     def __init__(self, row_ptr, col, val, nx, ny, nz, damp, smooth, precision="fp64",
                  precond="none", col_scale=None, stream=None, timing=False, graph=True,
