@@ -426,7 +426,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
 
     c->rp = ctx_alloc<int64_t>(c, m + 1);
     c->ci = ctx_alloc<int32_t>(c, nnz);
-    c->va = ctx_alloc<double>(c, nnz);
+    c->va = ctx_alloc<double>(c, nnz + 1);       // one zero past the end (paired loads)
     c->cp = ctx_alloc<int64_t>(c, n + 1);
     c->ri = ctx_alloc<int32_t>(c, nnz);
     c->cv = ctx_alloc<double>(c, nnz);
@@ -453,6 +453,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if (nnz > 0) {
         CR_TRY(hipMemcpyAsync(c->ci, G->col_idx, nnz * sizeof(int32_t), kind, st));
         CR_TRY(hipMemcpyAsync(c->va, G->val, nnz * sizeof(double), kind, st));
+        CR_TRY(hipMemsetAsync(c->va + nnz, 0, sizeof(double), st));
     }
     std::vector<int64_t> hrp;
     std::vector<int32_t> hci;
@@ -600,13 +601,14 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             c->gp = ctx_alloc<int32_t>(c, c->ngroups + 1);
             c->gcp = ctx_alloc<int64_t>(c, c->ngroups + 1);
             c->gcol = ctx_alloc<int32_t>(c, std::max<int64_t>(c->ngcols, 1));
-            c->slot = ctx_alloc<uint16_t>(c, nnz);
+            c->slot = ctx_alloc<uint16_t>(c, nnz + 1);
             if (!c->gp || !c->gcp || !c->gcol || !c->slot) return bail(LSQR_E_OOM, "device allocation failed");
             CR_TRY(hipMemcpy(c->gp, RG.gp.data(), (c->ngroups + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
             CR_TRY(hipMemcpy(c->gcp, RG.gcp.data(), (c->ngroups + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
             if (c->ngcols)
                 CR_TRY(hipMemcpy(c->gcol, RG.gcol.data(), c->ngcols * sizeof(int32_t), hipMemcpyHostToDevice));
             CR_TRY(hipMemcpy(c->slot, RG.slot.data(), nnz * sizeof(uint16_t), hipMemcpyHostToDevice));
+            CR_TRY(hipMemset(c->slot + nnz, 0, sizeof(uint16_t)));
         }
     }
     // run masks of the data rows (index the CSR values directly)
@@ -654,7 +656,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if (use_runs) { c->R64.run_ptr = c->run_ptr; c->R64.runs = c->runs; c->R64.roff = c->roff; }
     if (c->slot) {
         c->R64.gp = c->gp; c->R64.gcp = c->gcp; c->R64.gcol = c->gcol; c->R64.slot = c->slot;
-        c->R64.ngroups = c->ngroups; c->R64.gcap = c->gcap;
+        c->R64.ngroups = c->ngroups; c->R64.gcap = c->gcap; c->R64.padded = 1;
     }
     c->C64.vt = VT_F64; c->C64.cp = c->cp; c->C64.ri = c->ri; c->C64.val = c->cv;
     c->C64.lpc = o.lanes_per_col ? o.lanes_per_col : pick_lanes(avg_col);
@@ -690,7 +692,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         if (!c->va32 || !c->cv32) return bail(LSQR_E_OOM, "device allocation failed");
         launch_convert_f32(st, nnz, c->va, c->va32);
         launch_convert_f32(st, nnz, c->cv, c->cv32);
-        R.vt = VT_F32; R.val = c->va32;
+        R.vt = VT_F32; R.val = c->va32; R.padded = 0;
         C.vt = VT_F32; C.val = c->cv32;
         if (use_nruns) {
             c->nval32 = ctx_alloc<float>(c, nnz);
@@ -722,7 +724,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         launch_row_scales(st, m, c->rp, c->va, vt, c->sigma);
         launch_quantise_rows(st, m, c->rp, c->va, c->sigma, vt, c->qrow);
         launch_quantise_cols(st, nnz, c->ri, c->cv, c->sigma, vt, c->qcol);
-        R.vt = vt; R.val = c->qrow; R.sigma = c->sigma;
+        R.vt = vt; R.val = c->qrow; R.sigma = c->sigma; R.padded = 0;
         C.vt = vt; C.val = c->qcol;
         if (use_nruns) {      // the same codes, node-major
             c->nvalq = ctx_alloc<uint16_t>(c, nnz);

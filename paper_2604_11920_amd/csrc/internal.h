@@ -108,6 +108,7 @@ struct RowFmt {
     const uint16_t *slot = nullptr;    // [nnz]
     int ngroups = 0;
     int gcap = 0;                      // columns per group at most (<= kLcolMaxCap)
+    int padded = 0;                    // 1: val and slot hold one more (zero) element
 };
 
 // Stored transpose (CSC) for the transposed product.

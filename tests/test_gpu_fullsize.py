@@ -49,15 +49,16 @@ def test_fullsize_operator(big):
     lc = np.bincount(s.col, minlength=s.n)
     bt = 2 * (lc + 4) * eps * (absG.T @ np.abs(ybar[:s.m]) + 6 * np.abs(ybar[s.m:]).max())
     assert np.all(np.abs(xg - op.apply_t(ybar)) <= bt)
-    # the benchmark's forward product is the row-group kernel; it sums every
-    # row in the order of the pipelined CSR kernel, so the two agree to the bit
+    # the benchmark's forward product is the row-group kernel (FP64 values in
+    # pairs); against the pipelined CSR kernel, both within the bound above
     from paper_2604_11920_amd import Solver
     assert sol.kernel_stats()["row_format"] == 4
     assert sol.kernel_stats()["col_format"] == 4      # node runs, depth pairs (checked above)
     with Solver.from_system(s, row_format="csr") as sc:
         assert sc.kernel_stats()["row_format"] == 1
         yc = sc.apply(torch.from_numpy(x).cuda()).cpu().numpy()
-    assert np.array_equal(yg, yc)
+    assert np.all(np.abs(yg[:s.m] - yc[:s.m]) <= 2 * bd)
+    assert np.array_equal(yg[s.m:], yc[s.m:])         # regularisation rows: same kernel
 
 
 def test_fullsize_first_iterates(big):
