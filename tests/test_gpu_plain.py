@@ -525,7 +525,7 @@ def test_row_groups_pairs_at_odd_bounds():
     # padding element past the last entry)
     rng = np.random.default_rng(21)
     n = 1200
-    lens = np.array([3, 0, 401, 400, 5, 1, 0, 777, 2, 1])
+    lens = np.array([3, 0, 401, 400, 5, 1, 0, 777, 2, 2])
     assert lens.sum() % 2 == 1
     rows = [np.sort(rng.choice(n, size=L, replace=False)) for L in lens]
     row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
