@@ -687,12 +687,12 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     set_node_masks(c, C);
     int vec = VT_F64;
     if (o.precision == LSQR_FP32) {
-        c->va32 = ctx_alloc<float>(c, nnz);
+        c->va32 = ctx_alloc<float>(c, nnz + 1);     // with va's padding element
         c->cv32 = ctx_alloc<float>(c, nnz);
         if (!c->va32 || !c->cv32) return bail(LSQR_E_OOM, "device allocation failed");
-        launch_convert_f32(st, nnz, c->va, c->va32);
+        launch_convert_f32(st, nnz + 1, c->va, c->va32);
         launch_convert_f32(st, nnz, c->cv, c->cv32);
-        R.vt = VT_F32; R.val = c->va32; R.padded = 0;
+        R.vt = VT_F32; R.val = c->va32;
         C.vt = VT_F32; C.val = c->cv32;
         if (use_nruns) {
             c->nval32 = ctx_alloc<float>(c, nnz);
@@ -710,7 +710,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     } else if (mixed) {
         const int vt = o.precision == LSQR_BF16 ? VT_BF16 : VT_F16;
         c->sigma = ctx_alloc<float>(c, std::max<int64_t>(m, 1));
-        c->qrow = ctx_alloc<uint16_t>(c, nnz);
+        c->qrow = ctx_alloc<uint16_t>(c, nnz + 1);  // one zero code past the end
         c->qcol = ctx_alloc<uint16_t>(c, nnz);
         c->xbuf = ctx_alloc<double>(c, n);
         c->rbar = ctx_alloc<double>(c, mb);
@@ -722,9 +722,10 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             !c->ghat || !c->fbuf)
             return bail(LSQR_E_OOM, "device allocation failed");
         launch_row_scales(st, m, c->rp, c->va, vt, c->sigma);
+        CR_TRY(hipMemsetAsync(c->qrow + nnz, 0, sizeof(uint16_t), st));
         launch_quantise_rows(st, m, c->rp, c->va, c->sigma, vt, c->qrow);
         launch_quantise_cols(st, nnz, c->ri, c->cv, c->sigma, vt, c->qcol);
-        R.vt = vt; R.val = c->qrow; R.sigma = c->sigma; R.padded = 0;
+        R.vt = vt; R.val = c->qrow; R.sigma = c->sigma;
         C.vt = vt; C.val = c->qcol;
         if (use_nruns) {      // the same codes, node-major
             c->nvalq = ctx_alloc<uint16_t>(c, nnz);

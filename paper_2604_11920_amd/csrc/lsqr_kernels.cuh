@@ -558,23 +558,38 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pipe(FwdArgs a)
 // loads of an empty row) are below gcap too, so every LDS read stays inside
 // the array; such entries are not summed.
 
-// Row groups with FP64 values, two entries per lane and load: a row's
-// entries are taken in aligned pairs (even positions p, p + 1; the first pair
+// Row groups, two entries per lane and load: a row's entries are taken in
+// aligned pairs (even positions p, p + 1; the first pair
 // of a row starting at an odd position holds the previous row's last entry,
 // the last pair may hold the next row's first or, at the end of the arrays,
-// the one padding element), so one 16-byte load brings two values and one
-// 4-byte load their two slots.  Entries outside the row are left out of the
+// the one padding element), so one load brings two values (16 bytes for
+// FP64, 8 for FP32, 4 for 16-bit codes) and one 4-byte load their two slots.  Entries outside the row are left out of the
 // sums.  Halves the load instructions per entry of k_fwd_lcol.
 typedef double f64x2p __attribute__((ext_vector_type(2)));
-template <int U>
+typedef float f32x2p __attribute__((ext_vector_type(2)));
+// two raw stored values: one 16-, 8- or 4-byte word
+template <class M> struct PairRaw { using type = uint32_t; };
+template <> struct PairRaw<double> { using type = f64x2p; };
+template <> struct PairRaw<float> { using type = f32x2p; };
+template <class A, class M>
+__device__ __forceinline__ void pair_values(typename PairRaw<M>::type r, A &x0, A &x1)
+{
+    if constexpr (sizeof(M) >= 4) {
+        x0 = (A)r.x; x1 = (A)r.y;
+    } else {
+        x0 = from_raw<A, M>((uint16_t)(r & 0xffffu));
+        x1 = from_raw<A, M>((uint16_t)(r >> 16));
+    }
+}
+template <class M, int U>
 struct PairBatch {
     uint32_t c[U];                       // two slots
-    f64x2p r[U];                         // two values
+    typename PairRaw<M>::type r[U];      // two values
     int64_t e0[U];                       // position of the pair's first entry
 };
-template <int U>
-__device__ __forceinline__ void pair_batch(const FwdArgs &a, const double *va, int64_t jb, int64_t eb,
-                                           int lane, PairBatch<U> &b)
+template <class M, int U>
+__device__ __forceinline__ void pair_batch(const FwdArgs &a, const M *va, int64_t jb, int64_t eb,
+                                           int lane, PairBatch<M, U> &b)
 {
     // pairs p = jb + 2 lane + 128 u (jb even); a pair at or past eb loads the
     // pair holding entry eb - 1 (else pair 0): in bounds, not summed
@@ -585,7 +600,7 @@ __device__ __forceinline__ void pair_batch(const FwdArgs &a, const double *va, i
         const int64_t pp = p < eb ? p : safe;
         b.e0[u] = p;
         b.c[u] = __builtin_nontemporal_load((const uint32_t *)(a.slot + pp));
-        b.r[u] = __builtin_nontemporal_load((const f64x2p *)(va + pp));
+        b.r[u] = __builtin_nontemporal_load((const typename PairRaw<M>::type *)(va + pp));
     }
 }
 
@@ -693,7 +708,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol(FwdArgs a)
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
 }
 
-// FP64 values only (M = double); see pair_batch.
+// See pair_batch.
 template <class M, class V>
 __global__ __launch_bounds__(kBlock) void k_fwd_lcol_pair(FwdArgs a)
 {
@@ -749,24 +764,26 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol_pair(FwdArgs a)
         constexpr int UP = 3;
         constexpr int64_t BP = 128 * UP;
         int64_t jb = jr & ~(int64_t)1;
-        PairBatch<UP> b0, b1;
+        PairBatch<M, UP> b0, b1;
         A acc[UP];
-        pair_batch<UP>(a, (const double *)va, jb, e, lane, b0);
+        pair_batch<M, UP>(a, va, jb, e, lane, b0);
 #pragma unroll
         for (int u = 0; u < UP; ++u) acc[u] = 0;
-        auto step = [&](const PairBatch<UP> &cur, PairBatch<UP> &nxt) -> bool {
+        auto step = [&](const PairBatch<M, UP> &cur, PairBatch<M, UP> &nxt) -> bool {
             const bool last = jb + BP >= e;
             const int64_t jn = last ? (ns & ~(int64_t)1) : jb + BP, en = last ? ne : e;
             A z0[UP], z1[UP];
 #pragma unroll
             for (int u = 0; u < UP; ++u) { z0[u] = zl[cur.c[u] & 0xffffu]; z1[u] = zl[cur.c[u] >> 16]; }
-            pair_batch<UP>(a, (const double *)va, jn, en, lane, nxt);
+            pair_batch<M, UP>(a, va, jn, en, lane, nxt);
 #pragma unroll
             for (int u = 0; u < UP; ++u) {
                 const int64_t p = cur.e0[u];
-                const A q0 = fma((A)cur.r[u].x, z0[u], acc[u]);
+                A x0, x1;
+                pair_values<A, M>(cur.r[u], x0, x1);
+                const A q0 = fma(x0, z0[u], acc[u]);
                 acc[u] = (p >= jr && p < e) ? q0 : acc[u];
-                const A q1 = fma((A)cur.r[u].y, z1[u], acc[u]);
+                const A q1 = fma(x1, z1[u], acc[u]);
                 acc[u] = (p + 1 >= jr && p + 1 < e) ? q1 : acc[u];
             }
             jb = jn;
@@ -1707,11 +1724,12 @@ __global__ __launch_bounds__(kBlock) void k_update_lsmr(UpdArgs a)
 // Instantiated once per vector type V in kernels_f64.hip / kernels_f32.hip.
 namespace lsqr {
 
-// The paired row-group kernel reads values 16 bytes and slots 4 bytes at a
-// time, and one element past the last entry (RowFmt::padded).
+// The paired row-group kernel reads two values and two slots at a time from
+// even positions, and one element past the last entry (RowFmt::padded).
 static inline bool lcol_pairs_ok(const RowFmt &R)
 {
-    return R.padded && ((uintptr_t)R.val & 15u) == 0 && ((uintptr_t)R.slot & 3u) == 0;
+    const uintptr_t w = 2 * (uintptr_t)vt_size(R.vt);
+    return R.padded && ((uintptr_t)R.val & (w - 1)) == 0 && ((uintptr_t)R.slot & 3u) == 0;
 }
 
 template <class M, class V>
@@ -1727,11 +1745,9 @@ static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArg
     }
     if (R.slot) {
         const size_t sh = (size_t)R.gcap * sizeof(typename AccOf<V>::type);
-        if constexpr (sizeof(M) == 8) {
-            if (lcol_pairs_ok(R)) {
-                hipLaunchKernelGGL((k_fwd_lcol_pair<M, V>), dim3(grid), dim3(kBlock), sh, st, a);
-                return;
-            }
+        if (lcol_pairs_ok(R)) {
+            hipLaunchKernelGGL((k_fwd_lcol_pair<M, V>), dim3(grid), dim3(kBlock), sh, st, a);
+            return;
         }
         hipLaunchKernelGGL((k_fwd_lcol<M, V>), dim3(grid), dim3(kBlock), sh, st, a);
         return;
@@ -1845,9 +1861,12 @@ int fwd_lcol_blocks_per_cu(const RowFmt &R)
                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<double, V>, kBlock, sh);
     } else {
         switch (R.vt) {
-        case VT_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<float, V>, kBlock, sh); break;
-        case VT_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<bf16_t, V>, kBlock, sh); break;
-        case VT_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<fp16_t, V>, kBlock, sh); break;
+        case VT_F32: e = lcol_pairs_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<float, V>, kBlock, sh)
+                                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<float, V>, kBlock, sh); break;
+        case VT_BF16: e = lcol_pairs_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<bf16_t, V>, kBlock, sh)
+                                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<bf16_t, V>, kBlock, sh); break;
+        case VT_F16: e = lcol_pairs_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<fp16_t, V>, kBlock, sh)
+                                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<fp16_t, V>, kBlock, sh); break;
         default: break;
         }
     }
