@@ -67,6 +67,9 @@ def _lib():
         lib.oracle_lsqr.argtypes = [OP, P, ctypes.c_int, ctypes.c_double, P, P, P, P, P,
                                     ctypes.c_int]
         lib.oracle_lsqr.restype = ctypes.c_int
+        lib.oracle_lsqr_ref.argtypes = [OP, P, ctypes.c_int, ctypes.c_double, P, P, P,
+                                        ctypes.c_double, P, P, ctypes.c_int]
+        lib.oracle_lsqr_ref.restype = ctypes.c_int
         lib.oracle_lsqr_implicit.argtypes = [OP, P, ctypes.c_int, P]
         lib.oracle_lsqr_implicit.restype = ctypes.c_int
         _lib_handle = lib
@@ -150,6 +153,27 @@ class Operator:
             raise FloatingPointError(f"oracle_lsqr failed with code {rc}")
         k = int(info[1])
         return dict(x=x, hist=hist[:k + 1], istop=int(info[0]), iters=k, U=U, V=V)
+
+    def lsqr_ref(self, dt, iters, tol, snap_tol, stall=200):
+        """LSQR towards a converged reference: stops at eta <= tol, after `iters`,
+        or when eta has not reached a new low for `stall` iterations (istop 5);
+        also returns the first iterate with eta <= snap_tol (x_snap, k_snap = -1
+        if none)."""
+        dt = np.ascontiguousarray(dt, dtype=np.float64)
+        assert dt.shape == (self.m,)
+        x = np.empty(self.n)
+        xs = np.full(self.n, np.nan)
+        hist = np.full((iters + 1, 3), np.nan)
+        info = np.zeros(2, dtype=np.int32)
+        ks = np.zeros(1, dtype=np.int32)
+        rc = _lib().oracle_lsqr_ref(ctypes.byref(self._op), _p(dt), int(iters), float(tol), _p(x),
+                                    _p(hist), _p(info), float(snap_tol), _p(xs), _p(ks),
+                                    int(stall))
+        if rc != 0:
+            raise FloatingPointError(f"oracle_lsqr_ref failed with code {rc}")
+        k = int(info[1])
+        return dict(x=x, hist=hist[:k + 1], istop=int(info[0]), iters=k, x_snap=xs,
+                    k_snap=int(ks[0]))
 
     def lsqr_implicit(self, dt, iters):
         """Implicit-damp LSQR on [G; w L] with damp lambda (no column scaling)."""

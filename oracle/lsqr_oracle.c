@@ -201,10 +201,12 @@ void oracle_jacobi(const oracle_op *op, double *d)
  * Returns 0, or -3 when a scalar became non-finite, or -5 on allocation failure.
  *
  * istop: 0 bbar = 0 or Abar^T bbar = 0 (x = 0); 1 eta <= tol; 2 iteration
- * limit; 3 exact breakdown (alpha or beta = 0).
+ * limit; 3 exact breakdown (alpha or beta = 0); 5 eta stagnated
+ * (oracle_lsqr_ref only).
  */
-int oracle_lsqr(const oracle_op *op, const double *b, int iters, double tol, double *x,
-                double *hist, int32_t *info, double *ucap, double *vcap, int ncap)
+static int lsqr_core(const oracle_op *op, const double *b, int iters, double tol, double *x,
+                     double *hist, int32_t *info, double *ucap, double *vcap, int ncap,
+                     double snap_tol, double *xsnap, int32_t *ksnap, int stall)
 {
     int64_t m = op->m, n = op->n, mb = m + 2 * n;
     int comp = op->compensated;
@@ -242,6 +244,8 @@ int oracle_lsqr(const oracle_op *op, const double *b, int iters, double tol, dou
     double arnorm0 = alpha * beta * norm2(dv, n, comp);     /* |Abar^T bbar| */
     if (hist) { hist[0] = phibar; hist[1] = alpha * beta; hist[2] = 1.0; }
     info[0] = 2;
+    double eta_best = 1.0;
+    int k_best = 0;
 
     for (int k = 1; k <= iters; ++k) {
         /* step 3.1: beta u = A_D v - alpha u */
@@ -282,14 +286,44 @@ int oracle_lsqr(const oracle_op *op, const double *b, int iters, double tol, dou
         if (hist) { hist[3 * k] = phibar; hist[3 * k + 1] = psi; hist[3 * k + 2] = eta; }
         info[1] = k;
         if (!isfinite(rho) || !isfinite(phi)) { rc = -3; goto done; }
+        /* snapshot: the first iterate whose eta reaches snap_tol, as x = D y */
+        if (xsnap && *ksnap < 0 && eta <= snap_tol) {
+            for (int64_t j = 0; j < n; ++j) xsnap[j] = op->d ? op->d[j] * y[j] : y[j];
+            *ksnap = k;
+        }
         if (tol > 0.0 && eta <= tol) { info[0] = 1; break; }
         if (alpha == 0.0 || beta == 0.0) { info[0] = 3; break; }
+        /* stagnation: no new smallest eta over the last `stall` iterations */
+        if (eta < eta_best) { eta_best = eta; k_best = k; }
+        if (stall > 0 && k - k_best >= stall) { info[0] = 5; break; }
     }
     /* step 4: x = D y */
     for (int64_t j = 0; j < n; ++j) x[j] = op->d ? op->d[j] * y[j] : y[j];
 done:
     free(u); free(t); free(v); free(q); free(wv); free(y); free(sc); free(dv);
     return rc;
+}
+
+int oracle_lsqr(const oracle_op *op, const double *b, int iters, double tol, double *x,
+                double *hist, int32_t *info, double *ucap, double *vcap, int ncap)
+{
+    return lsqr_core(op, b, iters, tol, x, hist, info, ucap, vcap, ncap, 0.0, NULL, NULL, 0);
+}
+
+/*
+ * The same iteration, run towards a converged reference: besides stopping at
+ * eta <= tol it keeps a copy of the first iterate with eta <= snap_tol
+ * (xsnap [n], its iteration in *ksnap, -1 if never reached) and stops with
+ * istop 5 when no new smallest eta has appeared for `stall` iterations
+ * (0 = never).  The arithmetic is that of oracle_lsqr.
+ */
+int oracle_lsqr_ref(const oracle_op *op, const double *b, int iters, double tol, double *x,
+                    double *hist, int32_t *info, double snap_tol, double *xsnap, int32_t *ksnap,
+                    int stall)
+{
+    *ksnap = -1;
+    return lsqr_core(op, b, iters, tol, x, hist, info, NULL, NULL, 0, snap_tol, xsnap, ksnap,
+                     stall);
 }
 
 /*

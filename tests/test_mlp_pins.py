@@ -67,3 +67,67 @@ def test_features_against_independent_constructions():
         mu = (w * cen).sum() / w.sum()
         sd = np.sqrt(max((w * (cen - mu) ** 2).sum() / w.sum(), 0))
         assert abs(f[j, 3] - mu) < 1e-12 and abs(f[j, 4] - sd) < 1e-7
+
+
+# Independent values: Phi(1) and Phi(2), the standard normal distribution function,
+# from printed tables of the normal distribution, and ln 2.
+PHI_1 = 0.8413447460685429
+PHI_2 = 0.9772498680518208
+LN2 = 0.6931471805599453
+
+
+def test_gelu_and_softplus_at_known_points():
+    # GELU(x) = x Phi(x): Phi(0) = 1/2, Phi(1) from the table, Phi(-1) = 1 - Phi(1)
+    g = mlp.gelu(np.array([0.0, 1.0, -1.0, 2.0]))
+    assert g[0] == 0.0
+    assert abs(g[1] - PHI_1) < 1e-15
+    assert abs(g[2] + (1.0 - PHI_1)) < 1e-15
+    assert abs(g[3] - 2.0 * PHI_2) < 1e-15
+    # far tails: GELU(x) -> x for x >> 0 and -> 0 for x << 0
+    assert abs(mlp.gelu(np.array([12.0]))[0] - 12.0) < 1e-15
+    assert abs(mlp.gelu(np.array([-12.0]))[0]) < 1e-30
+    # softplus(0) = ln 2; softplus(z) - softplus(-z) = z; tails e^-|z|
+    assert abs(mlp.softplus(np.array([0.0]))[0] - LN2) < 1e-16
+    z = np.array([-7.5, -0.3, 0.0, 0.9, 31.0])
+    assert np.allclose(mlp.softplus(z) - mlp.softplus(-z), z, rtol=0, atol=2e-15)
+    assert abs(mlp.softplus(np.array([-40.0]))[0] - np.exp(-40.0)) < 1e-30
+    # softplus(log(e - 1)) = 1: the output bias that starts the net at Jacobi
+    assert abs(mlp.softplus(np.array([mlp.SOFTPLUS_INV_1]))[0] - 1.0) < 1e-15
+    # sigmoid is softplus' slope: 1/2 at 0, and symmetric
+    assert mlp.sigmoid(np.array([0.0]))[0] == 0.5
+    assert np.allclose(mlp.sigmoid(z) + mlp.sigmoid(-z), 1.0, atol=1e-15)
+
+
+def _two_unit_net():
+    """A net whose only non-zero weights form two units per hidden layer, with
+    values chosen so every activation is a multiple of Phi(1) or 0."""
+    p = {name: np.zeros(shp) for name, shp in mlp.SIZES}
+    p["W1"][0, 0] = 2.0               # a1_0 = 2 * 0.25 + 0.5 = 1       -> h1_0 = Phi(1)
+    p["b1"][0] = 0.5
+    p["W1"][1, 3] = -1.0              # a1_1 = -x3 = -1                  -> h1_1 = -(1 - Phi(1))
+    p["W2"][0, 0] = 1.0 / PHI_1       # a2_0 = 1                          -> h2_0 = Phi(1)
+    p["W2"][5, 0] = 1.0 / PHI_1       # a2_5 = 1 - 2 = -1                 -> h2_5 = -(1 - Phi(1))
+    p["W2"][5, 1] = 2.0 / (1.0 - PHI_1)
+    p["W3"][0] = 1.0                  # z = Phi(1) - (1 - Phi(1)) + b3
+    p["W3"][5] = 1.0
+    p["b3"][0] = 1.0 - 2.0 * PHI_1    # -> z = 0, multiplier ln 2
+    return mlp.pack(p)
+
+
+def test_forward_of_a_hand_evaluated_network():
+    theta = _two_unit_net()
+    x = np.zeros((2, mlp.NF))
+    x[:, 0] = 0.25
+    x[:, 3] = 1.0
+    x[1, 2] = 123.0                   # an input no unit reads
+    z, (xx, a1, h1, a2, h2) = mlp.forward(theta, x)
+    assert np.allclose(a1[:, :2], [[1.0, -1.0]] * 2, atol=1e-15)
+    assert np.allclose(h1[:, :2], [[PHI_1, -(1.0 - PHI_1)]] * 2, atol=1e-15)
+    assert np.all(h1[:, 2:] == 0.0)
+    assert np.allclose(a2[:, [0, 5]], [[1.0, -1.0]] * 2, atol=1e-14)
+    assert np.allclose(h2[:, [0, 5]], [[PHI_1, -(1.0 - PHI_1)]] * 2, atol=1e-14)
+    assert np.allclose(z, 0.0, atol=1e-14)
+    assert np.allclose(mlp.multiplier(theta, x), LN2, atol=1e-14)
+    # the loss against the exact target log(ln 2) is zero, against 0 it is log(ln 2)^2
+    assert mlp.loss(theta, x, np.full(2, np.log(LN2))) < 1e-28
+    assert abs(mlp.loss(theta, x, np.zeros(2)) - np.log(LN2) ** 2) < 1e-14
