@@ -33,6 +33,8 @@ def log(msg):
 
 
 def host_threads():
+    """Threads for the CPU legs: the host CPUs this process may use, at most 16
+    (the host-core share of one GPU on the benchmark machines)."""
     try:
         n = len(os.sched_getaffinity(0))
     except Exception:
@@ -40,18 +42,89 @@ def host_threads():
     return max(1, min(n, 16))
 
 
-def cpu_baseline(s, iters_sample):
-    """The FP64 oracle on the same system: a bounded number of LSQR iterations
-    timed on the host cores (transpose set-up excluded)."""
+def cpu_model():
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
+
+
+def trimmed_mean(xs):
+    """The paper's timing protocol: drop the largest and the smallest run,
+    average the rest."""
+    xs = sorted(xs)
+    core = xs[1:-1] if len(xs) > 2 else xs
+    return sum(core) / len(core)
+
+
+def cpu_baseline(s, iters_sample, runs=10):
+    """The FP64 oracle on the same system: `runs` timed runs of a bounded
+    number of LSQR iterations on the host cores after one untimed warm-up,
+    the slowest and fastest dropped (transpose set-up excluded)."""
     import oracle
     nt = host_threads()
     op = oracle.Operator.from_system(s, nthreads=nt)
-    t0 = time.perf_counter()
-    r = op.lsqr(s.dt, iters_sample)
-    dt = time.perf_counter() - t0
-    return {"value": r["iters"] / dt, "unit": "iters/s", "cores": nt, "kind": "oracle",
+    op.lsqr(s.dt, max(1, iters_sample // 4))            # warm-up (untimed)
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        r = op.lsqr(s.dt, iters_sample)
+        times.append(time.perf_counter() - t0)
+    t = trimmed_mean(times)
+    return {"value": r["iters"] / t, "unit": "iters/s", "cores": nt, "kind": "oracle",
             "sample": f"{r['iters']} FP64 LSQR iterations (plus the start step) of the same "
-                      f"system, {dt:.1f} s"}
+                      f"system, {runs} runs after a warm-up, slowest and fastest dropped, "
+                      f"{t:.2f} s per run",
+            "runs_s": times, "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def scipy_lsqr_context(s, iters=3):
+    """SciPy's LSQR (single-threaded sparse products) on the same regularised
+    operator for a few iterations: the analogue of the paper's CPU solver
+    path, for context only."""
+    import scipy.sparse as sp
+    from scipy.sparse.linalg import LinearOperator, lsqr
+    G = sp.csr_matrix((s.val, s.col, s.row_ptr), shape=(s.m, s.n), copy=False)
+    Gt = G.T                                   # CSC view, no copy
+    nx, ny, nz = s.nx, s.ny, s.nz
+
+    def lap(x):
+        u = x.reshape(ny, nx, nz)
+        y = np.zeros_like(u)
+        for ax in range(3):
+            k = u.shape[ax]
+            if k < 2:
+                continue
+            d = np.diff(u, axis=ax)
+            sl_lo = [slice(None)] * 3
+            sl_hi = [slice(None)] * 3
+            sl_lo[ax] = slice(0, k - 1)
+            sl_hi[ax] = slice(1, k)
+            y[tuple(sl_lo)] += d
+            y[tuple(sl_hi)] -= d
+        return y.reshape(-1)
+
+    m, n = s.m, s.n
+
+    def mv(x):
+        return np.concatenate([G @ x, s.smooth * lap(x), s.damp * x])
+
+    def rmv(y):
+        return Gt @ y[:m] + s.smooth * lap(y[m:m + n]) + s.damp * y[m + n:]
+
+    A = LinearOperator((m + 2 * n, n), matvec=mv, rmatvec=rmv, dtype=np.float64)
+    b = np.concatenate([s.dt, np.zeros(2 * n)])
+    t0 = time.perf_counter()
+    lsqr(A, b, damp=0.0, atol=0.0, btol=0.0, conlim=0.0, iter_lim=iters)
+    t = time.perf_counter() - t0
+    return {"value": iters / t, "unit": "iters/s", "iters": iters, "seconds": t,
+            "threads": 1, "kind": "scipy.sparse.linalg.lsqr on the same operator (context)"}
 
 
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_11920_amd", "csrc", f)
@@ -134,9 +207,11 @@ def assembly_check(s, host_s):
     return r
 
 
-def fp32_rate(s, dt, iters, fmt, steps=3):
+def fp32_rate(s, dt, iters, fmt, gold=None, steps=3):
     """FP32 values, vectors and accumulation (FP64 scalars): iterations/s and
-    kernel rates on the same system, same iteration count."""
+    kernel rates on the same system, same iteration count; with the stored
+    oracle results, the error of the last iterate against the oracle's FP64
+    iterate at the same count and against x*."""
     import torch
     from paper_2604_11920_amd import Solver
     with Solver.from_system(s, precision="fp32", timing=True, **fmt) as sol:
@@ -155,12 +230,34 @@ def fp32_rate(s, dt, iters, fmt, steps=3):
     r = {"iters_per_s": iters * steps / wall, "ms_per_step": wall * 1e3 / steps,
          "fwd": {"avg_us": fa * 1e3, "alg_bytes": ks["fwd_bytes"], "gbs": ks["fwd_bytes"] / fa / 1e6},
          "adj": {"avg_us": aa * 1e3, "alg_bytes": ks["adj_bytes"], "gbs": ks["adj_bytes"] / aa / 1e6}}
+    if gold is not None and f"x{iters}_comp" in gold:
+        x = dm.cpu().numpy()
+        ref, xs = gold[f"x{iters}_comp"], gold["x_star"]
+        r["err_vs_oracle_same_iters"] = float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+        r["err_vs_xstar"] = float(np.linalg.norm(x - xs) / np.linalg.norm(xs))
     log(f"[bench] fp32: {r['iters_per_s']:.1f} it/s; fwd {r['fwd']['gbs']:.0f} GB/s, "
         f"adj {r['adj']['gbs']:.0f} GB/s")
     return r
 
 
-def time_to_tol(s, dt, tol, fmt, model_path=None):
+GOLDEN = os.path.join(ROOT, "tests", "golden", "cfg1_seed0.npz")
+
+
+def golden_reference(s):
+    """The oracle's converged solution x* and fixed-count iterates for this
+    system, when the stored reference results describe it (else None)."""
+    import synth
+    try:
+        z = np.load(GOLDEN, allow_pickle=False)
+        meta = json.loads(str(z["meta"]))
+    except (OSError, KeyError, ValueError):
+        return None
+    if meta.get("fingerprint") != synth.fingerprint(s):
+        return None
+    return {k: z[k] for k in z.files if k != "meta"}
+
+
+def time_to_tol(s, dt, tol, fmt, model_path=None, xstar=None):
     """Wall time to eta = |Abar^T r| / |Abar^T bbar| <= tol for each form, each
     result's eta re-checked explicitly with the FP64 operator on the GPU.  The
     system is resident (created before the clock starts); for the learned
@@ -222,6 +319,9 @@ def time_to_tol(s, dt, tol, fmt, model_path=None):
             ref = dm.clone()
         if ref is not None and not (prec == "fp64" and pc == "jacobi"):
             out[key]["rel_diff_vs_fp64_jacobi"] = ((dm - ref).norm() / ref.norm()).item()
+        if xstar is not None:
+            out[key]["err_vs_xstar"] = ((dm - xstar).norm() / xstar.norm()).item()
+        out[key]["eta_final_fp64_lib"] = info["eta_final_fp64"]
         log(f"[bench] time-to-tol {key}: {wall:.2f}s, iters={info['iters']} "
             f"sweeps={info['sweeps']} istop={info['istop']} eta_fp64={eta:.2e}")
     checker.close()
@@ -344,8 +444,12 @@ def main():
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-runs", type=int, default=10,
+                    help="timed runs of the CPU oracle sample (the paper's protocol: 10)")
+    ap.add_argument("--no-scipy", action="store_true", help="skip the SciPy LSQR context timing")
     ap.add_argument("--row-format", default="auto", choices=["auto", "csr", "runs", "masks", "groups"])
-    ap.add_argument("--col-format", default="auto", choices=["auto", "csc", "runs", "masks", "pairs"])
+    ap.add_argument("--col-format", default="auto",
+                    choices=["auto", "csc", "runs", "masks", "pairs", "slices"])
     ap.add_argument("--xcd-bands", action="store_true",
                     help="transposed product: one contiguous column band per XCD")
     ap.add_argument("--no-extras", action="store_true",
@@ -477,7 +581,8 @@ def main():
                                 {1: "k_adj (transposed product, CSC)",
                                  2: "k_adj_nruns (transposed product, node runs)",
                                  3: "k_adj_nmask (transposed product, node masks)",
-                                 4: "k_adj_npair (transposed product, node runs, depth pairs)"}
+                                 4: "k_adj_npair (transposed product, node runs, depth pairs)",
+                                 5: "k_adj_slices (transposed product, run slices)"}
                                 [ks["col_format"]])},
         "kernels": {"fwd": {"avg_us": fwd_avg * 1e3, "alg_bytes": ks["fwd_bytes"], "gbs": fwd_gbs},
                     "adj": {"avg_us": adj_avg * 1e3, "alg_bytes": ks["adj_bytes"], "gbs": adj_gbs}},
@@ -486,14 +591,19 @@ def main():
     sol.close()
     del sol
     if not args.no_extras:
+        gold = golden_reference(s) if args.config == "cfg1" else None
+        xstar = torch.from_numpy(gold["x_star"]).cuda() if gold is not None else None
         out["assembly"] = assembly_check(s, gen_s)
-        out["fp32"] = fp32_rate(s, dt, iters, fmt)
-        out["time_to_tol"] = time_to_tol(s, dt, args.ttt_tol, fmt, args.model)
+        out["fp32"] = fp32_rate(s, dt, iters, fmt, gold)
+        out["time_to_tol"] = time_to_tol(s, dt, args.ttt_tol, fmt, args.model, xstar)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample ...")
-        out["cpu_baseline"] = cpu_baseline(s, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_iters, args.cpu_runs)
         log(f"[bench] cpu oracle {out['cpu_baseline']['value']:.3f} it/s on "
-            f"{out['cpu_baseline']['cores']} threads")
+            f"{out['cpu_baseline']['cores']} threads ({out['cpu_baseline']['cpu_model']})")
+        if args.config == "cfg1" and not args.no_scipy:
+            out["scipy_lsqr"] = scipy_lsqr_context(s)
+            log(f"[bench] scipy lsqr {out['scipy_lsqr']['value']:.3f} it/s (one thread)")
     print(json.dumps(out), flush=True)
 
 

@@ -126,7 +126,14 @@ typedef struct {
                                 /* layout (each run stored from an even position with */
                                 /* a zero before an odd first depth and after an odd  */
                                 /* end, so two depths load as one aligned word; a     */
-                                /* second, padded copy of the node-run values)        */
+                                /* second, padded copy of the node-run values), 5 =   */
+                                /* run slices (per node, its runs grouped by first    */
+                                /* depth and cut into slices of 64 runs, one run per  */
+                                /* lane; per step of depths the slice's 64 values     */
+                                /* side by side, so a wave-wide load covers one depth */
+                                /* step of 64 runs; shorter runs padded with zeros;   */
+                                /* a copy of the values in this layout, of the        */
+                                /* solver's value type)                               */
     double refine_inner_tol;    /* mixed precision: relative eta each inner solve     */
                                 /* reaches before the FP64 correction (0 = 1e-2); a   */
                                 /* sweep cannot gain more than the quantisation error */
@@ -141,6 +148,16 @@ typedef struct {
                                 /* |A_D^T r| / |A_D^T bbar| (equal to the original    */
                                 /* variables' for D = I); the batched entry point     */
                                 /* runs LSQR                                          */
+    int fallback_iters;         /* precond USER with tol > 0: when the solve has not  */
+                                /* reached tol after this many iterations (total      */
+                                /* inner iterations for BF16/FP16, or a refinement    */
+                                /* sweep that fails to halve eta), the Jacobi scale   */
+                                /* replaces the user scale and the solve continues    */
+                                /* from its current dm (info.fallback_used = 1; the   */
+                                /* history is the continuation's); a                  */
+                                /* natural choice is twice Jacobi's count on the      */
+                                /* system.  0 = no fallback.  The context keeps the   */
+                                /* user scale for later solves.                        */
 } lsqr_opts;
 
 /* Stop reasons (info.istop):
@@ -153,11 +170,19 @@ typedef struct {
  *   4  mixed-precision refinement stalled (eta did not halve in a sweep)  */
 typedef struct {
     int istop;
-    int iters;                  /* iterations done (total inner iterations if mixed)  */
+    int iters;                  /* iterations done (total inner iterations if mixed;  */
+                                /* with a fallback, the user-scale attempt included)  */
     int sweeps;                 /* refinement sweeps done (mixed forms), else 0        */
-    int fallback_used;          /* 1 if user scales were rejected for Jacobi           */
-    double eta;                 /* final eta estimate                                  */
+    int fallback_used;          /* 1 if user scales were rejected for Jacobi, at      */
+                                /* creation (not finite and > 0) or by the solve      */
+                                /* (opts.fallback_iters)                              */
+    double eta;                 /* final eta estimate (LSMR: scaled variables)         */
     double phibar;              /* final |bbar - Abar dm| estimate                     */
+    double eta_final_fp64;      /* eta of the returned dm recomputed at exit with the  */
+                                /* FP64 operator, |Abar^T (bbar - Abar dm)| /          */
+                                /* |Abar^T bbar| in the original variables (every     */
+                                /* form and method), when tol > 0; NaN for fixed      */
+                                /* iteration counts (tol = 0)                          */
 } lsqr_info;
 
 typedef struct lsqr_ctx lsqr_ctx;
@@ -173,7 +198,8 @@ typedef struct {
     int row_format;             /* format the solver's forward product reads: 1 CSR,  */
                                 /* 2 depth runs, 3 run masks, 4 row groups            */
     int col_format;             /* transposed product: 1 CSC, 2 node runs, 3 node     */
-                                /* masks, 4 node runs in the depth-pair layout        */
+                                /* masks, 4 node runs in the depth-pair layout, 5 run */
+                                /* slices                                             */
 } lsqr_kstats;
 
 /*
@@ -229,10 +255,12 @@ lsqr_status lsqr_rays_size(const lsqr_rays *rays, int64_t *m, int64_t *nnz);
  * row_ptr [m+1], col_idx [nnz], val [nnz] (sizes from lsqr_rays_size), on
  * `stream` (a hipStream_t, NULL = default); returns after the arrays are
  * complete.  The result can be passed to lsqr_create with mem = DEVICE.
- * The ray arrays are staged in temporary device buffers that the call
- * allocates (hipMalloc) and frees before it returns.
+ * The ray arrays are staged in temporary device buffers taken from alloc
+ * (hipMalloc when alloc is NULL) and returned through dealloc before the
+ * call returns.
  * Errors: INVALID_ARG, NONFINITE, UNSUPPORTED, DEVICE, OOM. */
-lsqr_status lsqr_assemble_rays(const lsqr_rays *rays, void *stream, int64_t *row_ptr,
+lsqr_status lsqr_assemble_rays(const lsqr_rays *rays, void *stream, lsqr_alloc_fn alloc,
+                               lsqr_free_fn dealloc, void *alloc_user, int64_t *row_ptr,
                                int32_t *col_idx, double *val);
 
 /*
@@ -353,6 +381,25 @@ lsqr_status lsqr_apply(lsqr_ctx *ctx, const double *x, double *y);
 lsqr_status lsqr_apply_t(lsqr_ctx *ctx, const double *y, double *x);
 
 /*
+ * lsqr_apply_stored / lsqr_apply_t_stored — the solver's own sparse products
+ * as plain operator applications: the stored format and value type its
+ * iterations read (FP64 or FP32 values, or for BF16/FP16 the row scales
+ * sigma times the 16-bit codes Q; the forward product of eq. (6) and its
+ * transpose), without the column scaling, for inspection and testing:
+ *   y = [Ghat z; w L z; lambda z],  Ghat = G in the solver's value type, or
+ *                                   diag(sigma) Q for the 16-bit forms;
+ *   q = Ghat^T y_G + w L y_L + lambda y_D, where the data block reads tg
+ *       instead of y_G when tg != NULL: the 16-bit forms' transposed product
+ *       gathers tg = sigma * y_G (the row scale applied to the gathered
+ *       vector, as in the solver) and computes Q^T tg.
+ * Vectors are device arrays of the solver's vector type (double for FP64,
+ * float for the other forms): z [n], y [m+2n], tg [m], q [n].  Enqueued
+ * only.  Errors: INVALID_ARG.
+ */
+lsqr_status lsqr_apply_stored(lsqr_ctx *ctx, const void *z, void *y);
+lsqr_status lsqr_apply_t_stored(lsqr_ctx *ctx, const void *y, const void *tg, void *q);
+
+/*
  * lsqr_set_scale — replace the column scaling D (x = D y) by host d [n],
  * finite and > 0 (else INVALID_ARG and D unchanged).  Any d leaves the
  * regularised least-squares solution unchanged (only the iteration count
@@ -415,8 +462,12 @@ lsqr_status lsqr_mlp_scale(lsqr_ctx *ctx, const float *params, const float *mean
 typedef struct lsqr_trainer lsqr_trainer;
 
 /* lsqr_trainer_create — params: host [LSQR_MLP_NPARAMS] initial values;
- * max_batch: largest minibatch; stream: hipStream_t for all its work. */
-lsqr_status lsqr_trainer_create(int max_batch, const float *params, void *stream, lsqr_trainer **out);
+ * max_batch: largest minibatch; stream: hipStream_t for all its work;
+ * alloc/dealloc/alloc_user: device allocator of its buffers (NULL alloc:
+ * hipMalloc), released by lsqr_trainer_destroy. */
+lsqr_status lsqr_trainer_create(int max_batch, const float *params, void *stream,
+                                lsqr_alloc_fn alloc, lsqr_free_fn dealloc, void *alloc_user,
+                                lsqr_trainer **out);
 
 /*
  * lsqr_trainer_grad — loss = mean over the batch of (log softplus(z_b) -

@@ -380,12 +380,13 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         return fail(nullptr, LSQR_E_INVALID_ARG, "lanes must be 0, 4, 8, 16, 32 or 64");
     if (o.row_format < 0 || o.row_format > 4)
         return fail(nullptr, LSQR_E_INVALID_ARG, "row_format must be 0, 1, 2, 3 or 4");
-    if (o.col_format < 0 || o.col_format > 4)
-        return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1, 2, 3 or 4");
+    if (o.col_format < 0 || o.col_format > 5)
+        return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1, 2, 3, 4 or 5");
     if (o.method < 0 || o.method > 1)
         return fail(nullptr, LSQR_E_INVALID_ARG, "method must be 0 (LSQR) or 1 (LSMR)");
     if (o.check_every < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "check_every must be >= 0");
     if (o.refine_sweeps < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "refine_sweeps must be >= 0");
+    if (o.fallback_iters < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "fallback_iters must be >= 0");
     if (!(o.refine_inner_tol >= 0.0 && o.refine_inner_tol < 1.0))
         return fail(nullptr, LSQR_E_INVALID_ARG, "refine_inner_tol must be in [0, 1)");
     if (G->mem == LSQR_MEM_HOST) {
@@ -403,6 +404,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     c->st = (hipStream_t)o.stream;
     c->prec = o.precision; c->precond = o.precond; c->flags = o.flags;
     c->method = o.method;
+    c->fallback_iters = o.fallback_iters;
     c->check_every = o.check_every > 0 ? o.check_every : 32;
     c->check_every += c->check_every & 1;
     c->refine_sweeps = o.refine_sweeps > 0 ? o.refine_sweeps : 5;
@@ -519,10 +521,14 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     // transposed product measured on gfx950)
     bool use_nruns = false;
     NodeRuns NR;
-    const bool nruns_ok = (o.col_format == 2 || o.col_format == 0 || o.col_format == 4) && nnz > 0 &&
+    const bool nruns_ok = (o.col_format == 2 || o.col_format == 0 || o.col_format == 4 ||
+                           o.col_format == 5) && nnz > 0 &&
                           build_node_runs_host(m, n, G->nz, hrow, hcol, NR);
-    if ((o.col_format == 2 || o.col_format == 4) && nnz > 0 && !nruns_ok)
+    if ((o.col_format == 2 || o.col_format == 4 || o.col_format == 5) && nnz > 0 && !nruns_ok)
         return bail(LSQR_E_UNSUPPORTED, "node runs need nz <= 64, m < 2^32 and nnz < 2^32");
+    const bool use_slices = nruns_ok && o.col_format == 5;
+    const int sl_vt = o.precision == LSQR_FP64 ? VT_F64 : o.precision == LSQR_FP32 ? VT_F32
+                      : o.precision == LSQR_BF16 ? VT_BF16 : VT_F16;
     if (nruns_ok) {
         const int64_t nr = NR.nrp.back(), nn = n / G->nz;
         c->nnruns = nr;
@@ -549,6 +555,26 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         CR_TRY(hipMemcpy(c->nsrc, NR.src.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->ndst, NR.dst.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         launch_gather_runs(st, nr, c->nsrc, c->ndst, c->ndesc, c->va, c->nval, 8);
+        if (use_slices) {      // run slices: structure now, values once their type exists
+            RunSlices RS;
+            slice_layout_host(NR, nn, slice_width(sl_vt), RS);
+            c->nslices = RS.sptr.back();
+            c->sl_total = RS.total;
+            c->sl_ptr = ctx_alloc<int64_t>(c, nn + 1);
+            c->sl_off = ctx_alloc<int64_t>(c, c->nslices);
+            c->sl_desc = ctx_alloc<uint16_t>(c, c->nslices);
+            c->sl_row = ctx_alloc<uint32_t>(c, c->nslices * 64);
+            c->sl_dst = ctx_alloc<uint64_t>(c, nr);
+            if (!c->sl_ptr || !c->sl_off || !c->sl_desc || !c->sl_row || !c->sl_dst)
+                return bail(LSQR_E_OOM, "device allocation failed");
+            CR_TRY(hipMemcpy(c->sl_ptr, RS.sptr.data(), (nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+            if (c->nslices) {
+                CR_TRY(hipMemcpy(c->sl_off, RS.off.data(), c->nslices * sizeof(int64_t), hipMemcpyHostToDevice));
+                CR_TRY(hipMemcpy(c->sl_desc, RS.desc.data(), c->nslices * sizeof(uint16_t), hipMemcpyHostToDevice));
+                CR_TRY(hipMemcpy(c->sl_row, RS.row.data(), c->nslices * 64 * sizeof(uint32_t), hipMemcpyHostToDevice));
+            }
+            CR_TRY(hipMemcpy(c->sl_dst, RS.dst.data(), nr * sizeof(uint64_t), hipMemcpyHostToDevice));
+        }
         // depth-pair layout (auto and col_format 4): runs padded to aligned
         // pairs of depths, the faster transposed product measured on gfx950
         std::vector<uint32_t> dstp;
@@ -670,8 +696,13 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         if (!use_jacobi) {
             bool ok = true;
             for (int64_t j = 0; j < n && ok; ++j) ok = isfinite(o.col_scale[j]) && o.col_scale[j] > 0.0;
-            if (ok) CR_TRY(hipMemcpyAsync(c->d, o.col_scale, n * sizeof(double), hipMemcpyHostToDevice, st));
-            else { use_jacobi = true; c->fallback_used = 1; }
+            if (ok) {
+                CR_TRY(hipMemcpyAsync(c->d, o.col_scale, n * sizeof(double), hipMemcpyHostToDevice, st));
+                c->user_scale = true;
+            } else {
+                use_jacobi = true;
+                c->fallback_used = 1;
+            }
         }
         if (use_jacobi) launch_jacobi(st, c->P, c->C64, c->d);
     }
@@ -686,6 +717,26 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     }
     set_node_masks(c, C);
     int vec = VT_F64;
+    // the run-slice values of the solver's type, scattered from its CSR-order
+    // copy (FP64 values, FP32 values or 16-bit codes)
+    auto attach_slices = [&](ColFmt &F, const void *src, int vt) -> lsqr_status {
+        const size_t es = vt_size(vt);
+        const int W = slice_width(vt);
+        c->sl_val = ctx_alloc_bytes(c, (size_t)(c->sl_total + W) * es);
+        if (!c->sl_val) return LSQR_E_OOM;
+        if (hipMemsetAsync(c->sl_val, 0, (size_t)(c->sl_total + W) * es, st) != hipSuccess)
+            return LSQR_E_DEVICE;
+        launch_scatter_slices(st, c->nnruns, c->nsrc, c->sl_dst, c->ndesc, W, src, c->sl_val, (int)es);
+        c->sl_vt = vt;
+        F.sl_ptr = c->sl_ptr; F.sl_off = c->sl_off; F.sl_desc = c->sl_desc; F.sl_row = c->sl_row;
+        F.norder = c->norder; F.nzt = G->nz; F.val = c->sl_val; F.vt = vt;
+        F.nrp = nullptr; F.pairs = 0; F.mmask = nullptr;
+        return LSQR_OK;
+    };
+    if (use_slices && o.precision == LSQR_FP64) {
+        lsqr_status ss = attach_slices(C, c->va, VT_F64);
+        if (ss != LSQR_OK) return bail(ss, "run-slice values: device allocation or fill failed");
+    }
     if (o.precision == LSQR_FP32) {
         c->va32 = ctx_alloc<float>(c, nnz + 1);     // with va's padding element
         c->cv32 = ctx_alloc<float>(c, nnz);
@@ -705,6 +756,10 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
                 launch_convert_f32(st, c->npad + 2, c->nvalp, c->nvalp32);
                 C.val = c->nvalp32;
             }
+        }
+        if (use_slices) {
+            lsqr_status ss = attach_slices(C, c->va32, VT_F32);
+            if (ss != LSQR_OK) return bail(ss, "run-slice values: device allocation or fill failed");
         }
         vec = VT_F32;
     } else if (mixed) {
@@ -751,6 +806,10 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
                 C.pairs = 4;
             }
         }
+        if (use_slices) {
+            lsqr_status ss = attach_slices(C, c->qrow, vt);
+            if (ss != LSQR_OK) return bail(ss, "run-slice values: device allocation or fill failed");
+        }
         c->CQ = C;
         vec = VT_F32;
     }
@@ -762,16 +821,94 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         ctx_release(c, c->nsrc);
         ctx_release(c, c->ndst);
         c->nsrc = c->ndst = nullptr;
+        if (c->sl_dst) {
+            ctx_release(c, c->sl_dst);
+            c->sl_dst = nullptr;
+        }
     }
     *out = c;
     return LSQR_OK;
 #undef CR_TRY
 }
 
+// eta of dm in the original variables, recomputed with the FP64 operator:
+// |Abar^T (bbar - Abar dm)| / |Abar^T bbar| (the stopping ratio of the
+// solver section's normal-equation residual, checked outside the
+// recurrence).  0 when Abar^T bbar = 0 and dm satisfies the normal equations.
+static lsqr_status verify_eta(lsqr_ctx *c, const double *ddt, const double *ddm, double *eta)
+{
+    hipStream_t st = c->st;
+    const Problem &P = c->P;
+    const int64_t n = P.n, mb = P.m + 2 * n;
+    const int gadj = std::min(2048, c->eng.g_adj);
+    if (!c->wr) c->wr = ctx_alloc<double>(c, mb);
+    if (!c->wg) c->wg = ctx_alloc<double>(c, n);
+    if (!c->wr || !c->wg) return fail(c, LSQR_E_OOM, "device allocation failed");
+    launch_fwd(st, P, c->eng.g_fwd, VT_F64, c->R64, ddm, nullptr, c->ybuf, nullptr, c->Pf, nullptr,
+               0, nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
+    launch_residual(st, P, c->g_ref, ddt, c->ybuf, c->wr, nullptr, nullptr, c->Pr);
+    launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, c->wr, c->wr, nullptr, c->wg, c->Pa, nullptr,
+               0, nullptr, nullptr, 0, MODE_OPERATOR, 0);
+    launch_sum_partials(st, c->Pa, gadj, c->sums + 0);
+    launch_residual(st, P, c->g_ref, ddt, nullptr, c->wr, nullptr, nullptr, c->Pr);
+    launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, c->wr, c->wr, nullptr, c->wg, c->Pa, nullptr,
+               0, nullptr, nullptr, 0, MODE_OPERATOR, 0);
+    launch_sum_partials(st, c->Pa, gadj, c->sums + 1);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipMemcpyAsync(c->hsum, c->sums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    const double num = sqrt(c->hsum[0]), den = sqrt(c->hsum[1]);
+    *eta = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+    return LSQR_OK;
+}
+
+// Learned-scale fallback: swap the Jacobi scale in (keeping the caller's
+// scale to restore afterwards), and back.
+static lsqr_status fallback_to_jacobi(lsqr_ctx *c)
+{
+    const int64_t n = c->P.n;
+    if (!c->d_user) c->d_user = ctx_alloc<double>(c, n);
+    if (!c->d_user) return fail(c, LSQR_E_OOM, "device allocation failed");
+    HIP_TRY(c, hipMemcpyAsync(c->d_user, c->d, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    launch_jacobi(c->st, c->P, c->C64, c->d);
+    HIP_TRY(c, hipGetLastError());
+    return LSQR_OK;
+}
+
+static lsqr_status restore_user_scale(lsqr_ctx *c)
+{
+    HIP_TRY(c, hipMemcpyAsync(c->d, c->d_user, c->P.n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return LSQR_OK;
+}
+
 static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0, int iters,
                                double tol, double *ddm, double *res_hist, lsqr_info *info);
 static lsqr_status solve_warm(lsqr_ctx *c, const double *ddt, int iters, double tol, double *ddm,
                               double *res_hist, lsqr_info *info);
+
+// Cold start of the plain (FP64 / FP32) forms on the device right-hand side.
+static lsqr_status solve_plain(lsqr_ctx *c, const double *ddt, int iters, double tol, double *ddm,
+                               double *res_hist, lsqr_info *info)
+{
+    const bool timing = (c->flags & LSQR_FLAG_TIMING) != 0;
+    if (timing) c->ks = lsqr_kstats{};
+    lsqr_status s = engine_solve(c, c->eng, ddt, 0, iters, tol, ddm, 0, timing);
+    if (s != LSQR_OK) return s;
+    std::vector<double> hs;
+    s = read_state(c, c->eng, iters, hs);
+    if (s != LSQR_OK) return s;
+    const int kdone = c->hctl[C_ITERS], istop = c->hctl[C_ISTOP];
+    if (res_hist) write_history(hs, iters, kdone, istop, res_hist);
+    info->istop = istop;
+    info->iters = kdone;
+    info->sweeps = 0;
+    info->fallback_used = c->fallback_used;
+    const double *Sk = hs.data() + (size_t)kdone * kStateWords;
+    info->eta = istop == 0 ? 0.0 : Sk[S_ETA];
+    info->phibar = istop == 0 ? hs[S_BETA] : Sk[S_PHIBAR];
+    return LSQR_OK;
+}
 
 static lsqr_status solve_common(lsqr_ctx *c, const double *dt, const double *x0, lsqr_mem vec_mem,
                                 int iters, double tol, double *dm, double *res_hist,
@@ -822,30 +959,42 @@ static lsqr_status solve_common(lsqr_ctx *c, const double *dt, const double *x0,
         }
     }
     lsqr_status s;
+    lsqr_info loc{};
+    if (!info) info = &loc;
+    // the learned-scale fallback: a first attempt capped at fallback_iters
+    const bool fb = !mixed && c->user_scale && c->fallback_iters > 0 && tol > 0.0 &&
+                    iters > c->fallback_iters;
     if (mixed) {
         s = solve_mixed(c, ddt, x0 ? ddm : nullptr, iters, tol, ddm, res_hist, info);
         if (s != LSQR_OK) return s;
-    } else if (x0) {
-        s = solve_warm(c, ddt, iters, tol, ddm, res_hist, info);
+    } else if (x0 || fb) {
+        const int first = fb ? c->fallback_iters : iters;
+        s = x0 ? solve_warm(c, ddt, first, tol, ddm, res_hist, info)
+               : solve_plain(c, ddt, first, tol, ddm, res_hist, info);
         if (s != LSQR_OK) return s;
+        if (fb && info->istop == 2) {
+            // not converged within the budget: Jacobi from the current dm
+            const int used = info->iters;
+            if ((s = fallback_to_jacobi(c)) != LSQR_OK) return s;
+            s = solve_warm(c, ddt, iters - used, tol, ddm, res_hist, info);
+            lsqr_status r = restore_user_scale(c);
+            if (s != LSQR_OK) return s;
+            if (r != LSQR_OK) return r;
+            info->iters += used;
+            info->fallback_used = 1;
+        }
     } else {
-        const bool timing = (c->flags & LSQR_FLAG_TIMING) != 0;
-        if (timing) c->ks = lsqr_kstats{};
-        s = engine_solve(c, c->eng, ddt, 0, iters, tol, ddm, 0, timing);
+        s = solve_plain(c, ddt, iters, tol, ddm, res_hist, info);
         if (s != LSQR_OK) return s;
-        std::vector<double> hs;
-        s = read_state(c, c->eng, iters, hs);
-        if (s != LSQR_OK) return s;
-        const int kdone = c->hctl[C_ITERS], istop = c->hctl[C_ISTOP];
-        if (res_hist) write_history(hs, iters, kdone, istop, res_hist);
-        if (info) {
-            info->istop = istop;
-            info->iters = kdone;
-            info->sweeps = 0;
-            info->fallback_used = c->fallback_used;
-            const double *Sk = hs.data() + (size_t)kdone * kStateWords;
-            info->eta = istop == 0 ? 0.0 : Sk[S_ETA];
-            info->phibar = istop == 0 ? hs[S_BETA] : Sk[S_PHIBAR];
+    }
+    info->eta_final_fp64 = NAN;
+    if (tol > 0.0) {
+        if (mixed) {
+            // every exit of the refinement follows its FP64 eta of the final dm
+            info->eta_final_fp64 = info->eta;
+        } else {
+            s = verify_eta(c, ddt, ddm, &info->eta_final_fp64);
+            if (s != LSQR_OK) return s;
         }
     }
     if (vec_mem == LSQR_MEM_HOST) {
@@ -902,6 +1051,9 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0
     const double arnorm = sqrt(c->hsum[0]);
     int istop = 2, total = 0, sweeps = 0, last_iters = 0, last_istop = 2;
     double eta = 0.0, rnorm = 0.0, eta_prev = INFINITY;
+    // learned-scale fallback: Jacobi once the inner iterations pass the budget
+    const bool fb = c->user_scale && c->fallback_iters > 0;
+    bool switched = false;
     std::vector<double> hs;
     if (!(arnorm > 0.0)) {
         istop = 0;
@@ -928,7 +1080,12 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0
             if (!isfinite(eta)) return fail(c, LSQR_E_NONFINITE, "refinement residual became non-finite");
             if (eta <= tol) { istop = 1; break; }
             if (sw >= c->refine_sweeps) { istop = 2; break; }
-            if (sw > 0 && eta > 0.5 * eta_prev) { istop = 4; break; }
+            if (sw > 0 && eta > 0.5 * eta_prev) {
+                if (!fb || switched) { istop = 4; break; }
+                // a user scale that stalls the refinement: Jacobi from here
+                if ((s = fallback_to_jacobi(c)) != LSQR_OK) return s;
+                switched = true;
+            }
             eta_prev = eta;
             // inner solve on the quantised operator, x += D y
             s = engine_solve(c, E, c->fbuf, 1, iters, inner_tol, c->xbuf, 1, timing);
@@ -938,8 +1095,14 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0
             last_istop = c->hctl[C_ISTOP];
             total += last_iters;
             ++sweeps;
+            if (fb && !switched && total >= c->fallback_iters) {
+                if ((s = fallback_to_jacobi(c)) != LSQR_OK) return s;
+                switched = true;
+                eta_prev = INFINITY;      // the stall test restarts with the new scale
+            }
         }
     }
+    if (switched && (s = restore_user_scale(c)) != LSQR_OK) return s;
     HIP_TRY(c, hipMemcpyAsync(ddm, c->xbuf, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIP_TRY(c, hipStreamSynchronize(st));
     if (res_hist) {
@@ -950,7 +1113,7 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0
         info->istop = istop;
         info->iters = total;
         info->sweeps = sweeps;
-        info->fallback_used = c->fallback_used;
+        info->fallback_used = c->fallback_used | (switched ? 1 : 0);
         info->eta = eta;
         info->phibar = rnorm;
     }
@@ -1056,9 +1219,37 @@ lsqr_status lsqr_apply_t(lsqr_ctx *c, const double *y, double *x)
         for (int x = 0; x < 9; ++x) C.nseg[x] = c->nseg[x];
         if (c->nvalp) { C.nvq = c->nvqp; C.val = c->nvalp; C.pairs = 2; }
     }
+    if (c->sl_val && c->sl_vt == VT_F64) {
+        C.sl_ptr = c->sl_ptr; C.sl_off = c->sl_off; C.sl_desc = c->sl_desc; C.sl_row = c->sl_row;
+        C.norder = c->norder; C.nzt = c->P.nz; C.val = c->sl_val; C.nrp = nullptr; C.pairs = 0;
+    }
     set_node_masks(c, C);
     launch_adj(c->st, c->P, std::min(2048, c->eng.g_adj), VT_F64, C, c->d, y, y, nullptr, x,
                c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 0);
+    HIP_TRY(c, hipGetLastError());
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_apply_stored(lsqr_ctx *c, const void *z, void *y)
+{
+    if (!c) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx is NULL");
+    if (!z || !y) return fail(c, LSQR_E_INVALID_ARG, "z and y must not be NULL");
+    DeviceGuard dg(c->device);
+    Engine &E = c->eng;
+    launch_fwd(c->st, c->P, E.g_fwd, E.vec, E.R, z, nullptr, y, nullptr, E.P1, nullptr, 0,
+               nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
+    HIP_TRY(c, hipGetLastError());
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_apply_t_stored(lsqr_ctx *c, const void *y, const void *tg, void *q)
+{
+    if (!c) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx is NULL");
+    if (!y || !q) return fail(c, LSQR_E_INVALID_ARG, "y and q must not be NULL");
+    DeviceGuard dg(c->device);
+    Engine &E = c->eng;
+    launch_adj(c->st, c->P, E.g_adj, E.vec, E.C, c->ones, y, tg ? tg : y, nullptr, q, E.P2,
+               nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 0);
     HIP_TRY(c, hipGetLastError());
     return LSQR_OK;
 }
@@ -1074,6 +1265,7 @@ lsqr_status lsqr_set_scale(lsqr_ctx *c, const double *d)
     HIP_TRY(c, hipMemcpyAsync(c->d, d, c->P.n * sizeof(double), hipMemcpyHostToDevice, c->st));
     HIP_TRY(c, hipStreamSynchronize(c->st));
     c->fallback_used = 0;
+    c->user_scale = true;
     return LSQR_OK;
 }
 
@@ -1134,16 +1326,24 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
     if (E.R.sigma) fwd += m * 4.0 + m * sx;
     out->fwd_bytes = fwd;
     out->row_format = E.R.slot ? 4 : E.R.rmask ? 3 : E.R.run_ptr ? 2 : 1;
-    out->col_format = E.C.mmask ? 3 : E.C.nrp ? (E.C.pairs ? 4 : 2) : 1;
-    if (E.C.mmask) {
+    out->col_format = E.C.sl_ptr ? 5 : E.C.mmask ? 3 : E.C.nrp ? (E.C.pairs ? 4 : 2) : 1;
+    if (E.C.sl_ptr) {
+        // values and one row index per run (padding excluded), per slice its
+        // offset and descriptor, per node its slice range and order entry
+        const double nn = n / (double)c->P.nz;
+        out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->nnruns * 4.0 +
+                         (double)c->nslices * 10.0 + (nn + 1) * 8.0 + nn * 4.0 + mb * sx +
+                         n * (8.0 + 2.0 * sx);
+    } else if (E.C.mmask) {
         const double nn = n / (double)c->P.nz, nzd = (double)c->P.nz;
         out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->mrows_n * 4.0 +
                          (double)c->mchunks * nzd * 8.0 + nn * 4.0 * nzd * 8.0 +
                          2.0 * (nn + 1) * 8.0 + nn * 4.0 + mb * sx + n * (8.0 + 2.0 * sx);
     } else if (E.C.nrp) {
+        // the method's values only: the zeros a layout pads runs with are
+        // format overhead, not algorithmic bytes (they show in the counters)
         const double nn = n / (double)c->P.nz;
-        const double stored = E.C.pairs == 4 ? (double)c->npad4 : E.C.pairs ? (double)c->npad : nnz;
-        out->adj_bytes = stored * (double)vt_size(E.C.vt) + (double)c->nnruns * 6.0 +
+        out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->nnruns * 6.0 +
                          (nn + 1) * 8.0 + (4 * nn + 1) * 8.0 + nn * 4.0 + mb * sx +
                          n * (8.0 + 2.0 * sx);
     } else {

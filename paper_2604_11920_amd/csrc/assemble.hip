@@ -102,14 +102,23 @@ lsqr_status ray_rows(const lsqr_rays *R, std::vector<int64_t> *rp, std::vector<i
     return LSQR_OK;
 }
 
+// A temporary device copy of a host array, from the caller's allocator.
+struct Staged {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
 template <class T>
-hipError_t upload(T **d, const T *h, int64_t count, hipStream_t st)
+hipError_t upload(lsqr::Allocator &al, std::vector<Staged> &held, T **d, const T *h, int64_t count,
+                  hipStream_t st)
 {
     *d = nullptr;
     if (count <= 0) return hipSuccess;
-    hipError_t e = hipMalloc((void **)d, (size_t)count * sizeof(T));
-    if (e != hipSuccess) return e;
-    return hipMemcpyAsync(*d, h, (size_t)count * sizeof(T), hipMemcpyHostToDevice, st);
+    const size_t bytes = (size_t)count * sizeof(T);
+    *d = (T *)al.get(bytes);
+    if (!*d) return hipErrorOutOfMemory;
+    held.push_back({(void *)*d, bytes});
+    return hipMemcpyAsync(*d, h, bytes, hipMemcpyHostToDevice, st);
 }
 
 }  // namespace
@@ -122,7 +131,8 @@ lsqr_status lsqr_rays_size(const lsqr_rays *rays, int64_t *m, int64_t *nnz)
     return ray_rows(rays, nullptr, nullptr, nullptr, m, nnz);
 }
 
-lsqr_status lsqr_assemble_rays(const lsqr_rays *rays, void *stream, int64_t *row_ptr,
+lsqr_status lsqr_assemble_rays(const lsqr_rays *rays, void *stream, lsqr_alloc_fn alloc,
+                               lsqr_free_fn dealloc, void *alloc_user, int64_t *row_ptr,
                                int32_t *col_idx, double *val)
 {
     std::vector<int64_t> rp;
@@ -141,17 +151,22 @@ lsqr_status lsqr_assemble_rays(const lsqr_rays *rays, void *stream, int64_t *row
         int64_t *d_np = nullptr, *d_wp = nullptr;
         double *d_len = nullptr, *d_c = nullptr, *d_w = nullptr;
         const int64_t nn = R.node_ptr[R.npairs];
+        lsqr::Allocator al;
+        al.alloc = alloc;
+        al.dealloc = dealloc;
+        al.user = alloc_user;
+        std::vector<Staged> held;
         hipError_t u = hipSuccess;
-        if (u == hipSuccess) u = upload(&d_rpair, rpair.data(), m, st);
-        if (u == hipSuccess) u = upload(&d_rper, rper.data(), m, st);
-        if (u == hipSuccess) u = upload(&d_np, R.node_ptr, R.npairs + 1, st);
-        if (u == hipSuccess) u = upload(&d_k, R.node_k, nn, st);
-        if (u == hipSuccess) u = upload(&d_len, R.node_len, nn, st);
-        if (u == hipSuccess) u = upload(&d_c, R.cvel, (int64_t)R.nper, st);
-        if (u == hipSuccess) u = upload(&d_j0, R.j0, (int64_t)R.nper, st);
-        if (u == hipSuccess) u = upload(&d_nj, R.nj, (int64_t)R.nper, st);
-        if (u == hipSuccess) u = upload(&d_wp, R.w_ptr, (int64_t)R.nper + 1, st);
-        if (u == hipSuccess) u = upload(&d_w, R.w, R.w_ptr[R.nper], st);
+        if (u == hipSuccess) u = upload(al, held, &d_rpair, rpair.data(), m, st);
+        if (u == hipSuccess) u = upload(al, held, &d_rper, rper.data(), m, st);
+        if (u == hipSuccess) u = upload(al, held, &d_np, R.node_ptr, R.npairs + 1, st);
+        if (u == hipSuccess) u = upload(al, held, &d_k, R.node_k, nn, st);
+        if (u == hipSuccess) u = upload(al, held, &d_len, R.node_len, nn, st);
+        if (u == hipSuccess) u = upload(al, held, &d_c, R.cvel, (int64_t)R.nper, st);
+        if (u == hipSuccess) u = upload(al, held, &d_j0, R.j0, (int64_t)R.nper, st);
+        if (u == hipSuccess) u = upload(al, held, &d_nj, R.nj, (int64_t)R.nper, st);
+        if (u == hipSuccess) u = upload(al, held, &d_wp, R.w_ptr, (int64_t)R.nper + 1, st);
+        if (u == hipSuccess) u = upload(al, held, &d_w, R.w, R.w_ptr[R.nper], st);
         if (u == hipSuccess) {
             const int64_t blocks = std::min<int64_t>((m + 3) / 4, 4096);
             hipLaunchKernelGGL(k_assemble, dim3((unsigned)std::max<int64_t>(blocks, 1)),
@@ -161,9 +176,7 @@ lsqr_status lsqr_assemble_rays(const lsqr_rays *rays, void *stream, int64_t *row
         }
         hipError_t w = hipStreamSynchronize(st);
         if (u == hipSuccess) u = w;
-        for (void *p : {(void *)d_rpair, (void *)d_rper, (void *)d_np, (void *)d_k, (void *)d_len,
-                        (void *)d_c, (void *)d_j0, (void *)d_nj, (void *)d_wp, (void *)d_w})
-            if (p) (void)hipFree(p);
+        for (const Staged &h : held) al.put(h.p, h.bytes);
         e = u;
     } else if (e == hipSuccess) {
         e = hipStreamSynchronize(st);

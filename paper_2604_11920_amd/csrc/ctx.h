@@ -64,7 +64,10 @@ struct lsqr_ctx {
     int method = 0;                 // 0 LSQR, 1 LSMR
     int refine_sweeps = 5;
     double refine_inner_tol = 1e-3;
-    int fallback_used = 0;
+    int fallback_used = 0;          // set at creation when user scales were rejected
+    int fallback_iters = 0;         // opts.fallback_iters
+    double *d_user = nullptr;       // the accepted user scale (restored after a fallback)
+    bool user_scale = false;        // D is a caller's scale (create USER or lsqr_set_scale)
     std::vector<std::pair<void *, size_t>> owned;
     // FP64 operator: CSR, depth runs, CSC, column scale
     int64_t *rp = nullptr; int32_t *ci = nullptr; double *va = nullptr;
@@ -81,6 +84,10 @@ struct lsqr_ctx {
     // depth-pair layout of the node-run values (k_adj_npair)
     int64_t *nvqp = nullptr; uint32_t *ndstp = nullptr; int64_t npad = 0;
     double *nvalp = nullptr; float *nvalp32 = nullptr; uint16_t *nvalpq = nullptr;
+    // run slices of the node runs (k_adj_slices), values of the solver's type
+    int64_t *sl_ptr = nullptr, *sl_off = nullptr; uint16_t *sl_desc = nullptr;
+    uint32_t *sl_row = nullptr; uint64_t *sl_dst = nullptr; void *sl_val = nullptr;
+    int64_t nslices = 0, sl_total = 0; int sl_vt = -1;
     // the 16-bit codes in the four-depth layout (mixed forms)
     int64_t *nvqp4 = nullptr; uint32_t *ndstp4 = nullptr; int64_t npad4 = 0;
     // row groups with local columns (forward product over va)

@@ -140,7 +140,23 @@ struct ColFmt {
     const uint64_t *mmask = nullptr;   // [chunks nz]
     const int64_t *mqoff = nullptr;    // [nnodes 4 nz]
     int nzt = 32;                      // compile-time depth bound of the kernel (>= nz)
+    // Run slices (used when sl_ptr is set; val holds the slice layout, see
+    // slice_layout_host): slices sl_ptr[k] .. sl_ptr[k+1]-1 of node k, slice
+    // s = 64 runs of one first depth, its values from sl_off[s] (W depths of
+    // the 64 lanes side by side per step), sl_desc[s] = (iz0 << 8) | padded
+    // length, sl_row[64 s + lane] = data row of the lane's run (norder as
+    // for node runs).
+    const int64_t *sl_ptr = nullptr;   // [nnodes+1]
+    const int64_t *sl_off = nullptr;   // [nslices]
+    const uint16_t *sl_desc = nullptr; // [nslices]
+    const uint32_t *sl_row = nullptr;  // [64 nslices]
 };
+
+// Depths per lane load of the run-slice layout for a stored value type: one
+// 8-byte value, two 4-byte values, two 16-bit codes.
+inline int slice_width(int vt) { return vt == VT_F64 ? 1 : 2; }
+// Compile-time bound on the depths of the run-slice kernel (>= nz <= 64).
+inline int slice_nzm(int nz) { return nz <= 8 ? 8 : nz <= 16 ? 16 : nz <= 24 ? 24 : nz <= 32 ? 32 : 64; }
 
 // Type-dispatched launchers (kernels_f64.hip, kernels_f32.hip).
 void launch_init(hipStream_t st, const Problem &P, int grid, int vec, const double *rhs, int full,
@@ -186,6 +202,9 @@ void launch_check_vec(hipStream_t st, int64_t n, const double *x, int positive, 
 // out[dst[r] + e] = in[src[r] + e] for e < len(desc[r]) (elements of elem_bytes = 2, 4 or 8)
 void launch_gather_runs(hipStream_t st, int64_t nr, const uint32_t *src, const uint32_t *dst,
                         const uint16_t *desc, const void *in, void *out, int elem_bytes);
+// out[dst[r] + (e / W) 64 W + e mod W] = in[src[r] + e] for e < len(desc[r]) (run slices)
+void launch_scatter_slices(hipStream_t st, int64_t nr, const uint32_t *src, const uint64_t *dst,
+                           const uint16_t *desc, int W, const void *in, void *out, int elem_bytes);
 void launch_convert_f32(hipStream_t st, int64_t nnz, const double *src, float *dst);
 void launch_row_scales(hipStream_t st, int64_t m, const int64_t *rp, const double *val, int vt,
                        float *sigma);

@@ -275,6 +275,7 @@ __global__ void k_adam(float *params, float *m, float *v, const float *g, float 
 
 struct lsqr_trainer {
     hipStream_t st = nullptr;
+    lsqr::Allocator al;
     int max_batch = 0;
     int t = 0;
     float *params = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
@@ -285,12 +286,26 @@ struct lsqr_trainer {
     std::string err;
 };
 
+// Device buffers of a trainer and their sizes (bytes), in one place so that
+// creation and release agree.
+static void trainer_buffers(lsqr_trainer *t, void **(&ptrs)[11], size_t (&bytes)[11])
+{
+    const size_t B = (size_t)t->max_batch;
+    void **p[11] = {(void **)&t->params, (void **)&t->m, (void **)&t->v, (void **)&t->grad,
+                    (void **)&t->h1, (void **)&t->h2, (void **)&t->d1, (void **)&t->d2,
+                    (void **)&t->dz, (void **)&t->part, (void **)&t->sum};
+    const size_t b[11] = {NP * 4, NP * 4, NP * 4, NP * 4, B * H * 4, B * H * 4, B * H * 4,
+                          B * H * 4, B * 4, 1024 * 8, 8};
+    for (int i = 0; i < 11; ++i) { ptrs[i] = p[i]; bytes[i] = b[i]; }
+}
+
 static void trainer_free(lsqr_trainer *t)
 {
-    for (void *p : {(void *)t->params, (void *)t->m, (void *)t->v, (void *)t->grad, (void *)t->h1,
-                    (void *)t->h2, (void *)t->d1, (void *)t->d2, (void *)t->dz, (void *)t->part,
-                    (void *)t->sum})
-        if (p) (void)hipFree(p);
+    void **ptrs[11];
+    size_t bytes[11];
+    trainer_buffers(t, ptrs, bytes);
+    for (int i = 0; i < 11; ++i)
+        if (*ptrs[i]) t->al.put(*ptrs[i], bytes[i]);
     if (t->hsum) (void)hipHostFree(t->hsum);
     delete t;
 }
@@ -316,23 +331,11 @@ lsqr_status lsqr_column_features(lsqr_ctx *c, float *feat)
     return LSQR_OK;
 }
 
-lsqr_status lsqr_mlp_scale(lsqr_ctx *c, const float *params, const float *mean, const float *std,
-                           unsigned centre, const float *feat, double *d)
+// Inference with the Jacobi scale and the feature means in djac [n + NF].
+static lsqr_status mlp_scale_into(lsqr_ctx *c, const float *params, const Norm &nrm,
+                                  unsigned centre, const float *feat, double *d, double *djac)
 {
-    if (!c || !params || !mean || !std || !feat || !d)
-        return fail(c, LSQR_E_INVALID_ARG, "arguments must not be NULL");
-    if (centre >> NF) return fail(c, LSQR_E_INVALID_ARG, "centre flags only features 0..5");
-    Norm nrm;
-    for (int f = 0; f < NF; ++f) {
-        if (!(std[f] > 0.0f) || !isfinite(std[f]) || !isfinite(mean[f]))
-            return fail(c, LSQR_E_INVALID_ARG, "standardisation must be finite with std > 0");
-        nrm.mean[f] = mean[f];
-        nrm.inv_std[f] = 1.0f / std[f];
-    }
-    DeviceGuard dg(c->device);
     const Problem &P = c->P;
-    double *djac = ctx_alloc<double>(c, P.n + NF);
-    if (!djac) return fail(c, LSQR_E_OOM, "device allocation failed");
     double *sysmean = djac + P.n;
     launch_jacobi(c->st, P, c->C64, djac);
     hipLaunchKernelGGL(k_feature_means, dim3(1), dim3(256), 0, c->st, (int)P.n, feat, centre,
@@ -342,13 +345,44 @@ lsqr_status lsqr_mlp_scale(lsqr_ctx *c, const float *params, const float *mean, 
                        nrm, centre, (const double *)sysmean, feat, (const double *)djac, d);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->st));
-    ctx_release(c, djac);
     return LSQR_OK;
+}
+
+static lsqr_status mlp_scale_args(lsqr_ctx *c, const float *params, const float *mean,
+                                  const float *std, unsigned centre, const float *feat, double *d,
+                                  Norm &nrm)
+{
+    if (!c || !params || !mean || !std || !feat || !d)
+        return fail(c, LSQR_E_INVALID_ARG, "arguments must not be NULL");
+    if (centre >> NF) return fail(c, LSQR_E_INVALID_ARG, "centre flags only features 0..5");
+    for (int f = 0; f < NF; ++f) {
+        if (!(std[f] > 0.0f) || !isfinite(std[f]) || !isfinite(mean[f]))
+            return fail(c, LSQR_E_INVALID_ARG, "standardisation must be finite with std > 0");
+        nrm.mean[f] = mean[f];
+        nrm.inv_std[f] = 1.0f / std[f];
+    }
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_mlp_scale(lsqr_ctx *c, const float *params, const float *mean, const float *std,
+                           unsigned centre, const float *feat, double *d)
+{
+    Norm nrm;
+    lsqr_status s = mlp_scale_args(c, params, mean, std, centre, feat, d, nrm);
+    if (s != LSQR_OK) return s;
+    DeviceGuard dg(c->device);
+    double *djac = ctx_alloc<double>(c, c->P.n + NF);
+    if (!djac) return fail(c, LSQR_E_OOM, "device allocation failed");
+    s = mlp_scale_into(c, params, nrm, centre, feat, d, djac);
+    ctx_release(c, djac);
+    return s;
 }
 
 static thread_local std::string t_err;
 
-lsqr_status lsqr_trainer_create(int max_batch, const float *params, void *stream, lsqr_trainer **out)
+lsqr_status lsqr_trainer_create(int max_batch, const float *params, void *stream,
+                                lsqr_alloc_fn alloc, lsqr_free_fn dealloc, void *alloc_user,
+                                lsqr_trainer **out)
 {
     if (!out || !params || max_batch < 1) {
         t_err = "invalid arguments";
@@ -357,16 +391,17 @@ lsqr_status lsqr_trainer_create(int max_batch, const float *params, void *stream
     *out = nullptr;
     lsqr_trainer *t = new lsqr_trainer();
     t->st = (hipStream_t)stream;
+    t->al.alloc = alloc;
+    t->al.dealloc = dealloc;
+    t->al.user = alloc_user;
     t->max_batch = max_batch;
     t->grid = std::min(1024, (max_batch + 255) / 256);
-    const size_t B = (size_t)max_batch;
-    bool ok = hipMalloc(&t->params, NP * 4) == hipSuccess && hipMalloc(&t->m, NP * 4) == hipSuccess &&
-              hipMalloc(&t->v, NP * 4) == hipSuccess && hipMalloc(&t->grad, NP * 4) == hipSuccess &&
-              hipMalloc(&t->h1, B * H * 4) == hipSuccess && hipMalloc(&t->h2, B * H * 4) == hipSuccess &&
-              hipMalloc(&t->d1, B * H * 4) == hipSuccess && hipMalloc(&t->d2, B * H * 4) == hipSuccess &&
-              hipMalloc(&t->dz, B * 4) == hipSuccess && hipMalloc(&t->part, 1024 * 8) == hipSuccess &&
-              hipMalloc(&t->sum, 8) == hipSuccess &&
-              hipHostMalloc((void **)&t->hsum, 8, hipHostMallocDefault) == hipSuccess;
+    void **ptrs[11];
+    size_t bytes[11];
+    trainer_buffers(t, ptrs, bytes);
+    bool ok = true;
+    for (int i = 0; i < 11 && ok; ++i) ok = (*ptrs[i] = t->al.get(bytes[i])) != nullptr;
+    ok = ok && hipHostMalloc((void **)&t->hsum, 8, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         trainer_free(t);
         t_err = "device allocation failed";

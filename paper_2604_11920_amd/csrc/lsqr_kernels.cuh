@@ -1025,6 +1025,11 @@ struct AdjArgs {
     const int64_t *mcptr;
     const uint64_t *mmask;
     const int64_t *mqoff;
+    // run slices (k_adj_slices): see ColFmt
+    const int64_t *sl_ptr;
+    const int64_t *sl_off;
+    const uint16_t *sl_desc;
+    const uint32_t *sl_row;
 };
 
 // beta_{k+1} from the forward partials (FP64, fixed order); false when the
@@ -1416,6 +1421,128 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
 }
 
+// Transposed product over run slices (see slice_layout_host).  A node's runs
+// are grouped by first depth and cut into slices of 64 runs, one run per
+// lane; a slice stores, for each step of W depths, the 64 lanes' W values
+// side by side, so every lane of a wave loads W values of its own run with
+// one contiguous wave-wide load and no lane idles on depths its run lacks
+// (slices hold runs of equal first depth and, after sorting by length,
+// nearly equal length; the shorter ones are padded with zeros).  A lane
+// gathers t for its run once and accumulates its values into per-depth
+// registers relative to the slice's first depth.  When the first depth
+// changes, and at the end of the node, each depth's register is summed over
+// the wave in a fixed butterfly and added to the column that depth maps to.
+// One workgroup per node (nodes by decreasing work, boustrophedon over the
+// workgroups); wave w takes slices w, w + 4, ... of the node; per column
+// the sum runs over the wave's slices in order, then the lanes' fixed tree,
+// then the waves in order: deterministic, no atomics.  NZM >= nz bounds the
+// depth registers at compile time.
+template <class A, class M, int W>
+__device__ __forceinline__ void ld_step(const M *p, A (&x)[W])
+{
+    if constexpr (W == 1) x[0] = ld_nt<A>(p);
+    else ld_word<A, M, W>(p, x);
+}
+
+template <class A, class M, int W, int NS, int NZM>
+__device__ __forceinline__ void slice_steps(const M *p, A t, A (&acc)[NZM])
+{
+#pragma clang fp contract(off)
+    A v[NS][W];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) ld_step<A, M, W>(p + k * 64 * W, v[k]);
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int h = 0; h < W; ++h) acc[k * W + h] = fma(v[k][h], t, acc[k * W + h]);
+}
+
+// the steps of one slice, ns = its padded length / W (uniform over the wave)
+template <class A, class M, int W, int NZM, int NS = 1>
+__device__ __forceinline__ void slice_dispatch(int ns, const M *p, A t, A (&acc)[NZM])
+{
+    if constexpr (NS * W <= NZM) {
+        if (ns == NS) {
+            slice_steps<A, M, W, NS, NZM>(p, t, acc);
+            return;
+        }
+        slice_dispatch<A, M, W, NZM, NS + 1>(ns, p, t, acc);
+    }
+}
+
+// adds the wave sums of acc[0 .. lmax) to the columns cls .. cls + lmax - 1
+// (lane iz holds column iz's running sum in col) and clears acc
+template <class A, int NZM>
+__device__ __forceinline__ void slice_flush(A (&acc)[NZM], int cls, int lmax, int lane, A &col)
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int e = 0; e < NZM; ++e) {
+        if (e < lmax) {
+            const A r = group_sum<64>(acc[e]);
+            col = lane == cls + e ? col + r : col;
+        }
+        acc[e] = 0;
+    }
+}
+
+template <class M, class V, int W, int NZM>
+__global__ __launch_bounds__(kBlock) void k_adj_slices(AdjArgs a)
+{
+#pragma clang fp contract(off)
+    using A = typename AccOf<V>::type;
+    __shared__ double lds[4];
+    __shared__ A wsum[kBlock / 64][64];
+    double beta;
+    if (!adj_prologue(a, beta, lds)) return;
+    const M *sv = (const M *)a.cv;
+    const V *Tg = (const V *)a.Tg;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int G = gridDim.x, slot = blockIdx.x, nnodes = a.n / a.nz;
+    double sq = 0.0;
+    for (int s = 0; s * G < nnodes; ++s) {
+        const int idx = s * G + ((s & 1) ? G - 1 - slot : slot);
+        if (idx >= nnodes) continue;         // uniform over the workgroup
+        const int node = a.norder[idx];
+        const int64_t s1 = a.sl_ptr[node + 1];
+        int64_t sl = a.sl_ptr[node] + wid;
+        A acc[NZM];
+#pragma unroll
+        for (int e = 0; e < NZM; ++e) acc[e] = 0;
+        A col = 0;
+        int cls = -1, lmax = 0;
+        uint32_t row = 0;
+        if (sl < s1) row = __builtin_nontemporal_load(a.sl_row + sl * 64 + lane);
+        for (; sl < s1; sl += 4) {
+            const uint32_t d = a.sl_desc[sl];
+            const int iz0 = (int)(d >> 8), len = (int)(d & 255u);
+            if (iz0 != cls) {
+                if (cls >= 0) slice_flush<A, NZM>(acc, cls, lmax, lane, col);
+                cls = iz0;
+                lmax = 0;
+            }
+            lmax = len > lmax ? len : lmax;
+            const A t = (A)Tg[row];
+            const M *p = sv + a.sl_off[sl] + lane * W;
+            // the next slice's rows, in flight while this slice's values load
+            uint32_t row_n = 0;
+            if (sl + 4 < s1) row_n = __builtin_nontemporal_load(a.sl_row + (sl + 4) * 64 + lane);
+            slice_dispatch<A, M, W, NZM>(len / W, p, t, acc);
+            row = row_n;
+        }
+        if (cls >= 0) slice_flush<A, NZM>(acc, cls, lmax, lane, col);
+        wsum[wid][lane] = col;
+        __syncthreads();
+        if (wid == 0 && lane < a.nz) {
+            const A g = ((wsum[0][lane] + wsum[1][lane]) + wsum[2][lane]) + wsum[3][lane];
+            sq += adj_col_out<V>(a, node * a.nz + lane, g, beta);
+        }
+        __syncthreads();
+    }
+    const double tot = block_sum(sq, lds);
+    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
+}
+
 // Transposed product over node masks: the CSC values, with the row indices
 // replaced by per-node row lists and bit masks.  Node k's rows (the data rows
 // reaching any of its nz columns, ascending) are cut into chunks of 64; lane l
@@ -1776,6 +1903,17 @@ static void adj_launch_m(hipStream_t st, int grid, const ColFmt &C, const AdjArg
         }
         return;
     }
+    if (C.sl_ptr) {
+        constexpr int W = sizeof(M) == 8 ? 1 : 2;
+        switch (slice_nzm(a.nz)) {
+        case 8: hipLaunchKernelGGL((k_adj_slices<M, V, W, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 16: hipLaunchKernelGGL((k_adj_slices<M, V, W, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 24: hipLaunchKernelGGL((k_adj_slices<M, V, W, 24>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 32: hipLaunchKernelGGL((k_adj_slices<M, V, W, 32>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_adj_slices<M, V, W, 64>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        }
+        return;
+    }
     if (C.nrp) {
         if (C.pairs) {
             if constexpr (sizeof(M) == 2) {
@@ -1880,6 +2018,26 @@ int adj_nruns_blocks_per_cu(const ColFmt &C)
 {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
+    if (C.sl_ptr) {
+#define LSQR_SL_OCC(M_, NZM_) hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_slices<M_, V, (sizeof(M_) == 8 ? 1 : 2), NZM_>, kBlock, 0)
+#define LSQR_SL_OCCZ(M_) (slice_nzm(C.nzt) == 8 ? LSQR_SL_OCC(M_, 8) : slice_nzm(C.nzt) == 16 ? LSQR_SL_OCC(M_, 16) \
+                          : slice_nzm(C.nzt) == 24 ? LSQR_SL_OCC(M_, 24) : slice_nzm(C.nzt) == 32 ? LSQR_SL_OCC(M_, 32) \
+                          : LSQR_SL_OCC(M_, 64))
+        switch (C.vt) {
+        case VT_F64:
+            if constexpr (Wide<V>::value) e = LSQR_SL_OCCZ(double);
+            break;
+        case VT_F32:
+            if constexpr (!Wide<V>::value) e = LSQR_SL_OCCZ(float);
+            break;
+        case VT_BF16: e = LSQR_SL_OCCZ(bf16_t); break;
+        case VT_F16: e = LSQR_SL_OCCZ(fp16_t); break;
+        default: break;
+        }
+#undef LSQR_SL_OCCZ
+#undef LSQR_SL_OCC
+        return e == hipSuccess ? nb : 0;
+    }
     if (!C.nrp || C.mmask) return 0;
 #define LSQR_ADJ_OCC(M_) (C.pairs == 4 && sizeof(M_) == 2                                                              \
                               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_npair<M_, V, (sizeof(M_) == 2 ? 4 : 2)>, kBlock, 0) \
@@ -1909,7 +2067,7 @@ hipError_t adj_launch(hipStream_t st, const Problem &P, int grid, const ColFmt &
     AdjArgs a{C.cp, C.ri, C.val, P.m, (int)P.n, P.nx, P.ny, P.nz, P.w, P.damp, d, T, Tg, v, q,
               part_out, part_t, np_t, S, ctl, parity, mode, data_only, C.xcd_bands,
               C.nrp, C.nvq, C.nrow, C.ndesc, C.norder, {}, C.mrptr, C.mrows, C.mcptr, C.mmask,
-              C.mqoff};
+              C.mqoff, C.sl_ptr, C.sl_off, C.sl_desc, C.sl_row};
     for (int x = 0; x < 9; ++x) a.nseg[x] = C.nseg[x];
     switch (C.vt) {
     case VT_F64:

@@ -490,4 +490,104 @@ inline bool pair_layout_host(const NodeRuns &R, int64_t nn, std::vector<uint32_t
     return off + 2 < ((int64_t)1 << 32);
 }
 
+// Run-slice layout of the node runs (k_adj_slices).  Per node, its runs are
+// ordered by first depth, then by decreasing length, then by row (a stable
+// order), and cut into slices of up to 64 runs that share a first depth.  A
+// slice's padded length L is its longest run rounded up to a multiple of W;
+// it occupies L * 64 values from off[s]: step k (depths kW .. kW+W-1 of every
+// run) holds lane j's W values at off[s] + k 64 W + j W.  Lanes without a
+// run (the last slice of a first depth) and depths past a run's end hold
+// zeros; their row is 0.  dst[r] = off[s] + j W for run r in lane j of
+// slice s, so value e of run r sits at dst[r] + (e / W) 64 W + e mod W.
+// total = padded values.  Rows must fit 32 bits (node runs already do).
+struct RunSlices {
+    std::vector<int64_t> sptr;      // [nn+1]
+    std::vector<int64_t> off;       // [nslices]
+    std::vector<uint16_t> desc;     // [nslices] (iz0 << 8) | L
+    std::vector<uint32_t> row;      // [64 nslices]
+    std::vector<uint64_t> dst;      // [nruns]
+    int64_t total = 0;
+};
+
+inline void slice_layout_host(const NodeRuns &R, int64_t nn, int W, RunSlices &S)
+{
+    const int64_t nr = R.nrp[(size_t)nn];
+    // slice counts per node (threads over nodes), then offsets, then fill
+    std::vector<int64_t> cnt((size_t)nn, 0), vals((size_t)nn, 0);
+    std::vector<std::vector<uint32_t>> ord((size_t)nn);
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (nr < (1 << 20)) nt = 1;
+    auto key_less = [&](uint32_t x, uint32_t y) {
+        const int ix = R.desc[x] >> 8, iy = R.desc[y] >> 8;
+        if (ix != iy) return ix < iy;
+        const int lx = R.desc[x] & 255, ly = R.desc[y] & 255;
+        if (lx != ly) return lx > ly;
+        return x < y;
+    };
+    {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t]() {
+                for (int64_t k = nn * t / nt; k < nn * (t + 1) / nt; ++k) {
+                    const int64_t r0 = R.nrp[(size_t)k], r1 = R.nrp[(size_t)k + 1];
+                    auto &o = ord[(size_t)k];
+                    o.resize((size_t)(r1 - r0));
+                    for (int64_t r = r0; r < r1; ++r) o[(size_t)(r - r0)] = (uint32_t)r;
+                    std::sort(o.begin(), o.end(), key_less);
+                    int64_t ns = 0, nv = 0;
+                    for (size_t i = 0; i < o.size();) {
+                        const int iz0 = R.desc[o[i]] >> 8;
+                        const int L = (((R.desc[o[i]] & 255) + W - 1) / W) * W;   // longest first
+                        size_t j = i;
+                        while (j < o.size() && j - i < 64 && (R.desc[o[j]] >> 8) == iz0) ++j;
+                        ++ns;
+                        nv += (int64_t)L * 64;
+                        i = j;
+                    }
+                    cnt[(size_t)k] = ns;
+                    vals[(size_t)k] = nv;
+                }
+            });
+        for (auto &x : th) x.join();
+    }
+    S.sptr.assign((size_t)nn + 1, 0);
+    std::vector<int64_t> voff((size_t)nn + 1, 0);
+    for (int64_t k = 0; k < nn; ++k) {
+        S.sptr[(size_t)k + 1] = S.sptr[(size_t)k] + cnt[(size_t)k];
+        voff[(size_t)k + 1] = voff[(size_t)k] + vals[(size_t)k];
+    }
+    const int64_t nsl = S.sptr[(size_t)nn];
+    S.total = voff[(size_t)nn];
+    S.off.resize((size_t)nsl);
+    S.desc.resize((size_t)nsl);
+    S.row.assign((size_t)nsl * 64, 0u);
+    S.dst.resize((size_t)nr);
+    {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t]() {
+                for (int64_t k = nn * t / nt; k < nn * (t + 1) / nt; ++k) {
+                    const auto &o = ord[(size_t)k];
+                    int64_t sl = S.sptr[(size_t)k], off = voff[(size_t)k];
+                    for (size_t i = 0; i < o.size();) {
+                        const int iz0 = R.desc[o[i]] >> 8;
+                        const int L = (((R.desc[o[i]] & 255) + W - 1) / W) * W;
+                        S.off[(size_t)sl] = off;
+                        S.desc[(size_t)sl] = (uint16_t)((iz0 << 8) | L);
+                        size_t j = i;
+                        for (; j < o.size() && j - i < 64 && (R.desc[o[j]] >> 8) == iz0; ++j) {
+                            const int lane = (int)(j - i);
+                            S.row[(size_t)(sl * 64 + lane)] = R.row[o[j]];
+                            S.dst[o[j]] = (uint64_t)(off + (int64_t)lane * W);
+                        }
+                        off += (int64_t)L * 64;
+                        ++sl;
+                        i = j;
+                    }
+                }
+            });
+        for (auto &x : th) x.join();
+    }
+}
+
 }  // namespace lsqr

@@ -19,8 +19,9 @@ round, minimising LSQR iterations to the tolerance, capped at twice Jacobi's
 count.  The target of column j is l_j at the best theta.
 
 Fallback and judge: a learned scale that is not finite and positive is
-replaced by Jacobi inside lsqr_create; a learned solve that has not reached
-the tolerance within twice the Jacobi iteration count is redone with Jacobi.
+replaced by Jacobi inside the library; a learned solve that has not reached
+the tolerance within twice the Jacobi iteration count continues with Jacobi
+(the library's fallback budget, opts.fallback_iters).
 """
 from __future__ import annotations
 
@@ -187,28 +188,25 @@ def learned_scale(system, model, solver=None):
 
 
 def solve_learned(system, model, tol, k_jacobi=None, cap=20000, precision="fp64"):
-    """Solve with the learned scale; fall back to Jacobi when the learned solve
-    has not converged within twice the Jacobi count (or within cap).  One
+    """Solve with the learned scale.  The Jacobi fallback runs inside the
+    library (opts.fallback_iters = twice the Jacobi count when k_jacobi is
+    given): a scale that is not finite and positive is rejected when it is
+    set, and a learned solve that has not reached the tolerance within the
+    budget continues from its current iterate with the Jacobi scale.  One
     context: features and inference on it, then the scale is swapped in."""
     t0 = time.perf_counter()
-    with Solver.from_system(system, precond="jacobi", precision=precision, check_every=16) as sol:
-        djac = sol.scale()
+    fb = 2 * int(k_jacobi) if k_jacobi else 0
+    with Solver.from_system(system, precond="jacobi", precision=precision, check_every=16,
+                            fallback_iters=fb) as sol:
         d = learned_scale(system, model, solver=sol)
         try:
             sol.set_scale(d)             # rejected unless finite and > 0
             rejected = False
         except LsqrError:
             rejected = True
-        limit = 2 * k_jacobi if k_jacobi else cap
-        dm, _, info = sol.solve(system.dt, int(limit if not rejected else cap), tol=tol,
-                                history=False)
-        info["fallback_used"] = int(rejected)
-        total = info["iters"]
-        if not rejected and info["istop"] != 1 and k_jacobi is not None:
-            sol.set_scale(djac)
-            dm, _, info = sol.solve(system.dt, cap, tol=tol, history=False)
+        dm, _, info = sol.solve(system.dt, int(cap), tol=tol, history=False)
+        if rejected:
             info["fallback_used"] = 1
-            total += info["iters"]
-    info["iters_total"] = total          # including a failed learned attempt
+    info["iters_total"] = info["iters"]  # including a failed learned attempt
     info["seconds"] = time.perf_counter() - t0
     return dm, info

@@ -49,13 +49,13 @@ class Opts(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("lanes_per_row", ctypes.c_int),
                 ("lanes_per_col", ctypes.c_int), ("row_format", ctypes.c_int),
                 ("col_format", ctypes.c_int), ("refine_inner_tol", ctypes.c_double),
-                ("method", ctypes.c_int)]
+                ("method", ctypes.c_int), ("fallback_iters", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("istop", ctypes.c_int), ("iters", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("fallback_used", ctypes.c_int), ("eta", ctypes.c_double),
-                ("phibar", ctypes.c_double)]
+                ("phibar", ctypes.c_double), ("eta_final_fp64", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -88,7 +88,7 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    path = os.environ.get("LSQR_MI355X_LIB", LIB_PATH)      # an alternative build
+    path = LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_2604_11920_amd.build.build()")
     lib = ctypes.CDLL(path)
@@ -99,6 +99,8 @@ def load():
         "lsqr_solve_x0": (I, [P, P, P, I, I, D, P, P, ctypes.POINTER(Info)]),
         "lsqr_apply": (I, [P, P, P]),
         "lsqr_apply_t": (I, [P, P, P]),
+        "lsqr_apply_stored": (I, [P, P, P]),
+        "lsqr_apply_t_stored": (I, [P, P, P, P]),
         "lsqr_get_scale": (I, [P, P]),
         "lsqr_set_scale": (I, [P, P]),
         "lsqr_get_transpose": (I, [P, P, P, P]),
@@ -112,14 +114,14 @@ def load():
         "lsqr_autotune_batched": (I, [P, I, I, ctypes.POINTER(BatchCfg)]),
         "lsqr_column_features": (I, [P, P]),
         "lsqr_mlp_scale": (I, [P, P, P, P, ctypes.c_uint, P, P]),
-        "lsqr_trainer_create": (I, [I, P, P, ctypes.POINTER(P)]),
+        "lsqr_trainer_create": (I, [I, P, P, _ALLOC_FN, _FREE_FN, P, ctypes.POINTER(P)]),
         "lsqr_trainer_grad": (I, [P, I, P, P, P, ctypes.POINTER(D)]),
         "lsqr_trainer_step": (I, [P, I, P, P, ctypes.c_float, ctypes.POINTER(D)]),
         "lsqr_trainer_params": (I, [P, P, P]),
         "lsqr_trainer_destroy": (None, [P]),
         "lsqr_rays_size": (I, [ctypes.POINTER(Rays), ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_int64)]),
-        "lsqr_assemble_rays": (I, [ctypes.POINTER(Rays), P, P, P, P]),
+        "lsqr_assemble_rays": (I, [ctypes.POINTER(Rays), P, _ALLOC_FN, _FREE_FN, P, P, P, P]),
         "lsqr_destroy": (None, [P]),
         "lsqr_status_string": (ctypes.c_char_p, [I]),
         "lsqr_last_error": (ctypes.c_char_p, [P]),
@@ -140,6 +142,28 @@ def header_functions():
     return sorted(set(re.findall(r"\b(lsqr_[a-z_]+)\s*\(", txt)))
 
 
+def torch_allocator(device, stream):
+    """(alloc, dealloc) ctypes callbacks drawing device memory from PyTorch's
+    caching allocator on `stream`; keep both referenced while in use."""
+    import torch
+    blocks = {}
+
+    def _alloc(nbytes, user):
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+        except Exception:
+            return None
+        blocks[p] = nbytes
+        return p
+
+    def _free(p, nbytes, user):
+        if p in blocks:
+            del blocks[p]
+            torch.cuda.caching_allocator_delete(p)
+
+    return _ALLOC_FN(_alloc), _FREE_FN(_free)
+
+
 def _ptr(a):
     if a is None:
         return None
@@ -156,8 +180,8 @@ class Solver:
     """One regularised LSQR system on the GPU (wraps an lsqr_ctx).
 
     row_format: "auto" | "csr" | "runs" | "masks" | "groups" (forward product);
-    col_format: "auto" | "csc" | "runs" | "masks" | "pairs" (transposed
-    product).  The formats are those of opts.row_format / opts.col_format in
+    col_format: "auto" | "csc" | "runs" | "masks" | "pairs" | "slices"
+    (transposed product).  The formats are those of opts.row_format / opts.col_format in
     include/lsqr_mi355x.h; "auto" picks row groups and depth pairs where the
     matrix fits them."""
 
@@ -165,7 +189,7 @@ class Solver:
                  precond="none", col_scale=None, stream=None, timing=False, graph=True,
                  lanes_per_row=0, lanes_per_col=0, check_every=0, refine_sweeps=5,
                  row_format="auto", col_format="auto", xcd_bands=False, refine_inner_tol=0.0,
-                 method="lsqr", torch_alloc=True):
+                 method="lsqr", torch_alloc=True, fallback_iters=0):
         import torch
         lib = load()
         self._torch = torch
@@ -195,6 +219,7 @@ class Solver:
         opts.refine_sweeps = int(refine_sweeps)
         opts.refine_inner_tol = float(refine_inner_tol)
         opts.method = {"lsqr": 0, "lsmr": 1}[method]
+        opts.fallback_iters = int(fallback_iters)
         opts.check_every = int(check_every)
         opts.stream = stream.cuda_stream
         opts.flags = ((FLAG_TIMING if timing else 0) | (0 if graph else FLAG_NO_GRAPH)
@@ -202,26 +227,11 @@ class Solver:
         opts.lanes_per_row = int(lanes_per_row)
         opts.lanes_per_col = int(lanes_per_col)
         opts.row_format = {"auto": 0, "csr": 1, "runs": 2, "masks": 3, "groups": 4}[row_format]
-        opts.col_format = {"auto": 0, "csc": 1, "runs": 2, "masks": 3, "pairs": 4}[col_format]
+        opts.col_format = {"auto": 0, "csc": 1, "runs": 2, "masks": 3, "pairs": 4,
+                           "slices": 5}[col_format]
         self.precision = precision
         if torch_alloc:
-            self._blocks = {}
-            sp = stream
-
-            def _alloc(nbytes, user):
-                try:
-                    p = torch.cuda.caching_allocator_alloc(int(nbytes), self._device, sp)
-                except Exception:
-                    return None
-                self._blocks[p] = nbytes
-                return p
-
-            def _free(p, nbytes, user):
-                if p in self._blocks:
-                    del self._blocks[p]
-                    torch.cuda.caching_allocator_delete(p)
-
-            self._alloc_cb, self._free_cb = _ALLOC_FN(_alloc), _FREE_FN(_free)
+            self._alloc_cb, self._free_cb = torch_allocator(self._device, stream)
             opts.alloc, opts.dealloc = self._alloc_cb, self._free_cb
         ctx = ctypes.c_void_p()
         rc = lib.lsqr_create(ctypes.byref(csr), float(damp), float(smooth), ctypes.byref(opts),
@@ -286,6 +296,24 @@ class Solver:
             x = self._torch.empty(self.n, dtype=self._torch.float64, device=y.device)
         self._check(self._lib.lsqr_apply_t(self._ctx, _ptr(y), _ptr(x)))
         return x
+
+    def apply_stored(self, z, y=None):
+        """y = [Ghat z; w L z; lambda z] with the solver's stored values (no
+        column scale); device tensors of the solver's vector type."""
+        dt = self._torch.float64 if self.precision == "fp64" else self._torch.float32
+        if y is None:
+            y = self._torch.empty(self.m + 2 * self.n, dtype=dt, device=z.device)
+        self._check(self._lib.lsqr_apply_stored(self._ctx, _ptr(z), _ptr(y)))
+        return y
+
+    def apply_t_stored(self, y, tg=None, q=None):
+        """q = Ghat^T (tg or y_G) + w L y_L + lambda y_D with the solver's
+        stored values (no column scale); for the 16-bit forms tg = sigma * y_G."""
+        dt = self._torch.float64 if self.precision == "fp64" else self._torch.float32
+        if q is None:
+            q = self._torch.empty(self.n, dtype=dt, device=y.device)
+        self._check(self._lib.lsqr_apply_t_stored(self._ctx, _ptr(y), _ptr(tg), _ptr(q)))
+        return q
 
     def set_scale(self, d):
         """Replace the column scaling D (host array [n], finite, > 0)."""
@@ -374,7 +402,7 @@ class Solver:
         self._check(self._lib.lsqr_column_features(self._ctx, _ptr(f)))
         return f
 
-    def mlp_scale(self, params, mean, std, feat=None, centre=0):
+    def mlp_scale(self, params, mean, std, feat=None, centre=0, d=None):
         """Learned column scale (device float64 [n]): Jacobi times softplus of the
         BF16 MLP on standardised features.  params: float32 device tensor;
         centre: bit mask of features centred on this system's own means."""
@@ -382,7 +410,8 @@ class Solver:
             feat = self.column_features()
         mean = np.ascontiguousarray(mean, dtype=np.float32)
         std = np.ascontiguousarray(std, dtype=np.float32)
-        d = self._torch.empty(self.n, dtype=self._torch.float64, device="cuda")
+        if d is None:
+            d = self._torch.empty(self.n, dtype=self._torch.float64, device="cuda")
         self._check(self._lib.lsqr_mlp_scale(self._ctx, _ptr(params), _ptr(mean), _ptr(std),
                                              int(centre), _ptr(feat), _ptr(d)))
         return d
@@ -454,9 +483,11 @@ class Trainer:
         self._torch = torch
         p = np.ascontiguousarray(params, dtype=np.float32)
         assert p.size == self.NPARAMS
-        st = (stream or torch.cuda.current_stream()).cuda_stream
+        stream = stream or torch.cuda.current_stream()
+        self._alloc_cb, self._free_cb = torch_allocator(torch.cuda.current_device(), stream)
         h = ctypes.c_void_p()
-        rc = self._lib.lsqr_trainer_create(int(max_batch), _ptr(p), st, ctypes.byref(h))
+        rc = self._lib.lsqr_trainer_create(int(max_batch), _ptr(p), stream.cuda_stream,
+                                           self._alloc_cb, self._free_cb, None, ctypes.byref(h))
         if rc != LSQR_OK:
             raise LsqrError(rc, "trainer creation failed")
         self._h = h
@@ -536,8 +567,10 @@ def assemble_rays(rays, stream=None):
     rp = torch.empty(m + 1, dtype=torch.int64, device=dev)
     col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]
     val = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)[:nnz]
-    s = (stream or torch.cuda.current_stream()).cuda_stream
-    rc = lib.lsqr_assemble_rays(ctypes.byref(st), s, _ptr(rp), _ptr(col), _ptr(val))
+    stream = stream or torch.cuda.current_stream()
+    alloc_cb, free_cb = torch_allocator(dev.index, stream)
+    rc = lib.lsqr_assemble_rays(ctypes.byref(st), stream.cuda_stream, alloc_cb, free_cb, None,
+                                _ptr(rp), _ptr(col), _ptr(val))
     if rc != LSQR_OK:
         raise LsqrError(rc, lib.lsqr_last_error(None).decode())
     return rp, col, val

@@ -62,6 +62,10 @@ def _lib():
         lib.synth_count.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P]
         lib.synth_fill.restype = None
         lib.synth_fill.argtypes = [ctypes.c_int64, ctypes.c_int32] + [P] * 15
+        lib.synth_count_rows.restype = ctypes.c_int64
+        lib.synth_count_rows.argtypes = [ctypes.c_int64, ctypes.c_int32] + [P] * 6
+        lib.synth_fill_rows.restype = None
+        lib.synth_fill_rows.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32] + [P] * 15
         _lib_handle = lib
     return _lib_handle
 
@@ -91,6 +95,13 @@ class Config:
     noise_frac: float = 0.005    # noise std as a fraction of t_ref
     checker_cells: int = 4       # checkerboard block size (cells)
     checker_amp: float = 0.05
+    # closer to the paper's G: a ray of its own for every (pair, period) (the
+    # paper traces each period's ray on that period's phase-velocity map) and
+    # a depth kernel of its own for every lateral node (eq. (5): the depth
+    # sensitivity follows the local model; here the kernel centre is scaled by
+    # 1 + depth_factor_amp * a smooth lateral pattern)
+    per_period_rays: bool = False
+    depth_factor_amp: float = 0.0
 
     @property
     def nz(self) -> int:
@@ -123,6 +134,25 @@ def config1(seed: int = 0, variant: str = "ge2", n_stations: int = 229,
                   n_stations=n_stations, periods=tuple(np.linspace(1.0, 40.0, n_periods)),
                   min_wavelengths=2.0, max_wavelengths=8.0 if variant == "2to8" else None,
                   bent=True, seed=seed)
+
+
+def config1_paperlike(seed: int = 0) -> Config:
+    """Config 1's geometry and sizes with a bent ray of its own for every
+    (pair, period) and node-dependent depth kernels (centre scaled by 0.8 ..
+    1.2 over the lateral grid): no two periods of a pair share their lateral
+    nodes, and no two nodes share their depth weights."""
+    c = config1(seed=seed)
+    c.per_period_rays = True
+    c.depth_factor_amp = 0.2
+    c.name = f"cfg1_paperlike_seed{seed}"
+    return c
+
+
+def depth_factor(nx, ny, amp):
+    """Smooth lateral pattern in [1 - amp, 1 + amp], node order k = iy*nx + ix."""
+    iy, ix = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    f = np.sin(2.0 * np.pi * 1.5 * ix / max(nx - 1, 1)) * np.cos(2.0 * np.pi * 1.2 * iy / max(ny - 1, 1))
+    return (1.0 + amp * f).reshape(-1)
 
 
 def config3_systems() -> list[Config]:
@@ -199,11 +229,12 @@ def phase_velocity(T):
 # ----------------------------------------------------------------------------
 # geometry
 # ----------------------------------------------------------------------------
-def depth_kernel(z_nodes, T):
-    """Normalised Gaussian depth weights for period T: centre T km, width
-    0.3 * centre, nodes below 1e-3 of the peak dropped.  Returns (j0, w)."""
+def depth_kernel(z_nodes, T, factor=1.0):
+    """Normalised Gaussian depth weights for period T: centre T km (times
+    `factor`), width 0.3 * centre, nodes below 1e-3 of the peak dropped.
+    Returns (j0, w)."""
     z = np.asarray(z_nodes, dtype=np.float64)
-    zc = float(T) * 1.0
+    zc = float(T) * 1.0 * float(factor)
     sig = 0.3 * zc
     g = np.exp(-((z - zc) ** 2) / (2.0 * sig * sig))
     keep = np.nonzero(g >= 1e-3)[0]
@@ -364,7 +395,104 @@ class System:
         return self.scipy() @ np.asarray(x, dtype=np.float64)
 
 
+def fingerprint(s) -> str:
+    """SHA-256 of a generated system's sizes, row pointer, right-hand side and
+    a stride of its column indices and values: identifies the system that
+    stored reference results were computed for."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.array([s.m, s.n, s.nnz], dtype=np.int64).tobytes())
+    h.update(np.ascontiguousarray(s.row_ptr).tobytes())
+    h.update(np.ascontiguousarray(s.dt).tobytes())
+    h.update(np.ascontiguousarray(s.col[::997]).tobytes())
+    h.update(np.ascontiguousarray(s.val[::997]).tobytes())
+    return h.hexdigest()
+
+
+def _make_paperlike(cfg: Config, threads: int | None = None) -> System:
+    """make_system for per-period rays and node-dependent depth kernels (see
+    Config).  Draw order: stations, then per period the bends of all pairs,
+    then the noise."""
+    rng = np.random.default_rng(cfg.seed)
+    R = cfg.region_deg
+    sta = rng.uniform(0.0, R, size=(cfg.n_stations, 2))
+    ia, ib = np.triu_indices(cfg.n_stations, k=1)
+    a, b = sta[ia], sta[ib]
+    npairs = len(ia)
+    periods = np.asarray(cfg.periods, dtype=np.float64)
+    nper = len(periods)
+    cvel = phase_velocity(periods)
+    lam = cvel * periods
+    Dst = np.hypot(*(b - a).T)
+    cnt = np.zeros((npairs, nper), dtype=np.int64)
+    per_t = []
+    path_len = np.zeros((npairs, nper))
+    for t in range(nper):
+        bend = rng.uniform(-0.05, 0.05, size=npairs) * Dst if cfg.bent else None
+        pt_ptr, px, py = polylines(a, b, cfg.h, R, bend)
+        node_ptr, node_k, node_len, plen = bilinear_split(pt_ptr, px, py, cfg.h, cfg.nx, cfg.ny)
+        cnt[:, t] = np.diff(node_ptr)
+        path_len[:, t] = plen
+        per_t.append((node_ptr, node_k, node_len))
+    path_ptr = np.zeros(npairs * nper + 1, dtype=np.int64)
+    path_ptr[1:] = np.cumsum(cnt.reshape(-1))
+    node_k = np.empty(path_ptr[-1], dtype=np.int32)
+    node_len = np.empty(path_ptr[-1], dtype=np.float64)
+    for t, (nptr, nk, nl) in enumerate(per_t):
+        dst0 = path_ptr[np.arange(npairs) * nper + t]          # start of (p, t)
+        rep = np.repeat(dst0 - nptr[:-1], np.diff(nptr))
+        pos = np.arange(len(nk)) + rep
+        node_k[pos] = nk
+        node_len[pos] = nl
+    keep = np.ones((npairs, nper), dtype=bool)
+    if cfg.min_wavelengths is not None:
+        keep &= path_len >= cfg.min_wavelengths * lam[None, :]
+    if cfg.max_wavelengths is not None:
+        keep &= path_len <= cfg.max_wavelengths * lam[None, :]
+    keep &= cnt > 0
+    # depth kernels per (lateral node, period)
+    nn = cfg.nx * cfg.ny
+    fac = depth_factor(cfg.nx, cfg.ny, cfg.depth_factor_amp)
+    dj0 = np.zeros(nn * nper, dtype=np.int32)
+    dnj = np.zeros(nn * nper, dtype=np.int32)
+    wl = []
+    for k in range(nn):
+        for t, T in enumerate(periods):
+            j, w = depth_kernel(cfg.z_nodes, T, fac[k])
+            dj0[k * nper + t], dnj[k * nper + t] = j, len(w)
+            wl.append(w)
+    dw_ptr = np.zeros(nn * nper + 1, dtype=np.int64)
+    dw_ptr[1:] = np.cumsum(dnj)
+    dw = np.concatenate(wl)
+    lib = _lib()
+    keep_u8 = np.ascontiguousarray(keep.astype(np.uint8))
+    m = lib.synth_count_rows(npairs, nper, _ptr(keep_u8), _ptr(path_ptr), _ptr(node_k),
+                             _ptr(dnj), None, None, None)
+    row_ptr = np.empty(m + 1, dtype=np.int64)
+    row_pair = np.empty(m, dtype=np.int32)
+    row_period = np.empty(m, dtype=np.int32)
+    lib.synth_count_rows(npairs, nper, _ptr(keep_u8), _ptr(path_ptr), _ptr(node_k), _ptr(dnj),
+                         _ptr(row_ptr), _ptr(row_pair), _ptr(row_period))
+    nnz = int(row_ptr[-1])
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    gm = np.empty(m, dtype=np.float64)
+    m_true = checkerboard(cfg.nx, cfg.ny, cfg.nz, cfg.checker_cells, cfg.checker_amp)
+    lib.synth_fill_rows(m, cfg.nz, nper, _ptr(row_ptr), _ptr(row_pair), _ptr(row_period),
+                        _ptr(path_ptr), _ptr(node_k), _ptr(node_len), _ptr(cvel), _ptr(dj0),
+                        _ptr(dnj), _ptr(dw_ptr), _ptr(dw), _ptr(m_true), _ptr(col), _ptr(val),
+                        _ptr(gm))
+    t_ref = path_len[row_pair, row_period] / cvel[row_period]
+    noise = rng.standard_normal(m) * (cfg.noise_frac * t_ref)
+    return System(cfg=cfg, m=int(m), n=cfg.n, nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, row_ptr=row_ptr,
+                  col=col, val=val, dt=gm + noise, m_true=m_true, t_ref=t_ref, gm_true=gm,
+                  row_pair=row_pair, row_period=row_period, periods=periods,
+                  path_len=path_len.mean(axis=1), damp=cfg.damp, smooth=cfg.smooth, rays=None)
+
+
 def make_system(cfg: Config, threads: int | None = None) -> System:
+    if cfg.per_period_rays or cfg.depth_factor_amp:
+        return _make_paperlike(cfg, threads)
     rng = np.random.default_rng(cfg.seed)
     R = cfg.region_deg
     sta = rng.uniform(0.0, R, size=(cfg.n_stations, 2))

@@ -12,6 +12,8 @@
 //        int32 gcol[ngcols]; uint16 slot[nnz]   (row groups of at most CAP columns)
 //        (node runs built, for W = 2 then W = 4) int64 ok_pairs, total; uint32 dstp[nnruns];
 //        int64 nvqp[4 nnodes+1]
+//        (node runs built, for W = 1 then W = 2) int64 nslices, total; int64 sptr[nnodes+1];
+//        int64 off[nslices]; uint16 desc[nslices]; uint32 row[64 nslices]; uint64 dst[nnruns]
 // usage: runs_check IN OUT [CAP]   (CAP defaults to 4096)
 #include <stdio.h>
 #include <stdlib.h>
@@ -103,6 +105,17 @@ int main(int argc, char **argv)
         put(fo, &ok6, 1);
         put(fo, &total, 1);
         put(fo, dstp.data(), dstp.size()); put(fo, nvqp.data(), nvqp.size());
+    }
+    for (int W : {1, 2}) {
+        if (!ok2) break;
+        lsqr::RunSlices S;
+        lsqr::slice_layout_host(R, nn, W, S);
+        const int64_t nsl = (int64_t)S.off.size();
+        put(fo, &nsl, 1);
+        put(fo, &S.total, 1);
+        put(fo, S.sptr.data(), S.sptr.size()); put(fo, S.off.data(), S.off.size());
+        put(fo, S.desc.data(), S.desc.size()); put(fo, S.row.data(), S.row.size());
+        put(fo, S.dst.data(), S.dst.size());
     }
     fclose(fo);
     return 0;

@@ -1,0 +1,172 @@
+"""The solver's own sparse products, in every value type and stored format,
+element by element against the oracle's operator built from the same stored
+values (lsqr_apply_stored / lsqr_apply_t_stored, no column scale).
+
+Expected values: the FP64 oracle (oracle.Operator) on Ghat, where Ghat is G
+for the FP64 form, G rounded to FP32 for the FP32 form, and for the 16-bit
+forms sigma_i times the codes of oracle/quant.py (the definition of the
+stored form, independent of the library).  Bound per output element k: the
+forward product sums len_k products in the kernel's accumulation type, so
+|y_k - yref_k| <= (len_k + 4) u sum_j |ghat_kj z_j| with u the unit roundoff
+of that type (2^-53 for FP64, 2^-24 for the FP32 accumulations), a
+standard a-priori bound for recursive or blocked summation with one rounding
+per product; the transposed product likewise with the column's entries and
+the smoothing and damping terms.  The 16-bit forms' transposed product reads
+tg = sigma * y_G (a power-of-two scale: exact), as the solver gathers it.
+
+Systems: rows of odd length starting at odd positions with empty rows (the
+paired row-group loads and their padding element), the tomography pattern of
+a small ray geometry (row groups, depth pairs and run slices in their real
+shape), and a ragged random structure (short rows, empty columns).
+"""
+import zlib
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+from _helpers import laplacian
+from oracle import quant
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def odd_bounds_system():
+    rng = np.random.default_rng(21)
+    n = 1200
+    lens = np.array([3, 0, 401, 400, 5, 1, 0, 777, 2, 2])
+    rows = [np.sort(rng.choice(n, size=L, replace=False)) for L in lens]
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate(rows).astype(np.int32)
+    return synth.RandomSystem(m=len(lens), n=n, nx=10, ny=12, nz=10, row_ptr=row_ptr, col=col,
+                              val=rng.standard_normal(len(col)) * 10.0 ** rng.uniform(-3, 1, len(col)),
+                              dt=rng.standard_normal(len(lens)), damp=0.1, smooth=0.5)
+
+
+SYSTEMS = {
+    "odd_bounds": odd_bounds_system,
+    "paths": lambda: synth.make_system(synth.small_config(nx=30, ny=30, nz=8, n_stations=24,
+                                                          n_periods=6, region=3.0)),
+    "ragged": lambda: synth.random_system(500, 6, 5, 7, row_len=(0, 40), seed=8),
+}
+
+FORMATS = [("groups", "pairs"), ("groups", "slices"), ("csr", "runs"), ("csr", "csc"),
+           ("auto", "auto")]
+
+
+@pytest.fixture(scope="module", params=sorted(SYSTEMS))
+def system(request):
+    return request.param, SYSTEMS[request.param]()
+
+
+def stored_values(s, precision):
+    """(Ghat values in FP64, unit roundoff of the kernel's accumulation)."""
+    if precision == "fp64":
+        return s.val.copy(), 2.0 ** -53
+    if precision == "fp32":
+        return s.val.astype(np.float32).astype(np.float64), 2.0 ** -24
+    sig, q = quant.quantise_csr(s.row_ptr, s.val, precision)
+    rows = np.repeat(np.arange(s.m), np.diff(s.row_ptr))
+    return sig[rows].astype(np.float64) * quant.decode(q, precision), 2.0 ** -24
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_stored_products_elementwise(system, precision, fmt):
+    name, s = system
+    rf, cf = fmt
+    if rf == "groups" and name == "ragged":
+        rf = "auto"                          # short rows: no row groups
+    ghat, u = stored_values(s, precision)
+    kw = dict(precision=precision, row_format=rf, col_format=cf)
+    if precision in ("bf16", "fp16"):
+        kw["precond"] = "jacobi"
+    print(f"stored: {name} {precision} {rf}/{cf}", flush=True)
+    op = oracle.Operator(s.row_ptr, s.col, ghat, s.nx, s.ny, s.nz, s.damp, s.smooth)
+    rng = np.random.default_rng(zlib.crc32(f"{name}/{precision}/{rf}/{cf}".encode()))
+    vdt = np.float64 if precision == "fp64" else np.float32
+    z = rng.standard_normal(s.n).astype(vdt)
+    ybar = rng.standard_normal(s.m + 2 * s.n).astype(vdt)
+    # absolute sums for the bounds
+    Gabs = sp.csr_matrix((np.abs(ghat), s.col, s.row_ptr), shape=(s.m, s.n))
+    Labs = abs(laplacian(s.nx, s.ny, s.nz))
+    za, ya = np.abs(z.astype(np.float64)), np.abs(ybar.astype(np.float64))
+    fwd_abs = np.r_[Gabs @ za, s.smooth * (Labs @ za), s.damp * za]
+    adj_abs = Gabs.T @ ya[:s.m] + s.smooth * (Labs @ ya[s.m:s.m + s.n]) + s.damp * ya[s.m + s.n:]
+    rlen = np.r_[np.diff(s.row_ptr), np.full(2 * s.n, 7)]
+    clen = np.bincount(s.col, minlength=s.n) + 8
+    with oracle_free_solver(s, kw) as sol:
+        zt = torch.from_numpy(z).cuda()
+        yt = torch.from_numpy(ybar).cuda()
+        tg = None
+        if precision in ("bf16", "fp16"):
+            sig, _ = quant.quantise_csr(s.row_ptr, s.val, precision)
+            tg = torch.from_numpy((sig.astype(np.float64) * ybar[:s.m].astype(np.float64))
+                                  .astype(np.float32)).cuda()
+        yg = sol.apply_stored(zt).cpu().numpy().astype(np.float64)
+        qg = sol.apply_t_stored(yt, tg).cpu().numpy().astype(np.float64)
+        ks = sol.kernel_stats()
+    yr = op.apply(z.astype(np.float64))
+    qr = op.apply_t(ybar.astype(np.float64))
+    ybound = (rlen + 4) * u * fwd_abs + 1e-300
+    qbound = (clen + 4) * u * adj_abs + 1e-300
+    if precision != "fp64":
+        # the output is stored in FP32: one more rounding of the result
+        ybound += 2.0 ** -24 * np.abs(yr)
+        qbound += 2.0 ** -24 * np.abs(qr)
+    ey, eq = np.abs(yg - yr), np.abs(qg - qr)
+    assert np.all(ey <= ybound), (ks, int(np.argmax(ey / ybound)), float((ey / ybound).max()))
+    assert np.all(eq <= qbound), (ks, int(np.argmax(eq / qbound)), float((eq / qbound).max()))
+    if cf == "slices":
+        assert ks["col_format"] == 5
+    if rf == "groups":
+        assert ks["row_format"] == 4
+
+
+def oracle_free_solver(s, kw):
+    from paper_2604_11920_amd import Solver
+    return Solver.from_system(s, **kw)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_stored_integer_bitwise(precision):
+    """Integer values and vectors (|entries| <= 8, codes exact in every form):
+    every partial sum is exact, so the slices, pairs and CSC products agree
+    with the oracle to the bit."""
+    base = synth.make_system(synth.small_config(nx=12, ny=10, nz=9, n_stations=16, n_periods=6,
+                                                region=1.1, seed=9))
+    rng = np.random.default_rng(12)
+    val = rng.integers(-8, 9, base.nnz).astype(np.float64)
+    val[val == 0] = 1.0
+    s = synth.RandomSystem(m=base.m, n=base.n, nx=base.nx, ny=base.ny, nz=base.nz,
+                           row_ptr=base.row_ptr, col=base.col, val=val, dt=base.dt, damp=0.25,
+                           smooth=0.5)
+    ghat, _ = stored_values(s, precision)
+    op = oracle.Operator(s.row_ptr, s.col, ghat, s.nx, s.ny, s.nz, s.damp, s.smooth)
+    vdt = np.float64 if precision == "fp64" else np.float32
+    z = rng.integers(-8, 9, s.n).astype(vdt)
+    ybar = rng.integers(-8, 9, s.m + 2 * s.n).astype(vdt)
+    kw = dict(precision=precision)
+    if precision == "bf16":
+        kw["precond"] = "jacobi"
+    for cf in ("slices", "pairs", "csc", "runs"):
+        with oracle_free_solver(s, dict(kw, col_format=cf)) as sol:
+            tg = None
+            if precision == "bf16":
+                sig, _ = quant.quantise_csr(s.row_ptr, s.val, precision)
+                tg = torch.from_numpy((sig.astype(np.float64) * ybar[:s.m].astype(np.float64))
+                                      .astype(np.float32)).cuda()
+            qg = sol.apply_t_stored(torch.from_numpy(ybar).cuda(), tg).cpu().numpy()
+            yg = sol.apply_stored(torch.from_numpy(z).cuda()).cpu().numpy()
+        assert np.array_equal(qg.astype(np.float64), op.apply_t(ybar.astype(np.float64))), cf
+        assert np.array_equal(yg.astype(np.float64), op.apply(z.astype(np.float64))), cf

@@ -100,6 +100,14 @@ def run_builders(exe, tmp, row_ptr, col, n, nz, cap=4096):
         out[f"pad_total{W}"] = int(tot6)
         out[f"dstp{W}"] = take(np.uint32, nr2)
         out[f"nvqp{W}"] = take(np.int64, 4 * nn + 1)
+    for W in ((1, 2) if ok2 else ()):
+        nsl, tot = take(np.int64, 2)
+        out[f"sl_total{W}"] = int(tot)
+        out[f"sptr{W}"] = take(np.int64, nn + 1)
+        out[f"soff{W}"] = take(np.int64, nsl)
+        out[f"sdesc{W}"] = take(np.uint16, nsl)
+        out[f"srow{W}"] = take(np.uint32, 64 * nsl)
+        out[f"sdst{W}"] = take(np.uint64, nr2)
     assert pos == len(buf)
     return out
 
@@ -425,3 +433,88 @@ def test_pair_layout(driver, tmp_path):
         assert o["nodes_ok"] and o["pairs_ok2"] and o["pairs_ok4"]
         check_pair_layout(o, s.nz, 2)
         check_pair_layout(o, s.nz, 4)
+
+
+def check_slices(o, row_ptr, col, n, nz, W, rng):
+    """The run-slice layout: every run in exactly one lane of one slice of its
+    node, slices of one first depth and at most 64 runs, padded lengths a
+    multiple of W and at least each run's length, offsets contiguous; and the
+    transposed product computed through the layout exactly as the kernel
+    sums it (per lane over its slices, lanes, waves) equals the CSC product
+    on integer data, where every order of the sum gives the same result."""
+    nn = n // nz
+    sptr, off, desc, srow, dst = (o[f"{k}{W}"] for k in ("sptr", "soff", "sdesc", "srow", "sdst"))
+    nrp, rrow, rsrc, rdesc = o["nrp"], o["row"], o["src"], o["desc"]
+    nsl = len(off)
+    assert sptr[0] == 0 and sptr[-1] == nsl and np.all(np.diff(sptr) >= 0)
+    L = (desc & 255).astype(np.int64)
+    iz0 = (desc >> 8).astype(np.int64)
+    assert np.all(L % W == 0) and np.all(L > 0)
+    assert off[0] == 0 if nsl else True
+    assert np.array_equal(np.r_[off[1:], o[f"sl_total{W}"]] - off, 64 * L)
+    # lane of each run, slice of each run
+    rel = dst.astype(np.int64)
+    sl_of = np.searchsorted(off, rel, side="right") - 1
+    lane = (rel - off[sl_of]) // W
+    assert np.all((rel - off[sl_of]) % W == 0) and np.all((lane >= 0) & (lane < 64))
+    pairs = sl_of * 64 + lane
+    assert len(np.unique(pairs)) == len(pairs)                # one run per lane
+    assert np.all(srow[pairs] == rrow)
+    node_of_run = np.repeat(np.arange(nn), np.diff(nrp))
+    node_of_sl = np.repeat(np.arange(nn), np.diff(sptr))
+    assert np.array_equal(node_of_sl[sl_of], node_of_run)       # slice of the run's node
+    assert np.array_equal(iz0[sl_of], (rdesc >> 8).astype(np.int64))
+    assert np.all(L[sl_of] >= (rdesc & 255))
+    used = np.zeros(64 * nsl, bool)
+    used[pairs] = True
+    assert np.all(srow[~used] == 0)                             # padding lanes: row 0
+    # the product through the layout (integer values, exact)
+    m = len(row_ptr) - 1
+    val = rng.integers(-8, 9, len(col)).astype(np.float64)
+    t = rng.integers(-8, 9, m).astype(np.float64)
+    lay = np.zeros(o[f"sl_total{W}"] + W)
+    for r in range(len(rrow)):
+        ln = int(rdesc[r] & 255)
+        e = np.arange(ln)
+        lay[rel[r] + (e // W) * 64 * W + e % W] = val[int(rsrc[r]) + e]
+    q = np.zeros(n)
+    for k in range(nn):
+        for sl in range(sptr[k], sptr[k + 1]):
+            for e in range(L[sl]):
+                v = lay[off[sl] + (e // W) * 64 * W + np.arange(64) * W + e % W]
+                if iz0[sl] + e >= nz:               # padding past the deepest node
+                    assert not np.any(v)
+                    continue
+                q[k * nz + iz0[sl] + e] += np.dot(v, t[srow[sl * 64:(sl + 1) * 64]])
+    row = np.repeat(np.arange(m), np.diff(row_ptr))
+    ref = np.zeros(n)
+    np.add.at(ref, col, val * t[row])
+    assert np.array_equal(q, ref)
+
+
+def test_run_slices(driver, tmp_path):
+    rng = np.random.default_rng(3)
+    s = synth.make_system(synth.small_config(nx=6, ny=5, nz=7, n_stations=10, n_periods=4,
+                                             region=0.5, seed=2))
+    o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
+    assert o["nodes_ok"]
+    for W in (1, 2):
+        check_slices(o, s.row_ptr, s.col, s.n, s.nz, W, rng)
+
+
+def test_run_slices_irregular_runs(driver, tmp_path):
+    """Random structure: runs of every first depth and length, gaps, empty
+    rows, nodes with more than 64 runs of one first depth."""
+    rng = np.random.default_rng(4)
+    nx, ny, nz = 3, 2, 9
+    n = nx * ny * nz
+    rows = []
+    for i in range(400):
+        cols = np.sort(rng.choice(n, size=rng.integers(0, 25), replace=False))
+        rows.append(cols)
+    row_ptr = np.r_[0, np.cumsum([len(c) for c in rows])].astype(np.int64)
+    col = np.concatenate(rows).astype(np.int32)
+    o = run_builders(driver, tmp_path, row_ptr, col, n, nz)
+    assert o["nodes_ok"]
+    for W in (1, 2):
+        check_slices(o, row_ptr, col, n, nz, W, rng)
