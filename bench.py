@@ -181,6 +181,29 @@ def measured_traffic(tag, formats=None):
 
 
 
+def kernel_label(tag, ks):
+    """Name of the kernel the solver's formats select (as lsqr_kernel_stats
+    reports them)."""
+    if tag == "fwd":
+        rf = ks["row_format"]
+        if rf == 4:
+            return ("k_fwd_lcol_pair (forward product, row groups, entries in aligned pairs)"
+                    if ks["fwd_pairs"] else
+                    "k_fwd_lcol (forward product, row groups, columns staged in LDS)")
+        return {1: "k_fwd_pipe / k_fwd_csr (forward product, CSR rows)",
+                2: "k_fwd_runs (forward product, depth-run rows)",
+                3: "k_fwd_rmask (forward product, run-mask rows)"}[rf]
+    cf = ks["col_format"]
+    if cf == 4:
+        w = ks["adj_depths_per_word"]
+        return (f"k_adj_npair<{w}> (transposed product, node runs, "
+                + ("depth pairs)" if w == 2 else "four-depth words)"))
+    return {1: "k_adj (transposed product, CSC)",
+            2: "k_adj_nruns (transposed product, node runs)",
+            3: "k_adj_nmask (transposed product, node masks)",
+            5: "k_adj_slices (transposed product, run slices)"}[cf]
+
+
 def assembly_check(s, host_s):
     """Device-side assembly of G from the same rays: seconds (host row
     structure + device fill, median of 3) against the host generator, and a
@@ -572,18 +595,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom_gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, f"{ks['row_format']}/{ks['col_format']}"),
-                     "kernel": ({1: "k_fwd_pipe (forward product, CSR rows, 64 lanes per row)",
-                                 2: "k_fwd_runs (forward product, depth-run rows)",
-                                 3: "k_fwd_rmask (forward product, run-mask rows)",
-                                 4: "k_fwd_lcol (forward product, row groups, columns staged in LDS)"}
-                                [ks["row_format"]]
-                                if dom == "fwd" else
-                                {1: "k_adj (transposed product, CSC)",
-                                 2: "k_adj_nruns (transposed product, node runs)",
-                                 3: "k_adj_nmask (transposed product, node masks)",
-                                 4: "k_adj_npair (transposed product, node runs, depth pairs)",
-                                 5: "k_adj_slices (transposed product, run slices)"}
-                                [ks["col_format"]])},
+                     "kernel": kernel_label(dom, ks)},
         "kernels": {"fwd": {"avg_us": fwd_avg * 1e3, "alg_bytes": ks["fwd_bytes"], "gbs": fwd_gbs},
                     "adj": {"avg_us": adj_avg * 1e3, "alg_bytes": ks["adj_bytes"], "gbs": adj_gbs}},
         "paper_protocol_ms_per_step": 1e3 * sum(trimmed) / len(trimmed),

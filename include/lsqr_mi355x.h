@@ -200,15 +200,25 @@ typedef struct {
     int col_format;             /* transposed product: 1 CSC, 2 node runs, 3 node     */
                                 /* masks, 4 node runs in the depth-pair layout, 5 run */
                                 /* slices                                             */
+    int fwd_pairs;              /* row groups: 1 when entries are read in aligned      */
+                                /* pairs (k_fwd_lcol_pair), 0 one at a time            */
+    int adj_depths_per_word;    /* node-run layouts: depths per lane and load (1 plain */
+                                /* runs, 2 depth pairs, 4 four-depth words)            */
+    int64_t groups;             /* row groups of the forward product (0 otherwise)     */
+    int64_t staged_cols;        /* columns staged in LDS per forward product, summed   */
+                                /* over the groups                                     */
+    int64_t padded_values;      /* zeros the transposed layout adds to the stored      */
+                                /* values (depth pairs, four-depth words, run slices)  */
 } lsqr_kstats;
 
 /*
  * lsqr_create — validate G (the data block of eq. (6), columns ordered as in
  * eq. (7)), copy it to the device, build its transpose (CSC, a stable device
  * sort by column so rows stay ascending within a column), the stored formats
- * opts.row_format / opts.col_format select (by default the node runs of the
- * data block for the transposed product, built from the CSR structure on the
- * host) and the column scaling.  damp >= 0 and smooth_weight >= 0 (damp > 0 is required by
+ * opts.row_format / opts.col_format select (by default, where the matrix fits
+ * them, row groups for the forward product and node runs in the depth-pair
+ * layout for the transposed product, both built from the CSR structure on
+ * the host) and the column scaling.  damp >= 0 and smooth_weight >= 0 (damp > 0 is required by
  * the mixed forms, whose refinement folds the FP64 correction into the damping
  * block).  opts may be NULL (FP64, no scaling, default stream, hipMalloc).
  * On success *out owns every derived buffer; free it with lsqr_destroy.

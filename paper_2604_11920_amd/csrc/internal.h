@@ -111,6 +111,14 @@ struct RowFmt {
     int padded = 0;                    // 1: val and slot hold one more (zero) element
 };
 
+// The paired row-group kernel reads two values and two slots at a time from
+// even positions, and one element past the last entry (RowFmt::padded).
+static inline bool lcol_pairs_ok(const RowFmt &R)
+{
+    const uintptr_t w = 2 * (uintptr_t)vt_size(R.vt);
+    return R.padded && ((uintptr_t)R.val & (w - 1)) == 0 && ((uintptr_t)R.slot & 3u) == 0;
+}
+
 // Stored transpose (CSC) for the transposed product.
 struct ColFmt {
     int vt = VT_F64;

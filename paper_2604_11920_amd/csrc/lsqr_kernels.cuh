@@ -1851,14 +1851,6 @@ __global__ __launch_bounds__(kBlock) void k_update_lsmr(UpdArgs a)
 // Instantiated once per vector type V in kernels_f64.hip / kernels_f32.hip.
 namespace lsqr {
 
-// The paired row-group kernel reads two values and two slots at a time from
-// even positions, and one element past the last entry (RowFmt::padded).
-static inline bool lcol_pairs_ok(const RowFmt &R)
-{
-    const uintptr_t w = 2 * (uintptr_t)vt_size(R.vt);
-    return R.padded && ((uintptr_t)R.val & (w - 1)) == 0 && ((uintptr_t)R.slot & 3u) == 0;
-}
-
 template <class M, class V>
 static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArgs &a)
 {

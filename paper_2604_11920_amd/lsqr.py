@@ -69,7 +69,10 @@ class KStats(ctypes.Structure):
     _fields_ = [("fwd_ms", ctypes.c_double), ("adj_ms", ctypes.c_double),
                 ("fwd_launches", ctypes.c_int), ("adj_launches", ctypes.c_int),
                 ("fwd_bytes", ctypes.c_double), ("adj_bytes", ctypes.c_double),
-                ("row_format", ctypes.c_int), ("col_format", ctypes.c_int)]
+                ("row_format", ctypes.c_int), ("col_format", ctypes.c_int),
+                ("fwd_pairs", ctypes.c_int), ("adj_depths_per_word", ctypes.c_int),
+                ("groups", ctypes.c_int64), ("staged_cols", ctypes.c_int64),
+                ("padded_values", ctypes.c_int64)]
 
 
 class Rays(ctypes.Structure):
