@@ -468,6 +468,28 @@ lsqr_status lsqr_column_features(lsqr_ctx *ctx, float *feat);
 lsqr_status lsqr_mlp_scale(lsqr_ctx *ctx, const float *params, const float *mean, const float *std,
                            unsigned centre, const float *feat, double *d);
 
+/*
+ * lsqr_mlp_scale_noalloc — for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same operation, arguments and result as lsqr_mlp_scale
+ * (the same kernels, so d is bitwise the same), with its temporary (the
+ * Jacobi scale and the feature means, n + 6 doubles) in a static device
+ * array of LSQR_NOALLOC_MAX_COLS + 6 doubles (8 MiB) that the library holds
+ * on each device it runs on until the process ends, instead of an
+ * allocation.  It calls no device allocator.
+ * Errors: LSQR_E_INVALID_ARG as lsqr_mlp_scale, and when ctx's system has
+ * more than LSQR_NOALLOC_MAX_COLS unknowns; LSQR_E_DEVICE if the array's
+ * device address cannot be obtained.
+ * All calls on one device share the array: calls that overlap on one device
+ * (different host threads, or different streams without ordering between
+ * them) race on it and must be serialised by the caller.  Every element a
+ * call reads is written earlier in the same call, so nothing carries over.
+ */
+#define LSQR_NOALLOC_MAX_COLS 1048576
+lsqr_status lsqr_mlp_scale_noalloc(lsqr_ctx *ctx, const float *params, const float *mean,
+                                   const float *std, unsigned centre, const float *feat,
+                                   double *d);
+
 /* Training state (FP32 parameters and Adam moments on the device). */
 typedef struct lsqr_trainer lsqr_trainer;
 

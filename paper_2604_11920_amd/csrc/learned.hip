@@ -6,6 +6,8 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "ctx.h"
@@ -310,6 +312,33 @@ static void trainer_free(lsqr_trainer *t)
     delete t;
 }
 
+// Scratch of lsqr_mlp_scale_noalloc: the Jacobi scale of up to
+// LSQR_NOALLOC_MAX_COLS columns followed by the NF feature means.  Host code
+// never passes this name to a kernel or a copy: it reads the array's device
+// address once per device (hipGetSymbolAddress) and uses that address.
+static __device__ __align__(256) double scratch[LSQR_NOALLOC_MAX_COLS + NF];
+
+static std::mutex g_scratch_mu;
+static std::vector<double *> g_scratch_ptr;      // per device; null until looked up
+
+static lsqr_status scratch_address(lsqr_ctx *c, double **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    const int dev = c->device;
+    if (dev < 0) return fail(c, LSQR_E_DEVICE, "invalid device of the context");
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        double *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(c, LSQR_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                              hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LSQR_OK;
+}
+
 extern "C" {
 
 lsqr_status lsqr_column_features(lsqr_ctx *c, float *feat)
@@ -376,6 +405,27 @@ lsqr_status lsqr_mlp_scale(lsqr_ctx *c, const float *params, const float *mean, 
     s = mlp_scale_into(c, params, nrm, centre, feat, d, djac);
     ctx_release(c, djac);
     return s;
+}
+
+lsqr_status lsqr_mlp_scale_noalloc(lsqr_ctx *c, const float *params, const float *mean,
+                                   const float *std, unsigned centre, const float *feat, double *d)
+{
+    Norm nrm;
+    lsqr_status s = mlp_scale_args(c, params, mean, std, centre, feat, d, nrm);
+    if (s != LSQR_OK) return s;
+    if (c->P.n > LSQR_NOALLOC_MAX_COLS)
+        return fail(c, LSQR_E_INVALID_ARG,
+                    "lsqr_mlp_scale_noalloc: n = " + std::to_string(c->P.n) +
+                        " columns exceeds the static scratch of " +
+                        std::to_string((long long)LSQR_NOALLOC_MAX_COLS) +
+                        " (use lsqr_mlp_scale)");
+    DeviceGuard dg(c->device);
+    double *djac = nullptr;
+    s = scratch_address(c, &djac);
+    if (s != LSQR_OK) return s;
+    // every element the kernels read is written first in the same call (the
+    // Jacobi scale of all n columns, then the NF means): nothing to clear
+    return mlp_scale_into(c, params, nrm, centre, feat, d, djac);
 }
 
 static thread_local std::string t_err;

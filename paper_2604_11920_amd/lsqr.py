@@ -117,6 +117,7 @@ def load():
         "lsqr_autotune_batched": (I, [P, I, I, ctypes.POINTER(BatchCfg)]),
         "lsqr_column_features": (I, [P, P]),
         "lsqr_mlp_scale": (I, [P, P, P, P, ctypes.c_uint, P, P]),
+        "lsqr_mlp_scale_noalloc": (I, [P, P, P, P, ctypes.c_uint, P, P]),
         "lsqr_trainer_create": (I, [I, P, P, _ALLOC_FN, _FREE_FN, P, ctypes.POINTER(P)]),
         "lsqr_trainer_grad": (I, [P, I, P, P, P, ctypes.POINTER(D)]),
         "lsqr_trainer_step": (I, [P, I, P, P, ctypes.c_float, ctypes.POINTER(D)]),
@@ -417,6 +418,15 @@ class Solver:
             d = self._torch.empty(self.n, dtype=self._torch.float64, device="cuda")
         self._check(self._lib.lsqr_mlp_scale(self._ctx, _ptr(params), _ptr(mean), _ptr(std),
                                              int(centre), _ptr(feat), _ptr(d)))
+        return d
+
+    def mlp_scale_noalloc(self, params, mean, std, feat, d, centre=0):
+        """lsqr_mlp_scale_noalloc: as mlp_scale, into the caller's d, with the
+        temporaries in the library's static device scratch (no allocation)."""
+        mean = np.ascontiguousarray(mean, dtype=np.float32)
+        std = np.ascontiguousarray(std, dtype=np.float32)
+        self._check(self._lib.lsqr_mlp_scale_noalloc(self._ctx, _ptr(params), _ptr(mean),
+                                                     _ptr(std), int(centre), _ptr(feat), _ptr(d)))
         return d
 
     def kernel_stats(self):
