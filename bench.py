@@ -197,7 +197,7 @@ def kernel_label(tag, ks):
     if cf == 4:
         w = ks["adj_depths_per_word"]
         return (f"k_adj_npair<{w}> (transposed product, node runs, "
-                + ("depth pairs)" if w == 2 else "four-depth words)"))
+                + {2: "depth pairs)", 4: "four-depth words)", 8: "eight-depth words)"}[w])
     return {1: "k_adj (transposed product, CSC)",
             2: "k_adj_nruns (transposed product, node runs)",
             3: "k_adj_nmask (transposed product, node masks)",
@@ -354,79 +354,149 @@ def time_to_tol(s, dt, tol, fmt, model_path=None, xstar=None):
     return out
 
 
-def batched_bench(args):
-    """Batched form: the four uneven systems of the batched workload, 32
-    right-hand sides each (16 checkerboards + 16 noise draws), fixed iteration
-    count, one batched call per step.  Prints one JSON line."""
+def batched_measure(iters=300, steps=1, warmup=1, row_format="auto", col_format="auto",
+                    refine=False):
+    """The batched workload: the four uneven systems of the batched case
+    (config-1 geometry, (stations, periods) = (60,10), (120,14), (180,17),
+    (229,20), seeds 0..3), 32 right-hand sides each (16 checkerboards, 16
+    noise draws), schedules from the autotuner, `iters` iterations per step.
+    Returns the right-hand-side iteration rate, the matrix bytes per batched
+    iteration (FP32 CSR + CSC values and indices) and their rate against the
+    HBM peak, and per system the block products' times."""
     import torch
 
     import synth
-    from paper_2604_11920_amd import Solver, solve_batched
-    iters = args.iters or 300
+    from paper_2604_11920_amd import Solver, solve_batched, solve_batched_refined
     sols, dts, nnz, rows = [], [], 0, 0
-    for cfg in synth.config3_systems():
-        t0 = time.perf_counter()
-        s = synth.make_system(cfg)
-        rhs = synth.checker_rhs_batch(s)
-        sols.append(Solver.from_system(s, row_format=args.row_format, col_format=args.col_format))
-        dts.append(torch.from_numpy(rhs).cuda())
-        nnz += s.nnz
-        rows += s.m
-        log(f"[batched] {cfg.name}: m={s.m} nnz={s.nnz} ({time.perf_counter() - t0:.1f}s)")
-        del s, rhs
-    R = int(dts[0].shape[1])
-    cache = os.path.join(ROOT, "gpurun_out", "batch_tune.json")
-    tuned = []
-    for sol in sols:
-        cfg = sol.autotune_batched(R, probe_iters=8, cache=cache)
-        tuned.append(cfg)
-        log(f"[batched] tuned {cfg}")
-    for _ in range(args.warmup):
-        solve_batched(sols, dts, iters, history=False)
-    torch.cuda.synchronize()
-    per = []
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        _, _, infos = solve_batched(sols, dts, iters, history=False)
-        per.append(time.perf_counter() - t0)
-    wall = sum(per)
-    rhs_its = len(sols) * R * iters * args.steps / wall
-    sec_per_batched_iter = wall / (iters * args.steps)
-    # the block products of each system under its tuned schedule, timed apart
-    # (HIP events on the solver's stream, mean of 10 calls)
-    products = []
-    for sol in sols:
-        x = torch.randn(sol.n, R, device="cuda", dtype=torch.float32)
-        yb = torch.randn(sol.m + 2 * sol.n, R, device="cuda", dtype=torch.float32)
-        y = sol.apply_block(x)
-        xt = sol.apply_t_block(yb)
-        row = {}
-        for name, f in (("fwd_ms", lambda: sol.apply_block(x, y)),
-                        ("adj_ms", lambda: sol.apply_t_block(yb, xt))):
-            f()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(10):
+    try:
+        for cfg in synth.config3_systems():
+            t0 = time.perf_counter()
+            s = synth.make_system(cfg)
+            rhs = synth.checker_rhs_batch(s)
+            sols.append(Solver.from_system(s, row_format=row_format, col_format=col_format,
+                                           precond="jacobi" if refine else "none"))
+            dts.append(torch.from_numpy(rhs).cuda())
+            nnz += s.nnz
+            rows += s.m
+            log(f"[batched] {cfg.name}: m={s.m} nnz={s.nnz} ({time.perf_counter() - t0:.1f}s)")
+            del s, rhs
+        R = int(dts[0].shape[1])
+        tuned = [sol.autotune_batched(R, probe_iters=8) for sol in sols]
+        log(f"[batched] tuned {tuned}")
+        for _ in range(warmup):
+            solve_batched(sols, dts, iters, history=False)
+        torch.cuda.synchronize()
+        per = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            solve_batched(sols, dts, iters, history=False)
+            per.append(time.perf_counter() - t0)
+        wall = sum(per)
+        sec_per_it = wall / (iters * steps)
+        products = []
+        for sol in sols:
+            x = torch.randn(sol.n, R, device="cuda", dtype=torch.float32)
+            yb = torch.randn(sol.m + 2 * sol.n, R, device="cuda", dtype=torch.float32)
+            y = sol.apply_block(x)
+            xt = sol.apply_t_block(yb)
+            row = {}
+            for name, f in (("fwd_ms", lambda: sol.apply_block(x, y)),
+                            ("adj_ms", lambda: sol.apply_t_block(yb, xt))):
                 f()
-            e1.record()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(10):
+                    f()
+                e1.record()
+                torch.cuda.synchronize()
+                row[name] = e0.elapsed_time(e1) / 10
+            products.append(row)
+        mat_bytes = 2 * nnz * 8.0
+        out = {"value": len(sols) * R * iters * steps / wall, "unit": "rhs-iters/s",
+               "systems": len(sols), "rhs_per_system": R, "iters": iters, "steps": steps,
+               "ms_per_step": 1e3 * wall / steps, "batched_iters_per_s": 1.0 / sec_per_it,
+               "matrix_bytes_per_batched_iter": mat_bytes,
+               "matrix_gbs": mat_bytes / sec_per_it / 1e9,
+               "matrix_frac_of_hbm_peak": mat_bytes / sec_per_it / 1e9 / HBM_PEAK_GBS,
+               "nnz_total": nnz, "rows_total": rows, "tuned": tuned, "block_products": products}
+        if refine:
             torch.cuda.synchronize()
-            row[name] = e0.elapsed_time(e1) / 10
-        products.append(row)
-        log(f"[batched] block products: forward {row['fwd_ms']:.3f} ms, "
-            f"transposed {row['adj_ms']:.3f} ms")
-    # matrix bytes of one batched iteration: FP32 CSR and CSC (value + index)
-    mat_bytes = 2 * nnz * 8.0
-    out = {"metric": "batched LSQR right-hand-side iterations/s", "value": rhs_its,
-           "unit": "rhs-iters/s", "systems": len(sols), "rhs_per_system": R,
-           "iters": iters, "steps": args.steps, "ms_per_step": 1e3 * wall / args.steps,
-           "batched_iters_per_s": 1.0 / sec_per_batched_iter,
-           "matrix_bytes_per_batched_iter": mat_bytes,
-           "matrix_gbs": mat_bytes / sec_per_batched_iter / 1e9, "nnz_total": nnz,
-           "rows_total": rows, "tuned": tuned, "block_products": products,
-           "dtype": "f32 values/vectors, f64 scalars",
+            t0 = time.perf_counter()
+            _, infos = solve_batched_refined(sols, dts, 3000, 1e-6, inner_tol=1e-4, sweeps=8)
+            torch.cuda.synchronize()
+            flat = [i for sys_i in infos for i in sys_i]
+            out["refined_to_1e-6"] = {
+                "seconds": time.perf_counter() - t0,
+                "inner_iters_max": max(i["iters"] for i in flat),
+                "sweeps_max": max(i["sweeps"] for i in flat),
+                "istop_counts": {str(k): sum(1 for i in flat if i["istop"] == k)
+                                 for k in sorted({i["istop"] for i in flat})},
+                "eta_fp64_max": max(i["eta_final_fp64"] for i in flat)}
+        return out
+    finally:
+        for sol in sols:
+            sol.close()
+
+
+def batched_bench(args):
+    """Batched form alone (see batched_measure), with the refined solve of
+    every right-hand side to eta <= 1e-6.  Prints one JSON line."""
+    iters = args.iters or 300
+    out = {"metric": "batched LSQR right-hand-side iterations/s"}
+    out.update(batched_measure(iters, args.steps, args.warmup, args.row_format, args.col_format,
+                               refine=True))
+    out.update(dtype="f32 values/vectors, f64 scalars", data="synthetic")
+    print(json.dumps(out), flush=True)
+
+
+def products_bench(args):
+    """The solver's two sparse products alone for one precision on the
+    paper-shaped system, in the formats the solver picks (lsqr_apply_stored /
+    lsqr_apply_t_stored: the same kernels and launch configuration as inside
+    its iterations), timed with HIP events on the solver's stream, mean of
+    `--steps` x 20 calls.  Prints one JSON line."""
+    import torch
+
+    import synth
+    from paper_2604_11920_amd import Solver
+    prec = args.products
+    s = synth.make_system(synth.config1())
+    kw = dict(precision=prec, row_format=args.row_format, col_format=args.col_format)
+    if prec in ("bf16", "fp16"):
+        kw["precond"] = "jacobi"
+    with Solver.from_system(s, **kw) as sol:
+        vdt = torch.float64 if prec == "fp64" else torch.float32
+        g = torch.Generator(device="cuda").manual_seed(1)
+        z = torch.randn(s.n, dtype=vdt, device="cuda", generator=g)
+        yb = torch.randn(s.m + 2 * s.n, dtype=vdt, device="cuda", generator=g)
+        y, q = torch.empty_like(yb), torch.empty_like(z)
+        tg = yb[:s.m].clone() if prec in ("bf16", "fp16") else None
+        st = torch.cuda.current_stream()
+        res = {}
+        for name, f in (("fwd", lambda: sol.apply_stored(z, y)),
+                        ("adj", lambda: sol.apply_t_stored(yb, tg, q))):
+            for _ in range(max(args.warmup, 1)):
+                f()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20 * max(args.steps, 1)
+            e0.record(st)
+            for _ in range(reps):
+                f()
+            e1.record(st)
+            torch.cuda.synchronize()
+            res[name] = e0.elapsed_time(e1) / reps * 1e3
+        ks = sol.kernel_stats()
+    out = {"metric": f"{prec} sparse products: microseconds per launch and GB/s",
+           "precision": prec, "m": s.m, "n": s.n, "nnz": s.nnz,
+           "fwd": {"kernel": kernel_label("fwd", ks), "avg_us": res["fwd"],
+                   "alg_bytes": ks["fwd_bytes"], "gbs": ks["fwd_bytes"] / res["fwd"] / 1e3,
+                   "frac_of_hbm_peak": ks["fwd_bytes"] / res["fwd"] / 1e3 / HBM_PEAK_GBS},
+           "adj": {"kernel": kernel_label("adj", ks), "avg_us": res["adj"],
+                   "alg_bytes": ks["adj_bytes"], "gbs": ks["adj_bytes"] / res["adj"] / 1e3,
+                   "frac_of_hbm_peak": ks["adj_bytes"] / res["adj"] / 1e3 / HBM_PEAK_GBS,
+                   "padded_values": ks["padded_values"]},
            "data": "synthetic"}
-    for sol in sols:
-        sol.close()
     print(json.dumps(out), flush=True)
 
 
@@ -466,7 +536,7 @@ def main():
     ap.add_argument("--config", default="cfg1", choices=["cfg1", "cfg0"])
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--cpu-runs", type=int, default=10,
                     help="timed runs of the CPU oracle sample (the paper's protocol: 10)")
     ap.add_argument("--no-scipy", action="store_true", help="skip the SciPy LSQR context timing")
@@ -475,6 +545,8 @@ def main():
                     choices=["auto", "csc", "runs", "masks", "pairs", "slices"])
     ap.add_argument("--xcd-bands", action="store_true",
                     help="transposed product: one contiguous column band per XCD")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched multi-right-hand-side measurement")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32 rate and the time-to-tolerance comparisons")
     ap.add_argument("--ttt-tol", type=float, default=1e-6)
@@ -483,6 +555,8 @@ def main():
                          "(default: the model fitted on config-1-geometry training systems)")
     ap.add_argument("--outer", action="store_true",
                     help="measure the outer iterations with re-linearisation instead (one JSON line)")
+    ap.add_argument("--products", choices=["fp64", "fp32", "bf16", "fp16"], default=None,
+                    help="time the two sparse products alone in this precision (one JSON line)")
     ap.add_argument("--batched", action="store_true",
                     help="measure the batched multi-RHS form instead (one JSON line)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -513,6 +587,9 @@ def main():
         return
     if args.batched:
         batched_bench(args)
+        return
+    if args.products:
+        products_bench(args)
         return
     t0 = time.perf_counter()
     if args.config == "cfg1":
@@ -608,6 +685,13 @@ def main():
         out["assembly"] = assembly_check(s, gen_s)
         out["fp32"] = fp32_rate(s, dt, iters, fmt, gold)
         out["time_to_tol"] = time_to_tol(s, dt, args.ttt_tol, fmt, args.model, xstar)
+    if not args.no_batched and args.config == "cfg1":
+        del dt, dm
+        import torch
+        torch.cuda.empty_cache()
+        out["batched"] = batched_measure()
+        log(f"[bench] batched: {out['batched']['value']:.0f} rhs-iters/s, matrix "
+            f"{out['batched']['matrix_gbs']:.0f} GB/s")
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_iters, args.cpu_runs)

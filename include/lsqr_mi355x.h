@@ -344,6 +344,37 @@ lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const 
                                double *const *res_hist, lsqr_info *info);
 
 /*
+ * lsqr_solve_batched_refined — the batched solve with iterative refinement
+ * per right-hand side, so that the FP32 values and vectors of the batch
+ * still reach the FP64 solution.  Each sweep computes, for every right-hand
+ * side that has not stopped, in FP64 with the FP64 operator: the residual
+ * rbar = bbar - Abar x, g = G^T r_G, ghat = Ghat^T r_G with Ghat the FP32
+ * values the batch reads, and eta = |Abar^T rbar| / |Abar^T bbar|; it stops
+ * that right-hand side when eta <= tol (istop 1), after `sweeps` sweeps
+ * (istop 2) or when eta fails to halve between sweeps (istop 4).  The others
+ * are then solved together by the batched LSQR (at most `iters` iterations,
+ * relative tolerance inner_tol, every system in one captured graph) on the
+ * corrected right-hand side f = [r_G; r_L; r_D + (g - ghat) / damp], whose
+ * Ahat^T f equals Abar^T rbar, so the refinement's fixed point is the FP64
+ * least-squares solution; x += D y.  (The solver section of the paper; the
+ * problem of eq. (6) with the smoothing and damping blocks.)
+ *   arguments as lsqr_solve_batched, plus
+ *   tol        > 0, the FP64 stopping ratio of every right-hand side
+ *   inner_tol  in [0, 1): relative tolerance of each sweep's batched solve
+ *   sweeps     >= 1: most refinement sweeps
+ *   info       NULL or [nsys*nrhs]: istop as above (0: Abar^T bbar = 0),
+ *              iters = inner iterations over all sweeps, sweeps, eta and
+ *              eta_final_fp64 = the FP64 eta of the returned dm, phibar =
+ *              |rbar| of the returned dm
+ * Errors: as lsqr_solve_batched; INVALID_ARG for tol <= 0, inner_tol or
+ * sweeps out of range; UNSUPPORTED when a system has damp = 0.
+ */
+lsqr_status lsqr_solve_batched_refined(lsqr_ctx *const *ctxs, int nsys, int nrhs,
+                                       const double *const *dt, lsqr_mem vec_mem, int iters,
+                                       double tol, double inner_tol, int sweeps,
+                                       double *const *dm, lsqr_info *info);
+
+/*
  * lsqr_apply_block / lsqr_apply_t_block — the batched kernels as plain
  * products on nrhs (a power of two <= 32) row-major FP32 blocks of device
  * vectors: Y [m+2n][nrhs] = Abar D X [n][nrhs]; X = D Abar^T Y.  Enqueued only.

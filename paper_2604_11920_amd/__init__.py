@@ -5,7 +5,8 @@ in include/lsqr_mi355x.h); this package is the build script and a ctypes
 binding.
 """
 from .lsqr import (CSR, Info, LsqrError, Solver, Trainer, assemble_rays,  # noqa: F401
-                   header_functions, load, rays_size, solve_batched)
+                   header_functions, load, rays_size, solve_batched, solve_batched_refined)
 
 __all__ = ["Solver", "Trainer", "LsqrError", "load", "header_functions", "solve_batched",
+           "solve_batched_refined",
            "assemble_rays", "rays_size"]

@@ -94,6 +94,45 @@ int cap_blocks(int64_t work, int per, int cap)
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
 }
 
+// FP32 values of the transposed product four depths to a word (one 16-byte
+// load per lane and run), like the 16-bit codes; else depth pairs.
+#ifndef LSQR_F32_FOUR_DEPTHS
+#define LSQR_F32_FOUR_DEPTHS 1
+#endif
+constexpr bool kF32FourDepths = LSQR_F32_FOUR_DEPTHS;
+// 16-bit codes of the transposed product: depths per lane and load (4: one
+// 8-byte load, 8: one 16-byte load).
+#ifndef LSQR_Q_DEPTHS
+#define LSQR_Q_DEPTHS 4
+#endif
+constexpr int kQDepths = LSQR_Q_DEPTHS;
+
+// The node-run values of `src` (CSR order, elem_bytes each) in the layout of
+// W depths to a word: every run from a position that is a multiple of W,
+// zeros before its first depth's offset in the word and after its end, W
+// zeros after the last run; the layout's quarter offsets and destinations
+// are kept in the context.
+static lsqr_status build_four_depth(lsqr_ctx *c, const NodeRuns &NR, int nz, const void *src,
+                                    int elem_bytes, int W, void **out)
+{
+    hipStream_t st = c->st;
+    const int64_t nn = c->P.n / nz;
+    std::vector<uint32_t> dst4;
+    std::vector<int64_t> nvq4;
+    if (!pair_layout_host(NR, nn, dst4, nvq4, c->npad4, W))
+        return fail(c, LSQR_E_UNSUPPORTED, "the wide depth layout needs fewer than 2^32 padded values");
+    c->nvqp4 = ctx_alloc<int64_t>(c, 4 * nn + 1);
+    c->ndstp4 = ctx_alloc<uint32_t>(c, c->nnruns);
+    void *vals = ctx_alloc_bytes(c, (size_t)(c->npad4 + W) * elem_bytes);
+    if (!c->nvqp4 || !c->ndstp4 || !vals) return fail(c, LSQR_E_OOM, "device allocation failed");
+    *out = vals;
+    HIP_TRY(c, hipMemcpy(c->nvqp4, nvq4.data(), (4 * nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->ndstp4, dst4.data(), c->nnruns * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemsetAsync(vals, 0, (size_t)(c->npad4 + W) * elem_bytes, st));
+    launch_gather_runs(st, c->nnruns, c->nsrc, c->ndstp4, c->ndesc, src, vals, elem_bytes);
+    return LSQR_OK;
+}
+
 lsqr_status setup_engine(lsqr_ctx *c, Engine &E, int vec, const RowFmt &R, const ColFmt &C)
 {
     const int64_t m = c->P.m, n = c->P.n, mb = m + 2 * n;
@@ -750,7 +789,13 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             if (!c->nval32) return bail(LSQR_E_OOM, "device allocation failed");
             launch_convert_f32(st, nnz, c->nval, c->nval32);
             C.val = c->nval32;
-            if (c->nvalp) {
+            if (c->nvalp && kF32FourDepths) {   // four depths to a word (one 16-byte load)
+                lsqr_status q4 = build_four_depth(c, NR, G->nz, c->va32, 4, 4, (void **)&c->nvalp4f);
+                if (q4 != LSQR_OK) { const std::string m = c->err; return bail(q4, m); }
+                C.val = c->nvalp4f;
+                C.nvq = c->nvqp4;
+                C.pairs = 4;
+            } else if (c->nvalp) {
                 c->nvalp32 = ctx_alloc<float>(c, c->npad + 2);
                 if (!c->nvalp32) return bail(LSQR_E_OOM, "device allocation failed");
                 launch_convert_f32(st, c->npad + 2, c->nvalp, c->nvalp32);
@@ -787,23 +832,12 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             if (!c->nvalq) return bail(LSQR_E_OOM, "device allocation failed");
             launch_gather_runs(st, c->nnruns, c->nsrc, c->ndst, c->ndesc, c->qrow, c->nvalq, 2);
             C.val = c->nvalq;
-            if (c->nvalp) {   // the codes four depths to a word (one 8-byte load)
-                const int64_t nn = n / G->nz;
-                std::vector<uint32_t> dst4;
-                std::vector<int64_t> nvq4;
-                if (!pair_layout_host(NR, nn, dst4, nvq4, c->npad4, 4))
-                    return bail(LSQR_E_UNSUPPORTED, "the four-depth layout needs fewer than 2^32 padded values");
-                c->nvqp4 = ctx_alloc<int64_t>(c, 4 * nn + 1);
-                c->ndstp4 = ctx_alloc<uint32_t>(c, c->nnruns);
-                c->nvalpq = ctx_alloc<uint16_t>(c, c->npad4 + 4);
-                if (!c->nvqp4 || !c->ndstp4 || !c->nvalpq) return bail(LSQR_E_OOM, "device allocation failed");
-                CR_TRY(hipMemcpy(c->nvqp4, nvq4.data(), (4 * nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-                CR_TRY(hipMemcpy(c->ndstp4, dst4.data(), c->nnruns * sizeof(uint32_t), hipMemcpyHostToDevice));
-                CR_TRY(hipMemsetAsync(c->nvalpq, 0, (c->npad4 + 4) * sizeof(uint16_t), st));
-                launch_gather_runs(st, c->nnruns, c->nsrc, c->ndstp4, c->ndesc, c->qrow, c->nvalpq, 2);
+            if (c->nvalp) {   // the codes kQDepths depths to a word (one 8- or 16-byte load)
+                lsqr_status q4 = build_four_depth(c, NR, G->nz, c->qrow, 2, kQDepths, (void **)&c->nvalpq);
+                if (q4 != LSQR_OK) { const std::string m = c->err; return bail(q4, m); }
                 C.val = c->nvalpq;
                 C.nvq = c->nvqp4;
-                C.pairs = 4;
+                C.pairs = kQDepths;
             }
         }
         if (use_slices) {
@@ -1333,7 +1367,7 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
     out->staged_cols = E.R.slot ? c->ngcols : 0;
     out->padded_values = E.C.sl_ptr ? c->sl_total - c->P.nnz
                          : (E.C.nrp && E.C.pairs == 2) ? c->npad - c->P.nnz
-                         : (E.C.nrp && E.C.pairs == 4) ? c->npad4 - c->P.nnz : 0;
+                         : (E.C.nrp && E.C.pairs >= 4) ? c->npad4 - c->P.nnz : 0;
     if (E.C.sl_ptr) {
         // values and one row index per run (padding excluded), per slice its
         // offset and descriptor, per node its slice range and order entry

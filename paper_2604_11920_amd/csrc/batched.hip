@@ -116,7 +116,7 @@ lsqr_status ensure_batch(lsqr_ctx *c, hipStream_t st, int R, int iters)
         for (void *p : {(void *)B.T[0], (void *)B.T[1], (void *)B.V, (void *)B.Q, (void *)B.Z,
                         (void *)B.W, (void *)B.Y, (void *)B.rhs, (void *)B.dm, (void *)B.P1,
                         (void *)B.P2, (void *)B.P3, (void *)B.act, (void *)B.why, (void *)B.ctl,
-                        (void *)B.Pr})
+                        (void *)B.Pr, (void *)B.X, (void *)B.F, (void *)B.rsum})
             if (p) ctx_release(c, p);
         const int keep_rt = B.tuned ? B.rt : 0, keep_grid = B.tuned ? B.grid : 0;
         B = BatchEngine{};
@@ -163,11 +163,12 @@ lsqr_status ensure_batch(lsqr_ctx *c, hipStream_t st, int R, int iters)
     return LSQR_OK;
 }
 
-void batch_init(lsqr_ctx *c, hipStream_t st, double tol)
+void batch_init(lsqr_ctx *c, hipStream_t st, double tol, bool full = false)
 {
     BatchEngine &B = c->beng;
     BArgs a = base_args(c, B);
-    a.rhs = B.rhs; a.Tcur = B.T[0]; a.V = B.V; a.Y = B.Y; a.W = B.W; a.Zout = B.Z; a.Q = B.Q;
+    a.rhs = full ? B.F : B.rhs; a.rhs_full = full ? 1 : 0;
+    a.Tcur = B.T[0]; a.V = B.V; a.Y = B.Y; a.W = B.W; a.Zout = B.Z; a.Q = B.Q;
     a.tol = tol;
     a.part_out = B.P1;
     launch_tiled(st, 0, B.g_fwd, a, B.R, B.rt);
@@ -198,13 +199,35 @@ void batch_iter(lsqr_ctx *c, hipStream_t st, int p, double tol)
 
 __global__ void k_set_kmax(int *ctl, int kmax) { ctl[C_KMAX] = kmax; }
 
-}  // namespace
+// Column r of a row-major [rows][R] FP64 block: read into v, write from v
+// (v == nullptr: zeros), or add the whole block src to dst.
+__global__ void k_col_get(int64_t rows, int R, int r, const double *blk, double *v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = blk[i * R + r];
+}
 
-extern "C" {
+__global__ void k_col_put(int64_t rows, int R, int r, const double *v, double *blk)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        blk[i * R + r] = v ? v[i] : 0.0;
+}
 
-lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const double *const *dt,
-                               lsqr_mem vec_mem, int iters, double tol, double *const *dm,
-                               double *const *res_hist, lsqr_info *info)
+__global__ void k_blk_add(int64_t count, const double *src, double *dst)
+{
+#pragma clang fp contract(off)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = dst[i] + src[i];
+}
+
+int grid_for(int64_t work) { return cap(work, 256, 4096); }
+
+// Checks shared by the batched entry points.
+lsqr_status batch_args(lsqr_ctx *const *ctxs, int nsys, int nrhs, const double *const *dt,
+                       lsqr_mem vec_mem, int iters, double tol, double *const *dm)
 {
     if (!ctxs || nsys < 1) return fail(nullptr, LSQR_E_INVALID_ARG, "need at least one context");
     for (int s = 0; s < nsys; ++s)
@@ -219,20 +242,23 @@ lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const 
     for (int s = 0; s < nsys; ++s) {
         if (!dt[s] || !dm[s]) return fail(c0, LSQR_E_INVALID_ARG, "dt[s] and dm[s] must not be NULL");
         if (ctxs[s]->device != c0->device) return fail(c0, LSQR_E_INVALID_ARG, "contexts on different devices");
+        if (vec_mem == LSQR_MEM_HOST)
+            for (int64_t i = 0; i < ctxs[s]->P.m * (int64_t)nrhs; ++i)
+                if (!isfinite(dt[s][i])) return fail(c0, LSQR_E_NONFINITE, "non-finite value in dt");
     }
-    DeviceGuard dg(c0->device);
+    return LSQR_OK;
+}
+
+// Copies every system's [m][nrhs] right-hand sides into its padded [m][R]
+// block B.rhs (buffers for `iters` iterations made ready first).
+lsqr_status batch_load_rhs(lsqr_ctx *const *ctxs, int nsys, int nrhs, int R, const double *const *dt,
+                           lsqr_mem vec_mem, int iters)
+{
+    lsqr_ctx *c0 = ctxs[0];
     hipStream_t st = c0->st;
-    const int R = pow2_at_least(nrhs);
     const hipMemcpyKind kin = vec_mem == LSQR_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    const hipMemcpyKind kout = vec_mem == LSQR_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-    // the batch runs on the first context's stream, after each context's own work
-    for (int s = 1; s < nsys; ++s)
-        if (ctxs[s]->st != st) HIP_TRY(c0, hipStreamSynchronize(ctxs[s]->st));
     for (int s = 0; s < nsys; ++s) {
         lsqr_ctx *c = ctxs[s];
-        if (vec_mem == LSQR_MEM_HOST)
-            for (int64_t i = 0; i < c->P.m * (int64_t)nrhs; ++i)
-                if (!isfinite(dt[s][i])) return fail(c0, LSQR_E_NONFINITE, "non-finite value in dt");
         lsqr_status e = ensure_batch(c, st, R, iters);
         if (e != LSQR_OK) return fail(c0, e, c->err);
         BatchEngine &B = c->beng;
@@ -240,11 +266,25 @@ lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const 
         if (c->P.m > 0)
             HIP_TRY(c0, hipMemcpy2DAsync(B.rhs, R * sizeof(double), dt[s], nrhs * sizeof(double),
                                          nrhs * sizeof(double), c->P.m, kin, st));
-        batch_init(c, st, tol);
-        hipLaunchKernelGGL(k_set_kmax, dim3(1), dim3(1), 0, st, B.ctl, iters);
     }
     HIP_TRY(c0, hipGetLastError());
-    // iterations: a graph of `gb` iterations of every system, replayed
+    return LSQR_OK;
+}
+
+// Runs every system's batch from its start (B.rhs, or B.F when full) for up
+// to `iters` iterations: a captured graph of a block of iterations of all
+// systems, replayed while any right-hand side is active, then single
+// iterations; leaves dm = D y of every system in its B.dm.
+lsqr_status batch_run(lsqr_ctx *const *ctxs, int nsys, int nrhs, int R, int iters, double tol,
+                      bool full)
+{
+    lsqr_ctx *c0 = ctxs[0];
+    hipStream_t st = c0->st;
+    for (int s = 0; s < nsys; ++s) {
+        batch_init(ctxs[s], st, tol, full);
+        hipLaunchKernelGGL(k_set_kmax, dim3(1), dim3(1), 0, st, ctxs[s]->beng.ctl, iters);
+    }
+    HIP_TRY(c0, hipGetLastError());
     int done = 0;
     bool stopped = false;
     std::vector<int> hact((size_t)R);
@@ -289,14 +329,107 @@ lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const 
         ++done;
         if (tol > 0.0 && done % c0->check_every == 0 && done < iters && (e = poll()) != LSQR_OK) return e;
     }
-    // outputs
     for (int s = 0; s < nsys; ++s) {
         lsqr_ctx *c = ctxs[s];
         BatchEngine &B = c->beng;
         BArgs a = base_args(c, B);
         a.Y = B.Y; a.tol = tol; a.part_in = B.P3; a.np_in = B.g_upd;
         hipLaunchKernelGGL(k_bfinal, dim3(cap(c->P.n * R, kBlock, 1024)), dim3(kBlock), 0, st, a, B.dm);
-        HIP_TRY(c0, hipMemcpy2DAsync(dm[s], nrhs * sizeof(double), B.dm, R * sizeof(double),
+    }
+    HIP_TRY(c0, hipGetLastError());
+    return LSQR_OK;
+}
+
+// The state rows of system c's last batch run: per right-hand side r <
+// nrhs its stop reason, the last iteration it advanced (klast) and the rows
+// hs [(kdone + 1)][R][kStateWords]; err |= the device error flag.
+lsqr_status batch_state(lsqr_ctx *c0, lsqr_ctx *c, int nrhs, int &err, std::vector<int> &why,
+                        std::vector<int> &klast, std::vector<double> &hs, int &kdone)
+{
+    BatchEngine &B = c->beng;
+    const int R = B.R;
+    int ctl[C_WORDS];
+    why.assign((size_t)R, 0);
+    klast.assign((size_t)nrhs, 0);
+    HIP_TRY(c0, hipMemcpy(ctl, B.ctl, sizeof(ctl), hipMemcpyDeviceToHost));
+    HIP_TRY(c0, hipMemcpy(why.data(), B.why, R * sizeof(int), hipMemcpyDeviceToHost));
+    kdone = ctl[C_ITERS];
+    err |= ctl[C_ERR];
+    hs.assign((size_t)(kdone + 1) * R * kStateWords, 0.0);
+    HIP_TRY(c0, hipMemcpy(hs.data(), B.S, hs.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int r = 0; r < nrhs; ++r) {
+        int kl = 0;
+        for (int k = 1; k <= kdone; ++k) {
+            const double *Sk = hs.data() + ((size_t)k * R + r) * kStateWords;
+            const double *Sp = hs.data() + ((size_t)(k - 1) * R + r) * kStateWords;
+            if (Sk[S_PHIBAR] != Sp[S_PHIBAR] || Sk[S_PSI] != Sp[S_PSI]) kl = k;
+        }
+        if (why[r] == 0) kl = 0;
+        if (why[r] == 2) kl = kdone;
+        klast[(size_t)r] = kl;
+    }
+    return LSQR_OK;
+}
+
+// FP64 refinement scratch of a context (allocated on first use).
+lsqr_status ensure_refine_buffers(lsqr_ctx *c)
+{
+    const int64_t m = c->P.m, n = c->P.n, mb = m + 2 * n;
+    if (!c->xbuf) c->xbuf = ctx_alloc<double>(c, n);
+    if (!c->rbar) c->rbar = ctx_alloc<double>(c, mb);
+    if (!c->gbuf) c->gbuf = ctx_alloc<double>(c, n);
+    if (!c->ghat) c->ghat = ctx_alloc<double>(c, n);
+    if (!c->fbuf) c->fbuf = ctx_alloc<double>(c, mb);
+    BatchEngine &B = c->beng;
+    if (!B.X) B.X = ctx_alloc<double>(c, n * B.R);
+    if (!B.F) B.F = ctx_alloc<double>(c, mb * B.R);
+    if (!B.rsum) B.rsum = ctx_alloc<double>(c, (size_t)4 * B.R);
+    if (!c->xbuf || !c->rbar || !c->gbuf || !c->ghat || !c->fbuf || !B.X || !B.F || !B.rsum)
+        return fail(c, LSQR_E_OOM, "device allocation failed");
+    return LSQR_OK;
+}
+
+// The transposed product over the FP32 values the batch reads (node runs
+// when present, else the CSC), for FP64 vectors: ghat = Ghat^T r_G.
+ColFmt fp32_col_format(const lsqr_ctx *c)
+{
+    ColFmt F = c->C64;                 // the FP64 CSC structure
+    F.vt = VT_F32;
+    F.pairs = 0;
+    F.sl_ptr = nullptr;
+    F.mmask = nullptr;
+    F.xcd_bands = 0;
+    F.val = c->cv32;
+    if (c->nval32) {                   // the plain node runs the batch reads
+        F.nrp = c->nrp; F.nvq = c->nvq; F.nrow = c->nrow; F.ndesc = c->ndesc;
+        F.norder = c->norder; F.val = c->nval32;
+    }
+    return F;
+}
+
+}  // namespace
+
+extern "C" {
+
+lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const double *const *dt,
+                               lsqr_mem vec_mem, int iters, double tol, double *const *dm,
+                               double *const *res_hist, lsqr_info *info)
+{
+    lsqr_status e = batch_args(ctxs, nsys, nrhs, dt, vec_mem, iters, tol, dm);
+    if (e != LSQR_OK) return e;
+    lsqr_ctx *c0 = ctxs[0];
+    DeviceGuard dg(c0->device);
+    hipStream_t st = c0->st;
+    const int R = pow2_at_least(nrhs);
+    const hipMemcpyKind kout = vec_mem == LSQR_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    // the batch runs on the first context's stream, after each context's own work
+    for (int s = 1; s < nsys; ++s)
+        if (ctxs[s]->st != st) HIP_TRY(c0, hipStreamSynchronize(ctxs[s]->st));
+    if ((e = batch_load_rhs(ctxs, nsys, nrhs, R, dt, vec_mem, iters)) != LSQR_OK) return e;
+    if ((e = batch_run(ctxs, nsys, nrhs, R, iters, tol, false)) != LSQR_OK) return e;
+    for (int s = 0; s < nsys; ++s) {
+        lsqr_ctx *c = ctxs[s];
+        HIP_TRY(c0, hipMemcpy2DAsync(dm[s], nrhs * sizeof(double), c->beng.dm, R * sizeof(double),
                                      nrhs * sizeof(double), c->P.n, kout, st));
     }
     HIP_TRY(c0, hipGetLastError());
@@ -304,30 +437,17 @@ lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const 
     int err = 0;
     for (int s = 0; s < nsys; ++s) {
         lsqr_ctx *c = ctxs[s];
-        BatchEngine &B = c->beng;
-        int ctl[C_WORDS];
-        std::vector<int> why((size_t)R), act((size_t)R);
-        HIP_TRY(c0, hipMemcpy(ctl, B.ctl, sizeof(ctl), hipMemcpyDeviceToHost));
-        HIP_TRY(c0, hipMemcpy(why.data(), B.why, R * sizeof(int), hipMemcpyDeviceToHost));
-        const int kdone = ctl[C_ITERS];
-        err |= ctl[C_ERR];
-        std::vector<double> hs((size_t)(kdone + 1) * R * kStateWords);
-        HIP_TRY(c0, hipMemcpy(hs.data(), B.S, hs.size() * sizeof(double), hipMemcpyDeviceToHost));
+        std::vector<int> why, klast;
+        std::vector<double> hs;
+        int kdone = 0;
+        if ((e = batch_state(c0, c, nrhs, err, why, klast, hs, kdone)) != LSQR_OK) return e;
         for (int r = 0; r < nrhs; ++r) {
-            // the last iteration this right-hand side actually advanced
-            int klast = 0;
-            for (int k = 1; k <= kdone; ++k) {
-                const double *Sk = hs.data() + ((size_t)k * R + r) * kStateWords;
-                const double *Sp = hs.data() + ((size_t)(k - 1) * R + r) * kStateWords;
-                if (Sk[S_PHIBAR] != Sp[S_PHIBAR] || Sk[S_PSI] != Sp[S_PSI]) klast = k;
-            }
-            if (why[r] == 0) klast = 0;
-            if (why[r] == 2) klast = kdone;
+            const int kl = klast[(size_t)r];
             if (res_hist && res_hist[s]) {
                 double *h = res_hist[s];
                 for (int k = 0; k <= iters; ++k)
                     for (int f = 0; f < 3; ++f) h[((size_t)k * nrhs + r) * 3 + f] = NAN;
-                for (int k = 0; k <= klast; ++k) {
+                for (int k = 0; k <= kl; ++k) {
                     const double *Sk = hs.data() + ((size_t)k * R + r) * kStateWords;
                     double *o = h + ((size_t)k * nrhs + r) * 3;
                     if (why[r] == 0) { o[0] = Sk[S_BETA]; o[1] = 0.0; o[2] = 0.0; break; }
@@ -336,17 +456,167 @@ lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const 
             }
             if (info) {
                 lsqr_info &I = info[(size_t)s * nrhs + r];
-                const double *Sk = hs.data() + ((size_t)klast * R + r) * kStateWords;
+                const double *Sk = hs.data() + ((size_t)kl * R + r) * kStateWords;
                 I.istop = why[r];
-                I.iters = klast;
+                I.iters = kl;
                 I.sweeps = 0;
                 I.fallback_used = c->fallback_used;
                 I.eta = why[r] == 0 ? 0.0 : Sk[S_ETA];
                 I.phibar = why[r] == 0 ? Sk[S_BETA] : Sk[S_PHIBAR];
+                I.eta_final_fp64 = NAN;
             }
         }
     }
     if (err) return fail(c0, LSQR_E_NONFINITE, "a solver scalar became non-finite");
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_solve_batched_refined(lsqr_ctx *const *ctxs, int nsys, int nrhs,
+                                       const double *const *dt, lsqr_mem vec_mem, int iters,
+                                       double tol, double inner_tol, int sweeps,
+                                       double *const *dm, lsqr_info *info)
+{
+    lsqr_status e = batch_args(ctxs, nsys, nrhs, dt, vec_mem, iters, tol, dm);
+    if (e != LSQR_OK) return e;
+    lsqr_ctx *c0 = ctxs[0];
+    if (!(tol > 0.0)) return fail(c0, LSQR_E_INVALID_ARG, "the refined batch needs tol > 0");
+    if (!(inner_tol >= 0.0 && inner_tol < 1.0))
+        return fail(c0, LSQR_E_INVALID_ARG, "inner_tol must be in [0, 1)");
+    if (sweeps < 1) return fail(c0, LSQR_E_INVALID_ARG, "sweeps must be >= 1");
+    for (int s = 0; s < nsys; ++s)
+        if (!(ctxs[s]->P.damp > 0.0))
+            return fail(c0, LSQR_E_UNSUPPORTED, "the refinement needs damp > 0 (its correction goes into the damping block)");
+    DeviceGuard dg(c0->device);
+    hipStream_t st = c0->st;
+    const int R = pow2_at_least(nrhs);
+    const hipMemcpyKind kout = vec_mem == LSQR_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    for (int s = 1; s < nsys; ++s)
+        if (ctxs[s]->st != st) HIP_TRY(c0, hipStreamSynchronize(ctxs[s]->st));
+    if ((e = batch_load_rhs(ctxs, nsys, nrhs, R, dt, vec_mem, iters)) != LSQR_OK) return e;
+    // per system and right-hand side: |Abar^T bbar|, eta, stop reason, work
+    const size_t NR = (size_t)nsys * nrhs;
+    std::vector<double> arnorm(NR, 0.0), eta(NR, INFINITY), eta_prev(NR, INFINITY), rn(NR, 0.0);
+    std::vector<int> istop(NR, 2), total(NR, 0), nsw(NR, 0), live(NR, 1);
+    std::vector<double> hsum((size_t)4 * R);
+    for (int s = 0; s < nsys; ++s) {
+        lsqr_ctx *c = ctxs[s];
+        if ((e = ensure_refine_buffers(c)) != LSQR_OK) return fail(c0, e, c->err);
+        BatchEngine &B = c->beng;
+        const Problem &P = c->P;
+        const int gadj = std::min(2048, c->eng.g_adj);
+        launch_fill(st, P.n * R, 0.0, B.X);
+        launch_fill(st, (P.m + 2 * P.n) * R, 0.0, B.F);
+        for (int r = 0; r < nrhs; ++r) {
+            if (P.m > 0)
+                hipLaunchKernelGGL(k_col_get, dim3(grid_for(P.m)), dim3(256), 0, st, P.m, R, r, B.rhs, c->dtbuf);
+            launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, nullptr, c->dtbuf, nullptr, c->gbuf, c->Pa,
+                       nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
+            launch_sum_partials(st, c->Pa, gadj, B.rsum + 4 * r);
+        }
+        HIP_TRY(c0, hipMemcpyAsync(hsum.data(), B.rsum, 4 * R * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(c0, hipStreamSynchronize(st));
+        for (int r = 0; r < nrhs; ++r) {
+            const size_t k = (size_t)s * nrhs + r;
+            arnorm[k] = sqrt(hsum[4 * (size_t)r]);
+            if (!(arnorm[k] > 0.0)) { istop[k] = 0; live[k] = 0; eta[k] = 0.0; }
+        }
+    }
+    for (int sw = 0;; ++sw) {
+        // FP64 residual of every live right-hand side and the next inner
+        // right-hand side f = [r_G; r_L; r_D + (g - ghat) / damp]
+        for (int s = 0; s < nsys; ++s) {
+            lsqr_ctx *c = ctxs[s];
+            BatchEngine &B = c->beng;
+            const Problem &P = c->P;
+            const int64_t mb = P.m + 2 * P.n;
+            const int gadj = std::min(2048, c->eng.g_adj);
+            const ColFmt C32 = fp32_col_format(c);
+            for (int r = 0; r < nrhs; ++r) {
+                const size_t k = (size_t)s * nrhs + r;
+                if (!live[k]) {
+                    hipLaunchKernelGGL(k_col_put, dim3(grid_for(mb)), dim3(256), 0, st, mb, R, r,
+                                       (const double *)nullptr, B.F);
+                    continue;
+                }
+                if (P.m > 0)
+                    hipLaunchKernelGGL(k_col_get, dim3(grid_for(P.m)), dim3(256), 0, st, P.m, R, r, B.rhs, c->dtbuf);
+                if (sw > 0) {
+                    hipLaunchKernelGGL(k_col_get, dim3(grid_for(P.n)), dim3(256), 0, st, P.n, R, r, B.X, c->xbuf);
+                    launch_fwd(st, P, c->eng.g_fwd, VT_F64, c->R64, c->xbuf, nullptr, c->ybuf, nullptr,
+                               c->Pf, nullptr, 0, nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
+                }
+                launch_residual(st, P, c->g_ref, c->dtbuf, sw > 0 ? c->ybuf : nullptr, c->rbar, nullptr,
+                                nullptr, c->Pr);
+                launch_sum_partials(st, c->Pr, c->g_ref, B.rsum + 4 * r + 1);
+                launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, nullptr, c->rbar, nullptr, c->gbuf,
+                           c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
+                launch_adj(st, P, gadj, VT_F64, C32, c->ones, nullptr, c->rbar, nullptr, c->ghat,
+                           c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
+                launch_form_rhs(st, P, c->g_ref, c->rbar, c->gbuf, c->ghat, c->fbuf, c->Pr);
+                launch_sum_partials(st, c->Pr, c->g_ref, B.rsum + 4 * r + 2);
+                hipLaunchKernelGGL(k_col_put, dim3(grid_for(mb)), dim3(256), 0, st, mb, R, r,
+                                   (const double *)c->fbuf, B.F);
+            }
+            HIP_TRY(c0, hipGetLastError());
+            HIP_TRY(c0, hipMemcpyAsync(hsum.data(), B.rsum, 4 * R * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIP_TRY(c0, hipStreamSynchronize(st));
+            for (int r = 0; r < nrhs; ++r) {
+                const size_t k = (size_t)s * nrhs + r;
+                if (!live[k]) continue;
+                rn[k] = sqrt(hsum[4 * (size_t)r + 1]);
+                eta[k] = sqrt(hsum[4 * (size_t)r + 2]) / arnorm[k];
+                if (!isfinite(eta[k])) return fail(c0, LSQR_E_NONFINITE, "refinement residual became non-finite");
+                if (eta[k] <= tol) { istop[k] = 1; live[k] = 0; }
+                else if (sw >= sweeps) { istop[k] = 2; live[k] = 0; }
+                else if (sw > 0 && eta[k] > 0.5 * eta_prev[k]) { istop[k] = 4; live[k] = 0; }
+                if (!live[k])          // no further correction for it
+                    hipLaunchKernelGGL(k_col_put, dim3(grid_for(mb)), dim3(256), 0, st, mb, R, r,
+                                       (const double *)nullptr, B.F);
+                eta_prev[k] = eta[k];
+            }
+        }
+        int any = 0;
+        for (size_t k = 0; k < NR; ++k) any |= live[k];
+        if (!any) break;
+        // inner batched LSQR on (Ahat D, f) for every right-hand side; x += D y
+        if ((e = batch_run(ctxs, nsys, nrhs, R, iters, inner_tol, true)) != LSQR_OK) return e;
+        int err = 0;
+        for (int s = 0; s < nsys; ++s) {
+            lsqr_ctx *c = ctxs[s];
+            BatchEngine &B = c->beng;
+            hipLaunchKernelGGL(k_blk_add, dim3(grid_for(c->P.n * R)), dim3(256), 0, st,
+                               c->P.n * (int64_t)R, (const double *)B.dm, B.X);
+            std::vector<int> why, klast;
+            std::vector<double> hs;
+            int kdone = 0;
+            if ((e = batch_state(c0, c, nrhs, err, why, klast, hs, kdone)) != LSQR_OK) return e;
+            for (int r = 0; r < nrhs; ++r) {
+                const size_t k = (size_t)s * nrhs + r;
+                if (!live[k]) continue;
+                total[k] += klast[(size_t)r];
+                nsw[k] += 1;
+            }
+        }
+        if (err) return fail(c0, LSQR_E_NONFINITE, "a solver scalar became non-finite");
+    }
+    for (int s = 0; s < nsys; ++s) {
+        lsqr_ctx *c = ctxs[s];
+        HIP_TRY(c0, hipMemcpy2DAsync(dm[s], nrhs * sizeof(double), c->beng.X, R * sizeof(double),
+                                     nrhs * sizeof(double), c->P.n, kout, st));
+    }
+    HIP_TRY(c0, hipGetLastError());
+    HIP_TRY(c0, hipStreamSynchronize(st));
+    if (info)
+        for (size_t k = 0; k < NR; ++k) {
+            lsqr_info &I = info[k];
+            I.istop = istop[k];
+            I.iters = total[k];
+            I.sweeps = nsw[k];
+            I.fallback_used = ctxs[k / nrhs]->fallback_used;
+            I.eta = eta[k];
+            I.phibar = rn[k];
+            I.eta_final_fp64 = eta[k];
+        }
     return LSQR_OK;
 }
 

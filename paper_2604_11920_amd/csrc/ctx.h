@@ -47,6 +47,11 @@ struct BatchEngine {
     int64_t s_rows = 0;
     int *act = nullptr, *why = nullptr, *ctl = nullptr;
     int tuned = 0;                 // 1 once rt/grid were chosen by the autotuner or the caller
+    // refinement (lsqr_solve_batched_refined): the solution, the inner
+    // right-hand sides, per-RHS reductions
+    double *X = nullptr;           // [n][R]
+    double *F = nullptr;           // [m+2n][R]
+    double *rsum = nullptr;        // [R][4]
 };
 
 }  // namespace lsqr
@@ -90,6 +95,7 @@ struct lsqr_ctx {
     int64_t nslices = 0, sl_total = 0; int sl_vt = -1;
     // the 16-bit codes in the four-depth layout (mixed forms)
     int64_t *nvqp4 = nullptr; uint32_t *ndstp4 = nullptr; int64_t npad4 = 0;
+    float *nvalp4f = nullptr;     // FP32 node-run values in the four-depth layout
     // row groups with local columns (forward product over va)
     int32_t *gp = nullptr, *gcol = nullptr; int64_t *gcp = nullptr; uint16_t *slot = nullptr;
     int ngroups = 0, gcap = 0;

@@ -160,11 +160,14 @@ struct ColFmt {
     const uint32_t *sl_row = nullptr;  // [64 nslices]
 };
 
-// Depths per lane load of the run-slice layout for a stored value type: one
-// 8-byte value, two 4-byte values, two 16-bit codes.
-inline int slice_width(int vt) { return vt == VT_F64 ? 1 : 2; }
+// Depths per lane and load of the run-slice kernel: 16-byte loads for FP64
+// and FP32 values, 8-byte loads for 16-bit codes.
+inline int slice_width(int vt) { return vt == VT_F64 ? 2 : 4; }
 // Compile-time bound on the depths of the run-slice kernel (>= nz <= 64).
-inline int slice_nzm(int nz) { return nz <= 8 ? 8 : nz <= 16 ? 16 : nz <= 24 ? 24 : nz <= 32 ? 32 : 64; }
+inline int slice_nzm(int nz)
+{
+    return nz <= 8 ? 8 : nz <= 12 ? 12 : nz <= 16 ? 16 : nz <= 20 ? 20 : nz <= 24 ? 24 : nz <= 32 ? 32 : 64;
+}
 
 // Type-dispatched launchers (kernels_f64.hip, kernels_f32.hip).
 void launch_init(hipStream_t st, const Problem &P, int grid, int vec, const double *rhs, int full,

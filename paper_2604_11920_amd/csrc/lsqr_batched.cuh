@@ -65,7 +65,8 @@ struct BArgs {
     float *Q;               // [n][R]
     double *W, *Y;          // [n][R]
     float *Zout;            // [n][R]
-    const double *rhs;      // [m][R] FP64 (init)
+    const double *rhs;      // [m][R] FP64 (init); [m+2n][R] with rhs_full
+    int rhs_full;           // 1: rhs holds every block of the right-hand side
     // partials [workgroup][R]
     double *part_out;
     const double *part_in;
@@ -121,7 +122,8 @@ __device__ __forceinline__ void block_sum_rhs(double v, double *accs, double *ou
 }
 
 // ----------------------------------------------------------------- init --
-// T0 = [rhs; 0; 0] for the tile's right-hand sides, y = v = 0, partials of |b|^2.
+// T0 = [rhs; 0; 0] (or the full rhs) for the tile's right-hand sides, y = v =
+// 0, partials of |b|^2.
 template <int RT>
 __global__ __launch_bounds__(kBlock) void k_binit(BArgs a)
 {
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_binit(BArgs a)
     for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < mb * RT;
          idx += (int64_t)gridDim.x * kBlock) {
         const int64_t i = idx / RT;
-        const double b = i < a.m ? a.rhs[i * a.R + c] : 0.0;
+        const double b = (a.rhs_full || i < a.m) ? a.rhs[i * a.R + c] : 0.0;
         a.Tcur[i * a.R + c] = (float)b;
         sq += b * b;
         if (i < a.n) { a.Y[i * a.R + c] = 0.0; a.V[i * a.R + c] = 0.0f; }

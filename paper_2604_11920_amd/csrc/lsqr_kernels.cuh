@@ -708,6 +708,13 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol(FwdArgs a)
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
 }
 
+// Pairs per lane and batch of k_fwd_lcol_pair.
+#ifdef LSQR_FWD_PAIR_U
+template <class M> struct PairU { static constexpr int value = LSQR_FWD_PAIR_U; };
+#else
+template <class M> struct PairU { static constexpr int value = 3; };
+#endif
+
 // See pair_batch.
 template <class M, class V>
 __global__ __launch_bounds__(kBlock) void k_fwd_lcol_pair(FwdArgs a)
@@ -761,7 +768,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol_pair(FwdArgs a)
         if (nrow < r1) { ns = ld_uniform(a.rp, nrow); ne = ld_uniform(a.rp, nrow + 1); }
         double up = iter ? (double)ld_uniform(tp, row) : 0.0;
         double sg = a.sigma ? (double)ld_uniform(a.sigma, row) : 1.0;
-        constexpr int UP = 3;
+        constexpr int UP = PairU<M>::value;
         constexpr int64_t BP = 128 * UP;
         int64_t jb = jr & ~(int64_t)1;
         PairBatch<M, UP> b0, b1;
@@ -1272,6 +1279,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
 // W = 4 for 16-bit codes).
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <class A, class M, int W>
 __device__ __forceinline__ void ld_word(const M *p, A (&x)[W])
 {
@@ -1279,19 +1288,29 @@ __device__ __forceinline__ void ld_word(const M *p, A (&x)[W])
         static_assert(W == 2, "FP64 values: pairs");
         const f64x2 v = __builtin_nontemporal_load((const f64x2 *)p);
         x[0] = (A)v.x; x[1] = (A)v.y;
+    } else if constexpr (sizeof(M) == 4 && W == 4) {       // FP32: four depths, 16 bytes
+        const f32x4 v = __builtin_nontemporal_load((const f32x4 *)p);
+        x[0] = (A)v.x; x[1] = (A)v.y; x[2] = (A)v.z; x[3] = (A)v.w;
     } else if constexpr (sizeof(M) == 4) {
-        static_assert(W == 2, "FP32 values: pairs");
+        static_assert(W == 2, "FP32 values: pairs or quads");
         const f32x2 v = __builtin_nontemporal_load((const f32x2 *)p);
         x[0] = (A)v.x; x[1] = (A)v.y;
     } else if constexpr (W == 2) {
         const uint32_t w = __builtin_nontemporal_load((const uint32_t *)p);
         x[0] = from_raw<A, M>((uint16_t)(w & 0xffffu));
         x[1] = from_raw<A, M>((uint16_t)(w >> 16));
-    } else {
-        static_assert(W == 4, "16-bit codes: pairs or quads");
+    } else if constexpr (W == 4) {
         const uint64_t w = __builtin_nontemporal_load((const uint64_t *)p);
 #pragma unroll
         for (int h = 0; h < 4; ++h) x[h] = from_raw<A, M>((uint16_t)(w >> (16 * h)));
+    } else {
+        static_assert(W == 8, "16-bit codes: two, four or eight depths");
+        const u32x4 w = __builtin_nontemporal_load((const u32x4 *)p);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            x[2 * h] = from_raw<A, M>((uint16_t)(w[h] & 0xffffu));
+            x[2 * h + 1] = from_raw<A, M>((uint16_t)(w[h] >> 16));
+        }
     }
 }
 
@@ -1306,14 +1325,28 @@ __device__ __forceinline__ void ld_word(const M *p, A (&x)[W])
 // the load, shuffle and multiply-add instructions per value of k_adj_nruns,
 // for about one padding element per run.  Per column the sum order is fixed
 // (chunks, runs of a group, groups, waves): no atomics.
-constexpr int kPairRunsPerGroup = 10;
+// Runs per group and chunk.  A chunk holds at most 64 runs (one descriptor
+// per lane), so with W = 4 (12 groups per wave at nz = 20) 6 runs per group
+// already cover it; more would only issue masked loads.
+#ifndef LSQR_PAIR_RPG2
+#define LSQR_PAIR_RPG2 10
+#endif
+#ifndef LSQR_PAIR_RPG4
+#define LSQR_PAIR_RPG4 6
+#endif
+#ifndef LSQR_PAIR_RPG8
+#define LSQR_PAIR_RPG8 4
+#endif
+template <int W> struct PairRPG {
+    static constexpr int value = W == 2 ? LSQR_PAIR_RPG2 : W == 4 ? LSQR_PAIR_RPG4 : LSQR_PAIR_RPG8;
+};
 
 template <class M, class V, int W>
 __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
 {
 #pragma clang fp contract(off)
     using A = typename AccOf<V>::type;
-    constexpr int RPG = kPairRunsPerGroup;
+    constexpr int RPG = PairRPG<W>::value;
     __shared__ double lds[4];
     __shared__ A wsum[kBlock / 64][64];
     double beta;
@@ -1379,6 +1412,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
                 const uint32_t p = __shfl(pk, r & 63);
                 const int iz0 = (int)((p >> 8) & 255u), lo = iz0 & ~(W - 1);
                 const bool in = live && r < nr && k2 >= lo && k2 < iz0 + (int)(p & 255u);
+                // a lane outside the run's window reads the quarter's first
+                // word (a line the wave streams anyway) and drops it
                 ld_word<A, M, W>(nv + (in ? vb + (int64_t)(p >> 16) + (k2 - lo) : vb), v[u]);
 #pragma unroll
                 for (int h = 0; h < W; ++h) v[u][h] = in ? v[u][h] : (A)0;
@@ -1424,73 +1459,92 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
 // Transposed product over run slices (see slice_layout_host).  A node's runs
 // are grouped by first depth and cut into slices of 64 runs, one run per
 // lane; a slice stores, for each step of W depths, the 64 lanes' W values
-// side by side, so every lane of a wave loads W values of its own run with
-// one contiguous wave-wide load and no lane idles on depths its run lacks
-// (slices hold runs of equal first depth and, after sorting by length,
-// nearly equal length; the shorter ones are padded with zeros).  A lane
-// gathers t for its run once and accumulates its values into per-depth
-// registers relative to the slice's first depth.  When the first depth
-// changes, and at the end of the node, each depth's register is summed over
-// the wave in a fixed butterfly and added to the column that depth maps to.
+// side by side, so one wave-wide load (16 bytes per lane for FP64 and FP32,
+// 8 for 16-bit codes) covers W depths of 64 runs with every lane busy
+// (slices hold runs of one first depth sorted by length, so only the last
+// W-step and the slices' length spread are padded with zeros).  A lane
+// gathers t for its run once per slice and accumulates W values per step
+// into per-depth registers relative to the slice's first depth; the step
+// count is uniform over the wave, every index into the registers is a
+// compile-time constant (no private memory).  When the first depth changes,
+// and at the end of the node, each depth register is summed over the wave
+// in a fixed butterfly and added to the lane that holds that depth's column.
 // One workgroup per node (nodes by decreasing work, boustrophedon over the
-// workgroups); wave w takes slices w, w + 4, ... of the node; per column
-// the sum runs over the wave's slices in order, then the lanes' fixed tree,
-// then the waves in order: deterministic, no atomics.  NZM >= nz bounds the
-// depth registers at compile time.
-template <class A, class M, int W>
-__device__ __forceinline__ void ld_step(const M *p, A (&x)[W])
-{
-    if constexpr (W == 1) x[0] = ld_nt<A>(p);
-    else ld_word<A, M, W>(p, x);
-}
+// workgroups); wave w takes slices w, w + 4, ... of the node; per column the
+// sum runs over the wave's slices in order, then the butterfly, then the
+// waves in order: deterministic, no atomics.  NZM >= nz (a multiple of W)
+// bounds the depth registers at compile time.
+template <class M> struct SliceW { static constexpr int value = sizeof(M) == 8 ? 2 : 4; };
 
-template <class A, class M, int W, int NS, int NZM>
-__device__ __forceinline__ void slice_steps(const M *p, A t, A (&acc)[NZM])
-{
-#pragma clang fp contract(off)
-    A v[NS][W];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) ld_step<A, M, W>(p + k * 64 * W, v[k]);
-#pragma unroll
-    for (int k = 0; k < NS; ++k)
-#pragma unroll
-        for (int h = 0; h < W; ++h) acc[k * W + h] = fma(v[k][h], t, acc[k * W + h]);
-}
-
-// the steps of one slice, ns = its padded length / W (uniform over the wave)
-template <class A, class M, int W, int NZM, int NS = 1>
-__device__ __forceinline__ void slice_dispatch(int ns, const M *p, A t, A (&acc)[NZM])
-{
-    if constexpr (NS * W <= NZM) {
-        if (ns == NS) {
-            slice_steps<A, M, W, NS, NZM>(p, t, acc);
-            return;
-        }
-        slice_dispatch<A, M, W, NZM, NS + 1>(ns, p, t, acc);
-    }
-}
-
-// adds the wave sums of acc[0 .. lmax) to the columns cls .. cls + lmax - 1
-// (lane iz holds column iz's running sum in col) and clears acc
 template <class A, int NZM>
-__device__ __forceinline__ void slice_flush(A (&acc)[NZM], int cls, int lmax, int lane, A &col)
+__device__ __forceinline__ void slice_flush(A (&acc)[NZM], int cls, int lane, A &col)
 {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int e = 0; e < NZM; ++e) {
-        if (e < lmax) {
-            const A r = group_sum<64>(acc[e]);
-            col = lane == cls + e ? col + r : col;
-        }
+        const A r = group_sum<64>(acc[e]);
+        col = lane == cls + e ? col + r : col;
         acc[e] = 0;
     }
 }
 
-template <class M, class V, int W, int NZM>
+// One slice's values (ns steps of W per lane; steps past ns read as zero)
+// and its t, issued together; consumed by slice_fma.
+template <class A, class M, int W, int NS>
+struct SliceBuf {
+    A v[NS][W];
+    A t;
+    int ns, iz0;
+};
+
+template <class A, class M, int W, int NS, class V>
+__device__ __forceinline__ void slice_issue(const AdjArgs &a, const M *sv, const V *Tg, int64_t sl,
+                                            uint32_t row, int lane, SliceBuf<A, M, W, NS> &b)
+{
+    const uint32_t d = a.sl_desc[sl];
+    b.iz0 = (int)(d >> 8);
+    b.ns = (int)(d & 255u) / W;
+    const M *p = sv + a.sl_off[sl] + lane * W;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        if (k < b.ns) {
+            ld_word<A, M, W>(p + k * 64 * W, b.v[k]);
+        } else {
+#pragma unroll
+            for (int h = 0; h < W; ++h) b.v[k][h] = 0;
+        }
+    }
+    b.t = (A)Tg[row];
+}
+
+template <class A, class M, int W, int NS, int NZM>
+__device__ __forceinline__ void slice_fma(const SliceBuf<A, M, W, NS> &b, A (&acc)[NZM], int &cls,
+                                          int lane, A &col)
+{
+#pragma clang fp contract(off)
+    if (b.iz0 != cls) {
+        if (cls >= 0) slice_flush<A, NZM>(acc, cls, lane, col);
+        cls = b.iz0;
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        if (k < b.ns) {
+#pragma unroll
+            for (int h = 0; h < W; ++h) acc[k * W + h] = fma(b.v[k][h], b.t, acc[k * W + h]);
+        }
+    }
+}
+
+// Two slices in flight per wave: the next slice's values and t are issued
+// before the current slice's multiply-adds (loads complete in issue order,
+// so the wait covers only the older slice).
+template <class M, class V, int NZM>
 __global__ __launch_bounds__(kBlock) void k_adj_slices(AdjArgs a)
 {
 #pragma clang fp contract(off)
     using A = typename AccOf<V>::type;
+    constexpr int W = SliceW<M>::value, NS = NZM / W;
+    static_assert(NZM % W == 0, "depth bound: a multiple of the step width");
     __shared__ double lds[4];
     __shared__ A wsum[kBlock / 64][64];
     double beta;
@@ -1510,27 +1564,28 @@ __global__ __launch_bounds__(kBlock) void k_adj_slices(AdjArgs a)
 #pragma unroll
         for (int e = 0; e < NZM; ++e) acc[e] = 0;
         A col = 0;
-        int cls = -1, lmax = 0;
+        int cls = -1;
+        SliceBuf<A, M, W, NS> b0, b1;
         uint32_t row = 0;
-        if (sl < s1) row = __builtin_nontemporal_load(a.sl_row + sl * 64 + lane);
-        for (; sl < s1; sl += 4) {
-            const uint32_t d = a.sl_desc[sl];
-            const int iz0 = (int)(d >> 8), len = (int)(d & 255u);
-            if (iz0 != cls) {
-                if (cls >= 0) slice_flush<A, NZM>(acc, cls, lmax, lane, col);
-                cls = iz0;
-                lmax = 0;
-            }
-            lmax = len > lmax ? len : lmax;
-            const A t = (A)Tg[row];
-            const M *p = sv + a.sl_off[sl] + lane * W;
-            // the next slice's rows, in flight while this slice's values load
-            uint32_t row_n = 0;
-            if (sl + 4 < s1) row_n = __builtin_nontemporal_load(a.sl_row + (sl + 4) * 64 + lane);
-            slice_dispatch<A, M, W, NZM>(len / W, p, t, acc);
-            row = row_n;
+        if (sl < s1) {
+            row = __builtin_nontemporal_load(a.sl_row + sl * 64 + lane);
+            slice_issue<A, M, W, NS, V>(a, sv, Tg, sl, row, lane, b0);
+            if (sl + 4 < s1) row = __builtin_nontemporal_load(a.sl_row + (sl + 4) * 64 + lane);
         }
-        if (cls >= 0) slice_flush<A, NZM>(acc, cls, lmax, lane, col);
+        // b0 holds slice sl (issued), row holds slice sl + 4's rows
+        while (sl < s1) {
+            const bool more1 = sl + 4 < s1;
+            if (more1) slice_issue<A, M, W, NS, V>(a, sv, Tg, sl + 4, row, lane, b1);
+            if (sl + 8 < s1) row = __builtin_nontemporal_load(a.sl_row + (sl + 8) * 64 + lane);
+            slice_fma<A, M, W, NS, NZM>(b0, acc, cls, lane, col);
+            if (!more1) break;
+            const bool more2 = sl + 8 < s1;
+            if (more2) slice_issue<A, M, W, NS, V>(a, sv, Tg, sl + 8, row, lane, b0);
+            if (sl + 12 < s1) row = __builtin_nontemporal_load(a.sl_row + (sl + 12) * 64 + lane);
+            slice_fma<A, M, W, NS, NZM>(b1, acc, cls, lane, col);
+            sl += 8;
+        }
+        if (cls >= 0) slice_flush<A, NZM>(acc, cls, lane, col);
         wsum[wid][lane] = col;
         __syncthreads();
         if (wid == 0 && lane < a.nz) {
@@ -1896,19 +1951,24 @@ static void adj_launch_m(hipStream_t st, int grid, const ColFmt &C, const AdjArg
         return;
     }
     if (C.sl_ptr) {
-        constexpr int W = sizeof(M) == 8 ? 1 : 2;
         switch (slice_nzm(a.nz)) {
-        case 8: hipLaunchKernelGGL((k_adj_slices<M, V, W, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 16: hipLaunchKernelGGL((k_adj_slices<M, V, W, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 24: hipLaunchKernelGGL((k_adj_slices<M, V, W, 24>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 32: hipLaunchKernelGGL((k_adj_slices<M, V, W, 32>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_adj_slices<M, V, W, 64>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_adj_slices<M, V, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 12: hipLaunchKernelGGL((k_adj_slices<M, V, 12>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 16: hipLaunchKernelGGL((k_adj_slices<M, V, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 20: hipLaunchKernelGGL((k_adj_slices<M, V, 20>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 24: hipLaunchKernelGGL((k_adj_slices<M, V, 24>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 32: hipLaunchKernelGGL((k_adj_slices<M, V, 32>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_adj_slices<M, V, 64>), dim3(grid), dim3(kBlock), 0, st, a); break;
         }
         return;
     }
     if (C.nrp) {
         if (C.pairs) {
             if constexpr (sizeof(M) == 2) {
+                if (C.pairs == 8) hipLaunchKernelGGL((k_adj_npair<M, V, 8>), dim3(grid), dim3(kBlock), 0, st, a);
+                else if (C.pairs == 4) hipLaunchKernelGGL((k_adj_npair<M, V, 4>), dim3(grid), dim3(kBlock), 0, st, a);
+                else hipLaunchKernelGGL((k_adj_npair<M, V, 2>), dim3(grid), dim3(kBlock), 0, st, a);
+            } else if constexpr (sizeof(M) == 4) {
                 if (C.pairs == 4) hipLaunchKernelGGL((k_adj_npair<M, V, 4>), dim3(grid), dim3(kBlock), 0, st, a);
                 else hipLaunchKernelGGL((k_adj_npair<M, V, 2>), dim3(grid), dim3(kBlock), 0, st, a);
             } else {
@@ -1928,8 +1988,8 @@ static void adj_launch_m(hipStream_t st, int grid, const ColFmt &C, const AdjArg
 }
 
 // The stored value types a vector type supports: FP64 vectors take FP64
-// values (and quantised values in the FP64 refinement products); FP32
-// vectors take FP32 and quantised values.
+// values (and, in the transposed product of the refinements, FP32 and
+// quantised values); FP32 vectors take FP32 and quantised values.
 template <class V> struct Wide { static constexpr bool value = false; };
 template <> struct Wide<double> { static constexpr bool value = true; };
 
@@ -2011,8 +2071,9 @@ int adj_nruns_blocks_per_cu(const ColFmt &C)
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     if (C.sl_ptr) {
-#define LSQR_SL_OCC(M_, NZM_) hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_slices<M_, V, (sizeof(M_) == 8 ? 1 : 2), NZM_>, kBlock, 0)
-#define LSQR_SL_OCCZ(M_) (slice_nzm(C.nzt) == 8 ? LSQR_SL_OCC(M_, 8) : slice_nzm(C.nzt) == 16 ? LSQR_SL_OCC(M_, 16) \
+#define LSQR_SL_OCC(M_, NZM_) hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_slices<M_, V, NZM_>, kBlock, 0)
+#define LSQR_SL_OCCZ(M_) (slice_nzm(C.nzt) == 8 ? LSQR_SL_OCC(M_, 8) : slice_nzm(C.nzt) == 12 ? LSQR_SL_OCC(M_, 12) \
+                          : slice_nzm(C.nzt) == 16 ? LSQR_SL_OCC(M_, 16) : slice_nzm(C.nzt) == 20 ? LSQR_SL_OCC(M_, 20) \
                           : slice_nzm(C.nzt) == 24 ? LSQR_SL_OCC(M_, 24) : slice_nzm(C.nzt) == 32 ? LSQR_SL_OCC(M_, 32) \
                           : LSQR_SL_OCC(M_, 64))
         switch (C.vt) {
@@ -2031,8 +2092,10 @@ int adj_nruns_blocks_per_cu(const ColFmt &C)
         return e == hipSuccess ? nb : 0;
     }
     if (!C.nrp || C.mmask) return 0;
-#define LSQR_ADJ_OCC(M_) (C.pairs == 4 && sizeof(M_) == 2                                                              \
-                              ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_npair<M_, V, (sizeof(M_) == 2 ? 4 : 2)>, kBlock, 0) \
+#define LSQR_ADJ_OCC(M_) (C.pairs == 8 && sizeof(M_) == 2                                                              \
+                              ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_npair<M_, V, (sizeof(M_) == 2 ? 8 : 2)>, kBlock, 0) \
+                          : C.pairs == 4 && sizeof(M_) <= 4                                                              \
+                              ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_npair<M_, V, (sizeof(M_) <= 4 ? 4 : 2)>, kBlock, 0) \
                           : C.pairs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_npair<M_, V, 2>, kBlock, 0) \
                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_nruns<M_, V>, kBlock, 0))
     switch (C.vt) {
@@ -2066,10 +2129,7 @@ hipError_t adj_launch(hipStream_t st, const Problem &P, int grid, const ColFmt &
         if constexpr (Wide<V>::value) adj_launch_m<double, V>(st, grid, C, a);
         else return hipErrorInvalidValue;
         break;
-    case VT_F32:
-        if constexpr (!Wide<V>::value) adj_launch_m<float, V>(st, grid, C, a);
-        else return hipErrorInvalidValue;
-        break;
+    case VT_F32: adj_launch_m<float, V>(st, grid, C, a); break;
     case VT_BF16: adj_launch_m<bf16_t, V>(st, grid, C, a); break;
     case VT_F16: adj_launch_m<fp16_t, V>(st, grid, C, a); break;
     default: return hipErrorInvalidValue;

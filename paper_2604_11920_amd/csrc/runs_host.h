@@ -457,18 +457,19 @@ inline bool build_row_groups_host(int64_t m, int64_t n, const int64_t *rp, const
     return true;
 }
 
-// Depth-pair layout of the node-run values (W = 2; W = 4 groups four depths
-// the same way): each run is stored from a position that is a multiple of W,
-// preceded by iz0 mod W zeros and followed by zeros up to a multiple of W, so
-// that depths Wk .. Wk+W-1 of a run share one aligned W-element word at run
-// start + Wk - (iz0 - iz0 mod W).  dst[r] = position of run r's first value;
-// nvq as in NodeRuns (the padded start of each quarter of a node's runs);
-// total = the padded length (a multiple of W).  Returns false when it does
-// not fit 32-bit positions or W is not 2 or 4.
+// Depth-pair layout of the node-run values (W = 2; W = 4 and W = 8 group
+// four and eight depths the same way): each run is stored from a position
+// that is a multiple of W, preceded by iz0 mod W zeros and followed by zeros
+// up to a multiple of W, so that depths Wk .. Wk+W-1 of a run share one
+// aligned W-element word at run start + Wk - (iz0 - iz0 mod W).  dst[r] =
+// position of run r's first value; nvq as in NodeRuns (the padded start of
+// each quarter of a node's runs); total = the padded length (a multiple of
+// W).  Returns false when it does not fit 32-bit positions or W is not 2, 4
+// or 8.
 inline bool pair_layout_host(const NodeRuns &R, int64_t nn, std::vector<uint32_t> &dst,
                              std::vector<int64_t> &nvq, int64_t &total, int W = 2)
 {
-    if (W != 2 && W != 4) return false;
+    if (W != 2 && W != 4 && W != 8) return false;
     const int64_t nr = R.nrp[(size_t)nn];
     dst.resize((size_t)nr);
     nvq.assign((size_t)(4 * nn + 1), 0);

@@ -111,6 +111,8 @@ def load():
         "lsqr_get_quantised": (I, [P, P, P, P]),
         "lsqr_solve_batched": (I, [ctypes.POINTER(P), I, I, ctypes.POINTER(P), I, I, D,
                                    ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(Info)]),
+        "lsqr_solve_batched_refined": (I, [ctypes.POINTER(P), I, I, ctypes.POINTER(P), I, I, D, D, I,
+                                           ctypes.POINTER(P), ctypes.POINTER(Info)]),
         "lsqr_apply_block": (I, [P, I, P, P]),
         "lsqr_apply_t_block": (I, [P, I, P, P]),
         "lsqr_set_batch_config": (I, [P, ctypes.POINTER(BatchCfg)]),
@@ -483,6 +485,37 @@ def solve_batched(solvers, dts, iters, tol=0.0, history=True):
         raise LsqrError(rc, lib.lsqr_last_error(solvers[0]._ctx).decode())
     out = [[infos[s * nrhs + r].as_dict() for r in range(nrhs)] for s in range(nsys)]
     return dms, hists, out
+
+
+def solve_batched_refined(solvers, dts, iters, tol, inner_tol=1e-4, sweeps=8):
+    """lsqr_solve_batched_refined: the batched solve with FP64 iterative
+    refinement per right-hand side (tol > 0).  dts as in solve_batched.
+    Returns (dms, infos)."""
+    lib = load()
+    nsys = len(solvers)
+    nrhs = int(dts[0].shape[1])
+    dev = _is_torch(dts[0])
+    if dev:
+        import torch
+        dts = [d.contiguous() for d in dts]
+        dms = [torch.empty((s.n, nrhs), dtype=torch.float64, device=dts[0].device) for s in solvers]
+    else:
+        dts = [np.ascontiguousarray(d, dtype=np.float64) for d in dts]
+        dms = [np.empty((s.n, nrhs)) for s in solvers]
+    for s, d in zip(solvers, dts):
+        assert tuple(d.shape) == (s.m, nrhs)
+    P = ctypes.c_void_p
+    ctxs = (P * nsys)(*[s._ctx.value for s in solvers])
+    dtp = (P * nsys)(*[_ptr(d).value for d in dts])
+    dmp = (P * nsys)(*[_ptr(d).value for d in dms])
+    infos = (Info * (nsys * nrhs))()
+    rc = lib.lsqr_solve_batched_refined(ctxs, nsys, nrhs, dtp, MEM_DEVICE if dev else MEM_HOST,
+                                        int(iters), float(tol), float(inner_tol), int(sweeps), dmp,
+                                        infos)
+    if rc != LSQR_OK:
+        raise LsqrError(rc, lib.lsqr_last_error(solvers[0]._ctx).decode())
+    out = [[infos[s * nrhs + r].as_dict() for r in range(nrhs)] for s in range(nsys)]
+    return dms, out
 
 
 class Trainer:

@@ -10,9 +10,9 @@
 //        (node runs built) int64 rrp[m+1]; uint32 rrid[nnruns]  (row order of the runs)
 //        int64 ok_groups, ngroups, ngcols; int32 gp[ngroups+1]; int64 gcp[ngroups+1];
 //        int32 gcol[ngcols]; uint16 slot[nnz]   (row groups of at most CAP columns)
-//        (node runs built, for W = 2 then W = 4) int64 ok_pairs, total; uint32 dstp[nnruns];
+//        (node runs built, for W = 2, 4 then 8) int64 ok_pairs, total; uint32 dstp[nnruns];
 //        int64 nvqp[4 nnodes+1]
-//        (node runs built, for W = 1 then W = 2) int64 nslices, total; int64 sptr[nnodes+1];
+//        (node runs built, for W = 1, 2 then 4) int64 nslices, total; int64 sptr[nnodes+1];
 //        int64 off[nslices]; uint16 desc[nslices]; uint32 row[64 nslices]; uint64 dst[nnruns]
 // usage: runs_check IN OUT [CAP]   (CAP defaults to 4096)
 #include <stdio.h>
@@ -96,7 +96,7 @@ int main(int argc, char **argv)
         put(fo, G.gp.data(), G.gp.size()); put(fo, G.gcp.data(), G.gcp.size());
         put(fo, G.gcol.data(), G.gcol.size()); put(fo, G.slot.data(), G.slot.size());
     }
-    for (int W : {2, 4}) {
+    for (int W : {2, 4, 8}) {
         if (!ok2) break;
         std::vector<uint32_t> dstp;
         std::vector<int64_t> nvqp;
@@ -106,7 +106,7 @@ int main(int argc, char **argv)
         put(fo, &total, 1);
         put(fo, dstp.data(), dstp.size()); put(fo, nvqp.data(), nvqp.size());
     }
-    for (int W : {1, 2}) {
+    for (int W : {1, 2, 4}) {
         if (!ok2) break;
         lsqr::RunSlices S;
         lsqr::slice_layout_host(R, nn, W, S);

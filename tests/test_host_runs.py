@@ -94,13 +94,13 @@ def run_builders(exe, tmp, row_ptr, col, n, nz, cap=4096):
         out["gcp"] = take(np.int64, ng5 + 1)
         out["gcol"] = take(np.int32, nc5)
         out["slot"] = take(np.uint16, len(col))
-    for W in ((2, 4) if ok2 else ()):
+    for W in ((2, 4, 8) if ok2 else ()):
         ok6, tot6 = take(np.int64, 2)
         out[f"pairs_ok{W}"] = bool(ok6)
         out[f"pad_total{W}"] = int(tot6)
         out[f"dstp{W}"] = take(np.uint32, nr2)
         out[f"nvqp{W}"] = take(np.int64, 4 * nn + 1)
-    for W in ((1, 2) if ok2 else ()):
+    for W in ((1, 2, 4) if ok2 else ()):
         nsl, tot = take(np.int64, 2)
         out[f"sl_total{W}"] = int(tot)
         out[f"sptr{W}"] = take(np.int64, nn + 1)
@@ -397,7 +397,8 @@ def test_row_groups_refused_for_a_row_above_the_cap(driver, tmp_path):
 
 
 def check_pair_layout(o, nz, W=2):
-    """Depth-pair (W = 2) and four-depth (W = 4) layouts: every run's depth
+    """Depth-pair (W = 2), four-depth (W = 4) and eight-depth (W = 8)
+    layouts: every run's depth
     iz sits at an index congruent to iz mod W (depths Wk .. Wk+W-1 share an
     aligned word), runs do not overlap, the padding is below W values on each
     side, and the quarter offsets are the padded starts of the quarters'
@@ -430,9 +431,9 @@ def test_pair_layout(driver, tmp_path):
               synth.random_system(300, 5, 4, 9, row_len=(0, 40), seed=9),
               synth.random_system(200, 3, 3, 1, row_len=(0, 6), seed=4)):
         o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
-        assert o["nodes_ok"] and o["pairs_ok2"] and o["pairs_ok4"]
-        check_pair_layout(o, s.nz, 2)
-        check_pair_layout(o, s.nz, 4)
+        assert o["nodes_ok"] and o["pairs_ok2"] and o["pairs_ok4"] and o["pairs_ok8"]
+        for W in (2, 4, 8):
+            check_pair_layout(o, s.nz, W)
 
 
 def check_slices(o, row_ptr, col, n, nz, W, rng):
@@ -498,7 +499,7 @@ def test_run_slices(driver, tmp_path):
                                              region=0.5, seed=2))
     o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
     assert o["nodes_ok"]
-    for W in (1, 2):
+    for W in (1, 2, 4):
         check_slices(o, s.row_ptr, s.col, s.n, s.nz, W, rng)
 
 
@@ -516,5 +517,5 @@ def test_run_slices_irregular_runs(driver, tmp_path):
     col = np.concatenate(rows).astype(np.int32)
     o = run_builders(driver, tmp_path, row_ptr, col, n, nz)
     assert o["nodes_ok"]
-    for W in (1, 2):
+    for W in (1, 2, 4):
         check_slices(o, row_ptr, col, n, nz, W, rng)
