@@ -1,0 +1,147 @@
+"""Full-size parity on the paper-shaped system (80x80x20 grid, 229 stations,
+26,106 pairs x 20 periods, bent rays, paths of >= 2 wavelengths; 594 M stored
+entries) against the oracle's stored results for it (tests/golden/
+cfg1_seed0.npz, written by tests/golden/make_cfg1_golden.py, which calls only
+oracle/), in the formats and launch configuration the benchmark times.
+
+* Fixed iteration counts (K = 3, 10, 30, 100, 300, no column scale).  The
+  oracle run twice, once with plain and once with Neumaier-compensated sums,
+  gives Delta_self(K): how far two valid summation orders of the same FP64
+  arithmetic drift apart after K iterations (LSQR's loss of orthogonality
+  amplifies last-bit differences).  The GPU's sums are a third order, so its
+  distance to the stored (compensated) iterate is held to the north-star
+  1e-10 where Delta_self is far below it, and to a small multiple of
+  Delta_self beyond that; the residual-norm history likewise.
+* Converged forms (against x*, the oracle's Jacobi-scaled LSQR with
+  compensated sums run to eta <= 1e-12): FP64 + Jacobi, BF16 and FP16 with
+  FP64 refinement, FP64 and BF16 with the learned column scale, each run to
+  eta <= TOL[precision] and held to 1e-5 relative; FP32 (no refinement) is
+  reported.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "cfg1_seed0.npz")
+ROOT = os.path.dirname(HERE)
+MODEL = os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp_cfg1.npz")
+
+# tolerances the converged forms run to: eta <= 1e-8 puts FP64 + Jacobi
+# within ~3e-6 of x* on this system; the 16-bit forms' refinement levels off
+# near eta = 3e-8 here (their FP32 inner vectors carry f ~ r*, whose rounding
+# bounds what a sweep can resolve), so they run to 5e-8, which leaves them
+# within ~3e-6 of x* as well
+TOL = {"fp64": 1e-8, "bf16": 5e-8, "fp16": 5e-8}
+
+
+@pytest.fixture(scope="module")
+def gold():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    z = np.load(GOLDEN, allow_pickle=False)
+    meta = json.loads(str(z["meta"]))
+    s = synth.make_system(synth.config1())
+    print(f"[cfg1-golden] m={s.m} n={s.n} nnz={s.nnz}", flush=True)
+    assert meta["fingerprint"] == synth.fingerprint(s), "the stored results describe another system"
+    return s, meta, {k: z[k] for k in z.files if k != "meta"}
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def plain(gold):
+    from paper_2604_11920_amd import Solver
+    s, _, _ = gold
+    sol = Solver.from_system(s)
+    yield sol
+    sol.close()
+
+
+def envelope(meta, K):
+    """max(1e-10, 20 Delta_self(K)): the benchmark spec's bound while the oracle's
+    own summation-order spread is far below it, a multiple of that spread
+    once LSQR's loss of orthogonality has amplified it."""
+    return max(1e-10, 20.0 * meta[f"delta_self_{K}"])
+
+
+@pytest.mark.parametrize("K", [3, 10, 30, 100, 300])
+def test_fixed_count_iterates(gold, plain, K):
+    s, meta, g = gold
+    ks = plain.kernel_stats()
+    assert ks["row_format"] == 4 and ks["col_format"] == 4     # the benchmark's formats
+    dm, hist, info = plain.solve(torch.from_numpy(s.dt).cuda(), K)
+    dm = dm.cpu().numpy()
+    e = rel(dm, g[f"x{K}_comp"])
+    print(f"[cfg1-golden] K={K}: |x - x_oracle| / |x_oracle| = {e:.3e} "
+          f"(Delta_self {meta[f'delta_self_{K}']:.3e})", flush=True)
+    assert info["iters"] == K and info["istop"] == 2
+    assert e <= envelope(meta, K)
+    if K == 300:
+        h = g["hist300_comp"]
+        dh = float(np.max(np.abs(hist[:, 0] - h[:, 0]) / h[:, 0]))
+        print(f"[cfg1-golden] K=300 residual-norm history: max rel diff {dh:.3e} "
+              f"(oracle's own {meta['hist_self_300']:.3e})", flush=True)
+        assert dh <= max(1e-10, 20.0 * meta["hist_self_300"])
+
+
+def _learned_scale(s):
+    from paper_2604_11920_amd import Solver, learned
+    model = learned.ColumnScaleModel.load(MODEL)
+    with Solver.from_system(s) as sol:
+        p = torch.from_numpy(np.ascontiguousarray(model.params, dtype=np.float32)).cuda()
+        return sol.mlp_scale(p, model.mean, model.std, centre=model.centre).cpu().numpy()
+
+
+FORMS = [("fp64", "jacobi"), ("bf16", "jacobi"), ("fp16", "jacobi"), ("fp64", "learned"),
+         ("bf16", "learned")]
+
+
+@pytest.mark.parametrize("prec,pc", FORMS)
+def test_converged_forms_reach_xstar(gold, prec, pc):
+    from paper_2604_11920_amd import Solver
+    s, meta, g = gold
+    assert meta["xstar_accepted"]
+    xs = g["x_star"]
+    kw = dict(precision=prec, refine_sweeps=10)
+    if pc == "learned":
+        kw.update(precond="user", col_scale=_learned_scale(s))
+    else:
+        kw.update(precond=pc)
+    with Solver.from_system(s, **kw) as sol:
+        dm, _, info = sol.solve(torch.from_numpy(s.dt).cuda(), 20000, tol=TOL[prec], history=False)
+    dm = dm.cpu().numpy()
+    e = rel(dm, xs)
+    print(f"[cfg1-golden] {prec}+{pc}: iters={info['iters']} sweeps={info['sweeps']} "
+          f"istop={info['istop']} eta_fp64={info['eta_final_fp64']:.2e} "
+          f"|x - x*| / |x*| = {e:.3e}", flush=True)
+    assert info["istop"] == 1 and info["eta_final_fp64"] <= TOL[prec]
+    assert not info["fallback_used"]
+    assert e <= 1e-5
+
+
+def test_fp32_error_reported(gold):
+    """FP32 values, vectors and sums (FP64 scalars), no refinement: the error
+    against the oracle's FP64 iterate at the same count and against x* is
+    reported; the check is only that FP32 rounding stays inside the spread
+    the FP64 summation orders themselves show at 300 iterations."""
+    from paper_2604_11920_amd import Solver
+    s, meta, g = gold
+    with Solver.from_system(s, precision="fp32") as sol:
+        dm, hist, info = sol.solve(torch.from_numpy(s.dt).cuda(), 300)
+    dm = dm.cpu().numpy()
+    e300, es = rel(dm, g["x300_comp"]), rel(dm, g["x_star"])
+    print(f"[cfg1-golden] fp32, 300 iterations: vs oracle x_300 {e300:.3e}, vs x* {es:.3e} "
+          f"(FP64 oracle x_300 vs x*: {rel(g['x300_comp'], g['x_star']):.3e})", flush=True)
+    assert info["iters"] == 300 and np.isfinite(dm).all()
+    assert e300 <= 20.0 * meta["delta_self_300"]
