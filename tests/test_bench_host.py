@@ -34,12 +34,17 @@ def test_pmc_summary_scales_by_the_calibration_kernel(tmp_path):
     # 2 GiB (FETCH) or 1 GiB (WRITE) gives factors 0.5 and 1.0
     gib_kib = float(1 << 30) / 1024.0
     fetch, write = str(tmp_path / "f.csv"), str(tmp_path / "w.csv")
+    # (other elementwise kernels, such as the random-number fill of the
+    # products mode, are not the calibration kernel)
+    calib = "void at::native::vectorized_elementwise_kernel<4, AUnaryFunctor<MulFunctor<double>>>"
     _write_counters(fetch, "FETCH_SIZE", [
-        ("void at::native::elementwise_kernel<copy>", 2 * gib_kib),
+        (calib, 2 * gib_kib),
+        ("void at::native::distribution_elementwise_grid_stride_kernel<float>", 31.0),
         ("lsqr::k_fwd_lcol<double, double>", 1000.0), ("lsqr::k_fwd_lcol<double, double>", 3000.0),
         ("lsqr::k_adj_npair<double, double, 2>", 500.0)])
     _write_counters(write, "WRITE_SIZE", [
-        ("void at::native::elementwise_kernel<copy>", gib_kib),
+        (calib, gib_kib),
+        ("void at::native::distribution_elementwise_grid_stride_kernel<float>", 9.0),
         ("lsqr::k_fwd_lcol<double, double>", 10.0), ("lsqr::k_fwd_lcol<double, double>", 30.0),
         ("lsqr::k_adj_npair<double, double, 2>", 4.0)])
     out = bench.pmc_summary(fetch, write, formats="4/4")
