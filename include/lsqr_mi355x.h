@@ -239,7 +239,9 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
  * j0[t] + b) of row (p, t): column node_k[a] nz + j0[t] + b, value
  * (-node_len[a] / cvel[t]) w[w_ptr[t] + b] (the traveltime sensitivity of
  * the synthetic generator, evaluated in this order in FP64).  All inputs are
- * host arrays (they are small next to G); outputs are device arrays.
+ * host arrays (they are small next to G) except node_k and node_len, which
+ * may be device arrays (node_mem, e.g. from lsqr_split_polylines); outputs
+ * are device arrays.
  */
 typedef struct {
     int64_t npairs;             /* paths                                                 */
@@ -254,7 +256,54 @@ typedef struct {
     const int64_t *w_ptr;       /* [nper+1] w_ptr[t+1] - w_ptr[t] == nj[t]                */
     const double *w;            /* [w_ptr[nper]] depth weights (finite)                   */
     const uint8_t *keep;        /* [npairs*nper] row (p, t) exists when nonzero           */
+    lsqr_mem node_mem;          /* where node_k and node_len live (LSQR_MEM_HOST = 0,     */
+                                /* the zero default, or LSQR_MEM_DEVICE: lsqr_rays_size  */
+                                /* does not read them; lsqr_assemble_rays checks them on */
+                                /* the device: nodes >= 0, lengths finite, columns below */
+                                /* 2^31)                                                 */
 } lsqr_rays;
+
+/*
+ * Ray polylines on the lateral grid, as a ray tracer hands them over (the
+ * rays of the travel-time step): per path its points and the length of each
+ * piece between consecutive points.  Node (ix, iy) sits at (ix h, iy h),
+ * k = iy nx + ix.  A piece may cross at most one grid line of each
+ * direction (|dx| < h and |dy| < h).
+ */
+typedef struct {
+    int64_t npaths;             /* paths                                                 */
+    int32_t nx, ny;             /* lateral nodes (>= 2 each)                             */
+    double h;                   /* node spacing (degrees, > 0)                           */
+    double km_per_deg;          /* length unit of the results (> 0)                      */
+    const int64_t *pt_ptr;      /* [npaths+1] path p owns points pt_ptr[p] .. pt_ptr[p+1]-1 */
+    const double *px, *py;      /* [pt_ptr[npaths]] point coordinates (degrees, finite)  */
+    const double *plen;         /* [pt_ptr[npaths]] length of the piece from point i to  */
+                                /* i + 1 (degrees, finite, >= 0); unused at a path's     */
+                                /* last point                                            */
+} lsqr_polylines;
+
+/*
+ * lsqr_split_polylines — the bilinear split of every path on the device
+ * (eq. (1)'s interpolation coefficients): each piece is cut where it crosses
+ * grid lines, the four bilinear corner weights are integrated exactly along
+ * every sub-piece (Simpson's rule; they are quadratic along it) and summed
+ * per node in the order the sub-pieces occur along the path; nodes with a
+ * positive integral are kept, ascending, with their lengths in km (length in
+ * degrees times km_per_deg).  The same arithmetic as the synthetic
+ * generator's split, so the result equals it to the bit.  One workgroup per
+ * path; at most 4096 corner records per path (4 per sub-piece) and 129
+ * contributions per node, else UNSUPPORTED.
+ *   node_ptr  host [npaths+1], always written: path p's nodes are
+ *             node_ptr[p] .. node_ptr[p+1]-1
+ *   node_k, node_len  NULL (sizes only), or device arrays of node_ptr[npaths]
+ *             entries (int32 node index, FP64 km), e.g. sized by a first call
+ * Inputs are staged in temporary device buffers from alloc (hipMalloc when
+ * alloc is NULL), returned before the call returns; work runs on `stream`.
+ * Errors: INVALID_ARG, NONFINITE, UNSUPPORTED, DEVICE, OOM.
+ */
+lsqr_status lsqr_split_polylines(const lsqr_polylines *poly, void *stream, lsqr_alloc_fn alloc,
+                                 lsqr_free_fn dealloc, void *alloc_user, int64_t *node_ptr,
+                                 int32_t *node_k, double *node_len);
 
 /* lsqr_rays_size — rows m and stored entries nnz of the assembled G (host
  * work only; validates the rays).  Errors: INVALID_ARG, NONFINITE (node_len

@@ -80,7 +80,14 @@ class Rays(ctypes.Structure):
                 ("node_ptr", ctypes.c_void_p), ("node_k", ctypes.c_void_p),
                 ("node_len", ctypes.c_void_p), ("cvel", ctypes.c_void_p),
                 ("j0", ctypes.c_void_p), ("nj", ctypes.c_void_p), ("w_ptr", ctypes.c_void_p),
-                ("w", ctypes.c_void_p), ("keep", ctypes.c_void_p)]
+                ("w", ctypes.c_void_p), ("keep", ctypes.c_void_p), ("node_mem", ctypes.c_int)]
+
+
+class Polylines(ctypes.Structure):
+    _fields_ = [("npaths", ctypes.c_int64), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("h", ctypes.c_double), ("km_per_deg", ctypes.c_double),
+                ("pt_ptr", ctypes.c_void_p), ("px", ctypes.c_void_p), ("py", ctypes.c_void_p),
+                ("plen", ctypes.c_void_p)]
 
 
 _lib = None
@@ -128,6 +135,8 @@ def load():
         "lsqr_rays_size": (I, [ctypes.POINTER(Rays), ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_int64)]),
         "lsqr_assemble_rays": (I, [ctypes.POINTER(Rays), P, _ALLOC_FN, _FREE_FN, P, P, P, P]),
+        "lsqr_split_polylines": (I, [ctypes.POINTER(Polylines), P, _ALLOC_FN, _FREE_FN, P, P, P,
+                                     P]),
         "lsqr_destroy": (None, [P]),
         "lsqr_status_string": (ctypes.c_char_p, [I]),
         "lsqr_last_error": (ctypes.c_char_p, [P]),
@@ -575,19 +584,23 @@ class Trainer:
             pass
 
 
-def _rays_struct(rays):
+def _rays_struct(rays, node_k=None, node_len=None, node_ptr=None):
     """ctypes view of a ray description (dict of numpy arrays, see synth's
-    System.rays); returns (struct, arrays kept alive)."""
-    keep = [np.ascontiguousarray(rays["node_ptr"], dtype=np.int64),
-            np.ascontiguousarray(rays["node_k"], dtype=np.int32),
-            np.ascontiguousarray(rays["node_len"], dtype=np.float64),
+    System.rays); returns (struct, arrays kept alive).  node_k / node_len /
+    node_ptr, when given, replace the dict's (node_k and node_len as device
+    tensors)."""
+    dev = node_k is not None
+    keep = [np.ascontiguousarray(rays["node_ptr"] if node_ptr is None else node_ptr, dtype=np.int64),
+            node_k if dev else np.ascontiguousarray(rays["node_k"], dtype=np.int32),
+            node_len if dev else np.ascontiguousarray(rays["node_len"], dtype=np.float64),
             np.ascontiguousarray(rays["cvel"], dtype=np.float64),
             np.ascontiguousarray(rays["j0"], dtype=np.int32),
             np.ascontiguousarray(rays["nj"], dtype=np.int32),
             np.ascontiguousarray(rays["w_ptr"], dtype=np.int64),
             np.ascontiguousarray(rays["w"], dtype=np.float64),
             np.ascontiguousarray(rays["keep"], dtype=np.uint8).reshape(-1)]
-    st = Rays(len(keep[0]) - 1, len(keep[3]), int(rays["nz"]), *[a.ctypes.data for a in keep])
+    st = Rays(len(keep[0]) - 1, len(keep[3]), int(rays["nz"]), *[_ptr(a) for a in keep],
+              MEM_DEVICE if dev else MEM_HOST)
     return st, keep
 
 
@@ -602,13 +615,59 @@ def rays_size(rays):
     return int(m.value), int(nnz.value)
 
 
-def assemble_rays(rays, stream=None):
-    """G assembled on the device from `rays`: (row_ptr, col, val) as torch
-    CUDA tensors (int64, int32, float64), ready for Solver(..., device G)."""
+def split_polylines(poly, stream=None):
+    """lsqr_split_polylines on the ray polylines `poly` (dict: pt_ptr, px, py,
+    plen, h, nx, ny, km_per_deg; see synth's System.rays["polyline"]):
+    (node_ptr numpy int64, node_k torch int32, node_len torch float64), the
+    node arrays on the device."""
     import torch
     lib = load()
-    m, nnz = rays_size(rays)
-    st, _keep = _rays_struct(rays)
+    keep = [np.ascontiguousarray(poly[k], dtype=np.int64 if k == "pt_ptr" else np.float64)
+            for k in ("pt_ptr", "px", "py", "plen")]
+    st = Polylines(len(keep[0]) - 1, int(poly["nx"]), int(poly["ny"]), float(poly["h"]),
+                   float(poly["km_per_deg"]), *[a.ctypes.data for a in keep])
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = stream or torch.cuda.current_stream()
+    alloc_cb, free_cb = torch_allocator(dev.index, stream)
+    node_ptr = np.empty(len(keep[0]), dtype=np.int64)
+    rc = lib.lsqr_split_polylines(ctypes.byref(st), stream.cuda_stream, alloc_cb, free_cb, None,
+                                  _ptr(node_ptr), None, None)
+    if rc != LSQR_OK:
+        raise LsqrError(rc, lib.lsqr_last_error(None).decode())
+    nn = int(node_ptr[-1])
+    node_k = torch.empty(max(nn, 1), dtype=torch.int32, device=dev)[:nn]
+    node_len = torch.empty(max(nn, 1), dtype=torch.float64, device=dev)[:nn]
+    rc = lib.lsqr_split_polylines(ctypes.byref(st), stream.cuda_stream, alloc_cb, free_cb, None,
+                                  _ptr(node_ptr), _ptr(node_k) if nn else None,
+                                  _ptr(node_len) if nn else None)
+    if rc != LSQR_OK:
+        raise LsqrError(rc, lib.lsqr_last_error(None).decode())
+    return node_ptr, node_k, node_len
+
+
+def assemble_polylines(rays, stream=None):
+    """G assembled on the device from the ray polylines: the bilinear split
+    (split_polylines) and the row assembly (lsqr_assemble_rays with the
+    node arrays left on the device).  `rays` as synth's System.rays (its
+    "polyline" entry and the per-period arrays).  Returns (row_ptr, col, val)
+    torch CUDA tensors."""
+    node_ptr, node_k, node_len = split_polylines(rays["polyline"], stream)
+    return assemble_rays(rays, stream, node_ptr=node_ptr, node_k=node_k, node_len=node_len)
+
+
+def assemble_rays(rays, stream=None, node_ptr=None, node_k=None, node_len=None):
+    """G assembled on the device from `rays`: (row_ptr, col, val) as torch
+    CUDA tensors (int64, int32, float64), ready for Solver(..., device G).
+    node_ptr / node_k / node_len (device tensors for the last two) replace
+    the dict's node arrays when given."""
+    import torch
+    lib = load()
+    st, _keep = _rays_struct(rays, node_k, node_len, node_ptr)
+    m, nnz = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib.lsqr_rays_size(ctypes.byref(st), ctypes.byref(m), ctypes.byref(nnz))
+    if rc != LSQR_OK:
+        raise LsqrError(rc, lib.lsqr_last_error(None).decode())
+    m, nnz = int(m.value), int(nnz.value)
     dev = torch.device("cuda", torch.cuda.current_device())
     rp = torch.empty(m + 1, dtype=torch.int64, device=dev)
     col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]

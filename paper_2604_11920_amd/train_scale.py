@@ -62,6 +62,8 @@ def family(name, first, count):
         return synth.learned_family_wide(first, count)
     if name == "cfg1large":
         return synth.learned_family_large(first, count)
+    if name in ("c17cfg0", "c17cfg1"):
+        return synth.c17_family(name[3:], first, count)
     raise SystemExit(f"unknown family {name}")
 
 
@@ -73,7 +75,7 @@ def cmd_search(args):
     for i, cfg in enumerate(family(args.family, args.first, args.count)):
         s = synth.make_system(cfg)
         f, t, theta, kj, kb = learned.search_targets(
-            s, tol=args.tol, family=args.param, rounds=args.rounds,
+            s, tol=args.tol, family=args.param, rounds=args.rounds, step=args.step,
             progress=log if s.nnz > 50_000_000 else None)
         feats.append(f.astype(np.float32))
         targets.append(t.astype(np.float32))
@@ -145,13 +147,15 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("search")
-    a.add_argument("--family", default="cfg0", choices=["cfg0", "cfg1", "cfg1large"])
+    a.add_argument("--family", default="cfg0", choices=["cfg0", "cfg1", "cfg1large", "c17cfg0", "c17cfg1"])
     a.add_argument("--first", type=int, default=1)
     a.add_argument("--count", type=int, default=160)
     a.add_argument("--tol", type=float, default=1e-6)
     a.add_argument("--param", default="depth", choices=["depth", "linear"],
                    help="target family: one log multiplier per depth layer, or linear in depth")
     a.add_argument("--rounds", type=int, default=2, help="coordinate-descent rounds (step halved)")
+    a.add_argument("--step", type=float, default=0.5,
+                   help="first round's step: candidates base + {-1, -1/2, 1/2, 1} x step")
     a.add_argument("--out", required=True)
     b = sub.add_parser("fit")
     b.add_argument("targets", nargs="+")
@@ -160,7 +164,7 @@ def main():
     b.add_argument("--out", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp.npz"))
     c = sub.add_parser("eval")
     c.add_argument("--model", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp.npz"))
-    c.add_argument("--family", default="cfg0", choices=["cfg0", "cfg1", "cfg1large"])
+    c.add_argument("--family", default="cfg0", choices=["cfg0", "cfg1", "cfg1large", "c17cfg0", "c17cfg1"])
     c.add_argument("--first", type=int, default=1001)
     c.add_argument("--count", type=int, default=20)
     c.add_argument("--tol", type=float, default=1e-6)

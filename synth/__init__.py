@@ -212,6 +212,28 @@ def learned_family_large(first_seed: int, count: int, stations=(100, 200), perio
     return learned_family_wide(first_seed, count, stations=stations, periods=periods, damp=damp)
 
 
+def c17_family(shape: str, first_seed: int, count: int) -> list[Config]:
+    """The learned scale's training and held-out systems: for every seed,
+    stations uniform in {30, ..., 229} and damping log-uniform in [0.05, 0.5]
+    (drawn from a generator of their own, so a system depends on its seed
+    only); shape "cfg0" keeps config 0's geometry (16x16x9 grid, 10 periods
+    2-20 s, straight rays), "cfg1" config 1's (80x80x20 grid, 20 periods 1-40 s,
+    bent rays, paths >= 2 wavelengths)."""
+    if shape not in ("cfg0", "cfg1"):
+        raise ValueError(shape)
+    out = []
+    for seed in range(first_seed, first_seed + count):
+        rng = np.random.default_rng(10_000 + seed)
+        ns = int(rng.integers(30, 230))
+        dp = float(np.exp(rng.uniform(np.log(0.05), np.log(0.5))))
+        c = config0(seed) if shape == "cfg0" else config1(seed=seed, n_stations=ns)
+        c.n_stations = ns
+        c.damp = dp
+        c.name = f"c17{shape}_s{ns}_d{dp:.3f}_seed{seed}"
+        out.append(c)
+    return out
+
+
 def small_config(nx=8, ny=8, nz=6, n_stations=12, n_periods=5, region=0.7, bent=True,
                  seed=0, damp=0.1, smooth=0.5, min_wavelengths=None) -> Config:
     """A reduced geometry with the same structure, for fast tests."""
@@ -505,6 +527,11 @@ def make_system(cfg: Config, threads: int | None = None) -> System:
     pt_ptr, px, py = polylines(a, b, cfg.h, R, bend)
     node_ptr, node_k, node_len, path_len = bilinear_split(pt_ptr, px, py, cfg.h, cfg.nx, cfg.ny)
     npairs = len(ia)
+    # the polylines as a ray tracer would hand them over: points and the
+    # length of every piece (point i to i + 1; unused at a path's last point)
+    plen = np.zeros(len(px))
+    plen[:-1] = np.hypot(px[1:] - px[:-1], py[1:] - py[:-1])
+    plen[pt_ptr[1:] - 1] = 0.0
     periods = np.asarray(cfg.periods, dtype=np.float64)
     cvel = phase_velocity(periods)
     lam = cvel * periods
@@ -562,7 +589,9 @@ def make_system(cfg: Config, threads: int | None = None) -> System:
                   damp=cfg.damp, smooth=cfg.smooth,
                   rays=dict(node_ptr=node_ptr, node_k=node_k, node_len=node_len, cvel=cvel,
                             j0=j0, nj=nj, w_ptr=w_ptr, w=wflat, keep=keep_u8.reshape(-1),
-                            nz=cfg.nz))
+                            nz=cfg.nz,
+                            polyline=dict(pt_ptr=pt_ptr, px=px, py=py, plen=plen, h=cfg.h,
+                                          nx=cfg.nx, ny=cfg.ny, km_per_deg=KM_PER_DEG)))
 
 
 # ----------------------------------------------------------------------------
