@@ -162,3 +162,21 @@ def multiplier(theta, xhat):
     """softplus(z): the learned multiplier of the Jacobi scale."""
     z, _ = forward(theta, xhat)
     return softplus(z)
+
+
+def multiplier_bf16(theta, xhat):
+    """softplus(z) of the reduced-precision inference: the parameters, the
+    standardised inputs and both layers' activations rounded to the nearest
+    BF16 value (ties to even), every product and sum exact up to FP64
+    rounding (the device accumulates in FP32)."""
+    from .quant import round_to_format
+
+    def b(a):
+        return round_to_format(np.asarray(a, dtype=np.float64), "bf16")
+
+    p = {k: b(v) for k, v in unpack(theta).items()}
+    x = b(xhat)
+    h1 = b(gelu(x @ p["W1"].T + p["b1"]))
+    h2 = b(gelu(h1 @ p["W2"].T + p["b2"]))
+    z = h2 @ p["W3"] + p["b3"][0]
+    return softplus(z)

@@ -1406,26 +1406,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
                 row_n = __builtin_nontemporal_load(a.nrow + nb + lane);
             }
             A v[RPG][W];
-            uint32_t inm = 0u;                // bit u: run slot u covers the lane's depths
 #pragma unroll
             for (int u = 0; u < RPG; ++u) {
                 const int r = grp + u * ngr;
                 const uint32_t p = __shfl(pk, r & 63);
                 const int iz0 = (int)((p >> 8) & 255u), lo = iz0 & ~(W - 1);
                 const bool in = live && r < nr && k2 >= lo && k2 < iz0 + (int)(p & 255u);
-                inm |= in ? (1u << u) : 0u;
                 // a lane outside the run's window reads the quarter's first
-                // word (a line the wave streams anyway); its t is taken as
-                // zero below, and the stored values are finite, so the
-                // products add zero
+                // word (a line the wave streams anyway) and drops it
                 ld_word<A, M, W>(nv + (in ? vb + (int64_t)(p >> 16) + (k2 - lo) : vb), v[u]);
+#pragma unroll
+                for (int h = 0; h < W; ++h) v[u][h] = in ? v[u][h] : (A)0;
             }
             A tr_n = 0;
             if (lane < nn) tr_n = (A)Tg[row_n];
 #pragma unroll
             for (int u = 0; u < RPG; ++u) {
-                const A t0 = __shfl(tr, (grp + u * ngr) & 63);
-                const A t = ((inm >> u) & 1u) ? t0 : (A)0;
+                const A t = __shfl(tr, (grp + u * ngr) & 63);
 #pragma unroll
                 for (int h = 0; h < W; ++h) acc[h] = fma(v[u][h], t, acc[h]);
             }

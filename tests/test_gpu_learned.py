@@ -1,9 +1,11 @@
 """GPU checks of the learned column scale.
 
 * Features (FP64 sums, stored FP32) match the oracle's features.
-* The training gradient (FP32) matches the oracle's FP64 gradient to 1e-4
-  relative; a few Adam steps on the GPU follow the oracle's Adam.
-* BF16 inference matches the FP64 reference multiplier to ~1e-2 relative, and
+* The training gradient (FP32) matches the oracle's FP64 gradient element by
+  element within an FP32 rounding bound; five Adam steps on the GPU follow
+  the oracle's Adam element by element.
+* BF16 inference matches the oracle's BF16 inference (the same roundings,
+  exact sums) at FP32 rounding level, and
   any learned scale leaves the solution unchanged (learned vs Jacobi at the
   tolerance: <= 1e-5, the judge), with the Jacobi fallback for bad scales.
 * If a trained model is present, it does not need more iterations than Jacobi
@@ -60,74 +62,135 @@ def batch(seed, B=512):
     return rng.standard_normal((B, 6)), rng.standard_normal(B) * 0.3
 
 
+U32 = 2.0 ** -24
+# a per-sample gradient entry passes through at most 6 + 64 + 64 FP32
+# products and sums and a few FP32 transcendental functions (erf, exp,
+# log1p: within a few ulps each), so its FP32 value lies within ~140 u of
+# the exact one relative to the magnitudes involved; 256 u leaves margin
+GRAD_U = 256 * U32
+
+
+def per_sample_abs(theta, x, t):
+    """sum over the batch of |per-sample contribution| to every gradient
+    entry (the oracle's gradient of one sample at a time, scaled as in the
+    batch mean)."""
+    B = len(t)
+    acc = np.zeros_like(theta)
+    for i in range(B):
+        _, gi = mlp.grad(theta, x[i:i + 1], t[i:i + 1])
+        acc += np.abs(gi) / B
+    return acc
+
+
 def test_training_gradient_matches_oracle():
+    """Element by element: |g_gpu - g| <= 256 u32 sum_i |g_i| + 1e-12 for
+    every parameter (the GPU sums the per-sample terms in FP64 in a fixed
+    order, so only their FP32 evaluation errs)."""
     from paper_2604_11920_amd import Trainer
     theta = mlp.init_params(5) + 0.05 * np.random.default_rng(1).standard_normal(mlp.NPARAMS)
     x, t = batch(2)
     L, g = mlp.grad(theta, x, t)
+    S = per_sample_abs(theta, x, t)
     tr = Trainer(theta.astype(np.float32), 512)
     gg, lg = tr.grad(torch.from_numpy(x.astype(np.float32)).cuda(),
                      torch.from_numpy(t.astype(np.float32)).cuda())
     gg = gg.cpu().numpy().astype(np.float64)
     tr.close()
+    err = np.abs(gg - g)
+    bound = GRAD_U * S + 1e-12
+    print(f"[learned] gradient: max err/bound {np.max(err / bound):.3f}, "
+          f"max rel err {np.max(err / np.maximum(np.abs(g), 1e-300)):.2e}", flush=True)
     assert abs(lg - L) <= 1e-5 * L
-    assert np.linalg.norm(gg - g) <= 1e-4 * np.linalg.norm(g)
+    assert np.all(err <= bound), int(np.argmax(err / bound))
 
 
 def test_adam_steps_follow_oracle():
+    """Element by element over 5 steps: each Adam step moves a parameter by
+    lr m^/(sqrt(v^) + eps), so a gradient error e per entry changes the step
+    by at most lr min(2, 4 e / |g|) (the ratio is bounded by 1 in size);
+    plus the FP32 rounding of the parameters."""
     from paper_2604_11920_amd import Trainer
     theta = mlp.init_params(7)
     tr = Trainer(theta.astype(np.float32), 512)
     m = np.zeros_like(theta)
     v = np.zeros_like(theta)
     th = theta.copy()
+    lr = 1e-3
+    bound = np.zeros_like(theta)
     for step in range(1, 6):
         x, t = batch(10 + step)
         _, g = mlp.grad(th, x, t)
-        th, m, v = mlp.adam_step(th, m, v, g, step, lr=1e-3)
+        e = GRAD_U * per_sample_abs(th, x, t) + 1e-12
+        bound += lr * np.minimum(2.0, 4.0 * e / np.maximum(np.abs(g), 1e-300))
+        bound += 2 * U32 * np.abs(th)
+        th, m, v = mlp.adam_step(th, m, v, g, step, lr=lr)
         tr.step(torch.from_numpy(x.astype(np.float32)).cuda(),
-                torch.from_numpy(t.astype(np.float32)).cuda(), 1e-3)
+                torch.from_numpy(t.astype(np.float32)).cuda(), lr)
     p = tr.params().astype(np.float64)
     tr.close()
+    err = np.abs(p - th)
+    print(f"[learned] adam: max err/bound {np.max(err / bound):.3f}, entries with a loose bound "
+          f"{np.mean(bound >= lr):.4f}", flush=True)
+    assert np.all(err <= bound), int(np.argmax(err / bound))
     assert np.linalg.norm(p - th) <= 1e-4 * np.linalg.norm(th - theta) + 1e-6
 
 
+def _bf16_check(d, ref, tag):
+    """The device's BF16 inference against the oracle's (same roundings,
+    exact sums): at FP32 rounding level (1e-5) except for the columns where
+    an FP32 sum and the exact one round to neighbouring BF16 values at one of
+    the 134 roundings on the way, which moves z by about one BF16 ulp of one
+    activation times its weight (< 1e-2 here)."""
+    r = np.abs(d / ref - 1)
+    close = np.mean(r <= 1e-5)
+    print(f"[learned] {tag}: median {np.median(r):.2e}, max {r.max():.2e}, within 1e-5: "
+          f"{close:.4f}", flush=True)
+    assert close >= 0.95 and r.max() <= 1e-2
+
+
 def test_bf16_inference_matches_reference(cfg0):
+    """Inference on the oracle's features (handed to the device in FP32, the
+    oracle evaluating the same FP32 values)."""
     s = cfg0
     theta = mlp.init_params(3) + 0.2 * np.random.default_rng(4).standard_normal(mlp.NPARAMS)
     feat = mlp.column_features(s.row_ptr, s.col, s.val, s.nx, s.ny, s.nz, s.damp, s.smooth)
-    mean, std = feat.mean(0), feat.std(0)
+    f32 = feat.astype(np.float32)
+    mean, std = feat.mean(0).astype(np.float32), feat.std(0).astype(np.float32)
     std[std == 0] = 1.0
     djac = oracle.Operator.from_system(s).jacobi()
-    ref = djac * mlp.multiplier(theta, (feat - mean) / std)
+    xhat = (f32.astype(np.float64) - mean.astype(np.float64)) / std.astype(np.float64)
+    ref = djac * mlp.multiplier_bf16(theta, xhat)
     with from_sys(s) as sol:
         p = torch.from_numpy(theta.astype(np.float32)).cuda()
-        d = sol.mlp_scale(p, mean.astype(np.float32), std.astype(np.float32)).cpu().numpy()
-    r = np.abs(d / ref - 1)
-    assert np.median(r) < 1e-2 and r.max() < 6e-2
+        d = sol.mlp_scale(p, mean, std, feat=torch.from_numpy(f32).cuda()).cpu().numpy()
+    _bf16_check(d, ref, "bf16 inference")
+    # against the unrounded FP64 network: the BF16 roundings themselves
+    r = np.abs(d / (djac * mlp.multiplier(theta, xhat)) - 1)
+    assert np.median(r) < 1e-2
 
 
 def test_bf16_inference_centred_features(cfg0):
     # flagged features are centred on the system's own means (computed by the
-    # library); the reference centres the oracle's FP64 features the same way
+    # library in FP64 from the FP32 features, then stored in FP32)
     s = cfg0
     theta = mlp.init_params(6) + 0.2 * np.random.default_rng(9).standard_normal(mlp.NPARAMS)
     feat = mlp.column_features(s.row_ptr, s.col, s.val, s.nx, s.ny, s.nz, s.damp, s.smooth)
+    f32 = feat.astype(np.float32)
     centre = (1 << 0) | (1 << 1) | (1 << 5)
-    mean, std = feat.mean(0) * 0.5, feat.std(0)
+    mean, std = (feat.mean(0) * 0.5).astype(np.float32), feat.std(0).astype(np.float32)
     std[std == 0] = 1.0
-    mu = mean.copy()
+    mu = mean.astype(np.float64)
     for f in range(6):
         if (centre >> f) & 1:
-            mu[f] = feat[:, f].mean()
+            mu[f] = float(np.float32(f32[:, f].astype(np.float64).mean()))
     djac = oracle.Operator.from_system(s).jacobi()
-    ref = djac * mlp.multiplier(theta, (feat - mu) / std)
+    xhat = (f32.astype(np.float64) - mu) / std.astype(np.float64)
+    ref = djac * mlp.multiplier_bf16(theta, xhat)
     with from_sys(s) as sol:
         p = torch.from_numpy(theta.astype(np.float32)).cuda()
-        d = sol.mlp_scale(p, mean.astype(np.float32), std.astype(np.float32),
+        d = sol.mlp_scale(p, mean, std, feat=torch.from_numpy(f32).cuda(),
                           centre=centre).cpu().numpy()
-    r = np.abs(d / ref - 1)
-    assert np.median(r) < 1e-2 and r.max() < 6e-2
+    _bf16_check(d, ref, "bf16 inference, centred features")
 
 
 def test_any_positive_scale_keeps_the_solution_and_bad_scales_fall_back(cfg0):

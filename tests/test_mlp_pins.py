@@ -131,3 +131,50 @@ def test_forward_of_a_hand_evaluated_network():
     # the loss against the exact target log(ln 2) is zero, against 0 it is log(ln 2)^2
     assert mlp.loss(theta, x, np.full(2, np.log(LN2))) < 1e-28
     assert abs(mlp.loss(theta, x, np.zeros(2)) - np.log(LN2) ** 2) < 1e-14
+
+
+def _bf16_bits(x):
+    """Nearest BF16 value of a double, ties to even, by integer arithmetic on
+    the FP32 bits (independent of oracle/quant.py); x must be an FP32 value
+    away from overflow."""
+    import struct
+    u = struct.unpack("<I", struct.pack("<f", x))[0]
+    assert struct.unpack("<f", struct.pack("<I", u))[0] == x
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    return struct.unpack("<f", struct.pack("<I", u))[0]
+
+
+def test_bf16_inference_hand_evaluated():
+    """One live path through the network (every other weight zero): a chain
+    of three roundings worked through by hand with math.erf and an
+    independent BF16 rounding of FP32 values."""
+    import math
+    p = {k: np.zeros_like(v) for k, v in mlp.unpack(mlp.init_params(0)).items()}
+    p["W1"][0, 0] = 1.5                     # BF16 values: exact
+    p["b1"][0] = -0.25
+    p["W2"][0, 0] = 0.75
+    p["b2"][0] = 0.125
+    p["W3"][0] = 2.0
+    p["b3"][0] = -0.5
+    theta = mlp.pack(p)
+    xin = 0.3                              # rounds to a BF16 value first
+
+    def g(v):
+        return 0.5 * v * (1.0 + math.erf(v / math.sqrt(2.0)))
+
+    def r(v):                             # via FP32 (no double rounding here:
+        return _bf16_bits(float(np.float32(v)))   # the inputs are far from ties)
+
+    x = r(xin)
+    h1 = r(g(1.5 * x - 0.25))
+    h2_0 = r(g(0.75 * h1 + 0.125))
+    h2_rest = r(g(0.0))                    # zero
+    z = 2.0 * h2_0 - 0.5 + 0.0 * h2_rest
+    expect = max(z, 0.0) + math.log1p(math.exp(-abs(z)))
+    xhat = np.zeros((1, mlp.NF))
+    xhat[0, 0] = xin
+    got = mlp.multiplier_bf16(theta, xhat)[0]
+    assert abs(got - expect) <= 1e-15 * expect
+    # and the rounding matters: the unrounded network differs
+    assert abs(mlp.multiplier(theta, xhat)[0] - expect) > 1e-5 * expect
