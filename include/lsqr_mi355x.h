@@ -324,12 +324,13 @@ lsqr_status lsqr_assemble_rays(const lsqr_rays *rays, void *stream, lsqr_alloc_f
 
 /*
  * lsqr_solve — run LSQR (Paige & Saunders) on bbar = [dt; 0; 0] from x0 = 0.
- * BF16/FP16 forms: each refinement sweep forms rbar = bbar - Abar dm, the
- * exact eta = |Abar^T rbar| / |Abar^T bbar| and g - ghat = (G - Ghat)^T r_G in
- * FP64, then runs the inner LSQR on [Ghat; w L; lambda I] D with right-hand
- * side [r_G; r_L; r_D + (g - ghat)/lambda] (so that its normal-equation
- * residual equals Abar^T rbar exactly) to the relative eta opts.refine_inner_tol
- * (default 1e-2), and adds
+ * BF16/FP16 forms: each refinement sweep forms rbar = bbar - Abar dm and
+ * Abar^T rbar in FP64 (FP64 values of G), the exact eta = |Abar^T rbar| /
+ * |Abar^T bbar|, then runs the inner LSQR on [Ghat; w L; lambda I] D with
+ * right-hand side [0; 0; (Abar^T rbar)/lambda] (whose image under the inner
+ * operator's transpose is Abar^T rbar exactly, and which, unlike rbar,
+ * vanishes at the solution, so its FP32 rounding does not bound eta) to the
+ * relative eta opts.refine_inner_tol (default 1e-2), and adds
  * the correction; the solve stops when eta <= tol (istop 1), after
  * opts.refine_sweeps sweeps (istop 2), or when a sweep fails to halve eta
  * (istop 4).
@@ -397,16 +398,16 @@ lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const 
  * per right-hand side, so that the FP32 values and vectors of the batch
  * still reach the FP64 solution.  Each sweep computes, for every right-hand
  * side that has not stopped, in FP64 with the FP64 operator: the residual
- * rbar = bbar - Abar x, g = G^T r_G, ghat = Ghat^T r_G with Ghat the FP32
- * values the batch reads, and eta = |Abar^T rbar| / |Abar^T bbar|; it stops
- * that right-hand side when eta <= tol (istop 1), after `sweeps` sweeps
- * (istop 2) or when eta fails to halve between sweeps (istop 4).  The others
- * are then solved together by the batched LSQR (at most `iters` iterations,
- * relative tolerance inner_tol, every system in one captured graph) on the
- * corrected right-hand side f = [r_G; r_L; r_D + (g - ghat) / damp], whose
- * Ahat^T f equals Abar^T rbar, so the refinement's fixed point is the FP64
- * least-squares solution; x += D y.  (The solver section of the paper; the
- * problem of eq. (6) with the smoothing and damping blocks.)
+ * rbar = bbar - Abar x, Abar^T rbar and eta = |Abar^T rbar| / |Abar^T bbar|;
+ * it stops that right-hand side when eta <= tol (istop 1), after `sweeps`
+ * sweeps (istop 2) or when eta fails to halve between sweeps (istop 4).  The
+ * others are then solved together by the batched LSQR (at most `iters`
+ * iterations, relative tolerance inner_tol, every system in one captured
+ * graph) on the right-hand side f = [0; 0; (Abar^T rbar) / damp], whose
+ * Ahat^T f equals Abar^T rbar for the FP32 values Ghat the batch reads, so
+ * the refinement's fixed point is the FP64 least-squares solution; x += D y.
+ * (The solver section of the paper; the problem of eq. (6) with the
+ * smoothing and damping blocks.)
  *   arguments as lsqr_solve_batched, plus
  *   tol        > 0, the FP64 stopping ratio of every right-hand side
  *   inner_tol  in [0, 1): relative tolerance of each sweep's batched solve

@@ -467,7 +467,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
 
     c->rp = ctx_alloc<int64_t>(c, m + 1);
     c->ci = ctx_alloc<int32_t>(c, nnz);
-    c->va = ctx_alloc<double>(c, nnz + 1);       // one zero past the end (paired loads)
+    c->va = ctx_alloc<double>(c, nnz + 4);       // zeros past the end (entries in pairs / quads)
     c->cp = ctx_alloc<int64_t>(c, n + 1);
     c->ri = ctx_alloc<int32_t>(c, nnz);
     c->cv = ctx_alloc<double>(c, nnz);
@@ -494,8 +494,8 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if (nnz > 0) {
         CR_TRY(hipMemcpyAsync(c->ci, G->col_idx, nnz * sizeof(int32_t), kind, st));
         CR_TRY(hipMemcpyAsync(c->va, G->val, nnz * sizeof(double), kind, st));
-        CR_TRY(hipMemsetAsync(c->va + nnz, 0, sizeof(double), st));
     }
+    CR_TRY(hipMemsetAsync(c->va + nnz, 0, 4 * sizeof(double), st));
     std::vector<int64_t> hrp;
     std::vector<int32_t> hci;
     const int64_t *hrow = G->row_ptr;
@@ -666,14 +666,14 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             c->gp = ctx_alloc<int32_t>(c, c->ngroups + 1);
             c->gcp = ctx_alloc<int64_t>(c, c->ngroups + 1);
             c->gcol = ctx_alloc<int32_t>(c, std::max<int64_t>(c->ngcols, 1));
-            c->slot = ctx_alloc<uint16_t>(c, nnz + 1);
+            c->slot = ctx_alloc<uint16_t>(c, nnz + 4);
             if (!c->gp || !c->gcp || !c->gcol || !c->slot) return bail(LSQR_E_OOM, "device allocation failed");
             CR_TRY(hipMemcpy(c->gp, RG.gp.data(), (c->ngroups + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
             CR_TRY(hipMemcpy(c->gcp, RG.gcp.data(), (c->ngroups + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
             if (c->ngcols)
                 CR_TRY(hipMemcpy(c->gcol, RG.gcol.data(), c->ngcols * sizeof(int32_t), hipMemcpyHostToDevice));
             CR_TRY(hipMemcpy(c->slot, RG.slot.data(), nnz * sizeof(uint16_t), hipMemcpyHostToDevice));
-            CR_TRY(hipMemset(c->slot + nnz, 0, sizeof(uint16_t)));
+            CR_TRY(hipMemset(c->slot + nnz, 0, 4 * sizeof(uint16_t)));
         }
     }
     // run masks of the data rows (index the CSR values directly)
@@ -721,7 +721,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if (use_runs) { c->R64.run_ptr = c->run_ptr; c->R64.runs = c->runs; c->R64.roff = c->roff; }
     if (c->slot) {
         c->R64.gp = c->gp; c->R64.gcp = c->gcp; c->R64.gcol = c->gcol; c->R64.slot = c->slot;
-        c->R64.ngroups = c->ngroups; c->R64.gcap = c->gcap; c->R64.padded = 1;
+        c->R64.ngroups = c->ngroups; c->R64.gcap = c->gcap; c->R64.padded = 4;
     }
     c->C64.vt = VT_F64; c->C64.cp = c->cp; c->C64.ri = c->ri; c->C64.val = c->cv;
     c->C64.lpc = o.lanes_per_col ? o.lanes_per_col : pick_lanes(avg_col);
@@ -777,10 +777,10 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         if (ss != LSQR_OK) return bail(ss, "run-slice values: device allocation or fill failed");
     }
     if (o.precision == LSQR_FP32) {
-        c->va32 = ctx_alloc<float>(c, nnz + 1);     // with va's padding element
+        c->va32 = ctx_alloc<float>(c, nnz + 4);     // with va's padding elements
         c->cv32 = ctx_alloc<float>(c, nnz);
         if (!c->va32 || !c->cv32) return bail(LSQR_E_OOM, "device allocation failed");
-        launch_convert_f32(st, nnz + 1, c->va, c->va32);
+        launch_convert_f32(st, nnz + 4, c->va, c->va32);
         launch_convert_f32(st, nnz, c->cv, c->cv32);
         R.vt = VT_F32; R.val = c->va32;
         C.vt = VT_F32; C.val = c->cv32;
@@ -810,19 +810,16 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     } else if (mixed) {
         const int vt = o.precision == LSQR_BF16 ? VT_BF16 : VT_F16;
         c->sigma = ctx_alloc<float>(c, std::max<int64_t>(m, 1));
-        c->qrow = ctx_alloc<uint16_t>(c, nnz + 1);  // one zero code past the end
+        c->qrow = ctx_alloc<uint16_t>(c, nnz + 4);  // zero codes past the end
         c->qcol = ctx_alloc<uint16_t>(c, nnz);
         c->xbuf = ctx_alloc<double>(c, n);
         c->rbar = ctx_alloc<double>(c, mb);
-        c->rs = ctx_alloc<double>(c, std::max<int64_t>(m, 1));
         c->gbuf = ctx_alloc<double>(c, n);
-        c->ghat = ctx_alloc<double>(c, n);
         c->fbuf = ctx_alloc<double>(c, mb);
-        if (!c->sigma || !c->qrow || !c->qcol || !c->xbuf || !c->rbar || !c->rs || !c->gbuf ||
-            !c->ghat || !c->fbuf)
+        if (!c->sigma || !c->qrow || !c->qcol || !c->xbuf || !c->rbar || !c->gbuf || !c->fbuf)
             return bail(LSQR_E_OOM, "device allocation failed");
         launch_row_scales(st, m, c->rp, c->va, vt, c->sigma);
-        CR_TRY(hipMemsetAsync(c->qrow + nnz, 0, sizeof(uint16_t), st));
+        CR_TRY(hipMemsetAsync(c->qrow + nnz, 0, 4 * sizeof(uint16_t), st));
         launch_quantise_rows(st, m, c->rp, c->va, c->sigma, vt, c->qrow);
         launch_quantise_cols(st, nnz, c->ri, c->cv, c->sigma, vt, c->qcol);
         R.vt = vt; R.val = c->qrow; R.sigma = c->sigma;
@@ -844,7 +841,6 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             lsqr_status ss = attach_slices(C, c->qrow, vt);
             if (ss != LSQR_OK) return bail(ss, "run-slice values: device allocation or fill failed");
         }
-        c->CQ = C;
         vec = VT_F32;
     }
     lsqr_status s = setup_engine(c, c->eng, vec, R, C);
@@ -880,11 +876,11 @@ static lsqr_status verify_eta(lsqr_ctx *c, const double *ddt, const double *ddm,
     if (!c->wr || !c->wg) return fail(c, LSQR_E_OOM, "device allocation failed");
     launch_fwd(st, P, c->eng.g_fwd, VT_F64, c->R64, ddm, nullptr, c->ybuf, nullptr, c->Pf, nullptr,
                0, nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
-    launch_residual(st, P, c->g_ref, ddt, c->ybuf, c->wr, nullptr, nullptr, c->Pr);
+    launch_residual(st, P, c->g_ref, ddt, c->ybuf, c->wr, c->Pr);
     launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, c->wr, c->wr, nullptr, c->wg, c->Pa, nullptr,
                0, nullptr, nullptr, 0, MODE_OPERATOR, 0);
     launch_sum_partials(st, c->Pa, gadj, c->sums + 0);
-    launch_residual(st, P, c->g_ref, ddt, nullptr, c->wr, nullptr, nullptr, c->Pr);
+    launch_residual(st, P, c->g_ref, ddt, nullptr, c->wr, c->Pr);
     launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, c->wr, c->wr, nullptr, c->wg, c->Pa, nullptr,
                0, nullptr, nullptr, 0, MODE_OPERATOR, 0);
     launch_sum_partials(st, c->Pa, gadj, c->sums + 1);
@@ -1052,12 +1048,11 @@ lsqr_status lsqr_solve_x0(lsqr_ctx *c, const double *dt, const double *x0, lsqr_
 }
 
 // Iterative refinement of the quantised forms.  Each sweep: rbar = bbar -
-// Abar x with the FP64 operator; g = G^T r_G (FP64 values) and ghat =
-// Ghat^T r_G (the quantised values, FP64 arithmetic); the exact eta =
+// Abar x with the FP64 operator; g = G^T r_G (FP64 values); the exact eta =
 // |Abar^T rbar| / |Abar^T bbar|; then an inner LSQR on the quantised
-// operator with right-hand side f = [r_G; r_L; r_D + (g - ghat)/lambda], for
-// which Ahat^T f = Abar^T rbar, so the refinement's fixed point is the FP64
-// solution; x += D y_inner.
+// operator with right-hand side f = [0; 0; (Abar^T rbar)/lambda], for which
+// Ahat^T f = Abar^T rbar, so the refinement's fixed point is the FP64
+// solution (and f, unlike rbar, vanishes there: see refine.hip); x += D y_inner.
 static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0, int iters,
                                double tol, double *ddm, double *res_hist, lsqr_info *info)
 {
@@ -1098,14 +1093,11 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0
             if (from_x)
                 launch_fwd(st, P, E.g_fwd, VT_F64, c->R64, c->xbuf, nullptr, c->ybuf, nullptr,
                            c->Pf, nullptr, 0, nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
-            launch_residual(st, P, c->g_ref, ddt, from_x ? c->ybuf : nullptr, c->rbar, c->sigma,
-                            c->rs, c->Pr);
+            launch_residual(st, P, c->g_ref, ddt, from_x ? c->ybuf : nullptr, c->rbar, c->Pr);
             launch_sum_partials(st, c->Pr, c->g_ref, c->sums + 1);
             launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, nullptr, c->rbar, nullptr, c->gbuf,
                        c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
-            launch_adj(st, P, gadj, VT_F64, c->CQ, c->ones, nullptr, c->rs, nullptr, c->ghat,
-                       c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
-            launch_form_rhs(st, P, c->g_ref, c->rbar, c->gbuf, c->ghat, c->fbuf, c->Pr);
+            launch_normal_rhs(st, P, c->g_ref, c->rbar, c->gbuf, c->fbuf, c->Pr);
             launch_sum_partials(st, c->Pr, c->g_ref, c->sums + 2);
             HIP_TRY(c, hipGetLastError());
             if ((s = fetch()) != LSQR_OK) return s;
@@ -1176,11 +1168,11 @@ static lsqr_status solve_warm(lsqr_ctx *c, const double *ddt, int iters, double 
     // r0 = bbar - Abar x0 and |Abar^T r0|; then bbar and |Abar^T bbar|
     launch_fwd(st, P, E.g_fwd, VT_F64, c->R64, ddm, nullptr, c->ybuf, nullptr, c->Pf, nullptr, 0,
                nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
-    launch_residual(st, P, c->g_ref, ddt, c->ybuf, c->wr, nullptr, nullptr, c->Pr);
+    launch_residual(st, P, c->g_ref, ddt, c->ybuf, c->wr, c->Pr);
     launch_adj(st, P, gadj, VT_F64, c->C64, dv, c->wr, c->wr, nullptr, c->wg, c->Pa, nullptr, 0,
                nullptr, nullptr, 0, MODE_OPERATOR, 0);
     launch_sum_partials(st, c->Pa, gadj, c->sums + 0);
-    launch_residual(st, P, c->g_ref, ddt, nullptr, c->ybuf, nullptr, nullptr, c->Pr);
+    launch_residual(st, P, c->g_ref, ddt, nullptr, c->ybuf, c->Pr);
     launch_adj(st, P, gadj, VT_F64, c->C64, dv, c->ybuf, c->ybuf, nullptr, c->wg, c->Pa, nullptr, 0,
                nullptr, nullptr, 0, MODE_OPERATOR, 0);
     launch_sum_partials(st, c->Pa, gadj, c->sums + 1);

@@ -378,33 +378,14 @@ lsqr_status ensure_refine_buffers(lsqr_ctx *c)
     if (!c->xbuf) c->xbuf = ctx_alloc<double>(c, n);
     if (!c->rbar) c->rbar = ctx_alloc<double>(c, mb);
     if (!c->gbuf) c->gbuf = ctx_alloc<double>(c, n);
-    if (!c->ghat) c->ghat = ctx_alloc<double>(c, n);
     if (!c->fbuf) c->fbuf = ctx_alloc<double>(c, mb);
     BatchEngine &B = c->beng;
     if (!B.X) B.X = ctx_alloc<double>(c, n * B.R);
     if (!B.F) B.F = ctx_alloc<double>(c, mb * B.R);
     if (!B.rsum) B.rsum = ctx_alloc<double>(c, (size_t)4 * B.R);
-    if (!c->xbuf || !c->rbar || !c->gbuf || !c->ghat || !c->fbuf || !B.X || !B.F || !B.rsum)
+    if (!c->xbuf || !c->rbar || !c->gbuf || !c->fbuf || !B.X || !B.F || !B.rsum)
         return fail(c, LSQR_E_OOM, "device allocation failed");
     return LSQR_OK;
-}
-
-// The transposed product over the FP32 values the batch reads (node runs
-// when present, else the CSC), for FP64 vectors: ghat = Ghat^T r_G.
-ColFmt fp32_col_format(const lsqr_ctx *c)
-{
-    ColFmt F = c->C64;                 // the FP64 CSC structure
-    F.vt = VT_F32;
-    F.pairs = 0;
-    F.sl_ptr = nullptr;
-    F.mmask = nullptr;
-    F.xcd_bands = 0;
-    F.val = c->cv32;
-    if (c->nval32) {                   // the plain node runs the batch reads
-        F.nrp = c->nrp; F.nvq = c->nvq; F.nrow = c->nrow; F.ndesc = c->ndesc;
-        F.norder = c->norder; F.val = c->nval32;
-    }
-    return F;
 }
 
 }  // namespace
@@ -523,14 +504,13 @@ lsqr_status lsqr_solve_batched_refined(lsqr_ctx *const *ctxs, int nsys, int nrhs
     }
     for (int sw = 0;; ++sw) {
         // FP64 residual of every live right-hand side and the next inner
-        // right-hand side f = [r_G; r_L; r_D + (g - ghat) / damp]
+        // right-hand side f = [0; 0; (Abar^T rbar) / damp] (refine.hip)
         for (int s = 0; s < nsys; ++s) {
             lsqr_ctx *c = ctxs[s];
             BatchEngine &B = c->beng;
             const Problem &P = c->P;
             const int64_t mb = P.m + 2 * P.n;
             const int gadj = std::min(2048, c->eng.g_adj);
-            const ColFmt C32 = fp32_col_format(c);
             for (int r = 0; r < nrhs; ++r) {
                 const size_t k = (size_t)s * nrhs + r;
                 if (!live[k]) {
@@ -545,14 +525,11 @@ lsqr_status lsqr_solve_batched_refined(lsqr_ctx *const *ctxs, int nsys, int nrhs
                     launch_fwd(st, P, c->eng.g_fwd, VT_F64, c->R64, c->xbuf, nullptr, c->ybuf, nullptr,
                                c->Pf, nullptr, 0, nullptr, nullptr, 0, 0.0, MODE_OPERATOR);
                 }
-                launch_residual(st, P, c->g_ref, c->dtbuf, sw > 0 ? c->ybuf : nullptr, c->rbar, nullptr,
-                                nullptr, c->Pr);
+                launch_residual(st, P, c->g_ref, c->dtbuf, sw > 0 ? c->ybuf : nullptr, c->rbar, c->Pr);
                 launch_sum_partials(st, c->Pr, c->g_ref, B.rsum + 4 * r + 1);
                 launch_adj(st, P, gadj, VT_F64, c->C64, c->ones, nullptr, c->rbar, nullptr, c->gbuf,
                            c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
-                launch_adj(st, P, gadj, VT_F64, C32, c->ones, nullptr, c->rbar, nullptr, c->ghat,
-                           c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 1);
-                launch_form_rhs(st, P, c->g_ref, c->rbar, c->gbuf, c->ghat, c->fbuf, c->Pr);
+                launch_normal_rhs(st, P, c->g_ref, c->rbar, c->gbuf, c->fbuf, c->Pr);
                 launch_sum_partials(st, c->Pr, c->g_ref, B.rsum + 4 * r + 2);
                 hipLaunchKernelGGL(k_col_put, dim3(grid_for(mb)), dim3(256), 0, st, mb, R, r,
                                    (const double *)c->fbuf, B.F);

@@ -54,6 +54,11 @@ struct BatchEngine {
     double *rsum = nullptr;        // [R][4]
 };
 
+// f = [0; 0; (Abar^T rbar) / damp] and the partials of |Abar^T rbar|^2: the
+// inner right-hand side of a refinement sweep (refine.hip).
+void launch_normal_rhs(hipStream_t st, const Problem &P, int grid, const double *rbar,
+                       const double *g, double *f, double *part);
+
 }  // namespace lsqr
 
 struct lsqr_ctx {
@@ -114,12 +119,11 @@ struct lsqr_ctx {
     float *va32 = nullptr, *cv32 = nullptr;
     float *sigma = nullptr;
     uint16_t *qrow = nullptr, *qcol = nullptr;
-    lsqr::ColFmt CQ;                // quantised transpose (FP64 refinement product)
     lsqr::Engine eng;               // the solver's kernel set
     lsqr::BatchEngine beng;         // the batched solver's buffers
     // refinement and operator scratch (FP64)
-    double *xbuf = nullptr, *ybuf = nullptr, *rbar = nullptr, *rs = nullptr, *gbuf = nullptr;
-    double *ghat = nullptr, *fbuf = nullptr, *Pr = nullptr, *Pa = nullptr, *Pf = nullptr;
+    double *xbuf = nullptr, *ybuf = nullptr, *rbar = nullptr, *gbuf = nullptr;
+    double *fbuf = nullptr, *Pr = nullptr, *Pa = nullptr, *Pf = nullptr;
     double *sums = nullptr;
     int g_ref = 1;
     double *dtbuf = nullptr, *dmbuf = nullptr;

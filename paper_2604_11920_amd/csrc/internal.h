@@ -108,15 +108,29 @@ struct RowFmt {
     const uint16_t *slot = nullptr;    // [nnz]
     int ngroups = 0;
     int gcap = 0;                      // columns per group at most (<= kLcolMaxCap)
-    int padded = 0;                    // 1: val and slot hold one more (zero) element
+    int padded = 0;                    // zero elements val and slot hold past the last entry
 };
 
-// The paired row-group kernel reads two values and two slots at a time from
-// even positions, and one element past the last entry (RowFmt::padded).
+// The row-group kernel with entries in pairs reads two values and two slots
+// at a time from even positions, and one element past the last entry
+// (RowFmt::padded).
 static inline bool lcol_pairs_ok(const RowFmt &R)
 {
     const uintptr_t w = 2 * (uintptr_t)vt_size(R.vt);
-    return R.padded && ((uintptr_t)R.val & (w - 1)) == 0 && ((uintptr_t)R.slot & 3u) == 0;
+    return R.padded >= 1 && ((uintptr_t)R.val & (w - 1)) == 0 && ((uintptr_t)R.slot & 3u) == 0;
+}
+
+// Entries in quads (4- and 2-byte values, when LSQR_FWD_QUADS is set): four
+// values and four slots from positions that are multiples of four, and up to
+// three elements past the last entry.
+#ifndef LSQR_FWD_QUADS
+#define LSQR_FWD_QUADS 0
+#endif
+static inline bool lcol_quads_ok(const RowFmt &R)
+{
+    const uintptr_t w = 4 * (uintptr_t)vt_size(R.vt);
+    return LSQR_FWD_QUADS && vt_size(R.vt) <= 4 && R.padded >= 3 && ((uintptr_t)R.val & (w - 1)) == 0 &&
+           ((uintptr_t)R.slot & 7u) == 0;
 }
 
 // Stored transpose (CSC) for the transposed product.
@@ -223,14 +237,9 @@ void launch_quantise_rows(hipStream_t st, int64_t m, const int64_t *rp, const do
                           const float *sigma, int vt, uint16_t *q);
 void launch_quantise_cols(hipStream_t st, int64_t nnz, const int32_t *ri, const double *cv,
                           const float *sigma, int vt, uint16_t *q);
-// refinement: rbar = bbar - y (FP64), rs = sigma * rbar_G; partials of |rbar|^2
+// rbar = bbar - y in FP64 (y = NULL: rbar = bbar); partials of |rbar|^2
 void launch_residual(hipStream_t st, const Problem &P, int grid, const double *dt,
-                     const double *y, double *rbar, const float *sigma, double *rs,
-                     double *part);
-// f = [r_G; r_L; r_D + (g - ghat)/lambda]; partials of |Abar^T rbar|^2 where
-// Abar^T rbar = g + w L r_L + lambda r_D
-void launch_form_rhs(hipStream_t st, const Problem &P, int grid, const double *rbar,
-                     const double *g, const double *ghat, double *f, double *part);
+                     const double *y, double *rbar, double *part);
 void launch_sum_partials(hipStream_t st, const double *part, int np, double *out);
 
 // Transpose (transpose.hip).

@@ -451,8 +451,7 @@ void launch_quantise_cols(hipStream_t st, int64_t nnz, const int32_t *ri, const 
 
 // ------------------------------------------------------------ refinement --
 __global__ __launch_bounds__(kBlock) void k_residual(int64_t m, int64_t n, const double *dt,
-                                                     const double *y, double *rbar,
-                                                     const float *sigma, double *rs, double *part)
+                                                     const double *y, double *rbar, double *part)
 {
 #pragma clang fp contract(off)
     __shared__ double lds[4];
@@ -463,7 +462,6 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t m, int64_t n, const
         const double b = i < m ? dt[i] : 0.0;
         const double r = y ? b - y[i] : b;
         rbar[i] = r;
-        if (rs && i < m) rs[i] = (double)sigma[i] * r;
         sq += r * r;
     }
     const double tot = block_sum(sq, lds);
@@ -471,39 +469,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t m, int64_t n, const
 }
 
 void launch_residual(hipStream_t st, const Problem &P, int grid, const double *dt,
-                     const double *y, double *rbar, const float *sigma, double *rs, double *part)
+                     const double *y, double *rbar, double *part)
 {
-    hipLaunchKernelGGL(k_residual, dim3(grid), dim3(kBlock), 0, st, P.m, P.n, dt, y, rbar, sigma,
-                       rs, part);
-}
-
-__global__ __launch_bounds__(kBlock) void k_form_rhs(int64_t m, int n, int nx, int ny, int nz,
-                                                     double w, double damp, const double *rbar,
-                                                     const double *g, const double *ghat,
-                                                     double *f, double *part)
-{
-#pragma clang fp contract(off)
-    __shared__ double lds[4];
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m + n;
-         i += (int64_t)gridDim.x * kBlock)
-        f[i] = rbar[i];
-    double sq = 0.0;
-    for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) {
-        const double rD = rbar[m + n + j];
-        f[m + n + j] = rD + (g[j] - ghat[j]) / damp;
-        const double lap = stencil<double>(rbar + m, j, nx, ny, nz);
-        const double at = g[j] + w * lap + damp * rD;
-        sq += at * at;
-    }
-    const double tot = block_sum(sq, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
-void launch_form_rhs(hipStream_t st, const Problem &P, int grid, const double *rbar,
-                     const double *g, const double *ghat, double *f, double *part)
-{
-    hipLaunchKernelGGL(k_form_rhs, dim3(grid), dim3(kBlock), 0, st, P.m, (int)P.n, P.nx, P.ny,
-                       P.nz, P.w, P.damp, rbar, g, ghat, f, part);
+    hipLaunchKernelGGL(k_residual, dim3(grid), dim3(kBlock), 0, st, P.m, P.n, dt, y, rbar, part);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_partials(const double *part, int np, double *out)

@@ -558,49 +558,61 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pipe(FwdArgs a)
 // loads of an empty row) are below gcap too, so every LDS read stays inside
 // the array; such entries are not summed.
 
-// Row groups, two entries per lane and load: a row's entries are taken in
-// aligned pairs (even positions p, p + 1; the first pair
-// of a row starting at an odd position holds the previous row's last entry,
-// the last pair may hold the next row's first or, at the end of the arrays,
-// the one padding element), so one load brings two values (16 bytes for
-// FP64, 8 for FP32, 4 for 16-bit codes) and one 4-byte load their two slots.  Entries outside the row are left out of the
-// sums.  Halves the load instructions per entry of k_fwd_lcol.
+// Row groups, E entries per lane and load (E = 2: pairs; E = 4: quads, for
+// 4- and 2-byte values): a row's entries are taken in aligned groups of E
+// (positions p .. p + E - 1, p a multiple of E; the first group of a row
+// that starts inside one holds entries of the previous row, the last may
+// hold the next row's first or, at the end of the arrays, padding elements),
+// so one load brings E values (pairs: 16 bytes for FP64, 8 for FP32, 4 for
+// 16-bit codes; quads: 16 bytes for FP32, 8 for 16-bit codes) and one load
+// their E 16-bit slots.  Entries outside the row are left out of the sums.
+// Pairs halve the load instructions per entry of k_fwd_lcol, quads halve
+// them again.
 typedef double f64x2p __attribute__((ext_vector_type(2)));
 typedef float f32x2p __attribute__((ext_vector_type(2)));
-// two raw stored values: one 16-, 8- or 4-byte word
-template <class M> struct PairRaw { using type = uint32_t; };
-template <> struct PairRaw<double> { using type = f64x2p; };
-template <> struct PairRaw<float> { using type = f32x2p; };
-template <class A, class M>
-__device__ __forceinline__ void pair_values(typename PairRaw<M>::type r, A &x0, A &x1)
+typedef float f32x4p __attribute__((ext_vector_type(4)));
+// E raw stored values in one word
+template <class M, int E> struct EntRaw { using type = uint32_t; };          // 2 x 16-bit
+template <> struct EntRaw<double, 2> { using type = f64x2p; };
+template <> struct EntRaw<float, 2> { using type = f32x2p; };
+template <> struct EntRaw<float, 4> { using type = f32x4p; };
+template <> struct EntRaw<bf16_t, 4> { using type = uint64_t; };
+template <> struct EntRaw<fp16_t, 4> { using type = uint64_t; };
+// E 16-bit slots in one word
+template <int E> struct SlotRaw { using type = uint32_t; };
+template <> struct SlotRaw<4> { using type = uint64_t; };
+template <class A, class M, int E>
+__device__ __forceinline__ void ent_values(typename EntRaw<M, E>::type r, A (&x)[E])
 {
     if constexpr (sizeof(M) >= 4) {
-        x0 = (A)r.x; x1 = (A)r.y;
+#pragma unroll
+        for (int k = 0; k < E; ++k) x[k] = (A)r[k];
     } else {
-        x0 = from_raw<A, M>((uint16_t)(r & 0xffffu));
-        x1 = from_raw<A, M>((uint16_t)(r >> 16));
+#pragma unroll
+        for (int k = 0; k < E; ++k) x[k] = from_raw<A, M>((uint16_t)((r >> (16 * k)) & 0xffffu));
     }
 }
-template <class M, int U>
-struct PairBatch {
-    uint32_t c[U];                       // two slots
-    typename PairRaw<M>::type r[U];      // two values
-    int64_t e0[U];                       // position of the pair's first entry
+template <class M, int U, int E>
+struct EntBatch {
+    typename SlotRaw<E>::type c[U];      // E slots
+    typename EntRaw<M, E>::type r[U];    // E values
+    int64_t e0[U];                       // position of the group's first entry
 };
-template <class M, int U>
-__device__ __forceinline__ void pair_batch(const FwdArgs &a, const M *va, int64_t jb, int64_t eb,
-                                           int lane, PairBatch<M, U> &b)
+template <class M, int U, int E>
+__device__ __forceinline__ void ent_batch(const FwdArgs &a, const M *va, int64_t jb, int64_t eb,
+                                          int lane, EntBatch<M, U, E> &b)
 {
-    // pairs p = jb + 2 lane + 128 u (jb even); a pair at or past eb loads the
-    // pair holding entry eb - 1 (else pair 0): in bounds, not summed
-    const int64_t safe = eb > 0 ? ((eb - 1) & ~(int64_t)1) : 0;
+    // groups p = jb + E lane + 64 E u (jb a multiple of E); a group at or
+    // past eb loads the group holding entry eb - 1 (else group 0): in
+    // bounds, not summed
+    const int64_t safe = eb > 0 ? ((eb - 1) & ~(int64_t)(E - 1)) : 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int64_t p = jb + 2 * lane + 128 * u;
+        const int64_t p = jb + E * lane + 64 * E * u;
         const int64_t pp = p < eb ? p : safe;
         b.e0[u] = p;
-        b.c[u] = __builtin_nontemporal_load((const uint32_t *)(a.slot + pp));
-        b.r[u] = __builtin_nontemporal_load((const typename PairRaw<M>::type *)(va + pp));
+        b.c[u] = __builtin_nontemporal_load((const typename SlotRaw<E>::type *)(a.slot + pp));
+        b.r[u] = __builtin_nontemporal_load((const typename EntRaw<M, E>::type *)(va + pp));
     }
 }
 
@@ -708,20 +720,18 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol(FwdArgs a)
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
 }
 
-// Pairs per lane and batch of k_fwd_lcol_pair.
+// Groups of E entries per lane and batch of k_fwd_lcol_pair.
 #ifdef LSQR_FWD_PAIR_U
-template <class M> struct PairU { static constexpr int value = LSQR_FWD_PAIR_U; };
+template <class M, int E> struct PairU { static constexpr int value = LSQR_FWD_PAIR_U; };
 #else
-template <class M> struct PairU { static constexpr int value = 3; };
+template <class M, int E> struct PairU { static constexpr int value = E == 2 ? 3 : 2; };
 #endif
 
-// See pair_batch.
-template <class M, class V>
+// See ent_batch.
+template <class M, class V, int E>
 __global__ __launch_bounds__(kBlock) void k_fwd_lcol_pair(FwdArgs a)
 {
     using A = typename AccOf<V>::type;
-    constexpr int U = PipeU<M>::value;
-    constexpr int64_t B = 64 * U;
     constexpr int SU = 8;                                 // staging loads in flight per thread
     __shared__ double lds[4];
     extern __shared__ double zdyn[];
@@ -768,30 +778,34 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol_pair(FwdArgs a)
         if (nrow < r1) { ns = ld_uniform(a.rp, nrow); ne = ld_uniform(a.rp, nrow + 1); }
         double up = iter ? (double)ld_uniform(tp, row) : 0.0;
         double sg = a.sigma ? (double)ld_uniform(a.sigma, row) : 1.0;
-        constexpr int UP = PairU<M>::value;
-        constexpr int64_t BP = 128 * UP;
-        int64_t jb = jr & ~(int64_t)1;
-        PairBatch<M, UP> b0, b1;
+        constexpr int UP = PairU<M, E>::value;
+        constexpr int64_t BP = 64 * E * UP;
+        constexpr int64_t AL = ~(int64_t)(E - 1);
+        int64_t jb = jr & AL;
+        EntBatch<M, UP, E> b0, b1;
         A acc[UP];
-        pair_batch<M, UP>(a, va, jb, e, lane, b0);
+        ent_batch<M, UP, E>(a, va, jb, e, lane, b0);
 #pragma unroll
         for (int u = 0; u < UP; ++u) acc[u] = 0;
-        auto step = [&](const PairBatch<M, UP> &cur, PairBatch<M, UP> &nxt) -> bool {
+        auto step = [&](const EntBatch<M, UP, E> &cur, EntBatch<M, UP, E> &nxt) -> bool {
             const bool last = jb + BP >= e;
-            const int64_t jn = last ? (ns & ~(int64_t)1) : jb + BP, en = last ? ne : e;
-            A z0[UP], z1[UP];
+            const int64_t jn = last ? (ns & AL) : jb + BP, en = last ? ne : e;
+            A zg[UP][E];
 #pragma unroll
-            for (int u = 0; u < UP; ++u) { z0[u] = zl[cur.c[u] & 0xffffu]; z1[u] = zl[cur.c[u] >> 16]; }
-            pair_batch<M, UP>(a, va, jn, en, lane, nxt);
+            for (int u = 0; u < UP; ++u)
+#pragma unroll
+                for (int k = 0; k < E; ++k) zg[u][k] = zl[(uint32_t)(cur.c[u] >> (16 * k)) & 0xffffu];
+            ent_batch<M, UP, E>(a, va, jn, en, lane, nxt);
 #pragma unroll
             for (int u = 0; u < UP; ++u) {
                 const int64_t p = cur.e0[u];
-                A x0, x1;
-                pair_values<A, M>(cur.r[u], x0, x1);
-                const A q0 = fma(x0, z0[u], acc[u]);
-                acc[u] = (p >= jr && p < e) ? q0 : acc[u];
-                const A q1 = fma(x1, z1[u], acc[u]);
-                acc[u] = (p + 1 >= jr && p + 1 < e) ? q1 : acc[u];
+                A x[E];
+                ent_values<A, M, E>(cur.r[u], x);
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const A q = fma(x[k], zg[u][k], acc[u]);
+                    acc[u] = (p + k >= jr && p + k < e) ? q : acc[u];
+                }
             }
             jb = jn;
             if (last) {
@@ -1355,7 +1369,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
     const V *Tg = (const V *)a.Tg;
     const int nz = a.nz, hz = (nz + W - 1) / W, ngr = 64 / hz;
     const int ch = ngr * RPG < 64 ? ngr * RPG : 64;       // runs per chunk
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // the wave index as a wave-uniform value: the quarter bounds, the value
+    // offset and the chunk loop are then scalar (BF16 codes: 459 -> 416 us on
+    // the paper-shaped system; FP64 and FP32 unchanged)
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int grp = lane / hz, k2 = W * (lane - grp * hz);  // the lane's depths k2 .. k2 + W - 1
     const bool live = grp < ngr;
     int G = gridDim.x, slot = blockIdx.x, nb0 = 0, nnodes = a.n / nz;
@@ -1919,8 +1937,14 @@ static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArg
     }
     if (R.slot) {
         const size_t sh = (size_t)R.gcap * sizeof(typename AccOf<V>::type);
+        if constexpr (sizeof(M) <= 4) {
+            if (lcol_quads_ok(R)) {
+                hipLaunchKernelGGL((k_fwd_lcol_pair<M, V, 4>), dim3(grid), dim3(kBlock), sh, st, a);
+                return;
+            }
+        }
         if (lcol_pairs_ok(R)) {
-            hipLaunchKernelGGL((k_fwd_lcol_pair<M, V>), dim3(grid), dim3(kBlock), sh, st, a);
+            hipLaunchKernelGGL((k_fwd_lcol_pair<M, V, 2>), dim3(grid), dim3(kBlock), sh, st, a);
             return;
         }
         hipLaunchKernelGGL((k_fwd_lcol<M, V>), dim3(grid), dim3(kBlock), sh, st, a);
@@ -2047,18 +2071,20 @@ int fwd_lcol_blocks_per_cu(const RowFmt &R)
     if constexpr (Wide<V>::value) {
         if (R.vt == VT_F64)
             e = lcol_pairs_ok(R)
-                    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<double, V>, kBlock, sh)
+                    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<double, V, 2>, kBlock, sh)
                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<double, V>, kBlock, sh);
     } else {
+#define LSQR_LCOL_OCC(M_)                                                                                   \
+    (lcol_quads_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<M_, V, 4>, kBlock, sh) \
+     : lcol_pairs_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<M_, V, 2>, kBlock, sh) \
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<M_, V>, kBlock, sh))
         switch (R.vt) {
-        case VT_F32: e = lcol_pairs_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<float, V>, kBlock, sh)
-                                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<float, V>, kBlock, sh); break;
-        case VT_BF16: e = lcol_pairs_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<bf16_t, V>, kBlock, sh)
-                                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<bf16_t, V>, kBlock, sh); break;
-        case VT_F16: e = lcol_pairs_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<fp16_t, V>, kBlock, sh)
-                                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<fp16_t, V>, kBlock, sh); break;
+        case VT_F32: e = LSQR_LCOL_OCC(float); break;
+        case VT_BF16: e = LSQR_LCOL_OCC(bf16_t); break;
+        case VT_F16: e = LSQR_LCOL_OCC(fp16_t); break;
         default: break;
         }
+#undef LSQR_LCOL_OCC
     }
     return e == hipSuccess ? nb : 0;
 }

@@ -70,7 +70,9 @@ def test_refinement_fixed_points(fmt):
     """With exact inner solves on the quantised operator, refinement on the
     plain residual converges to a point with Ahat^T (bbar - Abar x) = 0, away
     from x* when the data are noisy; the corrected right-hand side
-    [r_G; r_L; r_D + (g - ghat)/lambda] converges to x*."""
+    [r_G; r_L; r_D + (g - ghat)/lambda] converges to x*, and so does the one
+    the library uses, [0; 0; (Abar^T r)/lambda] (the same Ahat^T f, with
+    the residual itself taken out), sweep by sweep to the same iterates."""
     s = synth.make_system(synth.small_config(nx=6, ny=6, nz=5, n_stations=14, n_periods=5,
                                              region=0.6))
     A = _dense(s)
@@ -85,7 +87,8 @@ def test_refinement_fixed_points(fmt):
     solve_h = np.linalg.pinv(Ah)
     x_naive = np.zeros(s.n)
     x_corr = np.zeros(s.n)
-    for _ in range(12):
+    x_norm = np.zeros(s.n)
+    for sweep in range(12):
         r = b - A @ x_naive
         x_naive = x_naive + solve_h @ r
         r = b - A @ x_corr
@@ -93,7 +96,16 @@ def test_refinement_fixed_points(fmt):
         f = r.copy()
         f[s.m + s.n:] += (g - gh) / s.damp
         x_corr = x_corr + solve_h @ f
+        r = b - A @ x_norm
+        fn = np.zeros_like(r)
+        fn[s.m + s.n:] = (A.T @ r) / s.damp
+        assert np.allclose(Ah.T @ fn, A.T @ r, rtol=1e-12, atol=1e-14 * np.abs(A.T @ r).max())
+        x_norm = x_norm + solve_h @ fn
+        if sweep < 3:      # the same correction, up to rounding
+            assert np.linalg.norm(x_norm - x_corr) <= 1e-9 * np.linalg.norm(x_corr)
     err_naive = np.linalg.norm(x_naive - xs) / np.linalg.norm(xs)
     err_corr = np.linalg.norm(x_corr - xs) / np.linalg.norm(xs)
+    err_norm = np.linalg.norm(x_norm - xs) / np.linalg.norm(xs)
     assert err_corr < 1e-12
+    assert err_norm < 1e-12
     assert err_naive > 1e-6
