@@ -187,8 +187,9 @@ def kernel_label(tag, ks):
     if tag == "fwd":
         rf = ks["row_format"]
         if rf == 4:
-            return ("k_fwd_lcol_pair (forward product, row groups, entries in aligned pairs)"
-                    if ks["fwd_pairs"] else
+            e = ks["fwd_entries_per_load"]
+            return (f"k_fwd_lcol_pair<{e}> (forward product, row groups, entries in aligned "
+                    + {2: "pairs)", 4: "quads)"}[e] if e > 1 else
                     "k_fwd_lcol (forward product, row groups, columns staged in LDS)")
         return {1: "k_fwd_pipe / k_fwd_csr (forward product, CSR rows)",
                 2: "k_fwd_runs (forward product, depth-run rows)",
@@ -461,6 +462,57 @@ def copy_calibration():
     del a, b
 
 
+def block_products_bench(args):
+    """The batched solver's two block products alone, 32 right-hand sides, on
+    the batched workload's largest system (config-1 geometry, 229 stations,
+    20 periods, seed 3) in its tuned schedule (32-wide tiles, 2,048
+    workgroups): lsqr_apply_block (the per-run partial rows on the matrix
+    cores, then their sums per data row) and lsqr_apply_t_block, timed with
+    HIP events on the solver's stream, mean of `--steps` x 10 calls.  The
+    run's HBM counters give the bytes each kernel moves.  Prints one JSON
+    line."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2604_11920_amd import Solver
+    s = synth.make_system(synth.config3_systems()[-1])
+    k = s.col // s.nz                         # node runs: stretches of one lateral node
+    new_run = np.ones(s.nnz, dtype=bool)
+    new_run[1:] = k[1:] != k[:-1]
+    new_run[s.row_ptr[:-1][np.diff(s.row_ptr) > 0]] = True
+    runs = int(new_run.sum())
+    del k, new_run
+    if args.copy_calib:
+        copy_calibration()
+    R = 32
+    with Solver.from_system(s, precond="jacobi") as sol:
+        sol.set_batch_config(32, 2048)
+        g = torch.Generator(device="cuda").manual_seed(1)
+        x = torch.randn((s.n, R), dtype=torch.float32, device="cuda", generator=g)
+        yb = torch.randn((s.m + 2 * s.n, R), dtype=torch.float32, device="cuda", generator=g)
+        y, q = torch.empty_like(yb), torch.empty_like(x)
+        st = torch.cuda.current_stream()
+        res = {}
+        for name, f in (("fwd", lambda: sol.apply_block(x, y)), ("adj", lambda: sol.apply_t_block(yb, q))):
+            for _ in range(max(args.warmup, 1)):
+                f()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 10 * max(args.steps, 1)
+            e0.record(st)
+            for _ in range(reps):
+                f()
+            e1.record(st)
+            torch.cuda.synchronize()
+            res[name] = e0.elapsed_time(e1) / reps * 1e3
+    print(json.dumps({"metric": "32-wide block products: microseconds per call",
+                      "m": s.m, "n": s.n, "nnz": s.nnz, "node_runs": runs, "rhs": R,
+                      "fwd_us": res["fwd"], "adj_us": res["adj"],
+                      "fp32_value_bytes": 4 * s.nnz,
+                      "partial_row_bytes_per_pass": runs * R * 4}), flush=True)
+
+
 def products_bench(args):
     """The solver's two sparse products alone for one precision on the
     paper-shaped system, in the formats the solver picks (lsqr_apply_stored /
@@ -571,6 +623,8 @@ def main():
                     help="measure the outer iterations with re-linearisation instead (one JSON line)")
     ap.add_argument("--products", choices=["fp64", "fp32", "bf16", "fp16"], default=None,
                     help="time the two sparse products alone in this precision (one JSON line)")
+    ap.add_argument("--block-products", action="store_true",
+                    help="time the batched form's two block products alone (one JSON line)")
     ap.add_argument("--batched", action="store_true",
                     help="measure the batched multi-RHS form instead (one JSON line)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -604,6 +658,9 @@ def main():
         return
     if args.products:
         products_bench(args)
+        return
+    if args.block_products:
+        block_products_bench(args)
         return
     t0 = time.perf_counter()
     if args.config == "cfg1":

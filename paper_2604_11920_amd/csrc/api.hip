@@ -1353,7 +1353,7 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
     out->fwd_bytes = fwd;
     out->row_format = E.R.slot ? 4 : E.R.rmask ? 3 : E.R.run_ptr ? 2 : 1;
     out->col_format = E.C.sl_ptr ? 5 : E.C.mmask ? 3 : E.C.nrp ? (E.C.pairs ? 4 : 2) : 1;
-    out->fwd_pairs = E.R.slot && lcol_pairs_ok(E.R) ? 1 : 0;
+    out->fwd_entries_per_load = !E.R.slot ? 0 : lcol_quads_ok(E.R) ? 4 : lcol_pairs_ok(E.R) ? 2 : 1;
     out->adj_depths_per_word = E.C.nrp ? (E.C.pairs ? E.C.pairs : 1) : 0;
     out->groups = E.R.slot ? c->ngroups : 0;
     out->staged_cols = E.R.slot ? c->ngcols : 0;

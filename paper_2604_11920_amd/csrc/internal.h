@@ -120,11 +120,12 @@ static inline bool lcol_pairs_ok(const RowFmt &R)
     return R.padded >= 1 && ((uintptr_t)R.val & (w - 1)) == 0 && ((uintptr_t)R.slot & 3u) == 0;
 }
 
-// Entries in quads (4- and 2-byte values, when LSQR_FWD_QUADS is set): four
-// values and four slots from positions that are multiples of four, and up to
-// three elements past the last entry.
+// Entries in quads (4- and 2-byte values): four values and four slots from
+// positions that are multiples of four, and up to three elements past the
+// last entry.  Measured on the paper-shaped system against pairs: FP32
+// 699 -> 655 us, FP16 569 -> 527 us, BF16 585 -> 566 us.
 #ifndef LSQR_FWD_QUADS
-#define LSQR_FWD_QUADS 0
+#define LSQR_FWD_QUADS 1
 #endif
 static inline bool lcol_quads_ok(const RowFmt &R)
 {

@@ -131,21 +131,26 @@ def search_targets(system, tol=1e-6, family="depth", grid=(-1.0, -0.5, 0.5, 1.0)
     return feat, family_log_multiplier(feat, theta, nz), theta, kj, best
 
 
-def centred(feat, centre=CENTRE):
-    """Features of one system with the flagged columns minus their mean."""
+def centred(feat, centre=CENTRE, mean=None):
+    """Features of one system with the flagged columns minus their mean over
+    the system's columns (`mean`: those means, when feat holds a sample of
+    the columns only)."""
     f = np.array(feat, dtype=np.float64)
     for k in range(f.shape[1]):
         if (centre >> k) & 1:
-            f[:, k] -= f[:, k].mean()
+            f[:, k] -= f[:, k].mean() if mean is None else mean[k]
     return f
 
 
-def train(feats, targets, epochs=60, batch=4096, lr=1e-3, seed=0, centre=CENTRE, log=None):
+def train(feats, targets, epochs=60, batch=4096, lr=1e-3, seed=0, centre=CENTRE, log=None,
+          means=None):
     """Fit the MLP on the GPU (the library's FP32 forward/backward and Adam).
     feats: per-system [n_s, 6] feature blocks (flagged columns are centred per
-    system, as inference does)."""
+    system, as inference does; `means`: per-system feature means over all
+    columns, for blocks that hold a sample of them)."""
     import torch
-    X = np.concatenate([centred(f, centre) for f in feats]).astype(np.float64)
+    X = np.concatenate([centred(f, centre, None if means is None else means[i])
+                        for i, f in enumerate(feats)]).astype(np.float64)
     T = np.concatenate(targets).astype(np.float64)
     mean = X.mean(axis=0)
     std = X.std(axis=0)

@@ -70,7 +70,7 @@ class KStats(ctypes.Structure):
                 ("fwd_launches", ctypes.c_int), ("adj_launches", ctypes.c_int),
                 ("fwd_bytes", ctypes.c_double), ("adj_bytes", ctypes.c_double),
                 ("row_format", ctypes.c_int), ("col_format", ctypes.c_int),
-                ("fwd_pairs", ctypes.c_int), ("adj_depths_per_word", ctypes.c_int),
+                ("fwd_entries_per_load", ctypes.c_int), ("adj_depths_per_word", ctypes.c_int),
                 ("groups", ctypes.c_int64), ("staged_cols", ctypes.c_int64),
                 ("padded_values", ctypes.c_int64)]
 

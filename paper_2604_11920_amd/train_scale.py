@@ -88,17 +88,45 @@ def cmd_search(args):
                  sizes=np.array([len(x) for x in targets]), meta=np.array(json.dumps(rows)))
 
 
+def load_blocks(path, cols=0, seed=0):
+    """Per-system feature and target blocks of a target file, with each
+    system's feature means over all its columns; cols > 0 keeps a seeded
+    sample of at most that many columns per system (the means stay those of
+    all columns, so centring matches inference)."""
+    z = np.load(path, allow_pickle=False)
+    cut = np.cumsum(z["sizes"])[:-1]
+    feats = np.split(z["feat"].astype(np.float64), cut)
+    targets = np.split(z["target"].astype(np.float64), cut)
+    rows = json.loads(str(z["meta"]))
+    means = list(z["means"]) if "means" in z else [f.mean(axis=0) for f in feats]
+    if cols > 0:
+        for i, f in enumerate(feats):
+            if len(f) > cols:
+                keep = np.sort(np.random.default_rng(seed + i).choice(len(f), cols, replace=False))
+                feats[i], targets[i] = f[keep], targets[i][keep]
+    return feats, targets, means, rows
+
+
+def cmd_subsample(args):
+    feats, targets, means, rows = load_blocks(args.targets, args.cols)
+    np.savez(args.out, feat=np.concatenate(feats).astype(np.float32),
+             target=np.concatenate(targets).astype(np.float32),
+             sizes=np.array([len(x) for x in targets]), means=np.array(means),
+             meta=np.array(json.dumps(rows)))
+    log(f"[subsample] {len(rows)} systems, {sum(len(x) for x in targets)} columns -> {args.out}")
+
+
 def cmd_fit(args):
     from paper_2604_11920_amd import learned
-    feats, targets, rows = [], [], []
+    feats, targets, means, rows = [], [], [], []
     for path in args.targets:
-        z = np.load(path, allow_pickle=False)
         # per-system blocks (features are centred per system)
-        cut = np.cumsum(z["sizes"])[:-1]
-        feats += np.split(z["feat"].astype(np.float64), cut)
-        targets += np.split(z["target"].astype(np.float64), cut)
-        rows += json.loads(str(z["meta"]))
-    model = learned.train(feats, targets, epochs=args.epochs, log=log)
+        f, t, mu, r = load_blocks(path, args.cols_per_system)
+        feats += f
+        targets += t
+        means += mu
+        rows += r
+    model = learned.train(feats, targets, epochs=args.epochs, log=log, means=means)
     model.meta["train_systems"] = rows
     model.meta["tol"] = args.tol
     model.save(args.out)
@@ -160,6 +188,8 @@ def main():
     b = sub.add_parser("fit")
     b.add_argument("targets", nargs="+")
     b.add_argument("--epochs", type=int, default=60)
+    b.add_argument("--cols-per-system", type=int, default=0,
+                   help="fit on a seeded sample of at most this many columns per system")
     b.add_argument("--tol", type=float, default=1e-6)
     b.add_argument("--out", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp.npz"))
     c = sub.add_parser("eval")
@@ -169,7 +199,14 @@ def main():
     c.add_argument("--count", type=int, default=20)
     c.add_argument("--tol", type=float, default=1e-6)
     c.add_argument("--report", default=None)
+    d = sub.add_parser("subsample")
+    d.add_argument("targets")
+    d.add_argument("--cols", type=int, required=True)
+    d.add_argument("--out", required=True)
     args = ap.parse_args()
+    if args.cmd == "subsample":          # host only
+        cmd_subsample(args)
+        return
     import torch
     torch.cuda.set_device(0)
     {"search": cmd_search, "fit": cmd_fit, "eval": cmd_eval}[args.cmd](args)

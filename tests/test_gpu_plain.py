@@ -360,7 +360,8 @@ def test_row_groups_reduced_precision(cfg0, precision):
     if precision == "bf16":
         kw.update(refine_sweeps=10)
     with from_sys(s, row_format="groups", **kw) as sol:
-        assert sol.kernel_stats()["row_format"] == 4
+        ks = sol.kernel_stats()
+        assert ks["row_format"] == 4 and ks["fwd_entries_per_load"] == 4   # aligned quads
         dg, _, ig = sol.solve(s.dt, iters, tol=tol)
     with from_sys(s, row_format="csr", **kw) as sol:
         dc, _, ic = sol.solve(s.dt, iters, tol=tol)

@@ -14,8 +14,10 @@ per product; the transposed product likewise with the column's entries and
 the smoothing and damping terms.  The 16-bit forms' transposed product reads
 tg = sigma * y_G (a power-of-two scale: exact), as the solver gathers it.
 
-Systems: rows of odd length starting at odd positions with empty rows (the
-paired row-group loads and their padding element), the tomography pattern of
+Systems: rows of odd length starting at every position modulo four, with
+empty rows and an entry count of 3 modulo 4 (the row-group loads in aligned
+pairs for FP64 and quads for the 4- and 2-byte values, and their padding
+elements), the tomography pattern of
 a small ray geometry (row groups, depth pairs and run slices in their real
 shape), and a ragged random structure (short rows, empty columns).
 """
