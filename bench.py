@@ -616,9 +616,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32 rate and the time-to-tolerance comparisons")
     ap.add_argument("--ttt-tol", type=float, default=1e-6)
-    ap.add_argument("--model", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp_cfg1.npz"),
+    ap.add_argument("--model", default=os.path.join(ROOT, "paper_2604_11920_amd", "colscale_mlp_c17.npz"),
                     help="learned column-scale model for the learned time-to-tolerance forms "
-                         "(default: the model fitted on config-1-geometry training systems)")
+                         "(default: the model fitted on the 200 training systems of both shapes)")
     ap.add_argument("--outer", action="store_true",
                     help="measure the outer iterations with re-linearisation instead (one JSON line)")
     ap.add_argument("--products", choices=["fp64", "fp32", "bf16", "fp16"], default=None,

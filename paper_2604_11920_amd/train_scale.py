@@ -14,7 +14,23 @@ Three steps, each resumable on its own:
     python -m paper_2604_11920_amd.train_scale eval --model paper_2604_11920_amd/colscale_mlp.npz \
         --family cfg0 --first 1001 --count 20 --report report.json
 
-Shipped models: colscale_mlp.npz (fitted on cfg0 and cfg1 targets) and
+Shipped models: colscale_mlp_c17.npz (the benchmark's; fitted on the 200
+training systems of the family stated for the learned scale: c17cfg0 seeds
+1-160, per-depth targets, three rounds from step 1; c17cfg1 seeds 161-200,
+linear-in-depth targets, one round; 16,384 sampled columns per config-1-shape
+system):
+
+    python -m paper_2604_11920_amd.train_scale search --family c17cfg0 --first 1 --count 160 \
+        --param depth --rounds 3 --step 1.0 --out targets_c17cfg0.npz
+    python -m paper_2604_11920_amd.train_scale search --family c17cfg1 --first 161 --count 15 \
+        --param linear --rounds 1 --out targets_c17cfg1_a.npz     # and 176 / 15, 191 / 10
+    python -m paper_2604_11920_amd.train_scale fit targets_c17cfg0.npz targets_c17cfg1_a.npz \
+        targets_c17cfg1_b.npz targets_c17cfg1_c.npz --cols-per-system 16384 \
+        --out paper_2604_11920_amd/colscale_mlp_c17.npz
+    python -m paper_2604_11920_amd.train_scale eval --model paper_2604_11920_amd/colscale_mlp_c17.npz \
+        --family c17cfg1 --first 1001 --count 20 --report report.json
+
+colscale_mlp.npz (fitted on cfg0 and cfg1 targets) and
 colscale_mlp_cfg1.npz (fitted on config-1-geometry targets only: cfg1 seeds
 1-6, and cfg1large seeds 1-5, depth family, one search round; the benchmark
 system itself, seed 0 with 229 stations, is not among them):
