@@ -191,18 +191,14 @@ def kernel_label(tag, ks):
             return (f"k_fwd_lcol_pair<{e}> (forward product, row groups, entries in aligned "
                     + {2: "pairs)", 4: "quads)"}[e] if e > 1 else
                     "k_fwd_lcol (forward product, row groups, columns staged in LDS)")
-        return {1: "k_fwd_pipe / k_fwd_csr (forward product, CSR rows)",
-                2: "k_fwd_runs (forward product, depth-run rows)",
-                3: "k_fwd_rmask (forward product, run-mask rows)"}[rf]
+        return "k_fwd_pipe / k_fwd_csr (forward product, CSR rows)"
     cf = ks["col_format"]
     if cf == 4:
         w = ks["adj_depths_per_word"]
         return (f"k_adj_npair<{w}> (transposed product, node runs, "
                 + {2: "depth pairs)", 4: "four-depth words)", 8: "eight-depth words)"}[w])
     return {1: "k_adj (transposed product, CSC)",
-            2: "k_adj_nruns (transposed product, node runs)",
-            3: "k_adj_nmask (transposed product, node masks)",
-            5: "k_adj_slices (transposed product, run slices)"}[cf]
+            2: "k_adj_nruns (transposed product, node runs)"}[cf]
 
 
 def assembly_check(s, host_s):
@@ -606,11 +602,8 @@ def main():
     ap.add_argument("--cpu-runs", type=int, default=10,
                     help="timed runs of the CPU oracle sample (the paper's protocol: 10)")
     ap.add_argument("--no-scipy", action="store_true", help="skip the SciPy LSQR context timing")
-    ap.add_argument("--row-format", default="auto", choices=["auto", "csr", "runs", "masks", "groups"])
-    ap.add_argument("--col-format", default="auto",
-                    choices=["auto", "csc", "runs", "masks", "pairs", "slices"])
-    ap.add_argument("--xcd-bands", action="store_true",
-                    help="transposed product: one contiguous column band per XCD")
+    ap.add_argument("--row-format", default="auto", choices=["auto", "csr", "groups"])
+    ap.add_argument("--col-format", default="auto", choices=["auto", "csc", "runs", "pairs"])
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched multi-right-hand-side measurement")
     ap.add_argument("--no-extras", action="store_true",
@@ -679,7 +672,7 @@ def main():
     log(f"[bench] generated {args.config}: m={s.m} n={s.n} nnz={s.nnz} in {gen_s:.1f}s")
     t0 = time.perf_counter()
     fmt = dict(row_format=args.row_format, col_format=args.col_format)
-    sol = Solver.from_system(s, timing=True, xcd_bands=args.xcd_bands, **fmt)
+    sol = Solver.from_system(s, timing=True, **fmt)
     torch.cuda.synchronize()
     log(f"[bench] create (copy + device transpose) {time.perf_counter() - t0:.2f}s")
     dt = torch.from_numpy(s.dt).cuda()
@@ -732,8 +725,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": workload, "m": s.m, "n": s.n, "nnz": s.nnz,
                    "iters_per_step": iters, "precision": "fp64", "precond": "none",
-                   "row_format": args.row_format, "col_format": args.col_format,
-                   "xcd_bands": args.xcd_bands},
+                   "row_format": args.row_format, "col_format": args.col_format},
         "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom_gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, f"{ks['row_format']}/{ks['col_format']}"),

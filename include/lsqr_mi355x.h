@@ -83,10 +83,7 @@ typedef void (*lsqr_free_fn)(void *ptr, size_t bytes, void *user);
 
 #define LSQR_FLAG_TIMING 1u     /* record HIP events around the sparse kernels  */
 #define LSQR_FLAG_NO_GRAPH 2u   /* launch iterations one by one, no hipGraph     */
-#define LSQR_FLAG_XCD_BANDS 4u  /* transposed product: each of the 8 XCDs walks a
-                                   contiguous eighth of the columns (L2 locality);
-                                   the product is unchanged, the partial sums of
-                                   its norm are grouped differently (last bits)  */
+                                /* (other bits: INVALID_ARG)                     */
 
 typedef struct {
     lsqr_precision precision;
@@ -104,11 +101,7 @@ typedef struct {
     int row_format;             /* data rows of the forward product: 0 = auto (row    */
                                 /* groups for rows of >= 384 entries on average when  */
                                 /* the groups' column lists hold at most nnz / 2      */
-                                /* columns, else plain CSR), 1 = plain CSR, 2 = depth */
-                                /* runs (runs of consecutive columns, i.e. of depth   */
-                                /* nodes under one lateral node, eq. 7), 3 = run      */
-                                /* masks (CSR values; columns decoded from a          */
-                                /* run-start bit per entry and one word per run),     */
+                                /* columns, else plain CSR), 1 = plain CSR,           */
                                 /* 4 = row groups (CSR values; consecutive rows       */
                                 /* grouped while their columns number at most the    */
                                 /* longest row rounded up to 1024; per group its      */
@@ -120,20 +113,13 @@ typedef struct {
                                 /* matrix fits the format, else CSC), 1 = CSC, 2 =    */
                                 /* node runs (per node, the rows reaching it with     */
                                 /* their stretch of consecutive depths; needs nz <=   */
-                                /* 64, nnz < 2^32), 3 = node masks (CSC values; per   */
-                                /* node its row list and one bit per (row, depth);    */
-                                /* needs nz <= 32), 4 = node runs in the depth-pair   */
+                                /* 64, nnz < 2^32), 4 = node runs in the depth-pair   */
                                 /* layout (each run stored from an even position with */
                                 /* a zero before an odd first depth and after an odd  */
-                                /* end, so two depths load as one aligned word; a     */
-                                /* second, padded copy of the node-run values), 5 =   */
-                                /* run slices (per node, its runs grouped by first    */
-                                /* depth and cut into slices of 64 runs, one run per  */
-                                /* lane; per step of depths the slice's 64 values     */
-                                /* side by side, so a wave-wide load covers one depth */
-                                /* step of 64 runs; shorter runs padded with zeros;   */
-                                /* a copy of the values in this layout, of the        */
-                                /* solver's value type)                               */
+                                /* end, so two depths load as one aligned word; FP32  */
+                                /* values and 16-bit codes four depths to a word; a   */
+                                /* second, padded copy of the node-run values); other */
+                                /* values: INVALID_ARG                                */
     double refine_inner_tol;    /* mixed precision: relative eta each inner solve     */
                                 /* reaches before the FP64 correction (0 = 1e-2); a   */
                                 /* sweep cannot gain more than the quantisation error */
@@ -196,10 +182,9 @@ typedef struct {
     double fwd_bytes;           /* algorithmic bytes of one forward launch            */
     double adj_bytes;           /* algorithmic bytes of one transposed launch         */
     int row_format;             /* format the solver's forward product reads: 1 CSR,  */
-                                /* 2 depth runs, 3 run masks, 4 row groups            */
-    int col_format;             /* transposed product: 1 CSC, 2 node runs, 3 node     */
-                                /* masks, 4 node runs in the depth-pair layout, 5 run */
-                                /* slices                                             */
+                                /* 4 row groups                                       */
+    int col_format;             /* transposed product: 1 CSC, 2 node runs, 4 node     */
+                                /* runs in the depth-pair (four-depth) layout         */
     int fwd_entries_per_load;   /* row groups: entries a lane reads per load (1; 2:    */
                                 /* aligned pairs, 4: aligned quads, k_fwd_lcol_pair)   */
     int adj_depths_per_word;    /* node-run layouts: depths per lane and load (1 plain */
@@ -208,7 +193,7 @@ typedef struct {
     int64_t staged_cols;        /* columns staged in LDS per forward product, summed   */
                                 /* over the groups                                     */
     int64_t padded_values;      /* zeros the transposed layout adds to the stored      */
-                                /* values (depth pairs, four-depth words, run slices)  */
+                                /* values (depth pairs, four-depth words)              */
 } lsqr_kstats;
 
 /*

@@ -66,17 +66,6 @@ lsqr_status validate_host_csr(const lsqr_csr *G)
     return LSQR_OK;
 }
 
-// Attach the node masks (when built) to a transposed format whose values are
-// in CSC order.
-static void set_node_masks(const lsqr_ctx *c, ColFmt &C)
-{
-    if (!c->mmask) return;
-    C.mrptr = c->mrptr; C.mrows = c->mrows; C.mcptr = c->mcptr; C.mmask = c->mmask;
-    C.mqoff = c->mqoff; C.norder = c->morder;
-    const int nz = c->P.nz;
-    C.nzt = nz <= 8 ? 8 : nz <= 16 ? 16 : nz <= 24 ? 24 : 32;
-}
-
 int pick_lanes(double avg)
 {
     if (avg >= 384) return 64;
@@ -140,8 +129,7 @@ lsqr_status setup_engine(lsqr_ctx *c, Engine &E, int vec, const RowFmt &R, const
     E.vec = vec;
     E.R = R;
     E.C = C;
-    if (R.run_ptr) E.g_fwd = cap_blocks(std::max<int64_t>(m * 64, 2 * n), kBlock, 2048);
-    else E.g_fwd = cap_blocks(std::max<int64_t>(m * R.lpr, 2 * n), kBlock, 2048);
+    E.g_fwd = cap_blocks(std::max<int64_t>(m * R.lpr, 2 * n), kBlock, 2048);
     // pipelined CSR rows: as many workgroups as the device holds at once, on
     // contiguous row ranges balanced in entries
     const int gp = m > 0 ? fwd_pipe_grid(vec, R) : 0;
@@ -164,8 +152,8 @@ lsqr_status setup_engine(lsqr_ctx *c, Engine &E, int vec, const RowFmt &R, const
         E.R.wrow = E.wrow;
         E.R.wgrid = gp;
     }
-    if (C.nrp || C.mmask) {
-        // node formats: a workgroup per node; for node runs no more workgroups
+    if (C.nrp) {
+        // node runs: a workgroup per node, no more workgroups
         // than the device holds at once (one round, measured 3 % faster)
         const int ga = adj_nruns_grid(vec, C);
         const int64_t cap = ga > 0 ? std::min(ga, 2048) : 2048;
@@ -417,10 +405,12 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if ((o.lanes_per_row && !valid_lanes(o.lanes_per_row)) ||
         (o.lanes_per_col && !valid_lanes(o.lanes_per_col)))
         return fail(nullptr, LSQR_E_INVALID_ARG, "lanes must be 0, 4, 8, 16, 32 or 64");
-    if (o.row_format < 0 || o.row_format > 4)
-        return fail(nullptr, LSQR_E_INVALID_ARG, "row_format must be 0, 1, 2, 3 or 4");
-    if (o.col_format < 0 || o.col_format > 5)
-        return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1, 2, 3, 4 or 5");
+    if (o.row_format != 0 && o.row_format != 1 && o.row_format != 4)
+        return fail(nullptr, LSQR_E_INVALID_ARG, "row_format must be 0, 1 or 4");
+    if (o.col_format != 0 && o.col_format != 1 && o.col_format != 2 && o.col_format != 4)
+        return fail(nullptr, LSQR_E_INVALID_ARG, "col_format must be 0, 1, 2 or 4");
+    if (o.flags & ~(LSQR_FLAG_TIMING | LSQR_FLAG_NO_GRAPH))
+        return fail(nullptr, LSQR_E_INVALID_ARG, "unknown flag");
     if (o.method < 0 || o.method > 1)
         return fail(nullptr, LSQR_E_INVALID_ARG, "method must be 0 (LSQR) or 1 (LSMR)");
     if (o.check_every < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "check_every must be >= 0");
@@ -531,43 +521,17 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             return bail(e == hipErrorOutOfMemory ? LSQR_E_OOM : LSQR_E_DEVICE,
                         terr + ": " + hipGetErrorString(e));
     }
-    // depth runs of the data rows
     const double avg_row = m > 0 ? (double)nnz / (double)m : 0.0;
     const double avg_col = (double)nnz / (double)n;
-    bool use_runs = false;
-    if (o.row_format == 2 && m > 0 && nnz > 0) {
-        std::vector<int64_t> run_ptr;
-        std::vector<uint32_t> runs;
-        std::vector<uint16_t> roff;
-        if (build_runs_host(m, n, hrow, hcol, run_ptr, runs, roff)) {
-            c->nruns = run_ptr[m];
-            use_runs = true;
-            {
-                c->run_ptr = ctx_alloc<int64_t>(c, m + 1);
-                c->runs = ctx_alloc<uint32_t>(c, c->nruns);
-                c->roff = ctx_alloc<uint16_t>(c, c->nruns);
-                if (!c->run_ptr || !c->runs || !c->roff) return bail(LSQR_E_OOM, "device allocation failed");
-                CR_TRY(hipMemcpy(c->run_ptr, run_ptr.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-                CR_TRY(hipMemcpy(c->runs, runs.data(), c->nruns * sizeof(uint32_t), hipMemcpyHostToDevice));
-                CR_TRY(hipMemcpy(c->roff, roff.data(), c->nruns * sizeof(uint16_t), hipMemcpyHostToDevice));
-            }
-        } else if (o.row_format == 2) {
-            return bail(LSQR_E_UNSUPPORTED, "depth-run rows need rows of <= 65535 entries and n < 2^24");
-        }
-    }
     // node runs of the data block for the transposed product
     // (auto: node runs whenever the format can hold the matrix; the faster
     // transposed product measured on gfx950)
     bool use_nruns = false;
     NodeRuns NR;
-    const bool nruns_ok = (o.col_format == 2 || o.col_format == 0 || o.col_format == 4 ||
-                           o.col_format == 5) && nnz > 0 &&
+    const bool nruns_ok = (o.col_format == 2 || o.col_format == 0 || o.col_format == 4) && nnz > 0 &&
                           build_node_runs_host(m, n, G->nz, hrow, hcol, NR);
-    if ((o.col_format == 2 || o.col_format == 4 || o.col_format == 5) && nnz > 0 && !nruns_ok)
+    if ((o.col_format == 2 || o.col_format == 4) && nnz > 0 && !nruns_ok)
         return bail(LSQR_E_UNSUPPORTED, "node runs need nz <= 64, m < 2^32 and nnz < 2^32");
-    const bool use_slices = nruns_ok && o.col_format == 5;
-    const int sl_vt = o.precision == LSQR_FP64 ? VT_F64 : o.precision == LSQR_FP32 ? VT_F32
-                      : o.precision == LSQR_BF16 ? VT_BF16 : VT_F16;
     if (nruns_ok) {
         const int64_t nr = NR.nrp.back(), nn = n / G->nz;
         c->nnruns = nr;
@@ -585,35 +549,10 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         CR_TRY(hipMemcpy(c->nvq, NR.nvq.data(), (4 * nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->nrow, NR.row.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->ndesc, NR.desc.data(), nr * sizeof(uint16_t), hipMemcpyHostToDevice));
-        if (o.flags & LSQR_FLAG_XCD_BANDS) {   // nodes in 8 bands, one per XCD
-            std::vector<int32_t> seg;
-            xcd_band_order(NR, nn, 8, NR.order, seg);
-            for (int x = 0; x < 9; ++x) c->nseg[x] = seg[(size_t)x];
-        }
         CR_TRY(hipMemcpy(c->norder, NR.order.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->nsrc, NR.src.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         CR_TRY(hipMemcpy(c->ndst, NR.dst.data(), nr * sizeof(uint32_t), hipMemcpyHostToDevice));
         launch_gather_runs(st, nr, c->nsrc, c->ndst, c->ndesc, c->va, c->nval, 8);
-        if (use_slices) {      // run slices: structure now, values once their type exists
-            RunSlices RS;
-            slice_layout_host(NR, nn, slice_width(sl_vt), RS);
-            c->nslices = RS.sptr.back();
-            c->sl_total = RS.total;
-            c->sl_ptr = ctx_alloc<int64_t>(c, nn + 1);
-            c->sl_off = ctx_alloc<int64_t>(c, c->nslices);
-            c->sl_desc = ctx_alloc<uint16_t>(c, c->nslices);
-            c->sl_row = ctx_alloc<uint32_t>(c, c->nslices * 64);
-            c->sl_dst = ctx_alloc<uint64_t>(c, nr);
-            if (!c->sl_ptr || !c->sl_off || !c->sl_desc || !c->sl_row || !c->sl_dst)
-                return bail(LSQR_E_OOM, "device allocation failed");
-            CR_TRY(hipMemcpy(c->sl_ptr, RS.sptr.data(), (nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-            if (c->nslices) {
-                CR_TRY(hipMemcpy(c->sl_off, RS.off.data(), c->nslices * sizeof(int64_t), hipMemcpyHostToDevice));
-                CR_TRY(hipMemcpy(c->sl_desc, RS.desc.data(), c->nslices * sizeof(uint16_t), hipMemcpyHostToDevice));
-                CR_TRY(hipMemcpy(c->sl_row, RS.row.data(), c->nslices * 64 * sizeof(uint32_t), hipMemcpyHostToDevice));
-            }
-            CR_TRY(hipMemcpy(c->sl_dst, RS.dst.data(), nr * sizeof(uint64_t), hipMemcpyHostToDevice));
-        }
         // depth-pair layout (auto and col_format 4): runs padded to aligned
         // pairs of depths, the faster transposed product measured on gfx950
         std::vector<uint32_t> dstp;
@@ -676,56 +615,15 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             CR_TRY(hipMemset(c->slot + nnz, 0, 4 * sizeof(uint16_t)));
         }
     }
-    // run masks of the data rows (index the CSR values directly)
-    if (o.row_format == 3 && nnz > 0) {
-        RowMasks RM;
-        if (!build_row_masks_host(m, hrow, hcol, RM))
-            return bail(LSQR_E_UNSUPPORTED, "run masks need nnz < 2^32");
-        c->rmask_words = (int64_t)RM.mask.size();
-        c->rmask_runs = (int64_t)RM.rcol.size();
-        c->rmask = ctx_alloc<uint64_t>(c, c->rmask_words);
-        c->rbase = ctx_alloc<uint32_t>(c, c->rmask_words);
-        c->rcol = ctx_alloc<int32_t>(c, c->rmask_runs);
-        if (!c->rmask || !c->rbase || !c->rcol) return bail(LSQR_E_OOM, "device allocation failed");
-        CR_TRY(hipMemcpy(c->rmask, RM.mask.data(), c->rmask_words * sizeof(uint64_t), hipMemcpyHostToDevice));
-        CR_TRY(hipMemcpy(c->rbase, RM.base.data(), c->rmask_words * sizeof(uint32_t), hipMemcpyHostToDevice));
-        CR_TRY(hipMemcpy(c->rcol, RM.rcol.data(), c->rmask_runs * sizeof(int32_t), hipMemcpyHostToDevice));
-    }
-    // node masks of the data block (index the CSC values directly)
-    if (o.col_format == 3 && nnz > 0) {
-        NodeMasks NM;
-        if (!build_node_masks_host(m, n, G->nz, hrow, hcol, NM))
-            return bail(LSQR_E_UNSUPPORTED, "node masks need nz <= 32 and m < 2^32");
-        const int64_t nn = n / G->nz;
-        c->mrows_n = (int64_t)NM.rows.size();
-        c->mchunks = NM.cptr.back();
-        c->mrptr = ctx_alloc<int64_t>(c, nn + 1);
-        c->mcptr = ctx_alloc<int64_t>(c, nn + 1);
-        c->mrows = ctx_alloc<uint32_t>(c, c->mrows_n);
-        c->mmask = ctx_alloc<uint64_t>(c, c->mchunks * G->nz);
-        c->mqoff = ctx_alloc<int64_t>(c, nn * 4 * G->nz);
-        c->morder = ctx_alloc<int32_t>(c, nn);
-        if (!c->mrptr || !c->mcptr || !c->mrows || !c->mmask || !c->mqoff || !c->morder)
-            return bail(LSQR_E_OOM, "device allocation failed");
-        CR_TRY(hipMemcpy(c->mrptr, NM.rptr.data(), (nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-        CR_TRY(hipMemcpy(c->mcptr, NM.cptr.data(), (nn + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-        CR_TRY(hipMemcpy(c->mrows, NM.rows.data(), c->mrows_n * sizeof(uint32_t), hipMemcpyHostToDevice));
-        CR_TRY(hipMemcpy(c->mmask, NM.mask.data(), c->mchunks * G->nz * sizeof(uint64_t), hipMemcpyHostToDevice));
-        CR_TRY(hipMemcpy(c->mqoff, NM.qoff.data(), nn * 4 * G->nz * sizeof(int64_t), hipMemcpyHostToDevice));
-        CR_TRY(hipMemcpy(c->morder, NM.order.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice));
-    }
     // FP64 formats
     c->R64.vt = VT_F64; c->R64.rp = c->rp; c->R64.ci = c->ci; c->R64.val = c->va;
-    if (c->rmask) { c->R64.rmask = c->rmask; c->R64.rbase = c->rbase; c->R64.rcol = c->rcol; }
     c->R64.lpr = o.lanes_per_row ? o.lanes_per_row : pick_lanes(avg_row);
-    if (use_runs) { c->R64.run_ptr = c->run_ptr; c->R64.runs = c->runs; c->R64.roff = c->roff; }
     if (c->slot) {
         c->R64.gp = c->gp; c->R64.gcp = c->gcp; c->R64.gcol = c->gcol; c->R64.slot = c->slot;
         c->R64.ngroups = c->ngroups; c->R64.gcap = c->gcap; c->R64.padded = 4;
     }
     c->C64.vt = VT_F64; c->C64.cp = c->cp; c->C64.ri = c->ri; c->C64.val = c->cv;
     c->C64.lpc = o.lanes_per_col ? o.lanes_per_col : pick_lanes(avg_col);
-    c->C64.xcd_bands = (o.flags & LSQR_FLAG_XCD_BANDS) ? 1 : 0;
     // column scaling
     launch_fill(st, n, 1.0, c->ones);
     if (o.precond == LSQR_PRECOND_NONE) {
@@ -751,31 +649,9 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if (use_nruns) {
         C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
         C.norder = c->norder; C.val = c->nval;
-        for (int x = 0; x < 9; ++x) C.nseg[x] = c->nseg[x];
         if (c->nvalp) { C.nvq = c->nvqp; C.val = c->nvalp; C.pairs = 2; }
     }
-    set_node_masks(c, C);
     int vec = VT_F64;
-    // the run-slice values of the solver's type, scattered from its CSR-order
-    // copy (FP64 values, FP32 values or 16-bit codes)
-    auto attach_slices = [&](ColFmt &F, const void *src, int vt) -> lsqr_status {
-        const size_t es = vt_size(vt);
-        const int W = slice_width(vt);
-        c->sl_val = ctx_alloc_bytes(c, (size_t)(c->sl_total + W) * es);
-        if (!c->sl_val) return LSQR_E_OOM;
-        if (hipMemsetAsync(c->sl_val, 0, (size_t)(c->sl_total + W) * es, st) != hipSuccess)
-            return LSQR_E_DEVICE;
-        launch_scatter_slices(st, c->nnruns, c->nsrc, c->sl_dst, c->ndesc, W, src, c->sl_val, (int)es);
-        c->sl_vt = vt;
-        F.sl_ptr = c->sl_ptr; F.sl_off = c->sl_off; F.sl_desc = c->sl_desc; F.sl_row = c->sl_row;
-        F.norder = c->norder; F.nzt = G->nz; F.val = c->sl_val; F.vt = vt;
-        F.nrp = nullptr; F.pairs = 0; F.mmask = nullptr;
-        return LSQR_OK;
-    };
-    if (use_slices && o.precision == LSQR_FP64) {
-        lsqr_status ss = attach_slices(C, c->va, VT_F64);
-        if (ss != LSQR_OK) return bail(ss, "run-slice values: device allocation or fill failed");
-    }
     if (o.precision == LSQR_FP32) {
         c->va32 = ctx_alloc<float>(c, nnz + 4);     // with va's padding elements
         c->cv32 = ctx_alloc<float>(c, nnz);
@@ -801,10 +677,6 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
                 launch_convert_f32(st, c->npad + 2, c->nvalp, c->nvalp32);
                 C.val = c->nvalp32;
             }
-        }
-        if (use_slices) {
-            lsqr_status ss = attach_slices(C, c->va32, VT_F32);
-            if (ss != LSQR_OK) return bail(ss, "run-slice values: device allocation or fill failed");
         }
         vec = VT_F32;
     } else if (mixed) {
@@ -837,10 +709,6 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
                 C.pairs = kQDepths;
             }
         }
-        if (use_slices) {
-            lsqr_status ss = attach_slices(C, c->qrow, vt);
-            if (ss != LSQR_OK) return bail(ss, "run-slice values: device allocation or fill failed");
-        }
         vec = VT_F32;
     }
     lsqr_status s = setup_engine(c, c->eng, vec, R, C);
@@ -851,10 +719,6 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         ctx_release(c, c->nsrc);
         ctx_release(c, c->ndst);
         c->nsrc = c->ndst = nullptr;
-        if (c->sl_dst) {
-            ctx_release(c, c->sl_dst);
-            c->sl_dst = nullptr;
-        }
     }
     *out = c;
     return LSQR_OK;
@@ -1237,19 +1101,13 @@ lsqr_status lsqr_apply_t(lsqr_ctx *c, const double *y, double *x)
     if (!c) return fail(nullptr, LSQR_E_INVALID_ARG, "ctx is NULL");
     if (!x || !y) return fail(c, LSQR_E_INVALID_ARG, "x and y must not be NULL");
     DeviceGuard dg(c->device);
-    // the FP64 transposed format the solver reads (node runs / masks when built)
+    // the FP64 transposed format the solver reads (node runs when built)
     ColFmt C = c->C64;
     if (c->nrp) {
         C.nrp = c->nrp; C.nvq = c->nvq; C.nrow = c->nrow; C.ndesc = c->ndesc;
         C.norder = c->norder; C.val = c->nval;
-        for (int x = 0; x < 9; ++x) C.nseg[x] = c->nseg[x];
         if (c->nvalp) { C.nvq = c->nvqp; C.val = c->nvalp; C.pairs = 2; }
     }
-    if (c->sl_val && c->sl_vt == VT_F64) {
-        C.sl_ptr = c->sl_ptr; C.sl_off = c->sl_off; C.sl_desc = c->sl_desc; C.sl_row = c->sl_row;
-        C.norder = c->norder; C.nzt = c->P.nz; C.val = c->sl_val; C.nrp = nullptr; C.pairs = 0;
-    }
-    set_node_masks(c, C);
     launch_adj(c->st, c->P, std::min(2048, c->eng.g_adj), VT_F64, C, c->d, y, y, nullptr, x,
                c->Pa, nullptr, 0, nullptr, nullptr, 0, MODE_OPERATOR, 0);
     HIP_TRY(c, hipGetLastError());
@@ -1346,33 +1204,18 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
     const double sv = (double)vt_size(E.R.vt), sx = (double)vt_size(E.vec);
     double fwd = nnz * sv + (m + 1) * 8.0 + n * sx + 2.0 * mb * sx;
     if (E.R.slot) fwd += nnz * 2.0 + (double)c->ngcols * 4.0 + (double)(c->ngroups + 1) * 12.0;
-    else if (E.R.rmask) fwd += (double)c->rmask_words * 12.0 + (double)c->rmask_runs * 4.0;
-    else if (E.R.run_ptr) fwd += (double)c->nruns * 6.0 + (m + 1) * 8.0;
     else fwd += nnz * 4.0;
     if (E.R.sigma) fwd += m * 4.0 + m * sx;
     out->fwd_bytes = fwd;
-    out->row_format = E.R.slot ? 4 : E.R.rmask ? 3 : E.R.run_ptr ? 2 : 1;
-    out->col_format = E.C.sl_ptr ? 5 : E.C.mmask ? 3 : E.C.nrp ? (E.C.pairs ? 4 : 2) : 1;
+    out->row_format = E.R.slot ? 4 : 1;
+    out->col_format = E.C.nrp ? (E.C.pairs ? 4 : 2) : 1;
     out->fwd_entries_per_load = !E.R.slot ? 0 : lcol_quads_ok(E.R) ? 4 : lcol_pairs_ok(E.R) ? 2 : 1;
     out->adj_depths_per_word = E.C.nrp ? (E.C.pairs ? E.C.pairs : 1) : 0;
     out->groups = E.R.slot ? c->ngroups : 0;
     out->staged_cols = E.R.slot ? c->ngcols : 0;
-    out->padded_values = E.C.sl_ptr ? c->sl_total - c->P.nnz
-                         : (E.C.nrp && E.C.pairs == 2) ? c->npad - c->P.nnz
+    out->padded_values = (E.C.nrp && E.C.pairs == 2) ? c->npad - c->P.nnz
                          : (E.C.nrp && E.C.pairs >= 4) ? c->npad4 - c->P.nnz : 0;
-    if (E.C.sl_ptr) {
-        // values and one row index per run (padding excluded), per slice its
-        // offset and descriptor, per node its slice range and order entry
-        const double nn = n / (double)c->P.nz;
-        out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->nnruns * 4.0 +
-                         (double)c->nslices * 10.0 + (nn + 1) * 8.0 + nn * 4.0 + mb * sx +
-                         n * (8.0 + 2.0 * sx);
-    } else if (E.C.mmask) {
-        const double nn = n / (double)c->P.nz, nzd = (double)c->P.nz;
-        out->adj_bytes = nnz * (double)vt_size(E.C.vt) + (double)c->mrows_n * 4.0 +
-                         (double)c->mchunks * nzd * 8.0 + nn * 4.0 * nzd * 8.0 +
-                         2.0 * (nn + 1) * 8.0 + nn * 4.0 + mb * sx + n * (8.0 + 2.0 * sx);
-    } else if (E.C.nrp) {
+    if (E.C.nrp) {
         // the method's values only: the zeros a layout pads runs with are
         // format overhead, not algorithmic bytes (they show in the counters)
         const double nn = n / (double)c->P.nz;

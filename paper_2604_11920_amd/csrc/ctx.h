@@ -79,25 +79,18 @@ struct lsqr_ctx {
     double *d_user = nullptr;       // the accepted user scale (restored after a fallback)
     bool user_scale = false;        // D is a caller's scale (create USER or lsqr_set_scale)
     std::vector<std::pair<void *, size_t>> owned;
-    // FP64 operator: CSR, depth runs, CSC, column scale
+    // FP64 operator: CSR, CSC, column scale
     int64_t *rp = nullptr; int32_t *ci = nullptr; double *va = nullptr;
-    int64_t *run_ptr = nullptr; uint32_t *runs = nullptr; uint16_t *roff = nullptr;
-    int64_t nruns = 0;
     int64_t *cp = nullptr; int32_t *ri = nullptr; double *cv = nullptr;
     // node runs of the data block (transposed product), values in node-major order
     int64_t *nrp = nullptr, *nvq = nullptr; uint32_t *nrow = nullptr; uint16_t *ndesc = nullptr;
     int32_t *norder = nullptr; double *nval = nullptr; float *nval32 = nullptr;
-    int nseg[9] = {0};             // XCD bands of norder (when requested)
     int64_t *rrp = nullptr; uint32_t *rrid = nullptr;   // row order of the node runs (batched forward)
     uint16_t *nvalq = nullptr; uint32_t *nsrc = nullptr, *ndst = nullptr;
     int64_t nnruns = 0;
     // depth-pair layout of the node-run values (k_adj_npair)
     int64_t *nvqp = nullptr; uint32_t *ndstp = nullptr; int64_t npad = 0;
     double *nvalp = nullptr; float *nvalp32 = nullptr; uint16_t *nvalpq = nullptr;
-    // run slices of the node runs (k_adj_slices), values of the solver's type
-    int64_t *sl_ptr = nullptr, *sl_off = nullptr; uint16_t *sl_desc = nullptr;
-    uint32_t *sl_row = nullptr; uint64_t *sl_dst = nullptr; void *sl_val = nullptr;
-    int64_t nslices = 0, sl_total = 0; int sl_vt = -1;
     // the 16-bit codes in the four-depth layout (mixed forms)
     int64_t *nvqp4 = nullptr; uint32_t *ndstp4 = nullptr; int64_t npad4 = 0;
     float *nvalp4f = nullptr;     // FP32 node-run values in the four-depth layout
@@ -105,13 +98,6 @@ struct lsqr_ctx {
     int32_t *gp = nullptr, *gcol = nullptr; int64_t *gcp = nullptr; uint16_t *slot = nullptr;
     int ngroups = 0, gcap = 0;
     int64_t ngcols = 0;
-    // run masks of the data rows (forward product over va)
-    uint64_t *rmask = nullptr; uint32_t *rbase = nullptr; int32_t *rcol = nullptr;
-    int64_t rmask_words = 0, rmask_runs = 0;
-    // node masks of the data block (transposed product over cv)
-    int64_t *mrptr = nullptr, *mcptr = nullptr, *mqoff = nullptr; uint32_t *mrows = nullptr;
-    uint64_t *mmask = nullptr; int32_t *morder = nullptr;
-    int64_t mrows_n = 0, mchunks = 0;
     double *d = nullptr, *ones = nullptr;
     lsqr::RowFmt R64;
     lsqr::ColFmt C64;

@@ -78,19 +78,9 @@ struct RowFmt {
     int vt = VT_F64;
     const int64_t *rp = nullptr;       // [m+1] value offsets
     const int32_t *ci = nullptr;       // [nnz] columns (plain CSR)
-    const int64_t *run_ptr = nullptr;  // [m+1] run offsets (depth-run rows) or nullptr
-    const uint32_t *runs = nullptr;    // (first column << 8) | length
-    const uint16_t *roff = nullptr;    // value offset of each run in its row
     const void *val = nullptr;
     const float *sigma = nullptr;      // [m] row scales (quantised values) or nullptr
     int lpr = 64;                      // lanes per row (plain CSR)
-    // run masks (used instead of ci when rmask is set): bit p of rmask marks
-    // entry p as the start of a run of consecutive columns; rbase[w] = runs
-    // starting before word w; column of entry p of row i in run r =
-    // rcol[r] + (p - rp[i])
-    const uint64_t *rmask = nullptr;   // [ceil(nnz / 64)]
-    const uint32_t *rbase = nullptr;   // [ceil(nnz / 64)]
-    const int32_t *rcol = nullptr;     // [runs]
     // plain CSR with 64 lanes per row: a launch of wgrid workgroups takes
     // contiguous row ranges balanced in entries, wrow[p] .. wrow[p+1]-1, one
     // per workgroup (its waves interleaved) or per wave (fwd_pipe_parts);
@@ -141,7 +131,6 @@ struct ColFmt {
     const int32_t *ri = nullptr;       // [nnz] rows, ascending within a column
     const void *val = nullptr;
     int lpc = 64;
-    int xcd_bands = 0;                 // 1: contiguous column band per XCD (k_adj)
     // Node runs (used instead of the CSC when nrp is set; val then holds the
     // values in node-major run order).  Node k = columns [k nz, (k+1) nz).
     const int64_t *nrp = nullptr;      // [nnodes+1] runs of node k: [nrp[k], nrp[k+1])
@@ -149,40 +138,9 @@ struct ColFmt {
     const uint32_t *nrow = nullptr;    // [nruns] data row of the run
     const uint16_t *ndesc = nullptr;   // [nruns] (iz0 << 8) | len
     const int32_t *norder = nullptr;   // [nnodes] nodes by decreasing work
-    int pairs = 0;                     // W = 2 (4: 16-bit codes only): val / nvq in the
-                                       // depth-pair (four-depth) layout (k_adj_npair<W>)
-    int nseg[9] = {0};                 // with xcd_bands: band x = norder[nseg[x] .. nseg[x+1])
-    // Node masks (used instead of the CSC rows when mmask is set; val is the
-    // CSC value array): rows mrows[mrptr[k] ..] of node k in chunks of 64;
-    // word mmask[c nz + iz] of global chunk c flags the chunk's rows with an
-    // entry in depth iz; mqoff[(k 4 + w) nz + iz] = CSC position of the first
-    // value of column k nz + iz in quarter w of the node's chunks.
-    const int64_t *mrptr = nullptr;    // [nnodes+1]
-    const uint32_t *mrows = nullptr;   // [node rows]
-    const int64_t *mcptr = nullptr;    // [nnodes+1] first global chunk of node k
-    const uint64_t *mmask = nullptr;   // [chunks nz]
-    const int64_t *mqoff = nullptr;    // [nnodes 4 nz]
-    int nzt = 32;                      // compile-time depth bound of the kernel (>= nz)
-    // Run slices (used when sl_ptr is set; val holds the slice layout, see
-    // slice_layout_host): slices sl_ptr[k] .. sl_ptr[k+1]-1 of node k, slice
-    // s = 64 runs of one first depth, its values from sl_off[s] (W depths of
-    // the 64 lanes side by side per step), sl_desc[s] = (iz0 << 8) | padded
-    // length, sl_row[64 s + lane] = data row of the lane's run (norder as
-    // for node runs).
-    const int64_t *sl_ptr = nullptr;   // [nnodes+1]
-    const int64_t *sl_off = nullptr;   // [nslices]
-    const uint16_t *sl_desc = nullptr; // [nslices]
-    const uint32_t *sl_row = nullptr;  // [64 nslices]
+    int pairs = 0;                     // W = 2, 4 or 8: val / nvq in the layout of W
+                                       // depths to a word (k_adj_npair<W>)
 };
-
-// Depths per lane and load of the run-slice kernel: 16-byte loads for FP64
-// and FP32 values, 8-byte loads for 16-bit codes.
-inline int slice_width(int vt) { return vt == VT_F64 ? 2 : 4; }
-// Compile-time bound on the depths of the run-slice kernel (>= nz <= 64).
-inline int slice_nzm(int nz)
-{
-    return nz <= 8 ? 8 : nz <= 12 ? 12 : nz <= 16 ? 16 : nz <= 20 ? 20 : nz <= 24 ? 24 : nz <= 32 ? 32 : 64;
-}
 
 // Type-dispatched launchers (kernels_f64.hip, kernels_f32.hip).
 void launch_init(hipStream_t st, const Problem &P, int grid, int vec, const double *rhs, int full,
@@ -228,9 +186,6 @@ void launch_check_vec(hipStream_t st, int64_t n, const double *x, int positive, 
 // out[dst[r] + e] = in[src[r] + e] for e < len(desc[r]) (elements of elem_bytes = 2, 4 or 8)
 void launch_gather_runs(hipStream_t st, int64_t nr, const uint32_t *src, const uint32_t *dst,
                         const uint16_t *desc, const void *in, void *out, int elem_bytes);
-// out[dst[r] + (e / W) 64 W + e mod W] = in[src[r] + e] for e < len(desc[r]) (run slices)
-void launch_scatter_slices(hipStream_t st, int64_t nr, const uint32_t *src, const uint64_t *dst,
-                           const uint16_t *desc, int W, const void *in, void *out, int elem_bytes);
 void launch_convert_f32(hipStream_t st, int64_t nnz, const double *src, float *dst);
 void launch_row_scales(hipStream_t st, int64_t m, const int64_t *rp, const double *val, int vt,
                        float *sigma);

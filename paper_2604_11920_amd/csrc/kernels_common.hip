@@ -115,7 +115,7 @@ int fwd_pipe_parts(int grid) { return LSQR_FWD_WG_ROWS ? grid : grid * (kBlock /
 
 int fwd_pipe_grid(int vec, const RowFmt &R)
 {
-    if (!LSQR_FWD_PIPE || R.run_ptr || R.rmask || R.slot || R.lpr != 64) return 0;
+    if (!LSQR_FWD_PIPE || R.slot || R.lpr != 64) return 0;
     const int per_cu = vec == VT_F64 ? fwd_pipe_blocks_per_cu<double>(R) : fwd_pipe_blocks_per_cu<float>(R);
     int dev = 0, cus = 0;
     if (per_cu < 1 || hipGetDevice(&dev) != hipSuccess ||
@@ -499,40 +499,6 @@ __global__ void k_gather_runs(int64_t nr, const uint32_t *src, const uint32_t *d
         const int len = desc[r] & 255;
         const int64_t s = src[r], d = dst[r];
         for (int e = 0; e < len; ++e) out[d + e] = in[s + e];
-    }
-}
-
-// Run-slice layout: value e of run r goes to dst[r] + (e / W) 64 W + e mod W.
-template <class T>
-__global__ void k_scatter_slices(int64_t nr, const uint32_t *src, const uint64_t *dst,
-                                 const uint16_t *desc, int W, const T *in, T *out)
-{
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nr;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        const int len = desc[r] & 255;
-        const int64_t s = src[r], d = (int64_t)dst[r];
-        for (int e = 0; e < len; ++e) out[d + (int64_t)(e / W) * 64 * W + e % W] = in[s + e];
-    }
-}
-
-void launch_scatter_slices(hipStream_t st, int64_t nr, const uint32_t *src, const uint64_t *dst,
-                           const uint16_t *desc, int W, const void *in, void *out, int elem_bytes)
-{
-    if (nr <= 0) return;
-    const int grid = (int)std::min<int64_t>((nr + 255) / 256, 65536);
-    switch (elem_bytes) {
-    case 8:
-        hipLaunchKernelGGL(k_scatter_slices<uint64_t>, dim3(grid), dim3(256), 0, st, nr, src, dst,
-                           desc, W, (const uint64_t *)in, (uint64_t *)out);
-        break;
-    case 4:
-        hipLaunchKernelGGL(k_scatter_slices<uint32_t>, dim3(grid), dim3(256), 0, st, nr, src, dst,
-                           desc, W, (const uint32_t *)in, (uint32_t *)out);
-        break;
-    default:
-        hipLaunchKernelGGL(k_scatter_slices<uint16_t>, dim3(grid), dim3(256), 0, st, nr, src, dst,
-                           desc, W, (const uint16_t *)in, (uint16_t *)out);
-        break;
     }
 }
 

@@ -188,14 +188,8 @@ struct FwdArgs {
     // data rows
     const int64_t *rp;        // [m+1] value offsets
     const int32_t *ci;        // [nnz] columns (plain CSR) or nullptr
-    const int64_t *run_ptr;   // [m+1] run offsets (depth-run rows) or nullptr
-    const uint32_t *runs;     // (first column << 8) | length
-    const uint16_t *roff;     // value offset of each run within its row
     const void *va;           // [nnz] values of type M
     const float *sigma;       // [m] row scales or nullptr
-    const uint64_t *rmask;    // run masks (see RowFmt) or nullptr
-    const uint32_t *rbase;
-    const int32_t *rcol;
     int64_t m;
     int n, nx, ny, nz;
     double w, damp;
@@ -843,174 +837,6 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol_pair(FwdArgs a)
     if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
 }
 
-// Depth-run rows: one wave per row.  The wave loads up to 64 run descriptors
-// (one per lane, coalesced), expands them into the columns of the next
-// entries of the row in a wave-private LDS window (each run-lane writes its
-// stretch of consecutive columns), then walks the window like a CSR row: lane
-// l takes entries l, l + 64, ... with four entries in flight (value loads and
-// v gathers coalesced and fully active; out-of-range slots load a clamped
-// address and are multiplied by zero, so no branch splits the loads).  The
-// next window's descriptors are loaded while the current one is walked.
-// Index bytes: 6 per run instead of 4 per entry.
-constexpr int kFwdWin = 1024;        // columns per wave window (LDS)
-
-template <class M, class V>
-__global__ __launch_bounds__(kBlock) void k_fwd_runs(FwdArgs a)
-{
-    using A = typename AccOf<V>::type;
-    __shared__ double lds[4];
-    __shared__ int colw[kBlock / 64][kFwdWin];
-    double alpha, beta;
-    if (!fwd_prologue(a, alpha, beta, lds)) return;
-    const M *va = (const M *)a.va;
-    const V *z = (const V *)a.z;
-    double sq = 0.0;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int *cw = colw[wid];
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-#if LSQR_ROW_PREFETCH
-    int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + wid;
-    int64_t vs = 0, rs = 0, re = 0;
-    if (row < a.m) { vs = a.rp[row]; rs = a.run_ptr[row]; re = a.run_ptr[row + 1]; }
-    for (; row < a.m; row += nwaves) {
-        const int64_t nrow = row + nwaves;
-        int64_t nvs = 0, nrs = 0, nre = 0;
-        if (nrow < a.m) { nvs = a.rp[nrow]; nrs = a.run_ptr[nrow]; nre = a.run_ptr[nrow + 1]; }
-        double up = 0.0;
-        if (lane == 0 && a.mode == MODE_ITER) up = (double)((const V *)a.Tprev)[row];
-#else
-    for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + wid; row < a.m; row += nwaves) {
-        const int64_t vs = a.rp[row];
-        const int64_t rs = a.run_ptr[row], re = a.run_ptr[row + 1];
-#endif
-        A acc[4] = {0, 0, 0, 0};
-        int64_t vpos = vs;               // first entry of the current window
-        int64_t base = rs;
-        uint32_t md = 0u;
-        if (base + lane < re) md = __builtin_nontemporal_load(a.runs + base + lane);
-        while (base < re) {
-            // runs of this window: the longest prefix of the (up to 64) loaded
-            // runs whose lengths sum to <= kFwdWin (at least 4: len <= 255)
-            const int len = (int)(md & 255u);
-            int incl = len;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(incl, o);
-                if (lane >= o) incl += y;
-            }
-            const bool in_win = base + lane < re && incl <= kFwdWin;
-            const uint64_t fit = __ballot(in_win);
-            const int nr = __popcll(fit);                  // the fitting runs are a prefix
-            const int tot = nr > 0 ? __shfl(incl, nr - 1) : 0;
-            // expand the window's columns into LDS
-            const int c0 = (int)(md >> 8), off = incl - len;
-            int maxlen = in_win ? len : 0;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o));
-            for (int e = 0; e < maxlen; ++e)
-                if (in_win && e < len) cw[off + e] = c0 + e;
-            // next window's descriptors
-            const int64_t nb = base + nr;
-            uint32_t md_n = 0u;
-            if (nb + lane < re) md_n = __builtin_nontemporal_load(a.runs + nb + lane);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // walk the window's entries [vpos, vpos + tot)
-            for (int q = lane; q < tot; q += 4 * 64) {
-                int c[4];
-                A v[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int qq = q + u * 64 < tot ? q + u * 64 : tot - 1;   // clamped
-                    c[u] = cw[qq];
-                    v[u] = ld_nt<A>(va + vpos + qq);
-                    if (q + u * 64 >= tot) v[u] = 0;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) acc[u] = fma(v[u], (A)z[c[u]], acc[u]);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            vpos += tot;
-            base = nb;             // md_n holds the runs from nb on
-            md = md_n;
-        }
-        const A tot = group_sum<64>((acc[0] + acc[1]) + (acc[2] + acc[3]));
-#if LSQR_ROW_PREFETCH
-        if (lane == 0) sq += fwd_row_out_u<V>(a, row, (double)tot, alpha, beta, up);
-        vs = nvs;
-        rs = nrs;
-        re = nre;
-#else
-        if (lane == 0) sq += fwd_row_out<V>(a, row, (double)tot, alpha, beta);
-#endif
-    }
-    sq += fwd_reg_rows<V>(a, alpha, beta);
-    const double tot = block_sum(sq, lds);
-    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
-}
-
-// Run-mask rows: the CSR values, with the column indices replaced by run
-// masks.  One wave per row walks 64-aligned windows of the value array (lane l
-// of a window takes entry 64 w + l), four windows in flight.  A window's mask
-// word and run base are uniform: the run of entry p is rbase[w] plus the set
-// bits of the mask up to and including bit p (mbcnt), and its column is
-// rcol[run] + (p - row start).  Loads per window: the values, the run
-// descriptors (a few distinct words, one or two cache lines) and the v
-// gathers, as in plain CSR; index bytes fall from 4 per entry to ~0.2 plus
-// 4 per run.
-template <class M, class V>
-__global__ __launch_bounds__(kBlock) void k_fwd_rmask(FwdArgs a)
-{
-    using A = typename AccOf<V>::type;
-    __shared__ double lds[4];
-    double alpha, beta;
-    if (!fwd_prologue(a, alpha, beta, lds)) return;
-    const M *va = (const M *)a.va;
-    const V *z = (const V *)a.z;
-    double sq = 0.0;
-    const int lane = threadIdx.x & 63;
-    const uint64_t lanebit = 1ull << lane;
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); row < a.m;
-         row += nwaves) {
-        const int64_t s = a.rp[row], e = a.rp[row + 1];
-        A acc[4] = {0, 0, 0, 0};
-        for (int64_t w = s >> 6; w * 64 < e; w += 4) {
-            int col[4];
-            A val[4];
-            bool act[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t ww = w + u, p = ww * 64 + lane;
-                act[u] = p >= s && p < e;            // false for every lane past the row
-                col[u] = 0;
-                val[u] = 0;
-                if (ww * 64 < e) {                   // uniform
-                    const uint64_t mk = a.rmask[ww];
-                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
-                    const int64_t r = (int64_t)a.rbase[ww] + below + ((mk & lanebit) ? 1 : 0) - 1;
-                    if (act[u]) {
-                        col[u] = a.rcol[r] + (int)(p - s);
-                        val[u] = ld_nt<A>(va + p);
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (act[u]) acc[u] = fma(val[u], (A)z[col[u]], acc[u]);
-        }
-        const A tot = group_sum<64>((acc[0] + acc[1]) + (acc[2] + acc[3]));
-        if (lane == 0) sq += fwd_row_out<V>(a, row, (double)tot, alpha, beta);
-    }
-    sq += fwd_reg_rows<V>(a, alpha, beta);
-    const double tot = block_sum(sq, lds);
-    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
-}
-
 // ------------------------------------------------------------- transposed --
 struct AdjArgs {
     const int64_t *cp;
@@ -1032,25 +858,12 @@ struct AdjArgs {
     int parity;
     int mode;
     int data_only;           // 1: G^T part only (no smoothing/damping, no scale)
-    int xcd_bands;           // 1: each XCD's workgroups take a contiguous band of columns
     // node runs (k_adj_nruns): see ColFmt
     const int64_t *nrp;
     const int64_t *nvq;
     const uint32_t *nrow;
     const uint16_t *ndesc;
     const int32_t *norder;
-    int nseg[9];
-    // node masks (k_adj_nmask): see ColFmt
-    const int64_t *mrptr;
-    const uint32_t *mrows;
-    const int64_t *mcptr;
-    const uint64_t *mmask;
-    const int64_t *mqoff;
-    // run slices (k_adj_slices): see ColFmt
-    const int64_t *sl_ptr;
-    const int64_t *sl_off;
-    const uint16_t *sl_desc;
-    const uint32_t *sl_row;
 };
 
 // beta_{k+1} from the forward partials (FP64, fixed order); false when the
@@ -1110,17 +923,7 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjArgs a)
     double sq = 0.0;
     constexpr int CPB = kBlock / LPC;
     const int lane = threadIdx.x % LPC;
-    // Columns visited by this workgroup.  With XCD bands, workgroup b (which the
-    // dispatcher places on XCD b % 8) walks a contiguous eighth of the columns,
-    // so each XCD's L2 serves the gathers of one lateral band of the model.
-    int jlo = 0, jhi = a.n, jstart = blockIdx.x * CPB, jstep = gridDim.x * CPB;
-    if (a.xcd_bands && gridDim.x % 8 == 0) {
-        const int band = blockIdx.x & 7, slot = blockIdx.x >> 3;
-        jlo = (int)((int64_t)a.n * band / 8);
-        jhi = (int)((int64_t)a.n * (band + 1) / 8);
-        jstart = jlo + slot * CPB;
-        jstep = (gridDim.x >> 3) * CPB;
-    }
+    const int jhi = a.n, jstart = blockIdx.x * CPB, jstep = gridDim.x * CPB;
 #if LSQR_ROW_PREFETCH
     int j = jstart + threadIdx.x / LPC;
     int64_t s = 0, e = 0;
@@ -1203,21 +1006,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_nruns(AdjArgs a)
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int grp = lane / nz, iz = lane - grp * nz;
     const bool live = grp < ngr;
-    // nodes: serpentine over norder, or, with XCD bands, over band
-    // (blockIdx mod 8) by the workgroups of that XCD
-    int G = gridDim.x, slot = blockIdx.x, nb0 = 0, nnodes = a.n / nz;
-    if (a.xcd_bands && G % 8 == 0) {
-        const int x = blockIdx.x & 7;
-        G >>= 3;
-        slot = blockIdx.x >> 3;
-        nb0 = a.nseg[x];
-        nnodes = a.nseg[x + 1] - nb0;
-    }
+    // nodes: serpentine over norder
+    const int G = gridDim.x, slot = blockIdx.x, nnodes = a.n / nz;
     double sq = 0.0;
     for (int s = 0; s * G < nnodes; ++s) {
         const int idx = s * G + ((s & 1) ? G - 1 - slot : slot);
         if (idx >= nnodes) continue;         // uniform over the workgroup
-        const int node = a.norder[nb0 + idx];
+        const int node = a.norder[idx];
         const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
         const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
         int64_t vb = a.nvq[4 * (int64_t)node + wid];
@@ -1376,19 +1171,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int grp = lane / hz, k2 = W * (lane - grp * hz);  // the lane's depths k2 .. k2 + W - 1
     const bool live = grp < ngr;
-    int G = gridDim.x, slot = blockIdx.x, nb0 = 0, nnodes = a.n / nz;
-    if (a.xcd_bands && G % 8 == 0) {
-        const int x = blockIdx.x & 7;
-        G >>= 3;
-        slot = blockIdx.x >> 3;
-        nb0 = a.nseg[x];
-        nnodes = a.nseg[x + 1] - nb0;
-    }
+    const int G = gridDim.x, slot = blockIdx.x, nnodes = a.n / nz;
     double sq = 0.0;
     for (int s = 0; s * G < nnodes; ++s) {
         const int idx = s * G + ((s & 1) ? G - 1 - slot : slot);
         if (idx >= nnodes) continue;         // uniform over the workgroup
-        const int node = a.norder[nb0 + idx];
+        const int node = a.norder[idx];
         const int64_t rs0 = a.nrp[node], cnt = a.nrp[node + 1] - rs0;
         const int64_t rs = rs0 + cnt * wid / 4, re = rs0 + cnt * (wid + 1) / 4;
         int64_t vb = a.nvq[4 * (int64_t)node + wid];        // a multiple of W
@@ -1463,223 +1251,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
             col += c;
         }
         if (lane < nz) wsum[wid][lane] = col;
-        __syncthreads();
-        if (wid == 0 && lane < nz) {
-            const A g = ((wsum[0][lane] + wsum[1][lane]) + wsum[2][lane]) + wsum[3][lane];
-            sq += adj_col_out<V>(a, node * nz + lane, g, beta);
-        }
-        __syncthreads();
-    }
-    const double tot = block_sum(sq, lds);
-    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
-}
-
-// Transposed product over run slices (see slice_layout_host).  A node's runs
-// are grouped by first depth and cut into slices of 64 runs, one run per
-// lane; a slice stores, for each step of W depths, the 64 lanes' W values
-// side by side, so one wave-wide load (16 bytes per lane for FP64 and FP32,
-// 8 for 16-bit codes) covers W depths of 64 runs with every lane busy
-// (slices hold runs of one first depth sorted by length, so only the last
-// W-step and the slices' length spread are padded with zeros).  A lane
-// gathers t for its run once per slice and accumulates W values per step
-// into per-depth registers relative to the slice's first depth; the step
-// count is uniform over the wave, every index into the registers is a
-// compile-time constant (no private memory).  When the first depth changes,
-// and at the end of the node, each depth register is summed over the wave
-// in a fixed butterfly and added to the lane that holds that depth's column.
-// One workgroup per node (nodes by decreasing work, boustrophedon over the
-// workgroups); wave w takes slices w, w + 4, ... of the node; per column the
-// sum runs over the wave's slices in order, then the butterfly, then the
-// waves in order: deterministic, no atomics.  NZM >= nz (a multiple of W)
-// bounds the depth registers at compile time.
-template <class M> struct SliceW { static constexpr int value = sizeof(M) == 8 ? 2 : 4; };
-
-template <class A, int NZM>
-__device__ __forceinline__ void slice_flush(A (&acc)[NZM], int cls, int lane, A &col)
-{
-#pragma clang fp contract(off)
-#pragma unroll
-    for (int e = 0; e < NZM; ++e) {
-        const A r = group_sum<64>(acc[e]);
-        col = lane == cls + e ? col + r : col;
-        acc[e] = 0;
-    }
-}
-
-// One slice's values (ns steps of W per lane; steps past ns read as zero)
-// and its t, issued together; consumed by slice_fma.
-template <class A, class M, int W, int NS>
-struct SliceBuf {
-    A v[NS][W];
-    A t;
-    int ns, iz0;
-};
-
-template <class A, class M, int W, int NS, class V>
-__device__ __forceinline__ void slice_issue(const AdjArgs &a, const M *sv, const V *Tg, int64_t sl,
-                                            uint32_t row, int lane, SliceBuf<A, M, W, NS> &b)
-{
-    const uint32_t d = a.sl_desc[sl];
-    b.iz0 = (int)(d >> 8);
-    b.ns = (int)(d & 255u) / W;
-    const M *p = sv + a.sl_off[sl] + lane * W;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        if (k < b.ns) {
-            ld_word<A, M, W>(p + k * 64 * W, b.v[k]);
-        } else {
-#pragma unroll
-            for (int h = 0; h < W; ++h) b.v[k][h] = 0;
-        }
-    }
-    b.t = (A)Tg[row];
-}
-
-template <class A, class M, int W, int NS, int NZM>
-__device__ __forceinline__ void slice_fma(const SliceBuf<A, M, W, NS> &b, A (&acc)[NZM], int &cls,
-                                          int lane, A &col)
-{
-#pragma clang fp contract(off)
-    if (b.iz0 != cls) {
-        if (cls >= 0) slice_flush<A, NZM>(acc, cls, lane, col);
-        cls = b.iz0;
-    }
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        if (k < b.ns) {
-#pragma unroll
-            for (int h = 0; h < W; ++h) acc[k * W + h] = fma(b.v[k][h], b.t, acc[k * W + h]);
-        }
-    }
-}
-
-// Two slices in flight per wave: the next slice's values and t are issued
-// before the current slice's multiply-adds (loads complete in issue order,
-// so the wait covers only the older slice).
-template <class M, class V, int NZM>
-__global__ __launch_bounds__(kBlock) void k_adj_slices(AdjArgs a)
-{
-#pragma clang fp contract(off)
-    using A = typename AccOf<V>::type;
-    constexpr int W = SliceW<M>::value, NS = NZM / W;
-    static_assert(NZM % W == 0, "depth bound: a multiple of the step width");
-    __shared__ double lds[4];
-    __shared__ A wsum[kBlock / 64][64];
-    double beta;
-    if (!adj_prologue(a, beta, lds)) return;
-    const M *sv = (const M *)a.cv;
-    const V *Tg = (const V *)a.Tg;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int G = gridDim.x, slot = blockIdx.x, nnodes = a.n / a.nz;
-    double sq = 0.0;
-    for (int s = 0; s * G < nnodes; ++s) {
-        const int idx = s * G + ((s & 1) ? G - 1 - slot : slot);
-        if (idx >= nnodes) continue;         // uniform over the workgroup
-        const int node = a.norder[idx];
-        const int64_t s1 = a.sl_ptr[node + 1];
-        int64_t sl = a.sl_ptr[node] + wid;
-        A acc[NZM];
-#pragma unroll
-        for (int e = 0; e < NZM; ++e) acc[e] = 0;
-        A col = 0;
-        int cls = -1;
-        SliceBuf<A, M, W, NS> b0, b1;
-        uint32_t row = 0;
-        if (sl < s1) {
-            row = __builtin_nontemporal_load(a.sl_row + sl * 64 + lane);
-            slice_issue<A, M, W, NS, V>(a, sv, Tg, sl, row, lane, b0);
-            if (sl + 4 < s1) row = __builtin_nontemporal_load(a.sl_row + (sl + 4) * 64 + lane);
-        }
-        // b0 holds slice sl (issued), row holds slice sl + 4's rows
-        while (sl < s1) {
-            const bool more1 = sl + 4 < s1;
-            if (more1) slice_issue<A, M, W, NS, V>(a, sv, Tg, sl + 4, row, lane, b1);
-            if (sl + 8 < s1) row = __builtin_nontemporal_load(a.sl_row + (sl + 8) * 64 + lane);
-            slice_fma<A, M, W, NS, NZM>(b0, acc, cls, lane, col);
-            if (!more1) break;
-            const bool more2 = sl + 8 < s1;
-            if (more2) slice_issue<A, M, W, NS, V>(a, sv, Tg, sl + 8, row, lane, b0);
-            if (sl + 12 < s1) row = __builtin_nontemporal_load(a.sl_row + (sl + 12) * 64 + lane);
-            slice_fma<A, M, W, NS, NZM>(b1, acc, cls, lane, col);
-            sl += 8;
-        }
-        if (cls >= 0) slice_flush<A, NZM>(acc, cls, lane, col);
-        wsum[wid][lane] = col;
-        __syncthreads();
-        if (wid == 0 && lane < a.nz) {
-            const A g = ((wsum[0][lane] + wsum[1][lane]) + wsum[2][lane]) + wsum[3][lane];
-            sq += adj_col_out<V>(a, node * a.nz + lane, g, beta);
-        }
-        __syncthreads();
-    }
-    const double tot = block_sum(sq, lds);
-    if (threadIdx.x == 0) a.part_out[blockIdx.x] = tot;
-}
-
-// Transposed product over node masks: the CSC values, with the row indices
-// replaced by per-node row lists and bit masks.  Node k's rows (the data rows
-// reaching any of its nz columns, ascending) are cut into chunks of 64; lane l
-// of a chunk owns row 64 c + l, gathers t for it once and, for every depth iz,
-// adds its entry when bit l of the chunk's mask word for iz is set.  The set
-// bits enumerate column k nz + iz in CSC order, so the entry sits at the
-// column's running position plus mbcnt of the mask; the running positions are
-// uniform (scalar registers).  A workgroup takes a node (decreasing work,
-// boustrophedon over workgroups); its 4 waves take fixed quarters of the
-// node's chunks, the column sums combine lanes, then waves, in fixed order.
-// NZ >= nz is a compile-time bound (per-depth accumulators in registers).
-template <class M, class V, int NZ>
-__global__ __launch_bounds__(kBlock) void k_adj_nmask(AdjArgs a)
-{
-#pragma clang fp contract(off)
-    using A = typename AccOf<V>::type;
-    __shared__ double lds[4];
-    __shared__ A wsum[kBlock / 64][NZ];
-    double beta;
-    if (!adj_prologue(a, beta, lds)) return;
-    const M *cv = (const M *)a.cv;
-    const V *Tg = (const V *)a.Tg;
-    const int nz = a.nz;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const uint64_t lanebit = 1ull << lane;
-    const int nnodes = a.n / nz;
-    const int G = gridDim.x;
-    double sq = 0.0;
-    for (int s = 0; s * G < nnodes; ++s) {
-        const int idx = s * G + ((s & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
-        if (idx >= nnodes) continue;         // uniform over the workgroup
-        const int node = a.norder[idx];
-        const int64_t c0 = a.mcptr[node], nc = a.mcptr[node + 1] - c0;
-        const int64_t r0 = a.mrptr[node], nrows = a.mrptr[node + 1] - r0;
-        const int64_t cw0 = nc * wid / 4, cw1 = nc * (wid + 1) / 4;
-        int64_t vb[NZ];
-        A acc[NZ];
-#pragma unroll
-        for (int iz = 0; iz < NZ; ++iz) {
-            vb[iz] = iz < nz ? a.mqoff[((int64_t)node * 4 + wid) * nz + iz] : 0;
-            acc[iz] = 0;
-        }
-        for (int64_t c = cw0; c < cw1; ++c) {
-            const int64_t q = c * 64 + lane;
-            const A t = q < nrows ? (A)Tg[__builtin_nontemporal_load(a.mrows + r0 + q)] : (A)0;
-            const uint64_t *mk = a.mmask + (c0 + c) * nz;
-#pragma unroll
-            for (int iz = 0; iz < NZ; ++iz) {
-                if (iz < nz) {                   // uniform
-                    const uint64_t wbits = mk[iz];
-                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(wbits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)wbits, 0u));
-                    if (wbits & lanebit) acc[iz] = fma(ld_nt<A>(cv + vb[iz] + below), t, acc[iz]);
-                    vb[iz] += __builtin_popcountll(wbits);
-                }
-            }
-        }
-#pragma unroll
-        for (int iz = 0; iz < NZ; ++iz) {
-            if (iz < nz) {
-                const A v = group_sum<64>(acc[iz]);
-                if (lane == 0) wsum[wid][iz] = v;
-            }
-        }
         __syncthreads();
         if (wid == 0 && lane < nz) {
             const A g = ((wsum[0][lane] + wsum[1][lane]) + wsum[2][lane]) + wsum[3][lane];
@@ -1927,14 +1498,6 @@ namespace lsqr {
 template <class M, class V>
 static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArgs &a)
 {
-    if (R.rmask) {
-        hipLaunchKernelGGL((k_fwd_rmask<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
-        return;
-    }
-    if (R.run_ptr) {
-        hipLaunchKernelGGL((k_fwd_runs<M, V>), dim3(grid), dim3(kBlock), 0, st, a);
-        return;
-    }
     if (R.slot) {
         const size_t sh = (size_t)R.gcap * sizeof(typename AccOf<V>::type);
         if constexpr (sizeof(M) <= 4) {
@@ -1965,27 +1528,6 @@ static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArg
 template <class M, class V>
 static void adj_launch_m(hipStream_t st, int grid, const ColFmt &C, const AdjArgs &a)
 {
-    if (C.mmask) {
-        switch (C.nzt) {
-        case 8: hipLaunchKernelGGL((k_adj_nmask<M, V, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 16: hipLaunchKernelGGL((k_adj_nmask<M, V, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 24: hipLaunchKernelGGL((k_adj_nmask<M, V, 24>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_adj_nmask<M, V, 32>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        }
-        return;
-    }
-    if (C.sl_ptr) {
-        switch (slice_nzm(a.nz)) {
-        case 8: hipLaunchKernelGGL((k_adj_slices<M, V, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 12: hipLaunchKernelGGL((k_adj_slices<M, V, 12>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 16: hipLaunchKernelGGL((k_adj_slices<M, V, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 20: hipLaunchKernelGGL((k_adj_slices<M, V, 20>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 24: hipLaunchKernelGGL((k_adj_slices<M, V, 24>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 32: hipLaunchKernelGGL((k_adj_slices<M, V, 32>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_adj_slices<M, V, 64>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        }
-        return;
-    }
     if (C.nrp) {
         if (C.pairs) {
             if constexpr (sizeof(M) == 2) {
@@ -2023,8 +1565,7 @@ hipError_t fwd_launch(hipStream_t st, const Problem &P, int grid, const RowFmt &
                       const double *part_v, int np_v, double *S, int *ctl, int parity,
                       double tol, int mode)
 {
-    FwdArgs a{R.rp, R.ci, R.run_ptr, R.runs, R.roff, R.val, R.sigma, R.rmask, R.rbase, R.rcol,
-              P.m, (int)P.n, P.nx, P.ny,
+    FwdArgs a{R.rp, R.ci, R.val, R.sigma, P.m, (int)P.n, P.nx, P.ny,
               P.nz, P.w, P.damp, z, Tprev, Tcur, Ts, part_out, part_v, np_v, S, ctl, parity,
               mode, tol, R.wrow, R.wgrid, R.gp, R.gcp, R.gcol, R.slot, R.ngroups, R.gcap};
     if constexpr (Wide<V>::value) {
@@ -2096,28 +1637,7 @@ int adj_nruns_blocks_per_cu(const ColFmt &C)
 {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
-    if (C.sl_ptr) {
-#define LSQR_SL_OCC(M_, NZM_) hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_slices<M_, V, NZM_>, kBlock, 0)
-#define LSQR_SL_OCCZ(M_) (slice_nzm(C.nzt) == 8 ? LSQR_SL_OCC(M_, 8) : slice_nzm(C.nzt) == 12 ? LSQR_SL_OCC(M_, 12) \
-                          : slice_nzm(C.nzt) == 16 ? LSQR_SL_OCC(M_, 16) : slice_nzm(C.nzt) == 20 ? LSQR_SL_OCC(M_, 20) \
-                          : slice_nzm(C.nzt) == 24 ? LSQR_SL_OCC(M_, 24) : slice_nzm(C.nzt) == 32 ? LSQR_SL_OCC(M_, 32) \
-                          : LSQR_SL_OCC(M_, 64))
-        switch (C.vt) {
-        case VT_F64:
-            if constexpr (Wide<V>::value) e = LSQR_SL_OCCZ(double);
-            break;
-        case VT_F32:
-            if constexpr (!Wide<V>::value) e = LSQR_SL_OCCZ(float);
-            break;
-        case VT_BF16: e = LSQR_SL_OCCZ(bf16_t); break;
-        case VT_F16: e = LSQR_SL_OCCZ(fp16_t); break;
-        default: break;
-        }
-#undef LSQR_SL_OCCZ
-#undef LSQR_SL_OCC
-        return e == hipSuccess ? nb : 0;
-    }
-    if (!C.nrp || C.mmask) return 0;
+    if (!C.nrp) return 0;
 #define LSQR_ADJ_OCC(M_) (C.pairs == 8 && sizeof(M_) == 2                                                              \
                               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_npair<M_, V, (sizeof(M_) == 2 ? 8 : 2)>, kBlock, 0) \
                           : C.pairs == 4 && sizeof(M_) <= 4                                                              \
@@ -2146,10 +1666,8 @@ hipError_t adj_launch(hipStream_t st, const Problem &P, int grid, const ColFmt &
                       int parity, int mode, int data_only)
 {
     AdjArgs a{C.cp, C.ri, C.val, P.m, (int)P.n, P.nx, P.ny, P.nz, P.w, P.damp, d, T, Tg, v, q,
-              part_out, part_t, np_t, S, ctl, parity, mode, data_only, C.xcd_bands,
-              C.nrp, C.nvq, C.nrow, C.ndesc, C.norder, {}, C.mrptr, C.mrows, C.mcptr, C.mmask,
-              C.mqoff, C.sl_ptr, C.sl_off, C.sl_desc, C.sl_row};
-    for (int x = 0; x < 9; ++x) a.nseg[x] = C.nseg[x];
+              part_out, part_t, np_t, S, ctl, parity, mode, data_only,
+              C.nrp, C.nvq, C.nrow, C.ndesc, C.norder};
     switch (C.vt) {
     case VT_F64:
         if constexpr (Wide<V>::value) adj_launch_m<double, V>(st, grid, C, a);

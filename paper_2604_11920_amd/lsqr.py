@@ -22,7 +22,7 @@ LSQR_E_DEVICE, LSQR_E_OOM, LSQR_E_UNSUPPORTED = -4, -5, -6
 MEM_HOST, MEM_DEVICE = 0, 1
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 PRECOND = {"none": 0, "jacobi": 1, "user": 2}
-FLAG_TIMING, FLAG_NO_GRAPH, FLAG_XCD_BANDS = 1, 2, 4
+FLAG_TIMING, FLAG_NO_GRAPH = 1, 2
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -194,16 +194,15 @@ def _is_torch(a):
 class Solver:
     """One regularised LSQR system on the GPU (wraps an lsqr_ctx).
 
-    row_format: "auto" | "csr" | "runs" | "masks" | "groups" (forward product);
-    col_format: "auto" | "csc" | "runs" | "masks" | "pairs" | "slices"
-    (transposed product).  The formats are those of opts.row_format / opts.col_format in
+    row_format: "auto" | "csr" | "groups" (forward product);
+    col_format: "auto" | "csc" | "runs" | "pairs" (transposed product).  The formats are those of opts.row_format / opts.col_format in
     include/lsqr_mi355x.h; "auto" picks row groups and depth pairs where the
     matrix fits them."""
 
     def __init__(self, row_ptr, col, val, nx, ny, nz, damp, smooth, precision="fp64",
                  precond="none", col_scale=None, stream=None, timing=False, graph=True,
                  lanes_per_row=0, lanes_per_col=0, check_every=0, refine_sweeps=5,
-                 row_format="auto", col_format="auto", xcd_bands=False, refine_inner_tol=0.0,
+                 row_format="auto", col_format="auto", refine_inner_tol=0.0,
                  method="lsqr", torch_alloc=True, fallback_iters=0):
         import torch
         lib = load()
@@ -237,13 +236,11 @@ class Solver:
         opts.fallback_iters = int(fallback_iters)
         opts.check_every = int(check_every)
         opts.stream = stream.cuda_stream
-        opts.flags = ((FLAG_TIMING if timing else 0) | (0 if graph else FLAG_NO_GRAPH)
-                      | (FLAG_XCD_BANDS if xcd_bands else 0))
+        opts.flags = (FLAG_TIMING if timing else 0) | (0 if graph else FLAG_NO_GRAPH)
         opts.lanes_per_row = int(lanes_per_row)
         opts.lanes_per_col = int(lanes_per_col)
-        opts.row_format = {"auto": 0, "csr": 1, "runs": 2, "masks": 3, "groups": 4}[row_format]
-        opts.col_format = {"auto": 0, "csc": 1, "runs": 2, "masks": 3, "pairs": 4,
-                           "slices": 5}[col_format]
+        opts.row_format = {"auto": 0, "csr": 1, "groups": 4}[row_format]
+        opts.col_format = {"auto": 0, "csc": 1, "runs": 2, "pairs": 4}[col_format]
         self.precision = precision
         if torch_alloc:
             self._alloc_cb, self._free_cb = torch_allocator(self._device, stream)

@@ -1,19 +1,13 @@
-// CPU driver for the host run builders: reads a CSR structure from a binary
-// file, runs both builders and writes their arrays back for checking.
+// CPU driver for the host layout builders: reads a CSR structure from a
+// binary file, runs the builders and writes their arrays back for checking.
 //   in : int64 m, n, nz, nnz; int64 row_ptr[m+1]; int32 col[nnz]
-//   out: int64 ok_rows, nruns; int64 run_ptr[m+1]; uint32 runs[]; uint16 roff[];
-//        int64 ok_nodes, nnruns, nnodes; int64 nrp[nnodes+1]; int64 nvq[4 nnodes+1];
+//   out: int64 ok_nodes, nnruns, nnodes; int64 nrp[nnodes+1]; int64 nvq[4 nnodes+1];
 //        uint32 row[]; uint32 src[]; uint32 dst[]; uint16 desc[]; int32 order[nnodes];
-//        int64 ok_rmask, nwords, nruns; uint64 mask[]; uint32 base[]; int32 rcol[];
-//        int64 ok_nmask, nnodes, nrows, nchunks; int64 rptr[]; uint32 rows[]; int64 cptr[];
-//        uint64 mask[nchunks nz]; int64 qoff[nnodes 4 nz]; int32 order[];
 //        (node runs built) int64 rrp[m+1]; uint32 rrid[nnruns]  (row order of the runs)
 //        int64 ok_groups, ngroups, ngcols; int32 gp[ngroups+1]; int64 gcp[ngroups+1];
 //        int32 gcol[ngcols]; uint16 slot[nnz]   (row groups of at most CAP columns)
 //        (node runs built, for W = 2, 4 then 8) int64 ok_pairs, total; uint32 dstp[nnruns];
 //        int64 nvqp[4 nnodes+1]
-//        (node runs built, for W = 1, 2 then 4) int64 nslices, total; int64 sptr[nnodes+1];
-//        int64 off[nslices]; uint16 desc[nslices]; uint32 row[64 nslices]; uint64 dst[nnruns]
 // usage: runs_check IN OUT [CAP]   (CAP defaults to 4096)
 #include <stdio.h>
 #include <stdlib.h>
@@ -39,14 +33,6 @@ int main(int argc, char **argv)
     fclose(fi);
     FILE *fo = fopen(argv[2], "wb");
     if (!fo) return 2;
-    std::vector<int64_t> run_ptr;
-    std::vector<uint32_t> runs;
-    std::vector<uint16_t> roff;
-    const int64_t ok1 = lsqr::build_runs_host(m, n, rp.data(), ci.data(), run_ptr, runs, roff);
-    const int64_t nr1 = ok1 ? (int64_t)runs.size() : 0;
-    put(fo, &ok1, 1);
-    put(fo, &nr1, 1);
-    if (ok1) { put(fo, run_ptr.data(), run_ptr.size()); put(fo, runs.data(), runs.size()); put(fo, roff.data(), roff.size()); }
     lsqr::NodeRuns R;
     const int64_t ok2 = lsqr::build_node_runs_host(m, n, (int)nz, rp.data(), ci.data(), R);
     const int64_t nr2 = ok2 ? (int64_t)R.row.size() : 0, nn = ok2 ? n / nz : 0;
@@ -58,26 +44,6 @@ int main(int argc, char **argv)
         put(fo, R.row.data(), R.row.size()); put(fo, R.src.data(), R.src.size());
         put(fo, R.dst.data(), R.dst.size()); put(fo, R.desc.data(), R.desc.size());
         put(fo, R.order.data(), R.order.size());
-    }
-    lsqr::RowMasks M;
-    const int64_t ok3 = lsqr::build_row_masks_host(m, rp.data(), ci.data(), M);
-    const int64_t nw = ok3 ? (int64_t)M.mask.size() : 0, nr3 = ok3 ? (int64_t)M.rcol.size() : 0;
-    put(fo, &ok3, 1);
-    put(fo, &nw, 1);
-    put(fo, &nr3, 1);
-    if (ok3) { put(fo, M.mask.data(), M.mask.size()); put(fo, M.base.data(), M.base.size()); put(fo, M.rcol.data(), M.rcol.size()); }
-    lsqr::NodeMasks K;
-    const int64_t ok4 = lsqr::build_node_masks_host(m, n, (int)nz, rp.data(), ci.data(), K);
-    const int64_t nn4 = ok4 ? n / nz : 0, nrow4 = ok4 ? (int64_t)K.rows.size() : 0;
-    const int64_t nch4 = ok4 ? K.cptr.back() : 0;
-    put(fo, &ok4, 1);
-    put(fo, &nn4, 1);
-    put(fo, &nrow4, 1);
-    put(fo, &nch4, 1);
-    if (ok4) {
-        put(fo, K.rptr.data(), K.rptr.size()); put(fo, K.rows.data(), K.rows.size());
-        put(fo, K.cptr.data(), K.cptr.size()); put(fo, K.mask.data(), K.mask.size());
-        put(fo, K.qoff.data(), K.qoff.size()); put(fo, K.order.data(), K.order.size());
     }
     // row order of the node runs
     if (ok2) {
@@ -105,17 +71,6 @@ int main(int argc, char **argv)
         put(fo, &ok6, 1);
         put(fo, &total, 1);
         put(fo, dstp.data(), dstp.size()); put(fo, nvqp.data(), nvqp.size());
-    }
-    for (int W : {1, 2, 4}) {
-        if (!ok2) break;
-        lsqr::RunSlices S;
-        lsqr::slice_layout_host(R, nn, W, S);
-        const int64_t nsl = (int64_t)S.off.size();
-        put(fo, &nsl, 1);
-        put(fo, &S.total, 1);
-        put(fo, S.sptr.data(), S.sptr.size()); put(fo, S.off.data(), S.off.size());
-        put(fo, S.desc.data(), S.desc.size()); put(fo, S.row.data(), S.row.size());
-        put(fo, S.dst.data(), S.dst.size());
     }
     fclose(fo);
     return 0;

@@ -87,3 +87,20 @@ def test_null_arguments(lib):
     assert lib.lsqr_solve(None, None, 0, 1, 0.0, None, None, None) == L.LSQR_E_INVALID_ARG
     assert lib.lsqr_apply(None, None, None) == L.LSQR_E_INVALID_ARG
     lib.lsqr_destroy(None)
+
+
+@pytest.mark.parametrize("field,value", [("row_format", 2), ("row_format", 3), ("row_format", 5),
+                                         ("col_format", 3), ("col_format", 5), ("flags", 4)])
+def test_create_rejects_unknown_formats_and_flags(lib, field, value):
+    """Only the built formats and flags are accepted (row 0/1/4, column
+    0/1/2/4, flags TIMING and NO_GRAPH); the check comes before any device
+    call."""
+    rp = np.array([0, 2, 3], np.int64)
+    ci = np.array([0, 3, 1], np.int32)
+    va = np.array([1.0, 2.0, 3.0])
+    csr = L.CSR(2, 4, 3, 2, 2, 1, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, L.MEM_HOST)
+    opts = L.Opts()                     # zeros: FP64, no scaling, auto formats
+    setattr(opts, field, value)
+    ctx = ctypes.c_void_p()
+    rc = lib.lsqr_create(ctypes.byref(csr), 0.1, 0.5, ctypes.byref(opts), ctypes.byref(ctx))
+    assert rc == L.LSQR_E_INVALID_ARG, (rc, lib.lsqr_last_error(None).decode())

@@ -69,8 +69,8 @@ def ragged_system(seed=0, integer=False):
 
 
 # stored formats (forward rows, transposed columns) exercised by the solves
-FORMATS = {"auto": ("auto", "auto"), "csc": ("csr", "csc"), "runs": ("runs", "runs"),
-           "masks": ("masks", "masks"), "groups": ("groups", "auto"), "pairs": ("csr", "pairs")}
+FORMATS = {"auto": ("auto", "auto"), "csc": ("csr", "csc"), "runs": ("csr", "runs"),
+           "groups": ("groups", "auto"), "pairs": ("csr", "pairs")}
 
 
 @pytest.fixture(scope="module")
@@ -97,8 +97,8 @@ def test_transpose_matches_library_csc(which, cfg0):
 
 @pytest.mark.parametrize("lanes,row_format,col_format",
                          [(0, "auto", "auto"), (4, "csr", "csc"), (16, "csr", "csc"),
-                          (64, "csr", "csc"), (0, "runs", "runs"), (0, "masks", "masks"),
-                          (0, "groups", "auto"), (0, "groups", "pairs"), (8, "csr", "pairs")])
+                          (64, "csr", "csc"), (0, "csr", "runs"), (0, "groups", "auto"),
+                          (0, "groups", "pairs"), (8, "csr", "pairs")])
 def test_operator_integer_bitwise(lanes, row_format, col_format):
     s = ragged_system(2, integer=True)
     op = oracle.Operator.from_system(s)
@@ -113,8 +113,7 @@ def test_operator_integer_bitwise(lanes, row_format, col_format):
     assert np.array_equal(xg, op.apply_t(ybar))
 
 
-@pytest.mark.parametrize("row_format,col_format", [("csr", "csc"), ("runs", "csc"),
-                                                    ("runs", "runs"), ("masks", "masks"),
+@pytest.mark.parametrize("row_format,col_format", [("csr", "csc"), ("csr", "runs"),
                                                     ("groups", "runs"), ("csr", "pairs")])
 def test_operator_integer_bitwise_tomography_pattern(cfg0, row_format, col_format):
     # the tomography sparsity (runs of depth columns, merged across nodes) with
@@ -197,8 +196,8 @@ def test_operator_random_within_rounding(cfg0, precond):
 
 # --------------------------------------------------------------- solves -----
 @pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"), ("none", "csc"),
-                                         ("jacobi", "runs"), ("jacobi", "masks"),
-                                         ("jacobi", "groups"), ("jacobi", "pairs")])
+                                         ("jacobi", "runs"), ("jacobi", "groups"),
+                                         ("jacobi", "pairs")])
 def test_early_iterates_strict(cfg0, precond, fmt):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
@@ -213,24 +212,8 @@ def test_early_iterates_strict(cfg0, precond, fmt):
             assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0), K
 
 
-@pytest.mark.parametrize("col_format", ["runs", "csc"])
-def test_xcd_bands_iterates(cfg0, col_format):
-    # each XCD's workgroups take a band of nodes (node runs) or columns (CSC):
-    # same iterates as the oracle, only the partial sums are grouped otherwise
-    for s in (cfg0, synth.random_system(500, 8, 6, 5, row_len=(0, 50), seed=31)):
-        op = oracle.Operator.from_system(s)
-        with from_sys(s, col_format=col_format, xcd_bands=True) as sol:
-            for K in (1, 3, 8):
-                ref = op.lsqr(s.dt, K)
-                dm, hist, info = sol.solve(s.dt, K)
-                assert info["iters"] == K
-                assert rel(dm, ref["x"]) <= 1e-10, (K, rel(dm, ref["x"]))
-                assert np.allclose(hist, ref["hist"], rtol=1e-10, atol=0), K
-
-
 @pytest.mark.parametrize("precond,fmt", [("none", "auto"), ("jacobi", "auto"), ("none", "csc"),
-                                         ("none", "runs"), ("none", "masks"), ("none", "groups"),
-                                         ("none", "pairs")])
+                                         ("none", "runs"), ("none", "groups"), ("none", "pairs")])
 def test_converged_strict(cfg0, cfg0_xstar, precond, fmt):
     s = cfg0
     d = oracle.Operator.from_system(s).jacobi() if precond == "jacobi" else None
@@ -275,7 +258,7 @@ def test_tolerance_stop(cfg0):
     assert eta <= 2 * tol
 
 
-@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks", "groups", "pairs"])
+@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "groups", "pairs"])
 def test_ragged_system_strict(fmt):
     s = ragged_system(5)
     rf, cf = FORMATS[fmt]
@@ -383,7 +366,7 @@ def test_row_groups_refuse_rows_above_the_cap():
         assert sol.kernel_stats()["row_format"] == 1
 
 
-@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "masks", "groups", "pairs"])
+@pytest.mark.parametrize("fmt", ["auto", "csc", "runs", "groups", "pairs"])
 def test_small_shapes(fmt):
     rf, cf = FORMATS[fmt]
     for grid in [(1, 1, 1), (1, 1, 3), (2, 1, 1), (3, 2, 1)]:

@@ -73,7 +73,7 @@ def test_quantised_codes_bitwise(cfg0, fmt, which):
 @pytest.mark.parametrize("fmt,precond,col_format", [
     ("bf16", "none", "auto"), ("bf16", "jacobi", "auto"), ("fp16", "none", "csc"),
     ("fp16", "jacobi", "auto"), ("bf16", "jacobi", "runs"), ("fp16", "jacobi", "runs"),
-    ("bf16", "jacobi", "masks"), ("fp16", "none", "masks")])
+    ("bf16", "jacobi", "pairs"), ("fp16", "none", "pairs")])
 def test_refinement_reaches_fp64_solution(cfg0, xstar, fmt, precond, col_format):
     # Without column scaling the error at a given eta is ~100x larger on this
     # system (|x - x*| is bounded by cond(Abar^T Abar) eta, ~3e5 unscaled), and
@@ -83,7 +83,6 @@ def test_refinement_reaches_fp64_solution(cfg0, xstar, fmt, precond, col_format)
     tol = 1e-7
     inner = 0.0 if precond == "jacobi" else 1e-3
     with from_sys(cfg0, precision=fmt, precond=precond, refine_sweeps=10, refine_inner_tol=inner,
-                  row_format="masks" if col_format == "masks" else "auto",
                   col_format=col_format) as sol:
         dm, hist, info = sol.solve(cfg0.dt, 3000, tol=tol)
     err = rel(dm, xstar)
@@ -117,8 +116,8 @@ def test_mixed_form_rejections(cfg0):
             sol.solve(cfg0.dt, 100, tol=0.0)
 
 
-@pytest.mark.parametrize("row_format,col_format", [("csr", "csc"), ("runs", "csc"),
-                                                    ("runs", "runs"), ("masks", "masks")])
+@pytest.mark.parametrize("row_format,col_format", [("csr", "csc"), ("csr", "runs"),
+                                                    ("groups", "pairs")])
 def test_fp32_iterates(cfg0, row_format, col_format):
     ref = oracle.lsqr(cfg0, 5)
     with from_sys(cfg0, precision="fp32", row_format=row_format, col_format=col_format) as sol:
@@ -142,7 +141,7 @@ def test_fp32_converged(cfg0, xstar):
     assert info["istop"] == 1 and err <= 3 * err64 + 1e-4
 
 
-@pytest.mark.parametrize("row_format", ["csr", "runs", "masks"])
+@pytest.mark.parametrize("row_format", ["csr", "groups"])
 def test_fp64_row_formats_agree(cfg0, row_format):
     ref = oracle.lsqr(cfg0, 6)
     with from_sys(cfg0, row_format=row_format) as sol:

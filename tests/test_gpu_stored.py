@@ -18,8 +18,7 @@ Systems: rows of odd length starting at every position modulo four, with
 empty rows and an entry count of 3 modulo 4 (the row-group loads in aligned
 pairs for FP64 and quads for the 4- and 2-byte values, and their padding
 elements), the tomography pattern of
-a small ray geometry (row groups, depth pairs and run slices in their real
-shape), and a ragged random structure (short rows, empty columns).
+a small ray geometry (row groups and depth pairs in their real shape), and a ragged random structure (short rows, empty columns).
 """
 import zlib
 
@@ -62,7 +61,7 @@ SYSTEMS = {
     "ragged": lambda: synth.random_system(500, 6, 5, 7, row_len=(0, 40), seed=8),
 }
 
-FORMATS = [("groups", "pairs"), ("groups", "slices"), ("csr", "runs"), ("csr", "csc"),
+FORMATS = [("groups", "pairs"), ("groups", "runs"), ("csr", "runs"), ("csr", "csc"),
            ("auto", "auto")]
 
 
@@ -129,8 +128,8 @@ def test_stored_products_elementwise(system, precision, fmt):
     ey, eq = np.abs(yg - yr), np.abs(qg - qr)
     assert np.all(ey <= ybound), (ks, int(np.argmax(ey / ybound)), float((ey / ybound).max()))
     assert np.all(eq <= qbound), (ks, int(np.argmax(eq / qbound)), float((eq / qbound).max()))
-    if cf == "slices":
-        assert ks["col_format"] == 5
+    if cf == "pairs":
+        assert ks["col_format"] == 4
     if rf == "groups":
         assert ks["row_format"] == 4
 
@@ -143,8 +142,8 @@ def oracle_free_solver(s, kw):
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_stored_integer_bitwise(precision):
     """Integer values and vectors (|entries| <= 8, codes exact in every form):
-    every partial sum is exact, so the slices, pairs and CSC products agree
-    with the oracle to the bit."""
+    every partial sum is exact, so the depth-pair, node-run and CSC products
+    agree with the oracle to the bit."""
     base = synth.make_system(synth.small_config(nx=12, ny=10, nz=9, n_stations=16, n_periods=6,
                                                 region=1.1, seed=9))
     rng = np.random.default_rng(12)
@@ -161,7 +160,7 @@ def test_stored_integer_bitwise(precision):
     kw = dict(precision=precision)
     if precision == "bf16":
         kw["precond"] = "jacobi"
-    for cf in ("slices", "pairs", "csc", "runs"):
+    for cf in ("pairs", "csc", "runs"):
         with oracle_free_solver(s, dict(kw, col_format=cf)) as sol:
             tg = None
             if precision == "bf16":

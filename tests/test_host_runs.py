@@ -1,13 +1,14 @@
-"""CPU checks of the host builders of the run formats (no GPU).
+"""CPU checks of the host builders of the index formats (no GPU).
 
-The forward product's depth runs and the transposed product's node runs are
-built on the host from the CSR structure (csrc/runs_host.h); the kernels index
-memory with them, so they are checked here exhaustively against the CSR they
-describe: every stored entry covered exactly once, runs maximal, node runs in
-ascending row order, value offsets and quarter offsets consistent, the node
-order a stable sort by decreasing run count, and the row order of the node
-runs (the batched forward product's per-row sums) a permutation listing each
-row's runs in the order of its stored entries.
+The forward product's row groups and the transposed product's node runs (and
+their padded layouts) are built on the host from the CSR structure
+(csrc/runs_host.h); the kernels index memory with them, so they are checked
+here exhaustively against the CSR they describe: every stored entry covered
+exactly once, node runs maximal and in ascending row order, value offsets
+and quarter offsets consistent, the node order a stable sort by decreasing
+run count, and the row order of the node runs (the batched forward
+product's per-row sums) a permutation listing each row's runs in the order
+of its stored entries.
 """
 import os
 import shutil
@@ -53,12 +54,6 @@ def run_builders(exe, tmp, row_ptr, col, n, nz, cap=4096):
         return a
 
     out = {}
-    ok1, nr1 = take(np.int64, 2)
-    out["rows_ok"] = bool(ok1)
-    if ok1:
-        out["run_ptr"] = take(np.int64, m + 1)
-        out["runs"] = take(np.uint32, nr1)
-        out["roff"] = take(np.uint16, nr1)
     ok2, nr2, nn = take(np.int64, 3)
     out["nodes_ok"] = bool(ok2)
     if ok2:
@@ -69,21 +64,6 @@ def run_builders(exe, tmp, row_ptr, col, n, nz, cap=4096):
         out["dst"] = take(np.uint32, nr2)
         out["desc"] = take(np.uint16, nr2)
         out["order"] = take(np.int32, nn)
-    ok3, nw, nr3 = take(np.int64, 3)
-    out["rmask_ok"] = bool(ok3)
-    if ok3:
-        out["rmask"] = take(np.uint64, nw)
-        out["rbase"] = take(np.uint32, nw)
-        out["rcol"] = take(np.int32, nr3)
-    ok4, nn4, nrow4, nch4 = take(np.int64, 4)
-    out["nmask_ok"] = bool(ok4)
-    if ok4:
-        out["m_rptr"] = take(np.int64, nn4 + 1)
-        out["m_rows"] = take(np.uint32, nrow4)
-        out["m_cptr"] = take(np.int64, nn4 + 1)
-        out["m_mask"] = take(np.uint64, nch4 * nz)
-        out["m_qoff"] = take(np.int64, nn4 * 4 * nz)
-        out["m_order"] = take(np.int32, nn4)
     if ok2:
         out["rrp"] = take(np.int64, m + 1)
         out["rrid"] = take(np.uint32, nr2)
@@ -100,73 +80,8 @@ def run_builders(exe, tmp, row_ptr, col, n, nz, cap=4096):
         out[f"pad_total{W}"] = int(tot6)
         out[f"dstp{W}"] = take(np.uint32, nr2)
         out[f"nvqp{W}"] = take(np.int64, 4 * nn + 1)
-    for W in ((1, 2, 4) if ok2 else ()):
-        nsl, tot = take(np.int64, 2)
-        out[f"sl_total{W}"] = int(tot)
-        out[f"sptr{W}"] = take(np.int64, nn + 1)
-        out[f"soff{W}"] = take(np.int64, nsl)
-        out[f"sdesc{W}"] = take(np.uint16, nsl)
-        out[f"srow{W}"] = take(np.uint32, 64 * nsl)
-        out[f"sdst{W}"] = take(np.uint64, nr2)
     assert pos == len(buf)
     return out
-
-
-def bits_of(words, count):
-    """Bit p of a little-endian array of u64 words, for p < count."""
-    b = np.unpackbits(np.asarray(words, dtype='<u8').view(np.uint8), bitorder="little")
-    return b[:count].astype(bool)
-
-
-def check_row_masks(o, row_ptr, col):
-    nnz = len(col)
-    mask, base, rcol = o["rmask"], o["rbase"], o["rcol"]
-    bits = bits_of(mask, nnz)
-    row = np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
-    starts = np.ones(nnz, bool)
-    starts[1:] = (col[1:] != col[:-1] + 1) | (row[1:] != row[:-1])
-    assert np.array_equal(bits, starts)
-    pc = np.array([bin(int(w)).count("1") for w in mask], np.int64)
-    assert np.array_equal(base.astype(np.int64), np.concatenate([[0], np.cumsum(pc)[:-1]]))
-    assert len(rcol) == starts.sum()
-    ridx = np.cumsum(starts) - 1              # run of every entry
-    # what the kernel computes: base of the word + set bits up to and including p
-    p = np.arange(nnz)
-    incl = np.array([bin(int(mask[q >> 6]) & ((2 << (q & 63)) - 1)).count("1")
-                     for q in map(int, p)]) if nnz < 200000 else None
-    if incl is not None:
-        assert np.array_equal(base[p >> 6].astype(np.int64) + incl - 1, ridx)
-    assert np.array_equal(rcol[ridx].astype(np.int64) + (p - row_ptr[row]), col)
-
-
-def check_node_masks(o, row_ptr, col, n, nz):
-    rptr, rows, cptr, mask, qoff, order = (o[k] for k in
-                                           ("m_rptr", "m_rows", "m_cptr", "m_mask", "m_qoff", "m_order"))
-    nn = n // nz
-    row = np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
-    node = col // nz
-    # rows of each node: the ascending unique rows with an entry in the node
-    for k in range(nn):
-        ref = np.unique(row[node == k])
-        assert np.array_equal(rows[rptr[k]:rptr[k + 1]], ref)
-        assert cptr[k + 1] - cptr[k] == (len(ref) + 63) // 64
-    colptr = np.concatenate([[0], np.cumsum(np.bincount(col, minlength=n))])
-    for k in range(nn):
-        rk = rows[rptr[k]:rptr[k + 1]].astype(np.int64)
-        c0, nc = cptr[k], cptr[k + 1] - cptr[k]
-        for iz in range(nz):
-            j = k * nz + iz
-            words = mask[(c0 + np.arange(nc)) * nz + iz]
-            b = bits_of(words, len(rk))
-            assert not bits_of(words, 64 * nc)[len(rk):].any()
-            # the set bits, in order, are the column's rows in CSC order
-            assert np.array_equal(rk[b], np.sort(row[col == j]))
-            pos = colptr[j]
-            for w in range(4):
-                cw = nc * w // 4
-                assert qoff[(k * 4 + w) * nz + iz] == colptr[j] + b[:64 * cw].sum()
-    counts = np.diff(cptr)
-    assert np.array_equal(order, np.argsort(-counts, kind="stable"))
 
 
 def check_row_groups(o, row_ptr, col, cap):
@@ -188,25 +103,6 @@ def check_row_groups(o, row_ptr, col, cap):
         if g + 2 < len(gp):                        # greedy: the next row did not fit
             nxt = col[row_ptr[gp[g + 1]]:row_ptr[gp[g + 1] + 1]]
             assert len(np.union1d(lst, nxt)) > cap
-
-
-def check_row_runs(o, row_ptr, col):
-    rp, runs, roff, run_ptr = row_ptr, o["runs"], o["roff"], o["run_ptr"]
-    m = len(rp) - 1
-    assert run_ptr[0] == 0 and np.all(np.diff(run_ptr) >= 0) and run_ptr[-1] == len(runs)
-    for i in range(m):
-        cols = col[rp[i]:rp[i + 1]]
-        pos = 0
-        prev_end, prev_len = None, None
-        for r in range(run_ptr[i], run_ptr[i + 1]):
-            c0, ln = int(runs[r] >> 8), int(runs[r] & 255)
-            assert ln >= 1 and roff[r] == pos
-            assert np.array_equal(cols[pos:pos + ln], np.arange(c0, c0 + ln))
-            if prev_end is not None:      # maximal unless split at 255 entries
-                assert c0 != prev_end or prev_len == 255
-            prev_end, prev_len = c0 + ln, ln
-            pos += ln
-        assert pos == len(cols)
 
 
 def check_node_runs(o, row_ptr, col, n, nz):
@@ -252,16 +148,13 @@ def check_node_runs(o, row_ptr, col, n, nz):
 def test_small_config(driver, tmp_path):
     s = synth.make_system(synth.small_config(nx=8, ny=8, nz=6, n_stations=14, seed=2))
     o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
-    assert o["rows_ok"] and o["nodes_ok"]
-    check_row_runs(o, s.row_ptr, s.col)
+    assert o["nodes_ok"]
     check_node_runs(o, s.row_ptr, s.col, s.n, s.nz)
-    check_row_masks(o, s.row_ptr, s.col)
-    check_node_masks(o, s.row_ptr, s.col, s.n, s.nz)
 
 
 def test_full_depth_rows_cross_node_boundaries(driver, tmp_path):
-    # every row covers all depths of consecutive lateral nodes: one forward
-    # run spans several nodes, node runs split it at every node boundary
+    # every row covers all depths of consecutive lateral nodes: node runs
+    # split each row at every node boundary
     nx, ny, nz = 6, 5, 4
     n = nx * ny * nz
     rng = np.random.default_rng(3)
@@ -273,11 +166,7 @@ def test_full_depth_rows_cross_node_boundaries(driver, tmp_path):
     rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])])
     col = np.concatenate(rows)
     o = run_builders(driver, tmp_path, rp, col, n, nz)
-    check_row_runs(o, rp, col)
     check_node_runs(o, rp, col, n, nz)
-    check_row_masks(o, rp, col)
-    check_node_masks(o, rp, col, n, nz)
-    assert len(o["runs"]) == len(rows)            # one forward run per row
     assert len(o["row"]) == sum(len(r) // nz for r in rows)
 
 
@@ -295,19 +184,6 @@ def test_random_structure_with_gaps_and_empty_rows(driver, tmp_path):
     rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])])
     col = np.concatenate(rows)
     o = run_builders(driver, tmp_path, rp, col, n, nz)
-    check_row_runs(o, rp, col)
-    check_node_runs(o, rp, col, n, nz)
-    check_row_masks(o, rp, col)
-    check_node_masks(o, rp, col, n, nz)
-
-
-def test_long_rows_split_at_255(driver, tmp_path):
-    n, nz = 1000, 1
-    rp = np.array([0, 700, 700, 1000])
-    col = np.concatenate([np.arange(0, 700), np.arange(100, 400)])
-    o = run_builders(driver, tmp_path, rp, col, n, nz)
-    check_row_runs(o, rp, col)
-    assert [int(x & 255) for x in o["runs"]] == [255, 255, 190, 255, 45]
     check_node_runs(o, rp, col, n, nz)
 
 
@@ -316,13 +192,12 @@ def test_node_runs_refused_for_deep_grids(driver, tmp_path):
     rp = np.array([0, 3])
     col = np.array([0, 1, 70])
     o = run_builders(driver, tmp_path, rp, col, n, nz)
-    assert o["rows_ok"] and not o["nodes_ok"] and o["rmask_ok"] and not o["nmask_ok"]
+    assert not o["nodes_ok"]
 
 
 def test_config0(driver, tmp_path):
     s = synth.make_system(synth.config0())
     o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
-    check_row_runs(o, s.row_ptr, s.col)
     # node runs: vectorised subset of the checks (the system is ~1M entries)
     nrp, row, src, desc, dst = o["nrp"], o["row"], o["src"], o["desc"], o["dst"]
     ln = (desc & 255).astype(np.int64)
@@ -432,90 +307,6 @@ def test_pair_layout(driver, tmp_path):
               synth.random_system(200, 3, 3, 1, row_len=(0, 6), seed=4)):
         o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
         assert o["nodes_ok"] and o["pairs_ok2"] and o["pairs_ok4"] and o["pairs_ok8"]
+        check_node_runs(o, s.row_ptr, s.col, s.n, s.nz)     # nz = 6, 9 and 1
         for W in (2, 4, 8):
             check_pair_layout(o, s.nz, W)
-
-
-def check_slices(o, row_ptr, col, n, nz, W, rng):
-    """The run-slice layout: every run in exactly one lane of one slice of its
-    node, slices of one first depth and at most 64 runs, padded lengths a
-    multiple of W and at least each run's length, offsets contiguous; and the
-    transposed product computed through the layout exactly as the kernel
-    sums it (per lane over its slices, lanes, waves) equals the CSC product
-    on integer data, where every order of the sum gives the same result."""
-    nn = n // nz
-    sptr, off, desc, srow, dst = (o[f"{k}{W}"] for k in ("sptr", "soff", "sdesc", "srow", "sdst"))
-    nrp, rrow, rsrc, rdesc = o["nrp"], o["row"], o["src"], o["desc"]
-    nsl = len(off)
-    assert sptr[0] == 0 and sptr[-1] == nsl and np.all(np.diff(sptr) >= 0)
-    L = (desc & 255).astype(np.int64)
-    iz0 = (desc >> 8).astype(np.int64)
-    assert np.all(L % W == 0) and np.all(L > 0)
-    assert off[0] == 0 if nsl else True
-    assert np.array_equal(np.r_[off[1:], o[f"sl_total{W}"]] - off, 64 * L)
-    # lane of each run, slice of each run
-    rel = dst.astype(np.int64)
-    sl_of = np.searchsorted(off, rel, side="right") - 1
-    lane = (rel - off[sl_of]) // W
-    assert np.all((rel - off[sl_of]) % W == 0) and np.all((lane >= 0) & (lane < 64))
-    pairs = sl_of * 64 + lane
-    assert len(np.unique(pairs)) == len(pairs)                # one run per lane
-    assert np.all(srow[pairs] == rrow)
-    node_of_run = np.repeat(np.arange(nn), np.diff(nrp))
-    node_of_sl = np.repeat(np.arange(nn), np.diff(sptr))
-    assert np.array_equal(node_of_sl[sl_of], node_of_run)       # slice of the run's node
-    assert np.array_equal(iz0[sl_of], (rdesc >> 8).astype(np.int64))
-    assert np.all(L[sl_of] >= (rdesc & 255))
-    used = np.zeros(64 * nsl, bool)
-    used[pairs] = True
-    assert np.all(srow[~used] == 0)                             # padding lanes: row 0
-    # the product through the layout (integer values, exact)
-    m = len(row_ptr) - 1
-    val = rng.integers(-8, 9, len(col)).astype(np.float64)
-    t = rng.integers(-8, 9, m).astype(np.float64)
-    lay = np.zeros(o[f"sl_total{W}"] + W)
-    for r in range(len(rrow)):
-        ln = int(rdesc[r] & 255)
-        e = np.arange(ln)
-        lay[rel[r] + (e // W) * 64 * W + e % W] = val[int(rsrc[r]) + e]
-    q = np.zeros(n)
-    for k in range(nn):
-        for sl in range(sptr[k], sptr[k + 1]):
-            for e in range(L[sl]):
-                v = lay[off[sl] + (e // W) * 64 * W + np.arange(64) * W + e % W]
-                if iz0[sl] + e >= nz:               # padding past the deepest node
-                    assert not np.any(v)
-                    continue
-                q[k * nz + iz0[sl] + e] += np.dot(v, t[srow[sl * 64:(sl + 1) * 64]])
-    row = np.repeat(np.arange(m), np.diff(row_ptr))
-    ref = np.zeros(n)
-    np.add.at(ref, col, val * t[row])
-    assert np.array_equal(q, ref)
-
-
-def test_run_slices(driver, tmp_path):
-    rng = np.random.default_rng(3)
-    s = synth.make_system(synth.small_config(nx=6, ny=5, nz=7, n_stations=10, n_periods=4,
-                                             region=0.5, seed=2))
-    o = run_builders(driver, tmp_path, s.row_ptr, s.col, s.n, s.nz)
-    assert o["nodes_ok"]
-    for W in (1, 2, 4):
-        check_slices(o, s.row_ptr, s.col, s.n, s.nz, W, rng)
-
-
-def test_run_slices_irregular_runs(driver, tmp_path):
-    """Random structure: runs of every first depth and length, gaps, empty
-    rows, nodes with more than 64 runs of one first depth."""
-    rng = np.random.default_rng(4)
-    nx, ny, nz = 3, 2, 9
-    n = nx * ny * nz
-    rows = []
-    for i in range(400):
-        cols = np.sort(rng.choice(n, size=rng.integers(0, 25), replace=False))
-        rows.append(cols)
-    row_ptr = np.r_[0, np.cumsum([len(c) for c in rows])].astype(np.int64)
-    col = np.concatenate(rows).astype(np.int32)
-    o = run_builders(driver, tmp_path, row_ptr, col, n, nz)
-    assert o["nodes_ok"]
-    for W in (1, 2, 4):
-        check_slices(o, row_ptr, col, n, nz, W, rng)
