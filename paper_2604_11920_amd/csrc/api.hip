@@ -90,9 +90,10 @@ int cap_blocks(int64_t work, int per, int cap)
 #endif
 constexpr bool kF32FourDepths = LSQR_F32_FOUR_DEPTHS;
 // 16-bit codes of the transposed product: depths per lane and load (4: one
-// 8-byte load, 8: one 16-byte load).
+// 8-byte load, 8: one 16-byte load; 8 measured 2-3 % faster on the
+// paper-shaped system, BF16 423 -> 412 us, for 215 M padding codes against 80 M).
 #ifndef LSQR_Q_DEPTHS
-#define LSQR_Q_DEPTHS 4
+#define LSQR_Q_DEPTHS 8
 #endif
 constexpr int kQDepths = LSQR_Q_DEPTHS;
 

@@ -1136,15 +1136,17 @@ __device__ __forceinline__ void ld_word(const M *p, A (&x)[W])
 // (chunks, runs of a group, groups, waves): no atomics.
 // Runs per group and chunk.  A chunk holds at most 64 runs (one descriptor
 // per lane), so with W = 4 (12 groups per wave at nz = 20) 6 runs per group
-// already cover it; more would only issue masked loads.
+// already cover it and more only issue masked loads; with the wave-uniform
+// wave index 5 measured best (FP32 571 -> 545 us on the paper-shaped system;
+// 4: 736 us), and 3 at W = 8 (21 groups per wave).
 #ifndef LSQR_PAIR_RPG2
 #define LSQR_PAIR_RPG2 10
 #endif
 #ifndef LSQR_PAIR_RPG4
-#define LSQR_PAIR_RPG4 6
+#define LSQR_PAIR_RPG4 5
 #endif
 #ifndef LSQR_PAIR_RPG8
-#define LSQR_PAIR_RPG8 4
+#define LSQR_PAIR_RPG8 3
 #endif
 template <int W> struct PairRPG {
     static constexpr int value = W == 2 ? LSQR_PAIR_RPG2 : W == 4 ? LSQR_PAIR_RPG4 : LSQR_PAIR_RPG8;

@@ -469,7 +469,7 @@ def test_depth_pairs_deep_and_shallow_grids(nz):
             assert rel(dm, ref["x"]) <= 1e-10, (nz, K, rel(dm, ref["x"]))
     xr = op.apply_t(y)
     assert np.abs(xg - xr).max() <= 1e-12 * max(np.abs(xr).max(), 1.0)
-    # the BF16 codes in the four-depth layout (a lane owns depths 4k .. 4k+3)
+    # the BF16 codes eight depths to a word (a lane owns depths 8k .. 8k+7)
     kw = dict(precision="bf16", precond="jacobi", refine_sweeps=10)
     with from_sys(s, col_format="pairs", **kw) as sol:
         dq, _, _ = sol.solve(s.dt, 5000, tol=1e-7)
