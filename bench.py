@@ -189,7 +189,7 @@ def kernel_label(tag, ks):
         if rf == 4:
             e = ks["fwd_entries_per_load"]
             return (f"k_fwd_lcol_pair<{e}> (forward product, row groups, entries in aligned "
-                    + {2: "pairs)", 4: "quads)"}[e] if e > 1 else
+                    + {2: "pairs)", 4: "quads)", 8: "octets)"}[e] if e > 1 else
                     "k_fwd_lcol (forward product, row groups, columns staged in LDS)")
         return "k_fwd_pipe / k_fwd_csr (forward product, CSR rows)"
     cf = ks["col_format"]

@@ -186,7 +186,8 @@ typedef struct {
     int col_format;             /* transposed product: 1 CSC, 2 node runs, 4 node     */
                                 /* runs in the depth-pair (four-depth) layout         */
     int fwd_entries_per_load;   /* row groups: entries a lane reads per load (1; 2:    */
-                                /* aligned pairs, 4: aligned quads, k_fwd_lcol_pair)   */
+                                /* aligned pairs, 4: quads, 8: octets of 16-bit codes; */
+                                /* k_fwd_lcol_pair)                                    */
     int adj_depths_per_word;    /* node-run layouts: depths per lane and load (1 plain */
                                 /* runs, 2 depth pairs, 4 four-depth words)            */
     int64_t groups;             /* row groups of the forward product (0 otherwise)     */

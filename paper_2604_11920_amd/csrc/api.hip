@@ -458,7 +458,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
 
     c->rp = ctx_alloc<int64_t>(c, m + 1);
     c->ci = ctx_alloc<int32_t>(c, nnz);
-    c->va = ctx_alloc<double>(c, nnz + 4);       // zeros past the end (entries in pairs / quads)
+    c->va = ctx_alloc<double>(c, nnz + 8);       // zeros past the end (entries in groups of 2-8)
     c->cp = ctx_alloc<int64_t>(c, n + 1);
     c->ri = ctx_alloc<int32_t>(c, nnz);
     c->cv = ctx_alloc<double>(c, nnz);
@@ -486,7 +486,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         CR_TRY(hipMemcpyAsync(c->ci, G->col_idx, nnz * sizeof(int32_t), kind, st));
         CR_TRY(hipMemcpyAsync(c->va, G->val, nnz * sizeof(double), kind, st));
     }
-    CR_TRY(hipMemsetAsync(c->va + nnz, 0, 4 * sizeof(double), st));
+    CR_TRY(hipMemsetAsync(c->va + nnz, 0, 8 * sizeof(double), st));
     std::vector<int64_t> hrp;
     std::vector<int32_t> hci;
     const int64_t *hrow = G->row_ptr;
@@ -606,14 +606,14 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
             c->gp = ctx_alloc<int32_t>(c, c->ngroups + 1);
             c->gcp = ctx_alloc<int64_t>(c, c->ngroups + 1);
             c->gcol = ctx_alloc<int32_t>(c, std::max<int64_t>(c->ngcols, 1));
-            c->slot = ctx_alloc<uint16_t>(c, nnz + 4);
+            c->slot = ctx_alloc<uint16_t>(c, nnz + 8);
             if (!c->gp || !c->gcp || !c->gcol || !c->slot) return bail(LSQR_E_OOM, "device allocation failed");
             CR_TRY(hipMemcpy(c->gp, RG.gp.data(), (c->ngroups + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
             CR_TRY(hipMemcpy(c->gcp, RG.gcp.data(), (c->ngroups + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
             if (c->ngcols)
                 CR_TRY(hipMemcpy(c->gcol, RG.gcol.data(), c->ngcols * sizeof(int32_t), hipMemcpyHostToDevice));
             CR_TRY(hipMemcpy(c->slot, RG.slot.data(), nnz * sizeof(uint16_t), hipMemcpyHostToDevice));
-            CR_TRY(hipMemset(c->slot + nnz, 0, 4 * sizeof(uint16_t)));
+            CR_TRY(hipMemset(c->slot + nnz, 0, 8 * sizeof(uint16_t)));
         }
     }
     // FP64 formats
@@ -621,7 +621,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     c->R64.lpr = o.lanes_per_row ? o.lanes_per_row : pick_lanes(avg_row);
     if (c->slot) {
         c->R64.gp = c->gp; c->R64.gcp = c->gcp; c->R64.gcol = c->gcol; c->R64.slot = c->slot;
-        c->R64.ngroups = c->ngroups; c->R64.gcap = c->gcap; c->R64.padded = 4;
+        c->R64.ngroups = c->ngroups; c->R64.gcap = c->gcap; c->R64.padded = 8;
     }
     c->C64.vt = VT_F64; c->C64.cp = c->cp; c->C64.ri = c->ri; c->C64.val = c->cv;
     c->C64.lpc = o.lanes_per_col ? o.lanes_per_col : pick_lanes(avg_col);
@@ -654,10 +654,10 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     }
     int vec = VT_F64;
     if (o.precision == LSQR_FP32) {
-        c->va32 = ctx_alloc<float>(c, nnz + 4);     // with va's padding elements
+        c->va32 = ctx_alloc<float>(c, nnz + 8);     // with va's padding elements
         c->cv32 = ctx_alloc<float>(c, nnz);
         if (!c->va32 || !c->cv32) return bail(LSQR_E_OOM, "device allocation failed");
-        launch_convert_f32(st, nnz + 4, c->va, c->va32);
+        launch_convert_f32(st, nnz + 8, c->va, c->va32);
         launch_convert_f32(st, nnz, c->cv, c->cv32);
         R.vt = VT_F32; R.val = c->va32;
         C.vt = VT_F32; C.val = c->cv32;
@@ -683,7 +683,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     } else if (mixed) {
         const int vt = o.precision == LSQR_BF16 ? VT_BF16 : VT_F16;
         c->sigma = ctx_alloc<float>(c, std::max<int64_t>(m, 1));
-        c->qrow = ctx_alloc<uint16_t>(c, nnz + 4);  // zero codes past the end
+        c->qrow = ctx_alloc<uint16_t>(c, nnz + 8);  // zero codes past the end
         c->qcol = ctx_alloc<uint16_t>(c, nnz);
         c->xbuf = ctx_alloc<double>(c, n);
         c->rbar = ctx_alloc<double>(c, mb);
@@ -692,7 +692,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
         if (!c->sigma || !c->qrow || !c->qcol || !c->xbuf || !c->rbar || !c->gbuf || !c->fbuf)
             return bail(LSQR_E_OOM, "device allocation failed");
         launch_row_scales(st, m, c->rp, c->va, vt, c->sigma);
-        CR_TRY(hipMemsetAsync(c->qrow + nnz, 0, 4 * sizeof(uint16_t), st));
+        CR_TRY(hipMemsetAsync(c->qrow + nnz, 0, 8 * sizeof(uint16_t), st));
         launch_quantise_rows(st, m, c->rp, c->va, c->sigma, vt, c->qrow);
         launch_quantise_cols(st, nnz, c->ri, c->cv, c->sigma, vt, c->qcol);
         R.vt = vt; R.val = c->qrow; R.sigma = c->sigma;
@@ -1210,7 +1210,11 @@ lsqr_status lsqr_kernel_stats(const lsqr_ctx *c, lsqr_kstats *out)
     out->fwd_bytes = fwd;
     out->row_format = E.R.slot ? 4 : 1;
     out->col_format = E.C.nrp ? (E.C.pairs ? 4 : 2) : 1;
-    out->fwd_entries_per_load = !E.R.slot ? 0 : lcol_quads_ok(E.R) ? 4 : lcol_pairs_ok(E.R) ? 2 : 1;
+    out->fwd_entries_per_load = !E.R.slot            ? 0
+                                : lcol_octs_ok(E.R)  ? 8
+                                : lcol_quads_ok(E.R) ? 4
+                                : lcol_pairs_ok(E.R) ? 2
+                                                     : 1;
     out->adj_depths_per_word = E.C.nrp ? (E.C.pairs ? E.C.pairs : 1) : 0;
     out->groups = E.R.slot ? c->ngroups : 0;
     out->staged_cols = E.R.slot ? c->ngcols : 0;

@@ -124,6 +124,19 @@ static inline bool lcol_quads_ok(const RowFmt &R)
            ((uintptr_t)R.slot & 7u) == 0;
 }
 
+// Entries in octets (16-bit codes): eight codes and eight slots, one 16-byte
+// load each, from positions that are multiples of eight, and up to seven
+// elements past the last entry.  Measured on the config-1 system against
+// quads: BF16 532 -> 507 us, FP16 506 -> 467 us.
+#ifndef LSQR_FWD_OCTS
+#define LSQR_FWD_OCTS 1
+#endif
+static inline bool lcol_octs_ok(const RowFmt &R)
+{
+    return LSQR_FWD_OCTS && vt_size(R.vt) == 2 && R.padded >= 7 && ((uintptr_t)R.val & 15u) == 0 &&
+           ((uintptr_t)R.slot & 15u) == 0;
+}
+
 // Stored transpose (CSC) for the transposed product.
 struct ColFmt {
     int vt = VT_F64;

@@ -553,18 +553,20 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pipe(FwdArgs a)
 // the array; such entries are not summed.
 
 // Row groups, E entries per lane and load (E = 2: pairs; E = 4: quads, for
-// 4- and 2-byte values): a row's entries are taken in aligned groups of E
-// (positions p .. p + E - 1, p a multiple of E; the first group of a row
-// that starts inside one holds entries of the previous row, the last may
-// hold the next row's first or, at the end of the arrays, padding elements),
-// so one load brings E values (pairs: 16 bytes for FP64, 8 for FP32, 4 for
-// 16-bit codes; quads: 16 bytes for FP32, 8 for 16-bit codes) and one load
-// their E 16-bit slots.  Entries outside the row are left out of the sums.
-// Pairs halve the load instructions per entry of k_fwd_lcol, quads halve
-// them again.
+// 4- and 2-byte values; E = 8: octets, for 16-bit codes): a row's entries
+// are taken in aligned groups of E (positions p .. p + E - 1, p a multiple
+// of E; the first group of a row that starts inside one holds entries of
+// the previous row, the last may hold the next row's first or, at the end of
+// the arrays, padding elements), so one load brings E values (pairs: 16
+// bytes for FP64, 8 for FP32, 4 for 16-bit codes; quads: 16 bytes for FP32,
+// 8 for 16-bit codes; octets: 16 bytes of 16-bit codes) and one load their
+// E 16-bit slots.  Entries outside the row are left out of the sums.  Pairs
+// halve the load instructions per entry of k_fwd_lcol, quads halve them
+// again, and octets once more.
 typedef double f64x2p __attribute__((ext_vector_type(2)));
 typedef float f32x2p __attribute__((ext_vector_type(2)));
 typedef float f32x4p __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4p __attribute__((ext_vector_type(4)));
 // E raw stored values in one word
 template <class M, int E> struct EntRaw { using type = uint32_t; };          // 2 x 16-bit
 template <> struct EntRaw<double, 2> { using type = f64x2p; };
@@ -572,9 +574,19 @@ template <> struct EntRaw<float, 2> { using type = f32x2p; };
 template <> struct EntRaw<float, 4> { using type = f32x4p; };
 template <> struct EntRaw<bf16_t, 4> { using type = uint64_t; };
 template <> struct EntRaw<fp16_t, 4> { using type = uint64_t; };
+template <> struct EntRaw<bf16_t, 8> { using type = u32x4p; };
+template <> struct EntRaw<fp16_t, 8> { using type = u32x4p; };
 // E 16-bit slots in one word
 template <int E> struct SlotRaw { using type = uint32_t; };
 template <> struct SlotRaw<4> { using type = uint64_t; };
+template <> struct SlotRaw<8> { using type = u32x4p; };
+// 16-bit field k of a word of E of them
+template <int E, class T>
+__device__ __forceinline__ uint32_t half_at(T w, int k)
+{
+    if constexpr (E == 8) return (w[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+    else return (uint32_t)(w >> (16 * k)) & 0xffffu;
+}
 template <class A, class M, int E>
 __device__ __forceinline__ void ent_values(typename EntRaw<M, E>::type r, A (&x)[E])
 {
@@ -583,7 +595,7 @@ __device__ __forceinline__ void ent_values(typename EntRaw<M, E>::type r, A (&x)
         for (int k = 0; k < E; ++k) x[k] = (A)r[k];
     } else {
 #pragma unroll
-        for (int k = 0; k < E; ++k) x[k] = from_raw<A, M>((uint16_t)((r >> (16 * k)) & 0xffffu));
+        for (int k = 0; k < E; ++k) x[k] = from_raw<A, M>((uint16_t)half_at<E>(r, k));
     }
 }
 template <class M, int U, int E>
@@ -718,7 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol(FwdArgs a)
 #ifdef LSQR_FWD_PAIR_U
 template <class M, int E> struct PairU { static constexpr int value = LSQR_FWD_PAIR_U; };
 #else
-template <class M, int E> struct PairU { static constexpr int value = E == 2 ? 3 : 2; };
+template <class M, int E> struct PairU { static constexpr int value = E == 2 ? 3 : E == 4 ? 2 : 1; };
 #endif
 
 // See ent_batch.
@@ -788,7 +800,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol_pair(FwdArgs a)
 #pragma unroll
             for (int u = 0; u < UP; ++u)
 #pragma unroll
-                for (int k = 0; k < E; ++k) zg[u][k] = zl[(uint32_t)(cur.c[u] >> (16 * k)) & 0xffffu];
+                for (int k = 0; k < E; ++k) zg[u][k] = zl[half_at<E>(cur.c[u], k)];
             ent_batch<M, UP, E>(a, va, jn, en, lane, nxt);
 #pragma unroll
             for (int u = 0; u < UP; ++u) {
@@ -1502,6 +1514,12 @@ static void fwd_launch_m(hipStream_t st, int grid, const RowFmt &R, const FwdArg
 {
     if (R.slot) {
         const size_t sh = (size_t)R.gcap * sizeof(typename AccOf<V>::type);
+        if constexpr (sizeof(M) == 2) {
+            if (lcol_octs_ok(R)) {
+                hipLaunchKernelGGL((k_fwd_lcol_pair<M, V, 8>), dim3(grid), dim3(kBlock), sh, st, a);
+                return;
+            }
+        }
         if constexpr (sizeof(M) <= 4) {
             if (lcol_quads_ok(R)) {
                 hipLaunchKernelGGL((k_fwd_lcol_pair<M, V, 4>), dim3(grid), dim3(kBlock), sh, st, a);
@@ -1618,7 +1636,8 @@ int fwd_lcol_blocks_per_cu(const RowFmt &R)
                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<double, V>, kBlock, sh);
     } else {
 #define LSQR_LCOL_OCC(M_)                                                                                   \
-    (lcol_quads_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<M_, V, 4>, kBlock, sh) \
+    (sizeof(M_) == 2 && lcol_octs_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<M_, V, (sizeof(M_) == 2 ? 8 : 4)>, kBlock, sh) \
+     : lcol_quads_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<M_, V, 4>, kBlock, sh) \
      : lcol_pairs_ok(R) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol_pair<M_, V, 2>, kBlock, sh) \
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_lcol<M_, V>, kBlock, sh))
         switch (R.vt) {

@@ -14,10 +14,10 @@ per product; the transposed product likewise with the column's entries and
 the smoothing and damping terms.  The 16-bit forms' transposed product reads
 tg = sigma * y_G (a power-of-two scale: exact), as the solver gathers it.
 
-Systems: rows of odd length starting at every position modulo four, with
-empty rows and an entry count of 3 modulo 4 (the row-group loads in aligned
-pairs for FP64 and quads for the 4- and 2-byte values, and their padding
-elements), the tomography pattern of
+Systems: rows of odd length starting at every position modulo eight, with
+empty rows and an entry count of 7 modulo 8 (the row-group loads in aligned
+pairs for FP64, quads for FP32 and octets for the 16-bit codes, and their
+padding elements), the tomography pattern of
 a small ray geometry (row groups and depth pairs in their real shape), and a ragged random structure (short rows, empty columns).
 """
 import zlib
@@ -45,7 +45,7 @@ def _gpu():
 def odd_bounds_system():
     rng = np.random.default_rng(21)
     n = 1200
-    lens = np.array([3, 0, 401, 400, 5, 1, 0, 777, 2, 2])
+    lens = np.array([3, 0, 401, 400, 5, 1, 0, 777, 2, 2, 7, 9])
     rows = [np.sort(rng.choice(n, size=L, replace=False)) for L in lens]
     row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
     col = np.concatenate(rows).astype(np.int32)
