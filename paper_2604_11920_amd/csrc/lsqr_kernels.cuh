@@ -802,15 +802,20 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol_pair(FwdArgs a)
 #pragma unroll
                 for (int k = 0; k < E; ++k) zg[u][k] = zl[half_at<E>(cur.c[u], k)];
             ent_batch<M, UP, E>(a, va, jn, en, lane, nxt);
+            // entry p + k is in the row when 0 <= p + k - jr < e - jr: one
+            // unsigned 32-bit compare (p - jr lies in [1 - E, e - jr + BP),
+            // rows of row groups hold fewer than 2^31 entries), which keeps
+            // the sum a select rather than a branch per entry
+            const uint32_t len = (uint32_t)(e - jr);
 #pragma unroll
             for (int u = 0; u < UP; ++u) {
-                const int64_t p = cur.e0[u];
+                const int32_t d = (int32_t)(cur.e0[u] - jr);
                 A x[E];
                 ent_values<A, M, E>(cur.r[u], x);
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
                     const A q = fma(x[k], zg[u][k], acc[u]);
-                    acc[u] = (p + k >= jr && p + k < e) ? q : acc[u];
+                    acc[u] = (uint32_t)(d + k) < len ? q : acc[u];
                 }
             }
             jb = jn;
