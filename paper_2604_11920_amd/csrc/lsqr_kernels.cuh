@@ -1165,6 +1165,23 @@ __device__ __forceinline__ void ld_word(const M *p, A (&x)[W])
 #ifndef LSQR_PAIR_RPG8
 #define LSQR_PAIR_RPG8 3
 #endif
+// Inclusive prefix sum over the 64 lanes of a wave, on the VALU with DPP:
+// row shifts by 1, 2, 4 and 8 within rows of 16 lanes (a lane shifted in
+// from outside its row adds zero), then the broadcast of lane 15 into rows 1
+// and 3 and of lane 31 into rows 2 and 3.  In place of six dependent
+// shuffles through the LDS crossbar: BF16 codes 398 -> 385 us on the
+// transposed product of the config-1 system.
+__device__ __forceinline__ int wave_incl_scan(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    return x;
+}
+
 template <int W> struct PairRPG {
     static constexpr int value = W == 2 ? LSQR_PAIR_RPG2 : W == 4 ? LSQR_PAIR_RPG4 : LSQR_PAIR_RPG8;
 };
@@ -1202,60 +1219,69 @@ __global__ __launch_bounds__(kBlock) void k_adj_npair(AdjArgs a)
         A acc[W];
 #pragma unroll
         for (int h = 0; h < W; ++h) acc[h] = 0;
-        int64_t base = rs;
-        int nr = (int)(re - base < ch ? re - base : ch);
-        uint32_t dsc = 0u;
-        A tr = 0;
-        if (lane < nr) {
-            dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
-            tr = (A)Tg[__builtin_nontemporal_load(a.nrow + base + lane)];
-        }
-        while (base < re) {
-            // padded length: iz0 mod W zeros before, and up to a multiple of W
-            const int iz0l = (int)((dsc >> 8) & 255u);
-            const int plen = ((int)(dsc & 255u) + (iz0l & (W - 1)) + W - 1) & ~(W - 1);
-            int incl = plen;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(incl, o);
-                if (lane >= o) incl += y;
+        if (re > rs) {
+            // a chunk's descriptors and T values, loaded one chunk ahead
+            struct Pre {
+                uint32_t dsc;
+                A tr;
+            };
+            Pre s0, s1;
+            int64_t base = rs;
+            int nr = (int)(re - base < ch ? re - base : ch);
+            {
+                // every lane loads (lanes past the chunk reload its first
+                // run), so no load sits under a divergent branch; lanes past
+                // the chunk are masked where the descriptors are used
+                const int64_t li = lane < nr ? base + lane : base;
+                s0.dsc = __builtin_nontemporal_load(a.ndesc + li);
+                s0.tr = (A)Tg[__builtin_nontemporal_load(a.nrow + li)];
             }
-            // (padded offset in the chunk << 16) | (iz0 << 8) | len; offsets < 64 * 68
-            const uint32_t pk = ((uint32_t)(incl - plen) << 16) | dsc;
-            const int tot = __shfl(incl, 63);
-            const int64_t nb = base + nr;
-            const int nn = nb < re ? (int)(re - nb < ch ? re - nb : ch) : 0;
-            uint32_t dsc_n = 0u, row_n = 0u;
-            if (lane < nn) {
-                dsc_n = __builtin_nontemporal_load(a.ndesc + nb + lane);
-                row_n = __builtin_nontemporal_load(a.nrow + nb + lane);
+            auto step = [&](const Pre &cur, Pre &nxt) -> bool {
+                const uint32_t dsc = lane < nr ? cur.dsc : 0u;
+                // padded length: iz0 mod W zeros before, and up to a multiple of W
+                const int iz0l = (int)((dsc >> 8) & 255u);
+                const int plen = ((int)(dsc & 255u) + (iz0l & (W - 1)) + W - 1) & ~(W - 1);
+                const int incl = wave_incl_scan(plen);
+                // (padded offset in the chunk << 16) | (iz0 << 8) | len; offsets < 64 * 68
+                const uint32_t pk = ((uint32_t)(incl - plen) << 16) | dsc;
+                const int tot = __builtin_amdgcn_readlane(incl, 63);
+                const int64_t nb = base + nr;
+                const int nn = nb < re ? (int)(re - nb < ch ? re - nb : ch) : 0;
+                // the next chunk's runs; with none left, this chunk's last
+                // run again (in bounds, never used)
+                const int64_t li = lane < nn ? nb + lane : nb - 1;
+                nxt.dsc = __builtin_nontemporal_load(a.ndesc + li);
+                const uint32_t row_n = __builtin_nontemporal_load(a.nrow + li);
+                A v[RPG][W];
+#pragma unroll
+                for (int u = 0; u < RPG; ++u) {
+                    const int r = grp + u * ngr;
+                    const uint32_t p = __shfl(pk, r & 63);
+                    const int iz0 = (int)((p >> 8) & 255u), lo = iz0 & ~(W - 1);
+                    const bool in = live & (r < nr) & (k2 >= lo) & (k2 < iz0 + (int)(p & 255u));
+                    // a lane outside the run's window reads the quarter's first
+                    // word (a line the wave streams anyway) and drops it
+                    ld_word<A, M, W>(nv + (in ? vb + (int64_t)(p >> 16) + (k2 - lo) : vb), v[u]);
+#pragma unroll
+                    for (int h = 0; h < W; ++h) v[u][h] = in ? v[u][h] : (A)0;
+                }
+                nxt.tr = (A)Tg[row_n];
+                // runs past the chunk carry a finite T value and zero values
+#pragma unroll
+                for (int u = 0; u < RPG; ++u) {
+                    const A t = __shfl(cur.tr, (grp + u * ngr) & 63);
+#pragma unroll
+                    for (int h = 0; h < W; ++h) acc[h] = fma(v[u][h], t, acc[h]);
+                }
+                vb += tot;
+                base = nb;
+                nr = nn;
+                return nn == 0;
+            };
+            for (;;) {
+                if (step(s0, s1)) break;
+                if (step(s1, s0)) break;
             }
-            A v[RPG][W];
-#pragma unroll
-            for (int u = 0; u < RPG; ++u) {
-                const int r = grp + u * ngr;
-                const uint32_t p = __shfl(pk, r & 63);
-                const int iz0 = (int)((p >> 8) & 255u), lo = iz0 & ~(W - 1);
-                const bool in = live && r < nr && k2 >= lo && k2 < iz0 + (int)(p & 255u);
-                // a lane outside the run's window reads the quarter's first
-                // word (a line the wave streams anyway) and drops it
-                ld_word<A, M, W>(nv + (in ? vb + (int64_t)(p >> 16) + (k2 - lo) : vb), v[u]);
-#pragma unroll
-                for (int h = 0; h < W; ++h) v[u][h] = in ? v[u][h] : (A)0;
-            }
-            A tr_n = 0;
-            if (lane < nn) tr_n = (A)Tg[row_n];
-#pragma unroll
-            for (int u = 0; u < RPG; ++u) {
-                const A t = __shfl(tr, (grp + u * ngr) & 63);
-#pragma unroll
-                for (int h = 0; h < W; ++h) acc[h] = fma(v[u][h], t, acc[h]);
-            }
-            vb += tot;
-            base = nb;
-            nr = nn;
-            dsc = dsc_n;
-            tr = tr_n;
         }
         // lane l < nz: depth l = word l / W, element l mod W, summed over groups
         const int kk = lane / W, hh = lane % W;
@@ -1682,6 +1708,13 @@ int adj_nruns_blocks_per_cu(const ColFmt &C)
     default: break;
     }
 #undef LSQR_ADJ_OCC
+    // at most 4 workgroups per compute unit for depth pairs, 6 for words of
+    // 4 or 8 depths: with the registers the scan frees, one more resident
+    // workgroup per compute unit (a larger single-round grid) measured
+    // FP64 918 -> 940 us and BF16 385 -> 496 us on the config-1 system,
+    // and fewer than these caps were slower too
+    const int cap = C.pairs == 2 ? 4 : C.pairs ? 6 : nb;
+    if (nb > cap) nb = cap;
     return e == hipSuccess ? nb : 0;
 }
 
