@@ -234,6 +234,33 @@ def c17_family(shape: str, first_seed: int, count: int) -> list[Config]:
     return out
 
 
+def load_config_file(path: str) -> dict:
+    """A workload description (configs/config{0..4}.json) with its systems
+    as Config objects: "systems" lists them, and "families" entries
+    ({"family": "c17", "shape", "first_seed", "count"}) expand to the
+    c17_family systems they name."""
+    import json
+    with open(path) as f:
+        d = json.load(f)
+    fields = {f.name for f in dataclasses.fields(Config)}
+
+    def cfg(x):
+        x = {k: v for k, v in x.items() if k in fields}
+        x["z_nodes"] = tuple(float(z) for z in x["z_nodes"])
+        x["periods"] = tuple(float(p) for p in x["periods"])
+        return Config(**x)
+
+    d["systems"] = [cfg(x) for x in d.get("systems", [])]
+    for key, fams in d.get("families", {}).items():
+        out = []
+        for fam in fams:
+            if fam.get("family") != "c17":
+                raise ValueError(f"unknown family {fam.get('family')!r}")
+            out += c17_family(fam["shape"], int(fam["first_seed"]), int(fam["count"]))
+        d["families"][key] = out
+    return d
+
+
 def small_config(nx=8, ny=8, nz=6, n_stations=12, n_periods=5, region=0.7, bent=True,
                  seed=0, damp=0.1, smooth=0.5, min_wavelengths=None) -> Config:
     """A reduced geometry with the same structure, for fast tests."""
