@@ -117,9 +117,9 @@ typedef struct {
                                 /* layout (each run stored from an even position with */
                                 /* a zero before an odd first depth and after an odd  */
                                 /* end, so two depths load as one aligned word; FP32  */
-                                /* values and 16-bit codes four depths to a word; a   */
-                                /* second, padded copy of the node-run values); other */
-                                /* values: INVALID_ARG                                */
+                                /* values four and 16-bit codes eight depths to a     */
+                                /* word; a second, padded copy of the node-run        */
+                                /* values); other values: INVALID_ARG                 */
     double refine_inner_tol;    /* mixed precision: relative eta each inner solve     */
                                 /* reaches before the FP64 correction (0 = 1e-2); a   */
                                 /* sweep cannot gain more than the quantisation error */
@@ -144,6 +144,15 @@ typedef struct {
                                 /* natural choice is twice Jacobi's count on the      */
                                 /* system.  0 = no fallback.  The context keeps the   */
                                 /* user scale for later solves.                        */
+    double refine_stall_ratio;  /* mixed precision: a sweep stalls when it leaves eta  */
+                                /* above this times the previous sweep's (0 = 0.5;    */
+                                /* [0, 1], else INVALID_ARG).  On the first stall the */
+                                /* remaining inner solves run on FP32 copies of the   */
+                                /* FP64 values (row groups or CSR and the CSC, built  */
+                                /* then, 8 bytes per entry more) and info.inner_fp32  */
+                                /* is set; a stall after that ends the solve, istop 4 */
+                                /* (with a user scale and fallback_iters, the Jacobi  */
+                                /* fallback comes first)                              */
 } lsqr_opts;
 
 /* Stop reasons (info.istop):
@@ -153,7 +162,9 @@ typedef struct {
  *   2  iteration limit reached
  *   3  exact breakdown (alpha or beta exactly 0): dm is the least-squares
  *      solution over the Krylov space reached
- *   4  mixed-precision refinement stalled (eta did not halve in a sweep)  */
+ *   4  mixed-precision refinement stalled (eta did not fall below
+ *      opts.refine_stall_ratio times the previous sweep's), with FP32 inner
+ *      solves already tried  */
 typedef struct {
     int istop;
     int iters;                  /* iterations done (total inner iterations if mixed;  */
@@ -169,6 +180,8 @@ typedef struct {
                                 /* |Abar^T bbar| in the original variables (every     */
                                 /* form and method), when tol > 0; NaN for fixed      */
                                 /* iteration counts (tol = 0)                          */
+    int inner_fp32;             /* 1 if the refinement stalled and its later inner     */
+                                /* solves ran on FP32 values (BF16 / FP16 forms)       */
 } lsqr_info;
 
 typedef struct lsqr_ctx lsqr_ctx;
@@ -317,9 +330,11 @@ lsqr_status lsqr_assemble_rays(const lsqr_rays *rays, void *stream, lsqr_alloc_f
  * operator's transpose is Abar^T rbar exactly, and which, unlike rbar,
  * vanishes at the solution, so its FP32 rounding does not bound eta) to the
  * relative eta opts.refine_inner_tol (default 1e-2), and adds
- * the correction; the solve stops when eta <= tol (istop 1), after
- * opts.refine_sweeps sweeps (istop 2), or when a sweep fails to halve eta
- * (istop 4).
+ * the correction; the solve stops when eta <= tol (istop 1) or after
+ * opts.refine_sweeps sweeps (istop 2).  A sweep that leaves eta above
+ * opts.refine_stall_ratio (default 0.5) times the previous one switches the
+ * remaining inner solves to FP32 values (info.inner_fp32 = 1); a second
+ * stall ends the solve (istop 4).
  *   dt        [m]   data right-hand side (vec_mem says host or device), finite
  *   iters     >= 0  iteration limit K (forward products after the start)
  *   tol       >= 0  stop when eta_k <= tol (0: run exactly K iterations)

@@ -367,6 +367,7 @@ void lsqr_destroy(lsqr_ctx *c)
     DeviceGuard dg(c->device);
     if (c->st) (void)hipStreamSynchronize(c->st);
     if (c->eng.gexec) (void)hipGraphExecDestroy(c->eng.gexec);
+    if (c->eng32.gexec) (void)hipGraphExecDestroy(c->eng32.gexec);
     if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     for (auto &pr : c->owned) c->al.put(pr.first, pr.second);
@@ -419,6 +420,8 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     if (o.fallback_iters < 0) return fail(nullptr, LSQR_E_INVALID_ARG, "fallback_iters must be >= 0");
     if (!(o.refine_inner_tol >= 0.0 && o.refine_inner_tol < 1.0))
         return fail(nullptr, LSQR_E_INVALID_ARG, "refine_inner_tol must be in [0, 1)");
+    if (!(o.refine_stall_ratio >= 0.0 && o.refine_stall_ratio <= 1.0))
+        return fail(nullptr, LSQR_E_INVALID_ARG, "refine_stall_ratio must be in [0, 1]");
     if (G->mem == LSQR_MEM_HOST) {
         lsqr_status s = validate_host_csr(G);
         if (s != LSQR_OK) return s;
@@ -441,6 +444,7 @@ lsqr_status lsqr_create(const lsqr_csr *G, double damp, double smooth_weight,
     // an inner solve need not go far below the per-sweep gain the quantisation
     // allows (~1e-2 for BF16, ~1e-3 for FP16 on the tomography systems)
     c->refine_inner_tol = o.refine_inner_tol > 0.0 ? o.refine_inner_tol : 1e-2;
+    c->stall_ratio = o.refine_stall_ratio > 0.0 ? o.refine_stall_ratio : 0.5;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, LSQR_E_DEVICE, "no HIP device available");
@@ -779,6 +783,32 @@ static lsqr_status restore_user_scale(lsqr_ctx *c)
 
 static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0, int iters,
                                double tol, double *ddm, double *res_hist, lsqr_info *info);
+
+// The inner solves of a quantised context after its refinement stalled: FP32
+// copies of the FP64 values in the forward product's stored rows (row groups
+// or CSR) and in the CSC, FP32 vectors; built once, on first use (the node-run
+// layouts are not rebuilt: their value map is released after create).
+static lsqr_status ensure_fp32_engine(lsqr_ctx *c)
+{
+    if (c->have_eng32) return LSQR_OK;
+    const int64_t nnz = c->P.nnz;
+    if (!c->va32) c->va32 = ctx_alloc<float>(c, nnz + 8);   // with va's padding elements
+    if (!c->cv32) c->cv32 = ctx_alloc<float>(c, nnz);
+    if (!c->va32 || !c->cv32) return fail(c, LSQR_E_OOM, "device allocation failed");
+    launch_convert_f32(c->st, nnz + 8, c->va, c->va32);
+    launch_convert_f32(c->st, nnz, c->cv, c->cv32);
+    RowFmt R = c->R64;
+    R.vt = VT_F32;
+    R.val = c->va32;
+    ColFmt C = c->C64;
+    C.vt = VT_F32;
+    C.val = c->cv32;
+    lsqr_status s = setup_engine(c, c->eng32, VT_F32, R, C);
+    if (s != LSQR_OK) return fail(c, s, g_err);
+    HIP_TRY(c, hipGetLastError());
+    c->have_eng32 = true;
+    return LSQR_OK;
+}
 static lsqr_status solve_warm(lsqr_ctx *c, const double *ddt, int iters, double tol, double *ddm,
                               double *res_hist, lsqr_info *info);
 
@@ -799,6 +829,7 @@ static lsqr_status solve_plain(lsqr_ctx *c, const double *ddt, int iters, double
     info->iters = kdone;
     info->sweeps = 0;
     info->fallback_used = c->fallback_used;
+    info->inner_fp32 = 0;
     const double *Sk = hs.data() + (size_t)kdone * kStateWords;
     info->eta = istop == 0 ? 0.0 : Sk[S_ETA];
     info->phibar = istop == 0 ? hs[S_BETA] : Sk[S_PHIBAR];
@@ -948,6 +979,9 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0
     // learned-scale fallback: Jacobi once the inner iterations pass the budget
     const bool fb = c->user_scale && c->fallback_iters > 0;
     bool switched = false;
+    // the inner solves' kernels: the quantised ones, FP32 values after a stall
+    Engine *EI = &E;
+    int inner32 = 0;
     std::vector<double> hs;
     if (!(arnorm > 0.0)) {
         istop = 0;
@@ -971,17 +1005,27 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0
             if (!isfinite(eta)) return fail(c, LSQR_E_NONFINITE, "refinement residual became non-finite");
             if (eta <= tol) { istop = 1; break; }
             if (sw >= c->refine_sweeps) { istop = 2; break; }
-            if (sw > 0 && eta > 0.5 * eta_prev) {
-                if (!fb || switched) { istop = 4; break; }
-                // a user scale that stalls the refinement: Jacobi from here
-                if ((s = fallback_to_jacobi(c)) != LSQR_OK) return s;
-                switched = true;
+            if (sw > 0 && eta > c->stall_ratio * eta_prev) {
+                if (fb && !switched) {
+                    // a user scale that stalls the refinement: Jacobi from here
+                    if ((s = fallback_to_jacobi(c)) != LSQR_OK) return s;
+                    switched = true;
+                } else if (!inner32) {
+                    // the quantised operator is too far from the FP64 one for
+                    // the sweeps to contract: FP32 values from here
+                    if ((s = ensure_fp32_engine(c)) != LSQR_OK) return s;
+                    EI = &c->eng32;
+                    inner32 = 1;
+                } else {
+                    istop = 4;
+                    break;
+                }
             }
             eta_prev = eta;
-            // inner solve on the quantised operator, x += D y
-            s = engine_solve(c, E, c->fbuf, 1, iters, inner_tol, c->xbuf, 1, timing);
+            // inner solve on the quantised (or FP32) operator, x += D y
+            s = engine_solve(c, *EI, c->fbuf, 1, iters, inner_tol, c->xbuf, 1, timing);
             if (s != LSQR_OK) return s;
-            if ((s = read_state(c, E, iters, hs)) != LSQR_OK) return s;
+            if ((s = read_state(c, *EI, iters, hs)) != LSQR_OK) return s;
             last_iters = c->hctl[C_ITERS];
             last_istop = c->hctl[C_ISTOP];
             total += last_iters;
@@ -1005,6 +1049,7 @@ static lsqr_status solve_mixed(lsqr_ctx *c, const double *ddt, const double *dx0
         info->iters = total;
         info->sweeps = sweeps;
         info->fallback_used = c->fallback_used | (switched ? 1 : 0);
+        info->inner_fp32 = inner32;
         info->eta = eta;
         info->phibar = rnorm;
     }
@@ -1057,6 +1102,7 @@ static lsqr_status solve_warm(lsqr_ctx *c, const double *ddt, int iters, double 
             info->iters = 0;
             info->sweeps = 0;
             info->fallback_used = c->fallback_used;
+            info->inner_fp32 = 0;
             info->eta = 0.0;
             info->phibar = 0.0;
         }
@@ -1078,6 +1124,7 @@ static lsqr_status solve_warm(lsqr_ctx *c, const double *ddt, int iters, double 
         info->iters = kdone;
         info->sweeps = 0;
         info->fallback_used = c->fallback_used;
+        info->inner_fp32 = 0;
         const double *Sk = hs.data() + (size_t)kdone * kStateWords;
         info->eta = istop == 0 ? 0.0 : Sk[S_ETA] * ratio;
         info->phibar = istop == 0 ? hs[S_BETA] : Sk[S_PHIBAR];

@@ -442,6 +442,7 @@ lsqr_status lsqr_solve_batched(lsqr_ctx *const *ctxs, int nsys, int nrhs, const 
                 I.iters = kl;
                 I.sweeps = 0;
                 I.fallback_used = c->fallback_used;
+                I.inner_fp32 = 0;
                 I.eta = why[r] == 0 ? 0.0 : Sk[S_ETA];
                 I.phibar = why[r] == 0 ? Sk[S_BETA] : Sk[S_PHIBAR];
                 I.eta_final_fp64 = NAN;
@@ -590,6 +591,7 @@ lsqr_status lsqr_solve_batched_refined(lsqr_ctx *const *ctxs, int nsys, int nrhs
             I.iters = total[k];
             I.sweeps = nsw[k];
             I.fallback_used = ctxs[k / nrhs]->fallback_used;
+            I.inner_fp32 = 0;
             I.eta = eta[k];
             I.phibar = rn[k];
             I.eta_final_fp64 = eta[k];

@@ -106,6 +106,9 @@ struct lsqr_ctx {
     float *sigma = nullptr;
     uint16_t *qrow = nullptr, *qcol = nullptr;
     lsqr::Engine eng;               // the solver's kernel set
+    lsqr::Engine eng32;             // quantised forms: FP32 inner solves after a stall
+    bool have_eng32 = false;
+    double stall_ratio = 0.5;       // refinement: a sweep must bring eta below this x the last
     lsqr::BatchEngine beng;         // the batched solver's buffers
     // refinement and operator scratch (FP64)
     double *xbuf = nullptr, *ybuf = nullptr, *rbar = nullptr, *gbuf = nullptr;

@@ -49,13 +49,15 @@ class Opts(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("lanes_per_row", ctypes.c_int),
                 ("lanes_per_col", ctypes.c_int), ("row_format", ctypes.c_int),
                 ("col_format", ctypes.c_int), ("refine_inner_tol", ctypes.c_double),
-                ("method", ctypes.c_int), ("fallback_iters", ctypes.c_int)]
+                ("method", ctypes.c_int), ("fallback_iters", ctypes.c_int),
+                ("refine_stall_ratio", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("istop", ctypes.c_int), ("iters", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("fallback_used", ctypes.c_int), ("eta", ctypes.c_double),
-                ("phibar", ctypes.c_double), ("eta_final_fp64", ctypes.c_double)]
+                ("phibar", ctypes.c_double), ("eta_final_fp64", ctypes.c_double),
+                ("inner_fp32", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -203,7 +205,7 @@ class Solver:
                  precond="none", col_scale=None, stream=None, timing=False, graph=True,
                  lanes_per_row=0, lanes_per_col=0, check_every=0, refine_sweeps=5,
                  row_format="auto", col_format="auto", refine_inner_tol=0.0,
-                 method="lsqr", torch_alloc=True, fallback_iters=0):
+                 method="lsqr", torch_alloc=True, fallback_iters=0, refine_stall_ratio=0.0):
         import torch
         lib = load()
         self._torch = torch
@@ -234,6 +236,7 @@ class Solver:
         opts.refine_inner_tol = float(refine_inner_tol)
         opts.method = {"lsqr": 0, "lsmr": 1}[method]
         opts.fallback_iters = int(fallback_iters)
+        opts.refine_stall_ratio = float(refine_stall_ratio)
         opts.check_every = int(check_every)
         opts.stream = stream.cuda_stream
         opts.flags = (FLAG_TIMING if timing else 0) | (0 if graph else FLAG_NO_GRAPH)

@@ -90,11 +90,14 @@ def test_null_arguments(lib):
 
 
 @pytest.mark.parametrize("field,value", [("row_format", 2), ("row_format", 3), ("row_format", 5),
-                                         ("col_format", 3), ("col_format", 5), ("flags", 4)])
+                                         ("col_format", 3), ("col_format", 5), ("flags", 4),
+                                         ("refine_stall_ratio", -0.5),
+                                         ("refine_stall_ratio", 1.5),
+                                         ("refine_stall_ratio", float("nan"))])
 def test_create_rejects_unknown_formats_and_flags(lib, field, value):
     """Only the built formats and flags are accepted (row 0/1/4, column
-    0/1/2/4, flags TIMING and NO_GRAPH); the check comes before any device
-    call."""
+    0/1/2/4, flags TIMING and NO_GRAPH), and a stall ratio in [0, 1]; the
+    check comes before any device call."""
     rp = np.array([0, 2, 3], np.int64)
     ci = np.array([0, 3, 1], np.int32)
     va = np.array([1.0, 2.0, 3.0])

@@ -96,9 +96,9 @@ def test_refinement_reaches_fp64_solution(cfg0, xstar, fmt, precond, col_format)
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
 def test_refinement_floor_is_flagged(cfg0, xstar, fmt):
-    # FP32 inner vectors carry f ~ r* (large for noisy data) while
-    # Ahat^T f -> 0, which sets an eta floor of a few 1e-9 on this system;
-    # a tolerance below it ends with the stall flag and the FP64 solution
+    # a tolerance at the FP64 rounding level: the sweeps stop contracting,
+    # the inner solves switch to FP32 values, and the solve either reaches it
+    # or ends with the stall flag, at the FP64 solution
     with from_sys(cfg0, precision=fmt, precond="jacobi", refine_sweeps=10) as sol:
         dm, hist, info = sol.solve(cfg0.dt, 3000, tol=1e-13)
     err = rel(dm, xstar)
@@ -147,3 +147,58 @@ def test_fp64_row_formats_agree(cfg0, row_format):
     with from_sys(cfg0, row_format=row_format) as sol:
         dm, hist, info = sol.solve(cfg0.dt, 6)
     assert rel(dm, ref["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_stall_switches_inner_solves_to_fp32(cfg0, xstar, fmt):
+    """A sweep that does not bring eta below refine_stall_ratio times the
+    previous one counts as a stall: the first moves the remaining inner
+    solves to FP32 values (info.inner_fp32), the second ends the solve
+    (istop 4).  Forced from the host with a ratio no sweep can meet: sweep 0
+    runs on the quantised values, sweep 1 on the FP32 values, and that sweep
+    must carry the refinement on (eta and the error fall by the inner
+    solve's gain)."""
+    kw = dict(precision=fmt, precond="jacobi", refine_sweeps=10)
+    with from_sys(cfg0, refine_sweeps=1, **{k: v for k, v in kw.items() if k != "refine_sweeps"}) as sol:
+        dm1, _, i1 = sol.solve(cfg0.dt, 3000, tol=1e-14)
+    assert i1["istop"] == 2 and i1["sweeps"] == 1 and i1["inner_fp32"] == 0
+    with from_sys(cfg0, refine_stall_ratio=1e-300, **kw) as sol:
+        dm2, _, i2 = sol.solve(cfg0.dt, 3000, tol=1e-14)
+        # the context keeps its FP32 kernels: a second solve gives the same bits
+        dm3, _, i3 = sol.solve(cfg0.dt, 3000, tol=1e-14)
+    e1, e2 = rel(dm1, xstar), rel(dm2, xstar)
+    print(f"[{fmt}] stall switch: sweep-0 eta {i1['eta']:.2e} err {e1:.2e}; after the FP32 sweep "
+          f"eta {i2['eta']:.2e} err {e2:.2e} (istop {i2['istop']}, sweeps {i2['sweeps']})")
+    assert i2["istop"] == 4 and i2["sweeps"] == 2 and i2["inner_fp32"] == 1
+    assert i2["eta"] < 0.1 * i1["eta"] and e2 < 0.1 * e1
+    assert i2["eta_final_fp64"] == i2["eta"]
+    assert i3 == i2 and np.array_equal(dm3, dm2)
+
+
+def test_plain_forms_never_switch(cfg0):
+    with from_sys(cfg0, precision="fp32", precond="jacobi") as sol:
+        _, _, info = sol.solve(cfg0.dt, 500, tol=1e-6)
+    assert info["inner_fp32"] == 0
+
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_ill_conditioned_refinement_switches_to_fp32(fmt):
+    """Config 0 with damping 1e-3 and smoothing weight 0.01: the quantised
+    operator is too far from the FP64 one for the sweeps to keep halving eta,
+    so the stall guard moves the inner solves to FP32 values, and the
+    refinement then reaches eta <= 1e-10 and the oracle's x* (stored by
+    tests/golden/make_illcond_golden.py) within 1e-5."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "cfg0_illcond.npz"))
+    c = synth.config0()
+    c.damp, c.smooth = float(g["damp"]), float(g["smooth"])
+    s = synth.make_system(c)
+    assert synth.fingerprint(s) == str(g["fingerprint"]), "the generator changed"
+    with from_sys(s, precision=fmt, precond="jacobi", refine_sweeps=12) as sol:
+        dm, _, info = sol.solve(s.dt, 20000, tol=1e-10)
+    err = rel(dm, g["xstar"])
+    print(f"[{fmt}] ill-conditioned: istop={info['istop']} sweeps={info['sweeps']} "
+          f"iters={info['iters']} eta_fp64={info['eta_final_fp64']:.2e} err={err:.2e}")
+    assert info["inner_fp32"] == 1
+    assert info["istop"] == 1 and info["eta_final_fp64"] <= 1e-10 and err <= 1e-5
