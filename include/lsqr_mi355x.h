@@ -137,8 +137,9 @@ typedef struct {
     int fallback_iters;         /* precond USER with tol > 0: when the solve has not  */
                                 /* reached tol after this many iterations (total      */
                                 /* inner iterations for BF16/FP16, or a refinement    */
-                                /* sweep that fails to halve eta), the Jacobi scale   */
-                                /* replaces the user scale and the solve continues    */
+                                /* sweep that stalls: refine_stall_ratio), the Jacobi */
+                                /* scale replaces the user scale and the solve        */
+                                /* continues                                          */
                                 /* from its current dm (info.fallback_used = 1; the   */
                                 /* history is the continuation's); a                  */
                                 /* natural choice is twice Jacobi's count on the      */
