@@ -659,10 +659,13 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol(FwdArgs a)
                 const int j = j0 + (int)threadIdx.x + kBlock * u;
                 zs[u] = (A)z[a.gcol[c0 + (j < nc ? j : nc - 1)]];
             }
+            // lanes past the list store the last column's value again (the
+            // same value to the same slot): an unconditional store keeps the
+            // compiler from sinking a lane's loads into a branch of their own
 #pragma unroll
             for (int u = 0; u < SU; ++u) {
                 const int j = j0 + (int)threadIdx.x + kBlock * u;
-                if (j < nc) zl[j] = zs[u];
+                zl[j < nc ? j : nc - 1] = zs[u];
             }
         }
         __syncthreads();
@@ -769,10 +772,13 @@ __global__ __launch_bounds__(kBlock) void k_fwd_lcol_pair(FwdArgs a)
                 const int j = j0 + (int)threadIdx.x + kBlock * u;
                 zs[u] = (A)z[a.gcol[c0 + (j < nc ? j : nc - 1)]];
             }
+            // lanes past the list store the last column's value again (the
+            // same value to the same slot): an unconditional store keeps the
+            // compiler from sinking a lane's loads into a branch of their own
 #pragma unroll
             for (int u = 0; u < SU; ++u) {
                 const int j = j0 + (int)threadIdx.x + kBlock * u;
-                if (j < nc) zl[j] = zs[u];
+                zl[j < nc ? j : nc - 1] = zs[u];
             }
         }
         __syncthreads();
