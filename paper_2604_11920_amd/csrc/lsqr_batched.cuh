@@ -325,8 +325,10 @@ __global__ __launch_bounds__(kBlock) void k_bfwd_pr32(BArgs a)
         int64_t vb = a.nvq[4 * (int64_t)node + wid];
         for (int64_t base = rs; base < re; base += 64) {
             const int nr = (int)(re - base < 64 ? re - base : 64);
-            uint32_t dsc = 0u;
-            if (lane < nr) dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
+            // every lane loads (lanes past the chunk its last run, masked
+            // here), so the load does not sit under a divergent branch
+            uint32_t dsc = __builtin_nontemporal_load(a.ndesc + base + (lane < nr ? lane : nr - 1));
+            dsc = lane < nr ? dsc : 0u;
             const int len = (int)(dsc & 255u);
             int incl = len;
 #pragma unroll
@@ -350,10 +352,12 @@ __global__ __launch_bounds__(kBlock) void k_bfwd_pr32(BArgs a)
                     const int i = i0 + 64 * k + lane;
                     t[k] = __builtin_nontemporal_load(a.nval + vb + (i < tot ? i : tot - 1));
                 }
+                // slots past the end store the last value again (same value,
+                // same slot): no branch for the compiler to sink the loads into
 #pragma unroll
                 for (int k = 0; k < kStage; ++k) {
                     const int i = i0 + 64 * k + lane;
-                    if (i < tot) my[i] = t[k];
+                    my[i < tot ? i : tot - 1] = t[k];
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -530,11 +534,12 @@ __global__ __launch_bounds__(kBlock) void k_badj_mfma32(BArgs a)
         floatx16 acc = {};
         for (int64_t base = rs; base < re; base += 64) {
             const int nr = (int)(re - base < 64 ? re - base : 64);
-            uint32_t dsc = 0u, row = 0u;
-            if (lane < nr) {
-                dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
-                row = __builtin_nontemporal_load(a.nrow + base + lane);
-            }
+            // every lane loads (lanes past the chunk its last run: a valid
+            // row whose values are zero; the descriptor masked here)
+            const int64_t li = base + (lane < nr ? lane : nr - 1);
+            uint32_t dsc = __builtin_nontemporal_load(a.ndesc + li);
+            const uint32_t row = __builtin_nontemporal_load(a.nrow + li);
+            dsc = lane < nr ? dsc : 0u;
             const int len = (int)(dsc & 255u);
             int incl = len;
 #pragma unroll
@@ -558,7 +563,7 @@ __global__ __launch_bounds__(kBlock) void k_badj_mfma32(BArgs a)
 #pragma unroll
                 for (int q = 0; q < kStage; ++q) {
                     const int i = i0 + 64 * q + lane;
-                    if (i < tot) my[i] = t[q];
+                    my[i < tot ? i : tot - 1] = t[q];    // past the end: the last value again
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -671,11 +676,12 @@ __global__ __launch_bounds__(kBlock) void k_badj_nruns(BArgs a)
         for (int r = 0; r < RT; ++r) acc[r] = 0.f;
         for (int64_t base = rs; base < re; base += 64) {
             const int nr = (int)(re - base < 64 ? re - base : 64);
-            uint32_t dsc = 0u, row = 0u;
-            if (lane < nr) {
-                dsc = __builtin_nontemporal_load(a.ndesc + base + lane);
-                row = __builtin_nontemporal_load(a.nrow + base + lane);
-            }
+            // every lane loads (lanes past the chunk its last run: a valid
+            // row whose values are zero; the descriptor masked here)
+            const int64_t li = base + (lane < nr ? lane : nr - 1);
+            uint32_t dsc = __builtin_nontemporal_load(a.ndesc + li);
+            const uint32_t row = __builtin_nontemporal_load(a.nrow + li);
+            dsc = lane < nr ? dsc : 0u;
             const int len = (int)(dsc & 255u);
             int incl = len;
 #pragma unroll
@@ -692,7 +698,7 @@ __global__ __launch_bounds__(kBlock) void k_badj_nruns(BArgs a)
                 for (int u = 0; u < K; ++u) {
                     const int r = s0 + grp + u * ngr;
                     const uint32_t p = __shfl(pk, r & 63);
-                    rw[u] = __shfl(row, r & 63);               // rows past nr read row 0
+                    rw[u] = __shfl(row, r & 63);               // rows past nr: a valid row, zero values
                     const int e = iz - (int)((p >> 8) & 255u);
                     const bool in = live && r < nr && (unsigned)e < (p & 255u);
                     const float x = __builtin_nontemporal_load(
