@@ -106,9 +106,62 @@ __device__ __forceinline__ T tree_sum(const T *v)
     }
 }
 
+// One DPP move of a 32- or 64-bit value (64-bit: both halves); lanes whose
+// source is outside the row, and rows masked off, receive zero.
+template <int ctrl, int rmask, bool bound_zero, class T>
+__device__ __forceinline__ T dpp_move(T v)
+{
+    if constexpr (sizeof(T) == 8) {
+        int2 h;
+        __builtin_memcpy(&h, &v, 8);
+        h.x = __builtin_amdgcn_update_dpp(0, h.x, ctrl, rmask, 0xf, bound_zero);
+        h.y = __builtin_amdgcn_update_dpp(0, h.y, ctrl, rmask, 0xf, bound_zero);
+        __builtin_memcpy(&v, &h, 8);
+        return v;
+    } else {
+        int x;
+        __builtin_memcpy(&x, &v, 4);
+        x = __builtin_amdgcn_update_dpp(0, x, ctrl, rmask, 0xf, bound_zero);
+        __builtin_memcpy(&v, &x, 4);
+        return v;
+    }
+}
+template <class T>
+__device__ __forceinline__ T lane_value(T v, int lane)
+{
+    if constexpr (sizeof(T) == 8) {
+        int2 h;
+        __builtin_memcpy(&h, &v, 8);
+        h.x = __builtin_amdgcn_readlane(h.x, lane);
+        h.y = __builtin_amdgcn_readlane(h.y, lane);
+        __builtin_memcpy(&v, &h, 8);
+        return v;
+    } else {
+        int x;
+        __builtin_memcpy(&x, &v, 4);
+        x = __builtin_amdgcn_readlane(x, lane);
+        __builtin_memcpy(&v, &x, 4);
+        return v;
+    }
+}
+
 template <int W, class T>
 __device__ __forceinline__ T group_sum(T v)
 {
+    if constexpr (W == 64) {
+        // prefix sums within rows of 16 lanes, then the row sums into lane
+        // 63: ((row 3 + row 2) + (row 1 + row 0)), returned to every lane.
+        // On the VALU in place of six shuffles through the LDS crossbar: the
+        // per-row sums of the forward products, BF16 471 -> 457 us, FP32
+        // 650 -> 642 us, FP64 984 -> 980 us on the config-1 system
+        v += dpp_move<0x111, 0xf, true>(v);
+        v += dpp_move<0x112, 0xf, true>(v);
+        v += dpp_move<0x114, 0xf, true>(v);
+        v += dpp_move<0x118, 0xf, true>(v);
+        v += dpp_move<0x142, 0xa, false>(v);
+        v += dpp_move<0x143, 0xc, false>(v);
+        return lane_value(v, 63);
+    }
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
     return v;
